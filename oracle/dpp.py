@@ -1,0 +1,213 @@
+"""Oracle assembly of the CG-VMS four-field DPP system (test infrastructure).
+
+K and f are the block entries of eq. S4_cg_stiffness_matrix and eq. S4_cg_rhs
+(section "Proposed four-field solvers") obtained from the CG-VMS weak form
+(eq. CG_VMS_Weak_form) on P1 simplices; the numeric work is done in
+``dpp_oracle.c`` in plain FP64.  Unknown ordering [u1 | p1 | u2 | p2] with the
+velocity components interleaved per node (the ordering of the mixed space in
+the appendix listings: fields 0..3 = u1, p1, u2, p2).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import build as _build
+
+_lib = None
+MAXADJ = 32
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(_build.ensure_built())
+        P = C.c_void_p
+        _lib.or_num_nodes.restype = C.c_long
+        _lib.or_num_nodes.argtypes = [C.c_int, P]
+        _lib.or_num_cells.restype = C.c_long
+        _lib.or_num_cells.argtypes = [C.c_int, P]
+        _lib.or_mesh.restype = None
+        _lib.or_mesh.argtypes = [C.c_int, P, P, P, P]
+        _lib.or_adjacency.restype = None
+        _lib.or_adjacency.argtypes = [C.c_int, C.c_long, C.c_long, P, P, P, P, P]
+        _lib.or_rowptr.restype = C.c_int64
+        _lib.or_rowptr.argtypes = [C.c_int, C.c_long, P, P]
+        _lib.or_cols.restype = None
+        _lib.or_cols.argtypes = [C.c_int, C.c_long, P, P, P, P]
+        _lib.or_assemble.restype = None
+        _lib.or_assemble.argtypes = [C.c_int, P, C.c_long, C.c_long, P, P, P, P, P, P, P, P,
+                                     P, P, P, C.c_double, P, P, P]
+        _lib.or_spmv.restype = None
+        _lib.or_spmv.argtypes = [C.c_long, P, P, P, P, P]
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+@dataclass
+class Mesh:
+    dim: int
+    n: tuple
+    L: tuple
+    X: np.ndarray        # [N, d]
+    cells: np.ndarray    # [nc, d+1]
+    incptr: np.ndarray
+    inc: np.ndarray
+    adjcnt: np.ndarray
+    adj: np.ndarray
+
+    @property
+    def N(self):
+        return self.X.shape[0]
+
+    @property
+    def nc(self):
+        return self.cells.shape[0]
+
+
+def mesh(dim, n, L=None):
+    """Structured Kuhn box mesh (spec in the module docstring of dpp_inputs)."""
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    L = np.ascontiguousarray(L if L is not None else [1.0] * dim, dtype=np.float64)
+    lb = lib()
+    N = lb.or_num_nodes(dim, _p(n))
+    nc = lb.or_num_cells(dim, _p(n))
+    X = np.empty((N, dim))
+    cells = np.empty((nc, dim + 1), dtype=np.int32)
+    lb.or_mesh(dim, _p(n), _p(L), _p(X), _p(cells))
+    incptr = np.empty(N + 1, dtype=np.int64)
+    inc = np.empty(nc * (dim + 1), dtype=np.int32)
+    adjcnt = np.empty(N, dtype=np.int32)
+    adj = np.zeros((N, MAXADJ), dtype=np.int32)
+    lb.or_adjacency(dim, N, nc, _p(cells), _p(incptr), _p(inc), _p(adjcnt), _p(adj))
+    return Mesh(dim, tuple(int(v) for v in n), tuple(float(v) for v in L), X, cells, incptr,
+                inc, adjcnt, adj)
+
+
+@dataclass
+class System:
+    mesh: Mesh
+    K: sp.csr_matrix
+    f: np.ndarray
+    mu: float
+
+    @property
+    def dim(self):
+        return self.mesh.dim
+
+    @property
+    def N(self):
+        return self.mesh.N
+
+
+def fields(dim, N):
+    """Index slices of the four fields in the global vector (u1, p1, u2, p2)."""
+    d = dim
+    return dict(u1=slice(0, d * N), p1=slice(d * N, (d + 1) * N),
+                u2=slice((d + 1) * N, (2 * d + 1) * N), p2=slice((2 * d + 1) * N, (2 * d + 2) * N))
+
+
+def assemble(prob, msh=None):
+    """Assemble K, f of the CG-VMS system for a ``dpp_inputs.Problem``.
+
+    Follows eq. S4_cg_stiffness_matrix / eq. S4_cg_rhs; pressure boundary data
+    enter weakly through -(w.n; p0) (eq. VMS_classical_mixed_formulation and the
+    linear functional of the appendix CG-VMS listing), with p0 the P1 nodal
+    interpolant integrated exactly on each boundary facet.
+    """
+    d = prob.dim
+    msh = msh or mesh(d, prob.n, prob.L)
+    lb = lib()
+    N, nc = msh.N, msh.nc
+    ndof = (2 * d + 2) * N
+    rowptr = np.empty(ndof + 1, dtype=np.int64)
+    nnz = lb.or_rowptr(d, N, _p(msh.adjcnt), _p(rowptr))
+    cols = np.empty(nnz, dtype=np.int32)
+    lb.or_cols(d, N, _p(msh.adjcnt), _p(msh.adj), _p(rowptr), _p(cols))
+    vals = np.empty(nnz)
+    f = np.empty(ndof)
+    k1 = np.ascontiguousarray(prob.k1, dtype=np.float64)
+    k2 = np.ascontiguousarray(prob.k2, dtype=np.float64)
+    beta = np.ascontiguousarray(np.broadcast_to(np.asarray(prob.beta, dtype=np.float64), (nc,)))
+    body = None
+    if prob.body is not None:
+        body = np.ascontiguousarray(np.broadcast_to(np.asarray(prob.body, dtype=np.float64) *
+                                                    prob.gamma, (nc, d)))
+    p01 = np.ascontiguousarray(prob.p0_1, dtype=np.float64)
+    p02 = np.ascontiguousarray(prob.p0_2, dtype=np.float64)
+    nn = np.ascontiguousarray(msh.n, dtype=np.int32)
+    lb.or_assemble(d, _p(nn), N, nc, _p(msh.X), _p(msh.cells), _p(msh.incptr), _p(msh.inc),
+                   _p(rowptr), _p(cols), _p(vals), _p(f), _p(k1), _p(k2), _p(beta),
+                   float(prob.mu), _p(body) if body is not None else None, _p(p01), _p(p02))
+    K = sp.csr_matrix((vals, cols, rowptr), shape=(ndof, ndof))
+    return System(msh, K, f, float(prob.mu))
+
+
+def spmv(K, x):
+    """y = K x with the oracle's OpenMP CSR loop (large residual checks)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(K.shape[0])
+    rp = np.ascontiguousarray(K.indptr, dtype=np.int64)
+    ci = np.ascontiguousarray(K.indices, dtype=np.int32)
+    vv = np.ascontiguousarray(K.data, dtype=np.float64)
+    lib().or_spmv(K.shape[0], _p(rp), _p(ci), _p(vv), _p(x), _p(y))
+    return y
+
+
+def blocks(sys_or_K, dim=None, N=None):
+    """Sub-blocks of K by field (the fieldsplit index sets of the solver
+    options listings): Kuu[i], Kup[i], Kpu[i], Kpp[i], K12, K21."""
+    if isinstance(sys_or_K, System):
+        K, dim, N = sys_or_K.K, sys_or_K.dim, sys_or_K.N
+    else:
+        K = sys_or_K
+    F = fields(dim, N)
+    K = K.tocsr()
+    out = dict(Kuu=[], Kup=[], Kpu=[], Kpp=[])
+    for u, p in (("u1", "p1"), ("u2", "p2")):
+        out["Kuu"].append(K[F[u], :][:, F[u]].tocsr())
+        out["Kup"].append(K[F[u], :][:, F[p]].tocsr())
+        out["Kpu"].append(K[F[p], :][:, F[u]].tocsr())
+        out["Kpp"].append(K[F[p], :][:, F[p]].tocsr())
+    out["K12"] = K[F["p1"], :][:, F["p2"]].tocsr()
+    out["K21"] = K[F["p2"], :][:, F["p1"]].tocsr()
+    return out
+
+
+def selfp(sys_or_K, dim=None, N=None):
+    """S_p^i = K_pp^i - K_pu^i diag(K_uu^i)^-1 K_up^i  (eqs. S4_sp1, S4_sp2).
+
+    The inter-network blocks K12, K21 are left out: the preconditioner treats
+    the two diagonal blocks of S_p separately (Method 2 of the solver section).
+    """
+    B = blocks(sys_or_K, dim, N)
+    out = []
+    for i in range(2):
+        dinv = sp.diags(1.0 / B["Kuu"][i].diagonal())
+        out.append((B["Kpp"][i] - B["Kpu"][i] @ dinv @ B["Kup"][i]).tocsr())
+    return out
+
+
+def solve_direct(K, f):
+    """x* = K^-1 f by sparse LU (the plain definition of the discrete solution)."""
+    return spla.spsolve(K.tocsc(), f)
+
+
+def solve_dense(K, f):
+    return np.linalg.solve(K.toarray(), f)
+
+
+def sign_matrix(dim, N):
+    """D = diag(I_u, -I_p): D K is symmetric for the CG-VMS operator."""
+    F = fields(dim, N)
+    s = np.ones((2 * dim + 2) * N)
+    s[F["p1"]] = -1.0
+    s[F["p2"]] = -1.0
+    return s

@@ -1,0 +1,173 @@
+"""Oracle multigrid V-cycle for the pressure Schur blocks (test infrastructure).
+
+The paper applies one algebraic-multigrid V-cycle to each diagonal block
+S_p^i of the selfp Schur approximation (Method 1 and Method 2 of the solver
+section: one sweep of the velocity-block solver and one V-cycle per S_p^i
+inside GMRES), justified because S_p is spectrally equivalent to a Laplacian.
+The particular V-cycle is not fixed by the paper.  This build uses a geometric
+one on the structured box, defined here in plain steps:
+
+  * interpolation P: P1 nodal interpolation from the box with ceil(n/2) cells
+    per axis (coarse node C sits at fine index 2C, the last one at n when n is
+    odd) -- a fine node with odd indices on the axes in set O lies on the Kuhn
+    edge between coarse nodes lo and lo + 1_O and takes the mean of the two;
+  * coarse operators: Galerkin A_{l+1} = P^T A_l P;
+  * coarsest level (at most ``coarse_max`` nodes, or no further coarsening
+    possible): exact dense solve;
+  * smoother: Chebyshev iteration of degree ``degree`` preconditioned by the
+    diagonal D of A, on the interval [lo_frac*hi, hi], hi = hi_factor * lam,
+    lam = ||D^-1 A x_k|| after ``power_iters`` normalised power steps from the
+    integer-hash start vector x_0[i] = frac(i * 2654435761 / 2^32) - 1/2;
+  * V-cycle: zero initial guess, pre-smooth, restrict the residual with P^T,
+    recurse, prolongate and add, post-smooth with the same polynomial (the
+    cycle is a symmetric operator).
+
+This module is pinned by invariants (interpolation reproduces linear
+functions, Galerkin coarse operators equal re-discretised ones on nested
+meshes, the V-cycle is symmetric, a one-level cycle is the exact inverse);
+its numerical values are otherwise "parity unpinned" by the paper, which
+prints none.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def axis_map(n):
+    """Per-axis fine->coarse map: (lo[i], odd[i]) for fine indices 0..n."""
+    i = np.arange(n + 1)
+    m = (n + 1) // 2 + 1  # coarse nodes on this axis
+    odd = (i % 2 == 1)
+    lo = i // 2
+    if n % 2 == 1:
+        odd[n] = False
+        lo[n] = m - 1
+    return lo, odd.astype(np.int64), m
+
+
+def coarse_cells(n):
+    return tuple((v + 1) // 2 for v in n)
+
+
+def interpolation(dim, n):
+    """P1 interpolation P (N_fine x N_coarse) on the structured Kuhn box."""
+    n = tuple(int(v) for v in n)
+    maps = [axis_map(v) for v in n]
+    mc = [m for (_, _, m) in maps]
+    # fine node ids in x-fastest order
+    idx = np.indices([v + 1 for v in reversed(n)]).reshape(dim, -1)[::-1]  # idx[a] = index along axis a
+    lo = np.stack([maps[a][0][idx[a]] for a in range(dim)])
+    od = np.stack([maps[a][1][idx[a]] for a in range(dim)])
+    stride = np.cumprod([1] + mc[:-1])
+    c0 = (lo * stride[:, None]).sum(0)
+    c1 = ((lo + od) * stride[:, None]).sum(0)
+    nf = idx.shape[1]
+    has = od.any(0)
+    rows = np.concatenate([np.arange(nf), np.arange(nf)[has]])
+    cols = np.concatenate([c0, c1[has]])
+    vals = np.concatenate([np.where(has, 0.5, 1.0), np.full(has.sum(), 0.5)])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nf, int(np.prod(mc))))
+
+
+def hash_start(size):
+    i = np.arange(size, dtype=np.uint64)
+    h = (i * np.uint64(2654435761)) % np.uint64(2 ** 32)
+    return h.astype(np.float64) / 2.0 ** 32 - 0.5
+
+
+def power_lambda(A, dinv, iters):
+    """lam = ||D^-1 A x_k|| after ``iters`` normalised power steps."""
+    x = hash_start(A.shape[0])
+    x = x / np.linalg.norm(x)
+    lam = 0.0
+    for _ in range(iters):
+        y = dinv * (A @ x)
+        lam = np.linalg.norm(y)
+        x = y / lam
+    return lam
+
+
+def chebyshev(A, dinv, b, x, degree, lo, hi):
+    """Chebyshev iteration for A x = b preconditioned by D (Saad, Iterative
+    Methods for Sparse Linear Systems, Alg. 12.1, with a diagonal preconditioner)."""
+    theta = 0.5 * (hi + lo)
+    delta = 0.5 * (hi - lo)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    r = dinv * (b - A @ x)
+    d = r / theta
+    x = x + d
+    for _ in range(1, degree):
+        r = dinv * (b - A @ x)
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * r
+        x = x + d
+        rho = rho_new
+    return x
+
+
+@dataclass
+class MGOptions:
+    coarse_max: int = 1000
+    degree: int = 2
+    lo_frac: float = 0.3
+    hi_factor: float = 1.1
+    power_iters: int = 15
+
+
+@dataclass
+class Level:
+    A: sp.csr_matrix
+    n: tuple
+    dinv: np.ndarray = None
+    lo: float = 0.0
+    hi: float = 0.0
+    P: sp.csr_matrix = None
+
+
+@dataclass
+class Hierarchy:
+    levels: list = field(default_factory=list)
+    coarse_dense: np.ndarray = None
+    opts: MGOptions = None
+
+
+def setup(A, dim, n, opts=None):
+    """Build the level list: Galerkin operators, smoother bounds, coarse matrix."""
+    opts = opts or MGOptions()
+    H = Hierarchy(opts=opts)
+    A = A.tocsr()
+    n = tuple(int(v) for v in n)
+    while True:
+        lev = Level(A=A, n=n)
+        H.levels.append(lev)
+        nodes = int(np.prod([v + 1 for v in n]))
+        nc = coarse_cells(n)
+        if nodes <= opts.coarse_max or nc == n:
+            break
+        lev.dinv = 1.0 / A.diagonal()
+        lam = power_lambda(A, lev.dinv, opts.power_iters)
+        lev.hi = opts.hi_factor * lam
+        lev.lo = opts.lo_frac * lev.hi
+        lev.P = interpolation(dim, n)
+        A = (lev.P.T @ A @ lev.P).tocsr()
+        n = nc
+    H.coarse_dense = H.levels[-1].A.toarray()
+    return H
+
+
+def vcycle(H, b, l=0):
+    lev = H.levels[l]
+    if l == len(H.levels) - 1:
+        return np.linalg.solve(H.coarse_dense, b)
+    o = H.opts
+    x = np.zeros_like(b)
+    x = chebyshev(lev.A, lev.dinv, b, x, o.degree, lev.lo, lev.hi)
+    r = b - lev.A @ x
+    e = vcycle(H, lev.P.T @ r, l + 1)
+    x = x + lev.P @ e
+    x = chebyshev(lev.A, lev.dinv, b, x, o.degree, lev.lo, lev.hi)
+    return x

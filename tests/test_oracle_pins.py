@@ -1,0 +1,425 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test targets a plausible mistake: a dropped stabilisation term, a wrong
+sign or index, a transposed block, a wrong facet integral, a wrong mesh.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import dpp_inputs as I
+from oracle import dpp, mg, post, solver
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    out = []
+    with open(os.path.join(GOLD, name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                out.append(line.split())
+    return out
+
+
+# ------------------------------------------------------------ mesh / DoF --
+
+def test_dof_table_2d_matches_paper():
+    for n, dof in _rows("dof_2d_tri_cgvms.txt"):
+        m = dpp.mesh(2, (int(n), int(n)))
+        assert 6 * m.N == int(dof)
+        assert m.nc == 2 * int(n) ** 2
+
+
+def test_dof_table_3d_matches_paper():
+    for n, printed, used in _rows("dof_3d_tet_cgvms.txt"):
+        m = dpp.mesh(3, (int(n),) * 3) if int(n) <= 36 else None
+        N = (int(n) + 1) ** 3 if m is None else m.N
+        assert 8 * N == int(used)
+        assert abs(int(printed) - int(used)) <= 1
+
+
+def test_mesh_cells_are_kuhn_simplices():
+    m = dpp.mesh(3, (3, 2, 2), (1.0, 2.0, 0.5))
+    V = m.X[m.cells]
+    J = V[:, 1:, :] - V[:, :1, :]
+    vol = np.abs(np.linalg.det(J)) / 6.0
+    assert np.allclose(vol, (1 / 3) * (2 / 2) * (0.5 / 2) / 6.0)
+    assert np.isclose(vol.sum(), 1.0 * 2.0 * 0.5)
+    # all 6 tets of a hex share the main diagonal
+    assert np.all(m.cells.reshape(-1, 6, 4)[:, :, 0] == m.cells.reshape(-1, 6, 4)[:, :1, 0])
+
+
+def test_nnz_formula():
+    for dim, n, per_pair in ((2, 16, 16), (3, 5, 22), (2, 7, 16)):
+        S = dpp.assemble(I.mms_problem(dim, n))
+        assert S.K.nnz == per_pair * int(S.mesh.adjcnt.sum())
+    S = dpp.assemble(I.mms_problem(2, 16))
+    assert S.K.nnz == 30224
+    # interior node stencils: 7 (TRI) and 15 (Kuhn TET) nodes
+    assert dpp.mesh(2, (4, 4)).adjcnt.max() == 7
+    assert dpp.mesh(3, (4, 4, 4)).adjcnt.max() == 15
+
+
+# ------------------------------------------------------ element entries --
+
+def test_hand_derived_entries_unit_square():
+    prob = I.mms_problem(2, 1, k1=1.0, k2=0.1, beta=1.0, mu=1.0)
+    X = dpp.mesh(2, (1, 1)).X
+    prob.p0_1 = X[:, 0].copy()
+    prob.p0_2 = np.ones(4)
+    S = dpp.assemble(prob)
+    K = S.K.toarray()
+    N, d = 4, 2
+    F = dpp.fields(d, N)
+
+    def idx(field, node, comp):
+        base = F[field].start
+        return base + (d * node + comp if field.startswith("u") else node)
+
+    n_checked = 0
+    for row in _rows("element_2d_n1.txt"):
+        if row[0] == "f":
+            _, fld, node, comp, val = row
+            assert S.f[idx(fld, int(node), int(comp))] == pytest.approx(float(val), abs=1e-15)
+        else:
+            rf, rn, rc, cf, cn, cc, val = row
+            got = K[idx(rf, int(rn), int(rc)), idx(cf, int(cn), int(cc))]
+            assert got == pytest.approx(float(val), abs=1e-15), row
+        n_checked += 1
+    assert n_checked >= 20
+
+
+def test_block_identities():
+    """K_pu = -K_up^T, D K symmetric, K12 = K21 = -(beta/mu) M (eq. S4_cg_stiffness_matrix)."""
+    prob = I.grf_problem(3, 4)
+    prob.beta = 0.7
+    prob.mu = 1.3
+    S = dpp.assemble(prob)
+    B = dpp.blocks(S)
+    for i in range(2):
+        assert abs(B["Kpu"][i] + B["Kup"][i].T).max() == 0.0
+        assert abs(B["Kpp"][i] - B["Kpp"][i].T).max() < 1e-15
+    assert abs(B["K12"] - B["K21"].T).max() == 0.0
+    DK = sp.diags(dpp.sign_matrix(3, S.N)) @ S.K
+    assert abs(DK - DK.T).max() < 1e-15
+    # K12 is -beta/mu times the P1 mass matrix: total = -beta/mu |Omega|
+    assert B["K12"].sum() == pytest.approx(-0.7 / 1.3, rel=1e-13)
+    # [K_pp^i  K_pp^ij] annihilates constants: the stiffness part has zero row
+    # sums and the beta terms cancel
+    one = np.ones(S.N)
+    assert np.abs(B["Kpp"][0] @ one + B["K12"] @ one).max() < 1e-14
+    assert np.abs(B["Kpp"][1] @ one + B["K21"] @ one).max() < 1e-14
+
+
+def test_velocity_mass_and_boundary_identities():
+    prob = I.mms_problem(3, 3, k1=2.0, k2=0.25, beta=1.0, mu=1.5)
+    S = dpp.assemble(prob)
+    B = dpp.blocks(S)
+    N, d = S.N, 3
+    # one component block of K_uu integrates to (mu/(2k)) |Omega|
+    for i, k in enumerate((2.0, 0.25)):
+        Kxx = B["Kuu"][i].toarray()[0::3, 0::3]
+        assert Kxx.sum() == pytest.approx(1.5 / (2 * k), rel=1e-13)
+    # K_up 1 = -oint psi_a n_c : zero on interior rows, facet moments on the boundary
+    verts, normals, meas = post.boundary_facets(S.mesh)
+    expect = np.zeros(d * N)
+    for v, nv, m in zip(verts, normals, meas):
+        for a in v:
+            expect[d * a:d * a + d] -= nv * m / d
+    got = B["Kup"][0] @ np.ones(N)
+    assert np.abs(got - expect).max() < 1e-14
+
+
+# ------------------------------------------------------ exact solutions --
+
+@pytest.mark.parametrize("dim,n", [(2, 6), (3, 3)])
+def test_patch_test_linear_solution_is_exact(dim, n):
+    """p1 = p2 = a.x + c, u_i = (k_i/mu)(gamma b - a) solves the DPP equations
+    (div u_i = 0, p1 - p2 = 0) and lies in P1; the residual-based CG-VMS terms
+    vanish on it, so the discrete solution reproduces it exactly."""
+    a = np.array([0.7, -1.3, 0.4][:dim])
+    gb = np.array([0.2, 0.5, -0.1][:dim])
+    k1, k2, mu = 2.0, 0.3, 1.7
+    prob = I.mms_problem(dim, n, k1=k1, k2=k2, beta=3.0, mu=mu)
+    X = dpp.mesh(dim, prob.n).X
+    p = X @ a + 0.25
+    prob.p0_1, prob.p0_2 = p.copy(), p.copy()
+    prob.body = gb
+    S = dpp.assemble(prob)
+    x = dpp.solve_direct(S.K, S.f)
+    F = dpp.fields(dim, S.N)
+    assert np.abs(x[F["p1"]] - p).max() < 1e-12
+    assert np.abs(x[F["p2"]] - p).max() < 1e-12
+    assert np.abs(x[F["u1"]].reshape(-1, dim) - (k1 / mu) * (gb - a)).max() < 1e-12
+    assert np.abs(x[F["u2"]].reshape(-1, dim) - (k2 / mu) * (gb - a)).max() < 1e-12
+
+
+def test_dense_and_sparse_direct_agree():
+    for dim, n in ((2, 8), (3, 3)):
+        S = dpp.assemble(I.mms_problem(dim, n))
+        xs = dpp.solve_direct(S.K, S.f)
+        xd = dpp.solve_dense(S.K, S.f)
+        assert np.linalg.norm(xs - xd) <= 1e-12 * np.linalg.norm(xd)
+
+
+def _mms_errors(dim, ns, k2):
+    out = []
+    for n in ns:
+        prob = I.mms_problem(dim, n, k1=1.0, k2=k2, beta=1.0, mu=1.0)
+        S = dpp.assemble(prob)
+        if S.K.shape[0] < 20000:
+            x = dpp.solve_direct(S.K, S.f)
+        else:  # the oracle's FGMRES, pinned against the direct solve elsewhere
+            x = solver.solve(S, rtol=1e-12)[0]
+        out.append(post.l2_errors(S, x, lambda X: I.mms_fields(dim, X, 1.0, k2, 1.0, 1.0),
+                                   q=8 if dim == 2 else 6))
+    return out
+
+
+def test_mms_convergence_2d():
+    """L2 errors decay as h^2 for all four fields (section "Two-dimensional study":
+    slope alpha/d = 1 in DoA vs DoS, i.e. alpha = 2)."""
+    ns = [8, 16, 32, 64]
+    errs = _mms_errors(2, ns, 0.1)
+    for f in ("p1", "p2"):
+        assert post.rates([1 / n for n in ns], [e[f] for e in errs]).min() > 1.9
+    for f in ("u1", "u2"):
+        assert post.rates([1 / n for n in ns], [e[f] for e in errs]).min() > 1.8
+
+
+def test_mms_convergence_3d():
+    """3D manufactured solution with the parameters of the paper's 3D table
+    (k1 = 1, k2 = 0.1, beta = mu = 1, section "Three-dimensional study")."""
+    ns = [4, 8, 16]
+    errs = _mms_errors(3, ns, 0.1)
+    for f in ("p1", "p2"):
+        assert post.rates([1 / n for n in ns], [e[f] for e in errs])[-1] > 1.9
+    for f in ("u1", "u2"):
+        assert post.rates([1 / n for n in ns], [e[f] for e in errs])[-1] > 1.8
+
+
+def test_mms_3d_p2_reading():
+    """The 3D micro-pressure uses mu/(beta k2): with k1 in its place the fields
+    would not satisfy the mass balances, so errors would not decay."""
+    for X in (np.random.default_rng(0).random((20, 3)),):
+        k1, k2, beta, mu = 1.0, 0.1, 1.0, 1.0
+        h = 1e-4
+        p1, p2, u1, u2 = I.mms_fields(3, X, k1, k2, beta, mu)
+        div = []
+        for u_idx in (2, 3):
+            dv = 0.0
+            for c in range(3):
+                e = np.zeros(3)
+                e[c] = h
+                up = I.mms_fields(3, X + e, k1, k2, beta, mu)[u_idx][:, c]
+                um = I.mms_fields(3, X - e, k1, k2, beta, mu)[u_idx][:, c]
+                dv = dv + (up - um) / (2 * h)
+            div.append(dv)
+        chi = -(beta / mu) * (p1 - p2)
+        assert np.allclose(div[0], chi, rtol=1e-6, atol=1e-6)
+        assert np.allclose(div[1], -chi, rtol=1e-6, atol=1e-6)
+
+
+def test_mass_balance():
+    """Testing with q1 = 1: oint u1.n = -(beta/mu) int (p1 - p2); with q1 = q2 = 1
+    the transfer terms cancel: oint (u1 + u2).n = 0."""
+    for dim, n, beta, mu in ((2, 12, 2.5, 1.3), (3, 4, 0.5, 2.0)):
+        prob = I.mms_problem(dim, n, k1=1.0, k2=0.05, beta=beta, mu=mu)
+        prob.k1 = prob.k1 * np.linspace(0.5, 2.0, prob.n_cells)
+        S = dpp.assemble(prob)
+        x = dpp.solve_direct(S.K, S.f)
+        f1, f2, P1, P2 = post.balance(S, x)
+        scale = abs(f1) + abs(f2) + abs(P1) + abs(P2)
+        assert abs(f1 + beta / mu * (P1 - P2)) < 1e-11 * scale
+        assert abs(f1 + f2) < 1e-11 * scale
+        assert abs(f1) > 1e-3 * scale  # the check is not vacuous
+
+
+def test_beta_zero_decouples_networks():
+    prob = I.mms_problem(2, 6, k1=1.0, k2=0.2, beta=0.0, bc_params=(1.0, 0.2, 1.0, 1.0))
+    S = dpp.assemble(prob)
+    B = dpp.blocks(S)
+    assert B["K12"].nnz == 0 or abs(B["K12"]).max() == 0.0
+    F = dpp.fields(2, S.N)
+    x = dpp.solve_direct(S.K, S.f)
+    for u, p in (("u1", "p1"), ("u2", "p2")):
+        idx = np.r_[np.arange(S.K.shape[0])[F[u]], np.arange(S.K.shape[0])[F[p]]]
+        Ki = S.K[idx, :][:, idx]
+        xi = dpp.solve_direct(Ki, S.f[idx])
+        assert np.abs(xi - x[idx]).max() < 1e-12 * np.abs(x).max()
+
+
+def test_network_swap_symmetry():
+    prob = I.grf_problem(2, 6)
+    S = dpp.assemble(prob)
+    x = dpp.solve_direct(S.K, S.f)
+    sw = I.grf_problem(2, 6)
+    sw.k1, sw.k2 = prob.k2, prob.k1
+    sw.p0_1, sw.p0_2 = prob.p0_2, prob.p0_1
+    Sw = dpp.assemble(sw)
+    y = dpp.solve_direct(Sw.K, Sw.f)
+    F = dpp.fields(2, S.N)
+    for a, b in (("u1", "u2"), ("p1", "p2")):
+        assert np.abs(x[F[a]] - y[F[b]]).max() < 1e-11 * np.abs(x).max()
+
+
+# ------------------------------------------------------- preconditioner --
+
+def test_selfp_is_spd_and_matches_definition():
+    S = dpp.assemble(I.grf_problem(3, 4))
+    B = dpp.blocks(S)
+    for i, Sp in enumerate(dpp.selfp(S)):
+        A = Sp.toarray()
+        assert np.abs(A - A.T).max() < 1e-14 * np.abs(A).max()
+        np.linalg.cholesky(A)
+        # against a dense evaluation of K_pp - K_pu diag(K_uu)^-1 K_up
+        Kuu = B["Kuu"][i].toarray()
+        ref = B["Kpp"][i].toarray() - B["Kpu"][i].toarray() @ np.diag(1 / np.diag(Kuu)) @ \
+            B["Kup"][i].toarray()
+        assert np.abs(A - ref).max() < 1e-13 * np.abs(ref).max()
+        # 65-point stencil in 3D
+        assert np.diff(Sp.indptr).max() == 65
+
+
+def test_interpolation_reproduces_linear_functions():
+    for dim, n in ((2, (6, 5)), (3, (4, 3, 5)), (2, (7, 7))):
+        P = mg.interpolation(dim, n)
+        nc = mg.coarse_cells(n)
+        # coarse node coordinates in fine index units (last node at n when n odd)
+        ax = []
+        for a in range(dim):
+            lo, od, m = mg.axis_map(n[a])
+            pos = np.zeros(m)
+            for i in range(n[a] + 1):
+                if od[i] == 0:
+                    pos[lo[i]] = i
+            ax.append(pos)
+            assert m == nc[a] + 1
+        Xc = np.stack(np.meshgrid(*ax, indexing="ij"), -1).transpose(
+            tuple(range(dim))[::-1] + (dim,)).reshape(-1, dim)
+        Xf = np.stack(np.meshgrid(*[np.arange(v + 1.0) for v in n], indexing="ij"), -1).transpose(
+            tuple(range(dim))[::-1] + (dim,)).reshape(-1, dim)
+        c = np.array([0.3, -1.1, 0.7][:dim])
+        assert np.abs(P @ (Xc @ c + 2.0) - (Xf @ c + 2.0)).max() < 1e-13
+        assert np.allclose(P.sum(1), 1.0)
+
+
+def test_galerkin_coarse_operator_equals_rediscretisation():
+    """On nested Kuhn meshes (n even) P^T A_h P of the P1 pressure stiffness
+    equals the matrix assembled on the coarse mesh (Galerkin property)."""
+    for dim, n in ((2, 8), (3, 4)):
+        fine = dpp.assemble(I.mms_problem(dim, n, k1=1.0, k2=1.0, beta=0.0, bc_params=(1, 1, 1, 1)))
+        coarse = dpp.assemble(I.mms_problem(dim, n // 2, k1=1.0, k2=1.0, beta=0.0, bc_params=(1, 1, 1, 1)))
+        Af = dpp.blocks(fine)["Kpp"][0]
+        Ac = dpp.blocks(coarse)["Kpp"][0]
+        P = mg.interpolation(dim, (n,) * dim)
+        G = (P.T @ Af @ P).toarray()
+        assert np.abs(G - Ac.toarray()).max() < 1e-14 * np.abs(Ac).max()
+
+
+def test_chebyshev_degree_one_is_damped_jacobi_and_converges():
+    S = dpp.assemble(I.mms_problem(2, 10))
+    A = dpp.selfp(S)[0]
+    dinv = 1 / A.diagonal()
+    b = I.random_vector(A.shape[0], 7)
+    x1 = mg.chebyshev(A, dinv, b, np.zeros_like(b), 1, 0.2, 1.8)
+    assert np.allclose(x1, dinv * b / 1.0)
+    lam = np.linalg.eigvals(np.diag(dinv) @ A.toarray()).real
+    x = np.zeros_like(b)
+    for _ in range(60):
+        x = mg.chebyshev(A, dinv, b, x, 4, lam.min(), lam.max())
+    assert np.linalg.norm(A @ x - b) < 1e-10 * np.linalg.norm(b)
+
+
+def test_vcycle_symmetric_and_contracting():
+    S = dpp.assemble(I.mms_problem(3, 8, k2=1e-2))
+    A = dpp.selfp(S)[1]
+    H = mg.setup(A, 3, (8, 8, 8), mg.MGOptions(coarse_max=50))
+    assert len(H.levels) == 3
+    x, y = I.random_vector(A.shape[0], 1), I.random_vector(A.shape[0], 2)
+    assert abs(mg.vcycle(H, x) @ y - x @ mg.vcycle(H, y)) < 1e-11 * np.linalg.norm(x) ** 2
+    # error contraction of the stationary iteration e <- (I - V A) e
+    e = I.random_vector(A.shape[0], 3)
+    for _ in range(5):
+        e = e - mg.vcycle(H, A @ e)
+    e0 = e.copy()
+    e = e - mg.vcycle(H, A @ e)
+    assert np.sqrt(e @ (A @ e)) < 0.5 * np.sqrt(e0 @ (A @ e0))
+    # one level = exact inverse
+    H1 = mg.setup(A, 3, (8, 8, 8), mg.MGOptions(coarse_max=10 ** 6))
+    assert len(H1.levels) == 1
+    b = I.random_vector(A.shape[0], 4)
+    assert np.linalg.norm(A @ mg.vcycle(H1, b) - b) < 1e-11 * np.linalg.norm(b)
+
+
+def test_fieldsplit_with_exact_blocks_is_exact_inverse():
+    """The full block factorisation with exact A^-1 and the exact Schur complement
+    S = D - C A^-1 B is K^-1 (signs and ordering of the fieldsplit apply)."""
+    S = dpp.assemble(I.grf_problem(2, 4))
+    P = solver.FieldSplit(S, inner="exact_schur")
+    r = I.random_vector(S.K.shape[0], 11)
+    z = P.apply(r)
+    assert np.linalg.norm(S.K @ z - r) < 1e-10 * np.linalg.norm(r)
+    x, its, res = solver.fgmres(S.K, S.f, P.apply, rtol=1e-12)
+    assert its <= 2
+
+
+def test_fgmres_reaches_direct_solution():
+    S = dpp.assemble(I.mms_problem(3, 6, k2=1e-2))
+    x, its, res = solver.solve(S, rtol=1e-12, mg_opts=mg.MGOptions(coarse_max=40))
+    xd = dpp.solve_direct(S.K, S.f)
+    assert res <= 1e-12
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+    assert 5 <= its <= 60
+
+
+# ---------------------------------------------------------------- adjoint --
+
+def test_adjoint_sign_similarity_and_dot_test():
+    """K^T = D K D (D = diag(I_u, -I_p)), so K^T lam = g is lam = D K^-1 D g."""
+    S = dpp.assemble(I.grf_problem(3, 3))
+    D = dpp.sign_matrix(3, S.N)
+    g = I.random_vector(S.K.shape[0], 5)
+    lam = solver.adjoint_solve(S, g)
+    lam2 = D * dpp.solve_direct(S.K, D * g)
+    assert np.linalg.norm(lam - lam2) < 1e-11 * np.linalg.norm(lam)
+    x = I.random_vector(S.K.shape[0], 6)
+    assert abs((S.K.T @ lam) @ x - lam @ (S.K @ x)) < 1e-11 * np.linalg.norm(lam) * np.linalg.norm(x)
+
+
+def test_parameter_gradient_matches_finite_differences():
+    """dJ/d ln k1_e, dJ/d ln k2_e, dJ/d beta for J = ||p1 - p1_obs||^2 against
+    central differences of the oracle's own forward solves."""
+    prob = I.grf_problem(3, 3)
+    S = dpp.assemble(prob)
+    F = dpp.fields(3, S.N)
+    obs = I.random_vector(S.N, 9)
+
+    def J_of(k1, k2, beta):
+        pr = I.grf_problem(3, 3)
+        pr.k1, pr.k2, pr.beta = k1, k2, beta
+        Sx = dpp.assemble(pr)
+        x = dpp.solve_direct(Sx.K, Sx.f)
+        return np.sum((x[F["p1"]] - obs) ** 2)
+
+    x = dpp.solve_direct(S.K, S.f)
+    g = np.zeros_like(x)
+    g[F["p1"]] = 2.0 * (x[F["p1"]] - obs)
+    lam = solver.adjoint_solve(S, g)
+    g1, g2, gb = solver.param_gradient(S, prob, x, lam)
+    for j, d in enumerate(I.random_directions(3, prob.n_cells, seed0=4000)):
+        eps = 1e-5
+        for which, grad in ((0, g1), (1, g2)):
+            kp = [prob.k1.copy(), prob.k2.copy()]
+            km = [prob.k1.copy(), prob.k2.copy()]
+            kp[which] = kp[which] * np.exp(eps * d)
+            km[which] = km[which] * np.exp(-eps * d)
+            fd = (J_of(kp[0], kp[1], prob.beta) - J_of(km[0], km[1], prob.beta)) / (2 * eps)
+            assert grad @ d == pytest.approx(fd, rel=1e-5, abs=1e-9)
+    eps = 1e-5
+    fd = (J_of(prob.k1, prob.k2, prob.beta + eps) - J_of(prob.k1, prob.k2, prob.beta - eps)) / (2 * eps)
+    assert gb == pytest.approx(fd, rel=1e-5)
