@@ -1,0 +1,206 @@
+/*
+ * dpp.h -- C ABI of the MI355X (gfx950) solver library for the four-field
+ * double porosity/permeability (DPP) model discretised by the stabilised
+ * continuous-Galerkin CG-VMS formulation with equal-order P1 elements.
+ *
+ * Problem (paper, governing equations eq. DG_GE_Darcy_BLM):
+ *     mu k_i^-1 u_i + grad p_i = gamma b,   i = 1, 2
+ *     div u_1 = -(beta/mu)(p_1 - p_2),  div u_2 = +(beta/mu)(p_1 - p_2)
+ * with pressures p_i = p0_i imposed weakly on the whole boundary
+ * (eq. DG_GE_Darcy_pBC, linear functional L_Gal).  The discrete system
+ * K x = f (eq. S4_linear_problem) has the block entries of
+ * eq. S4_cg_stiffness_matrix and eq. S4_cg_rhs.
+ *
+ * Conventions shared by every entry point:
+ *   - All array arguments are DEVICE pointers on the current HIP device unless
+ *     stated otherwise; the caller owns them.  The library owns the opaque
+ *     handles (dpp_problem, dpp_precond) and their internal device memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  Work
+ *     is enqueued on it; calls that must return a scalar (solve statistics)
+ *     synchronise that stream before returning.
+ *   - Every function returns a dpp_status; nothing throws across the ABI.  On
+ *     failure dpp_last_error() returns a thread-local message.
+ *   - Mesh: box [0,L_x]x[0,L_y](x[0,L_z]) with n_x, n_y (, n_z) cells per side;
+ *     node id = i + (n_x+1)(j + (n_y+1)k); hexahedron h = i + n_x(j + n_y k) is
+ *     split into tetrahedra 6h+s (s = axis permutation, lexicographic; vertices
+ *     = corner then unit steps along the permuted axes); square h into
+ *     triangles 2h, 2h+1 (same rule).
+ *   - Unknown vector layout (length n_dof = (2d+2) n_nodes):
+ *       [u1 | p1 | u2 | p2], velocities node-major with the d components
+ *       interleaved (u_i at node a, component c sits at d*a + c of its block).
+ *     This is the field order 0..3 of the paper's solver listings.
+ */
+#ifndef DPP_H
+#define DPP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DPP_OK = 0,
+  DPP_ERR_ARG = 1,           /* invalid argument (null pointer, bad size, bad option) */
+  DPP_ERR_ALLOC = 2,         /* device allocation failed */
+  DPP_ERR_HIP = 3,           /* a HIP runtime call failed */
+  DPP_ERR_NOT_CONVERGED = 4, /* iteration limit reached; x holds the last iterate */
+  DPP_ERR_NUMERIC = 5,       /* NaN/Inf met in the input or the iteration */
+  DPP_ERR_BREAKDOWN = 6,     /* Krylov breakdown without convergence */
+  DPP_ERR_UNSUPPORTED = 7    /* valid request this version does not implement */
+} dpp_status;
+
+typedef struct dpp_problem_s *dpp_problem;
+typedef struct dpp_precond_s *dpp_precond;
+
+/* Structured box: dim 2 or 3, n[a] >= 1 cells per axis, L[a] > 0 extent. */
+typedef struct {
+  int dim;
+  int n[3];
+  double L[3];
+} dpp_box;
+
+/* Coefficients and boundary data (section "Boundary conditions"; parameters of
+ * the paper's data tables).  k1, k2: per-cell permeabilities [n_cells] (> 0).
+ * beta: scalar mass-transfer coefficient, used when beta_cells == NULL, else
+ * beta_cells [n_cells].  body: gamma*b per cell [n_cells*dim] or NULL (b = 0).
+ * p0_1, p0_2: nodal pressures [n_nodes]; only boundary nodes are read, and the
+ * boundary integral -(w.n; p0) uses their P1 interpolant exactly.
+ * facet_type must be NULL: velocity (flux) boundaries are not implemented and
+ * a non-NULL value returns DPP_ERR_UNSUPPORTED. */
+typedef struct {
+  double mu;
+  const double *k1;
+  const double *k2;
+  double beta;
+  const double *beta_cells;
+  const double *body;
+  const double *p0_1;
+  const double *p0_2;
+  const int8_t *facet_type;
+} dpp_params;
+
+/* Solver options; dpp_default_opts() fills the defaults in brackets.
+ *   restart [30]: flexible-GMRES restart length m (1..31).
+ *   maxiter [500]: total Krylov iterations (inner iterations in mixed mode).
+ *   rtol [1e-8]: stop when ||f - K x||_2 <= rtol ||f||_2 (true residual, FP64).
+ *   precision [0]: 0 = FP64 throughout; 1 = mixed: an inner flexible GMRES
+ *     with FP32 K and FP32 preconditioner (FP64 Arnoldi and coarse solve)
+ *     inside FP64 iterative refinement on the true residual; 2 = FP64 K and
+ *     Arnoldi with the FP32 preconditioner (FP64 coarse solve).
+ *   inner_rtol [1e-4], max_refine [20]: mixed mode only.
+ *   coarse_max [1000]: coarsest multigrid level has at most this many nodes
+ *     (1..4000).
+ *   cheb_degree [2], cheb_lo_frac [0.3], cheb_hi_factor [1.1], power_iters [15]:
+ *     Chebyshev smoother and its eigenvalue estimate.
+ *   use_graph [0]: capture one Arnoldi step in a hipGraph and replay it. */
+typedef struct {
+  int restart;
+  int maxiter;
+  double rtol;
+  int precision;
+  double inner_rtol;
+  int max_refine;
+  int coarse_max;
+  int cheb_degree;
+  double cheb_lo_frac;
+  double cheb_hi_factor;
+  int power_iters;
+  int use_graph;
+} dpp_solve_opts;
+
+typedef struct {
+  int iters;        /* Krylov iterations (all refinement sweeps together) */
+  int restarts;     /* GMRES restarts */
+  int refinements;  /* outer refinement sweeps (mixed mode), else 0 */
+  int converged;    /* 1 when the rtol test on the true residual passed */
+  double rel_residual; /* ||f - K x|| / ||f|| in FP64 at exit */
+  double ms_solve;  /* wall time of the call, milliseconds */
+} dpp_solve_stats;
+
+void dpp_default_opts(dpp_solve_opts *opts);
+const char *dpp_last_error(void);
+
+/* Assemble K and f (eq. S4_cg_stiffness_matrix, eq. S4_cg_rhs) on the device.
+ * Input arrays are read during the call only (copies are kept for the
+ * parameter gradient).  *out receives a new handle. */
+dpp_status dpp_assemble(const dpp_box *box, const dpp_params *params, void *stream,
+                        dpp_problem *out);
+
+/* Sizes of an assembled problem (host outputs; any may be NULL).  nnz is the
+ * number of structurally nonzero entries of K (22 per node pair in 3D, 16 in 2D). */
+dpp_status dpp_problem_sizes(dpp_problem prob, int64_t *n_dof, int64_t *n_nodes,
+                             int64_t *n_cells, int64_t *nnz);
+
+/* Copy the assembled right-hand side f into f_out [n_dof]. */
+dpp_status dpp_rhs(dpp_problem prob, double *f_out, void *stream);
+
+/* Test/inspection hook: write K in CSR form (columns ascending in each row)
+ * into rowptr [n_dof+1] (int64), cols [nnz] (int32), vals [nnz]. */
+dpp_status dpp_export_csr(dpp_problem prob, int64_t *rowptr, int32_t *cols, double *vals,
+                          void *stream);
+
+/* y = A x for a block of K (section "Proposed four-field solvers", the 2x2
+ * block views of Method 1 / Method 2):
+ *   which 0: A = K              x, y: [n_dof]
+ *   which 1/2: A = K_up^1 / K_up^2   x: [n_nodes], y: [dim*n_nodes]
+ *   which 3/4: A = K_pu^1 / K_pu^2   x: [dim*n_nodes], y: [n_nodes]
+ * FP64. */
+dpp_status dpp_spmv(dpp_problem prob, int which, const double *x, double *y, void *stream);
+
+/* Build the Schur fieldsplit preconditioner (Method 2 of the solver section):
+ * diag(K_uu^i)^-1, the selfp Schur blocks S_p^i = K_pp^i - K_pu^i
+ * diag(K_uu^i)^-1 K_up^i (eqs. S4_sp1, S4_sp2) and one geometric multigrid
+ * hierarchy per S_p^i.  opts may be NULL (defaults). */
+dpp_status dpp_setup_precond(dpp_problem prob, const dpp_solve_opts *opts, void *stream,
+                             dpp_precond *out);
+
+/* Number of multigrid levels, cells per axis of each level (level_n[3*l+a]),
+ * and the Chebyshev upper bound per level and network (hi[2*l+i]); host
+ * outputs, arrays sized for 16 levels; any may be NULL. */
+dpp_status dpp_precond_info(dpp_precond pc, int *n_levels, int *level_n, double *hi);
+
+/* z = P^-1 r: one application of the fieldsplit preconditioner
+ * (Jacobi on the velocities, one V-cycle per S_p^i), FP64, x/z: [n_dof]. */
+dpp_status dpp_precond_apply(dpp_precond pc, const double *r, double *z, void *stream);
+
+/* One V-cycle on both pressure Schur blocks: b, x: [2*n_nodes], network 1
+ * first.  Test hook. */
+dpp_status dpp_vcycle(dpp_precond pc, const double *b, double *x, void *stream);
+
+/* y = A_l x with the level-l operator of network net (level 0 = S_p^net);
+ * x, y: [nodes of level l].  Test hook. */
+dpp_status dpp_level_spmv(dpp_precond pc, int level, int net, const double *x, double *y,
+                          void *stream);
+
+/* Solve K x = rhs (rhs NULL = the assembled f) by flexible GMRES(m)
+ * preconditioned with pc (the outer GMRES picks up the inter-network coupling
+ * the preconditioner drops).  x: in = initial guess, out = solution.  stats may
+ * be NULL.  Returns DPP_ERR_NOT_CONVERGED (x = last iterate, stats filled)
+ * when maxiter is reached. */
+dpp_status dpp_solve(dpp_problem prob, dpp_precond pc, const dpp_solve_opts *opts,
+                     const double *rhs, double *x, dpp_solve_stats *stats, void *stream);
+
+/* Adjoint solve K^T lambda = g.  Uses K^T = D K D with D = diag(I_u, -I_p)
+ * (D K is symmetric because K_pu = -K_up^T and K_pp, K_uu are symmetric), so
+ * lambda = D * solve(K, D g) with the same preconditioner.  lambda: [n_dof]
+ * (zero initial guess). */
+dpp_status dpp_solve_adjoint(dpp_problem prob, dpp_precond pc, const dpp_solve_opts *opts,
+                             const double *g, double *lambda, dpp_solve_stats *stats,
+                             void *stream);
+
+/* Gradient of J(x(theta)) given x (K x = f) and lambda (K^T lambda = dJ/dx),
+ * boundary data held fixed:  dJ/dtheta = -lambda^T (dK/dtheta) x, for
+ * theta = ln k1_e, ln k2_e (outputs [n_cells]) and the scalar beta (g_beta [1],
+ * or [n_cells] per-cell derivatives when the problem was assembled with
+ * beta_cells).  Any output may be NULL. */
+dpp_status dpp_param_grad(dpp_problem prob, const double *x, const double *lambda,
+                          double *g_logk1, double *g_logk2, double *g_beta, void *stream);
+
+void dpp_destroy_problem(dpp_problem prob);
+void dpp_destroy_precond(dpp_precond pc);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPP_H */

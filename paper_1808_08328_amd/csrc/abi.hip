@@ -1,0 +1,310 @@
+// extern "C" entry points: argument checks, status codes, the solve drivers
+// (plain FP64, FP32-preconditioned, and FP64 iterative refinement around an
+// FP32 inner flexible GMRES) and the adjoint solve.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "objects.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+dpp_status guard(F &&f) {
+  try {
+    f();
+    g_last_error.clear();
+    return DPP_OK;
+  } catch (const dpp::Error &e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return DPP_ERR_ALLOC;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return DPP_ERR_HIP;
+  }
+}
+
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+void check_opts(const dpp_solve_opts &o) {
+  DPP_CHECK(o.restart >= 1 && o.restart <= 31, DPP_ERR_ARG, "restart must be in 1..31");
+  DPP_CHECK(o.maxiter >= 0, DPP_ERR_ARG, "maxiter must be >= 0");
+  DPP_CHECK(o.rtol > 0.0 && o.rtol < 1.0, DPP_ERR_ARG, "rtol must be in (0, 1)");
+  DPP_CHECK(o.precision >= 0 && o.precision <= 2, DPP_ERR_ARG, "precision must be 0, 1 or 2");
+  DPP_CHECK(o.inner_rtol > 0.0 && o.inner_rtol < 1.0, DPP_ERR_ARG, "inner_rtol must be in (0, 1)");
+  DPP_CHECK(o.max_refine >= 1, DPP_ERR_ARG, "max_refine must be >= 1");
+  DPP_CHECK(o.coarse_max >= 1 && o.coarse_max <= 4000, DPP_ERR_ARG, "coarse_max must be in 1..4000");
+  DPP_CHECK(o.cheb_degree >= 1 && o.cheb_degree <= 8, DPP_ERR_ARG, "cheb_degree must be in 1..8");
+  DPP_CHECK(o.cheb_lo_frac > 0.0 && o.cheb_lo_frac < 1.0, DPP_ERR_ARG, "cheb_lo_frac must be in (0,1)");
+  DPP_CHECK(o.cheb_hi_factor >= 1.0, DPP_ERR_ARG, "cheb_hi_factor must be >= 1");
+  DPP_CHECK(o.power_iters >= 1, DPP_ERR_ARG, "power_iters must be >= 1");
+}
+
+void set_device_of(const void *p) {
+  hipPointerAttribute_t at;
+  if (p && hipPointerGetAttributes(&at, p) == hipSuccess && at.type == hipMemoryTypeDevice)
+    DPP_HIP(hipSetDevice(at.device));
+}
+
+}  // namespace
+
+extern "C" {
+
+void dpp_default_opts(dpp_solve_opts *o) {
+  if (!o) return;
+  o->restart = 30;
+  o->maxiter = 500;
+  o->rtol = 1e-8;
+  o->precision = 0;
+  o->inner_rtol = 1e-4;
+  o->max_refine = 20;
+  o->coarse_max = 1000;
+  o->cheb_degree = 2;
+  o->cheb_lo_frac = 0.3;
+  o->cheb_hi_factor = 1.1;
+  o->power_iters = 15;
+  o->use_graph = 0;
+}
+
+const char *dpp_last_error(void) { return g_last_error.c_str(); }
+
+dpp_status dpp_assemble(const dpp_box *box, const dpp_params *params, void *stream,
+                        dpp_problem *out) {
+  return guard([&] {
+    DPP_CHECK(out, DPP_ERR_ARG, "null output handle");
+    *out = nullptr;
+    DPP_CHECK(params, DPP_ERR_ARG, "null params");
+    set_device_of(params->k1);
+    auto *P = new dpp_problem_s();
+    try {
+      dpp::assemble_problem(P, box, params, S(stream));
+      DPP_HIP(hipStreamSynchronize(S(stream)));
+    } catch (...) {
+      delete P;
+      throw;
+    }
+    *out = P;
+  });
+}
+
+dpp_status dpp_problem_sizes(dpp_problem P, int64_t *n_dof, int64_t *n_nodes, int64_t *n_cells,
+                             int64_t *nnz) {
+  return guard([&] {
+    DPP_CHECK(P, DPP_ERR_ARG, "null problem");
+    if (n_dof) *n_dof = P->ndof();
+    if (n_nodes) *n_nodes = P->g.N;
+    if (n_cells) *n_cells = P->g.nc;
+    if (nnz) *nnz = P->nnz;
+  });
+}
+
+dpp_status dpp_rhs(dpp_problem P, double *f_out, void *stream) {
+  return guard([&] {
+    DPP_CHECK(P && f_out, DPP_ERR_ARG, "null argument");
+    DPP_HIP(hipMemcpyAsync(f_out, P->f.ptr, sizeof(double) * P->ndof(), hipMemcpyDeviceToDevice,
+                           S(stream)));
+  });
+}
+
+dpp_status dpp_export_csr(dpp_problem P, int64_t *rowptr, int32_t *cols, double *vals, void *stream) {
+  return guard([&] {
+    DPP_CHECK(P && rowptr && cols && vals, DPP_ERR_ARG, "null argument");
+    dpp::export_csr(P, rowptr, cols, vals, S(stream));
+  });
+}
+
+dpp_status dpp_spmv(dpp_problem P, int which, const double *x, double *y, void *stream) {
+  return guard([&] {
+    DPP_CHECK(P && x && y, DPP_ERR_ARG, "null argument");
+    DPP_CHECK(which >= 0 && which <= 4, DPP_ERR_ARG, "which must be 0..4");
+    DPP_CHECK(x != y, DPP_ERR_ARG, "x and y must not alias");
+    if (which == 0)
+      dpp::spmv_K(P, x, y, S(stream));
+    else
+      dpp::spmv_block(P, which, x, y, S(stream));
+  });
+}
+
+dpp_status dpp_setup_precond(dpp_problem P, const dpp_solve_opts *opts, void *stream,
+                             dpp_precond *out) {
+  return guard([&] {
+    DPP_CHECK(P && out, DPP_ERR_ARG, "null argument");
+    *out = nullptr;
+    auto *pc = new dpp_precond_s();
+    pc->prob = P;
+    if (opts)
+      pc->opts = *opts;
+    else
+      dpp_default_opts(&pc->opts);
+    try {
+      check_opts(pc->opts);
+      dpp::precond_setup(pc, S(stream));
+    } catch (...) {
+      delete pc;
+      throw;
+    }
+    *out = pc;
+  });
+}
+
+dpp_status dpp_precond_info(dpp_precond pc, int *n_levels, int *level_n, double *hi) {
+  return guard([&] {
+    DPP_CHECK(pc, DPP_ERR_ARG, "null preconditioner");
+    const int nl = (int)pc->lv.size();
+    if (n_levels) *n_levels = nl;
+    for (int l = 0; l < nl && l < 16; ++l) {
+      if (level_n)
+        for (int a = 0; a < 3; ++a) level_n[3 * l + a] = pc->lv[l]->g.n[a];
+      if (hi)
+        for (int q = 0; q < 2; ++q) hi[2 * l + q] = pc->lv[l]->hi[q];
+    }
+  });
+}
+
+dpp_status dpp_precond_apply(dpp_precond pc, const double *r, double *z, void *stream) {
+  return guard([&] {
+    DPP_CHECK(pc && r && z && r != z, DPP_ERR_ARG, "bad argument");
+    dpp::precond_apply(pc, r, z, false, S(stream));
+  });
+}
+
+dpp_status dpp_vcycle(dpp_precond pc, const double *b, double *x, void *stream) {
+  return guard([&] {
+    DPP_CHECK(pc && b && x && b != x, DPP_ERR_ARG, "bad argument");
+    dpp::vcycle(pc, b, x, S(stream));
+  });
+}
+
+dpp_status dpp_level_spmv(dpp_precond pc, int level, int net, const double *x, double *y,
+                          void *stream) {
+  return guard([&] {
+    DPP_CHECK(pc && x && y, DPP_ERR_ARG, "null argument");
+    DPP_CHECK(level >= 0 && level < (int)pc->lv.size(), DPP_ERR_ARG, "level out of range");
+    DPP_CHECK(net == 0 || net == 1, DPP_ERR_ARG, "net must be 0 or 1");
+    dpp::level_spmv(pc, level, net, x, y, S(stream));
+  });
+}
+
+static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_opts *opts,
+                               const double *rhs, double *x, dpp_solve_stats *stats, void *stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  dpp::SolveResult res;
+  int refine = 0;
+  dpp_status st = guard([&] {
+    DPP_CHECK(P && pc && x, DPP_ERR_ARG, "null argument");
+    DPP_CHECK(pc->prob == P, DPP_ERR_ARG, "preconditioner belongs to another problem");
+    dpp_solve_opts o = pc->opts;
+    if (opts) {
+      o = *opts;
+      // the multigrid hierarchy is fixed at setup
+      o.coarse_max = pc->opts.coarse_max;
+      o.power_iters = pc->opts.power_iters;
+      o.cheb_lo_frac = pc->opts.cheb_lo_frac;
+      o.cheb_hi_factor = pc->opts.cheb_hi_factor;
+      pc->opts.cheb_degree = o.cheb_degree;
+    }
+    check_opts(o);
+    hipStream_t s = S(stream);
+    const double *b = rhs ? rhs : P->f.as<double>();
+    const long n = P->ndof();
+    if (!pc->part.ptr) pc->part.alloc(sizeof(double) * 34 * 1024);
+    const double bn = dpp::norm2(b, n, pc->part.as<double>(), s);
+    DPP_CHECK(std::isfinite(bn), DPP_ERR_NUMERIC, "right-hand side holds NaN/Inf");
+    if (o.precision != 1) {
+      if (o.precision == 2) dpp::precond_make32(pc, s);
+      res = dpp::fgmres(P, pc, o, b, x, o.precision == 2 ? 2 : 0, o.rtol, o.maxiter, bn, s);
+    } else {
+      dpp::precond_make32(pc, s);
+      if (!pc->xtmp.ptr) {
+        pc->xtmp.alloc(sizeof(double) * n);
+        pc->rtmp.alloc(sizeof(double) * n);
+      }
+      double *e = pc->xtmp.as<double>(), *r = pc->rtmp.as<double>();
+      while (true) {
+        dpp::residual_K(P, b, x, r, s);
+        const double rn = dpp::norm2(r, n, pc->part.as<double>(), s);
+        res.rel = bn > 0 ? rn / bn : 0.0;
+        DPP_CHECK(std::isfinite(rn), DPP_ERR_NUMERIC, "NaN/Inf in the refinement residual");
+        if (rn <= o.rtol * bn) {
+          res.converged = 1;
+          res.status = DPP_OK;
+          break;
+        }
+        if (res.iters >= o.maxiter || refine >= o.max_refine) {
+          res.status = DPP_ERR_NOT_CONVERGED;
+          break;
+        }
+        DPP_HIP(hipMemsetAsync(e, 0, sizeof(double) * n, s));
+        dpp::SolveResult in = dpp::fgmres(P, pc, o, r, e, 1, o.inner_rtol, o.maxiter - res.iters, rn, s);
+        if (in.status == DPP_ERR_NUMERIC) {
+          res.status = in.status;
+          break;
+        }
+        dpp::axpby(n, 1.0, e, 1.0, x, s);
+        res.iters += in.iters;
+        res.restarts += in.restarts;
+        ++refine;
+      }
+    }
+    DPP_HIP(hipStreamSynchronize(s));
+    if (res.status != DPP_OK) {
+      throw dpp::Error(res.status, res.status == DPP_ERR_NOT_CONVERGED
+                                       ? "iteration limit reached before the tolerance"
+                                       : res.status == DPP_ERR_NUMERIC ? "NaN/Inf in the iteration"
+                                                                      : "Krylov breakdown");
+    }
+  });
+  if (stats) {
+    stats->refinements = refine;
+    stats->iters = res.iters;
+    stats->restarts = res.restarts;
+    stats->converged = res.converged;
+    stats->rel_residual = res.rel;
+    stats->ms_solve =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return st;
+}
+
+dpp_status dpp_solve(dpp_problem P, dpp_precond pc, const dpp_solve_opts *opts, const double *rhs,
+                     double *x, dpp_solve_stats *stats, void *stream) {
+  return solve_common(P, pc, opts, rhs, x, stats, stream);
+}
+
+dpp_status dpp_solve_adjoint(dpp_problem P, dpp_precond pc, const dpp_solve_opts *opts,
+                             const double *g, double *lambda, dpp_solve_stats *stats, void *stream) {
+  dpp::DBuf dg;
+  dpp_status st = guard([&] {
+    DPP_CHECK(P && pc && g && lambda && g != lambda, DPP_ERR_ARG, "bad argument");
+    const long n = P->ndof();
+    dg.alloc(sizeof(double) * n);
+    dpp::flip_pressure_sign(P, g, dg.as<double>(), S(stream));
+    DPP_HIP(hipMemsetAsync(lambda, 0, sizeof(double) * n, S(stream)));
+  });
+  if (st != DPP_OK) return st;
+  st = solve_common(P, pc, opts, dg.as<double>(), lambda, stats, stream);
+  if (st != DPP_OK && st != DPP_ERR_NOT_CONVERGED) return st;
+  dpp_status st2 = guard([&] {
+    dpp::flip_pressure_sign(P, lambda, lambda, S(stream));
+    DPP_HIP(hipStreamSynchronize(S(stream)));
+  });
+  return st2 != DPP_OK ? st2 : st;
+}
+
+dpp_status dpp_param_grad(dpp_problem P, const double *x, const double *lambda, double *g_logk1,
+                          double *g_logk2, double *g_beta, void *stream) {
+  return guard([&] {
+    DPP_CHECK(P && x && lambda, DPP_ERR_ARG, "null argument");
+    dpp::param_grad(P, x, lambda, g_logk1, g_logk2, g_beta, S(stream));
+  });
+}
+
+void dpp_destroy_problem(dpp_problem P) { delete P; }
+void dpp_destroy_precond(dpp_precond pc) { delete pc; }
+
+}  // extern "C"

@@ -1,0 +1,414 @@
+// Assembly of the CG-VMS four-field DPP system on the device.
+//
+// K entries follow eq. S4_cg_stiffness_matrix (CG-VMS weak form
+// eq. CG_VMS_Weak_form, P1 on the Kuhn simplices of a structured box); f
+// follows eq. S4_cg_rhs with the pressure data imposed weakly,
+// -(w.n ; p0) over the boundary, p0 the P1 nodal interpolant.
+//
+// Storage: for every node a and every offset t of the node stencil St the
+// 4d+5 distinct values of the node-pair block (a, a+o_t) are kept in
+// structure-of-arrays form, kv[(v*NS + t)*N + a] (v = value kind, see
+// common.h).  Entries of pairs leaving the box are zero.  Each (a, t) is
+// computed by one thread that sums the contributions of the simplices holding
+// both nodes in a fixed order: no atomics, bit-reproducible.
+#include "objects.h"
+
+namespace dpp {
+
+namespace {
+
+// Axis permutations in lexicographic order: simplex s of a box cell visits
+// the corner, then steps along perm[s][0], perm[s][1] (, perm[s][2]).
+__device__ inline int perm_axis(int D, int s, int k) {
+  if (D == 2) return (s == 0) ? k : 1 - k;
+  const int P[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  return P[s][k];
+}
+
+// Local vertex index of the corner-relative binary offset `bits` in simplex s,
+// or -1 when it is not a vertex of that simplex.
+template <int D>
+__device__ inline int local_vertex(int s, int bits) {
+  int mask = 0;
+  if (bits == 0) return 0;
+  for (int k = 0; k < D; ++k) {
+    mask |= 1 << perm_axis(D, s, k);
+    if (mask == bits) return k + 1;
+  }
+  return -1;
+}
+
+// Component c of grad(lambda_k) on simplex s with cell sizes h:
+// lambda_0 = 1 - y_{p0}, lambda_k = y_{p(k-1)} - y_{pk}, lambda_D = y_{p(D-1)}.
+template <int D>
+__device__ inline double grad_lambda(int s, int k, int c, const double *h) {
+  double g = 0.0;
+  if (k >= 1 && perm_axis(D, s, k - 1) == c) g += 1.0 / h[c];
+  if (k < D && perm_axis(D, s, k) == c) g -= 1.0 / h[c];
+  return g;
+}
+
+struct Coef {
+  const double *k1, *k2, *betac;
+  double beta, mu;
+  double h[3];
+};
+
+template <int D>
+__global__ __launch_bounds__(256) void k_assemble(GridDev g, Coef cf, double *__restrict__ kv) {
+  constexpr int NS = Tabs<D>::NS;
+  constexpr int NV = nv_kinds(D);
+  const long N = g.N;
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * NS) return;
+  const int t = (int)(idx / N);
+  const long a = idx - (long)t * N;
+  int ia[3];
+  node_ijk(g, a, ia[0], ia[1], ia[2]);
+  const int *o = TAB<D>.so[t];
+  double uu[2] = {0, 0}, up[2][D], pu[2][D], pp[2] = {0, 0}, k12 = 0.0;
+  for (int q = 0; q < 2; ++q)
+    for (int c = 0; c < D; ++c) up[q][c] = pu[q][c] = 0.0;
+  const bool valid = inside(g, ia[0] + o[0], ia[1] + o[1], ia[2] + o[2]);
+  if (valid) {
+    const double vol = (D == 3) ? cf.h[0] * cf.h[1] * cf.h[2] / 6.0 : cf.h[0] * cf.h[1] / 2.0;
+    const double avg = vol / (D + 1);
+    const double moff = vol / ((D + 1.0) * (D + 2.0));
+    const int nper = (D == 3) ? 6 : 2;
+    for (int sb = 0; sb < (1 << D); ++sb) {       // box cells around a
+      int cc[3] = {0, 0, 0}, sa = sb, sbb = 0;
+      bool ok = true;
+      for (int ax = 0; ax < D; ++ax) {
+        int bit = (sb >> ax) & 1;
+        cc[ax] = ia[ax] - bit;
+        if (cc[ax] < 0 || cc[ax] >= g.n[ax]) ok = false;
+        int ob = bit + o[ax];                       // offset of b from the corner
+        if (ob < 0 || ob > 1) ok = false;
+        sbb |= (ob & 1) << ax;
+      }
+      if (!ok) continue;
+      long hexid = cc[0] + (long)g.n[0] * (cc[1] + (long)g.n[1] * cc[2]);
+      for (int s = 0; s < nper; ++s) {
+        int la = local_vertex<D>(s, sa), lb = local_vertex<D>(s, sbb);
+        if (la < 0 || lb < 0) continue;
+        long e = hexid * nper + s;
+        double ga[D], gb[D], gg = 0.0;
+        for (int c = 0; c < D; ++c) {
+          ga[c] = grad_lambda<D>(s, la, c, cf.h);
+          gb[c] = grad_lambda<D>(s, lb, c, cf.h);
+          gg += ga[c] * gb[c];
+        }
+        const double M = moff * (la == lb ? 2.0 : 1.0);
+        const double bm = (cf.betac ? cf.betac[e] : cf.beta) / cf.mu;
+        for (int q = 0; q < 2; ++q) {
+          const double kk = q ? cf.k2[e] : cf.k1[e];
+          uu[q] += 0.5 * (cf.mu / kk) * M;                 // 1/2 (w; mu/k u)
+          for (int c = 0; c < D; ++c) {
+            up[q][c] += -ga[c] * avg - 0.5 * gb[c] * avg;   // -(div w;p) - 1/2 (w;grad p)
+            pu[q][c] += gb[c] * avg + 0.5 * ga[c] * avg;    // (q;div u) + 1/2 (grad q;u)
+          }
+          pp[q] += 0.5 * (kk / cf.mu) * vol * gg + bm * M;  // 1/2 (grad q;k/mu grad p) + (q;beta/mu p)
+        }
+        k12 += -bm * M;                                     // -(q1; beta/mu p2)
+      }
+    }
+  }
+  const size_t vs = (size_t)NS * N;
+  double *base = kv + (size_t)t * N + a;
+  for (int q = 0; q < 2; ++q) {
+    base[kv_uu(D, q) * vs] = uu[q];
+    for (int c = 0; c < D; ++c) {
+      base[kv_up(D, q, c) * vs] = up[q][c];
+      base[kv_pu(D, q, c) * vs] = pu[q][c];
+    }
+    base[kv_pp(D, q) * vs] = pp[q];
+  }
+  base[kv_12(D) * vs] = k12;
+  (void)NV;
+}
+
+// Right-hand side, one thread per node: body-force terms
+// 1/2 (w; gamma b) and 1/2 (grad q; k/mu gamma b) over the incident simplices,
+// and -(w.n; p0) over the boundary facets holding the node.  On every face of
+// the box the facets are the 2D Kuhn triangles of that face's grid (in-plane
+// axes in ascending order).
+template <int D>
+__global__ __launch_bounds__(256) void k_rhs(GridDev g, Coef cf, const double *__restrict__ body,
+                                             const double *__restrict__ p01,
+                                             const double *__restrict__ p02, double *__restrict__ f) {
+  const long N = g.N;
+  long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  int ia[3];
+  node_ijk(g, a, ia[0], ia[1], ia[2]);
+  double fu[2][D], fp[2] = {0, 0};
+  for (int q = 0; q < 2; ++q)
+    for (int c = 0; c < D; ++c) fu[q][c] = 0.0;
+  const long stride[3] = {1, (long)g.m[0], (long)g.m[0] * g.m[1]};
+  if (body) {
+    const double vol = (D == 3) ? cf.h[0] * cf.h[1] * cf.h[2] / 6.0 : cf.h[0] * cf.h[1] / 2.0;
+    const double avg = vol / (D + 1);
+    const int nper = (D == 3) ? 6 : 2;
+    for (int sb = 0; sb < (1 << D); ++sb) {
+      int cc[3] = {0, 0, 0};
+      bool ok = true;
+      for (int ax = 0; ax < D; ++ax) {
+        cc[ax] = ia[ax] - ((sb >> ax) & 1);
+        if (cc[ax] < 0 || cc[ax] >= g.n[ax]) ok = false;
+      }
+      if (!ok) continue;
+      long hexid = cc[0] + (long)g.n[0] * (cc[1] + (long)g.n[1] * cc[2]);
+      for (int s = 0; s < nper; ++s) {
+        int la = local_vertex<D>(s, sb);
+        if (la < 0) continue;
+        long e = hexid * nper + s;
+        for (int q = 0; q < 2; ++q) {
+          const double kk = q ? cf.k2[e] : cf.k1[e];
+          double acc = 0.0;
+          for (int c = 0; c < D; ++c) {
+            const double gb = body[e * D + c];
+            fu[q][c] += 0.5 * gb * avg;                     // (w;gb) - 1/2 (mu/k w; k/mu gb)
+            acc += grad_lambda<D>(s, la, c, cf.h) * gb;
+          }
+          fp[q] += 0.5 * (kk / cf.mu) * vol * acc;          // 1/2 (grad q; k/mu gb)
+        }
+      }
+    }
+  }
+  for (int ax = 0; ax < D; ++ax) {
+    for (int side = 0; side < 2; ++side) {
+      if (ia[ax] != (side ? g.n[ax] : 0)) continue;
+      const double nrm = side ? 1.0 : -1.0;
+      double s1 = 0.0, s2 = 0.0;
+      if (D == 2) {
+        const int qa = 1 - ax;
+        for (int dn = -1; dn <= 1; dn += 2) {
+          int jq = ia[qa] + dn;
+          if (jq < 0 || jq > g.n[qa]) continue;
+          long b = a + dn * stride[qa];
+          const double w = cf.h[qa] / 6.0;                  // |F| (1 + delta) / (d (d+1))
+          s1 += w * (2.0 * p01[a] + p01[b]);
+          s2 += w * (2.0 * p02[a] + p02[b]);
+        }
+      } else {
+        const int pa = (ax == 0) ? 1 : 0, qa = (ax == 2) ? 1 : 2;
+        const double w = cf.h[pa] * cf.h[qa] / 2.0 / 12.0;
+        for (int sp = 0; sp < 2; ++sp)
+          for (int sq = 0; sq < 2; ++sq) {
+            int cp = ia[pa] - sp, cq = ia[qa] - sq;
+            if (cp < 0 || cp >= g.n[pa] || cq < 0 || cq >= g.n[qa]) continue;
+            long corner = a - sp * stride[pa] - sq * stride[qa];
+            // triangle 0: (0,0),(1,0),(1,1); triangle 1: (0,0),(0,1),(1,1)
+            for (int tri = 0; tri < 2; ++tri) {
+              int vp[3] = {0, tri == 0 ? 1 : 0, 1}, vq[3] = {0, tri == 0 ? 0 : 1, 1};
+              bool has = false;
+              for (int v = 0; v < 3; ++v)
+                if (vp[v] == sp && vq[v] == sq) has = true;
+              if (!has) continue;
+              for (int v = 0; v < 3; ++v) {
+                long b = corner + vp[v] * stride[pa] + vq[v] * stride[qa];
+                double wv = (b == a) ? 2.0 : 1.0;
+                s1 += w * wv * p01[b];
+                s2 += w * wv * p02[b];
+              }
+            }
+          }
+      }
+      fu[0][ax] -= nrm * s1;
+      fu[1][ax] -= nrm * s2;
+    }
+  }
+  for (int q = 0; q < 2; ++q) {
+    for (int c = 0; c < D; ++c) f[off_u(D, N, q) + (long)D * a + c] = fu[q][c];
+    f[off_p(D, N, q) + a] = fp[q];
+  }
+}
+
+// CSR export (test hook): one thread per node writes all 2d+2 rows of it.
+template <int D>
+__global__ void k_export(GridDev g, const double *__restrict__ kv, const int64_t *__restrict__ rowptr,
+                         int32_t *__restrict__ cols, double *__restrict__ vals) {
+  constexpr int NS = Tabs<D>::NS;
+  const long N = g.N;
+  long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  int ia[3];
+  node_ijk(g, a, ia[0], ia[1], ia[2]);
+  const size_t vs = (size_t)NS * N;
+  auto val = [&](int v, int t) { return kv[v * vs + (size_t)t * N + a]; };
+  auto nb = [&](int t, long &b) {
+    const int *o = TAB<D>.so[t];
+    if (!inside(g, ia[0] + o[0], ia[1] + o[1], ia[2] + o[2])) return false;
+    b = a + lin(g, o[0], o[1], o[2]);
+    return true;
+  };
+  for (int q = 0; q < 2; ++q) {
+    for (int c = 0; c < D; ++c) {
+      long row = off_u(D, N, q) + (long)D * a + c;
+      int64_t w = rowptr[row];
+      long b;
+      for (int t = 0; t < NS; ++t)
+        if (nb(t, b)) { cols[w] = (int32_t)(off_u(D, N, q) + D * b + c); vals[w++] = val(kv_uu(D, q), t); }
+      for (int t = 0; t < NS; ++t)
+        if (nb(t, b)) { cols[w] = (int32_t)(off_p(D, N, q) + b); vals[w++] = val(kv_up(D, q, c), t); }
+    }
+    long row = off_p(D, N, q) + a;
+    int64_t w = rowptr[row];
+    long b;
+    if (q == 1)
+      for (int t = 0; t < NS; ++t)
+        if (nb(t, b)) { cols[w] = (int32_t)(off_p(D, N, 0) + b); vals[w++] = val(kv_12(D), t); }
+    for (int t = 0; t < NS; ++t)
+      if (nb(t, b))
+        for (int c = 0; c < D; ++c) {
+          cols[w] = (int32_t)(off_u(D, N, q) + D * b + c);
+          vals[w++] = val(kv_pu(D, q, c), t);
+        }
+    for (int t = 0; t < NS; ++t)
+      if (nb(t, b)) { cols[w] = (int32_t)(off_p(D, N, q) + b); vals[w++] = val(kv_pp(D, q), t); }
+    if (q == 0)
+      for (int t = 0; t < NS; ++t)
+        if (nb(t, b)) { cols[w] = (int32_t)(off_p(D, N, 1) + b); vals[w++] = val(kv_12(D), t); }
+  }
+}
+
+template <int D>
+int count_neighbours_host(const Grid &g, long a) {
+  int ia[3] = {(int)(a % g.m[0]), (int)((a / g.m[0]) % g.m[1]), (int)(a / ((long)g.m[0] * g.m[1]))};
+  int cnt = 0;
+  for (int t = 0; t < Tabs<D>::NS; ++t) {
+    const int *o = TAB<D>.so[t];
+    bool ok = true;
+    for (int ax = 0; ax < 3; ++ax) {
+      int v = ia[ax] + o[ax];
+      if (v < 0 || v >= g.m[ax]) ok = false;
+    }
+    cnt += ok;
+  }
+  return cnt;
+}
+
+__global__ void k_check_positive(const double *v, long n, int *bad) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !(v[i] > 0.0 && v[i] < INFINITY)) bad[0] = 1;
+}
+
+__global__ void k_check_finite(const double *v, long n, int *bad) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !(fabs(v[i]) < INFINITY)) bad[0] = 1;
+}
+
+}  // namespace
+
+long count_nnz(const Grid &g) {
+  // node pairs (a, a+o) inside the box, summed over the stencil offsets
+  long pairs = 0;
+  auto count = [&](const int *o) {
+    long c = 1;
+    for (int ax = 0; ax < g.dim; ++ax) c *= (g.m[ax] - std::abs(o[ax]));
+    return c;
+  };
+  if (g.dim == 3)
+    for (int t = 0; t < Tabs<3>::NS; ++t) pairs += count(TAB<3>.so[t]);
+  else
+    for (int t = 0; t < Tabs<2>::NS; ++t) pairs += count(TAB<2>.so[t]);
+  return pairs * (g.dim == 3 ? 22 : 16);
+}
+
+static void check_input(const double *p, long n, bool positive, const char *name, hipStream_t s) {
+  DBuf flag(sizeof(int));
+  DPP_HIP(hipMemsetAsync(flag.ptr, 0, sizeof(int), s));
+  if (positive)
+    k_check_positive<<<blocks_for(n, 256), 256, 0, s>>>(p, n, flag.as<int>());
+  else
+    k_check_finite<<<blocks_for(n, 256), 256, 0, s>>>(p, n, flag.as<int>());
+  check_launch("check_input");
+  int h = 0;
+  DPP_HIP(hipMemcpyAsync(&h, flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+  DPP_HIP(hipStreamSynchronize(s));
+  DPP_CHECK(!h, DPP_ERR_NUMERIC, std::string(name) + " holds a non-finite or non-positive value");
+}
+
+void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, hipStream_t s) {
+  DPP_CHECK(box && prm, DPP_ERR_ARG, "null box or params");
+  DPP_CHECK(box->dim == 2 || box->dim == 3, DPP_ERR_ARG, "dim must be 2 or 3");
+  for (int a = 0; a < box->dim; ++a) {
+    DPP_CHECK(box->n[a] >= 1 && box->n[a] <= 4096, DPP_ERR_ARG, "cells per axis must be in 1..4096");
+    DPP_CHECK(box->L[a] > 0.0, DPP_ERR_ARG, "box extent must be positive");
+  }
+  DPP_CHECK(prm->facet_type == nullptr, DPP_ERR_UNSUPPORTED,
+            "velocity (flux) boundary facets are not supported: facet_type must be NULL");
+  DPP_CHECK(prm->k1 && prm->k2 && prm->p0_1 && prm->p0_2, DPP_ERR_ARG, "null coefficient array");
+  DPP_CHECK(prm->mu > 0.0, DPP_ERR_ARG, "mu must be positive");
+  Grid g = make_grid(box->dim, box->n, box->L);
+  const int D = g.dim;
+  const int NS = (D == 3) ? Tabs<3>::NS : Tabs<2>::NS;
+  DPP_CHECK((double)g.N * (2 * D + 2) < 2.0e9, DPP_ERR_ARG, "problem too large for 32-bit indices");
+  check_input(prm->k1, g.nc, true, "k1", s);
+  check_input(prm->k2, g.nc, true, "k2", s);
+  check_input(prm->p0_1, g.N, false, "p0_1", s);
+  check_input(prm->p0_2, g.N, false, "p0_2", s);
+  if (prm->beta_cells) check_input(prm->beta_cells, g.nc, false, "beta_cells", s);
+  if (prm->body) check_input(prm->body, g.nc * D, false, "body", s);
+  DPP_CHECK(std::isfinite(prm->beta) && prm->beta >= 0.0, DPP_ERR_ARG, "beta must be >= 0");
+
+  P->g = g;
+  P->mu = prm->mu;
+  P->beta = prm->beta;
+  P->beta_per_cell = prm->beta_cells != nullptr;
+  P->ns = NS;
+  P->nnz = count_nnz(g);
+  P->kvals.alloc(sizeof(double) * (size_t)nv_kinds(D) * NS * g.N);
+  P->f.alloc(sizeof(double) * P->ndof());
+  P->dinv.alloc(sizeof(double) * 2 * g.N);
+  P->k1.alloc(sizeof(double) * g.nc);
+  P->k2.alloc(sizeof(double) * g.nc);
+  DPP_HIP(hipMemcpyAsync(P->k1.ptr, prm->k1, sizeof(double) * g.nc, hipMemcpyDeviceToDevice, s));
+  DPP_HIP(hipMemcpyAsync(P->k2.ptr, prm->k2, sizeof(double) * g.nc, hipMemcpyDeviceToDevice, s));
+  if (prm->beta_cells) {
+    P->betac.alloc(sizeof(double) * g.nc);
+    DPP_HIP(hipMemcpyAsync(P->betac.ptr, prm->beta_cells, sizeof(double) * g.nc,
+                           hipMemcpyDeviceToDevice, s));
+  }
+  Coef cf{P->k1.as<double>(), P->k2.as<double>(), P->betac.as<double>(), prm->beta, prm->mu,
+          {g.h[0], g.h[1], g.h[2]}};
+  GridDev gd = dev(g);
+  long work = g.N * NS;
+  if (D == 3) {
+    k_assemble<3><<<blocks_for(work, 256), 256, 0, s>>>(gd, cf, P->kvals.as<double>());
+    k_rhs<3><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, cf, prm->body, prm->p0_1, prm->p0_2,
+                                                 P->f.as<double>());
+  } else {
+    k_assemble<2><<<blocks_for(work, 256), 256, 0, s>>>(gd, cf, P->kvals.as<double>());
+    k_rhs<2><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, cf, prm->body, prm->p0_1, prm->p0_2,
+                                                 P->f.as<double>());
+  }
+  check_launch("assemble");
+  make_dinv(P, s);
+}
+
+void export_csr(dpp_problem P, int64_t *rowptr, int32_t *cols, double *vals, hipStream_t s) {
+  const Grid &g = P->g;
+  const int D = g.dim;
+  const long N = g.N, nd = P->ndof();
+  std::vector<int64_t> rp(nd + 1, 0);
+  std::vector<int> m(N);
+  for (long a = 0; a < N; ++a) m[a] = (D == 3) ? count_neighbours_host<3>(g, a) : count_neighbours_host<2>(g, a);
+  long row = 0;
+  for (int q = 0; q < 2; ++q) {
+    for (long a = 0; a < N; ++a)
+      for (int c = 0; c < D; ++c, ++row) rp[row + 1] = rp[row] + 2 * m[a];
+    for (long a = 0; a < N; ++a, ++row) rp[row + 1] = rp[row] + (D + 2) * m[a];
+  }
+  DPP_CHECK(rp[nd] == P->nnz, DPP_ERR_HIP, "internal: CSR size mismatch");
+  DPP_HIP(hipMemcpyAsync(rowptr, rp.data(), sizeof(int64_t) * (nd + 1), hipMemcpyHostToDevice, s));
+  GridDev gd = dev(g);
+  if (D == 3)
+    k_export<3><<<blocks_for(N, 256), 256, 0, s>>>(gd, P->kvals.as<double>(), rowptr, cols, vals);
+  else
+    k_export<2><<<blocks_for(N, 256), 256, 0, s>>>(gd, P->kvals.as<double>(), rowptr, cols, vals);
+  check_launch("export_csr");
+  DPP_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace dpp

@@ -1,0 +1,222 @@
+// Internal definitions of the DPP library: errors, the structured box, the
+// stencil tables of the node-pair storage of K and of the pressure operators.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/dpp.h"
+
+namespace dpp {
+
+struct Error : std::runtime_error {
+  dpp_status status;
+  Error(dpp_status s, const std::string &m) : std::runtime_error(m), status(s) {}
+};
+
+#define DPP_HIP(call)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      throw ::dpp::Error(e_ == hipErrorOutOfMemory ? DPP_ERR_ALLOC : DPP_ERR_HIP,  \
+                         std::string(#call) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+#define DPP_CHECK(cond, status, msg)              \
+  do {                                            \
+    if (!(cond)) throw ::dpp::Error(status, msg); \
+  } while (0)
+
+inline void check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(DPP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- grid ----
+// Structured box: m[a] = n[a] + 1 nodes per axis (axis 2 unused in 2D:
+// n = 0, m = 1).
+struct Grid {
+  int dim = 3;
+  int n[3] = {1, 1, 0};
+  int m[3] = {2, 2, 1};
+  double h[3] = {1, 1, 1};
+  long N = 0;   // nodes
+  long nc = 0;  // simplices
+};
+
+inline Grid make_grid(int dim, const int *n, const double *L) {
+  Grid g;
+  g.dim = dim;
+  g.N = 1;
+  g.nc = (dim == 3) ? 6 : 2;
+  for (int a = 0; a < 3; ++a) {
+    if (a < dim) {
+      g.n[a] = n[a];
+      g.m[a] = n[a] + 1;
+      g.h[a] = (L ? L[a] : 1.0) / n[a];
+      g.N *= g.m[a];
+      g.nc *= n[a];
+    } else {
+      g.n[a] = 0;
+      g.m[a] = 1;
+      g.h[a] = 1.0;
+    }
+  }
+  return g;
+}
+
+// Coarse box of the multigrid hierarchy: ceil(n/2) cells per axis.
+inline Grid coarse_grid(const Grid &f) {
+  Grid g = f;
+  g.N = 1;
+  for (int a = 0; a < f.dim; ++a) {
+    g.n[a] = (f.n[a] + 1) / 2;
+    g.m[a] = g.n[a] + 1;
+    g.N *= g.m[a];
+  }
+  return g;
+}
+
+struct GridDev {
+  int n[3];
+  int m[3];
+  long N;
+};
+inline GridDev dev(const Grid &g) {
+  return GridDev{{g.n[0], g.n[1], g.n[2]}, {g.m[0], g.m[1], g.m[2]}, g.N};
+}
+
+// ---------------------------------------------------------- stencils ----
+// K couples node a with node a + o for o in the Kuhn node stencil St: 0 and
+// +-every nonzero binary vector (15 offsets in 3D, 7 in 2D).  The pressure
+// operators (selfp Schur blocks and every Galerkin coarse level) share the
+// stencil T = St - St (65 offsets in 3D, 19 in 2D, components in [-2, 2]).
+// Both lists are ordered by (dz, dy, dx), i.e. by linear node offset, so valid
+// neighbours of a node come out in ascending node id.
+template <int D>
+struct Tabs {
+  static constexpr int NS = D == 3 ? 15 : 7;
+  static constexpr int NT = D == 3 ? 65 : 19;
+  int so[NS][3];
+  int to[NT][3];
+  int sidx[27];   // (dx+1) + 3(dy+1) + 9(dz+1) -> index in St or -1
+  int tidx[125];  // (dx+2) + 5(dy+2) + 25(dz+2) -> index in T or -1
+  int s0;         // index of the zero offset in St
+  int t0;         // index of the zero offset in T
+};
+
+constexpr bool in_st(int dx, int dy, int dz) {
+  bool pos = dx >= 0 && dy >= 0 && dz >= 0 && dx <= 1 && dy <= 1 && dz <= 1;
+  bool neg = dx <= 0 && dy <= 0 && dz <= 0 && dx >= -1 && dy >= -1 && dz >= -1;
+  return pos || neg;
+}
+
+template <int D>
+constexpr Tabs<D> make_tabs() {
+  Tabs<D> t{};
+  const int zr = (D == 3) ? 1 : 0;
+  int k = 0;
+  for (int i = 0; i < 27; ++i) t.sidx[i] = -1;
+  for (int i = 0; i < 125; ++i) t.tidx[i] = -1;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx)
+        if (in_st(dx, dy, dz)) {
+          t.so[k][0] = dx;
+          t.so[k][1] = dy;
+          t.so[k][2] = dz;
+          if (dx == 0 && dy == 0 && dz == 0) t.s0 = k;
+          t.sidx[(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)] = k;
+          ++k;
+        }
+  int q = 0;
+  const int z2 = (D == 3) ? 2 : 0;
+  for (int dz = -z2; dz <= z2; ++dz)
+    for (int dy = -2; dy <= 2; ++dy)
+      for (int dx = -2; dx <= 2; ++dx) {
+        bool any = false;
+        for (int s = 0; s < Tabs<D>::NS; ++s) {
+          int ex = dx + t.so[s][0], ey = dy + t.so[s][1], ez = dz + t.so[s][2];
+          // t = s1 - s2 with s1 = t + s2 in St
+          if (in_st(ex, ey, ez) && (D == 3 || ez == 0)) any = true;
+        }
+        if (any) {
+          t.to[q][0] = dx;
+          t.to[q][1] = dy;
+          t.to[q][2] = dz;
+          if (dx == 0 && dy == 0 && dz == 0) t.t0 = q;
+          t.tidx[(dx + 2) + 5 * (dy + 2) + 25 * (dz + 2)] = q;
+          ++q;
+        }
+      }
+  return t;
+}
+
+template <int D>
+inline constexpr Tabs<D> TAB = make_tabs<D>();
+
+// Number of distinct value kinds stored per (offset, node) of K:
+// per network i: kuu (one scalar; the uu block is delta_cc' times it), kup[c],
+// kpu[c], kpp; plus k12 (the K12 = K21^T entry).  4d + 5 kinds.
+__host__ __device__ constexpr int nv_kinds(int dim) { return 4 * dim + 5; }
+__host__ __device__ constexpr int kv_uu(int dim, int net) { return net * (2 * dim + 2); }
+__host__ __device__ constexpr int kv_up(int dim, int net, int c) {
+  return net * (2 * dim + 2) + 1 + c;
+}
+__host__ __device__ constexpr int kv_pu(int dim, int net, int c) {
+  return net * (2 * dim + 2) + 1 + dim + c;
+}
+__host__ __device__ constexpr int kv_pp(int dim, int net) { return net * (2 * dim + 2) + 1 + 2 * dim; }
+__host__ __device__ constexpr int kv_12(int dim) { return 4 * dim + 4; }
+
+// Field offsets of the ABI vector layout [u1 | p1 | u2 | p2].
+__host__ __device__ inline long off_u(int dim, long N, int net) {
+  return net ? (long)(dim + 1) * N : 0;
+}
+__host__ __device__ inline long off_p(int dim, long N, int net) {
+  return net ? (long)(2 * dim + 1) * N : (long)dim * N;
+}
+
+// Node coordinates from its id.
+__device__ inline void node_ijk(const GridDev &g, long a, int &i, int &j, int &k) {
+  i = (int)(a % g.m[0]);
+  long r = a / g.m[0];
+  j = (int)(r % g.m[1]);
+  k = (int)(r / g.m[1]);
+}
+
+__device__ inline bool inside(const GridDev &g, int i, int j, int k) {
+  return i >= 0 && i < g.m[0] && j >= 0 && j < g.m[1] && k >= 0 && k < g.m[2];
+}
+
+__device__ inline long lin(const GridDev &g, int dx, int dy, int dz) {
+  return (long)dx + (long)g.m[0] * ((long)dy + (long)g.m[1] * dz);
+}
+
+// --------------------------------------------------------- XCD mapping ----
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with its own L2.  The remap gives every XCD one contiguous range of tiles
+// so that stencil neighbours mostly share an L2.
+__device__ inline int xcd_block(int bid, int nblk) {
+  const int nx = 8;
+  int per = (nblk + nx - 1) / nx;
+  int x = bid % nx, q = bid / nx;
+  int full = (nblk % nx == 0) ? nx : nblk % nx;  // XCDs that receive `per` blocks
+  int base = (x < full) ? x * per : full * per + (x - full) * (per - 1);
+  return base + q;
+}
+
+inline int blocks_for(long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// Two per-network pointers, passed by value.
+template <typename T>
+struct P2 {
+  T *p[2];
+};
+
+}  // namespace dpp

@@ -1,0 +1,585 @@
+// Multigrid V-cycle on the two pressure Schur blocks S_p^1, S_p^2 and the
+// Schur-complement fieldsplit application.
+//
+// The solver section applies one multigrid V-cycle to each diagonal block of
+// the selfp Schur approximation (eqs. S4_sp1, S4_sp2), relying on S_p being
+// spectrally equivalent to a Laplacian.  Here the cycle is geometric on the
+// structured box:
+//   * P: P1 interpolation from the box with ceil(n/2) cells per axis (coarse
+//     node C at fine index 2C, the last one at n when n is odd; a fine node
+//     with odd indices on the axes O averages the coarse nodes lo and lo+1_O,
+//     the ends of the Kuhn edge it sits on);
+//   * Galerkin coarse operators P^T A P, which keep the 65-point (19 in 2D)
+//     stencil of S_p on every level, so all levels share one index-free
+//     storage A[(i*NT + t)*N + a];
+//   * Chebyshev smoothing (degree `cheb_degree`, diagonal preconditioning,
+//     interval [lo_frac*hi, hi], hi = hi_factor * ||D^-1 A x_k|| after
+//     `power_iters` power steps from a fixed integer-hash start vector);
+//   * exact FP64 solve on the coarsest level through its inverse.
+// Both networks are processed by the same launches (blockIdx.y = network).
+#include "objects.h"
+
+namespace dpp {
+
+namespace {
+
+struct Sc2 {
+  double v[2];
+};
+
+__device__ inline void fine_to_coarse(int i, int n, int mc, int &lo, int &od) {
+  if ((n & 1) && i == n) {
+    lo = mc - 1;
+    od = 0;
+  } else {
+    lo = i >> 1;
+    od = i & 1;
+  }
+}
+
+__device__ inline int exact_fine(int c, int n, int mc) { return ((n & 1) && c == mc - 1) ? n : 2 * c; }
+
+// A x on a level, optionally returning b - A x and/or scaling by dinv.
+template <int D, typename TV, typename TX>
+__global__ __launch_bounds__(256) void k_lspmv(GridDev g, const TV *__restrict__ A,
+                                               const TX *__restrict__ x, TX *__restrict__ y,
+                                               const TX *__restrict__ b,
+                                               const TV *__restrict__ dinv) {
+  constexpr int NT = Tabs<D>::NT;
+  const long N = g.N;
+  const int q = blockIdx.y;
+  const long a = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  int i, j, k;
+  node_ijk(g, a, i, j, k);
+  const TV *Aq = A + (size_t)q * NT * N + a;
+  const TX *xq = x + (size_t)q * N;
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int *o = TAB<D>.to[t];
+    if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
+    acc += (double)Aq[(size_t)t * N] * (double)xq[a + lin(g, o[0], o[1], o[2])];
+  }
+  if (b) acc = (double)b[(size_t)q * N + a] - acc;
+  if (dinv) acc *= (double)dinv[(size_t)q * N + a];
+  y[(size_t)q * N + a] = (TX)acc;
+}
+
+// Chebyshev step k (Saad, Alg. 12.1 with diagonal preconditioning):
+//   r = D^-1 (b - A xin);  d = c1 d + c2 r;  xout = xin + d.
+// With zero_x the SpMV is skipped (xin = 0).
+template <int D, typename TV, typename TX>
+__global__ __launch_bounds__(256) void k_cheb(GridDev g, const TV *__restrict__ A,
+                                              const TV *__restrict__ dinv,
+                                              const TX *__restrict__ b, const TX *__restrict__ xin,
+                                              TX *__restrict__ xout, TX *__restrict__ d, Sc2 c1,
+                                              Sc2 c2, int zero_x) {
+  constexpr int NT = Tabs<D>::NT;
+  const long N = g.N;
+  const int q = blockIdx.y;
+  const long a = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  const size_t ia = (size_t)q * N + a;
+  double ax = 0.0, xa = 0.0;
+  if (!zero_x) {
+    int i, j, k;
+    node_ijk(g, a, i, j, k);
+    const TV *Aq = A + (size_t)q * NT * N + a;
+    const TX *xq = xin + (size_t)q * N;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int *o = TAB<D>.to[t];
+      if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
+      ax += (double)Aq[(size_t)t * N] * (double)xq[a + lin(g, o[0], o[1], o[2])];
+    }
+    xa = (double)xin[ia];
+  }
+  const double r = (double)dinv[ia] * ((double)b[ia] - ax);
+  const double dn = (c1.v[q] != 0.0 ? c1.v[q] * (double)d[ia] : 0.0) + c2.v[q] * r;
+  d[ia] = (TX)dn;
+  xout[ia] = (TX)(xa + dn);
+}
+
+// b_c(C) = sum_f P(f, C) r(f)
+template <int D, typename TX>
+__global__ __launch_bounds__(256) void k_restrict(GridDev gf, GridDev gc, const TX *__restrict__ r,
+                                                  TX *__restrict__ bc) {
+  const long Nc = gc.N;
+  const int q = blockIdx.y;
+  const long C = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (C >= Nc) return;
+  int cc[3];
+  node_ijk(gc, C, cc[0], cc[1], cc[2]);
+  const TX *rq = r + (size_t)q * gf.N;
+  int ex[3];
+  for (int ax = 0; ax < 3; ++ax) ex[ax] = exact_fine(cc[ax], gf.n[ax], gc.m[ax]);
+  auto fid = [&](const int *f) { return f[0] + (long)gf.m[0] * (f[1] + (long)gf.m[1] * f[2]); };
+  double acc = (double)rq[fid(ex)];
+  for (int mask = 1; mask < (1 << D); ++mask) {
+    int fu[3] = {ex[0], ex[1], ex[2]}, fd[3] = {ex[0], ex[1], ex[2]};
+    bool uok = true, dok = true;
+    for (int ax = 0; ax < D; ++ax) {
+      if (!((mask >> ax) & 1)) continue;
+      fu[ax] = 2 * cc[ax] + 1;
+      fd[ax] = 2 * cc[ax] - 1;
+      uok = uok && fu[ax] <= gf.n[ax] - 1;
+      dok = dok && fd[ax] >= 1 && fd[ax] <= gf.n[ax] - 1;
+    }
+    if (uok) acc += 0.5 * (double)rq[fid(fu)];
+    if (dok) acc += 0.5 * (double)rq[fid(fd)];
+  }
+  bc[(size_t)q * Nc + C] = (TX)acc;
+}
+
+// x(f) += (P e)(f)
+template <int D, typename TX>
+__global__ __launch_bounds__(256) void k_prolong(GridDev gf, GridDev gc, const TX *__restrict__ e,
+                                                 TX *__restrict__ x) {
+  const long N = gf.N;
+  const int q = blockIdx.y;
+  const long f = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (f >= N) return;
+  int fi[3];
+  node_ijk(gf, f, fi[0], fi[1], fi[2]);
+  int lo[3], od[3];
+  bool any = false;
+  for (int ax = 0; ax < 3; ++ax) {
+    fine_to_coarse(fi[ax], gf.n[ax], gc.m[ax], lo[ax], od[ax]);
+    any = any || od[ax];
+  }
+  const TX *eq = e + (size_t)q * gc.N;
+  const long c0 = lo[0] + (long)gc.m[0] * (lo[1] + (long)gc.m[1] * lo[2]);
+  double v = (double)eq[c0];
+  if (any) {
+    const long c1 = (lo[0] + od[0]) + (long)gc.m[0] * ((lo[1] + od[1]) + (long)gc.m[1] * (lo[2] + od[2]));
+    v = 0.5 * (v + (double)eq[c1]);
+  }
+  x[(size_t)q * N + f] = (TX)((double)x[(size_t)q * N + f] + v);
+}
+
+// Galerkin coarse operator A_c(C, C+t) = sum_{f, g} P(f,C) A(f,g) P(g,C+t).
+template <int D>
+__device__ inline int fine_support(const GridDev &gf, const GridDev &gc, const int *cc, int fs[][3],
+                                   double *w) {
+  int ex[3];
+  for (int ax = 0; ax < 3; ++ax) ex[ax] = exact_fine(cc[ax], gf.n[ax], gc.m[ax]);
+  int k = 0;
+  for (int ax = 0; ax < 3; ++ax) fs[0][ax] = ex[ax];
+  w[k++] = 1.0;
+  for (int mask = 1; mask < (1 << D); ++mask) {
+    int fu[3] = {ex[0], ex[1], ex[2]}, fd[3] = {ex[0], ex[1], ex[2]};
+    bool uok = true, dok = true;
+    for (int ax = 0; ax < D; ++ax) {
+      if (!((mask >> ax) & 1)) continue;
+      fu[ax] = 2 * cc[ax] + 1;
+      fd[ax] = 2 * cc[ax] - 1;
+      uok = uok && fu[ax] <= gf.n[ax] - 1;
+      dok = dok && fd[ax] >= 1 && fd[ax] <= gf.n[ax] - 1;
+    }
+    if (uok) {
+      for (int ax = 0; ax < 3; ++ax) fs[k][ax] = fu[ax];
+      w[k++] = 0.5;
+    }
+    if (dok) {
+      for (int ax = 0; ax < 3; ++ax) fs[k][ax] = fd[ax];
+      w[k++] = 0.5;
+    }
+  }
+  return k;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_galerkin(GridDev gf, GridDev gc, const double *__restrict__ A,
+                                                  double *__restrict__ Ac) {
+  constexpr int NT = Tabs<D>::NT;
+  constexpr int NS = Tabs<D>::NS;
+  const long Nc = gc.N;
+  const int q = blockIdx.y;
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= Nc * NT) return;
+  const int t = (int)(idx / Nc);
+  const long C = idx - (long)t * Nc;
+  int cc[3], c2[3];
+  node_ijk(gc, C, cc[0], cc[1], cc[2]);
+  const int *o = TAB<D>.to[t];
+  for (int ax = 0; ax < 3; ++ax) c2[ax] = cc[ax] + o[ax];
+  double acc = 0.0;
+  if (inside(gc, c2[0], c2[1], c2[2])) {
+    int fs[NS][3], gs[NS][3];
+    double wf[NS], wg[NS];
+    const int nf = fine_support<D>(gf, gc, cc, fs, wf);
+    const int ng = fine_support<D>(gf, gc, c2, gs, wg);
+    const double *Aq = A + (size_t)q * NT * gf.N;
+    for (int u = 0; u < nf; ++u) {
+      const long fidx = fs[u][0] + (long)gf.m[0] * (fs[u][1] + (long)gf.m[1] * fs[u][2]);
+      double s = 0.0;
+      for (int v = 0; v < ng; ++v) {
+        const int dx = gs[v][0] - fs[u][0], dy = gs[v][1] - fs[u][1], dz = gs[v][2] - fs[u][2];
+        if (dx < -2 || dx > 2 || dy < -2 || dy > 2 || dz < -2 || dz > 2) continue;
+        const int tt = TAB<D>.tidx[(dx + 2) + 5 * (dy + 2) + 25 * (dz + 2)];
+        if (tt < 0) continue;
+        s += wg[v] * Aq[(size_t)tt * gf.N + fidx];
+      }
+      acc += wf[u] * s;
+    }
+  }
+  Ac[((size_t)q * NT + t) * Nc + C] = acc;
+}
+
+template <int D>
+__global__ void k_diag_inv(GridDev g, const double *__restrict__ A, double *__restrict__ dinv) {
+  constexpr int NT = Tabs<D>::NT;
+  const long N = g.N;
+  const int q = blockIdx.y;
+  const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  dinv[(size_t)q * N + a] = 1.0 / A[((size_t)q * NT + TAB<D>.t0) * N + a];
+}
+
+template <int D>
+__global__ void k_dense_fill(GridDev g, const double *__restrict__ A, double *__restrict__ M) {
+  constexpr int NT = Tabs<D>::NT;
+  const long N = g.N;
+  const int q = blockIdx.y;
+  const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  int i, j, k;
+  node_ijk(g, a, i, j, k);
+  double *Mq = M + (size_t)q * N * N + (size_t)a * N;
+  for (long c = 0; c < N; ++c) Mq[c] = 0.0;
+  for (int t = 0; t < NT; ++t) {
+    const int *o = TAB<D>.to[t];
+    if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
+    Mq[a + lin(g, o[0], o[1], o[2])] = A[((size_t)q * NT + t) * N + a];
+  }
+}
+
+// In-place Gauss-Jordan inversion without pivoting (the coarse operators are
+// symmetric positive definite).  One workgroup per network.
+__global__ __launch_bounds__(1024) void k_gauss_jordan(double *__restrict__ M, int n) {
+  extern __shared__ double sh[];
+  double *rowk = sh, *colk = sh + n;
+  double *A = M + (size_t)blockIdx.x * n * n;
+  for (int k = 0; k < n; ++k) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      rowk[j] = A[(size_t)k * n + j];
+      colk[j] = A[(size_t)j * n + k];
+    }
+    __syncthreads();
+    const double p = rowk[k];
+    const double ip = 1.0 / p;
+    for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) {
+      const int i = (int)(e / n), j = (int)(e - (long)i * n);
+      double v;
+      if (i == k && j == k)
+        v = ip;
+      else if (i == k)
+        v = rowk[j] * ip;
+      else if (j == k)
+        v = -colk[i] * ip;
+      else
+        v = A[e] - colk[i] * rowk[j] * ip;
+      A[e] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// x = Cinv b on the coarsest level (FP64 arithmetic); one wavefront per row.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_coarse(const double *__restrict__ Cinv, int n,
+                                                const TX *__restrict__ b, TX *__restrict__ x) {
+  const int q = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const double *Mr = Cinv + (size_t)q * n * n + (size_t)row * n;
+  const TX *bq = b + (size_t)q * n;
+  double s = 0.0;
+  for (int c = lane; c < n; c += 64) s += Mr[c] * (double)bq[c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) x[(size_t)q * n + row] = (TX)s;
+}
+
+// Per-network sum of squares: partials [2][nblk], then a fixed-order final sum.
+__global__ __launch_bounds__(256) void k_sumsq2(const double *__restrict__ x, long n,
+                                                double *__restrict__ part) {
+  const int q = blockIdx.y;
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double v = x[(size_t)q * n + i];
+    s += v * v;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  __shared__ double w[4];
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[q * gridDim.x + blockIdx.x] = w[0] + w[1] + w[2] + w[3];
+}
+
+__global__ void k_sum2(const double *__restrict__ part, int nb, double *__restrict__ out) {
+  if (threadIdx.x < 2) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[threadIdx.x * nb + b];
+    out[threadIdx.x] = s;
+  }
+}
+
+__global__ void k_hash_start(double *__restrict__ x, long n) {
+  const int q = blockIdx.y;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned long long h = ((unsigned long long)i * 2654435761ull) & 0xffffffffull;
+  x[(size_t)q * n + i] = (double)h / 4294967296.0 - 0.5;
+}
+
+__global__ void k_scale2(double *__restrict__ x, long n, const double *__restrict__ ss) {
+  const int q = blockIdx.y;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[(size_t)q * n + i] /= sqrt(ss[q]);
+}
+
+__global__ void k_f64_to_f32(const double *__restrict__ x, float *__restrict__ y, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+constexpr int RED_BLOCKS = 512;
+
+template <int D>
+void sumsq2(dpp_precond pc, const double *x, long n, double *out_host, hipStream_t s) {
+  double *part = pc->red.as<double>();
+  k_sumsq2<<<dim3(RED_BLOCKS, 2), 256, 0, s>>>(x, n, part);
+  k_sum2<<<1, 64, 0, s>>>(part, RED_BLOCKS, part + 2 * RED_BLOCKS);
+  check_launch("sumsq2");
+  DPP_HIP(hipMemcpyAsync(out_host, part + 2 * RED_BLOCKS, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  DPP_HIP(hipStreamSynchronize(s));
+}
+
+template <int D>
+void setup_impl(dpp_precond pc, hipStream_t s) {
+  constexpr int NT = Tabs<D>::NT;
+  dpp_problem P = pc->prob;
+  const dpp_solve_opts &o = pc->opts;
+  pc->red.alloc(sizeof(double) * (2 * RED_BLOCKS + 4));
+  Grid g = P->g;
+  auto lev0 = std::make_unique<Level>();
+  lev0->g = g;
+  lev0->A.alloc(sizeof(double) * 2 * NT * g.N);
+  make_selfp(P, lev0->A.as<double>(), s);
+  pc->lv.push_back(std::move(lev0));
+  while (true) {
+    Level &L = *pc->lv.back();
+    const Grid &gl = L.g;
+    L.dinv.alloc(sizeof(double) * 2 * gl.N);
+    dim3 grid(blocks_for(gl.N, 256), 2);
+    k_diag_inv<D><<<grid, 256, 0, s>>>(dev(gl), L.A.as<double>(), L.dinv.as<double>());
+    check_launch("diag_inv");
+    for (DBuf *b : {&L.b, &L.xa, &L.xb, &L.d, &L.r, &L.e}) b->alloc(sizeof(double) * 2 * gl.N);
+    Grid gc = coarse_grid(gl);
+    const bool last = gl.N <= o.coarse_max || gc.N == gl.N || (int)pc->lv.size() >= 16;
+    if (last) break;
+    // Chebyshev bounds from normalised power steps on D^-1 A
+    double ss[2];
+    double *x = L.xa.as<double>(), *y = L.xb.as<double>();
+    k_hash_start<<<grid, 256, 0, s>>>(x, gl.N);
+    sumsq2<D>(pc, x, gl.N, ss, s);
+    DPP_HIP(hipMemcpyAsync(pc->red.as<double>() + 2 * RED_BLOCKS + 2, ss, 2 * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+    k_scale2<<<grid, 256, 0, s>>>(x, gl.N, pc->red.as<double>() + 2 * RED_BLOCKS + 2);
+    double lam[2] = {0, 0};
+    for (int it = 0; it < o.power_iters; ++it) {
+      k_lspmv<D, double, double><<<grid, 256, 0, s>>>(dev(gl), L.A.as<double>(), x, y, nullptr,
+                                                      L.dinv.as<double>());
+      sumsq2<D>(pc, y, gl.N, ss, s);
+      lam[0] = std::sqrt(ss[0]);
+      lam[1] = std::sqrt(ss[1]);
+      DPP_HIP(hipMemcpyAsync(pc->red.as<double>() + 2 * RED_BLOCKS + 2, ss, 2 * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+      k_scale2<<<grid, 256, 0, s>>>(y, gl.N, pc->red.as<double>() + 2 * RED_BLOCKS + 2);
+      std::swap(x, y);
+    }
+    for (int q = 0; q < 2; ++q) {
+      DPP_CHECK(std::isfinite(lam[q]) && lam[q] > 0.0, DPP_ERR_NUMERIC,
+                "multigrid eigenvalue estimate failed");
+      L.hi[q] = o.cheb_hi_factor * lam[q];
+      L.lo[q] = o.cheb_lo_frac * L.hi[q];
+    }
+    auto C = std::make_unique<Level>();
+    C->g = gc;
+    C->A.alloc(sizeof(double) * 2 * NT * gc.N);
+    dim3 gg(blocks_for(gc.N * NT, 256), 2);
+    k_galerkin<D><<<gg, 256, 0, s>>>(dev(gl), dev(gc), L.A.as<double>(), C->A.as<double>());
+    check_launch("galerkin");
+    pc->lv.push_back(std::move(C));
+  }
+  Level &Lc = *pc->lv.back();
+  const int n = (int)Lc.g.N;
+  DPP_CHECK(n <= 4000, DPP_ERR_ARG, "coarsest multigrid level too large (lower coarse_max)");
+  pc->ncoarse = n;
+  pc->cinv.alloc(sizeof(double) * 2 * (size_t)n * n);
+  k_dense_fill<D><<<dim3(blocks_for(n, 64), 2), 64, 0, s>>>(dev(Lc.g), Lc.A.as<double>(),
+                                                             pc->cinv.as<double>());
+  k_gauss_jordan<<<2, 1024, 2 * n * sizeof(double), s>>>(pc->cinv.as<double>(), n);
+  check_launch("coarse inverse");
+  pc->rhat.alloc(sizeof(double) * 2 * P->g.N);
+  DPP_HIP(hipStreamSynchronize(s));
+}
+
+// Chebyshev coefficients of step k: k = 0 -> (0, 1/theta); k >= 1 ->
+// (rho_k rho_{k-1}, 2 rho_k / delta), rho_0 = delta/theta,
+// rho_k = 1/(2 sigma - rho_{k-1}), sigma = theta/delta.
+void cheb_coefs(const Level &L, int deg, std::vector<Sc2> &c1, std::vector<Sc2> &c2) {
+  c1.assign(deg, Sc2{{0, 0}});
+  c2.assign(deg, Sc2{{0, 0}});
+  for (int q = 0; q < 2; ++q) {
+    const double theta = 0.5 * (L.hi[q] + L.lo[q]), delta = 0.5 * (L.hi[q] - L.lo[q]);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    c1[0].v[q] = 0.0;
+    c2[0].v[q] = 1.0 / theta;
+    for (int k = 1; k < deg; ++k) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      c1[k].v[q] = rn * rho;
+      c2[k].v[q] = 2.0 * rn / delta;
+      rho = rn;
+    }
+  }
+}
+
+template <typename TX>
+struct LevelBufs {
+  TX *b, *xa, *xb, *d, *r, *e;
+  const void *A, *dinv;
+};
+
+template <typename TX>
+LevelBufs<TX> bufs(Level &L);
+template <>
+LevelBufs<double> bufs<double>(Level &L) {
+  return {L.b.as<double>(), L.xa.as<double>(), L.xb.as<double>(), L.d.as<double>(),
+          L.r.as<double>(), L.e.as<double>(), L.A.ptr, L.dinv.ptr};
+}
+template <>
+LevelBufs<float> bufs<float>(Level &L) {
+  return {L.b32.as<float>(), L.xa32.as<float>(), L.xb32.as<float>(), L.d32.as<float>(),
+          L.r32.as<float>(), L.e32.as<float>(), L.A32.ptr, L.dinv32.ptr};
+}
+
+template <int D, typename TX>
+void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s) {
+  using TV = TX;  // FP64 levels in FP64 mode, FP32 levels in mixed mode
+  const int nl = (int)pc->lv.size();
+  Level &L = *pc->lv[l];
+  const GridDev gd = dev(L.g);
+  const dim3 grid(blocks_for(L.g.N, 256), 2);
+  if (l == nl - 1) {
+    const int n = pc->ncoarse;
+    k_coarse<TX><<<dim3(blocks_for(n, 4), 2), 256, 0, s>>>(pc->cinv.as<double>(), n, b, xout);
+    check_launch("coarse solve");
+    return;
+  }
+  LevelBufs<TX> B = bufs<TX>(L);
+  const TV *A = (const TV *)B.A, *di = (const TV *)B.dinv;
+  const int deg = pc->opts.cheb_degree;
+  std::vector<Sc2> c1, c2;
+  cheb_coefs(L, deg, c1, c2);
+  TX *cur = B.xa, *oth = B.xb;
+  // pre-smoothing from x = 0
+  k_cheb<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, di, b, nullptr, cur, B.d, c1[0], c2[0], 1);
+  for (int k = 1; k < deg; ++k) {
+    k_cheb<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, di, b, cur, oth, B.d, c1[k], c2[k], 0);
+    std::swap(cur, oth);
+  }
+  // residual, restriction, coarse correction
+  k_lspmv<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, cur, B.r, b, nullptr);
+  Level &Cl = *pc->lv[l + 1];
+  LevelBufs<TX> CB = bufs<TX>(Cl);
+  k_restrict<D, TX><<<dim3(blocks_for(Cl.g.N, 256), 2), 256, 0, s>>>(gd, dev(Cl.g), B.r, CB.b);
+  vcyc<D, TX>(pc, l + 1, CB.b, CB.e, s);
+  k_prolong<D, TX><<<grid, 256, 0, s>>>(gd, dev(Cl.g), CB.e, cur);
+  // post-smoothing
+  for (int k = 0; k < deg; ++k) {
+    TX *out = (k == deg - 1) ? xout : oth;
+    k_cheb<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, di, b, cur, out, B.d, c1[k], c2[k], 0);
+    oth = cur;
+    cur = out;
+  }
+  check_launch("vcycle");
+}
+
+}  // namespace
+
+void precond_setup(dpp_precond pc, hipStream_t s) {
+  if (pc->prob->g.dim == 3)
+    setup_impl<3>(pc, s);
+  else
+    setup_impl<2>(pc, s);
+}
+
+void precond_make32(dpp_precond pc, hipStream_t s) {
+  if (pc->has32) return;
+  make_k32(pc->prob, s);
+  for (auto &lp : pc->lv) {
+    Level &L = *lp;
+    const size_t nA = L.A.bytes / sizeof(double), nv = 2 * (size_t)L.g.N;
+    L.A32.alloc(nA * sizeof(float));
+    k_f64_to_f32<<<2048, 256, 0, s>>>(L.A.as<double>(), L.A32.as<float>(), nA);
+    if (L.dinv.ptr) {
+      L.dinv32.alloc(nv * sizeof(float));
+      k_f64_to_f32<<<256, 256, 0, s>>>(L.dinv.as<double>(), L.dinv32.as<float>(), nv);
+    }
+    for (DBuf *b : {&L.b32, &L.xa32, &L.xb32, &L.d32, &L.r32, &L.e32}) b->alloc(nv * sizeof(float));
+  }
+  pc->rhat32.alloc(sizeof(float) * 2 * pc->prob->g.N);
+  check_launch("precond fp32");
+  pc->has32 = true;
+}
+
+void vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s) {
+  if (pc->prob->g.dim == 3)
+    vcyc<3, double>(pc, 0, b, x, s);
+  else
+    vcyc<2, double>(pc, 0, b, x, s);
+}
+
+void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStream_t s) {
+  dpp_problem P = pc->prob;
+  Level &L0 = *pc->lv[0];
+  if (fp32) {
+    schur_rhs(P, r, pc->rhat32.ptr, true, s);
+    if (P->g.dim == 3)
+      vcyc<3, float>(pc, 0, pc->rhat32.as<float>(), L0.e32.as<float>(), s);
+    else
+      vcyc<2, float>(pc, 0, pc->rhat32.as<float>(), L0.e32.as<float>(), s);
+    schur_velocity(P, r, L0.e32.ptr, true, z, s);
+  } else {
+    schur_rhs(P, r, pc->rhat.ptr, false, s);
+    if (P->g.dim == 3)
+      vcyc<3, double>(pc, 0, pc->rhat.as<double>(), L0.e.as<double>(), s);
+    else
+      vcyc<2, double>(pc, 0, pc->rhat.as<double>(), L0.e.as<double>(), s);
+    schur_velocity(P, r, L0.e.ptr, false, z, s);
+  }
+}
+
+void level_spmv(dpp_precond pc, int level, int net, const double *x, double *y, hipStream_t s) {
+  Level &L = *pc->lv[level];
+  const long N = L.g.N;
+  // run both networks through the scratch vectors, copy the requested one
+  DPP_HIP(hipMemsetAsync(L.r.ptr, 0, sizeof(double) * 2 * N, s));
+  DPP_HIP(hipMemcpyAsync(L.r.as<double>() + net * N, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  dim3 grid(blocks_for(N, 256), 2);
+  if (pc->prob->g.dim == 3)
+    k_lspmv<3, double, double><<<grid, 256, 0, s>>>(dev(L.g), L.A.as<double>(), L.r.as<double>(),
+                                                    L.d.as<double>(), nullptr, nullptr);
+  else
+    k_lspmv<2, double, double><<<grid, 256, 0, s>>>(dev(L.g), L.A.as<double>(), L.r.as<double>(),
+                                                    L.d.as<double>(), nullptr, nullptr);
+  check_launch("level_spmv");
+  DPP_HIP(hipMemcpyAsync(y, L.d.as<double>() + net * N, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+}
+
+}  // namespace dpp

@@ -1,0 +1,132 @@
+// Library objects behind the opaque ABI handles and the cross-file launchers.
+#pragma once
+
+#include <memory>
+
+#include "common.h"
+
+namespace dpp {
+
+// Owning device buffer.
+struct DBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  explicit DBuf(size_t b) { alloc(b); }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) return;
+    DPP_HIP(hipMalloc(&ptr, b));
+    bytes = b;
+  }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  ~DBuf() { release(); }
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  template <typename T>
+  T *as() const {
+    return static_cast<T *>(ptr);
+  }
+};
+
+}  // namespace dpp
+
+// Assembled problem: K in node-pair stencil storage and f.
+struct dpp_problem_s {
+  dpp::Grid g;
+  double mu = 1.0;
+  int beta_per_cell = 0;
+  double beta = 0.0;
+  int ns = 0;           // K stencil size
+  long nnz = 0;         // structural nonzeros of K in CSR terms
+  dpp::DBuf kvals;      // [nv][ns][N] FP64
+  dpp::DBuf kvals32;    // FP32 copy (mixed precision), made on demand
+  dpp::DBuf f;          // [n_dof]
+  dpp::DBuf dinv;       // [2][N] 1/diag(K_uu^i)
+  dpp::DBuf k1, k2, betac;  // coefficient copies [n_cells] for the gradient
+  long ndof() const { return (long)(2 * g.dim + 2) * g.N; }
+};
+
+namespace dpp {
+
+struct Level {
+  Grid g;
+  DBuf A;        // [2][nt][N] FP64 stencil values (network-major)
+  DBuf A32;      // FP32 copy (mixed)
+  DBuf dinv;     // [2][N]
+  DBuf dinv32;
+  double lo[2] = {0, 0}, hi[2] = {0, 0};
+  // work vectors [2][N] each (FP64 and FP32 views share nothing)
+  DBuf b, xa, xb, d, r, e;          // e: coarse-grid correction received from below
+  DBuf b32, xa32, xb32, d32, r32, e32;
+};
+
+}  // namespace dpp
+
+struct dpp_precond_s {
+  dpp_problem prob = nullptr;
+  dpp_solve_opts opts;
+  std::vector<std::unique_ptr<dpp::Level>> lv;
+  dpp::DBuf cinv;   // [2][nc][nc] FP64 inverse of the coarsest operator
+  int ncoarse = 0;
+  dpp::DBuf rhat;   // [2][N] level-0 right-hand side of the V-cycle
+  dpp::DBuf rhat32;
+  dpp::DBuf red;    // reduction scratch
+  bool has32 = false;
+  // Krylov workspace, kept across solves
+  int ws_m = 0;
+  dpp::DBuf V, Z, w, part, hdev, ydev, xtmp, rtmp;
+};
+
+namespace dpp {
+
+// --- assemble.hip
+void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, hipStream_t s);
+void export_csr(dpp_problem P, int64_t *rowptr, int32_t *cols, double *vals, hipStream_t s);
+long count_nnz(const Grid &g);
+
+// --- ops.hip (operators on the ABI vector layout)
+void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32 = false);
+void residual_K(dpp_problem P, const double *b, const double *x, double *r, hipStream_t s,
+                bool fp32 = false);
+void spmv_block(dpp_problem P, int which, const double *x, double *y, hipStream_t s);
+void make_dinv(dpp_problem P, hipStream_t s);
+void make_selfp(dpp_problem P, double *S, hipStream_t s);
+void make_k32(dpp_problem P, hipStream_t s);
+// Schur fieldsplit pieces: rhat_i = r_p_i - K_pu^i diag^-1 r_u_i ; z_u = diag^-1 (r_u - K_up z_p)
+void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_t s);
+void schur_velocity(dpp_problem P, const double *r, const void *zp, bool fp32, double *z,
+                    hipStream_t s);
+
+// --- mg.hip
+void precond_setup(dpp_precond pc, hipStream_t s);
+void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStream_t s);
+void vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s);  // FP64, [2][N] in/out
+void level_spmv(dpp_precond pc, int level, int net, const double *x, double *y, hipStream_t s);
+void precond_make32(dpp_precond pc, hipStream_t s);
+
+// --- krylov.hip
+struct SolveResult {
+  int iters = 0, restarts = 0, converged = 0;
+  double rel = 0.0;
+  dpp_status status = DPP_OK;
+};
+double norm2(const double *x, long n, double *scratch, hipStream_t s);
+// mode 0: FP64 operator and preconditioner; 1: FP32 operator and
+// preconditioner (inner solve of iterative refinement); 2: FP64 operator with
+// the FP32 preconditioner.
+SolveResult fgmres(dpp_problem P, dpp_precond pc, const dpp_solve_opts &o, const double *b,
+                   double *x, int mode, double rtol, int maxiter, double bnorm_ref,
+                   hipStream_t s);
+void axpby(long n, double a, const double *x, double b, double *y, hipStream_t s);
+
+// --- adjoint.hip
+void param_grad(dpp_problem P, const double *x, const double *lam, double *g1, double *g2,
+                double *gb, hipStream_t s);
+void flip_pressure_sign(dpp_problem P, const double *in, double *out, hipStream_t s);
+
+}  // namespace dpp

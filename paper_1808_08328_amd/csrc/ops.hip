@@ -1,0 +1,344 @@
+// Operators on the unknown vector [u1 | p1 | u2 | p2]: y = K x from the
+// node-pair stencil storage, residuals, the block views K_up^i / K_pu^i, the
+// selfp Schur blocks and the two velocity-side steps of the Schur fieldsplit.
+//
+// The K product is bandwidth bound (about 0.2 flop per byte): one thread per
+// node reads the 4d+5 value streams of every stencil offset (coalesced,
+// structure-of-arrays) and the 2d+2 unknowns of each neighbour, which are
+// contiguous in node order and mostly served from L2.
+#include "objects.h"
+
+namespace dpp {
+
+namespace {
+
+template <int D, typename TV>
+__global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict__ kv,
+                                                const double *__restrict__ x,
+                                                const double *__restrict__ bsub,
+                                                double *__restrict__ y) {
+  constexpr int NS = Tabs<D>::NS;
+  const long N = g.N;
+  const long a = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  int i, j, k;
+  node_ijk(g, a, i, j, k);
+  double au[2][D], ap[2] = {0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int c = 0; c < D; ++c) au[q][c] = 0.0;
+  const size_t vs = (size_t)NS * N;
+  const long ou0 = off_u(D, N, 0), ou1 = off_u(D, N, 1), op0 = off_p(D, N, 0),
+             op1 = off_p(D, N, 1);
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const int *o = TAB<D>.so[t];
+    if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
+    const long b = a + lin(g, o[0], o[1], o[2]);
+    double xu[2][D], xp[2];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      xu[0][c] = x[ou0 + D * b + c];
+      xu[1][c] = x[ou1 + D * b + c];
+    }
+    xp[0] = x[op0 + b];
+    xp[1] = x[op1 + b];
+    const TV *base = kv + (size_t)t * N + a;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const double uu = (double)base[kv_uu(D, q) * vs];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double up = (double)base[kv_up(D, q, c) * vs];
+        const double pu = (double)base[kv_pu(D, q, c) * vs];
+        au[q][c] += uu * xu[q][c] + up * xp[q];
+        ap[q] += pu * xu[q][c];
+      }
+      ap[q] += (double)base[kv_pp(D, q) * vs] * xp[q];
+    }
+    const double k12 = (double)base[kv_12(D) * vs];
+    ap[0] += k12 * xp[1];
+    ap[1] += k12 * xp[0];
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const long ou = q ? ou1 : ou0, op = q ? op1 : op0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const long r = ou + D * a + c;
+      y[r] = bsub ? bsub[r] - au[q][c] : au[q][c];
+    }
+    y[op + a] = bsub ? bsub[op + a] - ap[q] : ap[q];
+  }
+}
+
+// which: 1/2 -> y_u = K_up^i x_p ; 3/4 -> y_p = K_pu^i x_u
+template <int D>
+__global__ void k_spmv_block(GridDev g, const double *__restrict__ kv, int which,
+                             const double *__restrict__ x, double *__restrict__ y) {
+  constexpr int NS = Tabs<D>::NS;
+  const long N = g.N;
+  const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  int i, j, k;
+  node_ijk(g, a, i, j, k);
+  const int q = (which - 1) & 1;
+  const bool up = which <= 2;
+  const size_t vs = (size_t)NS * N;
+  double acc[D], accp = 0.0;
+  for (int c = 0; c < D; ++c) acc[c] = 0.0;
+  for (int t = 0; t < NS; ++t) {
+    const int *o = TAB<D>.so[t];
+    if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
+    const long b = a + lin(g, o[0], o[1], o[2]);
+    const double *base = kv + (size_t)t * N + a;
+    for (int c = 0; c < D; ++c) {
+      if (up)
+        acc[c] += base[kv_up(D, q, c) * vs] * x[b];
+      else
+        accp += base[kv_pu(D, q, c) * vs] * x[D * b + c];
+    }
+  }
+  if (up)
+    for (int c = 0; c < D; ++c) y[D * a + c] = acc[c];
+  else
+    y[a] = accp;
+}
+
+template <int D>
+__global__ void k_dinv(GridDev g, const double *__restrict__ kv, double *__restrict__ dinv) {
+  constexpr int NS = Tabs<D>::NS;
+  const long N = g.N;
+  const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  const size_t vs = (size_t)NS * N;
+  const int t0 = TAB<D>.s0;
+  for (int q = 0; q < 2; ++q) dinv[q * N + a] = 1.0 / kv[kv_uu(D, q) * vs + (size_t)t0 * N + a];
+}
+
+// selfp Schur block (eqs. S4_sp1, S4_sp2):
+//   S_i(b, b+t) = K_pp^i(b, b+t) - sum_{a, c} K_pu^i(b, (a,c)) dinv_i(a) K_up^i((a,c), b+t)
+// with a = b + s (s in St) and b + t - a in St.  One thread per (t, b, i).
+template <int D>
+__global__ __launch_bounds__(256) void k_selfp(GridDev g, const double *__restrict__ kv,
+                                               const double *__restrict__ dinv,
+                                               double *__restrict__ S) {
+  constexpr int NS = Tabs<D>::NS;
+  constexpr int NT = Tabs<D>::NT;
+  const long N = g.N;
+  const int q = blockIdx.y;
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * NT) return;
+  const int t = (int)(idx / N);
+  const long b = idx - (long)t * N;
+  int ib[3];
+  node_ijk(g, b, ib[0], ib[1], ib[2]);
+  const int *to = TAB<D>.to[t];
+  double acc = 0.0;
+  if (inside(g, ib[0] + to[0], ib[1] + to[1], ib[2] + to[2])) {
+    const size_t vs = (size_t)NS * N;
+    const int st = TAB<D>.sidx[(to[0] + 1) + 3 * (to[1] + 1) + 9 * (to[2] + 1)];
+    const bool small = to[0] >= -1 && to[0] <= 1 && to[1] >= -1 && to[1] <= 1 && to[2] >= -1 &&
+                       to[2] <= 1;
+    if (small && st >= 0) acc = kv[kv_pp(D, q) * vs + (size_t)st * N + b];
+    for (int s = 0; s < NS; ++s) {
+      const int *so = TAB<D>.so[s];
+      if (!inside(g, ib[0] + so[0], ib[1] + so[1], ib[2] + so[2])) continue;
+      const int rx = to[0] - so[0], ry = to[1] - so[1], rz = to[2] - so[2];
+      if (rx < -1 || rx > 1 || ry < -1 || ry > 1 || rz < -1 || rz > 1) continue;
+      const int r = TAB<D>.sidx[(rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)];
+      if (r < 0) continue;
+      const long a = b + lin(g, so[0], so[1], so[2]);
+      double sum = 0.0;
+      for (int c = 0; c < D; ++c)
+        sum += kv[kv_pu(D, q, c) * vs + (size_t)s * N + b] * kv[kv_up(D, q, c) * vs + (size_t)r * N + a];
+      acc -= sum * dinv[q * N + a];
+    }
+  }
+  S[((size_t)q * NT + t) * N + b] = acc;
+}
+
+// rhat_i(b) = r_p_i(b) - sum_t sum_c K_pu^i(b, (b+o_t, c)) dinv_i(b+o_t) r_u_i(b+o_t, c)
+template <int D, typename TV, typename TX>
+__global__ __launch_bounds__(256) void k_schur_rhs(GridDev g, const TV *__restrict__ kv,
+                                                   const double *__restrict__ dinv,
+                                                   const double *__restrict__ r,
+                                                   TX *__restrict__ rhat) {
+  constexpr int NS = Tabs<D>::NS;
+  const long N = g.N;
+  const int q = blockIdx.y;
+  const long b = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (b >= N) return;
+  int i, j, k;
+  node_ijk(g, b, i, j, k);
+  const size_t vs = (size_t)NS * N;
+  const long ou = off_u(D, N, q);
+  double acc = r[off_p(D, N, q) + b];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const int *o = TAB<D>.so[t];
+    if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
+    const long a = b + lin(g, o[0], o[1], o[2]);
+    const double di = dinv[q * N + a];
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+      s += (double)kv[kv_pu(D, q, c) * vs + (size_t)t * N + b] * r[ou + D * a + c];
+    acc -= s * di;
+  }
+  rhat[q * N + b] = (TX)acc;
+}
+
+// z_u_i(a, c) = dinv_i(a) (r_u_i(a, c) - sum_t K_up^i((a,c), a+o_t) z_p_i(a+o_t)), z_p_i = zp_i
+template <int D, typename TV, typename TX>
+__global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restrict__ kv,
+                                                   const double *__restrict__ dinv,
+                                                   const double *__restrict__ r,
+                                                   const TX *__restrict__ zp,
+                                                   double *__restrict__ z) {
+  constexpr int NS = Tabs<D>::NS;
+  const long N = g.N;
+  const int q = blockIdx.y;
+  const long a = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  int i, j, k;
+  node_ijk(g, a, i, j, k);
+  const size_t vs = (size_t)NS * N;
+  const long ou = off_u(D, N, q);
+  double acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = r[ou + D * a + c];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const int *o = TAB<D>.so[t];
+    if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
+    const long b = a + lin(g, o[0], o[1], o[2]);
+    const double zb = (double)zp[q * N + b];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] -= (double)kv[kv_up(D, q, c) * vs + (size_t)t * N + a] * zb;
+  }
+  const double di = dinv[q * N + a];
+#pragma unroll
+  for (int c = 0; c < D; ++c) z[ou + D * a + c] = di * acc[c];
+  z[off_p(D, N, q) + a] = (double)zp[q * N + a];
+}
+
+__global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) y[i] = (float)x[i];
+}
+
+}  // namespace
+
+void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32) {
+  const Grid &g = P->g;
+  const int nb = blocks_for(g.N, 256);
+  if (g.dim == 3) {
+    if (fp32)
+      k_spmv_K<3, float><<<nb, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), x, nullptr, y);
+    else
+      k_spmv_K<3, double><<<nb, 256, 0, s>>>(dev(g), P->kvals.as<double>(), x, nullptr, y);
+  } else {
+    if (fp32)
+      k_spmv_K<2, float><<<nb, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), x, nullptr, y);
+    else
+      k_spmv_K<2, double><<<nb, 256, 0, s>>>(dev(g), P->kvals.as<double>(), x, nullptr, y);
+  }
+  check_launch("spmv_K");
+}
+
+void residual_K(dpp_problem P, const double *b, const double *x, double *r, hipStream_t s,
+                bool fp32) {
+  const Grid &g = P->g;
+  const int nb = blocks_for(g.N, 256);
+  if (g.dim == 3) {
+    if (fp32)
+      k_spmv_K<3, float><<<nb, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), x, b, r);
+    else
+      k_spmv_K<3, double><<<nb, 256, 0, s>>>(dev(g), P->kvals.as<double>(), x, b, r);
+  } else {
+    if (fp32)
+      k_spmv_K<2, float><<<nb, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), x, b, r);
+    else
+      k_spmv_K<2, double><<<nb, 256, 0, s>>>(dev(g), P->kvals.as<double>(), x, b, r);
+  }
+  check_launch("residual_K");
+}
+
+void spmv_block(dpp_problem P, int which, const double *x, double *y, hipStream_t s) {
+  const Grid &g = P->g;
+  if (g.dim == 3)
+    k_spmv_block<3><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), which, x, y);
+  else
+    k_spmv_block<2><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), which, x, y);
+  check_launch("spmv_block");
+}
+
+void make_dinv(dpp_problem P, hipStream_t s) {
+  const Grid &g = P->g;
+  if (g.dim == 3)
+    k_dinv<3><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->dinv.as<double>());
+  else
+    k_dinv<2><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->dinv.as<double>());
+  check_launch("dinv");
+}
+
+void make_selfp(dpp_problem P, double *S, hipStream_t s) {
+  const Grid &g = P->g;
+  if (g.dim == 3) {
+    dim3 grid(blocks_for(g.N * Tabs<3>::NT, 256), 2);
+    k_selfp<3><<<grid, 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->dinv.as<double>(), S);
+  } else {
+    dim3 grid(blocks_for(g.N * Tabs<2>::NT, 256), 2);
+    k_selfp<2><<<grid, 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->dinv.as<double>(), S);
+  }
+  check_launch("selfp");
+}
+
+void make_k32(dpp_problem P, hipStream_t s) {
+  if (P->kvals32.ptr) return;
+  size_t n = P->kvals.bytes / sizeof(double);
+  P->kvals32.alloc(n * sizeof(float));
+  k_to_f32<<<2048, 256, 0, s>>>(P->kvals.as<double>(), P->kvals32.as<float>(), n);
+  check_launch("k32");
+}
+
+void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_t s) {
+  const Grid &g = P->g;
+  dim3 grid(blocks_for(g.N, 256), 2);
+  const double *di = P->dinv.as<double>();
+  if (g.dim == 3) {
+    if (fp32)
+      k_schur_rhs<3, float, float><<<grid, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), di, r, (float *)rhat);
+    else
+      k_schur_rhs<3, double, double><<<grid, 256, 0, s>>>(dev(g), P->kvals.as<double>(), di, r, (double *)rhat);
+  } else {
+    if (fp32)
+      k_schur_rhs<2, float, float><<<grid, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), di, r, (float *)rhat);
+    else
+      k_schur_rhs<2, double, double><<<grid, 256, 0, s>>>(dev(g), P->kvals.as<double>(), di, r, (double *)rhat);
+  }
+  check_launch("schur_rhs");
+}
+
+void schur_velocity(dpp_problem P, const double *r, const void *zp, bool fp32, double *z,
+                    hipStream_t s) {
+  const Grid &g = P->g;
+  dim3 grid(blocks_for(g.N, 256), 2);
+  const double *di = P->dinv.as<double>();
+  if (g.dim == 3) {
+    if (fp32)
+      k_schur_vel<3, float, float><<<grid, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), di, r, (const float *)zp, z);
+    else
+      k_schur_vel<3, double, double><<<grid, 256, 0, s>>>(dev(g), P->kvals.as<double>(), di, r, (const double *)zp, z);
+  } else {
+    if (fp32)
+      k_schur_vel<2, float, float><<<grid, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), di, r, (const float *)zp, z);
+    else
+      k_schur_vel<2, double, double><<<grid, 256, 0, s>>>(dev(g), P->kvals.as<double>(), di, r, (const double *)zp, z);
+  }
+  check_launch("schur_velocity");
+}
+
+}  // namespace dpp

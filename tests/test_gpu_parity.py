@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars (derived in the design doc): assembly and every operator product to 1e-13
+relative (FP64, only the summation order differs); the multigrid cycle and the
+fieldsplit apply to 1e-11; FP64 solves at rtol 1e-12 to 1e-10 relative per
+field; the mixed-precision solve to 1e-7 per field; full-size solves by the
+oracle's own residual ||f - K_oracle x_gpu|| / ||f|| <= 1.05e-8.
+"""
+import numpy as np
+import pytest
+
+import dpp_inputs as I
+from oracle import dpp as odpp
+from oracle import mg as omg
+from oracle import solver as osolver
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def lib():
+    import paper_1808_08328_amd as dpp
+    return dpp
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def H(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+CASES = {
+    "c1_2d16": lambda: I.make_config("c1_2d16"),
+    "2d_ragged_grf": lambda: _ragged2d(),
+    "3d_ragged_body": lambda: _ragged3d(),
+    "3d_8_mms": lambda: I.mms_problem(3, 8, k1=1.0, k2=1e-2),
+}
+
+
+def _ragged2d():
+    p = I.grf_problem(2, 9)
+    q = I.mms_problem(2, (9, 6), k1=1.0, k2=0.1, beta=2.0, mu=1.3, L=(1.0, 0.7))
+    q.k1 = I.hex_to_cells(10 ** I.grf_log10((9, 6), 2, 5, 0.0, 1.0), 2)
+    q.k2 = q.k1 * 0.05
+    del p
+    return q
+
+
+def _ragged3d():
+    q = I.mms_problem(3, (5, 3, 4), k1=1.0, k2=0.1, beta=1.0, mu=0.8, L=(1.0, 0.6, 0.8))
+    q.k1 = I.hex_to_cells(10 ** I.grf_log10((5, 3, 4), 3, 7, 0.0, 1.0), 3)
+    q.k2 = I.hex_to_cells(10 ** I.grf_log10((5, 3, 4), 3, 8, -2.0, 1.0), 3)
+    q.beta = np.linspace(0.5, 1.5, q.n_cells)
+    q.body = np.array([0.3, -0.2, 0.1])
+    return q
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_assembly_matches_oracle(case):
+    print("case", case, flush=True)
+    prob = CASES[case]()
+    S = odpp.assemble(prob)
+    P = lib().assemble_problem(prob)
+    assert P.n_dof == S.K.shape[0] and P.nnz == S.K.nnz
+    rp, ci, vv = P.export_csr()
+    assert np.array_equal(H(rp), S.K.indptr)
+    assert np.array_equal(H(ci), S.K.indices)
+    scale = np.abs(S.K.data).max()
+    assert np.abs(H(vv) - S.K.data).max() <= 1e-13 * scale
+    f = H(P.rhs())
+    assert np.abs(f - S.f).max() <= 1e-13 * np.abs(S.f).max()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_operator_products_match_oracle(case):
+    prob = CASES[case]()
+    S = odpp.assemble(prob)
+    P = lib().assemble_problem(prob)
+    x = I.random_vector(P.n_dof, 1)
+    y = H(P.spmv(T(x)))
+    ref = S.K @ x
+    assert relmax(y, ref) <= 1e-13
+    B = odpp.blocks(S)
+    xp = I.random_vector(P.n_nodes, 2)
+    xu = I.random_vector(P.dim * P.n_nodes, 3)
+    for i in range(2):
+        assert relmax(H(P.spmv(T(xp), which=1 + i)), B["Kup"][i] @ xp) <= 1e-13
+        assert relmax(H(P.spmv(T(xu), which=3 + i)), B["Kpu"][i] @ xu) <= 1e-13
+
+
+@pytest.mark.parametrize("case,cmax", [("c1_2d16", 30), ("2d_ragged_grf", 10),
+                                       ("3d_ragged_body", 8), ("3d_8_mms", 40)])
+def test_multigrid_hierarchy_and_cycle_match_oracle(case, cmax):
+    prob = CASES[case]()
+    S = odpp.assemble(prob)
+    P = lib().assemble_problem(prob)
+    pc = P.setup_precond(coarse_max=cmax)
+    info = pc.info()
+    Sp = odpp.selfp(S)
+    Hs = [omg.setup(Sp[i], prob.dim, prob.n, omg.MGOptions(coarse_max=cmax)) for i in range(2)]
+    assert info["levels"] == len(Hs[0].levels) >= 2
+    for l, lev in enumerate(Hs[0].levels):
+        assert tuple(info["level_n"][l][:prob.dim]) == tuple(lev.n)
+    for i in range(2):
+        for l, lev in enumerate(Hs[i].levels):
+            x = I.random_vector(lev.A.shape[0], 10 + l)
+            assert relmax(H(pc.level_spmv(l, i, T(x))), lev.A @ x) <= 1e-13, (i, l)
+            if l < len(Hs[i].levels) - 1:
+                assert info["hi"][l][i] == pytest.approx(lev.hi, rel=1e-10)
+    b = I.random_vector(2 * P.n_nodes, 21)
+    xg = H(pc.vcycle(T(b)))
+    N = P.n_nodes
+    for i in range(2):
+        assert relmax(xg[i * N:(i + 1) * N], omg.vcycle(Hs[i], b[i * N:(i + 1) * N])) <= 1e-11
+    # full fieldsplit apply
+    F = osolver.FieldSplit(S, omg.MGOptions(coarse_max=cmax))
+    r = I.random_vector(P.n_dof, 22)
+    assert relmax(H(pc.apply(T(r))), F.apply(r)) <= 1e-11
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_fp64_solve_matches_oracle_direct_solve(case):
+    prob = CASES[case]()
+    S = odpp.assemble(prob)
+    xo = odpp.solve_direct(S.K, S.f)
+    P = lib().assemble_problem(prob)
+    pc = P.setup_precond(coarse_max=40)
+    x, st = P.solve(pc, rtol=1e-12)
+    x = H(x)
+    assert st.converged == 1 and st.rel_residual <= 1e-12
+    F = odpp.fields(prob.dim, S.N)
+    for f in ("u1", "p1", "u2", "p2"):
+        assert np.linalg.norm(x[F[f]] - xo[F[f]]) <= 1e-10 * np.linalg.norm(xo[F[f]]), f
+    # the oracle's own residual of the GPU answer
+    assert np.linalg.norm(S.f - S.K @ x) <= 1.05e-12 * np.linalg.norm(S.f)
+
+
+def test_iteration_count_in_paper_band_and_deterministic():
+    prob = I.mms_problem(3, 16, k1=1.0, k2=1e-2)
+    P = lib().assemble_problem(prob)
+    pc = P.setup_precond()
+    x1, s1 = P.solve(pc)
+    x2, s2 = P.solve(pc)
+    assert s1.converged and 8 <= s1.iters <= 30
+    assert torch.equal(x1, x2) and s1.iters == s2.iters
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_mixed_precision_matches_oracle(precision):
+    prob = I.grf_problem(3, 8)
+    S = odpp.assemble(prob)
+    xo = odpp.solve_direct(S.K, S.f)
+    P = lib().assemble_problem(prob)
+    pc = P.setup_precond(coarse_max=40)
+    x, st = P.solve(pc, rtol=1e-10, precision=precision)
+    x = H(x)
+    assert st.converged == 1
+    F = odpp.fields(3, S.N)
+    for f in ("u1", "p1", "u2", "p2"):
+        assert np.linalg.norm(x[F[f]] - xo[F[f]]) <= 1e-7 * np.linalg.norm(xo[F[f]]), f
+    if precision == 1:
+        assert st.refinements >= 2
+
+
+def test_adjoint_and_gradient_match_oracle():
+    prob = I.grf_problem(3, 5)
+    S = odpp.assemble(prob)
+    P = lib().assemble_problem(prob)
+    pc = P.setup_precond(coarse_max=40)
+    x, _ = P.solve(pc, rtol=1e-12)
+    F = odpp.fields(3, S.N)
+    obs = I.random_vector(S.N, 33)
+    g = np.zeros(P.n_dof)
+    xh = H(x)
+    g[F["p1"]] = 2 * (xh[F["p1"]] - obs)
+    lam, st = P.solve_adjoint(pc, T(g), rtol=1e-12)
+    lo = osolver.adjoint_solve(S, g)
+    assert np.linalg.norm(H(lam) - lo) <= 1e-10 * np.linalg.norm(lo)
+    g1, g2, gb = P.param_grad(x, lam)
+    r1, r2, rb = osolver.param_gradient(S, prob, xh, H(lam))
+    assert relmax(H(g1), r1) <= 1e-11 and relmax(H(g2), r2) <= 1e-11
+    assert H(gb)[0] == pytest.approx(rb, rel=1e-10)
+
+
+def test_error_paths():
+    dpp = lib()
+    prob = I.mms_problem(2, 4)
+    P = dpp.assemble_problem(prob)
+    pc = P.setup_precond(coarse_max=10)
+    with pytest.raises(dpp.DppError) as e:
+        P.solve(pc, maxiter=1)
+    assert e.value.status == 4
+    x, st = P.solve(pc, maxiter=1, allow_unconverged=True)
+    assert st.converged == 0 and st.iters == 1
+    x, st = P.solve(pc, rhs=torch.zeros(P.n_dof, dtype=torch.float64, device="cuda"))
+    assert st.converged == 1 and st.iters == 0 and float(x.abs().max()) == 0.0
+    bad = torch.full((P.n_dof,), float("nan"), dtype=torch.float64, device="cuda")
+    with pytest.raises(dpp.DppError) as e:
+        P.solve(pc, rhs=bad)
+    assert e.value.status == 5
+    k = T(prob.k1)
+    k[3] = float("nan")
+    with pytest.raises(dpp.DppError) as e:
+        dpp.assemble(2, prob.n, k, T(prob.k2), T(prob.p0_1), T(prob.p0_2))
+    assert e.value.status == 5
+    with pytest.raises(dpp.DppError) as e:
+        P.setup_precond(restart=0)
+    assert e.value.status == 1
+
+
+@pytest.mark.parametrize("name", ["c2_3d64"])
+def test_full_size_solve_oracle_residual(name):
+    """Full workload size, the launch configuration of the benchmark: the
+    oracle's own FP64 K applied to the GPU solution."""
+    print("full-size case", name, flush=True)
+    prob = I.make_config(name)
+    P = lib().assemble_problem(prob)
+    pc = P.setup_precond()
+    x, st = P.solve(pc)
+    assert st.converged == 1
+    S = odpp.assemble(prob)
+    r = S.f - odpp.spmv(S.K, H(x))
+    assert np.linalg.norm(r) <= 1.05e-8 * np.linalg.norm(S.f)
+    # sampled entries of K against the oracle
+    rp, ci, vv = P.export_csr()
+    rows = np.random.default_rng(0).integers(0, P.n_dof, 2000)
+    rph, cih, vvh = H(rp), H(ci), H(vv)
+    for rr in rows:
+        a, b = rph[rr], rph[rr + 1]
+        assert np.array_equal(cih[a:b], S.K.indices[S.K.indptr[rr]:S.K.indptr[rr + 1]])
+        assert np.abs(vvh[a:b] - S.K.data[S.K.indptr[rr]:S.K.indptr[rr + 1]]).max() <= \
+            1e-13 * np.abs(S.K.data).max()
