@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark: DPP solve time and DOF/s to 1e-8 relative residual on one MI355X.
+
+One step = one solve of the assembled CG-VMS four-field system from a zero
+initial guess to ||f - K x|| <= 1e-8 ||f|| (flexible GMRES with the Schur
+fieldsplit / multigrid preconditioner).  Assembly and preconditioner setup are
+timed separately, as the paper reports assembly and solver times separately.
+Inputs are synthetic (manufactured-solution boundary data of the paper's 3D
+study), already resident in HBM when the timed region starts.
+
+Prints one JSON line (metric, value, ..., roofline, cpu_baseline).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "DPP solve time & DOF/s to 1e-8 rel residual; SpMV HBM GB/s vs peak"
+WORKLOADS = {
+    "c2_3d64": "3D unit cube, 64^3 hexahedra x 6 Kuhn tetrahedra (65^3 nodes), CG-VMS P1, "
+               "8 unknowns/node = 2,197,000 DOF; k1=1, k2=1e-2, beta=mu=1; manufactured-solution "
+               "pressure data on all faces; FP64 flexible GMRES + Schur fieldsplit + MG V-cycles",
+    "c3_3d96_grf": "3D unit cube 96^3 x 6 tetrahedra (97^3 nodes) = 7,301,384 DOF; log-normal "
+                   "per-hex k1, k2 (Gaussian random field, correlation length 0.1, seeds 1001/1002)",
+    "c5_3d48_grf": "3D unit cube 48^3 x 6 tetrahedra (49^3 nodes) = 941,192 DOF; log-normal k1, k2",
+    "c1_2d16": "2D unit square 16^2 x 2 triangles (289 nodes) = 1,734 DOF; k1=1, k2=0.1, beta=mu=1",
+}
+PRECISION = {0: "f64", 1: "f64+f32 refinement", 2: "f64 Krylov, f32 preconditioner"}
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("mg.hip", "ops.hip", "krylov.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_1808_08328_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(family, launches_bytes):
+    """HBM traffic per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_sha") != kernel_source_sha():
+        return None
+    ent = d.get("families", {}).get(family)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def cpu_baseline(prob, gpu_iters, max_iters):
+    """The CPU oracle (FP64 numpy/scipy, its own assembly and preconditioner of
+    the same definition) solving the same system; BLAS pinned to one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import dpp as odpp
+    from oracle import solver as osolver
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        S = odpp.assemble(prob)
+        t1 = time.perf_counter()
+        F = osolver.FieldSplit(S)
+        t2 = time.perf_counter()
+        x, its, res = osolver.fgmres(S.K, S.f, F.apply, restart=30, rtol=1e-8, maxiter=max_iters)
+        t3 = time.perf_counter()
+    n_dof = S.K.shape[0]
+    t_solve = t3 - t2
+    full = res <= 1e-8
+    # when the sample stops before convergence, scale its per-iteration time
+    # to the iteration count the same preconditioner needs on the GPU
+    t_est = t_solve if full else t_solve / max(its, 1) * gpu_iters
+    return {
+        "value": n_dof / t_est, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+        "sample": ("oracle FGMRES solve of the same %d-DOF system to 1e-8 (%d iterations, "
+                   "%.2f s; assembly %.2f s and preconditioner setup %.2f s not counted)"
+                   % (n_dof, its, t_solve, t1 - t0, t2 - t1)) if full else
+                  ("first %d oracle FGMRES iterations on the same %d-DOF system (%.2f s), "
+                   "scaled to the %d iterations the solve needs" % (its, n_dof, t_solve, gpu_iters)),
+        "solve_s": t_est,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2_3d64", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", type=int, default=0, choices=[0, 1, 2])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-max-iters", type=int, default=60)
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (no multi-GPU path); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import dpp_inputs as I
+    import paper_1808_08328_amd as dpp
+    assert torch.cuda.is_available(), "no GPU"
+    dpp.lib()  # fail loudly if the HIP library is missing
+
+    prob = I.make_config(args.config)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = dpp.assemble_problem(prob)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pc = P.setup_precond()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    opts = dict(rtol=1e-8, precision=args.precision)
+    for _ in range(args.warmup):
+        P.solve(pc, **opts)
+    torch.cuda.synchronize()
+    stats = []
+    tb = time.perf_counter()
+    for _ in range(args.steps):
+        x, st = P.solve(pc, **opts)
+        stats.append(st.as_dict())
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    ms = (te - tb) * 1e3 / args.steps
+    iters = stats[-1]["iters"]
+    value = P.n_dof / (ms / 1e3)
+
+    kernels, roof = {}, None
+    if not args.no_profile:
+        dpp.profile_enable(True)
+        for _ in range(args.steps):
+            P.solve(pc, **opts)
+        torch.cuda.synchronize()
+        prof = dpp.profile_read()
+        dpp.profile_enable(False)
+        tot_ms = sum(v[1] for v in prof.values())
+        for name, (n, t, by) in prof.items():
+            if n:
+                kernels[name] = {"launches_per_solve": n / args.steps, "ms_per_solve": t / args.steps,
+                                 "avg_us": 1e3 * t / n, "GBps": by / (t * 1e6) if t > 0 else None,
+                                 "share": t / tot_ms if tot_ms else None}
+        dom = max(kernels, key=lambda k: kernels[k]["ms_per_solve"])
+        n, t, by = prof[dom]
+        achieved = by / (t * 1e6)
+        per_launch = by / n
+        tr = measured_traffic(dom, per_launch)
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": tr, "kernel": dom,
+                "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": 1e3 * t / n}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64/f32",
+        "data": "synthetic",
+        "config": {"workload": args.config, "description": WORKLOADS[args.config],
+                   "n_dof": P.n_dof, "rtol": 1e-8, "precision": PRECISION[args.precision]},
+        "iters": iters, "rel_residual": stats[-1]["rel_residual"],
+        "assemble_ms": (t1 - t0) * 1e3, "setup_ms": (t2 - t1) * 1e3,
+        "roofline": roof, "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prob, iters, args.cpu_max_iters)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

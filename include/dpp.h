@@ -197,6 +197,20 @@ dpp_status dpp_solve_adjoint(dpp_problem prob, dpp_precond pc, const dpp_solve_o
 dpp_status dpp_param_grad(dpp_problem prob, const double *x, const double *lambda,
                           double *g_logk1, double *g_logk2, double *g_beta, void *stream);
 
+/* Kernel-family timing (instrumentation, for benchmarks): while enabled,
+ * launches of the families below are bracketed by HIP events on the stream
+ * they run on, and the algorithmic bytes each launch must move (matrix
+ * entries inside the box, vectors read and written once) are accumulated.
+ * dpp_profile_enable(on) also clears earlier records.  Families:
+ *   0 y = K x / r = b - K x          1 Chebyshev step on S_p (finest level)
+ *   2 residual b - S_p x (finest)    3 r_p - K_pu D^-1 r_u
+ *   4 D^-1 (r_u - K_up z_p)          5 coarser multigrid levels + coarse solve
+ *   6 restriction / prolongation     7 Arnoldi (CGS2 passes, update)
+ * dpp_profile_read synchronises on the recorded events and returns the launch
+ * count, total milliseconds and total algorithmic bytes of one family. */
+dpp_status dpp_profile_enable(int on);
+dpp_status dpp_profile_read(int family, int64_t *launches, double *total_ms, double *total_bytes);
+
 void dpp_destroy_problem(dpp_problem prob);
 void dpp_destroy_precond(dpp_precond pc);
 

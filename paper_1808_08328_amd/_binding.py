@@ -72,6 +72,8 @@ def lib():
         "dpp_solve": (C.c_int, [P, P, C.POINTER(_Opts), P, P, C.POINTER(SolveStats), P]),
         "dpp_solve_adjoint": (C.c_int, [P, P, C.POINTER(_Opts), P, P, C.POINTER(SolveStats), P]),
         "dpp_param_grad": (C.c_int, [P, P, P, P, P, P, P]),
+        "dpp_profile_enable": (C.c_int, [C.c_int]),
+        "dpp_profile_read": (C.c_int, [C.c_int, I64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "dpp_destroy_problem": (None, [P]),
         "dpp_destroy_precond": (None, [P]),
     }
@@ -102,6 +104,25 @@ def _ptr(t):
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+PROFILE_FAMILIES = ["spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "schur_vel", "coarse_levels",
+                    "transfer_l0", "arnoldi"]
+
+
+def profile_enable(on=True):
+    """dpp_profile_enable: time kernel families with HIP events (clears records)."""
+    _check(lib().dpp_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """dpp_profile_read for every family -> {name: (launches, total_ms, total_bytes)}."""
+    out = {}
+    for i, name in enumerate(PROFILE_FAMILIES):
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        _check(lib().dpp_profile_read(i, C.byref(n), C.byref(ms), C.byref(by)))
+        out[name] = (n.value, ms.value, by.value)
+    return out
 
 
 def default_opts(**kw):

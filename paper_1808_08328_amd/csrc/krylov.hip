@@ -14,6 +14,7 @@
 #include <cmath>
 
 #include "objects.h"
+#include "profile.h"
 
 namespace dpp {
 
@@ -238,16 +239,20 @@ SolveResult fgmres(dpp_problem P, dpp_precond pc, const dpp_solve_opts &o, const
       precond_apply(pc, vj, zj, pre32, s);
       spmv_K(P, zj, w, s, op32);
       const int nk = j + 1;
-      // pass 1: h1 = V^T w  -> hd[0..nk)
-      k_mdot<<<nb, BS, 0, s>>>(V, n, nk, w, part);
-      k_finish<<<1, 64, 0, s>>>(part, nb, nk, hd);
-      // pass 2: w -= V h1 ; h2 = V^T w -> hd[MAXK+1 ..], ||w||^2
-      k_axpy_mdot<<<nb, BS, 0, s>>>(V, n, nk, hd, w, part);
-      k_finish<<<1, 64, 0, s>>>(part, nb, nk + 1, hd + MAXK + 1);
-      // pass 3: v_{j+1} = w - V h2 and its squared norm -> hd[2 MAXK + 3]
-      k_axpy_norm<<<nb, BS, 0, s>>>(V, n, nk, hd + MAXK + 1, w, vn, part);
-      k_finish<<<1, 64, 0, s>>>(part, nb, 1, hd + 2 * MAXK + 3);
-      k_scale_rsqrt<<<std::min(2048, blocks_for(n, 256)), 256, 0, s>>>(vn, n, hd + 2 * MAXK + 3);
+      {
+        // V read three times; w read 3x, written 1x; v_{j+1} written, then read+written
+        ProfScope ps(PF_ARNOLDI, 8.0 * n * (3.0 * nk + 7.0), s);
+        // pass 1: h1 = V^T w  -> hd[0..nk)
+        k_mdot<<<nb, BS, 0, s>>>(V, n, nk, w, part);
+        k_finish<<<1, 64, 0, s>>>(part, nb, nk, hd);
+        // pass 2: w -= V h1 ; h2 = V^T w -> hd[MAXK+1 ..], ||w||^2
+        k_axpy_mdot<<<nb, BS, 0, s>>>(V, n, nk, hd, w, part);
+        k_finish<<<1, 64, 0, s>>>(part, nb, nk + 1, hd + MAXK + 1);
+        // pass 3: v_{j+1} = w - V h2 and its squared norm -> hd[2 MAXK + 3]
+        k_axpy_norm<<<nb, BS, 0, s>>>(V, n, nk, hd + MAXK + 1, w, vn, part);
+        k_finish<<<1, 64, 0, s>>>(part, nb, 1, hd + 2 * MAXK + 3);
+        k_scale_rsqrt<<<std::min(2048, blocks_for(n, 256)), 256, 0, s>>>(vn, n, hd + 2 * MAXK + 3);
+      }
       check_launch("arnoldi");
       DPP_HIP(hipMemcpyAsync(hh.data(), hd, sizeof(double) * (2 * MAXK + 4), hipMemcpyDeviceToHost, s));
       DPP_HIP(hipStreamSynchronize(s));

@@ -18,6 +18,7 @@
 //   * exact FP64 solve on the coarsest level through its inverse.
 // Both networks are processed by the same launches (blockIdx.y = network).
 #include "objects.h"
+#include "profile.h"
 
 namespace dpp {
 
@@ -475,8 +476,11 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s) {
   Level &L = *pc->lv[l];
   const GridDev gd = dev(L.g);
   const dim3 grid(blocks_for(L.g.N, 256), 2);
+  const double tv = sizeof(TV), tx = sizeof(TX), Nl = (double)L.g.N;
+  const double pairs = valid_pairs<D, true>(L.g);
   if (l == nl - 1) {
     const int n = pc->ncoarse;
+    ProfScope ps(PF_COARSE, 2.0 * n * (n * 8.0 + 2 * tx), s);
     k_coarse<TX><<<dim3(blocks_for(n, 4), 2), 256, 0, s>>>(pc->cinv.as<double>(), n, b, xout);
     check_launch("coarse solve");
     return;
@@ -487,22 +491,44 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s) {
   std::vector<Sc2> c1, c2;
   cheb_coefs(L, deg, c1, c2);
   TX *cur = B.xa, *oth = B.xb;
+  const int fam_cheb = l == 0 ? PF_CHEB_L0 : PF_COARSE;
+  const int fam_res = l == 0 ? PF_RESID_L0 : PF_COARSE;
+  const int fam_tr = l == 0 ? PF_TRANSFER : PF_COARSE;
+  // Chebyshev step bytes: matrix entries + dinv, b, x_in, d_in (k>=1), d, x_out
+  auto cheb_bytes = [&](bool zero_x, bool dread) {
+    return 2.0 * ((zero_x ? 0.0 : pairs * tv) + Nl * (tv + tx * (zero_x ? 3.0 : 4.0) +
+                                                     (dread ? tx : 0.0)));
+  };
   // pre-smoothing from x = 0
-  k_cheb<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, di, b, nullptr, cur, B.d, c1[0], c2[0], 1);
+  {
+    ProfScope ps(fam_cheb, cheb_bytes(true, false), s);
+    k_cheb<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, di, b, nullptr, cur, B.d, c1[0], c2[0], 1);
+  }
   for (int k = 1; k < deg; ++k) {
+    ProfScope ps(fam_cheb, cheb_bytes(false, true), s);
     k_cheb<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, di, b, cur, oth, B.d, c1[k], c2[k], 0);
     std::swap(cur, oth);
   }
   // residual, restriction, coarse correction
-  k_lspmv<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, cur, B.r, b, nullptr);
+  {
+    ProfScope ps(fam_res, 2.0 * (pairs * tv + 3.0 * Nl * tx), s);
+    k_lspmv<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, cur, B.r, b, nullptr);
+  }
   Level &Cl = *pc->lv[l + 1];
   LevelBufs<TX> CB = bufs<TX>(Cl);
-  k_restrict<D, TX><<<dim3(blocks_for(Cl.g.N, 256), 2), 256, 0, s>>>(gd, dev(Cl.g), B.r, CB.b);
+  {
+    ProfScope ps(fam_tr, 2.0 * tx * (Nl + Cl.g.N), s);
+    k_restrict<D, TX><<<dim3(blocks_for(Cl.g.N, 256), 2), 256, 0, s>>>(gd, dev(Cl.g), B.r, CB.b);
+  }
   vcyc<D, TX>(pc, l + 1, CB.b, CB.e, s);
-  k_prolong<D, TX><<<grid, 256, 0, s>>>(gd, dev(Cl.g), CB.e, cur);
+  {
+    ProfScope ps(fam_tr, 2.0 * tx * (2.0 * Nl + Cl.g.N), s);
+    k_prolong<D, TX><<<grid, 256, 0, s>>>(gd, dev(Cl.g), CB.e, cur);
+  }
   // post-smoothing
   for (int k = 0; k < deg; ++k) {
     TX *out = (k == deg - 1) ? xout : oth;
+    ProfScope ps(fam_cheb, cheb_bytes(false, k > 0), s);
     k_cheb<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, di, b, cur, out, B.d, c1[k], c2[k], 0);
     oth = cur;
     cur = out;

@@ -7,6 +7,7 @@
 // structure-of-arrays) and the 2d+2 unknowns of each neighbour, which are
 // contiguous in node order and mostly served from L2.
 #include "objects.h"
+#include "profile.h"
 
 namespace dpp {
 
@@ -231,9 +232,16 @@ __global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, si
 
 }  // namespace
 
+static double kbytes(const Grid &g, bool fp32, bool resid) {
+  const double pairs = g.dim == 3 ? valid_pairs<3, false>(g) : valid_pairs<2, false>(g);
+  const double nd = (2.0 * g.dim + 2.0) * g.N;
+  return pairs * nv_kinds(g.dim) * (fp32 ? 4.0 : 8.0) + nd * 8.0 * (resid ? 3.0 : 2.0);
+}
+
 void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32) {
   const Grid &g = P->g;
   const int nb = blocks_for(g.N, 256);
+  ProfScope ps(PF_SPMV_K, kbytes(g, fp32, false), s);
   if (g.dim == 3) {
     if (fp32)
       k_spmv_K<3, float><<<nb, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), x, nullptr, y);
@@ -252,6 +260,7 @@ void residual_K(dpp_problem P, const double *b, const double *x, double *r, hipS
                 bool fp32) {
   const Grid &g = P->g;
   const int nb = blocks_for(g.N, 256);
+  ProfScope ps(PF_SPMV_K, kbytes(g, fp32, true), s);
   if (g.dim == 3) {
     if (fp32)
       k_spmv_K<3, float><<<nb, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), x, b, r);
@@ -306,6 +315,10 @@ void make_k32(dpp_problem P, hipStream_t s) {
 
 void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_t s) {
   const Grid &g = P->g;
+  const double pairs = g.dim == 3 ? valid_pairs<3, false>(g) : valid_pairs<2, false>(g);
+  ProfScope ps(PF_SCHUR_RHS,
+               2.0 * (pairs * g.dim * (fp32 ? 4.0 : 8.0) + g.N * (g.dim + 2.0) * 8.0 +
+                      g.N * (fp32 ? 4.0 : 8.0)), s);
   dim3 grid(blocks_for(g.N, 256), 2);
   const double *di = P->dinv.as<double>();
   if (g.dim == 3) {
@@ -325,6 +338,10 @@ void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_
 void schur_velocity(dpp_problem P, const double *r, const void *zp, bool fp32, double *z,
                     hipStream_t s) {
   const Grid &g = P->g;
+  const double pairs = g.dim == 3 ? valid_pairs<3, false>(g) : valid_pairs<2, false>(g);
+  ProfScope ps(PF_SCHUR_VEL,
+               2.0 * (pairs * g.dim * (fp32 ? 4.0 : 8.0) + g.N * (2.0 * g.dim + 2.0) * 8.0 +
+                      g.N * (fp32 ? 4.0 : 8.0)), s);
   dim3 grid(blocks_for(g.N, 256), 2);
   const double *di = P->dinv.as<double>();
   if (g.dim == 3) {

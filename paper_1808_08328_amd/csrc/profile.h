@@ -1,0 +1,53 @@
+// Kernel-family timing: when enabled, launches of the instrumented families
+// are bracketed by HIP events on their own stream, and the algorithmic bytes
+// each launch must move are accumulated next to the measured time.
+#pragma once
+
+#include "common.h"
+
+namespace dpp {
+
+enum ProfFamily {
+  PF_SPMV_K = 0,     // y = K x and r = b - K x (node-pair stencil)
+  PF_CHEB_L0 = 1,    // Chebyshev step with S_p product, finest level
+  PF_RESID_L0 = 2,   // residual b - S_p x, finest level
+  PF_SCHUR_RHS = 3,  // r_p - K_pu D^-1 r_u
+  PF_SCHUR_VEL = 4,  // D^-1 (r_u - K_up z_p)
+  PF_COARSE = 5,     // every kernel of the coarser levels and the coarse solve
+  PF_TRANSFER = 6,   // restriction and prolongation from/to the finest level
+  PF_ARNOLDI = 7,    // CGS2 passes, norms, scaling, solution update
+  PF_COUNT = 8
+};
+
+bool prof_on();
+void prof_begin(int fam, hipStream_t s);
+void prof_end(int fam, double bytes, hipStream_t s);
+
+struct ProfScope {
+  int fam;
+  double bytes;
+  hipStream_t s;
+  bool on;
+  ProfScope(int f, double b, hipStream_t st) : fam(f), bytes(b), s(st), on(prof_on()) {
+    if (on) prof_begin(fam, s);
+  }
+  ~ProfScope() {
+    if (on) prof_end(fam, bytes, s);
+  }
+};
+
+// Number of (node, offset) pairs of a stencil that stay inside the box.
+template <int D, bool PRESSURE>
+inline double valid_pairs(const Grid &g) {
+  double tot = 0.0;
+  constexpr int n = PRESSURE ? Tabs<D>::NT : Tabs<D>::NS;
+  for (int t = 0; t < n; ++t) {
+    const int *o = PRESSURE ? TAB<D>.to[t] : TAB<D>.so[t];
+    double c = 1.0;
+    for (int a = 0; a < D; ++a) c *= std::max(0, g.m[a] - std::abs(o[a]));
+    tot += c;
+  }
+  return tot;
+}
+
+}  // namespace dpp
