@@ -257,33 +257,44 @@ __global__ void k_dense_fill(GridDev g, const double *__restrict__ A, double *__
 }
 
 // In-place Gauss-Jordan inversion without pivoting (the coarse operators are
-// symmetric positive definite).  One workgroup per network.
-__global__ __launch_bounds__(1024) void k_gauss_jordan(double *__restrict__ M, int n) {
-  extern __shared__ double sh[];
-  double *rowk = sh, *colk = sh + n;
-  double *A = M + (size_t)blockIdx.x * n * n;
-  for (int k = 0; k < n; ++k) {
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      rowk[j] = A[(size_t)k * n + j];
-      colk[j] = A[(size_t)j * n + k];
-    }
-    __syncthreads();
-    const double p = rowk[k];
-    const double ip = 1.0 / p;
-    for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) {
-      const int i = (int)(e / n), j = (int)(e - (long)i * n);
-      double v;
-      if (i == k && j == k)
-        v = ip;
-      else if (i == k)
-        v = rowk[j] * ip;
-      else if (j == k)
-        v = -colk[i] * ip;
-      else
-        v = A[e] - colk[i] * rowk[j] * ip;
-      A[e] = v;
-    }
-    __syncthreads();
+// symmetric positive definite), one launch per pivot k over all n^2 entries
+// of both networks.  Row k and column k of the current matrix are read from
+// a double buffer that the previous step filled (k_gj_init for k = 0).
+__global__ void k_gj_init(const double *__restrict__ M, int n, double *__restrict__ rowb,
+                          double *__restrict__ colb) {
+  const int q = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double *A = M + (size_t)q * n * n;
+  rowb[(size_t)q * n + i] = A[i];
+  colb[(size_t)q * n + i] = A[(size_t)i * n];
+}
+
+__global__ __launch_bounds__(256) void k_gj_step(double *__restrict__ M, int n, int k,
+                                                 double *__restrict__ rowb,
+                                                 double *__restrict__ colb) {
+  const int q = blockIdx.y;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  const int i = (int)(e / n), j = (int)(e - (long)i * n);
+  const int p = k & 1;
+  const double *rk = rowb + ((size_t)p * 2 + q) * n, *ck = colb + ((size_t)p * 2 + q) * n;
+  double *A = M + (size_t)q * n * n;
+  const double ip = 1.0 / rk[k];
+  double v;
+  if (i == k && j == k)
+    v = ip;
+  else if (i == k)
+    v = rk[j] * ip;
+  else if (j == k)
+    v = -ck[i] * ip;
+  else
+    v = A[e] - ck[i] * rk[j] * ip;
+  A[e] = v;
+  if (k + 1 < n) {
+    double *rn = rowb + ((size_t)(p ^ 1) * 2 + q) * n, *cn = colb + ((size_t)(p ^ 1) * 2 + q) * n;
+    if (i == k + 1) rn[j] = v;
+    if (j == k + 1) cn[i] = v;
   }
 }
 
@@ -423,8 +434,16 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
   pc->cinv.alloc(sizeof(double) * 2 * (size_t)n * n);
   k_dense_fill<D><<<dim3(blocks_for(n, 64), 2), 64, 0, s>>>(dev(Lc.g), Lc.A.as<double>(),
                                                              pc->cinv.as<double>());
-  k_gauss_jordan<<<2, 1024, 2 * n * sizeof(double), s>>>(pc->cinv.as<double>(), n);
-  check_launch("coarse inverse");
+  {
+    DBuf rowb(sizeof(double) * 4 * n), colb(sizeof(double) * 4 * n);
+    k_gj_init<<<dim3(blocks_for(n, 256), 2), 256, 0, s>>>(pc->cinv.as<double>(), n,
+                                                           rowb.as<double>(), colb.as<double>());
+    const dim3 gg(blocks_for((long)n * n, 256), 2);
+    for (int k = 0; k < n; ++k)
+      k_gj_step<<<gg, 256, 0, s>>>(pc->cinv.as<double>(), n, k, rowb.as<double>(), colb.as<double>());
+    check_launch("coarse inverse");
+    DPP_HIP(hipStreamSynchronize(s));
+  }
   pc->rhat.alloc(sizeof(double) * 2 * P->g.N);
   DPP_HIP(hipStreamSynchronize(s));
 }

@@ -79,7 +79,7 @@ struct dpp_precond_s {
   bool has32 = false;
   // Krylov workspace, kept across solves
   int ws_m = 0;
-  dpp::DBuf V, Z, w, part, hdev, ydev, xtmp, rtmp;
+  dpp::DBuf V, Z, w, part, hdev, ydev, xtmp, rtmp, ticket;
 };
 
 namespace dpp {
@@ -115,7 +115,8 @@ struct SolveResult {
   double rel = 0.0;
   dpp_status status = DPP_OK;
 };
-double norm2(const double *x, long n, double *scratch, hipStream_t s);
+double norm2(const double *x, long n, double *scratch, unsigned *ticket, hipStream_t s);
+void ensure_reduction(dpp_precond pc);
 // mode 0: FP64 operator and preconditioner; 1: FP32 operator and
 // preconditioner (inner solve of iterative refinement); 2: FP64 operator with
 // the FP32 preconditioner.
