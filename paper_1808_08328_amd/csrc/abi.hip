@@ -213,7 +213,7 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
     const double *b = rhs ? rhs : P->f.as<double>();
     const long n = P->ndof();
     dpp::ensure_reduction(pc);
-    const double bn = dpp::norm2(b, n, pc->part.as<double>(), pc->ticket.as<unsigned>(), s);
+    const double bn = dpp::norm2(b, n, pc->part.as<double>(), s);
     DPP_CHECK(std::isfinite(bn), DPP_ERR_NUMERIC, "right-hand side holds NaN/Inf");
     if (o.precision != 1) {
       if (o.precision == 2) dpp::precond_make32(pc, s);
@@ -227,7 +227,7 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
       double *e = pc->xtmp.as<double>(), *r = pc->rtmp.as<double>();
       while (true) {
         dpp::residual_K(P, b, x, r, s);
-        const double rn = dpp::norm2(r, n, pc->part.as<double>(), pc->ticket.as<unsigned>(), s);
+        const double rn = dpp::norm2(r, n, pc->part.as<double>(), s);
         res.rel = bn > 0 ? rn / bn : 0.0;
         DPP_CHECK(std::isfinite(rn), DPP_ERR_NUMERIC, "NaN/Inf in the refinement residual");
         if (rn <= o.rtol * bn) {

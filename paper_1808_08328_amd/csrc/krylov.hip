@@ -29,14 +29,10 @@ __device__ inline double wave_sum(double v) {
 }
 
 // Block-reduce nk (<= MAXK) per-thread values, plus one extra value stored
-// in slot nk when with_extra, into partials part[k*gridDim.x + block].  The
-// last block to finish (ticket counter) then sums the partials of every slot
-// in a fixed order into out[] and re-arms the counter: one launch per
-// reduction, bit-reproducible.
-__device__ inline void block_store(const double *acc, int nk, double *part, double *out,
-                                   unsigned *ticket, double extra = 0.0, bool with_extra = false) {
+// in slot nk when with_extra, into partials part[k*gridDim.x + block].
+__device__ inline void block_store(const double *acc, int nk, double *part, double extra = 0.0,
+                                   bool with_extra = false) {
   __shared__ double sh[BS / 64][MAXK + 1];
-  __shared__ bool last;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) {
@@ -57,27 +53,28 @@ __device__ inline void block_store(const double *acc, int nk, double *part, doub
     for (int w = 0; w < BS / 64; ++w) s += sh[w][slot];
     part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
   }
-  __threadfence();
+}
+
+// out[k] = sum over the nb partials of slot k (one block per slot, fixed tree).
+__global__ __launch_bounds__(BS) void k_finish(const double *__restrict__ part, int nb,
+                                               double *__restrict__ out) {
+  const int k = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += BS) s += part[(size_t)k * nb + b];
+  s = wave_sum(s);
+  __shared__ double sh[BS / 64];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // final sums: one wavefront per slot, lanes stride the partials, fixed tree
-  const int nb = gridDim.x;
-  for (int k = wv; k < tot; k += BS / 64) {
-    double s = 0.0;
-    for (int b = lane; b < nb; b += 64) s += part[(size_t)k * nb + b];
-    s = wave_sum(s);
-    if (lane == 0) out[k] = s;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < BS / 64; ++w) t += sh[w];
+    out[k] = t;
   }
-  if (threadIdx.x == 0) *ticket = 0u;
 }
 
 // part[k] = sum_i V_k[i] w[i], k < nk
 __global__ __launch_bounds__(BS) void k_mdot(const double *__restrict__ V, long n, int nk,
-                                             const double *__restrict__ w, double *__restrict__ part,
-                                             double *__restrict__ out, unsigned *ticket) {
+                                             const double *__restrict__ w, double *__restrict__ part) {
   double acc[MAXK];
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) acc[k] = 0.0;
@@ -87,14 +84,13 @@ __global__ __launch_bounds__(BS) void k_mdot(const double *__restrict__ V, long 
     for (int k = 0; k < MAXK; ++k)
       if (k < nk) acc[k] += V[(size_t)k * n + i] * wi;
   }
-  block_store(acc, nk, part, out, ticket);
+  block_store(acc, nk, part);
 }
 
 // w <- w - V h ; part[k] = V_k . w (k < nk), part[nk] = ||w||^2
 __global__ __launch_bounds__(BS) void k_axpy_mdot(const double *__restrict__ V, long n, int nk,
                                                   const double *__restrict__ h,
-                                                  double *__restrict__ w, double *__restrict__ part,
-                                                  double *__restrict__ out, unsigned *ticket) {
+                                                  double *__restrict__ w, double *__restrict__ part) {
   double acc[MAXK];
   double hk[MAXK], nrm = 0.0;
 #pragma unroll
@@ -114,15 +110,14 @@ __global__ __launch_bounds__(BS) void k_axpy_mdot(const double *__restrict__ V, 
     for (int k = 0; k < MAXK; ++k) acc[k] += v[k] * s;
     nrm += s * s;
   }
-  block_store(acc, nk, part, out, ticket, nrm, true);
+  block_store(acc, nk, part, nrm, true);
 }
 
 // out <- w - V h ; part[0] = ||out||^2
 __global__ __launch_bounds__(BS) void k_axpy_norm(const double *__restrict__ V, long n, int nk,
                                                   const double *__restrict__ h,
                                                   const double *__restrict__ w,
-                                                  double *__restrict__ vout, double *__restrict__ part,
-                                                  double *__restrict__ out, unsigned *ticket) {
+                                                  double *__restrict__ vout, double *__restrict__ part) {
   double hk[MAXK];
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) hk[k] = (k < nk) ? h[k] : 0.0;
@@ -135,7 +130,7 @@ __global__ __launch_bounds__(BS) void k_axpy_norm(const double *__restrict__ V, 
     vout[i] = s;
     nrm += s * s;
   }
-  block_store(hk, 0, part, out, ticket, nrm, true);
+  block_store(hk, 0, part, nrm, true);
 }
 
 // v <- v / sqrt(ss)   (ss read from device memory; zero norm leaves v as is)
@@ -190,10 +185,6 @@ void ensure_ws(dpp_precond pc, int m) {
 
 void ensure_reduction(dpp_precond pc) {
   if (!pc->part.ptr) pc->part.alloc(sizeof(double) * (size_t)(MAXK + 2) * 1024);
-  if (!pc->ticket.ptr) {
-    pc->ticket.alloc(sizeof(unsigned) * 4);
-    DPP_HIP(hipMemset(pc->ticket.ptr, 0, sizeof(unsigned) * 4));
-  }
 }
 
 void axpby(long n, double a, const double *x, double b, double *y, hipStream_t s) {
@@ -201,9 +192,10 @@ void axpby(long n, double a, const double *x, double b, double *y, hipStream_t s
   check_launch("axpby");
 }
 
-double norm2(const double *x, long n, double *scratch, unsigned *ticket, hipStream_t s) {
+double norm2(const double *x, long n, double *scratch, hipStream_t s) {
   const int nb = red_blocks(n);
-  k_mdot<<<nb, BS, 0, s>>>(x, n, 1, x, scratch, scratch + (size_t)(MAXK + 1) * 1024, ticket);
+  k_mdot<<<nb, BS, 0, s>>>(x, n, 1, x, scratch);
+  k_finish<<<1, BS, 0, s>>>(scratch, nb, scratch + (size_t)(MAXK + 1) * 1024);
   check_launch("norm2");
   double h = 0.0;
   DPP_HIP(hipMemcpyAsync(&h, scratch + (size_t)(MAXK + 1) * 1024, sizeof(double),
@@ -224,7 +216,6 @@ SolveResult fgmres(dpp_problem P, dpp_precond pc, const dpp_solve_opts &o, const
   const bool op32 = mode == 1, pre32 = mode != 0;
   double *V = pc->V.as<double>(), *Z = pc->Z.as<double>(), *w = pc->w.as<double>();
   double *part = pc->part.as<double>(), *hd = pc->hdev.as<double>();
-  unsigned *tk = pc->ticket.as<unsigned>();
   const int nb = red_blocks(n);
   std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), hh(2 * MAXK + 4), y(m);
   auto Hc = [&](int i, int j) -> double & { return H[(size_t)j * (m + 1) + i]; };
@@ -236,7 +227,7 @@ SolveResult fgmres(dpp_problem P, dpp_precond pc, const dpp_solve_opts &o, const
   while (true) {
     // true residual r = b - K x into V_0
     residual_K(P, b, x, V, s, op32);
-    const double beta = norm2(V, n, part, tk, s);
+    const double beta = norm2(V, n, part, s);
     res.rel = beta / bn;
     if (!std::isfinite(beta)) {
       res.status = DPP_ERR_NUMERIC;
@@ -264,11 +255,14 @@ SolveResult fgmres(dpp_problem P, dpp_precond pc, const dpp_solve_opts &o, const
         // V read three times; w read 3x, written 1x; v_{j+1} written, then read+written
         ProfScope ps(PF_ARNOLDI, 8.0 * n * (3.0 * nk + 7.0), s);
         // pass 1: h1 = V^T w  -> hd[0..nk)
-        k_mdot<<<nb, BS, 0, s>>>(V, n, nk, w, part, hd, tk);
+        k_mdot<<<nb, BS, 0, s>>>(V, n, nk, w, part);
+        k_finish<<<nk, BS, 0, s>>>(part, nb, hd);
         // pass 2: w -= V h1 ; h2 = V^T w -> hd[MAXK+1 ..], ||w||^2
-        k_axpy_mdot<<<nb, BS, 0, s>>>(V, n, nk, hd, w, part, hd + MAXK + 1, tk);
+        k_axpy_mdot<<<nb, BS, 0, s>>>(V, n, nk, hd, w, part);
+        k_finish<<<nk + 1, BS, 0, s>>>(part, nb, hd + MAXK + 1);
         // pass 3: v_{j+1} = w - V h2 and its squared norm -> hd[2 MAXK + 3]
-        k_axpy_norm<<<nb, BS, 0, s>>>(V, n, nk, hd + MAXK + 1, w, vn, part, hd + 2 * MAXK + 3, tk);
+        k_axpy_norm<<<nb, BS, 0, s>>>(V, n, nk, hd + MAXK + 1, w, vn, part);
+        k_finish<<<1, BS, 0, s>>>(part, nb, hd + 2 * MAXK + 3);
         k_scale_rsqrt<<<std::min(2048, blocks_for(n, 256)), 256, 0, s>>>(vn, n, hd + 2 * MAXK + 3);
       }
       check_launch("arnoldi");

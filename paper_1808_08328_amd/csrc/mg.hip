@@ -17,6 +17,10 @@
 //     `power_iters` power steps from a fixed integer-hash start vector);
 //   * exact FP64 solve on the coarsest level through its inverse.
 // Both networks are processed by the same launches (blockIdx.y = network).
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "objects.h"
 #include "profile.h"
 
@@ -40,8 +44,40 @@ __device__ inline void fine_to_coarse(int i, int n, int mc, int &lo, int &od) {
 
 __device__ inline int exact_fine(int c, int n, int mc) { return ((n & 1) && c == mc - 1) ? n : 2 * c; }
 
+// Stencil product of one row, split over LPR lanes (offsets t = sub, sub+LPR,
+// ...); the lanes of a row are adjacent and reduce with shuffles.  LPR = 1 is
+// the fully unrolled one-thread-per-row form used on large levels; smaller
+// levels use more lanes per row so the launch still fills the GPU.
+template <int D, typename TV, typename TX, int LPR>
+__device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq,
+                                     const TX *__restrict__ xq, long a, int i, int j, int k, int sub) {
+  constexpr int NT = Tabs<D>::NT;
+  const long N = g.N;
+  double acc = 0.0;
+  if constexpr (LPR == 1) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int *o = TAB<D>.to[t];
+      if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
+      acc += (double)Aq[(size_t)t * N + a] * (double)xq[a + lin(g, o[0], o[1], o[2])];
+    }
+  } else {
+#pragma unroll
+    for (int tt = 0; tt < (NT + LPR - 1) / LPR; ++tt) {
+      const int t = tt * LPR + sub;
+      if (t >= NT) continue;
+      const int *o = TAB<D>.to[t];
+      if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
+      acc += (double)Aq[(size_t)t * N + a] * (double)xq[a + lin(g, o[0], o[1], o[2])];
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
+  }
+  return acc;
+}
+
 // A x on a level, optionally returning b - A x and/or scaling by dinv.
-template <int D, typename TV, typename TX>
+template <int D, typename TV, typename TX, int LPR>
 __global__ __launch_bounds__(256) void k_lspmv(GridDev g, const TV *__restrict__ A,
                                                const TX *__restrict__ x, TX *__restrict__ y,
                                                const TX *__restrict__ b,
@@ -49,19 +85,14 @@ __global__ __launch_bounds__(256) void k_lspmv(GridDev g, const TV *__restrict__
   constexpr int NT = Tabs<D>::NT;
   const long N = g.N;
   const int q = blockIdx.y;
-  const long a = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const long a = gid / LPR;
+  const int sub = (int)(gid % LPR);
   if (a >= N) return;
   int i, j, k;
   node_ijk(g, a, i, j, k);
-  const TV *Aq = A + (size_t)q * NT * N + a;
-  const TX *xq = x + (size_t)q * N;
-  double acc = 0.0;
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int *o = TAB<D>.to[t];
-    if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
-    acc += (double)Aq[(size_t)t * N] * (double)xq[a + lin(g, o[0], o[1], o[2])];
-  }
+  double acc = row_product<D, TV, TX, LPR>(g, A + (size_t)q * NT * N, x + (size_t)q * N, a, i, j, k, sub);
+  if (sub != 0) return;
   if (b) acc = (double)b[(size_t)q * N + a] - acc;
   if (dinv) acc *= (double)dinv[(size_t)q * N + a];
   y[(size_t)q * N + a] = (TX)acc;
@@ -69,8 +100,8 @@ __global__ __launch_bounds__(256) void k_lspmv(GridDev g, const TV *__restrict__
 
 // Chebyshev step k (Saad, Alg. 12.1 with diagonal preconditioning):
 //   r = D^-1 (b - A xin);  d = c1 d + c2 r;  xout = xin + d.
-// With zero_x the SpMV is skipped (xin = 0).
-template <int D, typename TV, typename TX>
+// With zero_x the product is skipped (xin = 0).
+template <int D, typename TV, typename TX, int LPR>
 __global__ __launch_bounds__(256) void k_cheb(GridDev g, const TV *__restrict__ A,
                                               const TV *__restrict__ dinv,
                                               const TX *__restrict__ b, const TX *__restrict__ xin,
@@ -79,27 +110,48 @@ __global__ __launch_bounds__(256) void k_cheb(GridDev g, const TV *__restrict__ 
   constexpr int NT = Tabs<D>::NT;
   const long N = g.N;
   const int q = blockIdx.y;
-  const long a = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const long a = gid / LPR;
+  const int sub = (int)(gid % LPR);
   if (a >= N) return;
   const size_t ia = (size_t)q * N + a;
   double ax = 0.0, xa = 0.0;
   if (!zero_x) {
     int i, j, k;
     node_ijk(g, a, i, j, k);
-    const TV *Aq = A + (size_t)q * NT * N + a;
-    const TX *xq = xin + (size_t)q * N;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int *o = TAB<D>.to[t];
-      if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
-      ax += (double)Aq[(size_t)t * N] * (double)xq[a + lin(g, o[0], o[1], o[2])];
-    }
+    ax = row_product<D, TV, TX, LPR>(g, A + (size_t)q * NT * N, xin + (size_t)q * N, a, i, j, k, sub);
     xa = (double)xin[ia];
   }
+  if (sub != 0) return;
   const double r = (double)dinv[ia] * ((double)b[ia] - ax);
   const double dn = (c1.v[q] != 0.0 ? c1.v[q] * (double)d[ia] : 0.0) + c2.v[q] * r;
   d[ia] = (TX)dn;
   xout[ia] = (TX)(xa + dn);
+}
+
+template <int D, typename TV, typename TX>
+void launch_lspmv(int lpr, const Grid &gl, hipStream_t s, const TV *A, const TX *x, TX *y,
+                  const TX *b, const TV *dinv) {
+  const dim3 grid(blocks_for(gl.N * lpr, 256), 2);
+  switch (lpr) {
+    case 1: k_lspmv<D, TV, TX, 1><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv); break;
+    case 2: k_lspmv<D, TV, TX, 2><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv); break;
+    case 4: k_lspmv<D, TV, TX, 4><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv); break;
+    default: k_lspmv<D, TV, TX, 8><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv); break;
+  }
+}
+
+template <int D, typename TV, typename TX>
+void launch_cheb(int lpr, const Grid &gl, hipStream_t s, const TV *A, const TV *di, const TX *b,
+                 const TX *xin, TX *xout, TX *d, Sc2 c1, Sc2 c2, int zero_x) {
+  const int l = zero_x ? 1 : lpr;
+  const dim3 grid(blocks_for(gl.N * l, 256), 2);
+  switch (l) {
+    case 1: k_cheb<D, TV, TX, 1><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin, xout, d, c1, c2, zero_x); break;
+    case 2: k_cheb<D, TV, TX, 2><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin, xout, d, c1, c2, zero_x); break;
+    case 4: k_cheb<D, TV, TX, 4><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin, xout, d, c1, c2, zero_x); break;
+    default: k_cheb<D, TV, TX, 8><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin, xout, d, c1, c2, zero_x); break;
+  }
 }
 
 // b_c(C) = sum_f P(f, C) r(f)
@@ -360,6 +412,49 @@ __global__ void k_f64_to_f32(const double *__restrict__ x, float *__restrict__ y
 
 constexpr int RED_BLOCKS = 512;
 
+// Autotuner for the lanes-per-row width of the level stencil kernels: each
+// candidate is timed with HIP events on the level's own operator, the fastest
+// wins; results are cached per (dim, nodes, value bytes) for the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, long, int>, int> g_tune_cache;
+
+template <int D>
+int tune_lpr(Level &L, hipStream_t s) {
+  const auto key = std::make_tuple(D, L.g.N, 8);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) return it->second;
+  }
+  hipEvent_t e0, e1;
+  DPP_HIP(hipEventCreate(&e0));
+  DPP_HIP(hipEventCreate(&e1));
+  int best = 1;
+  float best_ms = 1e30f;
+  const double *A = L.A.as<double>(), *x = L.xa.as<double>();
+  double *y = L.xb.as<double>();
+  DPP_HIP(hipMemsetAsync(L.xa.ptr, 0, L.xa.bytes, s));
+  for (int cand : {1, 2, 4, 8}) {
+    launch_lspmv<D, double, double>(cand, L.g, s, A, x, y, nullptr, nullptr);
+    DPP_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < 5; ++r) launch_lspmv<D, double, double>(cand, L.g, s, A, x, y, nullptr, nullptr);
+    DPP_HIP(hipEventRecord(e1, s));
+    DPP_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    DPP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms * 0.97f) {  // prefer fewer lanes unless clearly faster
+      best_ms = ms;
+      best = cand;
+    }
+  }
+  check_launch("tune_lpr");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = best;
+  return best;
+}
+
 template <int D>
 void sumsq2(dpp_precond pc, const double *x, long n, double *out_host, hipStream_t s) {
   double *part = pc->red.as<double>();
@@ -403,8 +498,7 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
     k_scale2<<<grid, 256, 0, s>>>(x, gl.N, pc->red.as<double>() + 2 * RED_BLOCKS + 2);
     double lam[2] = {0, 0};
     for (int it = 0; it < o.power_iters; ++it) {
-      k_lspmv<D, double, double><<<grid, 256, 0, s>>>(dev(gl), L.A.as<double>(), x, y, nullptr,
-                                                      L.dinv.as<double>());
+      launch_lspmv<D, double, double>(1, gl, s, L.A.as<double>(), x, y, nullptr, L.dinv.as<double>());
       sumsq2<D>(pc, y, gl.N, ss, s);
       lam[0] = std::sqrt(ss[0]);
       lam[1] = std::sqrt(ss[1]);
@@ -427,6 +521,7 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
     check_launch("galerkin");
     pc->lv.push_back(std::move(C));
   }
+  for (size_t l = 0; l + 1 < pc->lv.size(); ++l) pc->lv[l]->lpr = tune_lpr<D>(*pc->lv[l], s);
   Level &Lc = *pc->lv.back();
   const int n = (int)Lc.g.N;
   DPP_CHECK(n <= 4000, DPP_ERR_ARG, "coarsest multigrid level too large (lower coarse_max)");
@@ -519,19 +614,20 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s) {
                                                      (dread ? tx : 0.0)));
   };
   // pre-smoothing from x = 0
+  const int lpr = L.lpr;
   {
     ProfScope ps(fam_cheb, cheb_bytes(true, false), s);
-    k_cheb<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, di, b, nullptr, cur, B.d, c1[0], c2[0], 1);
+    launch_cheb<D, TV, TX>(lpr, L.g, s, A, di, b, nullptr, cur, B.d, c1[0], c2[0], 1);
   }
   for (int k = 1; k < deg; ++k) {
     ProfScope ps(fam_cheb, cheb_bytes(false, true), s);
-    k_cheb<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, di, b, cur, oth, B.d, c1[k], c2[k], 0);
+    launch_cheb<D, TV, TX>(lpr, L.g, s, A, di, b, cur, oth, B.d, c1[k], c2[k], 0);
     std::swap(cur, oth);
   }
   // residual, restriction, coarse correction
   {
     ProfScope ps(fam_res, 2.0 * (pairs * tv + 3.0 * Nl * tx), s);
-    k_lspmv<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, cur, B.r, b, nullptr);
+    launch_lspmv<D, TV, TX>(lpr, L.g, s, A, cur, B.r, b, (const TV *)nullptr);
   }
   Level &Cl = *pc->lv[l + 1];
   LevelBufs<TX> CB = bufs<TX>(Cl);
@@ -548,7 +644,7 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s) {
   for (int k = 0; k < deg; ++k) {
     TX *out = (k == deg - 1) ? xout : oth;
     ProfScope ps(fam_cheb, cheb_bytes(false, k > 0), s);
-    k_cheb<D, TV, TX><<<grid, 256, 0, s>>>(gd, A, di, b, cur, out, B.d, c1[k], c2[k], 0);
+    launch_cheb<D, TV, TX>(lpr, L.g, s, A, di, b, cur, out, B.d, c1[k], c2[k], 0);
     oth = cur;
     cur = out;
   }
@@ -616,13 +712,12 @@ void level_spmv(dpp_precond pc, int level, int net, const double *x, double *y, 
   // run both networks through the scratch vectors, copy the requested one
   DPP_HIP(hipMemsetAsync(L.r.ptr, 0, sizeof(double) * 2 * N, s));
   DPP_HIP(hipMemcpyAsync(L.r.as<double>() + net * N, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-  dim3 grid(blocks_for(N, 256), 2);
   if (pc->prob->g.dim == 3)
-    k_lspmv<3, double, double><<<grid, 256, 0, s>>>(dev(L.g), L.A.as<double>(), L.r.as<double>(),
-                                                    L.d.as<double>(), nullptr, nullptr);
+    launch_lspmv<3, double, double>(L.lpr, L.g, s, L.A.as<double>(), L.r.as<double>(),
+                                    L.d.as<double>(), nullptr, nullptr);
   else
-    k_lspmv<2, double, double><<<grid, 256, 0, s>>>(dev(L.g), L.A.as<double>(), L.r.as<double>(),
-                                                    L.d.as<double>(), nullptr, nullptr);
+    launch_lspmv<2, double, double>(L.lpr, L.g, s, L.A.as<double>(), L.r.as<double>(),
+                                    L.d.as<double>(), nullptr, nullptr);
   check_launch("level_spmv");
   DPP_HIP(hipMemcpyAsync(y, L.d.as<double>() + net * N, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
 }

@@ -60,6 +60,7 @@ struct Level {
   DBuf dinv;     // [2][N]
   DBuf dinv32;
   double lo[2] = {0, 0}, hi[2] = {0, 0};
+  int lpr = 1;     // lanes per stencil row in the level kernels (autotuned)
   // work vectors [2][N] each (FP64 and FP32 views share nothing)
   DBuf b, xa, xb, d, r, e;          // e: coarse-grid correction received from below
   DBuf b32, xa32, xb32, d32, r32, e32;
@@ -79,7 +80,7 @@ struct dpp_precond_s {
   bool has32 = false;
   // Krylov workspace, kept across solves
   int ws_m = 0;
-  dpp::DBuf V, Z, w, part, hdev, ydev, xtmp, rtmp, ticket;
+  dpp::DBuf V, Z, w, part, hdev, ydev, xtmp, rtmp;
 };
 
 namespace dpp {
@@ -115,7 +116,7 @@ struct SolveResult {
   double rel = 0.0;
   dpp_status status = DPP_OK;
 };
-double norm2(const double *x, long n, double *scratch, unsigned *ticket, hipStream_t s);
+double norm2(const double *x, long n, double *scratch, hipStream_t s);
 void ensure_reduction(dpp_precond pc);
 // mode 0: FP64 operator and preconditioner; 1: FP32 operator and
 // preconditioner (inner solve of iterative refinement); 2: FP64 operator with
