@@ -67,6 +67,8 @@ def lib():
         "dpp_precond_info": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                        C.POINTER(C.c_double)]),
         "dpp_precond_apply": (C.c_int, [P, P, P, P]),
+        "dpp_precond_shape": (C.c_int, [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "dpp_precond_set_shape": (C.c_int, [P, C.c_int, C.c_int, C.c_int]),
         "dpp_vcycle": (C.c_int, [P, P, P, P]),
         "dpp_level_spmv": (C.c_int, [P, C.c_int, C.c_int, P, P, P]),
         "dpp_solve": (C.c_int, [P, P, C.POINTER(_Opts), P, P, C.POINTER(SolveStats), P]),
@@ -152,6 +154,14 @@ class Precond:
         return dict(levels=nl.value,
                     level_n=[tuple(ln[3 * l:3 * l + 3]) for l in range(nl.value)],
                     hi=[(hi[2 * l], hi[2 * l + 1]) for l in range(nl.value)])
+
+    def shape(self, level):
+        lanes, sym = C.c_int(), C.c_int()
+        _check(lib().dpp_precond_shape(self.handle, level, C.byref(lanes), C.byref(sym)))
+        return lanes.value, sym.value
+
+    def set_shape(self, level, lanes, sym):
+        _check(lib().dpp_precond_set_shape(self.handle, level, lanes, sym))
 
     def apply(self, r, stream=None):
         z = torch.empty_like(r)

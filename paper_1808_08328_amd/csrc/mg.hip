@@ -48,36 +48,57 @@ __device__ inline int exact_fine(int c, int n, int mc) { return ((n & 1) && c ==
 // ...); the lanes of a row are adjacent and reduce with shuffles.  LPR = 1 is
 // the fully unrolled one-thread-per-row form used on large levels; smaller
 // levels use more lanes per row so the launch still fills the GPU.
-template <int D, typename TV, typename TX, int LPR>
+//
+// SYM: the operators are symmetric, so only the zero offset and the positive
+// half of T (linear offset > 0; T is sorted, so these are indices t0..NT-1)
+// are stored, H[h][a] = A(a, a + o_{t0+h}); the entries of the negative
+// half are read from the neighbour's row, A(a, a - o) = H[h][a - o].  That
+// halves the matrix bytes streamed from HBM when the mirror reads hit in L2
+// or the Infinity Cache (rows a and a - o are at most two planes apart).
+template <int D, typename TV, typename TX, int LPR, bool SYM>
 __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq,
                                      const TX *__restrict__ xq, long a, int i, int j, int k, int sub) {
   constexpr int NT = Tabs<D>::NT;
+  constexpr int T0 = TAB<D>.t0;
+  constexpr int NH = NT - T0;  // zero offset + positive half
   const long N = g.N;
   double acc = 0.0;
-  if constexpr (LPR == 1) {
+  if constexpr (!SYM) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
+    for (int tt = 0; tt < (NT + LPR - 1) / LPR; ++tt) {
+      const int t = tt * LPR + (LPR == 1 ? 0 : sub);
+      if (LPR > 1 && t >= NT) continue;
       const int *o = TAB<D>.to[t];
       if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
       acc += (double)Aq[(size_t)t * N + a] * (double)xq[a + lin(g, o[0], o[1], o[2])];
     }
   } else {
 #pragma unroll
-    for (int tt = 0; tt < (NT + LPR - 1) / LPR; ++tt) {
-      const int t = tt * LPR + sub;
-      if (t >= NT) continue;
-      const int *o = TAB<D>.to[t];
-      if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
-      acc += (double)Aq[(size_t)t * N + a] * (double)xq[a + lin(g, o[0], o[1], o[2])];
+    for (int hh = 0; hh < (NH + LPR - 1) / LPR; ++hh) {
+      const int h = hh * LPR + (LPR == 1 ? 0 : sub);
+      if (LPR > 1 && h >= NH) continue;
+      const int *o = TAB<D>.to[T0 + h];
+      const long lo = lin(g, o[0], o[1], o[2]);
+      if (inside(g, i + o[0], j + o[1], k + o[2]))
+        acc += (double)Aq[(size_t)h * N + a] * (double)xq[a + lo];
+      if (h > 0 && inside(g, i - o[0], j - o[1], k - o[2]))
+        acc += (double)Aq[(size_t)h * N + a - lo] * (double)xq[a - lo];
     }
+  }
+  if constexpr (LPR > 1) {
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
   }
   return acc;
 }
 
+template <int D, bool SYM>
+constexpr int stored_offsets() {
+  return SYM ? Tabs<D>::NT - TAB<D>.t0 : Tabs<D>::NT;
+}
+
 // A x on a level, optionally returning b - A x and/or scaling by dinv.
-template <int D, typename TV, typename TX, int LPR>
+template <int D, typename TV, typename TX, int LPR, bool SYM>
 __global__ __launch_bounds__(256) void k_lspmv(GridDev g, const TV *__restrict__ A,
                                                const TX *__restrict__ x, TX *__restrict__ y,
                                                const TX *__restrict__ b,
@@ -91,7 +112,8 @@ __global__ __launch_bounds__(256) void k_lspmv(GridDev g, const TV *__restrict__
   if (a >= N) return;
   int i, j, k;
   node_ijk(g, a, i, j, k);
-  double acc = row_product<D, TV, TX, LPR>(g, A + (size_t)q * NT * N, x + (size_t)q * N, a, i, j, k, sub);
+  constexpr int NA = stored_offsets<D, SYM>();
+  double acc = row_product<D, TV, TX, LPR, SYM>(g, A + (size_t)q * NA * N, x + (size_t)q * N, a, i, j, k, sub);
   if (sub != 0) return;
   if (b) acc = (double)b[(size_t)q * N + a] - acc;
   if (dinv) acc *= (double)dinv[(size_t)q * N + a];
@@ -101,7 +123,7 @@ __global__ __launch_bounds__(256) void k_lspmv(GridDev g, const TV *__restrict__
 // Chebyshev step k (Saad, Alg. 12.1 with diagonal preconditioning):
 //   r = D^-1 (b - A xin);  d = c1 d + c2 r;  xout = xin + d.
 // With zero_x the product is skipped (xin = 0).
-template <int D, typename TV, typename TX, int LPR>
+template <int D, typename TV, typename TX, int LPR, bool SYM>
 __global__ __launch_bounds__(256) void k_cheb(GridDev g, const TV *__restrict__ A,
                                               const TV *__restrict__ dinv,
                                               const TX *__restrict__ b, const TX *__restrict__ xin,
@@ -119,7 +141,8 @@ __global__ __launch_bounds__(256) void k_cheb(GridDev g, const TV *__restrict__ 
   if (!zero_x) {
     int i, j, k;
     node_ijk(g, a, i, j, k);
-    ax = row_product<D, TV, TX, LPR>(g, A + (size_t)q * NT * N, xin + (size_t)q * N, a, i, j, k, sub);
+    constexpr int NA = stored_offsets<D, SYM>();
+    ax = row_product<D, TV, TX, LPR, SYM>(g, A + (size_t)q * NA * N, xin + (size_t)q * N, a, i, j, k, sub);
     xa = (double)xin[ia];
   }
   if (sub != 0) return;
@@ -129,29 +152,53 @@ __global__ __launch_bounds__(256) void k_cheb(GridDev g, const TV *__restrict__ 
   xout[ia] = (TX)(xa + dn);
 }
 
+#define DPP_SHAPE_SWITCH(sh, KCALL)                         \
+  do {                                                      \
+    if (sh.sym) {                                           \
+      switch (sh.lpr) {                                     \
+        case 1: { constexpr int L_ = 1; constexpr bool S_ = true; KCALL; } break; \
+        case 2: { constexpr int L_ = 2; constexpr bool S_ = true; KCALL; } break; \
+        case 4: { constexpr int L_ = 4; constexpr bool S_ = true; KCALL; } break; \
+        default: { constexpr int L_ = 8; constexpr bool S_ = true; KCALL; } break; \
+      }                                                     \
+    } else {                                                \
+      switch (sh.lpr) {                                     \
+        case 1: { constexpr int L_ = 1; constexpr bool S_ = false; KCALL; } break; \
+        case 2: { constexpr int L_ = 2; constexpr bool S_ = false; KCALL; } break; \
+        case 4: { constexpr int L_ = 4; constexpr bool S_ = false; KCALL; } break; \
+        default: { constexpr int L_ = 8; constexpr bool S_ = false; KCALL; } break; \
+      }                                                     \
+    }                                                       \
+  } while (0)
+
 template <int D, typename TV, typename TX>
-void launch_lspmv(int lpr, const Grid &gl, hipStream_t s, const TV *A, const TX *x, TX *y,
+void launch_lspmv(Shape sh, const Grid &gl, hipStream_t s, const TV *A, const TX *x, TX *y,
                   const TX *b, const TV *dinv) {
-  const dim3 grid(blocks_for(gl.N * lpr, 256), 2);
-  switch (lpr) {
-    case 1: k_lspmv<D, TV, TX, 1><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv); break;
-    case 2: k_lspmv<D, TV, TX, 2><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv); break;
-    case 4: k_lspmv<D, TV, TX, 4><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv); break;
-    default: k_lspmv<D, TV, TX, 8><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv); break;
-  }
+  const dim3 grid(blocks_for(gl.N * sh.lpr, 256), 2);
+  DPP_SHAPE_SWITCH(sh, (k_lspmv<D, TV, TX, L_, S_><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv)));
 }
 
 template <int D, typename TV, typename TX>
-void launch_cheb(int lpr, const Grid &gl, hipStream_t s, const TV *A, const TV *di, const TX *b,
+void launch_cheb(Shape sh, const Grid &gl, hipStream_t s, const TV *A, const TV *di, const TX *b,
                  const TX *xin, TX *xout, TX *d, Sc2 c1, Sc2 c2, int zero_x) {
-  const int l = zero_x ? 1 : lpr;
-  const dim3 grid(blocks_for(gl.N * l, 256), 2);
-  switch (l) {
-    case 1: k_cheb<D, TV, TX, 1><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin, xout, d, c1, c2, zero_x); break;
-    case 2: k_cheb<D, TV, TX, 2><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin, xout, d, c1, c2, zero_x); break;
-    case 4: k_cheb<D, TV, TX, 4><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin, xout, d, c1, c2, zero_x); break;
-    default: k_cheb<D, TV, TX, 8><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin, xout, d, c1, c2, zero_x); break;
-  }
+  if (zero_x) sh.lpr = 1;
+  const dim3 grid(blocks_for(gl.N * sh.lpr, 256), 2);
+  DPP_SHAPE_SWITCH(sh, (k_cheb<D, TV, TX, L_, S_><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin, xout,
+                                                                          d, c1, c2, zero_x)));
+}
+
+// Ah[q][h][a] = A[q][t0 + h][a]: the zero offset and positive half of T.
+template <int D, typename TV>
+__global__ void k_pack_half(const TV *__restrict__ A, long N, TV *__restrict__ Ah) {
+  constexpr int NT = Tabs<D>::NT;
+  constexpr int T0 = TAB<D>.t0;
+  constexpr int NH = NT - T0;
+  const int q = blockIdx.y;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)NH * N) return;
+  const int h = (int)(idx / N);
+  const long a = idx - (long)h * N;
+  Ah[((size_t)q * NH + h) * N + a] = A[((size_t)q * NT + T0 + h) * N + a];
 }
 
 // b_c(C) = sum_f P(f, C) r(f)
@@ -412,14 +459,15 @@ __global__ void k_f64_to_f32(const double *__restrict__ x, float *__restrict__ y
 
 constexpr int RED_BLOCKS = 512;
 
-// Autotuner for the lanes-per-row width of the level stencil kernels: each
-// candidate is timed with HIP events on the level's own operator, the fastest
-// wins; results are cached per (dim, nodes, value bytes) for the process.
+// Autotuner for the kernel shape of the level stencil kernels (lanes per
+// row 1/2/4/8, full or symmetric-half storage): each candidate is timed with
+// HIP events on the level's own operator and the fastest wins; results are
+// cached per (dim, nodes, value bytes) for the process.
 std::mutex g_tune_mu;
-std::map<std::tuple<int, long, int>, int> g_tune_cache;
+std::map<std::tuple<int, long, int>, Shape> g_tune_cache;
 
 template <int D>
-int tune_lpr(Level &L, hipStream_t s) {
+Shape tune_shape(Level &L, hipStream_t s) {
   const auto key = std::make_tuple(D, L.g.N, 8);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -429,30 +477,42 @@ int tune_lpr(Level &L, hipStream_t s) {
   hipEvent_t e0, e1;
   DPP_HIP(hipEventCreate(&e0));
   DPP_HIP(hipEventCreate(&e1));
-  int best = 1;
+  Shape best;
   float best_ms = 1e30f;
-  const double *A = L.A.as<double>(), *x = L.xa.as<double>();
+  const double *x = L.xa.as<double>();
   double *y = L.xb.as<double>();
   DPP_HIP(hipMemsetAsync(L.xa.ptr, 0, L.xa.bytes, s));
-  for (int cand : {1, 2, 4, 8}) {
-    launch_lspmv<D, double, double>(cand, L.g, s, A, x, y, nullptr, nullptr);
-    DPP_HIP(hipEventRecord(e0, s));
-    for (int r = 0; r < 5; ++r) launch_lspmv<D, double, double>(cand, L.g, s, A, x, y, nullptr, nullptr);
-    DPP_HIP(hipEventRecord(e1, s));
-    DPP_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    DPP_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms * 0.97f) {  // prefer fewer lanes unless clearly faster
-      best_ms = ms;
-      best = cand;
+  for (int sym = 0; sym < 2; ++sym)
+    for (int cand : {1, 2, 4, 8}) {
+      const Shape sh{cand, sym != 0};
+      const double *A = sh.sym ? L.Ah.as<double>() : L.A.as<double>();
+      launch_lspmv<D, double, double>(sh, L.g, s, A, x, y, nullptr, nullptr);
+      DPP_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 5; ++r) launch_lspmv<D, double, double>(sh, L.g, s, A, x, y, nullptr, nullptr);
+      DPP_HIP(hipEventRecord(e1, s));
+      DPP_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      DPP_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms * 0.97f) {  // prefer the simpler shape unless clearly faster
+        best_ms = ms;
+        best = sh;
+      }
     }
-  }
-  check_launch("tune_lpr");
+  check_launch("tune_shape");
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache[key] = best;
   return best;
+}
+
+template <int D>
+void pack_half(Level &L, hipStream_t s) {
+  constexpr int NH = Tabs<D>::NT - TAB<D>.t0;
+  L.Ah.alloc(sizeof(double) * 2 * NH * L.g.N);
+  k_pack_half<D, double><<<dim3(blocks_for((long)NH * L.g.N, 256), 2), 256, 0, s>>>(
+      L.A.as<double>(), L.g.N, L.Ah.as<double>());
+  check_launch("pack_half");
 }
 
 template <int D>
@@ -498,7 +558,7 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
     k_scale2<<<grid, 256, 0, s>>>(x, gl.N, pc->red.as<double>() + 2 * RED_BLOCKS + 2);
     double lam[2] = {0, 0};
     for (int it = 0; it < o.power_iters; ++it) {
-      launch_lspmv<D, double, double>(1, gl, s, L.A.as<double>(), x, y, nullptr, L.dinv.as<double>());
+      launch_lspmv<D, double, double>(Shape{}, gl, s, L.A.as<double>(), x, y, nullptr, L.dinv.as<double>());
       sumsq2<D>(pc, y, gl.N, ss, s);
       lam[0] = std::sqrt(ss[0]);
       lam[1] = std::sqrt(ss[1]);
@@ -521,7 +581,10 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
     check_launch("galerkin");
     pc->lv.push_back(std::move(C));
   }
-  for (size_t l = 0; l + 1 < pc->lv.size(); ++l) pc->lv[l]->lpr = tune_lpr<D>(*pc->lv[l], s);
+  for (size_t l = 0; l + 1 < pc->lv.size(); ++l) {
+    pack_half<D>(*pc->lv[l], s);
+    pc->lv[l]->shape = tune_shape<D>(*pc->lv[l], s);
+  }
   Level &Lc = *pc->lv.back();
   const int n = (int)Lc.g.N;
   DPP_CHECK(n <= 4000, DPP_ERR_ARG, "coarsest multigrid level too large (lower coarse_max)");
@@ -575,12 +638,13 @@ LevelBufs<TX> bufs(Level &L);
 template <>
 LevelBufs<double> bufs<double>(Level &L) {
   return {L.b.as<double>(), L.xa.as<double>(), L.xb.as<double>(), L.d.as<double>(),
-          L.r.as<double>(), L.e.as<double>(), L.A.ptr, L.dinv.ptr};
+          L.r.as<double>(), L.e.as<double>(), L.shape.sym ? L.Ah.ptr : L.A.ptr, L.dinv.ptr};
 }
 template <>
 LevelBufs<float> bufs<float>(Level &L) {
   return {L.b32.as<float>(), L.xa32.as<float>(), L.xb32.as<float>(), L.d32.as<float>(),
-          L.r32.as<float>(), L.e32.as<float>(), L.A32.ptr, L.dinv32.ptr};
+          L.r32.as<float>(), L.e32.as<float>(), L.shape.sym ? L.Ah32.ptr : L.A32.ptr,
+          L.dinv32.ptr};
 }
 
 template <int D, typename TX>
@@ -614,7 +678,7 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s) {
                                                      (dread ? tx : 0.0)));
   };
   // pre-smoothing from x = 0
-  const int lpr = L.lpr;
+  const Shape lpr = L.shape;
   {
     ProfScope ps(fam_cheb, cheb_bytes(true, false), s);
     launch_cheb<D, TV, TX>(lpr, L.g, s, A, di, b, nullptr, cur, B.d, c1[0], c2[0], 1);
@@ -668,6 +732,11 @@ void precond_make32(dpp_precond pc, hipStream_t s) {
     const size_t nA = L.A.bytes / sizeof(double), nv = 2 * (size_t)L.g.N;
     L.A32.alloc(nA * sizeof(float));
     k_f64_to_f32<<<2048, 256, 0, s>>>(L.A.as<double>(), L.A32.as<float>(), nA);
+    if (L.Ah.ptr) {
+      const size_t nH = L.Ah.bytes / sizeof(double);
+      L.Ah32.alloc(nH * sizeof(float));
+      k_f64_to_f32<<<2048, 256, 0, s>>>(L.Ah.as<double>(), L.Ah32.as<float>(), nH);
+    }
     if (L.dinv.ptr) {
       L.dinv32.alloc(nv * sizeof(float));
       k_f64_to_f32<<<256, 256, 0, s>>>(L.dinv.as<double>(), L.dinv32.as<float>(), nv);
@@ -712,12 +781,13 @@ void level_spmv(dpp_precond pc, int level, int net, const double *x, double *y, 
   // run both networks through the scratch vectors, copy the requested one
   DPP_HIP(hipMemsetAsync(L.r.ptr, 0, sizeof(double) * 2 * N, s));
   DPP_HIP(hipMemcpyAsync(L.r.as<double>() + net * N, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  const double *A = L.shape.sym ? L.Ah.as<double>() : L.A.as<double>();
   if (pc->prob->g.dim == 3)
-    launch_lspmv<3, double, double>(L.lpr, L.g, s, L.A.as<double>(), L.r.as<double>(),
-                                    L.d.as<double>(), nullptr, nullptr);
+    launch_lspmv<3, double, double>(L.shape, L.g, s, A, L.r.as<double>(), L.d.as<double>(),
+                                    nullptr, nullptr);
   else
-    launch_lspmv<2, double, double>(L.lpr, L.g, s, L.A.as<double>(), L.r.as<double>(),
-                                    L.d.as<double>(), nullptr, nullptr);
+    launch_lspmv<2, double, double>(L.shape, L.g, s, A, L.r.as<double>(), L.d.as<double>(),
+                                    nullptr, nullptr);
   check_launch("level_spmv");
   DPP_HIP(hipMemcpyAsync(y, L.d.as<double>() + net * N, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
 }

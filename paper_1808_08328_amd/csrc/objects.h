@@ -53,14 +53,22 @@ struct dpp_problem_s {
 
 namespace dpp {
 
+// Kernel shape of a multigrid level: lanes per stencil row (1, 2, 4, 8) and
+// full or symmetric-half storage; chosen per level by the autotuner.
+struct Shape {
+  int lpr = 1;
+  bool sym = false;
+};
+
 struct Level {
   Grid g;
   DBuf A;        // [2][nt][N] FP64 stencil values (network-major)
   DBuf A32;      // FP32 copy (mixed)
+  DBuf Ah, Ah32; // symmetric half: zero offset + positive half of T
   DBuf dinv;     // [2][N]
   DBuf dinv32;
   double lo[2] = {0, 0}, hi[2] = {0, 0};
-  int lpr = 1;     // lanes per stencil row in the level kernels (autotuned)
+  Shape shape;     // level kernel shape (autotuned)
   // work vectors [2][N] each (FP64 and FP32 views share nothing)
   DBuf b, xa, xb, d, r, e;          // e: coarse-grid correction received from below
   DBuf b32, xa32, xb32, d32, r32, e32;

@@ -126,6 +126,30 @@ def test_multigrid_hierarchy_and_cycle_match_oracle(case, cmax):
     assert relmax(H(pc.apply(T(r))), F.apply(r)) <= 1e-11
 
 
+@pytest.mark.parametrize("case", ["2d_ragged_grf", "3d_8_mms"])
+def test_every_level_kernel_shape_matches_oracle(case):
+    """All lanes-per-row / symmetric-storage variants the autotuner may pick."""
+    prob = CASES[case]()
+    S = odpp.assemble(prob)
+    P = lib().assemble_problem(prob)
+    pc = P.setup_precond(coarse_max=10)
+    Hs = [omg.setup(sp_, prob.dim, prob.n, omg.MGOptions(coarse_max=10)) for sp_ in odpp.selfp(S)]
+    nlev = pc.info()["levels"]
+    assert nlev >= 3
+    N = P.n_nodes
+    b = I.random_vector(2 * N, 5)
+    ref = np.concatenate([omg.vcycle(Hs[i], b[i * N:(i + 1) * N]) for i in range(2)])
+    for lanes in (1, 2, 4, 8):
+        for sym in (0, 1):
+            for l in range(nlev - 1):
+                pc.set_shape(l, lanes, sym)
+                assert pc.shape(l) == (lanes, sym)
+            x = I.random_vector(N, 6)
+            for i in range(2):
+                assert relmax(H(pc.level_spmv(0, i, T(x))), Hs[i].levels[0].A @ x) <= 1e-13
+            assert relmax(H(pc.vcycle(T(b))), ref) <= 1e-11, (lanes, sym)
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_fp64_solve_matches_oracle_direct_solve(case):
     prob = CASES[case]()
