@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-max-iters", type=int, default=60)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 512 MiB device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); "
@@ -114,6 +116,12 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     dpp.lib()  # fail loudly if the HIP library is missing
 
+    if args.calibrate_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prob = I.make_config(args.config)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

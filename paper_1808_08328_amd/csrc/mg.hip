@@ -655,7 +655,10 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s) {
   const GridDev gd = dev(L.g);
   const dim3 grid(blocks_for(L.g.N, 256), 2);
   const double tv = sizeof(TV), tx = sizeof(TX), Nl = (double)L.g.N;
-  const double pairs = valid_pairs<D, true>(L.g);
+  // stored matrix entries the format must stream: the full stencil, or with
+  // symmetric storage the zero offset plus the positive half
+  const double pairs_full = valid_pairs<D, true>(L.g);
+  const double pairs = L.shape.sym ? 0.5 * (pairs_full + Nl) : pairs_full;
   if (l == nl - 1) {
     const int n = pc->ncoarse;
     ProfScope ps(PF_COARSE, 2.0 * n * (n * 8.0 + 2 * tx), s);
