@@ -209,10 +209,11 @@ dpp_status dpp_param_grad(dpp_problem prob, const double *x, const double *lambd
  * they run on, and the algorithmic bytes each launch must move (matrix
  * entries inside the box, vectors read and written once) are accumulated.
  * dpp_profile_enable(on) also clears earlier records.  Families:
- *   0 y = K x / r = b - K x          1 Chebyshev step on S_p (finest level)
+ *   0 y = K x / r = b - K x          1 Chebyshev step with S_p product (finest)
  *   2 residual b - S_p x (finest)    3 r_p - K_pu D^-1 r_u
  *   4 D^-1 (r_u - K_up z_p)          5 coarser multigrid levels + coarse solve
- *   6 restriction / prolongation     7 Arnoldi (CGS2 passes, update)
+ *   6 finest-level vector steps (first Chebyshev step, restriction,
+ *     prolongation)                  7 Arnoldi (CGS2 passes, norms, scaling)
  * dpp_profile_read synchronises on the recorded events and returns the launch
  * count, total milliseconds and total algorithmic bytes of one family. */
 dpp_status dpp_profile_enable(int on);

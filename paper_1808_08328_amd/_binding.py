@@ -109,7 +109,7 @@ def _stream(stream=None):
 
 
 PROFILE_FAMILIES = ["spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "schur_vel", "coarse_levels",
-                    "transfer_l0", "arnoldi"]
+                    "vector_l0", "arnoldi"]
 
 
 def profile_enable(on=True):

@@ -98,7 +98,9 @@ constexpr int stored_offsets() {
 }
 
 // A x on a level, optionally returning b - A x and/or scaling by dinv.
-template <int D, typename TV, typename TX, int LPR, bool SYM>
+// FINE only separates the finest-level instances from the coarse-level ones
+// (distinct kernel names in profiles); the code is the same.
+template <int D, typename TV, typename TX, int LPR, bool SYM, bool FINE>
 __global__ __launch_bounds__(256) void k_lspmv(GridDev g, const TV *__restrict__ A,
                                                const TX *__restrict__ x, TX *__restrict__ y,
                                                const TX *__restrict__ b,
@@ -122,13 +124,13 @@ __global__ __launch_bounds__(256) void k_lspmv(GridDev g, const TV *__restrict__
 
 // Chebyshev step k (Saad, Alg. 12.1 with diagonal preconditioning):
 //   r = D^-1 (b - A xin);  d = c1 d + c2 r;  xout = xin + d.
-// With zero_x the product is skipped (xin = 0).
-template <int D, typename TV, typename TX, int LPR, bool SYM>
+// (The first step from a zero guess has no product: k_cheb_first.)
+template <int D, typename TV, typename TX, int LPR, bool SYM, bool FINE>
 __global__ __launch_bounds__(256) void k_cheb(GridDev g, const TV *__restrict__ A,
                                               const TV *__restrict__ dinv,
                                               const TX *__restrict__ b, const TX *__restrict__ xin,
                                               TX *__restrict__ xout, TX *__restrict__ d, Sc2 c1,
-                                              Sc2 c2, int zero_x) {
+                                              Sc2 c2) {
   constexpr int NT = Tabs<D>::NT;
   const long N = g.N;
   const int q = blockIdx.y;
@@ -137,15 +139,13 @@ __global__ __launch_bounds__(256) void k_cheb(GridDev g, const TV *__restrict__ 
   const int sub = (int)(gid % LPR);
   if (a >= N) return;
   const size_t ia = (size_t)q * N + a;
-  double ax = 0.0, xa = 0.0;
-  if (!zero_x) {
-    int i, j, k;
-    node_ijk(g, a, i, j, k);
-    constexpr int NA = stored_offsets<D, SYM>();
-    ax = row_product<D, TV, TX, LPR, SYM>(g, A + (size_t)q * NA * N, xin + (size_t)q * N, a, i, j, k, sub);
-    xa = (double)xin[ia];
-  }
+  int i, j, k;
+  node_ijk(g, a, i, j, k);
+  constexpr int NA = stored_offsets<D, SYM>();
+  const double ax =
+      row_product<D, TV, TX, LPR, SYM>(g, A + (size_t)q * NA * N, xin + (size_t)q * N, a, i, j, k, sub);
   if (sub != 0) return;
+  const double xa = (double)xin[ia];
   const double r = (double)dinv[ia] * ((double)b[ia] - ax);
   const double dn = (c1.v[q] != 0.0 ? c1.v[q] * (double)d[ia] : 0.0) + c2.v[q] * r;
   d[ia] = (TX)dn;
@@ -173,18 +173,24 @@ __global__ __launch_bounds__(256) void k_cheb(GridDev g, const TV *__restrict__ 
 
 template <int D, typename TV, typename TX>
 void launch_lspmv(Shape sh, const Grid &gl, hipStream_t s, const TV *A, const TX *x, TX *y,
-                  const TX *b, const TV *dinv) {
+                  const TX *b, const TV *dinv, bool fine = false) {
   const dim3 grid(blocks_for(gl.N * sh.lpr, 256), 2);
-  DPP_SHAPE_SWITCH(sh, (k_lspmv<D, TV, TX, L_, S_><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv)));
+  if (fine)
+    DPP_SHAPE_SWITCH(sh, (k_lspmv<D, TV, TX, L_, S_, true><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv)));
+  else
+    DPP_SHAPE_SWITCH(sh, (k_lspmv<D, TV, TX, L_, S_, false><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv)));
 }
 
 template <int D, typename TV, typename TX>
 void launch_cheb(Shape sh, const Grid &gl, hipStream_t s, const TV *A, const TV *di, const TX *b,
-                 const TX *xin, TX *xout, TX *d, Sc2 c1, Sc2 c2, int zero_x) {
-  if (zero_x) sh.lpr = 1;
+                 const TX *xin, TX *xout, TX *d, Sc2 c1, Sc2 c2, bool fine) {
   const dim3 grid(blocks_for(gl.N * sh.lpr, 256), 2);
-  DPP_SHAPE_SWITCH(sh, (k_cheb<D, TV, TX, L_, S_><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin, xout,
-                                                                          d, c1, c2, zero_x)));
+  if (fine)
+    DPP_SHAPE_SWITCH(sh, (k_cheb<D, TV, TX, L_, S_, true><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin,
+                                                                                xout, d, c1, c2)));
+  else
+    DPP_SHAPE_SWITCH(sh, (k_cheb<D, TV, TX, L_, S_, false><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin,
+                                                                                 xout, d, c1, c2)));
 }
 
 // Ah[q][h][a] = A[q][t0 + h][a]: the zero offset and positive half of T.
@@ -199,6 +205,20 @@ __global__ void k_pack_half(const TV *__restrict__ A, long N, TV *__restrict__ A
   const int h = (int)(idx / N);
   const long a = idx - (long)h * N;
   Ah[((size_t)q * NH + h) * N + a] = A[((size_t)q * NT + T0 + h) * N + a];
+}
+
+// First Chebyshev step from a zero guess: x = d = c2 D^-1 b (no product).
+template <typename TV, typename TX>
+__global__ __launch_bounds__(256) void k_cheb_first(long N, const TV *__restrict__ dinv,
+                                                    const TX *__restrict__ b, TX *__restrict__ x,
+                                                    TX *__restrict__ d, Sc2 c2) {
+  const int q = blockIdx.y;
+  const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  const size_t ia = (size_t)q * N + a;
+  const double v = c2.v[q] * (double)dinv[ia] * (double)b[ia];
+  d[ia] = (TX)v;
+  x[ia] = (TX)v;
 }
 
 // b_c(C) = sum_f P(f, C) r(f)
@@ -672,9 +692,10 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s) {
   std::vector<Sc2> c1, c2;
   cheb_coefs(L, deg, c1, c2);
   TX *cur = B.xa, *oth = B.xb;
-  const int fam_cheb = l == 0 ? PF_CHEB_L0 : PF_COARSE;
-  const int fam_res = l == 0 ? PF_RESID_L0 : PF_COARSE;
-  const int fam_tr = l == 0 ? PF_TRANSFER : PF_COARSE;
+  const bool fine = l == 0;
+  const int fam_cheb = fine ? PF_CHEB_L0 : PF_COARSE;
+  const int fam_res = fine ? PF_RESID_L0 : PF_COARSE;
+  const int fam_vec = fine ? PF_VECTOR_L0 : PF_COARSE;
   // Chebyshev step bytes: matrix entries + dinv, b, x_in, d_in (k>=1), d, x_out
   auto cheb_bytes = [&](bool zero_x, bool dread) {
     return 2.0 * ((zero_x ? 0.0 : pairs * tv) + Nl * (tv + tx * (zero_x ? 3.0 : 4.0) +
@@ -683,35 +704,35 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s) {
   // pre-smoothing from x = 0
   const Shape lpr = L.shape;
   {
-    ProfScope ps(fam_cheb, cheb_bytes(true, false), s);
-    launch_cheb<D, TV, TX>(lpr, L.g, s, A, di, b, nullptr, cur, B.d, c1[0], c2[0], 1);
+    ProfScope ps(fam_vec, cheb_bytes(true, false), s);
+    k_cheb_first<TV, TX><<<dim3(blocks_for(L.g.N, 256), 2), 256, 0, s>>>(L.g.N, di, b, cur, B.d, c2[0]);
   }
   for (int k = 1; k < deg; ++k) {
     ProfScope ps(fam_cheb, cheb_bytes(false, true), s);
-    launch_cheb<D, TV, TX>(lpr, L.g, s, A, di, b, cur, oth, B.d, c1[k], c2[k], 0);
+    launch_cheb<D, TV, TX>(lpr, L.g, s, A, di, b, cur, oth, B.d, c1[k], c2[k], fine);
     std::swap(cur, oth);
   }
   // residual, restriction, coarse correction
   {
     ProfScope ps(fam_res, 2.0 * (pairs * tv + 3.0 * Nl * tx), s);
-    launch_lspmv<D, TV, TX>(lpr, L.g, s, A, cur, B.r, b, (const TV *)nullptr);
+    launch_lspmv<D, TV, TX>(lpr, L.g, s, A, cur, B.r, b, (const TV *)nullptr, fine);
   }
   Level &Cl = *pc->lv[l + 1];
   LevelBufs<TX> CB = bufs<TX>(Cl);
   {
-    ProfScope ps(fam_tr, 2.0 * tx * (Nl + Cl.g.N), s);
+    ProfScope ps(fam_vec, 2.0 * tx * (Nl + Cl.g.N), s);
     k_restrict<D, TX><<<dim3(blocks_for(Cl.g.N, 256), 2), 256, 0, s>>>(gd, dev(Cl.g), B.r, CB.b);
   }
   vcyc<D, TX>(pc, l + 1, CB.b, CB.e, s);
   {
-    ProfScope ps(fam_tr, 2.0 * tx * (2.0 * Nl + Cl.g.N), s);
+    ProfScope ps(fam_vec, 2.0 * tx * (2.0 * Nl + Cl.g.N), s);
     k_prolong<D, TX><<<grid, 256, 0, s>>>(gd, dev(Cl.g), CB.e, cur);
   }
   // post-smoothing
   for (int k = 0; k < deg; ++k) {
     TX *out = (k == deg - 1) ? xout : oth;
     ProfScope ps(fam_cheb, cheb_bytes(false, k > 0), s);
-    launch_cheb<D, TV, TX>(lpr, L.g, s, A, di, b, cur, out, B.d, c1[k], c2[k], 0);
+    launch_cheb<D, TV, TX>(lpr, L.g, s, A, di, b, cur, out, B.d, c1[k], c2[k], fine);
     oth = cur;
     cur = out;
   }

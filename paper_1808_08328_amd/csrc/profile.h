@@ -14,7 +14,7 @@ enum ProfFamily {
   PF_SCHUR_RHS = 3,  // r_p - K_pu D^-1 r_u
   PF_SCHUR_VEL = 4,  // D^-1 (r_u - K_up z_p)
   PF_COARSE = 5,     // every kernel of the coarser levels and the coarse solve
-  PF_TRANSFER = 6,   // restriction and prolongation from/to the finest level
+  PF_VECTOR_L0 = 6,  // finest level: first Chebyshev step (no product), restriction, prolongation
   PF_ARNOLDI = 7,    // CGS2 passes, norms, scaling, solution update
   PF_COUNT = 8
 };
