@@ -7,8 +7,9 @@
 //
 // Storage: for every node a and every offset t of the node stencil St the
 // 4d+5 distinct values of the node-pair block (a, a+o_t) are kept in
-// structure-of-arrays form, kv[(v*NS + t)*N + a] (v = value kind, see
-// common.h).  Entries of pairs leaving the box are zero.  Each (a, t) is
+// structure-of-arrays form, kv[(v*NS + t)*ld + a] (v = value kind, see
+// common.h; ld = N rounded up to 32).  Entries of pairs leaving the box are
+// zero.  Each (a, t) is
 // computed by one thread that sums the contributions of the simplices holding
 // both nodes in a fixed order: no atomics, bit-reproducible.
 #include "objects.h"
@@ -113,8 +114,8 @@ __global__ __launch_bounds__(256) void k_assemble(GridDev g, Coef cf, double *__
       }
     }
   }
-  const size_t vs = (size_t)NS * N;
-  double *base = kv + (size_t)t * N + a;
+  const size_t vs = (size_t)NS * g.ld;
+  double *base = kv + (size_t)t * g.ld + a;
   for (int q = 0; q < 2; ++q) {
     base[kv_uu(D, q) * vs] = uu[q];
     for (int c = 0; c < D; ++c) {
@@ -234,8 +235,8 @@ __global__ void k_export(GridDev g, const double *__restrict__ kv, const int64_t
   if (a >= N) return;
   int ia[3];
   node_ijk(g, a, ia[0], ia[1], ia[2]);
-  const size_t vs = (size_t)NS * N;
-  auto val = [&](int v, int t) { return kv[v * vs + (size_t)t * N + a]; };
+  const size_t vs = (size_t)NS * g.ld;
+  auto val = [&](int v, int t) { return kv[v * vs + (size_t)t * g.ld + a]; };
   auto nb = [&](int t, long &b) {
     const int *o = TAB<D>.so[t];
     if (!inside(g, ia[0] + o[0], ia[1] + o[1], ia[2] + o[2])) return false;
@@ -358,7 +359,7 @@ void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, 
   P->beta_per_cell = prm->beta_cells != nullptr;
   P->ns = NS;
   P->nnz = count_nnz(g);
-  P->kvals.alloc(sizeof(double) * (size_t)nv_kinds(D) * NS * g.N);
+  P->kvals.alloc(sizeof(double) * (size_t)nv_kinds(D) * NS * padded(g.N));
   P->f.alloc(sizeof(double) * P->ndof());
   P->dinv.alloc(sizeof(double) * 2 * g.N);
   P->k1.alloc(sizeof(double) * g.nc);

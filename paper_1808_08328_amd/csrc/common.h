@@ -82,13 +82,19 @@ inline Grid coarse_grid(const Grid &f) {
   return g;
 }
 
+// Leading dimension of the structure-of-arrays operator storage: every
+// offset's value stream starts on a 256-byte boundary (no partial cache
+// lines at the stream ends).
+inline long padded(long N) { return (N + 31) / 32 * 32; }
+
 struct GridDev {
   int n[3];
   int m[3];
   long N;
+  long ld;
 };
 inline GridDev dev(const Grid &g) {
-  return GridDev{{g.n[0], g.n[1], g.n[2]}, {g.m[0], g.m[1], g.m[2]}, g.N};
+  return GridDev{{g.n[0], g.n[1], g.n[2]}, {g.m[0], g.m[1], g.m[2]}, g.N, padded(g.N)};
 }
 
 // ---------------------------------------------------------- stencils ----

@@ -11,7 +11,7 @@
 //     the ends of the Kuhn edge it sits on);
 //   * Galerkin coarse operators P^T A P, which keep the 65-point (19 in 2D)
 //     stencil of S_p on every level, so all levels share one index-free
-//     storage A[(i*NT + t)*N + a];
+//     storage A[(i*NT + t)*ld + a] (ld = N rounded up to 32);
 //   * Chebyshev smoothing (degree `cheb_degree`, diagonal preconditioning,
 //     interval [lo_frac*hi, hi], hi = hi_factor * ||D^-1 A x_k|| after
 //     `power_iters` power steps from a fixed integer-hash start vector);
@@ -70,7 +70,7 @@ __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq
       if (LPR > 1 && t >= NT) continue;
       const int *o = TAB<D>.to[t];
       if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
-      acc += (double)Aq[(size_t)t * N + a] * (double)xq[a + lin(g, o[0], o[1], o[2])];
+      acc += (double)Aq[(size_t)t * g.ld + a] * (double)xq[a + lin(g, o[0], o[1], o[2])];
     }
   } else {
 #pragma unroll
@@ -80,9 +80,9 @@ __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq
       const int *o = TAB<D>.to[T0 + h];
       const long lo = lin(g, o[0], o[1], o[2]);
       if (inside(g, i + o[0], j + o[1], k + o[2]))
-        acc += (double)Aq[(size_t)h * N + a] * (double)xq[a + lo];
+        acc += (double)Aq[(size_t)h * g.ld + a] * (double)xq[a + lo];
       if (h > 0 && inside(g, i - o[0], j - o[1], k - o[2]))
-        acc += (double)Aq[(size_t)h * N + a - lo] * (double)xq[a - lo];
+        acc += (double)Aq[(size_t)h * g.ld + a - lo] * (double)xq[a - lo];
     }
   }
   if constexpr (LPR > 1) {
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void k_lspmv(GridDev g, const TV *__restrict__
   int i, j, k;
   node_ijk(g, a, i, j, k);
   constexpr int NA = stored_offsets<D, SYM>();
-  double acc = row_product<D, TV, TX, LPR, SYM>(g, A + (size_t)q * NA * N, x + (size_t)q * N, a, i, j, k, sub);
+  double acc = row_product<D, TV, TX, LPR, SYM>(g, A + (size_t)q * NA * g.ld, x + (size_t)q * N, a, i, j, k, sub);
   if (sub != 0) return;
   if (b) acc = (double)b[(size_t)q * N + a] - acc;
   if (dinv) acc *= (double)dinv[(size_t)q * N + a];
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_cheb(GridDev g, const TV *__restrict__ 
   node_ijk(g, a, i, j, k);
   constexpr int NA = stored_offsets<D, SYM>();
   const double ax =
-      row_product<D, TV, TX, LPR, SYM>(g, A + (size_t)q * NA * N, xin + (size_t)q * N, a, i, j, k, sub);
+      row_product<D, TV, TX, LPR, SYM>(g, A + (size_t)q * NA * g.ld, xin + (size_t)q * N, a, i, j, k, sub);
   if (sub != 0) return;
   const double xa = (double)xin[ia];
   const double r = (double)dinv[ia] * ((double)b[ia] - ax);
@@ -195,7 +195,7 @@ void launch_cheb(Shape sh, const Grid &gl, hipStream_t s, const TV *A, const TV 
 
 // Ah[q][h][a] = A[q][t0 + h][a]: the zero offset and positive half of T.
 template <int D, typename TV>
-__global__ void k_pack_half(const TV *__restrict__ A, long N, TV *__restrict__ Ah) {
+__global__ void k_pack_half(const TV *__restrict__ A, long N, long ld, TV *__restrict__ Ah) {
   constexpr int NT = Tabs<D>::NT;
   constexpr int T0 = TAB<D>.t0;
   constexpr int NH = NT - T0;
@@ -204,7 +204,7 @@ __global__ void k_pack_half(const TV *__restrict__ A, long N, TV *__restrict__ A
   if (idx >= (long)NH * N) return;
   const int h = (int)(idx / N);
   const long a = idx - (long)h * N;
-  Ah[((size_t)q * NH + h) * N + a] = A[((size_t)q * NT + T0 + h) * N + a];
+  Ah[((size_t)q * NH + h) * ld + a] = A[((size_t)q * NT + T0 + h) * ld + a];
 }
 
 // First Chebyshev step from a zero guess: x = d = c2 D^-1 b (no product).
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) void k_galerkin(GridDev gf, GridDev gc, const 
     double wf[NS], wg[NS];
     const int nf = fine_support<D>(gf, gc, cc, fs, wf);
     const int ng = fine_support<D>(gf, gc, c2, gs, wg);
-    const double *Aq = A + (size_t)q * NT * gf.N;
+    const double *Aq = A + (size_t)q * NT * gf.ld;
     for (int u = 0; u < nf; ++u) {
       const long fidx = fs[u][0] + (long)gf.m[0] * (fs[u][1] + (long)gf.m[1] * fs[u][2]);
       double s = 0.0;
@@ -339,12 +339,12 @@ __global__ __launch_bounds__(256) void k_galerkin(GridDev gf, GridDev gc, const 
         if (dx < -2 || dx > 2 || dy < -2 || dy > 2 || dz < -2 || dz > 2) continue;
         const int tt = TAB<D>.tidx[(dx + 2) + 5 * (dy + 2) + 25 * (dz + 2)];
         if (tt < 0) continue;
-        s += wg[v] * Aq[(size_t)tt * gf.N + fidx];
+        s += wg[v] * Aq[(size_t)tt * gf.ld + fidx];
       }
       acc += wf[u] * s;
     }
   }
-  Ac[((size_t)q * NT + t) * Nc + C] = acc;
+  Ac[((size_t)q * NT + t) * gc.ld + C] = acc;
 }
 
 template <int D>
@@ -354,7 +354,7 @@ __global__ void k_diag_inv(GridDev g, const double *__restrict__ A, double *__re
   const int q = blockIdx.y;
   const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= N) return;
-  dinv[(size_t)q * N + a] = 1.0 / A[((size_t)q * NT + TAB<D>.t0) * N + a];
+  dinv[(size_t)q * N + a] = 1.0 / A[((size_t)q * NT + TAB<D>.t0) * g.ld + a];
 }
 
 template <int D>
@@ -371,7 +371,7 @@ __global__ void k_dense_fill(GridDev g, const double *__restrict__ A, double *__
   for (int t = 0; t < NT; ++t) {
     const int *o = TAB<D>.to[t];
     if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
-    Mq[a + lin(g, o[0], o[1], o[2])] = A[((size_t)q * NT + t) * N + a];
+    Mq[a + lin(g, o[0], o[1], o[2])] = A[((size_t)q * NT + t) * g.ld + a];
   }
 }
 
@@ -529,9 +529,9 @@ Shape tune_shape(Level &L, hipStream_t s) {
 template <int D>
 void pack_half(Level &L, hipStream_t s) {
   constexpr int NH = Tabs<D>::NT - TAB<D>.t0;
-  L.Ah.alloc(sizeof(double) * 2 * NH * L.g.N);
+  L.Ah.alloc(sizeof(double) * 2 * NH * padded(L.g.N));
   k_pack_half<D, double><<<dim3(blocks_for((long)NH * L.g.N, 256), 2), 256, 0, s>>>(
-      L.A.as<double>(), L.g.N, L.Ah.as<double>());
+      L.A.as<double>(), L.g.N, padded(L.g.N), L.Ah.as<double>());
   check_launch("pack_half");
 }
 
@@ -554,7 +554,7 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
   Grid g = P->g;
   auto lev0 = std::make_unique<Level>();
   lev0->g = g;
-  lev0->A.alloc(sizeof(double) * 2 * NT * g.N);
+  lev0->A.alloc(sizeof(double) * 2 * NT * padded(g.N));
   make_selfp(P, lev0->A.as<double>(), s);
   pc->lv.push_back(std::move(lev0));
   while (true) {
@@ -595,7 +595,7 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
     }
     auto C = std::make_unique<Level>();
     C->g = gc;
-    C->A.alloc(sizeof(double) * 2 * NT * gc.N);
+    C->A.alloc(sizeof(double) * 2 * NT * padded(gc.N));
     dim3 gg(blocks_for(gc.N * NT, 256), 2);
     k_galerkin<D><<<gg, 256, 0, s>>>(dev(gl), dev(gc), L.A.as<double>(), C->A.as<double>());
     check_launch("galerkin");

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict_
   for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int c = 0; c < D; ++c) au[q][c] = 0.0;
-  const size_t vs = (size_t)NS * N;
+  const size_t vs = (size_t)NS * g.ld;
   const long ou0 = off_u(D, N, 0), ou1 = off_u(D, N, 1), op0 = off_p(D, N, 0),
              op1 = off_p(D, N, 1);
 #pragma unroll
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict_
     }
     xp[0] = x[op0 + b];
     xp[1] = x[op1 + b];
-    const TV *base = kv + (size_t)t * N + a;
+    const TV *base = kv + (size_t)t * g.ld + a;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const double uu = (double)base[kv_uu(D, q) * vs];
@@ -86,14 +86,14 @@ __global__ void k_spmv_block(GridDev g, const double *__restrict__ kv, int which
   node_ijk(g, a, i, j, k);
   const int q = (which - 1) & 1;
   const bool up = which <= 2;
-  const size_t vs = (size_t)NS * N;
+  const size_t vs = (size_t)NS * g.ld;
   double acc[D], accp = 0.0;
   for (int c = 0; c < D; ++c) acc[c] = 0.0;
   for (int t = 0; t < NS; ++t) {
     const int *o = TAB<D>.so[t];
     if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
     const long b = a + lin(g, o[0], o[1], o[2]);
-    const double *base = kv + (size_t)t * N + a;
+    const double *base = kv + (size_t)t * g.ld + a;
     for (int c = 0; c < D; ++c) {
       if (up)
         acc[c] += base[kv_up(D, q, c) * vs] * x[b];
@@ -113,9 +113,9 @@ __global__ void k_dinv(GridDev g, const double *__restrict__ kv, double *__restr
   const long N = g.N;
   const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= N) return;
-  const size_t vs = (size_t)NS * N;
+  const size_t vs = (size_t)NS * g.ld;
   const int t0 = TAB<D>.s0;
-  for (int q = 0; q < 2; ++q) dinv[q * N + a] = 1.0 / kv[kv_uu(D, q) * vs + (size_t)t0 * N + a];
+  for (int q = 0; q < 2; ++q) dinv[q * N + a] = 1.0 / kv[kv_uu(D, q) * vs + (size_t)t0 * g.ld + a];
 }
 
 // selfp Schur block (eqs. S4_sp1, S4_sp2):
@@ -138,11 +138,11 @@ __global__ __launch_bounds__(256) void k_selfp(GridDev g, const double *__restri
   const int *to = TAB<D>.to[t];
   double acc = 0.0;
   if (inside(g, ib[0] + to[0], ib[1] + to[1], ib[2] + to[2])) {
-    const size_t vs = (size_t)NS * N;
+    const size_t vs = (size_t)NS * g.ld;
     const int st = TAB<D>.sidx[(to[0] + 1) + 3 * (to[1] + 1) + 9 * (to[2] + 1)];
     const bool small = to[0] >= -1 && to[0] <= 1 && to[1] >= -1 && to[1] <= 1 && to[2] >= -1 &&
                        to[2] <= 1;
-    if (small && st >= 0) acc = kv[kv_pp(D, q) * vs + (size_t)st * N + b];
+    if (small && st >= 0) acc = kv[kv_pp(D, q) * vs + (size_t)st * g.ld + b];
     for (int s = 0; s < NS; ++s) {
       const int *so = TAB<D>.so[s];
       if (!inside(g, ib[0] + so[0], ib[1] + so[1], ib[2] + so[2])) continue;
@@ -153,11 +153,12 @@ __global__ __launch_bounds__(256) void k_selfp(GridDev g, const double *__restri
       const long a = b + lin(g, so[0], so[1], so[2]);
       double sum = 0.0;
       for (int c = 0; c < D; ++c)
-        sum += kv[kv_pu(D, q, c) * vs + (size_t)s * N + b] * kv[kv_up(D, q, c) * vs + (size_t)r * N + a];
+        sum += kv[kv_pu(D, q, c) * vs + (size_t)s * g.ld + b] *
+               kv[kv_up(D, q, c) * vs + (size_t)r * g.ld + a];
       acc -= sum * dinv[q * N + a];
     }
   }
-  S[((size_t)q * NT + t) * N + b] = acc;
+  S[((size_t)q * NT + t) * g.ld + b] = acc;
 }
 
 // rhat_i(b) = r_p_i(b) - sum_t sum_c K_pu^i(b, (b+o_t, c)) dinv_i(b+o_t) r_u_i(b+o_t, c)
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(256) void k_schur_rhs(GridDev g, const TV *__restri
   if (b >= N) return;
   int i, j, k;
   node_ijk(g, b, i, j, k);
-  const size_t vs = (size_t)NS * N;
+  const size_t vs = (size_t)NS * g.ld;
   const long ou = off_u(D, N, q);
   double acc = r[off_p(D, N, q) + b];
 #pragma unroll
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(256) void k_schur_rhs(GridDev g, const TV *__restri
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < D; ++c)
-      s += (double)kv[kv_pu(D, q, c) * vs + (size_t)t * N + b] * r[ou + D * a + c];
+      s += (double)kv[kv_pu(D, q, c) * vs + (size_t)t * g.ld + b] * r[ou + D * a + c];
     acc -= s * di;
   }
   rhat[q * N + b] = (TX)acc;
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restri
   if (a >= N) return;
   int i, j, k;
   node_ijk(g, a, i, j, k);
-  const size_t vs = (size_t)NS * N;
+  const size_t vs = (size_t)NS * g.ld;
   const long ou = off_u(D, N, q);
   double acc[D];
 #pragma unroll
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restri
     const long b = a + lin(g, o[0], o[1], o[2]);
     const double zb = (double)zp[q * N + b];
 #pragma unroll
-    for (int c = 0; c < D; ++c) acc[c] -= (double)kv[kv_up(D, q, c) * vs + (size_t)t * N + a] * zb;
+    for (int c = 0; c < D; ++c) acc[c] -= (double)kv[kv_up(D, q, c) * vs + (size_t)t * g.ld + a] * zb;
   }
   const double di = dinv[q * N + a];
 #pragma unroll
