@@ -58,10 +58,16 @@ __device__ inline int exact_fine(int c, int n, int mc) { return ((n & 1) && c ==
 template <int D, typename TV, typename TX, int LPR, bool SYM>
 __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq,
                                      const TX *__restrict__ xq, long a, int i, int j, int k, int sub) {
+  // Entries of pairs that leave the box are stored as zeros, so the loads
+  // need no guard: the vector index is clamped into range (the zero entry
+  // multiplies a finite value) and only a mirror entry whose row index falls
+  // outside [0, N) is masked.  Unguarded loads let every load of the row be
+  // in flight at once.
   constexpr int NT = Tabs<D>::NT;
   constexpr int T0 = TAB<D>.t0;
   constexpr int NH = NT - T0;  // zero offset + positive half
-  const long N = g.N;
+  const long N = g.N, ld = g.ld;
+  (void)i; (void)j; (void)k;
   double acc = 0.0;
   if constexpr (!SYM) {
 #pragma unroll
@@ -69,8 +75,8 @@ __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq
       const int t = tt * LPR + (LPR == 1 ? 0 : sub);
       if (LPR > 1 && t >= NT) continue;
       const int *o = TAB<D>.to[t];
-      if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
-      acc += (double)Aq[(size_t)t * g.ld + a] * (double)xq[a + lin(g, o[0], o[1], o[2])];
+      const long b = min(max(a + lin(g, o[0], o[1], o[2]), 0L), N - 1);
+      acc += (double)Aq[(size_t)t * ld + a] * (double)xq[b];
     }
   } else {
 #pragma unroll
@@ -79,10 +85,14 @@ __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq
       if (LPR > 1 && h >= NH) continue;
       const int *o = TAB<D>.to[T0 + h];
       const long lo = lin(g, o[0], o[1], o[2]);
-      if (inside(g, i + o[0], j + o[1], k + o[2]))
-        acc += (double)Aq[(size_t)h * g.ld + a] * (double)xq[a + lo];
-      if (h > 0 && inside(g, i - o[0], j - o[1], k - o[2]))
-        acc += (double)Aq[(size_t)h * g.ld + a - lo] * (double)xq[a - lo];
+      const long bp = min(a + lo, N - 1);
+      acc += (double)Aq[(size_t)h * ld + a] * (double)xq[bp];
+      if (h > 0) {
+        const long bm = a - lo;
+        const long bc = max(bm, 0L);
+        const double v = (double)Aq[(size_t)h * ld + bc] * (double)xq[bc];
+        acc += (bm >= 0) ? v : 0.0;
+      }
     }
   }
   if constexpr (LPR > 1) {
