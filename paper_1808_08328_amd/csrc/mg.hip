@@ -69,8 +69,10 @@ __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq
   const long N = g.N, ld = g.ld;
   (void)i; (void)j; (void)k;
   double acc = 0.0;
+  // Offsets are processed in unrolled groups of 8: each group's loads are
+  // issued together without exhausting the register budget.
   if constexpr (!SYM) {
-#pragma unroll
+#pragma unroll 8
     for (int tt = 0; tt < (NT + LPR - 1) / LPR; ++tt) {
       const int t = tt * LPR + (LPR == 1 ? 0 : sub);
       if (LPR > 1 && t >= NT) continue;
@@ -79,7 +81,7 @@ __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq
       acc += (double)Aq[(size_t)t * ld + a] * (double)xq[b];
     }
   } else {
-#pragma unroll
+#pragma unroll 8
     for (int hh = 0; hh < (NH + LPR - 1) / LPR; ++hh) {
       const int h = hh * LPR + (LPR == 1 ? 0 : sub);
       if (LPR > 1 && h >= NH) continue;
@@ -110,8 +112,10 @@ constexpr int stored_offsets() {
 // A x on a level, optionally returning b - A x and/or scaling by dinv.
 // FINE only separates the finest-level instances from the coarse-level ones
 // (distinct kernel names in profiles); the code is the same.
+// Occupancy floor of the stencil kernels: at least 4 waves per SIMD (<= 128
+// VGPRs), which still leaves a whole row's loads in flight per wave.
 template <int D, typename TV, typename TX, int LPR, bool SYM, bool FINE>
-__global__ __launch_bounds__(256) void k_lspmv(GridDev g, const TV *__restrict__ A,
+__global__ __launch_bounds__(256, 4) void k_lspmv(GridDev g, const TV *__restrict__ A,
                                                const TX *__restrict__ x, TX *__restrict__ y,
                                                const TX *__restrict__ b,
                                                const TV *__restrict__ dinv) {
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(256) void k_lspmv(GridDev g, const TV *__restrict__
 //   r = D^-1 (b - A xin);  d = c1 d + c2 r;  xout = xin + d.
 // (The first step from a zero guess has no product: k_cheb_first.)
 template <int D, typename TV, typename TX, int LPR, bool SYM, bool FINE>
-__global__ __launch_bounds__(256) void k_cheb(GridDev g, const TV *__restrict__ A,
+__global__ __launch_bounds__(256, 4) void k_cheb(GridDev g, const TV *__restrict__ A,
                                               const TV *__restrict__ dinv,
                                               const TX *__restrict__ b, const TX *__restrict__ xin,
                                               TX *__restrict__ xout, TX *__restrict__ d, Sc2 c1,

@@ -35,7 +35,9 @@ __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict_
   // Out-of-box pairs hold zeros, so the neighbour index is clamped instead of
   // guarded (all loads of the row can be in flight together).
   (void)i; (void)j; (void)k;
-#pragma unroll
+  // one offset per trip: its 4d+5 value streams and 2d+2 neighbour unknowns
+  // are loaded together
+#pragma unroll 1
   for (int t = 0; t < NS; ++t) {
     const int *o = TAB<D>.so[t];
     const long b = min(max(a + lin(g, o[0], o[1], o[2]), 0L), N - 1);
