@@ -262,3 +262,60 @@ def test_full_size_solve_oracle_residual(name):
         assert np.array_equal(cih[a:b], S.K.indices[S.K.indptr[rr]:S.K.indptr[rr + 1]])
         assert np.abs(vvh[a:b] - S.K.data[S.K.indptr[rr]:S.K.indptr[rr + 1]]).max() <= \
             1e-13 * np.abs(S.K.data).max()
+
+
+def test_adjoint_gradient_full_size_finite_differences():
+    """48^3 log-normal workload: J = ||p1 - p1_obs||^2 with p1_obs from a solve
+    with ln k perturbed by 0.1 x an independent field (seed 3003); the adjoint
+    gradient's directional derivatives against central differences of GPU
+    forward solves on 20 random directions (seeds 4000-4019), the adjoint
+    residual checked with the oracle's own K (K^T lambda = g)."""
+    print("adjoint 48^3", flush=True)
+    dpp = lib()
+    base = I.make_config("c5_3d48_grf")
+    n = base.n
+    pert = I.hex_to_cells(I.grf_log10(n, 3, 3003, 0.0, 1.0), 3)
+    opts = dict(rtol=1e-12, maxiter=400)
+
+    def forward(lk1, lk2, beta):
+        P = dpp.assemble(3, n, T(np.exp(lk1)), T(np.exp(lk2)), T(base.p0_1), T(base.p0_2), beta=beta)
+        pc = P.setup_precond()
+        x, st = P.solve(pc, **opts)
+        assert st.converged
+        return P, pc, x
+
+    lk1, lk2 = np.log(base.k1), np.log(base.k2)
+    N = base.n_nodes
+    F = odpp.fields(3, N)
+    _, _, xo = forward(lk1 + 0.1 * pert, lk2 + 0.1 * pert, 1.0)
+    p_obs = H(xo)[F["p1"]]
+
+    def J(lk1_, lk2_, beta_):
+        _, _, x_ = forward(lk1_, lk2_, beta_)
+        return float(np.sum((H(x_)[F["p1"]] - p_obs) ** 2))
+
+    P, pc, x = forward(lk1, lk2, 1.0)
+    xh = H(x)
+    g = np.zeros(P.n_dof)
+    g[F["p1"]] = 2.0 * (xh[F["p1"]] - p_obs)
+    lam, st = P.solve_adjoint(pc, T(g), **opts)
+    lamh = H(lam)
+    # adjoint residual with the oracle's K
+    S = odpp.assemble(base)
+    rt = g - odpp.spmv(S.K.T.tocsr(), lamh)
+    assert np.linalg.norm(rt) <= 1e-10 * np.linalg.norm(g)
+    g1, g2, gb = (H(v) for v in P.param_grad(x, lam))
+    eps = 1e-5 * max(np.abs(lk1).max(), np.abs(lk2).max())
+    worst = 0.0
+    for j, d in enumerate(I.random_directions(20, base.n_cells, seed0=4000)):
+        which = j % 2
+        dk1 = d if which == 0 else 0.0
+        dk2 = d if which == 1 else 0.0
+        fd = (J(lk1 + eps * dk1, lk2 + eps * dk2, 1.0) - J(lk1 - eps * dk1, lk2 - eps * dk2, 1.0)) / (2 * eps)
+        ad = float((g1 if which == 0 else g2) @ d)
+        worst = max(worst, abs(ad - fd) / max(abs(fd), 1e-30))
+        print("direction %d (%s): adjoint %.10e fd %.10e" % (j, "k1" if which == 0 else "k2", ad, fd), flush=True)
+    fdb = (J(lk1, lk2, 1.0 + 1e-5) - J(lk1, lk2, 1.0 - 1e-5)) / 2e-5
+    print("beta: adjoint %.10e fd %.10e" % (gb[0], fdb), flush=True)
+    assert worst <= 1e-5
+    assert abs(gb[0] - fdb) <= 1e-5 * abs(fdb)
