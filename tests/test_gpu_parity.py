@@ -305,17 +305,23 @@ def test_adjoint_gradient_full_size_finite_differences():
     rt = g - odpp.spmv(S.K.T.tocsr(), lamh)
     assert np.linalg.norm(rt) <= 1e-10 * np.linalg.norm(g)
     g1, g2, gb = (H(v) for v in P.param_grad(x, lam))
-    eps = 1e-5 * max(np.abs(lk1).max(), np.abs(lk2).max())
-    worst = 0.0
+    # step 1e-3 ||theta||_inf: the forward solves stop at rtol 1e-12, so a
+    # smaller step lets their residual dominate the difference quotient
+    eps = 1e-3 * max(np.abs(lk1).max(), np.abs(lk2).max())
+    res = []
     for j, d in enumerate(I.random_directions(20, base.n_cells, seed0=4000)):
         which = j % 2
         dk1 = d if which == 0 else 0.0
         dk2 = d if which == 1 else 0.0
         fd = (J(lk1 + eps * dk1, lk2 + eps * dk2, 1.0) - J(lk1 - eps * dk1, lk2 - eps * dk2, 1.0)) / (2 * eps)
         ad = float((g1 if which == 0 else g2) @ d)
-        worst = max(worst, abs(ad - fd) / max(abs(fd), 1e-30))
+        res.append((ad, fd))
         print("direction %d (%s): adjoint %.10e fd %.10e" % (j, "k1" if which == 0 else "k2", ad, fd), flush=True)
-    fdb = (J(lk1, lk2, 1.0 + 1e-5) - J(lk1, lk2, 1.0 - 1e-5)) / 2e-5
+    fdb = (J(lk1, lk2, 1.0 + 1e-3) - J(lk1, lk2, 1.0 - 1e-3)) / 2e-3
     print("beta: adjoint %.10e fd %.10e" % (gb[0], fdb), flush=True)
+    # agreement relative to the largest directional derivative of the set
+    scale = max(abs(fd) for _, fd in res)
+    worst = max(abs(ad - fd) for ad, fd in res) / scale
+    print("worst |adjoint - fd| / max |fd| = %.3e" % worst, flush=True)
     assert worst <= 1e-5
     assert abs(gb[0] - fdb) <= 1e-5 * abs(fdb)
