@@ -30,6 +30,8 @@ WORKLOADS = {
                    "per-hex k1, k2 (Gaussian random field, correlation length 0.1, seeds 1001/1002)",
     "c5_3d48_grf": "3D unit cube 48^3 x 6 tetrahedra (49^3 nodes) = 941,192 DOF; log-normal k1, k2",
     "c1_2d16": "2D unit square 16^2 x 2 triangles (289 nodes) = 1,734 DOF; k1=1, k2=0.1, beta=mu=1",
+    "c4_batch64": "64 independent 2D unit-square instances, n ~ U{32..256} cells per side (seed 2024), "
+                  "beta ~ logU[0.1,10], k2/k1 ~ logU[1e-3,1]; one batched launch per phase",
 }
 PRECISION = {0: "f64", 1: "f64+f32 refinement", 2: "f64 Krylov, f32 preconditioner"}
 
@@ -91,6 +93,55 @@ def cpu_baseline(prob, gpu_iters, max_iters):
     }
 
 
+def bench_batch(args, torch, I, dpp):
+    """64 uneven 2D instances: batched solve vs the same instances solved one
+    after another with the single-problem path."""
+    probs = I.batch_configs(64, seed=2024)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B = dpp.assemble_batch(probs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    opts = dict(rtol=1e-8, precision=args.precision, use_graph=1)
+    for _ in range(args.warmup):
+        B.solve(**opts)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for _ in range(args.steps):
+        x, st = B.solve(**opts)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - tb) * 1e3 / args.steps
+    # reference: the single-problem FP64 path, instance by instance
+    singles = []
+    for pr in probs:
+        P = dpp.assemble_problem(pr)
+        singles.append((P, P.setup_precond()))
+    for P, pc in singles[:4]:
+        P.solve(pc, rtol=1e-8)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for P, pc in singles:
+        P.solve(pc, rtol=1e-8)
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - ts) * 1e3
+    line = {
+        "metric": METRIC, "value": B.n_dof / (ms / 1e3), "unit": "DOF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64/f32",
+        "data": "synthetic",
+        "config": {"workload": "c4_batch64", "description": WORKLOADS["c4_batch64"],
+                   "n_dof": B.n_dof, "instances": len(probs), "rtol": 1e-8,
+                   "precision": PRECISION[args.precision], "graph": True},
+        "iters_max": max(s.iters for s in st), "iters_min": min(s.iters for s in st),
+        "all_converged": all(s.converged for s in st),
+        "setup_ms": (t1 - t0) * 1e3, "lanes_per_level": B.lanes(),
+        "sequential_single_fp64_ms": seq_ms,
+        "speedup_vs_sequential": seq_ms / ms,
+        "roofline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +173,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.config == "c4_batch64":
+        return bench_batch(args, torch, I, dpp)
     prob = I.make_config(args.config)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -52,6 +52,7 @@ typedef enum {
 
 typedef struct dpp_problem_s *dpp_problem;
 typedef struct dpp_precond_s *dpp_precond;
+typedef struct dpp_batch_s *dpp_batch;
 
 /* Structured box: dim 2 or 3, n[a] >= 1 cells per axis, L[a] > 0 extent. */
 typedef struct {
@@ -218,6 +219,31 @@ dpp_status dpp_param_grad(dpp_problem prob, const double *x, const double *lambd
  * count, total milliseconds and total algorithmic bytes of one family. */
 dpp_status dpp_profile_enable(int on);
 dpp_status dpp_profile_read(int family, int64_t *launches, double *total_ms, double *total_bytes);
+
+/* ---- Batched solves: many independent instances, one launch per phase ----
+ * dpp_assemble_batch assembles nb instances (boxes[i], params[i]; uneven
+ * sizes allowed, all of one dimension), builds each one's fieldsplit
+ * preconditioner (opts may be NULL) and autotunes the lanes per stencil row of
+ * every multigrid level index over the whole batch.  The solution vector is
+ * the concatenation of the instances' vectors (each in the single-problem
+ * layout) at offsets given by dpp_batch_sizes.  All kernels of a solve phase
+ * (operator products, Schur steps, every V-cycle level, the coarse solves,
+ * the Arnoldi passes) are single launches over all instances; converged
+ * instances are masked out.  opts->use_graph replays each Arnoldi step from a
+ * captured hipGraph. */
+dpp_status dpp_assemble_batch(int nb, const dpp_box *boxes, const dpp_params *params,
+                              const dpp_solve_opts *opts, void *stream, dpp_batch *out);
+/* total_dof (host, may be NULL); offsets: host [nb+1] or NULL. */
+dpp_status dpp_batch_sizes(dpp_batch b, int64_t *total_dof, int64_t *offsets);
+/* Lanes per row chosen by the autotuner per multigrid level index (host, [16]). */
+dpp_status dpp_batch_lanes(dpp_batch b, int *n_levels, int *lanes);
+/* Solve every instance: x_concat (device [total_dof]) in = initial guess,
+ * out = solution; stats: host array [nb] or NULL.  precision 0 or 2 (the FP32
+ * preconditioner); returns DPP_ERR_NOT_CONVERGED when an instance stopped at
+ * maxiter. */
+dpp_status dpp_solve_batch(dpp_batch b, const dpp_solve_opts *opts, double *x_concat,
+                           dpp_solve_stats *stats, void *stream);
+void dpp_destroy_batch(dpp_batch b);
 
 void dpp_destroy_problem(dpp_problem prob);
 void dpp_destroy_precond(dpp_precond pc);

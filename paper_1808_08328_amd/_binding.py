@@ -76,6 +76,12 @@ def lib():
         "dpp_param_grad": (C.c_int, [P, P, P, P, P, P, P]),
         "dpp_profile_enable": (C.c_int, [C.c_int]),
         "dpp_profile_read": (C.c_int, [C.c_int, I64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "dpp_assemble_batch": (C.c_int, [C.c_int, C.POINTER(_Box), C.POINTER(_Params),
+                                         C.POINTER(_Opts), P, C.POINTER(P)]),
+        "dpp_batch_sizes": (C.c_int, [P, I64, I64]),
+        "dpp_batch_lanes": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "dpp_solve_batch": (C.c_int, [P, C.POINTER(_Opts), P, C.POINTER(SolveStats), P]),
+        "dpp_destroy_batch": (None, [P]),
         "dpp_destroy_problem": (None, [P]),
         "dpp_destroy_precond": (None, [P]),
     }
@@ -281,6 +287,68 @@ def assemble_problem(prob, device="cuda", stream=None):
     return assemble(prob.dim, prob.n, dv(prob.k1), dv(prob.k2), dv(prob.p0_1), dv(prob.p0_2),
                     beta=float(beta), mu=prob.mu, L=prob.L, body=body, beta_cells=beta_cells,
                     stream=stream)
+
+
+class Batch:
+    """Many independent instances solved together (handle over dpp_batch)."""
+
+    def __init__(self, handle, nb, dim, keep):
+        self.handle, self.nb, self.dim, self._keep = handle, nb, dim, keep
+        tot = C.c_int64()
+        offs = (C.c_int64 * (nb + 1))()
+        _check(lib().dpp_batch_sizes(handle, C.byref(tot), offs))
+        self.n_dof = tot.value
+        self.offsets = [offs[i] for i in range(nb + 1)]
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.dpp_destroy_batch(self.handle)
+            self.handle = None
+
+    def lanes(self):
+        nl = C.c_int()
+        ln = (C.c_int * 16)()
+        _check(lib().dpp_batch_lanes(self.handle, C.byref(nl), ln))
+        return [ln[i] for i in range(nl.value)]
+
+    def solve(self, x0=None, stream=None, allow_unconverged=False, **opts):
+        o = default_opts(**opts)
+        x = torch.zeros(self.n_dof, dtype=torch.float64, device="cuda") if x0 is None else x0.clone()
+        st = (SolveStats * self.nb)()
+        _check(lib().dpp_solve_batch(self.handle, C.byref(o), _ptr(x), st, _stream(stream)),
+               allow=(4,) if allow_unconverged else ())
+        return x, [st[i] for i in range(self.nb)]
+
+    def split(self, x):
+        return [x[self.offsets[i]:self.offsets[i + 1]] for i in range(self.nb)]
+
+
+def assemble_batch(problems, stream=None, **opts):
+    """dpp_assemble_batch over a list of ``dpp_inputs.Problem`` (one dimension)."""
+    lib()
+    nb = len(problems)
+    boxes = (_Box * nb)()
+    params = (_Params * nb)()
+    keep = []
+    dv = lambda a: torch.as_tensor(a, dtype=torch.float64).contiguous().to("cuda")
+    for i, pr in enumerate(problems):
+        boxes[i].dim = pr.dim
+        for a in range(3):
+            boxes[i].n[a] = int(pr.n[a]) if a < pr.dim else 0
+            boxes[i].L[a] = float(pr.L[a]) if a < pr.dim else 0.0
+        arrs = [dv(pr.k1), dv(pr.k2), dv(pr.p0_1), dv(pr.p0_2)]
+        keep.append(arrs)
+        p = params[i]
+        p.mu = float(pr.mu)
+        p.k1, p.k2, p.p0_1, p.p0_2 = (_ptr(t) for t in arrs)
+        p.beta = float(pr.beta)
+        p.beta_cells = None
+        p.body = None
+        p.facet_type = None
+    o = default_opts(**opts)
+    h = C.c_void_p()
+    _check(lib().dpp_assemble_batch(nb, boxes, params, C.byref(o), _stream(stream), C.byref(h)))
+    return Batch(h, nb, problems[0].dim, keep)
 
 
 class DppSolve(torch.autograd.Function):

@@ -8,8 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdpp.so")
-SOURCES = ["assemble.hip", "ops.hip", "mg.hip", "krylov.hip", "adjoint.hip", "profile.hip",
-           "abi.hip"]
+SOURCES = ["assemble.hip", "ops.hip", "mg.hip", "krylov.hip", "adjoint.hip", "batch.hip",
+           "profile.hip", "abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Wno-unused-variable",

@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "objects.h"
+#include "batch.h"
 
 namespace {
 
@@ -324,6 +325,90 @@ dpp_status dpp_param_grad(dpp_problem P, const double *x, const double *lambda, 
     dpp::param_grad(P, x, lambda, g_logk1, g_logk2, g_beta, S(stream));
   });
 }
+
+dpp_status dpp_assemble_batch(int nb, const dpp_box *boxes, const dpp_params *params,
+                              const dpp_solve_opts *opts, void *stream, dpp_batch *out) {
+  return guard([&] {
+    DPP_CHECK(out && boxes && params, DPP_ERR_ARG, "null argument");
+    *out = nullptr;
+    DPP_CHECK(nb >= 1 && nb <= 4096, DPP_ERR_ARG, "nb must be in 1..4096");
+    auto *B = new dpp_batch_s();
+    try {
+      B->nb = nb;
+      B->dim = boxes[0].dim;
+      if (opts)
+        B->opts = *opts;
+      else
+        dpp_default_opts(&B->opts);
+      check_opts(B->opts);
+      set_device_of(params[0].k1);
+      for (int i = 0; i < nb; ++i) {
+        DPP_CHECK(boxes[i].dim == B->dim, DPP_ERR_ARG, "all instances of a batch share one dimension");
+        auto *P = new dpp_problem_s();
+        B->P.push_back(P);
+        dpp::assemble_problem(P, &boxes[i], &params[i], S(stream));
+        auto *pc = new dpp_precond_s();
+        B->pc.push_back(pc);
+        pc->prob = P;
+        pc->opts = B->opts;
+        dpp::precond_setup(pc, S(stream));
+      }
+      dpp::batch_setup(B, S(stream));
+    } catch (...) {
+      delete B;
+      throw;
+    }
+    *out = B;
+  });
+}
+
+dpp_status dpp_batch_sizes(dpp_batch B, int64_t *total_dof, int64_t *offsets) {
+  return guard([&] {
+    DPP_CHECK(B, DPP_ERR_ARG, "null batch");
+    if (total_dof) *total_dof = B->ntot;
+    if (offsets)
+      for (int i = 0; i <= B->nb; ++i) offsets[i] = B->doff[i];
+  });
+}
+
+dpp_status dpp_batch_lanes(dpp_batch B, int *n_levels, int *lanes) {
+  return guard([&] {
+    DPP_CHECK(B, DPP_ERR_ARG, "null batch");
+    if (n_levels) *n_levels = B->nlev;
+    if (lanes)
+      for (int l = 0; l < B->nlev && l < 16; ++l) lanes[l] = B->lpr[l];
+  });
+}
+
+dpp_status dpp_solve_batch(dpp_batch B, const dpp_solve_opts *opts, double *x, dpp_solve_stats *stats,
+                           void *stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<dpp_solve_stats> st;
+  dpp_status status = guard([&] {
+    DPP_CHECK(B && x, DPP_ERR_ARG, "null argument");
+    dpp_solve_opts o = opts ? *opts : B->opts;
+    o.coarse_max = B->opts.coarse_max;
+    o.cheb_lo_frac = B->opts.cheb_lo_frac;
+    o.cheb_hi_factor = B->opts.cheb_hi_factor;
+    o.power_iters = B->opts.power_iters;
+    o.cheb_degree = B->opts.cheb_degree;
+    check_opts(o);
+    st.resize(B->nb);
+    dpp::batch_solve(B, o, x, st.data(), S(stream));
+    for (auto &s : st)
+      if (!s.converged) throw dpp::Error(DPP_ERR_NOT_CONVERGED, "an instance reached maxiter");
+  });
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats && B)
+    for (int i = 0; i < (int)st.size(); ++i) {
+      stats[i] = st[i];
+      stats[i].ms_solve = ms;
+    }
+  return status;
+}
+
+void dpp_destroy_batch(dpp_batch B) { delete B; }
 
 void dpp_destroy_problem(dpp_problem P) { delete P; }
 void dpp_destroy_precond(dpp_precond pc) { delete pc; }

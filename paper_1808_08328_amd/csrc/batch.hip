@@ -1,0 +1,877 @@
+// Batched solve of many independent DPP instances (uneven boxes): one launch
+// per phase covers every instance.
+//
+// Each launch walks a table of per-instance descriptors; a workgroup finds
+// its instance by binary search on the descriptors' first-block indices.
+// The V-cycle is level-synchronous: going down, level l of every instance
+// deeper than l+1 is smoothed in one launch; the coarsest levels (which sit at
+// different depths) are solved in one launch; going up mirrors the descent.
+// The Krylov method is the same flexible GMRES(m) with CGS2 as the single
+// solve, run in lockstep with per-instance Hessenberg systems; an instance
+// that has converged is masked out of every later launch.  One Arnoldi step
+// can be captured in a hipGraph per step index and replayed.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+
+#include "objects.h"
+#include "profile.h"
+#include "stencil.h"
+#include "batch.h"
+
+namespace dpp {
+
+template <typename Desc>
+__device__ inline int find_desc(const Desc *__restrict__ d, int nd, int bid, int Desc::*first) {
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].*first <= bid)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline double bwave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+namespace {
+
+// ---------------------------------------------------------------- K level --
+template <int D, typename TV>
+__global__ __launch_bounds__(256) void kb_spmv_K(const KDesc *__restrict__ kd, int nd,
+                                                 const int *__restrict__ active,
+                                                 const double *__restrict__ x,
+                                                 const double *__restrict__ bsub,
+                                                 double *__restrict__ y) {
+  const int di = find_desc(kd, nd, (int)blockIdx.x, &KDesc::blk0);
+  const KDesc &k = kd[di];
+  if (!active[k.inst]) return;
+  const long a = (long)(blockIdx.x - k.blk0) * blockDim.x + threadIdx.x;
+  const GridDev g = k.g;
+  if (a >= g.N) return;
+  double au[2][D], ap[2];
+  spmv_K_node<D, TV>(g, (const TV *)k.kv, x + k.off, a, au, ap);
+  const long N = g.N;
+  for (int q = 0; q < 2; ++q) {
+    const long ou = k.off + off_u(D, N, q), op = k.off + off_p(D, N, q);
+    for (int c = 0; c < D; ++c) {
+      const long r = ou + D * a + c;
+      y[r] = bsub ? bsub[r] - au[q][c] : au[q][c];
+    }
+    y[op + a] = bsub ? bsub[op + a] - ap[q] : ap[q];
+  }
+}
+
+template <int D, typename TV, typename TX>
+__global__ __launch_bounds__(256) void kb_schur_rhs(const KDesc *__restrict__ kd, int nd,
+                                                    const int *__restrict__ active,
+                                                    const double *__restrict__ r) {
+  const int di = find_desc(kd, nd, (int)blockIdx.x, &KDesc::blk0);
+  const KDesc &k = kd[di];
+  if (!active[k.inst]) return;
+  const int q = blockIdx.y;
+  const long b = (long)(blockIdx.x - k.blk0) * blockDim.x + threadIdx.x;
+  if (b >= k.g.N) return;
+  ((TX *)k.rhat)[q * k.g.N + b] = (TX)schur_rhs_node<D, TV>(k.g, (const TV *)k.kv, k.dinv, r + k.off, q, b);
+}
+
+template <int D, typename TV, typename TX>
+__global__ __launch_bounds__(256) void kb_schur_vel(const KDesc *__restrict__ kd, int nd,
+                                                    const int *__restrict__ active,
+                                                    const double *__restrict__ r,
+                                                    double *__restrict__ z) {
+  const int di = find_desc(kd, nd, (int)blockIdx.x, &KDesc::blk0);
+  const KDesc &k = kd[di];
+  if (!active[k.inst]) return;
+  const int q = blockIdx.y;
+  const long a = (long)(blockIdx.x - k.blk0) * blockDim.x + threadIdx.x;
+  const long N = k.g.N;
+  if (a >= N) return;
+  double out[D];
+  const TX *zp = (const TX *)k.zp;
+  schur_vel_node<D, TV, TX>(k.g, (const TV *)k.kv, k.dinv, r + k.off, zp, q, a, out);
+  const long ou = k.off + off_u(D, N, q);
+  for (int c = 0; c < D; ++c) z[ou + D * a + c] = out[c];
+  z[k.off + off_p(D, N, q) + a] = (double)zp[q * N + a];
+}
+
+// ---------------------------------------------------------- level kernels --
+template <typename TX>
+__device__ inline TX *lbuf(const LDesc &l, int which) {
+  return (TX *)(which == 0 ? l.xa : which == 1 ? l.xb : l.e);
+}
+
+template <typename TV, typename TX>
+__global__ __launch_bounds__(256) void kb_cheb_first(const LDesc *__restrict__ ld, int nd,
+                                                     const int *__restrict__ active, int out_w) {
+  const int di = find_desc(ld, nd, (int)blockIdx.x, &LDesc::blk0);
+  const LDesc &l = ld[di];
+  if (!active[l.inst]) return;
+  const int q = blockIdx.y;
+  const long a = (long)(blockIdx.x - l.blk0) * blockDim.x + threadIdx.x;
+  if (a >= l.g.N) return;
+  const size_t ia = (size_t)q * l.g.N + a;
+  const double v = l.c2[0][q] * (double)((const TV *)l.dinv)[ia] * (double)((const TX *)l.b)[ia];
+  ((TX *)l.d)[ia] = (TX)v;
+  lbuf<TX>(l, out_w)[ia] = (TX)v;
+}
+
+// Chebyshev step `step` (>= 0, nonzero guess): in -> out, d updated.  With
+// resid_only, writes r = b - A in instead.
+template <int D, typename TV, typename TX, int LPR>
+__global__ __launch_bounds__(256, 4) void kb_cheb(const LDesc *__restrict__ ld, int nd,
+                                                  const int *__restrict__ active, int step,
+                                                  int in_w, int out_w, int resid_only) {
+  const int di = find_desc(ld, nd, (int)blockIdx.x, &LDesc::blk0);
+  const LDesc &l = ld[di];
+  if (!active[l.inst]) return;
+  const int q = blockIdx.y;
+  const long gid = (long)(blockIdx.x - l.blk0) * blockDim.x + threadIdx.x;
+  const long a = gid / LPR;
+  const int sub = (int)(gid % LPR);
+  const GridDev g = l.g;
+  if (a >= g.N) return;
+  constexpr int NA = stored_offsets<D, true>();
+  const TX *xin = lbuf<TX>(l, in_w);
+  const double ax = row_product<D, TV, TX, LPR, true>(g, (const TV *)l.A + (size_t)q * NA * g.ld,
+                                                      xin + (size_t)q * g.N, a, 0, 0, 0, sub);
+  if (sub != 0) return;
+  const size_t ia = (size_t)q * g.N + a;
+  const double bb = (double)((const TX *)l.b)[ia];
+  if (resid_only) {
+    ((TX *)l.r)[ia] = (TX)(bb - ax);
+    return;
+  }
+  const double r = (double)((const TV *)l.dinv)[ia] * (bb - ax);
+  const double c1 = l.c1[step][q], c2 = l.c2[step][q];
+  const double dn = (c1 != 0.0 ? c1 * (double)((TX *)l.d)[ia] : 0.0) + c2 * r;
+  ((TX *)l.d)[ia] = (TX)dn;
+  lbuf<TX>(l, out_w)[ia] = (TX)((double)xin[ia] + dn);
+}
+
+template <int D, typename TX>
+__global__ __launch_bounds__(256) void kb_restrict(const LDesc *__restrict__ ld, int nd,
+                                                   const int *__restrict__ active) {
+  const int di = find_desc(ld, nd, (int)blockIdx.x, &LDesc::cblk0);
+  const LDesc &l = ld[di];
+  if (!active[l.inst]) return;
+  const int q = blockIdx.y;
+  const long C = (long)(blockIdx.x - l.cblk0) * blockDim.x + threadIdx.x;
+  if (C >= l.gc.N) return;
+  ((TX *)l.bc)[(size_t)q * l.gc.N + C] =
+      (TX)restrict_node<D, TX>(l.g, l.gc, (const TX *)l.r + (size_t)q * l.g.N, C);
+}
+
+template <int D, typename TX>
+__global__ __launch_bounds__(256) void kb_prolong(const LDesc *__restrict__ ld, int nd,
+                                                  const int *__restrict__ active, int x_w) {
+  const int di = find_desc(ld, nd, (int)blockIdx.x, &LDesc::blk0);
+  const LDesc &l = ld[di];
+  if (!active[l.inst]) return;
+  const int q = blockIdx.y;
+  // node blocks were sized for LPR lanes; one thread per node here
+  const long f = (long)(blockIdx.x - l.blk0) * blockDim.x + threadIdx.x;
+  if (f >= l.g.N) return;
+  const double v = prolong_node<D, TX>(l.g, l.gc, (const TX *)l.ec + (size_t)q * l.gc.N, f);
+  TX *x = lbuf<TX>(l, x_w);
+  x[(size_t)q * l.g.N + f] = (TX)((double)x[(size_t)q * l.g.N + f] + v);
+}
+
+template <typename TX>
+__global__ __launch_bounds__(256) void kb_coarse(const CDesc *__restrict__ cd, int nd,
+                                                 const int *__restrict__ active) {
+  const int di = find_desc(cd, nd, (int)blockIdx.x, &CDesc::blk0);
+  const CDesc &c = cd[di];
+  if (!active[c.inst]) return;
+  const int q = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int row = (blockIdx.x - c.blk0) * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (row >= c.n) return;
+  const double *Mr = c.Cinv + (size_t)q * c.n * c.n + (size_t)row * c.n;
+  const TX *bq = (const TX *)c.b + (size_t)q * c.n;
+  double s = 0.0;
+  for (int k = lane; k < c.n; k += 64) s += Mr[k] * (double)bq[k];
+  s = bwave_sum(s);
+  if (lane == 0) ((TX *)c.x)[(size_t)q * c.n + row] = (TX)s;
+}
+
+// ---------------------------------------------------------------- Krylov --
+__device__ inline void bblock_store(const double *acc, int nk, double *part, int tb,
+                                    double extra = 0.0, bool with_extra = false) {
+  __shared__ double sh[BBS / 64][BMAXK + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < BMAXK; ++k) {
+    if (k < nk) {
+      double v = bwave_sum(acc[k]);
+      if (lane == 0) sh[wv][k] = v;
+    }
+  }
+  if (with_extra) {
+    double v = bwave_sum(extra);
+    if (lane == 0) sh[wv][BMAXK] = v;
+  }
+  __syncthreads();
+  const int tot = nk + (with_extra ? 1 : 0);
+  if ((int)threadIdx.x < tot) {
+    const int slot = ((int)threadIdx.x == nk) ? BMAXK : (int)threadIdx.x;
+    double s = 0.0;
+    for (int w = 0; w < BBS / 64; ++w) s += sh[w][slot];
+    part[(size_t)threadIdx.x * tb + blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(BBS) void kb_mdot(const VDesc *__restrict__ vd, int nd,
+                                               const int *__restrict__ active,
+                                               const double *__restrict__ V, long ldv, int nk,
+                                               const double *__restrict__ w, double *__restrict__ part) {
+  const int di = find_desc(vd, nd, (int)blockIdx.x, &VDesc::blk0);
+  const VDesc &v = vd[di];
+  if (!active[v.inst]) return;
+  double acc[BMAXK];
+#pragma unroll
+  for (int k = 0; k < BMAXK; ++k) acc[k] = 0.0;
+  for (long i = (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x; i < v.n; i += (long)v.nblk * BBS) {
+    const double wi = w[v.off + i];
+#pragma unroll
+    for (int k = 0; k < BMAXK; ++k)
+      if (k < nk) acc[k] += V[(size_t)k * ldv + v.off + i] * wi;
+  }
+  bblock_store(acc, nk, part, gridDim.x);
+}
+
+__global__ __launch_bounds__(BBS) void kb_axpy_mdot(const VDesc *__restrict__ vd, int nd,
+                                                    const int *__restrict__ active,
+                                                    const double *__restrict__ V, long ldv, int nk,
+                                                    const double *__restrict__ hb, int hslot,
+                                                    double *__restrict__ w, double *__restrict__ part) {
+  const int di = find_desc(vd, nd, (int)blockIdx.x, &VDesc::blk0);
+  const VDesc &v = vd[di];
+  if (!active[v.inst]) return;
+  double acc[BMAXK], hk[BMAXK], nrm = 0.0;
+#pragma unroll
+  for (int k = 0; k < BMAXK; ++k) {
+    acc[k] = 0.0;
+    hk[k] = (k < nk) ? hb[(size_t)v.inst * HS + hslot + k] : 0.0;
+  }
+  for (long i = (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x; i < v.n; i += (long)v.nblk * BBS) {
+    double vv[BMAXK];
+    double s = w[v.off + i];
+#pragma unroll
+    for (int k = 0; k < BMAXK; ++k) {
+      vv[k] = (k < nk) ? V[(size_t)k * ldv + v.off + i] : 0.0;
+      s -= hk[k] * vv[k];
+    }
+    w[v.off + i] = s;
+#pragma unroll
+    for (int k = 0; k < BMAXK; ++k) acc[k] += vv[k] * s;
+    nrm += s * s;
+  }
+  bblock_store(acc, nk, part, gridDim.x, nrm, true);
+}
+
+__global__ __launch_bounds__(BBS) void kb_axpy_norm(const VDesc *__restrict__ vd, int nd,
+                                                    const int *__restrict__ active,
+                                                    const double *__restrict__ V, long ldv, int nk,
+                                                    const double *__restrict__ hb, int hslot,
+                                                    const double *__restrict__ w,
+                                                    double *__restrict__ vout, double *__restrict__ part) {
+  const int di = find_desc(vd, nd, (int)blockIdx.x, &VDesc::blk0);
+  const VDesc &v = vd[di];
+  if (!active[v.inst]) return;
+  double hk[BMAXK], nrm = 0.0;
+#pragma unroll
+  for (int k = 0; k < BMAXK; ++k) hk[k] = (k < nk) ? hb[(size_t)v.inst * HS + hslot + k] : 0.0;
+  for (long i = (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x; i < v.n; i += (long)v.nblk * BBS) {
+    double s = w[v.off + i];
+#pragma unroll
+    for (int k = 0; k < BMAXK; ++k)
+      if (k < nk) s -= hk[k] * V[(size_t)k * ldv + v.off + i];
+    vout[v.off + i] = s;
+    nrm += s * s;
+  }
+  bblock_store(hk, 0, part, gridDim.x, nrm, true);
+}
+
+// hb[inst*HS + hslot + k] = sum of instance inst's partials of slot k
+__global__ __launch_bounds__(BBS) void kb_finish(const VDesc *__restrict__ vd,
+                                                 const int *__restrict__ active,
+                                                 const double *__restrict__ part, int tb,
+                                                 double *__restrict__ hb, int hslot) {
+  const int k = blockIdx.x, di = blockIdx.y;
+  const VDesc &v = vd[di];
+  if (!active[v.inst]) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < v.nblk; b += BBS) s += part[(size_t)k * tb + v.blk0 + b];
+  s = bwave_sum(s);
+  __shared__ double sh[BBS / 64];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < BBS / 64; ++w) t += sh[w];
+    hb[(size_t)v.inst * HS + hslot + k] = t;
+  }
+}
+
+// v <- v / sqrt(hb[inst*HS + slot]) (or times fac[inst] when fac != null)
+__global__ __launch_bounds__(BBS) void kb_scale(const VDesc *__restrict__ vd, int nd,
+                                                const int *__restrict__ active, double *__restrict__ v,
+                                                const double *__restrict__ hb, int slot,
+                                                const double *__restrict__ fac) {
+  const int di = find_desc(vd, nd, (int)blockIdx.x, &VDesc::blk0);
+  const VDesc &d = vd[di];
+  if (!active[d.inst]) return;
+  double a;
+  if (fac) {
+    a = fac[d.inst];
+  } else {
+    const double s2 = hb[(size_t)d.inst * HS + slot];
+    if (!(s2 > 0.0)) return;
+    a = 1.0 / sqrt(s2);
+  }
+  for (long i = (long)(blockIdx.x - d.blk0) * BBS + threadIdx.x; i < d.n; i += (long)d.nblk * BBS)
+    v[d.off + i] *= a;
+}
+
+// x_i <- x_i + Z_i y_i (y per instance, nk_i columns; nk_i = 0 skips)
+__global__ __launch_bounds__(BBS) void kb_update(const VDesc *__restrict__ vd, int nd,
+                                                 const double *__restrict__ Z, long ldz,
+                                                 const double *__restrict__ y,
+                                                 const int *__restrict__ nks, double *__restrict__ x) {
+  const int di = find_desc(vd, nd, (int)blockIdx.x, &VDesc::blk0);
+  const VDesc &d = vd[di];
+  const int nk = nks[d.inst];
+  if (nk == 0) return;
+  double yk[BMAXK];
+#pragma unroll
+  for (int k = 0; k < BMAXK; ++k) yk[k] = (k < nk) ? y[(size_t)d.inst * BMAXK + k] : 0.0;
+  for (long i = (long)(blockIdx.x - d.blk0) * BBS + threadIdx.x; i < d.n; i += (long)d.nblk * BBS) {
+    double s = x[d.off + i];
+#pragma unroll
+    for (int k = 0; k < BMAXK; ++k)
+      if (k < nk) s += yk[k] * Z[(size_t)k * ldz + d.off + i];
+    x[d.off + i] = s;
+  }
+}
+
+}  // namespace
+
+}  // namespace dpp
+
+namespace dpp {
+
+namespace {
+
+void cheb_coefs_l(const Level &L, int deg, LDesc &d) {
+  for (int q = 0; q < 2; ++q) {
+    const double theta = 0.5 * (L.hi[q] + L.lo[q]), delta = 0.5 * (L.hi[q] - L.lo[q]);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    d.c1[0][q] = 0.0;
+    d.c2[0][q] = 1.0 / theta;
+    for (int k = 1; k < deg; ++k) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      d.c1[k][q] = rn * rho;
+      d.c2[k][q] = 2.0 * rn / delta;
+      rho = rn;
+    }
+  }
+}
+
+void build_level_tables(dpp_batch B, int l, int lanes, bool fp32, DTable<LDesc> &out) {
+  std::vector<LDesc> v;
+  int blk = 0, cblk = 0;
+  std::vector<LDesc> tmp;
+  for (int i = 0; i < B->nb; ++i) {
+    dpp_precond pc = B->pc[i];
+    if ((int)pc->lv.size() - 1 <= l) continue;  // level l is this instance's coarsest (or absent)
+    Level &L = *pc->lv[l];
+    Level &C = *pc->lv[l + 1];
+    LDesc d{};
+    d.g = dev(L.g);
+    d.gc = dev(C.g);
+    d.inst = i;
+    d.blk0 = blk;
+    d.nblk = blocks_for(L.g.N * lanes, 256);
+    blk += d.nblk;
+    d.cblk0 = cblk;
+    d.cnblk = blocks_for(C.g.N, 256);
+    cblk += d.cnblk;
+    if (fp32) {
+      d.A = L.Ah32.ptr;
+      d.dinv = L.dinv32.ptr;
+      d.b = L.b32.ptr; d.xa = L.xa32.ptr; d.xb = L.xb32.ptr; d.d = L.d32.ptr; d.r = L.r32.ptr; d.e = L.e32.ptr;
+      d.bc = C.b32.ptr; d.ec = C.e32.ptr;
+    } else {
+      d.A = L.Ah.ptr;
+      d.dinv = L.dinv.ptr;
+      d.b = L.b.ptr; d.xa = L.xa.ptr; d.xb = L.xb.ptr; d.d = L.d.ptr; d.r = L.r.ptr; d.e = L.e.ptr;
+      d.bc = C.b.ptr; d.ec = C.e.ptr;
+    }
+    cheb_coefs_l(L, B->opts.cheb_degree, d);
+    v.push_back(d);
+  }
+  // restriction blocks are looked up through cblk0: keep both orders valid
+  out.upload(v, blk);
+  (void)cblk;
+}
+
+int level_cblocks(dpp_batch B, int l) {
+  int c = 0;
+  for (int i = 0; i < B->nb; ++i) {
+    dpp_precond pc = B->pc[i];
+    if ((int)pc->lv.size() - 1 <= l) continue;
+    c += blocks_for(pc->lv[l + 1]->g.N, 256);
+  }
+  return c;
+}
+
+template <int D, typename TV, typename TX>
+void launch_cheb_b(dpp_batch B, int l, const DTable<LDesc> &t, hipStream_t s, int step, int in_w,
+                   int out_w, int resid_only) {
+  if (!t.count) return;
+  const dim3 grid(t.blocks, 2);
+  const int *act = B->active.as<int>();
+  switch (B->lpr[l]) {
+    case 1: kb_cheb<D, TV, TX, 1><<<grid, 256, 0, s>>>(t.get(), t.count, act, step, in_w, out_w, resid_only); break;
+    case 2: kb_cheb<D, TV, TX, 2><<<grid, 256, 0, s>>>(t.get(), t.count, act, step, in_w, out_w, resid_only); break;
+    case 4: kb_cheb<D, TV, TX, 4><<<grid, 256, 0, s>>>(t.get(), t.count, act, step, in_w, out_w, resid_only); break;
+    default: kb_cheb<D, TV, TX, 8><<<grid, 256, 0, s>>>(t.get(), t.count, act, step, in_w, out_w, resid_only); break;
+  }
+}
+
+// Level-synchronous V-cycle over every instance (finest-level input and output
+// are each instance's level-0 b and e buffers).
+template <int D, typename TV, typename TX>
+void vcycle_b(dpp_batch B, bool fp32, hipStream_t s) {
+  const int deg = B->opts.cheb_degree;
+  const int *act = B->active.as<int>();
+  auto &tabs = fp32 ? B->ld32 : B->ld;
+  std::vector<int> cur_after_pre(B->nlev, 0);
+  for (int l = 0; l < B->nlev; ++l) {
+    const DTable<LDesc> &t = tabs[l];
+    if (!t.count) continue;
+    const dim3 g1(t.blocks, 2);
+    kb_cheb_first<TV, TX><<<g1, 256, 0, s>>>(t.get(), t.count, act, 0);
+    int cur = 0, oth = 1;
+    for (int k = 1; k < deg; ++k) {
+      launch_cheb_b<D, TV, TX>(B, l, t, s, k, cur, oth, 0);
+      std::swap(cur, oth);
+    }
+    cur_after_pre[l] = cur;
+    launch_cheb_b<D, TV, TX>(B, l, t, s, 0, cur, 0, 1);  // r = b - A x
+    const int cb = level_cblocks(B, l);
+    // restriction: grid over coarse-node blocks, descriptors found through cblk0
+    kb_restrict<D, TX><<<dim3(cb, 2), 256, 0, s>>>(t.get(), t.count, act);
+  }
+  const DTable<CDesc> &c = fp32 ? B->cd32 : B->cd;
+  kb_coarse<TX><<<dim3(c.blocks, 2), 256, 0, s>>>(c.get(), c.count, act);
+  for (int l = B->nlev - 1; l >= 0; --l) {
+    const DTable<LDesc> &t = tabs[l];
+    if (!t.count) continue;
+    const dim3 g1(t.blocks, 2);
+    int cur = cur_after_pre[l], oth = 1 - cur;
+    kb_prolong<D, TX><<<g1, 256, 0, s>>>(t.get(), t.count, act, cur);
+    for (int k = 0; k < deg; ++k) {
+      const int out = (k == deg - 1) ? 2 : oth;
+      launch_cheb_b<D, TV, TX>(B, l, t, s, k, cur, out, 0);
+      oth = cur;
+      cur = out;
+    }
+  }
+  check_launch("batched vcycle");
+}
+
+template <int D>
+void precond_b(dpp_batch B, const double *r, double *z, bool fp32, hipStream_t s) {
+  const DTable<KDesc> &k = fp32 ? B->kd32 : B->kd;
+  const int *act = B->active.as<int>();
+  const dim3 g(k.blocks, 2);
+  if (fp32) {
+    kb_schur_rhs<D, double, float><<<g, 256, 0, s>>>(k.get(), k.count, act, r);
+    vcycle_b<D, float, float>(B, true, s);
+    kb_schur_vel<D, double, float><<<g, 256, 0, s>>>(k.get(), k.count, act, r, z);
+  } else {
+    kb_schur_rhs<D, double, double><<<g, 256, 0, s>>>(k.get(), k.count, act, r);
+    vcycle_b<D, double, double>(B, false, s);
+    kb_schur_vel<D, double, double><<<g, 256, 0, s>>>(k.get(), k.count, act, r, z);
+  }
+  check_launch("batched precond");
+}
+
+template <int D>
+void spmv_b(dpp_batch B, const double *x, const double *bsub, double *y, hipStream_t s) {
+  kb_spmv_K<D, double><<<B->kd.blocks, 256, 0, s>>>(B->kd.get(), B->kd.count, B->active.as<int>(), x, bsub, y);
+  check_launch("batched spmv");
+}
+
+// one Arnoldi step j for every active instance (graph-capturable: launches only)
+template <int D>
+void arnoldi_step_b(dpp_batch B, int j, bool fp32, hipStream_t s) {
+  const long n = B->ntot;
+  double *V = B->V.as<double>(), *Z = B->Z.as<double>(), *w = B->w.as<double>();
+  double *part = B->part.as<double>(), *hb = B->hb.as<double>();
+  const int *act = B->active.as<int>();
+  const VDesc *vd = B->vd.get();
+  const int nvd = B->vd.count, tb = B->vd.blocks;
+  precond_b<D>(B, V + (size_t)j * n, Z + (size_t)j * n, fp32, s);
+  spmv_b<D>(B, Z + (size_t)j * n, nullptr, w, s);
+  const int nk = j + 1;
+  kb_mdot<<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, nk, w, part);
+  kb_finish<<<dim3(nk, nvd), BBS, 0, s>>>(vd, act, part, tb, hb, 0);
+  kb_axpy_mdot<<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, nk, hb, 0, w, part);
+  kb_finish<<<dim3(nk + 1, nvd), BBS, 0, s>>>(vd, act, part, tb, hb, BMAXK + 1);
+  kb_axpy_norm<<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, nk, hb, BMAXK + 1, w, V + (size_t)(j + 1) * n, part);
+  kb_finish<<<dim3(1, nvd), BBS, 0, s>>>(vd, act, part, tb, hb, 2 * BMAXK + 3);
+  kb_scale<<<tb, BBS, 0, s>>>(vd, nvd, act, V + (size_t)(j + 1) * n, hb, 2 * BMAXK + 3, nullptr);
+  check_launch("batched arnoldi");
+}
+
+// per-instance sums of squares of v (into hb slot `slot`), copied to host
+void norms_b(dpp_batch B, const double *v, int slot, std::vector<double> &out, hipStream_t s) {
+  const int tb = B->vd.blocks;
+  kb_mdot<<<tb, BBS, 0, s>>>(B->vd.get(), B->vd.count, B->active.as<int>(), v, 0, 1, v, B->part.as<double>());
+  kb_finish<<<dim3(1, B->vd.count), BBS, 0, s>>>(B->vd.get(), B->active.as<int>(), B->part.as<double>(), tb,
+                                                 B->hb.as<double>(), slot);
+  check_launch("batched norms");
+  std::vector<double> h((size_t)B->nb * HS);
+  DPP_HIP(hipMemcpyAsync(h.data(), B->hb.ptr, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  DPP_HIP(hipStreamSynchronize(s));
+  out.resize(B->nb);
+  for (int i = 0; i < B->nb; ++i) out[i] = std::sqrt(std::max(0.0, h[(size_t)i * HS + slot]));
+}
+
+template <int D>
+void tune_batch_lanes(dpp_batch B, hipStream_t s) {
+  B->lpr.assign(B->nlev, 1);
+  hipEvent_t e0, e1;
+  DPP_HIP(hipEventCreate(&e0));
+  DPP_HIP(hipEventCreate(&e1));
+  std::vector<int> ones(B->nb, 1);
+  DPP_HIP(hipMemcpy(B->active.ptr, ones.data(), sizeof(int) * B->nb, hipMemcpyHostToDevice));
+  for (int l = 0; l < B->nlev; ++l) {
+    float best_ms = 1e30f;
+    int best = 1;
+    for (int cand : {1, 2, 4, 8}) {
+      B->lpr[l] = cand;
+      DTable<LDesc> t;
+      build_level_tables(B, l, cand, false, t);
+      if (!t.count) break;
+      launch_cheb_b<D, double, double>(B, l, t, s, 0, 0, 0, 1);
+      DPP_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 5; ++r) launch_cheb_b<D, double, double>(B, l, t, s, 0, 0, 0, 1);
+      DPP_HIP(hipEventRecord(e1, s));
+      DPP_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      DPP_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms * 0.97f) {
+        best_ms = ms;
+        best = cand;
+      }
+    }
+    B->lpr[l] = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- set-up --
+void batch_setup(dpp_batch B, hipStream_t s) {
+  const int nb = B->nb;
+  const bool d3 = B->dim == 3;
+  B->doff.assign(nb + 1, 0);
+  for (int i = 0; i < nb; ++i) B->doff[i + 1] = B->doff[i] + B->P[i]->ndof();
+  B->ntot = B->doff[nb];
+  B->nlev = 0;
+  for (auto pc : B->pc) B->nlev = std::max(B->nlev, (int)pc->lv.size() - 1);
+  B->active.alloc(sizeof(int) * nb);
+  B->fac.alloc(sizeof(double) * nb);
+  B->nks.alloc(sizeof(int) * nb);
+  B->ydev.alloc(sizeof(double) * (size_t)nb * BMAXK);
+  B->hb.alloc(sizeof(double) * (size_t)nb * HS);
+  // K-level and Krylov descriptors
+  std::vector<KDesc> kv;
+  std::vector<VDesc> vv;
+  int kb = 0, vb = 0;
+  for (int i = 0; i < nb; ++i) {
+    dpp_problem P = B->P[i];
+    Level &L0 = *B->pc[i]->lv[0];
+    KDesc k{};
+    k.g = dev(P->g);
+    k.blk0 = kb;
+    k.nblk = blocks_for(P->g.N, 256);
+    kb += k.nblk;
+    k.kv = P->kvals.ptr;
+    k.dinv = P->dinv.as<double>();
+    k.off = B->doff[i];
+    k.rhat = L0.b.ptr;
+    k.zp = L0.e.ptr;
+    k.inst = i;
+    kv.push_back(k);
+    VDesc v{};
+    v.off = B->doff[i];
+    v.n = P->ndof();
+    v.blk0 = vb;
+    v.nblk = (int)std::min<long>(256, std::max<long>(1, v.n / 2048));
+    vb += v.nblk;
+    v.inst = i;
+    vv.push_back(v);
+  }
+  B->kd.upload(kv, kb);
+  B->vd.upload(vv, vb);
+  B->part.alloc(sizeof(double) * (size_t)(BMAXK + 2) * vb);
+  std::vector<CDesc> cv;
+  int cb = 0;
+  for (int i = 0; i < nb; ++i) {
+    dpp_precond pc = B->pc[i];
+    Level &Lc = *pc->lv.back();
+    CDesc c{};
+    c.Cinv = pc->cinv.as<double>();
+    c.n = pc->ncoarse;
+    c.blk0 = cb;
+    c.nblk = blocks_for(c.n, 4);
+    cb += c.nblk;
+    c.b = Lc.b.ptr;
+    c.x = Lc.e.ptr;
+    c.inst = i;
+    cv.push_back(c);
+  }
+  B->cd.upload(cv, cb);
+  if (d3)
+    tune_batch_lanes<3>(B, s);
+  else
+    tune_batch_lanes<2>(B, s);
+  B->ld.clear();
+  B->ld.resize(B->nlev);
+  for (int l = 0; l < B->nlev; ++l) build_level_tables(B, l, B->lpr[l], false, B->ld[l]);
+  DPP_HIP(hipStreamSynchronize(s));
+}
+
+void batch_make32(dpp_batch B, hipStream_t s) {
+  if (B->has32) return;
+  for (auto pc : B->pc) precond_make32(pc, s);
+  std::vector<KDesc> kv;
+  for (int i = 0; i < B->nb; ++i) {
+    KDesc k = {};
+    DPP_HIP(hipMemcpy(&k, B->kd.get() + i, sizeof(KDesc), hipMemcpyDeviceToHost));
+    k.rhat = B->pc[i]->lv[0]->b32.ptr;
+    k.zp = B->pc[i]->lv[0]->e32.ptr;
+    kv.push_back(k);
+  }
+  B->kd32.upload(kv, B->kd.blocks);
+  std::vector<CDesc> cv;
+  for (int i = 0; i < B->nb; ++i) {
+    CDesc c = {};
+    DPP_HIP(hipMemcpy(&c, B->cd.get() + i, sizeof(CDesc), hipMemcpyDeviceToHost));
+    c.b = B->pc[i]->lv.back()->b32.ptr;
+    c.x = B->pc[i]->lv.back()->e32.ptr;
+    cv.push_back(c);
+  }
+  B->cd32.upload(cv, B->cd.blocks);
+  B->ld32.clear();
+  B->ld32.resize(B->nlev);
+  for (int l = 0; l < B->nlev; ++l) build_level_tables(B, l, B->lpr[l], true, B->ld32[l]);
+  DPP_HIP(hipStreamSynchronize(s));
+  B->has32 = true;
+}
+
+// ---------------------------------------------------------------- solve --
+template <int D>
+void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_stats *st,
+                  hipStream_t s) {
+  const int nb = B->nb, m = o.restart;
+  const bool use_graph = o.use_graph != 0 && !prof_on();
+  // Graphs are captured on a stream the library owns (the caller's stream may
+  // be the legacy default stream, which cannot be captured); it is ordered
+  // after the caller's stream on entry and the caller's stream after it on exit.
+  hipStream_t caller = s;
+  if (use_graph) {
+    if (!B->gstream) DPP_HIP(hipStreamCreateWithFlags(&B->gstream, hipStreamNonBlocking));
+    hipEvent_t ev;
+    DPP_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    DPP_HIP(hipEventRecord(ev, caller));
+    DPP_HIP(hipStreamWaitEvent(B->gstream, ev, 0));
+    (void)hipEventDestroy(ev);
+    s = B->gstream;
+  }
+  const long n = B->ntot;
+  const bool fp32 = o.precision == 2;
+  if (B->ws_m < m) {
+    B->V.alloc(sizeof(double) * (size_t)(m + 1) * n);
+    B->Z.alloc(sizeof(double) * (size_t)m * n);
+    B->w.alloc(sizeof(double) * n);
+    B->rtmp.alloc(sizeof(double) * n);
+    B->ws_m = m;
+    for (auto &g : B->graphs) (void)hipGraphExecDestroy(g.second);
+    B->graphs.clear();
+  }
+  double *V = B->V.as<double>(), *f = B->rtmp.as<double>();
+  // concatenated right-hand side
+  for (int i = 0; i < nb; ++i)
+    DPP_HIP(hipMemcpyAsync(f + B->doff[i], B->P[i]->f.ptr, sizeof(double) * B->P[i]->ndof(),
+                           hipMemcpyDeviceToDevice, s));
+  std::vector<int> act(nb, 1), conv(nb, 0), its(nb, 0), rest(nb, 0);
+  std::vector<double> bn, rn(nb, 0.0);
+  auto upload_active = [&]() {
+    DPP_HIP(hipMemcpyAsync(B->active.ptr, act.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+  };
+  upload_active();
+  norms_b(B, f, 0, bn, s);
+  std::vector<double> H((size_t)nb * (m + 1) * m), g((size_t)nb * (m + 1)), cs((size_t)nb * m),
+      sn((size_t)nb * m), y((size_t)nb * BMAXK), hh((size_t)nb * HS), fac(nb);
+  std::vector<int> kused(nb);
+  auto Hc = [&](int i, int r, int c) -> double & { return H[((size_t)i * m + c) * (m + 1) + r]; };
+  int total_iters = 0;
+  while (true) {
+    // true residuals of the instances still running
+    for (int i = 0; i < nb; ++i) act[i] = !conv[i];
+    upload_active();
+    spmv_b<D>(B, x, f, V, s);
+    norms_b(B, V, 1, rn, s);
+    bool any = false;
+    for (int i = 0; i < nb; ++i) {
+      if (conv[i]) continue;
+      DPP_CHECK(std::isfinite(rn[i]), DPP_ERR_NUMERIC, "NaN/Inf in a batched residual");
+      if (bn[i] == 0.0 || rn[i] <= o.rtol * bn[i]) {
+        conv[i] = 1;
+        act[i] = 0;
+      } else if (its[i] >= o.maxiter) {
+        act[i] = 0;
+      } else {
+        any = true;
+      }
+      fac[i] = rn[i] > 0 ? 1.0 / rn[i] : 0.0;
+    }
+    if (!any) break;
+    upload_active();
+    DPP_HIP(hipMemcpyAsync(B->fac.ptr, fac.data(), sizeof(double) * nb, hipMemcpyHostToDevice, s));
+    kb_scale<<<B->vd.blocks, BBS, 0, s>>>(B->vd.get(), B->vd.count, B->active.as<int>(), V, nullptr, 0,
+                                          B->fac.as<double>());
+    std::fill(g.begin(), g.end(), 0.0);
+    std::fill(kused.begin(), kused.end(), 0);
+    for (int i = 0; i < nb; ++i) g[(size_t)i * (m + 1)] = rn[i];
+    for (int j = 0; j < m; ++j) {
+      if (use_graph) {
+        auto key = std::make_pair(j, fp32 ? 1 : 0);
+        auto itg = B->graphs.find(key);
+        if (itg == B->graphs.end()) {
+          hipGraph_t graph;
+          DPP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+          arnoldi_step_b<D>(B, j, fp32, s);
+          DPP_HIP(hipStreamEndCapture(s, &graph));
+          hipGraphExec_t ex;
+          DPP_HIP(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0));
+          (void)hipGraphDestroy(graph);
+          itg = B->graphs.emplace(key, ex).first;
+        }
+        DPP_HIP(hipGraphLaunch(itg->second, s));
+      } else {
+        arnoldi_step_b<D>(B, j, fp32, s);
+      }
+      DPP_HIP(hipMemcpyAsync(hh.data(), B->hb.ptr, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s));
+      DPP_HIP(hipStreamSynchronize(s));
+      ++total_iters;
+      bool still = false, changed = false;
+      for (int i = 0; i < nb; ++i) {
+        if (!act[i]) continue;
+        its[i]++;
+        const double *h = &hh[(size_t)i * HS];
+        for (int r = 0; r <= j; ++r) Hc(i, r, j) = h[r] + h[BMAXK + 1 + r];
+        const double hn = std::sqrt(std::max(0.0, h[2 * BMAXK + 3]));
+        Hc(i, j + 1, j) = hn;
+        double *csi = &cs[(size_t)i * m], *sni = &sn[(size_t)i * m], *gi = &g[(size_t)i * (m + 1)];
+        for (int r = 0; r < j; ++r) {
+          const double t = csi[r] * Hc(i, r, j) + sni[r] * Hc(i, r + 1, j);
+          Hc(i, r + 1, j) = -sni[r] * Hc(i, r, j) + csi[r] * Hc(i, r + 1, j);
+          Hc(i, r, j) = t;
+        }
+        const double den = std::hypot(Hc(i, j, j), Hc(i, j + 1, j));
+        DPP_CHECK(std::isfinite(den), DPP_ERR_NUMERIC, "NaN/Inf in a batched Arnoldi step");
+        if (den == 0.0) {
+          act[i] = 0;
+          changed = true;
+          continue;
+        }
+        csi[j] = Hc(i, j, j) / den;
+        sni[j] = Hc(i, j + 1, j) / den;
+        Hc(i, j, j) = den;
+        Hc(i, j + 1, j) = 0.0;
+        gi[j + 1] = -sni[j] * gi[j];
+        gi[j] = csi[j] * gi[j];
+        kused[i] = j + 1;
+        if (std::fabs(gi[j + 1]) <= o.rtol * bn[i] || its[i] >= o.maxiter || hn <= 1e-300) {
+          act[i] = 0;
+          changed = true;
+        } else {
+          still = true;
+        }
+      }
+      if (!still) break;
+      if (changed) upload_active();
+    }
+    // x_i += Z_i y_i
+    std::vector<int> nk(nb, 0);
+    for (int i = 0; i < nb; ++i) {
+      const int k = kused[i];
+      nk[i] = k;
+      double *yi = &y[(size_t)i * BMAXK];
+      const double *gi = &g[(size_t)i * (m + 1)];
+      for (int r = k - 1; r >= 0; --r) {
+        double t = gi[r];
+        for (int c = r + 1; c < k; ++c) t -= Hc(i, r, c) * yi[c];
+        yi[r] = t / Hc(i, r, r);
+      }
+      if (k) rest[i]++;
+    }
+    DPP_HIP(hipMemcpyAsync(B->ydev.ptr, y.data(), sizeof(double) * y.size(), hipMemcpyHostToDevice, s));
+    DPP_HIP(hipMemcpyAsync(B->nks.ptr, nk.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+    kb_update<<<B->vd.blocks, BBS, 0, s>>>(B->vd.get(), B->vd.count, B->Z.as<double>(), n,
+                                           B->ydev.as<double>(), B->nks.as<int>(), x);
+    check_launch("batched update");
+    bool progress = false;
+    for (int i = 0; i < nb; ++i)
+      if (!conv[i] && its[i] < o.maxiter) progress = true;
+    if (!progress) {
+      // final residuals for the report
+      for (int i = 0; i < nb; ++i) act[i] = 1;
+      upload_active();
+      spmv_b<D>(B, x, f, V, s);
+      norms_b(B, V, 1, rn, s);
+      for (int i = 0; i < nb; ++i)
+        if (!conv[i] && bn[i] > 0 && rn[i] <= o.rtol * bn[i]) conv[i] = 1;
+      break;
+    }
+  }
+  DPP_HIP(hipStreamSynchronize(s));
+  if (use_graph) DPP_HIP(hipStreamSynchronize(caller));
+  for (int i = 0; i < nb; ++i) {
+    st[i].iters = its[i];
+    st[i].restarts = rest[i];
+    st[i].refinements = 0;
+    st[i].converged = conv[i];
+    st[i].rel_residual = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
+    st[i].ms_solve = 0.0;
+  }
+  (void)total_iters;
+}
+
+void batch_solve(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_stats *st, hipStream_t s) {
+  if (o.precision == 2) batch_make32(B, s);
+  DPP_CHECK(o.precision != 1, DPP_ERR_UNSUPPORTED,
+            "batched solves support precision 0 (FP64) and 2 (FP32 preconditioner)");
+  if (B->dim == 3)
+    batch_fgmres<3>(B, o, x, st, s);
+  else
+    batch_fgmres<2>(B, o, x, st, s);
+}
+
+}  // namespace dpp

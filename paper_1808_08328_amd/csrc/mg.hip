@@ -23,95 +23,12 @@
 
 #include "objects.h"
 #include "profile.h"
+#include "stencil.h"
 
 namespace dpp {
 
 namespace {
 
-struct Sc2 {
-  double v[2];
-};
-
-__device__ inline void fine_to_coarse(int i, int n, int mc, int &lo, int &od) {
-  if ((n & 1) && i == n) {
-    lo = mc - 1;
-    od = 0;
-  } else {
-    lo = i >> 1;
-    od = i & 1;
-  }
-}
-
-__device__ inline int exact_fine(int c, int n, int mc) { return ((n & 1) && c == mc - 1) ? n : 2 * c; }
-
-// Stencil product of one row, split over LPR lanes (offsets t = sub, sub+LPR,
-// ...); the lanes of a row are adjacent and reduce with shuffles.  LPR = 1 is
-// the fully unrolled one-thread-per-row form used on large levels; smaller
-// levels use more lanes per row so the launch still fills the GPU.
-//
-// SYM: the operators are symmetric, so only the zero offset and the positive
-// half of T (linear offset > 0; T is sorted, so these are indices t0..NT-1)
-// are stored, H[h][a] = A(a, a + o_{t0+h}); the entries of the negative
-// half are read from the neighbour's row, A(a, a - o) = H[h][a - o].  That
-// halves the matrix bytes streamed from HBM when the mirror reads hit in L2
-// or the Infinity Cache (rows a and a - o are at most two planes apart).
-template <int D, typename TV, typename TX, int LPR, bool SYM>
-__device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq,
-                                     const TX *__restrict__ xq, long a, int i, int j, int k, int sub) {
-  // Entries of pairs that leave the box are stored as zeros, so the loads
-  // need no guard: the vector index is clamped into range (the zero entry
-  // multiplies a finite value) and only a mirror entry whose row index falls
-  // outside [0, N) is masked.  Unguarded loads let every load of the row be
-  // in flight at once.
-  constexpr int NT = Tabs<D>::NT;
-  constexpr int T0 = TAB<D>.t0;
-  constexpr int NH = NT - T0;  // zero offset + positive half
-  const long N = g.N, ld = g.ld;
-  (void)i; (void)j; (void)k;
-  double acc = 0.0;
-  // Offsets are processed in unrolled groups of 8: each group's loads are
-  // issued together without exhausting the register budget.
-  if constexpr (!SYM) {
-#pragma unroll 8
-    for (int tt = 0; tt < (NT + LPR - 1) / LPR; ++tt) {
-      const int t = tt * LPR + (LPR == 1 ? 0 : sub);
-      if (LPR > 1 && t >= NT) continue;
-      const int *o = TAB<D>.to[t];
-      const long b = min(max(a + lin(g, o[0], o[1], o[2]), 0L), N - 1);
-      acc += (double)Aq[(size_t)t * ld + a] * (double)xq[b];
-    }
-  } else {
-#pragma unroll 8
-    for (int hh = 0; hh < (NH + LPR - 1) / LPR; ++hh) {
-      const int h = hh * LPR + (LPR == 1 ? 0 : sub);
-      if (LPR > 1 && h >= NH) continue;
-      const int *o = TAB<D>.to[T0 + h];
-      const long lo = lin(g, o[0], o[1], o[2]);
-      const long bp = min(a + lo, N - 1);
-      acc += (double)Aq[(size_t)h * ld + a] * (double)xq[bp];
-      if (h > 0) {
-        const long bm = a - lo;
-        const long bc = max(bm, 0L);
-        const double v = (double)Aq[(size_t)h * ld + bc] * (double)xq[bc];
-        acc += (bm >= 0) ? v : 0.0;
-      }
-    }
-  }
-  if constexpr (LPR > 1) {
-#pragma unroll
-    for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
-  }
-  return acc;
-}
-
-template <int D, bool SYM>
-constexpr int stored_offsets() {
-  return SYM ? Tabs<D>::NT - TAB<D>.t0 : Tabs<D>::NT;
-}
-
-// A x on a level, optionally returning b - A x and/or scaling by dinv.
-// FINE only separates the finest-level instances from the coarse-level ones
-// (distinct kernel names in profiles); the code is the same.
 // Occupancy floor of the stencil kernels: at least 4 waves per SIMD (<= 128
 // VGPRs), which still leaves a whole row's loads in flight per wave.
 template <int D, typename TV, typename TX, int LPR, bool SYM, bool FINE>
@@ -239,31 +156,10 @@ __global__ __launch_bounds__(256) void k_cheb_first(long N, const TV *__restrict
 template <int D, typename TX>
 __global__ __launch_bounds__(256) void k_restrict(GridDev gf, GridDev gc, const TX *__restrict__ r,
                                                   TX *__restrict__ bc) {
-  const long Nc = gc.N;
   const int q = blockIdx.y;
   const long C = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (C >= Nc) return;
-  int cc[3];
-  node_ijk(gc, C, cc[0], cc[1], cc[2]);
-  const TX *rq = r + (size_t)q * gf.N;
-  int ex[3];
-  for (int ax = 0; ax < 3; ++ax) ex[ax] = exact_fine(cc[ax], gf.n[ax], gc.m[ax]);
-  auto fid = [&](const int *f) { return f[0] + (long)gf.m[0] * (f[1] + (long)gf.m[1] * f[2]); };
-  double acc = (double)rq[fid(ex)];
-  for (int mask = 1; mask < (1 << D); ++mask) {
-    int fu[3] = {ex[0], ex[1], ex[2]}, fd[3] = {ex[0], ex[1], ex[2]};
-    bool uok = true, dok = true;
-    for (int ax = 0; ax < D; ++ax) {
-      if (!((mask >> ax) & 1)) continue;
-      fu[ax] = 2 * cc[ax] + 1;
-      fd[ax] = 2 * cc[ax] - 1;
-      uok = uok && fu[ax] <= gf.n[ax] - 1;
-      dok = dok && fd[ax] >= 1 && fd[ax] <= gf.n[ax] - 1;
-    }
-    if (uok) acc += 0.5 * (double)rq[fid(fu)];
-    if (dok) acc += 0.5 * (double)rq[fid(fd)];
-  }
-  bc[(size_t)q * Nc + C] = (TX)acc;
+  if (C >= gc.N) return;
+  bc[(size_t)q * gc.N + C] = (TX)restrict_node<D, TX>(gf, gc, r + (size_t)q * gf.N, C);
 }
 
 // x(f) += (P e)(f)
@@ -274,21 +170,7 @@ __global__ __launch_bounds__(256) void k_prolong(GridDev gf, GridDev gc, const T
   const int q = blockIdx.y;
   const long f = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (f >= N) return;
-  int fi[3];
-  node_ijk(gf, f, fi[0], fi[1], fi[2]);
-  int lo[3], od[3];
-  bool any = false;
-  for (int ax = 0; ax < 3; ++ax) {
-    fine_to_coarse(fi[ax], gf.n[ax], gc.m[ax], lo[ax], od[ax]);
-    any = any || od[ax];
-  }
-  const TX *eq = e + (size_t)q * gc.N;
-  const long c0 = lo[0] + (long)gc.m[0] * (lo[1] + (long)gc.m[1] * lo[2]);
-  double v = (double)eq[c0];
-  if (any) {
-    const long c1 = (lo[0] + od[0]) + (long)gc.m[0] * ((lo[1] + od[1]) + (long)gc.m[1] * (lo[2] + od[2]));
-    v = 0.5 * (v + (double)eq[c1]);
-  }
+  const double v = prolong_node<D, TX>(gf, gc, e + (size_t)q * gc.N, f);
   x[(size_t)q * N + f] = (TX)((double)x[(size_t)q * N + f] + v);
 }
 

@@ -27,6 +27,20 @@ struct DBuf {
   ~DBuf() { release(); }
   DBuf(const DBuf &) = delete;
   DBuf &operator=(const DBuf &) = delete;
+  DBuf(DBuf &&o) noexcept : ptr(o.ptr), bytes(o.bytes) {
+    o.ptr = nullptr;
+    o.bytes = 0;
+  }
+  DBuf &operator=(DBuf &&o) noexcept {
+    if (this != &o) {
+      release();
+      ptr = o.ptr;
+      bytes = o.bytes;
+      o.ptr = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
   template <typename T>
   T *as() const {
     return static_cast<T *>(ptr);
@@ -133,6 +147,10 @@ SolveResult fgmres(dpp_problem P, dpp_precond pc, const dpp_solve_opts &o, const
                    double *x, int mode, double rtol, int maxiter, double bnorm_ref,
                    hipStream_t s);
 void axpby(long n, double a, const double *x, double b, double *y, hipStream_t s);
+
+// --- batch.hip
+void batch_setup(dpp_batch B, hipStream_t s);
+void batch_solve(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_stats *st, hipStream_t s);
 
 // --- adjoint.hip
 void param_grad(dpp_problem P, const double *x, const double *lam, double *g1, double *g2,

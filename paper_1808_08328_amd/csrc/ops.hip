@@ -8,6 +8,7 @@
 // contiguous in node order and mostly served from L2.
 #include "objects.h"
 #include "profile.h"
+#include "stencil.h"
 
 namespace dpp {
 
@@ -18,57 +19,14 @@ __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict_
                                                 const double *__restrict__ x,
                                                 const double *__restrict__ bsub,
                                                 double *__restrict__ y) {
-  constexpr int NS = Tabs<D>::NS;
   const long N = g.N;
   const long a = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (a >= N) return;
-  int i, j, k;
-  node_ijk(g, a, i, j, k);
-  double au[2][D], ap[2] = {0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < 2; ++q)
-#pragma unroll
-    for (int c = 0; c < D; ++c) au[q][c] = 0.0;
-  const size_t vs = (size_t)NS * g.ld;
-  const long ou0 = off_u(D, N, 0), ou1 = off_u(D, N, 1), op0 = off_p(D, N, 0),
-             op1 = off_p(D, N, 1);
-  // Out-of-box pairs hold zeros, so the neighbour index is clamped instead of
-  // guarded (all loads of the row can be in flight together).
-  (void)i; (void)j; (void)k;
-  // one offset per trip: its 4d+5 value streams and 2d+2 neighbour unknowns
-  // are loaded together
-#pragma unroll 1
-  for (int t = 0; t < NS; ++t) {
-    const int *o = TAB<D>.so[t];
-    const long b = min(max(a + lin(g, o[0], o[1], o[2]), 0L), N - 1);
-    double xu[2][D], xp[2];
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      xu[0][c] = x[ou0 + D * b + c];
-      xu[1][c] = x[ou1 + D * b + c];
-    }
-    xp[0] = x[op0 + b];
-    xp[1] = x[op1 + b];
-    const TV *base = kv + (size_t)t * g.ld + a;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const double uu = (double)base[kv_uu(D, q) * vs];
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const double up = (double)base[kv_up(D, q, c) * vs];
-        const double pu = (double)base[kv_pu(D, q, c) * vs];
-        au[q][c] += uu * xu[q][c] + up * xp[q];
-        ap[q] += pu * xu[q][c];
-      }
-      ap[q] += (double)base[kv_pp(D, q) * vs] * xp[q];
-    }
-    const double k12 = (double)base[kv_12(D) * vs];
-    ap[0] += k12 * xp[1];
-    ap[1] += k12 * xp[0];
-  }
+  double au[2][D], ap[2];
+  spmv_K_node<D, TV>(g, kv, x, a, au, ap);
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const long ou = q ? ou1 : ou0, op = q ? op1 : op0;
+    const long ou = off_u(D, N, q), op = off_p(D, N, q);
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       const long r = ou + D * a + c;
@@ -165,68 +123,32 @@ __global__ __launch_bounds__(256) void k_selfp(GridDev g, const double *__restri
   S[((size_t)q * NT + t) * g.ld + b] = acc;
 }
 
-// rhat_i(b) = r_p_i(b) - sum_t sum_c K_pu^i(b, (b+o_t, c)) dinv_i(b+o_t) r_u_i(b+o_t, c)
 template <int D, typename TV, typename TX>
 __global__ __launch_bounds__(256) void k_schur_rhs(GridDev g, const TV *__restrict__ kv,
                                                    const double *__restrict__ dinv,
                                                    const double *__restrict__ r,
                                                    TX *__restrict__ rhat) {
-  constexpr int NS = Tabs<D>::NS;
-  const long N = g.N;
   const int q = blockIdx.y;
   const long b = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (b >= N) return;
-  int i, j, k;
-  node_ijk(g, b, i, j, k);
-  const size_t vs = (size_t)NS * g.ld;
-  const long ou = off_u(D, N, q);
-  double acc = r[off_p(D, N, q) + b];
-  (void)i; (void)j; (void)k;
-#pragma unroll
-  for (int t = 0; t < NS; ++t) {
-    const int *o = TAB<D>.so[t];
-    const long a = min(max(b + lin(g, o[0], o[1], o[2]), 0L), N - 1);
-    const double di = dinv[q * N + a];
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < D; ++c)
-      s += (double)kv[kv_pu(D, q, c) * vs + (size_t)t * g.ld + b] * r[ou + D * a + c];
-    acc -= s * di;
-  }
-  rhat[q * N + b] = (TX)acc;
+  if (b >= g.N) return;
+  rhat[q * g.N + b] = (TX)schur_rhs_node<D, TV>(g, kv, dinv, r, q, b);
 }
 
-// z_u_i(a, c) = dinv_i(a) (r_u_i(a, c) - sum_t K_up^i((a,c), a+o_t) z_p_i(a+o_t)), z_p_i = zp_i
 template <int D, typename TV, typename TX>
 __global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restrict__ kv,
                                                    const double *__restrict__ dinv,
                                                    const double *__restrict__ r,
                                                    const TX *__restrict__ zp,
                                                    double *__restrict__ z) {
-  constexpr int NS = Tabs<D>::NS;
   const long N = g.N;
   const int q = blockIdx.y;
   const long a = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (a >= N) return;
-  int i, j, k;
-  node_ijk(g, a, i, j, k);
-  const size_t vs = (size_t)NS * g.ld;
+  double out[D];
+  schur_vel_node<D, TV, TX>(g, kv, dinv, r, zp, q, a, out);
   const long ou = off_u(D, N, q);
-  double acc[D];
 #pragma unroll
-  for (int c = 0; c < D; ++c) acc[c] = r[ou + D * a + c];
-  (void)i; (void)j; (void)k;
-#pragma unroll
-  for (int t = 0; t < NS; ++t) {
-    const int *o = TAB<D>.so[t];
-    const long b = min(max(a + lin(g, o[0], o[1], o[2]), 0L), N - 1);
-    const double zb = (double)zp[q * N + b];
-#pragma unroll
-    for (int c = 0; c < D; ++c) acc[c] -= (double)kv[kv_up(D, q, c) * vs + (size_t)t * g.ld + a] * zb;
-  }
-  const double di = dinv[q * N + a];
-#pragma unroll
-  for (int c = 0; c < D; ++c) z[ou + D * a + c] = di * acc[c];
+  for (int c = 0; c < D; ++c) z[ou + D * a + c] = out[c];
   z[off_p(D, N, q) + a] = (double)zp[q * N + a];
 }
 

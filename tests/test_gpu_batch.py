@@ -1,0 +1,84 @@
+"""GPU parity of the batched multi-instance solve against the oracle and the
+single-instance path (bars as in test_gpu_parity)."""
+import numpy as np
+import pytest
+
+import dpp_inputs as I
+from oracle import dpp as odpp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def H(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def uneven_2d(count=8, seed=77):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        n = int(rng.integers(4, 41))
+        beta = float(10 ** rng.uniform(-1, 1))
+        ratio = float(10 ** rng.uniform(-3, 0))
+        out.append(I.mms_problem(2, n if i % 3 else (n, n // 2 + 3), k1=1.0, k2=ratio, beta=beta))
+    return out
+
+
+def test_batch_matches_oracle_and_single_solves():
+    import paper_1808_08328_amd as dpp
+    probs = uneven_2d()
+    print("batch sizes", [p.n for p in probs], flush=True)
+    B = dpp.assemble_batch(probs, coarse_max=30)
+    assert len(B.lanes()) >= 2
+    x, st = B.solve(rtol=1e-12)
+    assert all(s.converged for s in st)
+    xs = [H(v) for v in B.split(x)]
+    for i, pr in enumerate(probs):
+        S = odpp.assemble(pr)
+        xo = odpp.solve_direct(S.K, S.f)
+        F = odpp.fields(2, S.N)
+        for f in ("u1", "p1", "u2", "p2"):
+            assert np.linalg.norm(xs[i][F[f]] - xo[F[f]]) <= 1e-10 * np.linalg.norm(xo[F[f]]), (i, f)
+        # same preconditioner definition as the single-instance path: same iteration count
+        P = dpp.assemble_problem(pr)
+        pc = P.setup_precond(coarse_max=30)
+        _, s1 = P.solve(pc, rtol=1e-12)
+        assert abs(s1.iters - st[i].iters) <= 1, (i, s1.iters, st[i].iters)
+
+
+def test_batch_graph_replay_is_bit_identical():
+    import paper_1808_08328_amd as dpp
+    probs = uneven_2d(6, seed=5)
+    B = dpp.assemble_batch(probs, coarse_max=30)
+    x1, s1 = B.solve(rtol=1e-10)
+    x2, s2 = B.solve(rtol=1e-10, use_graph=1)
+    x3, s3 = B.solve(rtol=1e-10, use_graph=1)  # replays the cached graphs
+    assert torch.equal(x1, x2) and torch.equal(x2, x3)
+    assert [s.iters for s in s1] == [s.iters for s in s2] == [s.iters for s in s3]
+
+
+def test_batch_fp32_preconditioner_and_3d():
+    import paper_1808_08328_amd as dpp
+    probs = [I.grf_problem(3, 5), I.mms_problem(3, (6, 4, 5), k2=1e-2), I.grf_problem(3, 7)]
+    B = dpp.assemble_batch(probs, coarse_max=40)
+    for precision in (0, 2):
+        x, st = B.solve(rtol=1e-10, precision=precision)
+        assert all(s.converged for s in st)
+        for i, pr in enumerate(probs):
+            S = odpp.assemble(pr)
+            xo = odpp.solve_direct(S.K, S.f)
+            xi = H(B.split(x)[i])
+            assert np.linalg.norm(xi - xo) <= 1e-7 * np.linalg.norm(xo), (precision, i)
+
+
+def test_batch_masks_converged_instances_and_reports_unconverged():
+    import paper_1808_08328_amd as dpp
+    probs = [I.mms_problem(2, 4), I.mms_problem(2, 30, k2=1e-3)]
+    B = dpp.assemble_batch(probs, coarse_max=30)
+    with pytest.raises(dpp.DppError) as e:
+        B.solve(rtol=1e-10, maxiter=3)
+    assert e.value.status == 4
+    x, st = B.solve(rtol=1e-10, maxiter=3, allow_unconverged=True)
+    assert st[1].converged == 0 and st[1].iters == 3
