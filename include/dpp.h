@@ -243,6 +243,10 @@ dpp_status dpp_batch_lanes(dpp_batch b, int *n_levels, int *lanes);
  * maxiter. */
 dpp_status dpp_solve_batch(dpp_batch b, const dpp_solve_opts *opts, double *x_concat,
                            dpp_solve_stats *stats, void *stream);
+/* Test hooks on concatenated vectors (device [total_dof]): y = K x and
+ * z = P^-1 r for every instance in one batched launch sequence (FP64). */
+dpp_status dpp_batch_spmv(dpp_batch b, const double *x, double *y, void *stream);
+dpp_status dpp_batch_precond_apply(dpp_batch b, const double *r, double *z, void *stream);
 void dpp_destroy_batch(dpp_batch b);
 
 void dpp_destroy_problem(dpp_problem prob);

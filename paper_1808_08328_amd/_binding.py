@@ -81,6 +81,8 @@ def lib():
         "dpp_batch_sizes": (C.c_int, [P, I64, I64]),
         "dpp_batch_lanes": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "dpp_solve_batch": (C.c_int, [P, C.POINTER(_Opts), P, C.POINTER(SolveStats), P]),
+        "dpp_batch_spmv": (C.c_int, [P, P, P, P]),
+        "dpp_batch_precond_apply": (C.c_int, [P, P, P, P]),
         "dpp_destroy_batch": (None, [P]),
         "dpp_destroy_problem": (None, [P]),
         "dpp_destroy_precond": (None, [P]),
@@ -318,6 +320,16 @@ class Batch:
         _check(lib().dpp_solve_batch(self.handle, C.byref(o), _ptr(x), st, _stream(stream)),
                allow=(4,) if allow_unconverged else ())
         return x, [st[i] for i in range(self.nb)]
+
+    def spmv(self, x, stream=None):
+        y = torch.empty_like(x)
+        _check(lib().dpp_batch_spmv(self.handle, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def precond_apply(self, r, stream=None):
+        z = torch.empty_like(r)
+        _check(lib().dpp_batch_precond_apply(self.handle, _ptr(r), _ptr(z), _stream(stream)))
+        return z
 
     def split(self, x):
         return [x[self.offsets[i]:self.offsets[i + 1]] for i in range(self.nb)]

@@ -408,6 +408,20 @@ dpp_status dpp_solve_batch(dpp_batch B, const dpp_solve_opts *opts, double *x, d
   return status;
 }
 
+dpp_status dpp_batch_spmv(dpp_batch B, const double *x, double *y, void *stream) {
+  return guard([&] {
+    DPP_CHECK(B && x && y && x != y, DPP_ERR_ARG, "bad argument");
+    dpp::batch_apply(B, 0, x, y, S(stream));
+  });
+}
+
+dpp_status dpp_batch_precond_apply(dpp_batch B, const double *r, double *z, void *stream) {
+  return guard([&] {
+    DPP_CHECK(B && r && z && r != z, DPP_ERR_ARG, "bad argument");
+    dpp::batch_apply(B, 1, r, z, S(stream));
+  });
+}
+
 void dpp_destroy_batch(dpp_batch B) { delete B; }
 
 void dpp_destroy_problem(dpp_problem P) { delete P; }

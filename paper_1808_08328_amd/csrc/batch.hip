@@ -737,6 +737,9 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
     upload_active();
     spmv_b<D>(B, x, f, V, s);
     norms_b(B, V, 1, rn, s);
+    if (getenv("DPP_BATCH_VERBOSE"))
+      for (int i = 0; i < nb; ++i)
+        fprintf(stderr, "batch cycle: inst %d its %d bn %.6e rn %.6e conv %d\n", i, its[i], bn[i], rn[i], conv[i]);
     bool any = false;
     for (int i = 0; i < nb; ++i) {
       if (conv[i]) continue;
@@ -862,6 +865,18 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
     st[i].ms_solve = 0.0;
   }
   (void)total_iters;
+}
+
+void batch_apply(dpp_batch B, int what, const double *x, double *y, hipStream_t s) {
+  std::vector<int> ones(B->nb, 1);
+  DPP_HIP(hipMemcpyAsync(B->active.ptr, ones.data(), sizeof(int) * B->nb, hipMemcpyHostToDevice, s));
+  DPP_HIP(hipStreamSynchronize(s));
+  if (B->dim == 3) {
+    if (what == 0) spmv_b<3>(B, x, nullptr, y, s); else precond_b<3>(B, x, y, false, s);
+  } else {
+    if (what == 0) spmv_b<2>(B, x, nullptr, y, s); else precond_b<2>(B, x, y, false, s);
+  }
+  DPP_HIP(hipStreamSynchronize(s));
 }
 
 void batch_solve(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_stats *st, hipStream_t s) {

@@ -151,6 +151,7 @@ void axpby(long n, double a, const double *x, double b, double *y, hipStream_t s
 // --- batch.hip
 void batch_setup(dpp_batch B, hipStream_t s);
 void batch_solve(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_stats *st, hipStream_t s);
+void batch_apply(dpp_batch B, int what, const double *x, double *y, hipStream_t s);
 
 // --- adjoint.hip
 void param_grad(dpp_problem P, const double *x, const double *lam, double *g1, double *g2,

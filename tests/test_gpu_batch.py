@@ -20,10 +20,29 @@ def uneven_2d(count=8, seed=77):
     out = []
     for i in range(count):
         n = int(rng.integers(4, 41))
-        beta = float(10 ** rng.uniform(-1, 1))
-        ratio = float(10 ** rng.uniform(-3, 0))
+        # eta = sqrt(beta (k1 + k2) / (k1 k2)) stays below about 10, so the
+        # manufactured solution's exp(eta y) layer stays representable
+        beta = float(10 ** rng.uniform(-1, 0.5))
+        ratio = float(10 ** rng.uniform(-1.5, 0))
         out.append(I.mms_problem(2, n if i % 3 else (n, n // 2 + 3), k1=1.0, k2=ratio, beta=beta))
     return out
+
+
+def test_batch_operator_and_preconditioner_match_single_path():
+    import paper_1808_08328_amd as dpp
+    probs = uneven_2d()
+    B = dpp.assemble_batch(probs, coarse_max=30)
+    x = torch.as_tensor(I.random_vector(B.n_dof, 3), device="cuda")
+    yb = [H(v) for v in B.split(B.spmv(x))]
+    zb = [H(v) for v in B.split(B.precond_apply(x))]
+    xs = B.split(x)
+    for i, pr in enumerate(probs):
+        P = dpp.assemble_problem(pr)
+        pc = P.setup_precond(coarse_max=30)
+        ys = H(P.spmv(xs[i].contiguous()))
+        assert np.abs(yb[i] - ys).max() <= 1e-13 * np.abs(ys).max(), ("spmv", i)
+        zs = H(pc.apply(xs[i].contiguous()))
+        assert np.abs(zb[i] - zs).max() <= 1e-11 * np.abs(zs).max(), ("precond", i)
 
 
 def test_batch_matches_oracle_and_single_solves():
