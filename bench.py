@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-max-iters", type=int, default=60)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--graph", type=int, default=0, choices=[0, 1],
+                    help="replay each Arnoldi step from a captured hipGraph")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 512 MiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -184,7 +186,7 @@ def main():
     pc = P.setup_precond()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    opts = dict(rtol=1e-8, precision=args.precision)
+    opts = dict(rtol=1e-8, precision=args.precision, use_graph=args.graph)
     for _ in range(args.warmup):
         P.solve(pc, **opts)
     torch.cuda.synchronize()
@@ -228,7 +230,8 @@ def main():
         "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64/f32",
         "data": "synthetic",
         "config": {"workload": args.config, "description": WORKLOADS[args.config],
-                   "n_dof": P.n_dof, "rtol": 1e-8, "precision": PRECISION[args.precision]},
+                   "n_dof": P.n_dof, "rtol": 1e-8, "precision": PRECISION[args.precision],
+                   "graph": bool(args.graph)},
         "iters": iters, "rel_residual": stats[-1]["rel_residual"],
         "assemble_ms": (t1 - t0) * 1e3, "setup_ms": (t2 - t1) * 1e3,
         "roofline": roof, "kernels": kernels,

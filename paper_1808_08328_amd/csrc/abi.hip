@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "objects.h"
+#include "profile.h"
 #include "batch.h"
 
 namespace {
@@ -185,6 +186,7 @@ dpp_status dpp_precond_set_shape(dpp_precond pc, int level, int lanes, int sym) 
     DPP_CHECK(sym == 0 || sym == 1, DPP_ERR_ARG, "sym must be 0 or 1");
     pc->lv[level]->shape.lpr = lanes;
     pc->lv[level]->shape.sym = sym != 0;
+    pc->drop_graphs();
   });
 }
 
@@ -232,6 +234,18 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
     }
     check_opts(o);
     hipStream_t s = S(stream);
+    if (o.use_graph && !dpp::prof_on()) {
+      // Graphs are captured and replayed on a stream the library owns (the
+      // caller's may be the legacy default stream, which cannot be captured),
+      // ordered after the caller's stream; the solve ends with a host wait.
+      if (!pc->gstream) DPP_HIP(hipStreamCreateWithFlags(&pc->gstream, hipStreamNonBlocking));
+      hipEvent_t ev;
+      DPP_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      DPP_HIP(hipEventRecord(ev, s));
+      DPP_HIP(hipStreamWaitEvent(pc->gstream, ev, 0));
+      (void)hipEventDestroy(ev);
+      s = pc->gstream;
+    }
     const double *b = rhs ? rhs : P->f.as<double>();
     const long n = P->ndof();
     dpp::ensure_reduction(pc);

@@ -386,6 +386,7 @@ void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, 
   }
   check_launch("assemble");
   make_dinv(P, s);
+  make_kh(P, s);
 }
 
 void export_csr(dpp_problem P, int64_t *rowptr, int32_t *cols, double *vals, hipStream_t s) {

@@ -19,6 +19,7 @@
 #include "profile.h"
 #include "stencil.h"
 #include "batch.h"
+#include "mvec.h"
 
 namespace dpp {
 
@@ -202,31 +203,9 @@ __global__ __launch_bounds__(256) void kb_coarse(const CDesc *__restrict__ cd, i
 }
 
 // ---------------------------------------------------------------- Krylov --
-__device__ inline void bblock_store(const double *acc, int nk, double *part, int tb,
-                                    double extra = 0.0, bool with_extra = false) {
-  __shared__ double sh[BBS / 64][BMAXK + 1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < BMAXK; ++k) {
-    if (k < nk) {
-      double v = bwave_sum(acc[k]);
-      if (lane == 0) sh[wv][k] = v;
-    }
-  }
-  if (with_extra) {
-    double v = bwave_sum(extra);
-    if (lane == 0) sh[wv][BMAXK] = v;
-  }
-  __syncthreads();
-  const int tot = nk + (with_extra ? 1 : 0);
-  if ((int)threadIdx.x < tot) {
-    const int slot = ((int)threadIdx.x == nk) ? BMAXK : (int)threadIdx.x;
-    double s = 0.0;
-    for (int w = 0; w < BBS / 64; ++w) s += sh[w][slot];
-    part[(size_t)threadIdx.x * tb + blockIdx.x] = s;
-  }
-}
-
+// Every block works on its instance's slice [off, off + n) with the
+// instance's own grid stride; partials are indexed by the global block.
+template <int NKP>
 __global__ __launch_bounds__(BBS) void kb_mdot(const VDesc *__restrict__ vd, int nd,
                                                const int *__restrict__ active,
                                                const double *__restrict__ V, long ldv, int nk,
@@ -234,18 +213,15 @@ __global__ __launch_bounds__(BBS) void kb_mdot(const VDesc *__restrict__ vd, int
   const int di = find_desc(vd, nd, (int)blockIdx.x, &VDesc::blk0);
   const VDesc &v = vd[di];
   if (!active[v.inst]) return;
-  double acc[BMAXK];
+  double acc[NKP];
 #pragma unroll
-  for (int k = 0; k < BMAXK; ++k) acc[k] = 0.0;
-  for (long i = (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x; i < v.n; i += (long)v.nblk * BBS) {
-    const double wi = w[v.off + i];
-#pragma unroll
-    for (int k = 0; k < BMAXK; ++k)
-      if (k < nk) acc[k] += V[(size_t)k * ldv + v.off + i] * wi;
-  }
-  bblock_store(acc, nk, part, gridDim.x);
+  for (int k = 0; k < NKP; ++k) acc[k] = 0.0;
+  mv_dot<NKP>(V + v.off, ldv, nk, w + v.off, (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x, v.n,
+              (long)v.nblk * BBS, acc);
+  mv_block_store<NKP>(acc, nk, 0.0, false, part, gridDim.x, blockIdx.x);
 }
 
+template <int NKP>
 __global__ __launch_bounds__(BBS) void kb_axpy_mdot(const VDesc *__restrict__ vd, int nd,
                                                     const int *__restrict__ active,
                                                     const double *__restrict__ V, long ldv, int nk,
@@ -254,28 +230,16 @@ __global__ __launch_bounds__(BBS) void kb_axpy_mdot(const VDesc *__restrict__ vd
   const int di = find_desc(vd, nd, (int)blockIdx.x, &VDesc::blk0);
   const VDesc &v = vd[di];
   if (!active[v.inst]) return;
-  double acc[BMAXK], hk[BMAXK], nrm = 0.0;
+  double acc[NKP], hk[NKP], nrm = 0.0;
 #pragma unroll
-  for (int k = 0; k < BMAXK; ++k) {
-    acc[k] = 0.0;
-    hk[k] = (k < nk) ? hb[(size_t)v.inst * HS + hslot + k] : 0.0;
-  }
-  for (long i = (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x; i < v.n; i += (long)v.nblk * BBS) {
-    double vv[BMAXK];
-    double s = w[v.off + i];
-#pragma unroll
-    for (int k = 0; k < BMAXK; ++k) {
-      vv[k] = (k < nk) ? V[(size_t)k * ldv + v.off + i] : 0.0;
-      s -= hk[k] * vv[k];
-    }
-    w[v.off + i] = s;
-#pragma unroll
-    for (int k = 0; k < BMAXK; ++k) acc[k] += vv[k] * s;
-    nrm += s * s;
-  }
-  bblock_store(acc, nk, part, gridDim.x, nrm, true);
+  for (int k = 0; k < NKP; ++k) acc[k] = 0.0;
+  mv_coefs<NKP>(hb + (size_t)v.inst * HS + hslot, nk, hk);
+  mv_axpy<NKP, true>(V + v.off, ldv, nk, hk, w + v.off, w + v.off,
+                     (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x, v.n, (long)v.nblk * BBS, acc, nrm);
+  mv_block_store<NKP>(acc, nk, nrm, true, part, gridDim.x, blockIdx.x);
 }
 
+template <int NKP>
 __global__ __launch_bounds__(BBS) void kb_axpy_norm(const VDesc *__restrict__ vd, int nd,
                                                     const int *__restrict__ active,
                                                     const double *__restrict__ V, long ldv, int nk,
@@ -285,18 +249,11 @@ __global__ __launch_bounds__(BBS) void kb_axpy_norm(const VDesc *__restrict__ vd
   const int di = find_desc(vd, nd, (int)blockIdx.x, &VDesc::blk0);
   const VDesc &v = vd[di];
   if (!active[v.inst]) return;
-  double hk[BMAXK], nrm = 0.0;
-#pragma unroll
-  for (int k = 0; k < BMAXK; ++k) hk[k] = (k < nk) ? hb[(size_t)v.inst * HS + hslot + k] : 0.0;
-  for (long i = (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x; i < v.n; i += (long)v.nblk * BBS) {
-    double s = w[v.off + i];
-#pragma unroll
-    for (int k = 0; k < BMAXK; ++k)
-      if (k < nk) s -= hk[k] * V[(size_t)k * ldv + v.off + i];
-    vout[v.off + i] = s;
-    nrm += s * s;
-  }
-  bblock_store(hk, 0, part, gridDim.x, nrm, true);
+  double hk[NKP], nrm = 0.0;
+  mv_coefs<NKP>(hb + (size_t)v.inst * HS + hslot, nk, hk);
+  mv_axpy<NKP, false>(V + v.off, ldv, nk, hk, w + v.off, vout + v.off,
+                      (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x, v.n, (long)v.nblk * BBS, hk, nrm);
+  mv_block_store<NKP>(hk, 0, nrm, true, part, gridDim.x, blockIdx.x);
 }
 
 // hb[inst*HS + hslot + k] = sum of instance inst's partials of slot k
@@ -340,7 +297,8 @@ __global__ __launch_bounds__(BBS) void kb_scale(const VDesc *__restrict__ vd, in
     v[d.off + i] *= a;
 }
 
-// x_i <- x_i + Z_i y_i (y per instance, nk_i columns; nk_i = 0 skips)
+// x_i <- x_i + Z_i y_i (y per instance, nk_i <= NKP columns; nk_i = 0 skips)
+template <int NKP>
 __global__ __launch_bounds__(BBS) void kb_update(const VDesc *__restrict__ vd, int nd,
                                                  const double *__restrict__ Z, long ldz,
                                                  const double *__restrict__ y,
@@ -349,16 +307,10 @@ __global__ __launch_bounds__(BBS) void kb_update(const VDesc *__restrict__ vd, i
   const VDesc &d = vd[di];
   const int nk = nks[d.inst];
   if (nk == 0) return;
-  double yk[BMAXK];
-#pragma unroll
-  for (int k = 0; k < BMAXK; ++k) yk[k] = (k < nk) ? y[(size_t)d.inst * BMAXK + k] : 0.0;
-  for (long i = (long)(blockIdx.x - d.blk0) * BBS + threadIdx.x; i < d.n; i += (long)d.nblk * BBS) {
-    double s = x[d.off + i];
-#pragma unroll
-    for (int k = 0; k < BMAXK; ++k)
-      if (k < nk) s += yk[k] * Z[(size_t)k * ldz + d.off + i];
-    x[d.off + i] = s;
-  }
+  double yk[NKP];
+  mv_coefs<NKP>(y + (size_t)d.inst * BMAXK, nk, yk);
+  mv_update<NKP>(Z + d.off, ldz, nk, yk, x + d.off, (long)(blockIdx.x - d.blk0) * BBS + threadIdx.x,
+                 d.n, (long)d.nblk * BBS);
 }
 
 }  // namespace
@@ -524,11 +476,12 @@ void arnoldi_step_b(dpp_batch B, int j, bool fp32, hipStream_t s) {
   precond_b<D>(B, V + (size_t)j * n, Z + (size_t)j * n, fp32, s);
   spmv_b<D>(B, Z + (size_t)j * n, nullptr, w, s);
   const int nk = j + 1;
-  kb_mdot<<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, nk, w, part);
+  DPP_NK_SWITCH(nk, kb_mdot<NKP><<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, nk, w, part));
   kb_finish<<<dim3(nk, nvd), BBS, 0, s>>>(vd, act, part, tb, hb, 0);
-  kb_axpy_mdot<<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, nk, hb, 0, w, part);
+  DPP_NK_SWITCH(nk, kb_axpy_mdot<NKP><<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, nk, hb, 0, w, part));
   kb_finish<<<dim3(nk + 1, nvd), BBS, 0, s>>>(vd, act, part, tb, hb, BMAXK + 1);
-  kb_axpy_norm<<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, nk, hb, BMAXK + 1, w, V + (size_t)(j + 1) * n, part);
+  DPP_NK_SWITCH(nk, kb_axpy_norm<NKP><<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, nk, hb, BMAXK + 1, w,
+                                                         V + (size_t)(j + 1) * n, part));
   kb_finish<<<dim3(1, nvd), BBS, 0, s>>>(vd, act, part, tb, hb, 2 * BMAXK + 3);
   kb_scale<<<tb, BBS, 0, s>>>(vd, nvd, act, V + (size_t)(j + 1) * n, hb, 2 * BMAXK + 3, nullptr);
   check_launch("batched arnoldi");
@@ -537,7 +490,7 @@ void arnoldi_step_b(dpp_batch B, int j, bool fp32, hipStream_t s) {
 // per-instance sums of squares of v (into hb slot `slot`), copied to host
 void norms_b(dpp_batch B, const double *v, int slot, std::vector<double> &out, hipStream_t s) {
   const int tb = B->vd.blocks;
-  kb_mdot<<<tb, BBS, 0, s>>>(B->vd.get(), B->vd.count, B->active.as<int>(), v, 0, 1, v, B->part.as<double>());
+  kb_mdot<1><<<tb, BBS, 0, s>>>(B->vd.get(), B->vd.count, B->active.as<int>(), v, 0, 1, v, B->part.as<double>());
   kb_finish<<<dim3(1, B->vd.count), BBS, 0, s>>>(B->vd.get(), B->active.as<int>(), B->part.as<double>(), tb,
                                                  B->hb.as<double>(), slot);
   check_launch("batched norms");
@@ -610,7 +563,7 @@ void batch_setup(dpp_batch B, hipStream_t s) {
     k.blk0 = kb;
     k.nblk = blocks_for(P->g.N, 256);
     kb += k.nblk;
-    k.kv = P->kvals.ptr;
+    k.kv = P->kh.ptr;
     k.dinv = P->dinv.as<double>();
     k.off = B->doff[i];
     k.rhat = L0.b.ptr;
@@ -837,8 +790,10 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
     }
     DPP_HIP(hipMemcpyAsync(B->ydev.ptr, y.data(), sizeof(double) * y.size(), hipMemcpyHostToDevice, s));
     DPP_HIP(hipMemcpyAsync(B->nks.ptr, nk.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
-    kb_update<<<B->vd.blocks, BBS, 0, s>>>(B->vd.get(), B->vd.count, B->Z.as<double>(), n,
-                                           B->ydev.as<double>(), B->nks.as<int>(), x);
+    const int nkmax = *std::max_element(nk.begin(), nk.end());
+    if (nkmax > 0)
+      DPP_NK_SWITCH(nkmax, kb_update<NKP><<<B->vd.blocks, BBS, 0, s>>>(B->vd.get(), B->vd.count, B->Z.as<double>(), n,
+                                                                      B->ydev.as<double>(), B->nks.as<int>(), x));
     check_launch("batched update");
     bool progress = false;
     for (int i = 0; i < nb; ++i)

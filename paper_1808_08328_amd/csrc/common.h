@@ -180,6 +180,42 @@ __host__ __device__ constexpr int kv_pu(int dim, int net, int c) {
 __host__ __device__ constexpr int kv_pp(int dim, int net) { return net * (2 * dim + 2) + 1 + 2 * dim; }
 __host__ __device__ constexpr int kv_12(int dim) { return 4 * dim + 4; }
 
+// Half storage of K used by the hot kernels.  D K is symmetric (D = diag(I_u,
+// -I_p)): K_uu^i, K_pp^i and K12 are symmetric and K_pu^i = -(K_up^i)^T.  So
+// per node a it keeps
+//   sym kinds (kuu0, kuu1, kpp0, kpp1, k12) for the zero offset and the
+//     positive half of St (t >= s0; NH = NS - s0 offsets), stream
+//     sym(kind, t - s0);
+//   kup^i[c] for every offset t of St, stream up(i, c, t);
+// and reads the rest from the neighbour's row: for t < s0 the sym value of
+// (a, a + o_t) is the one stored at a + o_t for the mirrored offset, and
+// K_pu^i(a, (a + o_t, c)) = -kup^i[c] stored at a + o_t for the mirror of t.
+// St is sorted by linear offset and symmetric, so the mirror of t is NS-1-t.
+// Stream s of a node is kh[s * ld + a].  130 of the 255 streams in 3D.
+template <int D>
+struct KH {
+  static constexpr int NS = D == 3 ? 15 : 7;
+  static constexpr int S0 = (NS - 1) / 2;
+  static constexpr int NH = NS - S0;
+  static constexpr int NSYM = 5;
+  static constexpr int streams = NSYM * NH + 2 * D * NS;
+  // sym kind ids
+  static constexpr int UU0 = 0, UU1 = 1, PP0 = 2, PP1 = 3, K12 = 4;
+  __host__ __device__ static constexpr int sym(int kind, int h) { return kind * NH + h; }
+  __host__ __device__ static constexpr int up(int net, int c, int t) {
+    return NSYM * NH + (net * D + c) * NS + t;
+  }
+};
+
+template <int D>
+constexpr bool kh_layout_ok() {
+  for (int t = 0; t < KH<D>::NS; ++t)
+    for (int a = 0; a < 3; ++a)
+      if (TAB<D>.so[KH<D>::NS - 1 - t][a] != -TAB<D>.so[t][a]) return false;
+  return TAB<D>.s0 == KH<D>::S0 && Tabs<D>::NS == KH<D>::NS;
+}
+static_assert(kh_layout_ok<2>() && kh_layout_ok<3>(), "St must be symmetric and sorted");
+
 // Field offsets of the ABI vector layout [u1 | p1 | u2 | p2].
 __host__ __device__ inline long off_u(int dim, long N, int net) {
   return net ? (long)(dim + 1) * N : 0;

@@ -1,7 +1,9 @@
 // Library objects behind the opaque ABI handles and the cross-file launchers.
 #pragma once
 
+#include <map>
 #include <memory>
+#include <tuple>
 
 #include "common.h"
 
@@ -57,8 +59,9 @@ struct dpp_problem_s {
   double beta = 0.0;
   int ns = 0;           // K stencil size
   long nnz = 0;         // structural nonzeros of K in CSR terms
-  dpp::DBuf kvals;      // [nv][ns][N] FP64
-  dpp::DBuf kvals32;    // FP32 copy (mixed precision), made on demand
+  dpp::DBuf kvals;      // [nv][ns][N] FP64, every kind on every offset (assembly, selfp, export)
+  dpp::DBuf kh;         // half storage (layout KH<dim>) read by the hot kernels
+  dpp::DBuf kh32;       // FP32 copy of kh (mixed precision), made on demand
   dpp::DBuf f;          // [n_dof]
   dpp::DBuf dinv;       // [2][N] 1/diag(K_uu^i)
   dpp::DBuf k1, k2, betac;  // coefficient copies [n_cells] for the gradient
@@ -103,6 +106,23 @@ struct dpp_precond_s {
   // Krylov workspace, kept across solves
   int ws_m = 0;
   dpp::DBuf V, Z, w, part, hdev, ydev, xtmp, rtmp;
+  // Arnoldi steps captured as graphs, keyed by (step j, mode, Chebyshev
+  // degree); they hold the workspace pointers above, so any reallocation or
+  // change of a level's kernel shape drops them.
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+  hipStream_t gstream = nullptr;  // capture/replay stream (default priority)
+  double *hpin = nullptr;         // pinned host copy of one step's reductions
+  hipEvent_t hev = nullptr;       // marks that copy
+  void drop_graphs() {
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+    graphs.clear();
+  }
+  ~dpp_precond_s() {
+    drop_graphs();
+    if (gstream) (void)hipStreamDestroy(gstream);
+    if (hev) (void)hipEventDestroy(hev);
+    if (hpin) (void)hipHostFree(hpin);
+  }
 };
 
 namespace dpp {
@@ -119,6 +139,7 @@ void residual_K(dpp_problem P, const double *b, const double *x, double *r, hipS
 void spmv_block(dpp_problem P, int which, const double *x, double *y, hipStream_t s);
 void make_dinv(dpp_problem P, hipStream_t s);
 void make_selfp(dpp_problem P, double *S, hipStream_t s);
+void make_kh(dpp_problem P, hipStream_t s);
 void make_k32(dpp_problem P, hipStream_t s);
 // Schur fieldsplit pieces: rhat_i = r_p_i - K_pu^i diag^-1 r_u_i ; z_u = diag^-1 (r_u - K_up z_p)
 void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_t s);

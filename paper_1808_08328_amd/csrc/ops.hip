@@ -1,11 +1,13 @@
-// Operators on the unknown vector [u1 | p1 | u2 | p2]: y = K x from the
-// node-pair stencil storage, residuals, the block views K_up^i / K_pu^i, the
-// selfp Schur blocks and the two velocity-side steps of the Schur fieldsplit.
+// Operators on the unknown vector [u1 | p1 | u2 | p2]: y = K x, residuals,
+// the block views K_up^i / K_pu^i, the selfp Schur blocks and the two
+// velocity-side steps of the Schur fieldsplit.
 //
-// The K product is bandwidth bound (about 0.2 flop per byte): one thread per
-// node reads the 4d+5 value streams of every stencil offset (coalesced,
-// structure-of-arrays) and the 2d+2 unknowns of each neighbour, which are
-// contiguous in node order and mostly served from L2.
+// The K product is bandwidth bound (about 0.2 flop per byte).  It reads the
+// half storage of K (the symmetric kinds on the zero offset and the positive
+// half of the stencil, kup on every offset; structure-of-arrays, coalesced)
+// and takes the other half from the neighbours' rows, which are at most one
+// node plane away and mostly served from L2.  Assembly, selfp and the CSR
+// export read the full node-pair storage.
 #include "objects.h"
 #include "profile.h"
 #include "stencil.h"
@@ -78,6 +80,32 @@ __global__ void k_dinv(GridDev g, const double *__restrict__ kv, double *__restr
   const size_t vs = (size_t)NS * g.ld;
   const int t0 = TAB<D>.s0;
   for (int q = 0; q < 2; ++q) dinv[q * N + a] = 1.0 / kv[kv_uu(D, q) * vs + (size_t)t0 * g.ld + a];
+}
+
+// Half storage of K (layout KH<D>) from the full node-pair storage.  One
+// thread per (stream, node).
+template <int D>
+__global__ void k_pack_kh(GridDev g, const double *__restrict__ kv, double *__restrict__ kh) {
+  using L = KH<D>;
+  const long N = g.N;
+  const size_t ld = g.ld, vs = (size_t)L::NS * ld;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)L::streams * N) return;
+  const int st = (int)(idx / N);
+  const long a = idx - (long)st * N;
+  int kind, t;
+  if (st < L::NSYM * L::NH) {
+    const int k = st / L::NH;
+    t = st % L::NH + L::S0;
+    kind = k == L::UU0 ? kv_uu(D, 0) : k == L::UU1 ? kv_uu(D, 1) : k == L::PP0 ? kv_pp(D, 0)
+         : k == L::PP1 ? kv_pp(D, 1) : kv_12(D);
+  } else {
+    const int r = st - L::NSYM * L::NH;
+    const int qc = r / L::NS;
+    t = r % L::NS;
+    kind = kv_up(D, qc / D, qc % D);
+  }
+  kh[(size_t)st * ld + a] = kv[kind * vs + (size_t)t * ld + a];
 }
 
 // selfp Schur block (eqs. S4_sp1, S4_sp2):
@@ -159,10 +187,14 @@ __global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, si
 
 }  // namespace
 
+// Algorithmic bytes of y = K x (or r = b - K x) from the half storage: the
+// stored own-row values (kup on every in-box St pair, the five symmetric
+// kinds on the zero offset and the positive half) once, and the vectors.
 static double kbytes(const Grid &g, bool fp32, bool resid) {
   const double pairs = g.dim == 3 ? valid_pairs<3, false>(g) : valid_pairs<2, false>(g);
+  const double half = 0.5 * (pairs + g.N);
   const double nd = (2.0 * g.dim + 2.0) * g.N;
-  return pairs * nv_kinds(g.dim) * (fp32 ? 4.0 : 8.0) + nd * 8.0 * (resid ? 3.0 : 2.0);
+  return (pairs * 2.0 * g.dim + half * 5.0) * (fp32 ? 4.0 : 8.0) + nd * 8.0 * (resid ? 3.0 : 2.0);
 }
 
 void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32) {
@@ -171,14 +203,14 @@ void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32)
   ProfScope ps(PF_SPMV_K, kbytes(g, fp32, false), s);
   if (g.dim == 3) {
     if (fp32)
-      k_spmv_K<3, float><<<nb, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), x, nullptr, y);
+      k_spmv_K<3, float><<<nb, 256, 0, s>>>(dev(g), P->kh32.as<float>(), x, nullptr, y);
     else
-      k_spmv_K<3, double><<<nb, 256, 0, s>>>(dev(g), P->kvals.as<double>(), x, nullptr, y);
+      k_spmv_K<3, double><<<nb, 256, 0, s>>>(dev(g), P->kh.as<double>(), x, nullptr, y);
   } else {
     if (fp32)
-      k_spmv_K<2, float><<<nb, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), x, nullptr, y);
+      k_spmv_K<2, float><<<nb, 256, 0, s>>>(dev(g), P->kh32.as<float>(), x, nullptr, y);
     else
-      k_spmv_K<2, double><<<nb, 256, 0, s>>>(dev(g), P->kvals.as<double>(), x, nullptr, y);
+      k_spmv_K<2, double><<<nb, 256, 0, s>>>(dev(g), P->kh.as<double>(), x, nullptr, y);
   }
   check_launch("spmv_K");
 }
@@ -190,14 +222,14 @@ void residual_K(dpp_problem P, const double *b, const double *x, double *r, hipS
   ProfScope ps(PF_SPMV_K, kbytes(g, fp32, true), s);
   if (g.dim == 3) {
     if (fp32)
-      k_spmv_K<3, float><<<nb, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), x, b, r);
+      k_spmv_K<3, float><<<nb, 256, 0, s>>>(dev(g), P->kh32.as<float>(), x, b, r);
     else
-      k_spmv_K<3, double><<<nb, 256, 0, s>>>(dev(g), P->kvals.as<double>(), x, b, r);
+      k_spmv_K<3, double><<<nb, 256, 0, s>>>(dev(g), P->kh.as<double>(), x, b, r);
   } else {
     if (fp32)
-      k_spmv_K<2, float><<<nb, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), x, b, r);
+      k_spmv_K<2, float><<<nb, 256, 0, s>>>(dev(g), P->kh32.as<float>(), x, b, r);
     else
-      k_spmv_K<2, double><<<nb, 256, 0, s>>>(dev(g), P->kvals.as<double>(), x, b, r);
+      k_spmv_K<2, double><<<nb, 256, 0, s>>>(dev(g), P->kh.as<double>(), x, b, r);
   }
   check_launch("residual_K");
 }
@@ -232,11 +264,23 @@ void make_selfp(dpp_problem P, double *S, hipStream_t s) {
   check_launch("selfp");
 }
 
+void make_kh(dpp_problem P, hipStream_t s) {
+  const Grid &g = P->g;
+  const int streams = g.dim == 3 ? KH<3>::streams : KH<2>::streams;
+  P->kh.alloc(sizeof(double) * (size_t)streams * padded(g.N));
+  const long work = (long)streams * g.N;
+  if (g.dim == 3)
+    k_pack_kh<3><<<blocks_for(work, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->kh.as<double>());
+  else
+    k_pack_kh<2><<<blocks_for(work, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->kh.as<double>());
+  check_launch("pack K half storage");
+}
+
 void make_k32(dpp_problem P, hipStream_t s) {
-  if (P->kvals32.ptr) return;
-  size_t n = P->kvals.bytes / sizeof(double);
-  P->kvals32.alloc(n * sizeof(float));
-  k_to_f32<<<2048, 256, 0, s>>>(P->kvals.as<double>(), P->kvals32.as<float>(), n);
+  if (P->kh32.ptr) return;
+  size_t n = P->kh.bytes / sizeof(double);
+  P->kh32.alloc(n * sizeof(float));
+  k_to_f32<<<2048, 256, 0, s>>>(P->kh.as<double>(), P->kh32.as<float>(), n);
   check_launch("k32");
 }
 
@@ -250,14 +294,14 @@ void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_
   const double *di = P->dinv.as<double>();
   if (g.dim == 3) {
     if (fp32)
-      k_schur_rhs<3, float, float><<<grid, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), di, r, (float *)rhat);
+      k_schur_rhs<3, float, float><<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (float *)rhat);
     else
-      k_schur_rhs<3, double, double><<<grid, 256, 0, s>>>(dev(g), P->kvals.as<double>(), di, r, (double *)rhat);
+      k_schur_rhs<3, double, double><<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (double *)rhat);
   } else {
     if (fp32)
-      k_schur_rhs<2, float, float><<<grid, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), di, r, (float *)rhat);
+      k_schur_rhs<2, float, float><<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (float *)rhat);
     else
-      k_schur_rhs<2, double, double><<<grid, 256, 0, s>>>(dev(g), P->kvals.as<double>(), di, r, (double *)rhat);
+      k_schur_rhs<2, double, double><<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (double *)rhat);
   }
   check_launch("schur_rhs");
 }
@@ -273,14 +317,14 @@ void schur_velocity(dpp_problem P, const double *r, const void *zp, bool fp32, d
   const double *di = P->dinv.as<double>();
   if (g.dim == 3) {
     if (fp32)
-      k_schur_vel<3, float, float><<<grid, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), di, r, (const float *)zp, z);
+      k_schur_vel<3, float, float><<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (const float *)zp, z);
     else
-      k_schur_vel<3, double, double><<<grid, 256, 0, s>>>(dev(g), P->kvals.as<double>(), di, r, (const double *)zp, z);
+      k_schur_vel<3, double, double><<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (const double *)zp, z);
   } else {
     if (fp32)
-      k_schur_vel<2, float, float><<<grid, 256, 0, s>>>(dev(g), P->kvals32.as<float>(), di, r, (const float *)zp, z);
+      k_schur_vel<2, float, float><<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (const float *)zp, z);
     else
-      k_schur_vel<2, double, double><<<grid, 256, 0, s>>>(dev(g), P->kvals.as<double>(), di, r, (const double *)zp, z);
+      k_schur_vel<2, double, double><<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (const double *)zp, z);
   }
   check_launch("schur_velocity");
 }

@@ -92,100 +92,141 @@ constexpr int stored_offsets() {
 // (distinct kernel names in profiles); the code is the same.
 
 // y for the 2d+2 unknowns of node a: au[i][c] (velocity rows), ap[i]
-// (pressure rows), from the node-pair stencil storage of K.  Out-of-box pairs
-// hold zeros, so the neighbour index is clamped instead of guarded (all loads
-// of an offset can be in flight together).
+// (pressure rows), from the half storage kh of K.
+//
+// One trip per stored offset o = o_{s0+h} (h = 0 .. NH-1) covers the pairs
+// (a, a + o) and (a, a - o).  The values of (a, a - o) are the ones node
+// a - o stores for +o, and K_pu(a, (a +- o, c)) = -kup[c] stored at a +- o for
+// -+o: every value read from a neighbour's row is one that the neighbour reads
+// as its own in the same trip, so with all waves in step those reads hit L2.
+// Own-row values of pairs that leave the box are stored zeros (the neighbour
+// index is clamped, not guarded); neighbour-row values are masked when the
+// neighbour's linear index falls outside [0, N) (a wrapped index inside
+// [0, N) reads a pair that leaves the box from that node, a stored zero).
 template <int D, typename TV>
-__device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kv,
+__device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
                                    const double *__restrict__ x, long a, double au[2][D],
                                    double ap[2]) {
-  constexpr int NS = Tabs<D>::NS;
+  using L = KH<D>;
   const long N = g.N;
+  const size_t ld = g.ld;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     ap[q] = 0.0;
 #pragma unroll
     for (int c = 0; c < D; ++c) au[q][c] = 0.0;
   }
-  const size_t vs = (size_t)NS * g.ld;
-  const long ou0 = off_u(D, N, 0), ou1 = off_u(D, N, 1), op0 = off_p(D, N, 0),
-             op1 = off_p(D, N, 1);
-  // one offset per trip: its 4d+5 value streams and 2d+2 neighbour unknowns
-  // are loaded together
+  const long ou[2] = {off_u(D, N, 0), off_u(D, N, 1)};
+  const long op[2] = {off_p(D, N, 0), off_p(D, N, 1)};
 #pragma unroll 1
-  for (int t = 0; t < NS; ++t) {
-    const int *o = TAB<D>.so[t];
-    const long b = min(max(a + lin(g, o[0], o[1], o[2]), 0L), N - 1);
-    double xu[2][D], xp[2];
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      xu[0][c] = x[ou0 + D * b + c];
-      xu[1][c] = x[ou1 + D * b + c];
-    }
-    xp[0] = x[op0 + b];
-    xp[1] = x[op1 + b];
-    const TV *base = kv + (size_t)t * g.ld + a;
+  for (int h = 0; h < L::NH; ++h) {
+    const int tp = L::S0 + h, tn = L::S0 - h;
+    const int *o = TAB<D>.so[tp];
+    const long lo = lin(g, o[0], o[1], o[2]);
+    const long bp = min(a + lo, N - 1);     // a + o (own-row values guard it)
+    const long bnr = a - lo;
+    const long bn = max(bnr, 0L);           // a - o
+    const double mp = (a + lo < N) ? 1.0 : 0.0, mn = (bnr >= 0) ? 1.0 : 0.0;
+    // pair (a, a + o): symmetric kinds own, kup own at tp, kup of a + o at tn
+    double xu[D], xp[2], xo[2];
+    // symmetric kinds
+    const double uu0 = (double)kh[L::sym(L::UU0, h) * ld + a];
+    const double uu1 = (double)kh[L::sym(L::UU1, h) * ld + a];
+    const double pp0 = (double)kh[L::sym(L::PP0, h) * ld + a];
+    const double pp1 = (double)kh[L::sym(L::PP1, h) * ld + a];
+    const double s12 = (double)kh[L::sym(L::K12, h) * ld + a];
+    xp[0] = x[op[0] + bp];
+    xp[1] = x[op[1] + bp];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const double uu = (double)base[kv_uu(D, q) * vs];
+#pragma unroll
+      for (int c = 0; c < D; ++c) xu[c] = x[ou[q] + D * bp + c];
+      const double uu = q ? uu1 : uu0, pp = q ? pp1 : pp0;
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        const double up = (double)base[kv_up(D, q, c) * vs];
-        const double pu = (double)base[kv_pu(D, q, c) * vs];
-        au[q][c] += uu * xu[q][c] + up * xp[q];
-        ap[q] += pu * xu[q][c];
+        const double up = (double)kh[L::up(q, c, tp) * ld + a];
+        const double pu = -mp * (double)kh[L::up(q, c, tn) * ld + bp];
+        au[q][c] += uu * xu[c] + up * xp[q];
+        ap[q] += pu * xu[c];
       }
-      ap[q] += (double)base[kv_pp(D, q) * vs] * xp[q];
+      ap[q] += pp * xp[q];
     }
-    const double k12 = (double)base[kv_12(D) * vs];
-    ap[0] += k12 * xp[1];
-    ap[1] += k12 * xp[0];
+    ap[0] += s12 * xp[1];
+    ap[1] += s12 * xp[0];
+    if (h == 0) continue;  // the zero offset has no mirror pair
+    // pair (a, a - o): symmetric kinds stored at a - o, kup own at tn, kup of a - o at tp
+    const double vuu0 = mn * (double)kh[L::sym(L::UU0, h) * ld + bn];
+    const double vuu1 = mn * (double)kh[L::sym(L::UU1, h) * ld + bn];
+    const double vpp0 = mn * (double)kh[L::sym(L::PP0, h) * ld + bn];
+    const double vpp1 = mn * (double)kh[L::sym(L::PP1, h) * ld + bn];
+    const double v12 = mn * (double)kh[L::sym(L::K12, h) * ld + bn];
+    xo[0] = x[op[0] + bn];
+    xo[1] = x[op[1] + bn];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) xu[c] = x[ou[q] + D * bn + c];
+      const double uu = q ? vuu1 : vuu0, pp = q ? vpp1 : vpp0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double up = (double)kh[L::up(q, c, tn) * ld + a];
+        const double pu = -mn * (double)kh[L::up(q, c, tp) * ld + bn];
+        au[q][c] += uu * xu[c] + up * xo[q];
+        ap[q] += pu * xu[c];
+      }
+      ap[q] += pp * xo[q];
+    }
+    ap[0] += v12 * xo[1];
+    ap[1] += v12 * xo[0];
   }
 }
 
 // rhat_i(b) = r_p_i(b) - sum_t sum_c K_pu^i(b, (b+o_t, c)) dinv_i(b+o_t) r_u_i(b+o_t, c)
+// with K_pu^i(b, (a, c)) = -kup^i[c] stored at a = b + o_t for the mirror of t.
 template <int D, typename TV>
-__device__ inline double schur_rhs_node(const GridDev &g, const TV *__restrict__ kv,
+__device__ inline double schur_rhs_node(const GridDev &g, const TV *__restrict__ kh,
                                         const double *__restrict__ dinv,
                                         const double *__restrict__ r, int q, long b) {
-  constexpr int NS = Tabs<D>::NS;
+  using L = KH<D>;
   const long N = g.N;
-  const size_t vs = (size_t)NS * g.ld;
+  const size_t ld = g.ld;
   const long ou = off_u(D, N, q);
   double acc = r[off_p(D, N, q) + b];
-#pragma unroll
-  for (int t = 0; t < NS; ++t) {
+  // offsets in unrolled groups of 5 (loads of a group in flight together)
+#pragma unroll 5
+  for (int t = 0; t < L::NS; ++t) {
     const int *o = TAB<D>.so[t];
-    const long a = min(max(b + lin(g, o[0], o[1], o[2]), 0L), N - 1);
-    const double di = dinv[q * N + a];
+    const long araw = b + lin(g, o[0], o[1], o[2]);
+    const long a = min(max(araw, 0L), N - 1);
+    const double di = (araw == a) ? dinv[q * N + a] : 0.0;
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < D; ++c)
-      s += (double)kv[kv_pu(D, q, c) * vs + (size_t)t * g.ld + b] * r[ou + D * a + c];
-    acc -= s * di;
+      s += (double)kh[L::up(q, c, L::NS - 1 - t) * ld + a] * r[ou + D * a + c];
+    acc += s * di;
   }
   return acc;
 }
 
 // z_u_i(a, c) = dinv_i(a) (r_u_i(a, c) - sum_t K_up^i((a,c), a+o_t) z_p_i(a+o_t))
 template <int D, typename TV, typename TX>
-__device__ inline void schur_vel_node(const GridDev &g, const TV *__restrict__ kv,
+__device__ inline void schur_vel_node(const GridDev &g, const TV *__restrict__ kh,
                                       const double *__restrict__ dinv,
                                       const double *__restrict__ r, const TX *__restrict__ zp,
                                       int q, long a, double out[D]) {
-  constexpr int NS = Tabs<D>::NS;
+  using L = KH<D>;
   const long N = g.N;
-  const size_t vs = (size_t)NS * g.ld;
+  const size_t ld = g.ld;
   const long ou = off_u(D, N, q);
 #pragma unroll
   for (int c = 0; c < D; ++c) out[c] = r[ou + D * a + c];
 #pragma unroll
-  for (int t = 0; t < NS; ++t) {
+  for (int t = 0; t < L::NS; ++t) {
     const int *o = TAB<D>.so[t];
     const long b = min(max(a + lin(g, o[0], o[1], o[2]), 0L), N - 1);
     const double zb = (double)zp[q * N + b];
 #pragma unroll
-    for (int c = 0; c < D; ++c) out[c] -= (double)kv[kv_up(D, q, c) * vs + (size_t)t * g.ld + a] * zb;
+    for (int c = 0; c < D; ++c) out[c] -= (double)kh[L::up(q, c, t) * ld + a] * zb;
   }
   const double di = dinv[q * N + a];
 #pragma unroll

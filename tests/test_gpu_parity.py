@@ -177,6 +177,28 @@ def test_iteration_count_in_paper_band_and_deterministic():
     assert torch.equal(x1, x2) and s1.iters == s2.iters
 
 
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_graph_replay_matches_eager_solve(precision):
+    """Arnoldi steps replayed from captured graphs give the eager solve bit
+    for bit, on every replay, with eager work and host waits in between and
+    after a kernel-shape change (which drops the captured graphs)."""
+    prob = I.mms_problem(3, 12, k1=1.0, k2=1e-2)
+    P = lib().assemble_problem(prob)
+    pc = P.setup_precond(coarse_max=60)
+    xe, se = P.solve(pc, rtol=1e-10, precision=precision)
+    for rep in range(3):
+        xg, sg = P.solve(pc, rtol=1e-10, precision=precision, use_graph=1)
+        assert torch.equal(xg, xe) and sg.iters == se.iters, rep
+        y = P.spmv(xg)  # eager work between replays
+        torch.cuda.synchronize()
+        del y
+    lanes, sym = pc.shape(0)
+    pc.set_shape(0, 2 if lanes != 2 else 4, sym)
+    xe2, se2 = P.solve(pc, rtol=1e-10, precision=precision)
+    xg2, sg2 = P.solve(pc, rtol=1e-10, precision=precision, use_graph=1)
+    assert torch.equal(xg2, xe2) and sg2.iters == se2.iters
+
+
 @pytest.mark.parametrize("precision", [1, 2])
 def test_mixed_precision_matches_oracle(precision):
     prob = I.grf_problem(3, 8)
