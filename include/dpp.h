@@ -162,9 +162,10 @@ dpp_status dpp_setup_precond(dpp_problem prob, const dpp_solve_opts *opts, void 
 dpp_status dpp_precond_info(dpp_precond pc, int *n_levels, int *level_n, double *hi);
 
 /* Kernel shape of multigrid level `level` (the autotuner's choice): lanes per
- * stencil row (1, 2, 4, 8) and whether the symmetric half of the stencil is
- * stored (1) or the full stencil (0).  dpp_precond_set_shape overrides it
- * (for tests and tuning studies; the values must be one of those listed). */
+ * stencil row (1, 2, 4, 8, or 0 for two rows per lane with paired 16-byte
+ * loads) and whether the symmetric half of the stencil is stored (1) or the
+ * full stencil (0).  dpp_precond_set_shape overrides it (for tests and tuning
+ * studies; the values must be one of those listed). */
 dpp_status dpp_precond_shape(dpp_precond pc, int level, int *lanes, int *sym);
 dpp_status dpp_precond_set_shape(dpp_precond pc, int level, int lanes, int sym);
 

@@ -182,7 +182,8 @@ dpp_status dpp_precond_set_shape(dpp_precond pc, int level, int lanes, int sym) 
     DPP_CHECK(pc, DPP_ERR_ARG, "null preconditioner");
     DPP_CHECK(level >= 0 && level + 1 < (int)pc->lv.size(), DPP_ERR_ARG,
               "level out of range (the coarsest level has no stencil kernels)");
-    DPP_CHECK(lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8, DPP_ERR_ARG, "lanes must be 1, 2, 4 or 8");
+    DPP_CHECK(lanes == 0 || lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8, DPP_ERR_ARG,
+              "lanes must be 0 (two rows per lane), 1, 2, 4 or 8");
     DPP_CHECK(sym == 0 || sym == 1, DPP_ERR_ARG, "sym must be 0 or 1");
     pc->lv[level]->shape.lpr = lanes;
     pc->lv[level]->shape.sym = sym != 0;

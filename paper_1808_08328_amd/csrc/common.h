@@ -191,7 +191,10 @@ __host__ __device__ constexpr int kv_12(int dim) { return 4 * dim + 4; }
 // (a, a + o_t) is the one stored at a + o_t for the mirrored offset, and
 // K_pu^i(a, (a + o_t, c)) = -kup^i[c] stored at a + o_t for the mirror of t.
 // St is sorted by linear offset and symmetric, so the mirror of t is NS-1-t.
-// Stream s of a node is kh[s * ld + a].  130 of the 255 streams in 3D.
+// 130 of the 255 streams in 3D.  The storage is sliced: the values of 64
+// consecutive nodes form one run per stream and the runs of all streams of a
+// slice are contiguous, so a wave reads one contiguous block of DRAM pages
+// instead of one page per stream (and node pairs 2i, 2i + 1 stay adjacent).
 template <int D>
 struct KH {
   static constexpr int NS = D == 3 ? 15 : 7;
@@ -204,6 +207,14 @@ struct KH {
   __host__ __device__ static constexpr int sym(int kind, int h) { return kind * NH + h; }
   __host__ __device__ static constexpr int up(int net, int c, int t) {
     return NSYM * NH + (net * D + c) * NS + t;
+  }
+  static constexpr int SLICE = 64;
+  // element of stream s at node a
+  __host__ __device__ static size_t at(int s, long a) {
+    return ((size_t)(a / SLICE) * streams + s) * SLICE + (size_t)(a % SLICE);
+  }
+  __host__ __device__ static size_t size(long N) {
+    return (size_t)((N + SLICE - 1) / SLICE) * streams * SLICE;
   }
 };
 

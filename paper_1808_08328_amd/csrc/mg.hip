@@ -40,13 +40,41 @@ __global__ __launch_bounds__(256, 4) void k_lspmv(GridDev g, const TV *__restric
   const long N = g.N;
   const int q = blockIdx.y;
   const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const long a = gid / LPR;
-  const int sub = (int)(gid % LPR);
+  constexpr int NA = stored_offsets<D, SYM>();
+  if constexpr (LPR == 0) {
+    // rows a, a + 1 per thread (paired loads)
+    const long a = 2 * gid;
+    if (a >= N) return;
+    double r0, r1;
+    row_product2<D, TV, TX, SYM>(g, A + (size_t)q * NA * g.ld, x + (size_t)q * N, a, r0, r1);
+    const size_t ia = (size_t)q * N + a;
+    if (a + 1 < N) {
+      if (b) {
+        TX b0, b1;
+        ld2(b + ia, b0, b1);
+        r0 = (double)b0 - r0;
+        r1 = (double)b1 - r1;
+      }
+      if (dinv) {
+        TV d0, d1;
+        ld2(dinv + ia, d0, d1);
+        r0 *= (double)d0;
+        r1 *= (double)d1;
+      }
+      st2(y + ia, (TX)r0, (TX)r1);
+    } else {
+      if (b) r0 = (double)b[ia] - r0;
+      if (dinv) r0 *= (double)dinv[ia];
+      y[ia] = (TX)r0;
+    }
+    return;
+  }
+  const long a = gid / (LPR > 0 ? LPR : 1);
+  const int sub = (int)(gid % (LPR > 0 ? LPR : 1));
   if (a >= N) return;
   int i, j, k;
   node_ijk(g, a, i, j, k);
-  constexpr int NA = stored_offsets<D, SYM>();
-  double acc = row_product<D, TV, TX, LPR, SYM>(g, A + (size_t)q * NA * g.ld, x + (size_t)q * N, a, i, j, k, sub);
+  double acc = row_product<D, TV, TX, (LPR > 0 ? LPR : 1), SYM>(g, A + (size_t)q * NA * g.ld, x + (size_t)q * N, a, i, j, k, sub);
   if (sub != 0) return;
   if (b) acc = (double)b[(size_t)q * N + a] - acc;
   if (dinv) acc *= (double)dinv[(size_t)q * N + a];
@@ -66,15 +94,43 @@ __global__ __launch_bounds__(256, 4) void k_cheb(GridDev g, const TV *__restrict
   const long N = g.N;
   const int q = blockIdx.y;
   const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const long a = gid / LPR;
-  const int sub = (int)(gid % LPR);
+  constexpr int NA = stored_offsets<D, SYM>();
+  if constexpr (LPR == 0) {
+    // rows a, a + 1 per thread (paired loads)
+    const long a = 2 * gid;
+    if (a >= N) return;
+    double ax0, ax1;
+    row_product2<D, TV, TX, SYM>(g, A + (size_t)q * NA * g.ld, xin + (size_t)q * N, a, ax0, ax1);
+    const size_t ia = (size_t)q * N + a;
+    const bool first = c1.v[q] == 0.0;
+    if (a + 1 < N) {
+      TX x0, x1, b0, b1, d0 = 0, d1 = 0;
+      TV i0, i1;
+      ld2(xin + ia, x0, x1);
+      ld2(b + ia, b0, b1);
+      ld2(dinv + ia, i0, i1);
+      if (!first) ld2(d + ia, d0, d1);
+      const double r0 = (double)i0 * ((double)b0 - ax0), r1 = (double)i1 * ((double)b1 - ax1);
+      const double n0 = (first ? 0.0 : c1.v[q] * (double)d0) + c2.v[q] * r0;
+      const double n1 = (first ? 0.0 : c1.v[q] * (double)d1) + c2.v[q] * r1;
+      st2(d + ia, (TX)n0, (TX)n1);
+      st2(xout + ia, (TX)((double)x0 + n0), (TX)((double)x1 + n1));
+    } else {
+      const double r0 = (double)dinv[ia] * ((double)b[ia] - ax0);
+      const double n0 = (first ? 0.0 : c1.v[q] * (double)d[ia]) + c2.v[q] * r0;
+      d[ia] = (TX)n0;
+      xout[ia] = (TX)((double)xin[ia] + n0);
+    }
+    return;
+  }
+  const long a = gid / (LPR > 0 ? LPR : 1);
+  const int sub = (int)(gid % (LPR > 0 ? LPR : 1));
   if (a >= N) return;
   const size_t ia = (size_t)q * N + a;
   int i, j, k;
   node_ijk(g, a, i, j, k);
-  constexpr int NA = stored_offsets<D, SYM>();
   const double ax =
-      row_product<D, TV, TX, LPR, SYM>(g, A + (size_t)q * NA * g.ld, xin + (size_t)q * N, a, i, j, k, sub);
+      row_product<D, TV, TX, (LPR > 0 ? LPR : 1), SYM>(g, A + (size_t)q * NA * g.ld, xin + (size_t)q * N, a, i, j, k, sub);
   if (sub != 0) return;
   const double xa = (double)xin[ia];
   const double r = (double)dinv[ia] * ((double)b[ia] - ax);
@@ -87,6 +143,7 @@ __global__ __launch_bounds__(256, 4) void k_cheb(GridDev g, const TV *__restrict
   do {                                                      \
     if (sh.sym) {                                           \
       switch (sh.lpr) {                                     \
+        case 0: { constexpr int L_ = 0; constexpr bool S_ = true; KCALL; } break; \
         case 1: { constexpr int L_ = 1; constexpr bool S_ = true; KCALL; } break; \
         case 2: { constexpr int L_ = 2; constexpr bool S_ = true; KCALL; } break; \
         case 4: { constexpr int L_ = 4; constexpr bool S_ = true; KCALL; } break; \
@@ -94,6 +151,7 @@ __global__ __launch_bounds__(256, 4) void k_cheb(GridDev g, const TV *__restrict
       }                                                     \
     } else {                                                \
       switch (sh.lpr) {                                     \
+        case 0: { constexpr int L_ = 0; constexpr bool S_ = false; KCALL; } break; \
         case 1: { constexpr int L_ = 1; constexpr bool S_ = false; KCALL; } break; \
         case 2: { constexpr int L_ = 2; constexpr bool S_ = false; KCALL; } break; \
         case 4: { constexpr int L_ = 4; constexpr bool S_ = false; KCALL; } break; \
@@ -102,10 +160,13 @@ __global__ __launch_bounds__(256, 4) void k_cheb(GridDev g, const TV *__restrict
     }                                                       \
   } while (0)
 
+// threads of a level launch: lpr lanes per row, or one thread per row pair (lpr = 0)
+inline long shape_threads(Shape sh, long N) { return sh.lpr > 0 ? N * sh.lpr : (N + 1) / 2; }
+
 template <int D, typename TV, typename TX>
 void launch_lspmv(Shape sh, const Grid &gl, hipStream_t s, const TV *A, const TX *x, TX *y,
                   const TX *b, const TV *dinv, bool fine = false) {
-  const dim3 grid(blocks_for(gl.N * sh.lpr, 256), 2);
+  const dim3 grid(blocks_for(shape_threads(sh, gl.N), 256), 2);
   if (fine)
     DPP_SHAPE_SWITCH(sh, (k_lspmv<D, TV, TX, L_, S_, true><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv)));
   else
@@ -115,7 +176,7 @@ void launch_lspmv(Shape sh, const Grid &gl, hipStream_t s, const TV *A, const TX
 template <int D, typename TV, typename TX>
 void launch_cheb(Shape sh, const Grid &gl, hipStream_t s, const TV *A, const TV *di, const TX *b,
                  const TX *xin, TX *xout, TX *d, Sc2 c1, Sc2 c2, bool fine) {
-  const dim3 grid(blocks_for(gl.N * sh.lpr, 256), 2);
+  const dim3 grid(blocks_for(shape_threads(sh, gl.N), 256), 2);
   if (fine)
     DPP_SHAPE_SWITCH(sh, (k_cheb<D, TV, TX, L_, S_, true><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin,
                                                                                 xout, d, c1, c2)));
@@ -160,6 +221,26 @@ __global__ __launch_bounds__(256) void k_restrict(GridDev gf, GridDev gc, const 
   const long C = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (C >= gc.N) return;
   bc[(size_t)q * gc.N + C] = (TX)restrict_node<D, TX>(gf, gc, r + (size_t)q * gf.N, C);
+}
+
+// Restriction fused with the coarse level's first Chebyshev step (which needs
+// only its own node): bc = R r, xc = dc = c2 D_c^-1 bc.
+template <int D, typename TV, typename TX>
+__global__ __launch_bounds__(256) void k_restrict_first(GridDev gf, GridDev gc,
+                                                        const TX *__restrict__ r,
+                                                        TX *__restrict__ bc,
+                                                        const TV *__restrict__ dinvc,
+                                                        TX *__restrict__ xc, TX *__restrict__ dc,
+                                                        Sc2 c2) {
+  const int q = blockIdx.y;
+  const long C = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (C >= gc.N) return;
+  const size_t ic = (size_t)q * gc.N + C;
+  const TX bv = (TX)restrict_node<D, TX>(gf, gc, r + (size_t)q * gf.N, C);
+  bc[ic] = bv;
+  const double v = c2.v[q] * (double)dinvc[ic] * (double)bv;
+  dc[ic] = (TX)v;
+  xc[ic] = (TX)v;
 }
 
 // x(f) += (P e)(f)
@@ -376,9 +457,10 @@ __global__ void k_f64_to_f32(const double *__restrict__ x, float *__restrict__ y
 constexpr int RED_BLOCKS = 512;
 
 // Autotuner for the kernel shape of the level stencil kernels (lanes per
-// row 1/2/4/8, full or symmetric-half storage): each candidate is timed with
-// HIP events on the level's own operator and the fastest wins; results are
-// cached per (dim, nodes, value bytes) for the process.
+// row 1/2/4/8 or two rows per lane, full or symmetric-half storage): each
+// candidate is timed with HIP events on the level's own operator and the
+// fastest wins; results are cached per (dim, nodes, value bytes) for the
+// process.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, long, int>, Shape> g_tune_cache;
 
@@ -399,7 +481,7 @@ Shape tune_shape(Level &L, hipStream_t s) {
   double *y = L.xb.as<double>();
   DPP_HIP(hipMemsetAsync(L.xa.ptr, 0, L.xa.bytes, s));
   for (int sym = 0; sym < 2; ++sym)
-    for (int cand : {1, 2, 4, 8}) {
+    for (int cand : {1, 0, 2, 4, 8}) {
       const Shape sh{cand, sym != 0};
       const double *A = sh.sym ? L.Ah.as<double>() : L.A.as<double>();
       launch_lspmv<D, double, double>(sh, L.g, s, A, x, y, nullptr, nullptr);
@@ -563,8 +645,10 @@ LevelBufs<float> bufs<float>(Level &L) {
           L.dinv32.ptr};
 }
 
+// V-cycle from level l.  first_done: the producer of b already wrote the
+// first Chebyshev step (x = d = c2 D^-1 b) into the level's xa and d.
 template <int D, typename TX>
-void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s) {
+void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s, bool first_done = false) {
   using TV = TX;  // FP64 levels in FP64 mode, FP32 levels in mixed mode
   const int nl = (int)pc->lv.size();
   Level &L = *pc->lv[l];
@@ -599,7 +683,7 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s) {
   };
   // pre-smoothing from x = 0
   const Shape lpr = L.shape;
-  {
+  if (!first_done) {
     ProfScope ps(fam_vec, cheb_bytes(true, false), s);
     k_cheb_first<TV, TX><<<dim3(blocks_for(L.g.N, 256), 2), 256, 0, s>>>(L.g.N, di, b, cur, B.d, c2[0]);
   }
@@ -615,11 +699,18 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s) {
   }
   Level &Cl = *pc->lv[l + 1];
   LevelBufs<TX> CB = bufs<TX>(Cl);
-  {
+  const bool fuse = l + 1 < nl - 1;  // the coarse level smooths: fuse its first step
+  if (fuse) {
+    std::vector<Sc2> cc1, cc2;
+    cheb_coefs(Cl, deg, cc1, cc2);
+    ProfScope ps(fam_vec, 2.0 * (tx * (Nl + 3.0 * Cl.g.N) + tv * Cl.g.N), s);
+    k_restrict_first<D, TV, TX><<<dim3(blocks_for(Cl.g.N, 256), 2), 256, 0, s>>>(
+        gd, dev(Cl.g), B.r, CB.b, (const TV *)CB.dinv, CB.xa, CB.d, cc2[0]);
+  } else {
     ProfScope ps(fam_vec, 2.0 * tx * (Nl + Cl.g.N), s);
     k_restrict<D, TX><<<dim3(blocks_for(Cl.g.N, 256), 2), 256, 0, s>>>(gd, dev(Cl.g), B.r, CB.b);
   }
-  vcyc<D, TX>(pc, l + 1, CB.b, CB.e, s);
+  vcyc<D, TX>(pc, l + 1, CB.b, CB.e, s, fuse);
   {
     ProfScope ps(fam_vec, 2.0 * tx * (2.0 * Nl + Cl.g.N), s);
     k_prolong<D, TX><<<grid, 256, 0, s>>>(gd, dev(Cl.g), CB.e, cur);
@@ -678,19 +769,29 @@ void vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s) {
 void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStream_t s) {
   dpp_problem P = pc->prob;
   Level &L0 = *pc->lv[0];
+  // the Schur right-hand side kernel also writes the finest level's first
+  // Chebyshev step when that level smooths
+  const bool fuse = pc->lv.size() > 1;
+  double c2q[2] = {0.0, 0.0};
+  if (fuse) {
+    std::vector<Sc2> c1, c2;
+    cheb_coefs(L0, pc->opts.cheb_degree, c1, c2);
+    c2q[0] = c2[0].v[0];
+    c2q[1] = c2[0].v[1];
+  }
   if (fp32) {
-    schur_rhs(P, r, pc->rhat32.ptr, true, s);
+    schur_rhs(P, r, pc->rhat32.ptr, true, s, fuse ? L0.dinv32.ptr : nullptr, L0.xa32.ptr, L0.d32.ptr, c2q);
     if (P->g.dim == 3)
-      vcyc<3, float>(pc, 0, pc->rhat32.as<float>(), L0.e32.as<float>(), s);
+      vcyc<3, float>(pc, 0, pc->rhat32.as<float>(), L0.e32.as<float>(), s, fuse);
     else
-      vcyc<2, float>(pc, 0, pc->rhat32.as<float>(), L0.e32.as<float>(), s);
+      vcyc<2, float>(pc, 0, pc->rhat32.as<float>(), L0.e32.as<float>(), s, fuse);
     schur_velocity(P, r, L0.e32.ptr, true, z, s);
   } else {
-    schur_rhs(P, r, pc->rhat.ptr, false, s);
+    schur_rhs(P, r, pc->rhat.ptr, false, s, fuse ? L0.dinv.ptr : nullptr, L0.xa.ptr, L0.d.ptr, c2q);
     if (P->g.dim == 3)
-      vcyc<3, double>(pc, 0, pc->rhat.as<double>(), L0.e.as<double>(), s);
+      vcyc<3, double>(pc, 0, pc->rhat.as<double>(), L0.e.as<double>(), s, fuse);
     else
-      vcyc<2, double>(pc, 0, pc->rhat.as<double>(), L0.e.as<double>(), s);
+      vcyc<2, double>(pc, 0, pc->rhat.as<double>(), L0.e.as<double>(), s, fuse);
     schur_velocity(P, r, L0.e.ptr, false, z, s);
   }
 }

@@ -142,7 +142,11 @@ void make_selfp(dpp_problem P, double *S, hipStream_t s);
 void make_kh(dpp_problem P, hipStream_t s);
 void make_k32(dpp_problem P, hipStream_t s);
 // Schur fieldsplit pieces: rhat_i = r_p_i - K_pu^i diag^-1 r_u_i ; z_u = diag^-1 (r_u - K_up z_p)
-void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_t s);
+// With ldinv non-null it also writes the finest level's first Chebyshev step
+// x = d = c2 ldinv rhat into xa and d (ldinv, xa, d in the level's precision).
+void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_t s,
+               const void *ldinv = nullptr, void *xa = nullptr, void *d = nullptr,
+               const double *c2 = nullptr);
 void schur_velocity(dpp_problem P, const double *r, const void *zp, bool fp32, double *z,
                     hipStream_t s);
 

@@ -105,7 +105,7 @@ __global__ void k_pack_kh(GridDev g, const double *__restrict__ kv, double *__re
     t = r % L::NS;
     kind = kv_up(D, qc / D, qc % D);
   }
-  kh[(size_t)st * ld + a] = kv[kind * vs + (size_t)t * ld + a];
+  kh[L::at(st, a)] = kv[kind * vs + (size_t)t * ld + a];
 }
 
 // selfp Schur block (eqs. S4_sp1, S4_sp2):
@@ -151,15 +151,27 @@ __global__ __launch_bounds__(256) void k_selfp(GridDev g, const double *__restri
   S[((size_t)q * NT + t) * g.ld + b] = acc;
 }
 
+// rhat = r_p - K_pu D^-1 r_u; with ldinv non-null also the multigrid's first
+// Chebyshev step on rhat (pointwise): xa = d = c2 ldinv rhat.
 template <int D, typename TV, typename TX>
 __global__ __launch_bounds__(256) void k_schur_rhs(GridDev g, const TV *__restrict__ kv,
                                                    const double *__restrict__ dinv,
                                                    const double *__restrict__ r,
-                                                   TX *__restrict__ rhat) {
+                                                   TX *__restrict__ rhat,
+                                                   const TX *__restrict__ ldinv,
+                                                   TX *__restrict__ xa, TX *__restrict__ dd,
+                                                   Sc2 c2) {
   const int q = blockIdx.y;
   const long b = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (b >= g.N) return;
-  rhat[q * g.N + b] = (TX)schur_rhs_node<D, TV>(g, kv, dinv, r, q, b);
+  const size_t ib = (size_t)q * g.N + b;
+  const TX v = (TX)schur_rhs_node<D, TV>(g, kv, dinv, r, q, b);
+  rhat[ib] = v;
+  if (ldinv) {
+    const double x0 = c2.v[q] * (double)ldinv[ib] * (double)v;
+    xa[ib] = (TX)x0;
+    dd[ib] = (TX)x0;
+  }
 }
 
 template <int D, typename TV, typename TX>
@@ -170,14 +182,24 @@ __global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restri
                                                    double *__restrict__ z) {
   const long N = g.N;
   const int q = blockIdx.y;
-  const long a = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const long a = 2 * ((long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
   if (a >= N) return;
-  double out[D];
-  schur_vel_node<D, TV, TX>(g, kv, dinv, r, zp, q, a, out);
   const long ou = off_u(D, N, q);
+  if (a + 1 < N) {
+    double out[2 * D];
+    schur_vel_node2<D, TV, TX>(g, kv, dinv, r, zp, q, a, out);
 #pragma unroll
-  for (int c = 0; c < D; ++c) z[ou + D * a + c] = out[c];
-  z[off_p(D, N, q) + a] = (double)zp[q * N + a];
+    for (int k = 0; k < D; ++k) st2(z + ou + D * a + 2 * k, out[2 * k], out[2 * k + 1]);
+    TX p0, p1;
+    ld2(zp + q * N + a, p0, p1);
+    st2(z + off_p(D, N, q) + a, (double)p0, (double)p1);
+  } else {
+    double out[D];
+    schur_vel_node<D, TV, TX>(g, kv, dinv, r, zp, q, a, out);
+#pragma unroll
+    for (int c = 0; c < D; ++c) z[ou + D * a + c] = out[c];
+    z[off_p(D, N, q) + a] = (double)zp[q * N + a];
+  }
 }
 
 __global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, size_t n) {
@@ -267,7 +289,7 @@ void make_selfp(dpp_problem P, double *S, hipStream_t s) {
 void make_kh(dpp_problem P, hipStream_t s) {
   const Grid &g = P->g;
   const int streams = g.dim == 3 ? KH<3>::streams : KH<2>::streams;
-  P->kh.alloc(sizeof(double) * (size_t)streams * padded(g.N));
+  P->kh.alloc(sizeof(double) * (g.dim == 3 ? KH<3>::size(g.N) : KH<2>::size(g.N)));
   const long work = (long)streams * g.N;
   if (g.dim == 3)
     k_pack_kh<3><<<blocks_for(work, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->kh.as<double>());
@@ -284,24 +306,31 @@ void make_k32(dpp_problem P, hipStream_t s) {
   check_launch("k32");
 }
 
-void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_t s) {
+void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_t s,
+               const void *ldinv, void *xa, void *dd, const double *c2) {
   const Grid &g = P->g;
   const double pairs = g.dim == 3 ? valid_pairs<3, false>(g) : valid_pairs<2, false>(g);
+  const double tx = fp32 ? 4.0 : 8.0;
   ProfScope ps(PF_SCHUR_RHS,
-               2.0 * (pairs * g.dim * (fp32 ? 4.0 : 8.0) + g.N * (g.dim + 2.0) * 8.0 +
-                      g.N * (fp32 ? 4.0 : 8.0)), s);
+               2.0 * (pairs * g.dim * tx + g.N * (g.dim + 2.0) * 8.0 + g.N * tx +
+                      (ldinv ? 3.0 * g.N * tx : 0.0)), s);
   dim3 grid(blocks_for(g.N, 256), 2);
   const double *di = P->dinv.as<double>();
+  const Sc2 c{{c2 ? c2[0] : 0.0, c2 ? c2[1] : 0.0}};
   if (g.dim == 3) {
     if (fp32)
-      k_schur_rhs<3, float, float><<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (float *)rhat);
+      k_schur_rhs<3, float, float><<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (float *)rhat,
+                                                        (const float *)ldinv, (float *)xa, (float *)dd, c);
     else
-      k_schur_rhs<3, double, double><<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (double *)rhat);
+      k_schur_rhs<3, double, double><<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (double *)rhat,
+                                                          (const double *)ldinv, (double *)xa, (double *)dd, c);
   } else {
     if (fp32)
-      k_schur_rhs<2, float, float><<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (float *)rhat);
+      k_schur_rhs<2, float, float><<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (float *)rhat,
+                                                        (const float *)ldinv, (float *)xa, (float *)dd, c);
     else
-      k_schur_rhs<2, double, double><<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (double *)rhat);
+      k_schur_rhs<2, double, double><<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (double *)rhat,
+                                                          (const double *)ldinv, (double *)xa, (double *)dd, c);
   }
   check_launch("schur_rhs");
 }
@@ -313,7 +342,7 @@ void schur_velocity(dpp_problem P, const double *r, const void *zp, bool fp32, d
   ProfScope ps(PF_SCHUR_VEL,
                2.0 * (pairs * g.dim * (fp32 ? 4.0 : 8.0) + g.N * (2.0 * g.dim + 2.0) * 8.0 +
                       g.N * (fp32 ? 4.0 : 8.0)), s);
-  dim3 grid(blocks_for(g.N, 256), 2);
+  dim3 grid(blocks_for((g.N + 1) / 2, 256), 2);
   const double *di = P->dinv.as<double>();
   if (g.dim == 3) {
     if (fp32)

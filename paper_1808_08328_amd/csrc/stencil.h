@@ -82,6 +82,93 @@ __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq
   return acc;
 }
 
+// Two consecutive values with one wide load / store (dword alignment is all
+// the wide global accesses need, so odd element indices are fine).
+__device__ inline void ld2(const double *p, double &v0, double &v1) {
+  double2 t;
+  __builtin_memcpy(&t, p, sizeof(t));
+  v0 = t.x;
+  v1 = t.y;
+}
+__device__ inline void ld2(const float *p, float &v0, float &v1) {
+  float2 t;
+  __builtin_memcpy(&t, p, sizeof(t));
+  v0 = t.x;
+  v1 = t.y;
+}
+__device__ inline void st2(double *p, double v0, double v1) {
+  const double2 t = {v0, v1};
+  __builtin_memcpy(p, &t, sizeof(t));
+}
+__device__ inline void st2(float *p, float v0, float v1) {
+  const float2 t = {v0, v1};
+  __builtin_memcpy(p, &t, sizeof(t));
+}
+
+// Stencil products of rows a and a + 1 (a even) with paired loads: every
+// matrix and vector access reads two consecutive values in one 16-byte load
+// (8 bytes in FP32), which halves the load instructions, the limit of these
+// gather-heavy kernels.  A neighbour pair starting at b = a + o is read from
+// c = clamp(b, 0, N - 2) and the lane values are picked by d = b - c: an
+// index that falls outside [0, N) only ever meets a stored zero (own rows) or
+// is masked (mirror rows).  Row a + 1 may be N (N odd): its result is
+// meaningless and must not be stored; all its loads stay inside the arrays.
+template <int D, typename TV, typename TX, bool SYM>
+__device__ inline void row_product2(const GridDev &g, const TV *__restrict__ Aq,
+                                    const TX *__restrict__ xq, long a, double &r0, double &r1) {
+  constexpr int NT = Tabs<D>::NT;
+  constexpr int T0 = TAB<D>.t0;
+  constexpr int NH = NT - T0;
+  const long N = g.N, ld = g.ld;
+  double acc0 = 0.0, acc1 = 0.0;
+  if constexpr (!SYM) {
+#pragma unroll 8
+    for (int t = 0; t < NT; ++t) {
+      const int *o = TAB<D>.to[t];
+      const long b = a + lin(g, o[0], o[1], o[2]);
+      const long c = min(max(b, 0L), N - 2);
+      const long d = b - c;
+      TV a0, a1;
+      TX x0, x1;
+      ld2(Aq + (size_t)t * ld + a, a0, a1);
+      ld2(xq + c, x0, x1);
+      acc0 += (double)a0 * (double)(d > 0 ? x1 : x0);
+      acc1 += (double)a1 * (double)(d < 0 ? x0 : x1);
+    }
+  } else {
+#pragma unroll 8
+    for (int h = 0; h < NH; ++h) {
+      const int *o = TAB<D>.to[T0 + h];
+      const long lo = lin(g, o[0], o[1], o[2]);
+      const long b = a + lo;
+      const long c = min(b, N - 2);
+      const long d = b - c;
+      TV a0, a1;
+      TX x0, x1;
+      ld2(Aq + (size_t)h * ld + a, a0, a1);
+      ld2(xq + c, x0, x1);
+      // b >= a >= 0; b + 1 >= N means row a + 1's pair leaves the box (a1 = 0)
+      acc0 += (double)a0 * (double)(d > 0 ? x1 : x0);
+      acc1 += (double)a1 * (double)x1;
+      if (h > 0) {
+        // rows a - o and a + 1 - o hold the negative-half entries
+        const long bm = a - lo;
+        const long cm = min(max(bm, 0L), N - 2);
+        const long dm = bm - cm;
+        TV m0, m1;
+        TX y0, y1;
+        ld2(Aq + (size_t)h * ld + cm, m0, m1);
+        ld2(xq + cm, y0, y1);
+        const double p0 = (double)m0 * (double)y0, p1 = (double)m1 * (double)y1;
+        acc0 += dm == 0 ? p0 : (dm == 1 ? p1 : 0.0);
+        acc1 += dm == 0 ? p1 : (dm == -1 ? p0 : 0.0);
+      }
+    }
+  }
+  r0 = acc0;
+  r1 = acc1;
+}
+
 template <int D, bool SYM>
 constexpr int stored_offsets() {
   return SYM ? Tabs<D>::NT - TAB<D>.t0 : Tabs<D>::NT;
@@ -109,7 +196,6 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
                                    double ap[2]) {
   using L = KH<D>;
   const long N = g.N;
-  const size_t ld = g.ld;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     ap[q] = 0.0;
@@ -130,11 +216,11 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
     // pair (a, a + o): symmetric kinds own, kup own at tp, kup of a + o at tn
     double xu[D], xp[2], xo[2];
     // symmetric kinds
-    const double uu0 = (double)kh[L::sym(L::UU0, h) * ld + a];
-    const double uu1 = (double)kh[L::sym(L::UU1, h) * ld + a];
-    const double pp0 = (double)kh[L::sym(L::PP0, h) * ld + a];
-    const double pp1 = (double)kh[L::sym(L::PP1, h) * ld + a];
-    const double s12 = (double)kh[L::sym(L::K12, h) * ld + a];
+    const double uu0 = (double)kh[L::at(L::sym(L::UU0, h), a)];
+    const double uu1 = (double)kh[L::at(L::sym(L::UU1, h), a)];
+    const double pp0 = (double)kh[L::at(L::sym(L::PP0, h), a)];
+    const double pp1 = (double)kh[L::at(L::sym(L::PP1, h), a)];
+    const double s12 = (double)kh[L::at(L::sym(L::K12, h), a)];
     xp[0] = x[op[0] + bp];
     xp[1] = x[op[1] + bp];
 #pragma unroll
@@ -144,8 +230,8 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
       const double uu = q ? uu1 : uu0, pp = q ? pp1 : pp0;
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        const double up = (double)kh[L::up(q, c, tp) * ld + a];
-        const double pu = -mp * (double)kh[L::up(q, c, tn) * ld + bp];
+        const double up = (double)kh[L::at(L::up(q, c, tp), a)];
+        const double pu = -mp * (double)kh[L::at(L::up(q, c, tn), bp)];
         au[q][c] += uu * xu[c] + up * xp[q];
         ap[q] += pu * xu[c];
       }
@@ -155,11 +241,11 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
     ap[1] += s12 * xp[0];
     if (h == 0) continue;  // the zero offset has no mirror pair
     // pair (a, a - o): symmetric kinds stored at a - o, kup own at tn, kup of a - o at tp
-    const double vuu0 = mn * (double)kh[L::sym(L::UU0, h) * ld + bn];
-    const double vuu1 = mn * (double)kh[L::sym(L::UU1, h) * ld + bn];
-    const double vpp0 = mn * (double)kh[L::sym(L::PP0, h) * ld + bn];
-    const double vpp1 = mn * (double)kh[L::sym(L::PP1, h) * ld + bn];
-    const double v12 = mn * (double)kh[L::sym(L::K12, h) * ld + bn];
+    const double vuu0 = mn * (double)kh[L::at(L::sym(L::UU0, h), bn)];
+    const double vuu1 = mn * (double)kh[L::at(L::sym(L::UU1, h), bn)];
+    const double vpp0 = mn * (double)kh[L::at(L::sym(L::PP0, h), bn)];
+    const double vpp1 = mn * (double)kh[L::at(L::sym(L::PP1, h), bn)];
+    const double v12 = mn * (double)kh[L::at(L::sym(L::K12, h), bn)];
     xo[0] = x[op[0] + bn];
     xo[1] = x[op[1] + bn];
 #pragma unroll
@@ -169,8 +255,8 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
       const double uu = q ? vuu1 : vuu0, pp = q ? vpp1 : vpp0;
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        const double up = (double)kh[L::up(q, c, tn) * ld + a];
-        const double pu = -mn * (double)kh[L::up(q, c, tp) * ld + bn];
+        const double up = (double)kh[L::at(L::up(q, c, tn), a)];
+        const double pu = -mn * (double)kh[L::at(L::up(q, c, tp), bn)];
         au[q][c] += uu * xu[c] + up * xo[q];
         ap[q] += pu * xu[c];
       }
@@ -189,7 +275,6 @@ __device__ inline double schur_rhs_node(const GridDev &g, const TV *__restrict__
                                         const double *__restrict__ r, int q, long b) {
   using L = KH<D>;
   const long N = g.N;
-  const size_t ld = g.ld;
   const long ou = off_u(D, N, q);
   double acc = r[off_p(D, N, q) + b];
   // offsets in unrolled groups of 5 (loads of a group in flight together)
@@ -202,7 +287,7 @@ __device__ inline double schur_rhs_node(const GridDev &g, const TV *__restrict__
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < D; ++c)
-      s += (double)kh[L::up(q, c, L::NS - 1 - t) * ld + a] * r[ou + D * a + c];
+      s += (double)kh[L::at(L::up(q, c, L::NS - 1 - t), a)] * r[ou + D * a + c];
     acc += s * di;
   }
   return acc;
@@ -216,7 +301,6 @@ __device__ inline void schur_vel_node(const GridDev &g, const TV *__restrict__ k
                                       int q, long a, double out[D]) {
   using L = KH<D>;
   const long N = g.N;
-  const size_t ld = g.ld;
   const long ou = off_u(D, N, q);
 #pragma unroll
   for (int c = 0; c < D; ++c) out[c] = r[ou + D * a + c];
@@ -226,11 +310,49 @@ __device__ inline void schur_vel_node(const GridDev &g, const TV *__restrict__ k
     const long b = min(max(a + lin(g, o[0], o[1], o[2]), 0L), N - 1);
     const double zb = (double)zp[q * N + b];
 #pragma unroll
-    for (int c = 0; c < D; ++c) out[c] -= (double)kh[L::up(q, c, t) * ld + a] * zb;
+    for (int c = 0; c < D; ++c) out[c] -= (double)kh[L::at(L::up(q, c, t), a)] * zb;
   }
   const double di = dinv[q * N + a];
 #pragma unroll
   for (int c = 0; c < D; ++c) out[c] *= di;
+}
+
+// schur_vel_node for rows a and a + 1 (a even, a + 1 < N), paired loads.
+template <int D, typename TV, typename TX>
+__device__ inline void schur_vel_node2(const GridDev &g, const TV *__restrict__ kh,
+                                       const double *__restrict__ dinv,
+                                       const double *__restrict__ r, const TX *__restrict__ zp,
+                                       int q, long a, double out[2 * D]) {
+  using L = KH<D>;
+  const long N = g.N;
+  const long ou = off_u(D, N, q);
+#pragma unroll
+  for (int k = 0; k < D; ++k) ld2(r + ou + D * a + 2 * k, out[2 * k], out[2 * k + 1]);
+#pragma unroll 5
+  for (int t = 0; t < L::NS; ++t) {
+    const int *o = TAB<D>.so[t];
+    const long b = a + lin(g, o[0], o[1], o[2]);
+    const long c = min(max(b, 0L), N - 2);
+    const long d = b - c;
+    TX z0, z1;
+    ld2(zp + q * N + c, z0, z1);
+    // own-row kup of pairs that leave the box are stored zeros
+    const double za = (double)(d > 0 ? z1 : z0), zb = (double)(d < 0 ? z0 : z1);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      TV u0, u1;
+      ld2(kh + L::at(L::up(q, k, t), a), u0, u1);
+      out[k] -= (double)u0 * za;
+      out[D + k] -= (double)u1 * zb;
+    }
+  }
+  double di0, di1;
+  ld2(dinv + q * N + a, di0, di1);
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    out[k] *= di0;
+    out[D + k] *= di1;
+  }
 }
 
 // b_c(C) = sum_f P(f, C) r(f) for one coarse node (one network's slice rq)

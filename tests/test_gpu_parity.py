@@ -128,7 +128,8 @@ def test_multigrid_hierarchy_and_cycle_match_oracle(case, cmax):
 
 @pytest.mark.parametrize("case", ["2d_ragged_grf", "3d_8_mms"])
 def test_every_level_kernel_shape_matches_oracle(case):
-    """All lanes-per-row / symmetric-storage variants the autotuner may pick."""
+    """All lanes-per-row (0 = two rows per lane) / symmetric-storage variants
+    the autotuner may pick; 3d_8_mms has an odd node count on every level."""
     prob = CASES[case]()
     S = odpp.assemble(prob)
     P = lib().assemble_problem(prob)
@@ -139,7 +140,7 @@ def test_every_level_kernel_shape_matches_oracle(case):
     N = P.n_nodes
     b = I.random_vector(2 * N, 5)
     ref = np.concatenate([omg.vcycle(Hs[i], b[i * N:(i + 1) * N]) for i in range(2)])
-    for lanes in (1, 2, 4, 8):
+    for lanes in (0, 1, 2, 4, 8):
         for sym in (0, 1):
             for l in range(nlev - 1):
                 pc.set_shape(l, lanes, sym)
@@ -200,12 +201,16 @@ def test_graph_replay_matches_eager_solve(precision):
 
 
 @pytest.mark.parametrize("precision", [1, 2])
-def test_mixed_precision_matches_oracle(precision):
+@pytest.mark.parametrize("lanes", [None, 0])
+def test_mixed_precision_matches_oracle(precision, lanes):
     prob = I.grf_problem(3, 8)
     S = odpp.assemble(prob)
     xo = odpp.solve_direct(S.K, S.f)
     P = lib().assemble_problem(prob)
     pc = P.setup_precond(coarse_max=40)
+    if lanes is not None:  # force the FP32 instances of one kernel shape
+        for l in range(pc.info()["levels"] - 1):
+            pc.set_shape(l, lanes, pc.shape(l)[1])
     x, st = P.solve(pc, rtol=1e-10, precision=precision)
     x = H(x)
     assert st.converged == 1
