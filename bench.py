@@ -36,12 +36,27 @@ WORKLOADS = {
 PRECISION = {0: "f64", 1: "f64+f32 refinement", 2: "f64 Krylov, f32 preconditioner"}
 
 
+# profiling families that are one kernel each (the roofline reports the one
+# with the largest share of the solve; the others group several kernels)
+SINGLE_KERNEL_FAMILIES = ("spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "schur_vel")
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("mg.hip", "ops.hip", "krylov.hip", "common.h"):
+    for f in ("mg.hip", "ops.hip", "krylov.hip", "common.h", "stencil.h", "mvec.h"):
         with open(os.path.join(ROOT, "paper_1808_08328_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def kernel_name(family, dim, pc):
+    """rocprofv3 name of a single-kernel family's FP64 kernel."""
+    if family in ("cheb_S_l0", "resid_S_l0"):
+        lanes, sym = pc.shape(0)
+        k = "k_cheb" if family == "cheb_S_l0" else "k_lspmv"
+        return "%s<%d, double, double, %d, %s, true>" % (k, dim, lanes, "true" if sym else "false")
+    return {"spmv_K": "k_spmv_K<%d, double>", "schur_rhs": "k_schur_rhs<%d, double, double>",
+            "schur_vel": "k_schur_vel<%d, double, double>"}[family] % dim
 
 
 def measured_traffic(family, launches_bytes):
@@ -152,6 +167,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-max-iters", type=int, default=60)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--shapes", default=None,
+                    help="JSON file of per-level kernel shapes: written after autotuning when "
+                         "absent, applied instead of the autotuner's choice when present "
+                         "(so profiler runs time the same kernels)")
     ap.add_argument("--graph", type=int, default=0, choices=[0, 1],
                     help="replay each Arnoldi step from a captured hipGraph")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -186,6 +205,14 @@ def main():
     pc = P.setup_precond()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    if args.shapes:
+        nlev = pc.info()["levels"]
+        if os.path.exists(args.shapes):
+            for lvl, (lanes, sym) in enumerate(json.load(open(args.shapes))["shapes"]):
+                pc.set_shape(lvl, lanes, sym)
+        else:
+            json.dump({"workload": args.config, "shapes": [list(pc.shape(lvl)) for lvl in range(nlev - 1)]},
+                      open(args.shapes, "w"))
     opts = dict(rtol=1e-8, precision=args.precision, use_graph=args.graph)
     for _ in range(args.warmup):
         P.solve(pc, **opts)
@@ -215,13 +242,15 @@ def main():
                 kernels[name] = {"launches_per_solve": n / args.steps, "ms_per_solve": t / args.steps,
                                  "avg_us": 1e3 * t / n, "GBps": by / (t * 1e6) if t > 0 else None,
                                  "share": t / tot_ms if tot_ms else None}
-        dom = max(kernels, key=lambda k: kernels[k]["ms_per_solve"])
+        dom = max((k for k in kernels if k in SINGLE_KERNEL_FAMILIES),
+                  key=lambda k: kernels[k]["ms_per_solve"])
         n, t, by = prof[dom]
         achieved = by / (t * 1e6)
         per_launch = by / n
         tr = measured_traffic(dom, per_launch)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": tr, "kernel": dom,
+                "kernel_name": kernel_name(dom, prob.dim, pc),
                 "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": 1e3 * t / n}
 
     line = {

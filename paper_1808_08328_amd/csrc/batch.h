@@ -9,6 +9,11 @@ namespace dpp {
 
 constexpr int BMAXK = 32;           // basis vectors per instance in the fused kernels
 constexpr int HS = 2 * BMAXK + 4;   // per-instance slots of the Hessenberg scratch
+// per-instance slot layout: [a (nj) | b (nj) | t.w] from 0, ||v~||^2 of two
+// consecutive steps, rho and hjj of the current step
+constexpr int HB_ALPHA = 2 * BMAXK;
+constexpr int HB_RHO = HB_ALPHA + 2;
+constexpr int HB_HJJ = HB_RHO + 1;
 constexpr int BBS = 256;
 
 struct KDesc {
@@ -79,9 +84,13 @@ struct dpp_batch_s {
   bool has32 = false;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   hipStream_t gstream = nullptr;  // capture/replay stream (default priority)
+  double *hpin = nullptr;         // pinned host copy of one step's reductions [nb][HS]
+  hipEvent_t hev = nullptr;       // marks that copy
   ~dpp_batch_s() {
     for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
     if (gstream) (void)hipStreamDestroy(gstream);
+    if (hev) (void)hipEventDestroy(hev);
+    if (hpin) (void)hipHostFree(hpin);
     for (auto p : pc) delete p;
     for (auto p : P) delete p;
   }

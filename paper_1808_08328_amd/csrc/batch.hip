@@ -221,39 +221,47 @@ __global__ __launch_bounds__(BBS) void kb_mdot(const VDesc *__restrict__ vd, int
   mv_block_store<NKP>(acc, nk, 0.0, false, part, gridDim.x, blockIdx.x);
 }
 
+// DCGS2 pass A per instance (t = V_nj of the instance): partial rows
+// [0, nj) = V_k . t, [nj, 2nj) = V_k . w, 2nj = t . w.
 template <int NKP>
-__global__ __launch_bounds__(BBS) void kb_axpy_mdot(const VDesc *__restrict__ vd, int nd,
-                                                    const int *__restrict__ active,
-                                                    const double *__restrict__ V, long ldv, int nk,
-                                                    const double *__restrict__ hb, int hslot,
-                                                    double *__restrict__ w, double *__restrict__ part) {
+__global__ __launch_bounds__(BBS) void kb_dcgs_a(const VDesc *__restrict__ vd, int nd,
+                                                 const int *__restrict__ active,
+                                                 const double *__restrict__ V, long ldv, int nj,
+                                                 const double *__restrict__ w, double *__restrict__ part) {
   const int di = find_desc(vd, nd, (int)blockIdx.x, &VDesc::blk0);
   const VDesc &v = vd[di];
   if (!active[v.inst]) return;
-  double acc[NKP], hk[NKP], nrm = 0.0;
+  double aa[NKP], bb[NKP], tw = 0.0;
 #pragma unroll
-  for (int k = 0; k < NKP; ++k) acc[k] = 0.0;
-  mv_coefs<NKP>(hb + (size_t)v.inst * HS + hslot, nk, hk);
-  mv_axpy<NKP, true>(V + v.off, ldv, nk, hk, w + v.off, w + v.off,
-                     (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x, v.n, (long)v.nblk * BBS, acc, nrm);
-  mv_block_store<NKP>(acc, nk, nrm, true, part, gridDim.x, blockIdx.x);
+  for (int k = 0; k < NKP; ++k) aa[k] = bb[k] = 0.0;
+  mv_dot2<NKP>(V + v.off, ldv, nj, V + (size_t)nj * ldv + v.off, w + v.off,
+               (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x, v.n, (long)v.nblk * BBS, aa, bb, tw);
+  mv_block_store2<NKP>(aa, bb, nj, tw, part, gridDim.x, blockIdx.x);
 }
 
+// DCGS2 pass B per instance, coefficients from the instance's reduced sums in
+// hb; the instance's first block publishes rho and hjj.
 template <int NKP>
-__global__ __launch_bounds__(BBS) void kb_axpy_norm(const VDesc *__restrict__ vd, int nd,
-                                                    const int *__restrict__ active,
-                                                    const double *__restrict__ V, long ldv, int nk,
-                                                    const double *__restrict__ hb, int hslot,
-                                                    const double *__restrict__ w,
-                                                    double *__restrict__ vout, double *__restrict__ part) {
+__global__ __launch_bounds__(BBS) void kb_dcgs_b(const VDesc *__restrict__ vd, int nd,
+                                                 const int *__restrict__ active,
+                                                 double *__restrict__ V, long ldv, int nj,
+                                                 const double *__restrict__ w,
+                                                 double *__restrict__ hb, double *__restrict__ part) {
   const int di = find_desc(vd, nd, (int)blockIdx.x, &VDesc::blk0);
   const VDesc &v = vd[di];
   if (!active[v.inst]) return;
-  double hk[NKP], nrm = 0.0;
-  mv_coefs<NKP>(hb + (size_t)v.inst * HS + hslot, nk, hk);
-  mv_axpy<NKP, false>(V + v.off, ldv, nk, hk, w + v.off, vout + v.off,
-                      (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x, v.n, (long)v.nblk * BBS, hk, nrm);
-  mv_block_store<NKP>(hk, 0, nrm, true, part, gridDim.x, blockIdx.x);
+  double *h = hb + (size_t)v.inst * HS;
+  double a[NKP], b[NKP], rho, inv, hjj;
+  mv_dcgs_coefs<NKP>(h, h[HB_ALPHA + (nj & 1)], nj, a, b, rho, inv, hjj);
+  if ((int)blockIdx.x == v.blk0 && threadIdx.x == 0) {
+    h[HB_RHO] = rho;
+    h[HB_HJJ] = hjj;
+  }
+  double nrm = 0.0;
+  mv_dcgs_update<NKP>(V + v.off, ldv, nj, a, b, inv, hjj, V + (size_t)nj * ldv + v.off, w + v.off,
+                      V + (size_t)(nj + 1) * ldv + v.off, (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x,
+                      v.n, (long)v.nblk * BBS, nrm);
+  mv_block_store<NKP>(a, 0, nrm, true, part, gridDim.x, blockIdx.x);
 }
 
 // hb[inst*HS + hslot + k] = sum of instance inst's partials of slot k
@@ -464,7 +472,8 @@ void spmv_b(dpp_batch B, const double *x, const double *bsub, double *y, hipStre
   check_launch("batched spmv");
 }
 
-// one Arnoldi step j for every active instance (graph-capturable: launches only)
+// one Arnoldi step j for every active instance: z_j = M^-1 v~_j, w = K z_j and
+// the two DCGS2 passes (graph-capturable: launches only)
 template <int D>
 void arnoldi_step_b(dpp_batch B, int j, bool fp32, hipStream_t s) {
   const long n = B->ntot;
@@ -475,15 +484,10 @@ void arnoldi_step_b(dpp_batch B, int j, bool fp32, hipStream_t s) {
   const int nvd = B->vd.count, tb = B->vd.blocks;
   precond_b<D>(B, V + (size_t)j * n, Z + (size_t)j * n, fp32, s);
   spmv_b<D>(B, Z + (size_t)j * n, nullptr, w, s);
-  const int nk = j + 1;
-  DPP_NK_SWITCH(nk, kb_mdot<NKP><<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, nk, w, part));
-  kb_finish<<<dim3(nk, nvd), BBS, 0, s>>>(vd, act, part, tb, hb, 0);
-  DPP_NK_SWITCH(nk, kb_axpy_mdot<NKP><<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, nk, hb, 0, w, part));
-  kb_finish<<<dim3(nk + 1, nvd), BBS, 0, s>>>(vd, act, part, tb, hb, BMAXK + 1);
-  DPP_NK_SWITCH(nk, kb_axpy_norm<NKP><<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, nk, hb, BMAXK + 1, w,
-                                                         V + (size_t)(j + 1) * n, part));
-  kb_finish<<<dim3(1, nvd), BBS, 0, s>>>(vd, act, part, tb, hb, 2 * BMAXK + 3);
-  kb_scale<<<tb, BBS, 0, s>>>(vd, nvd, act, V + (size_t)(j + 1) * n, hb, 2 * BMAXK + 3, nullptr);
+  DPP_NK_SWITCH(std::max(j, 1), kb_dcgs_a<NKP><<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, j, w, part));
+  kb_finish<<<dim3(2 * j + 1, nvd), BBS, 0, s>>>(vd, act, part, tb, hb, 0);
+  DPP_NK_SWITCH(std::max(j, 1), kb_dcgs_b<NKP><<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, j, w, hb, part));
+  kb_finish<<<dim3(1, nvd), BBS, 0, s>>>(vd, act, part, tb, hb, HB_ALPHA + ((j + 1) & 1));
   check_launch("batched arnoldi");
 }
 
@@ -658,6 +662,8 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
   }
   const long n = B->ntot;
   const bool fp32 = o.precision == 2;
+  if (!B->hpin) DPP_HIP(hipHostMalloc((void **)&B->hpin, sizeof(double) * (size_t)nb * HS, hipHostMallocDefault));
+  if (!B->hev) DPP_HIP(hipEventCreateWithFlags(&B->hev, hipEventDisableTiming));
   if (B->ws_m < m) {
     B->V.alloc(sizeof(double) * (size_t)(m + 1) * n);
     B->Z.alloc(sizeof(double) * (size_t)m * n);
@@ -679,10 +685,57 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
   };
   upload_active();
   norms_b(B, f, 0, bn, s);
-  std::vector<double> H((size_t)nb * (m + 1) * m), g((size_t)nb * (m + 1)), cs((size_t)nb * m),
-      sn((size_t)nb * m), y((size_t)nb * BMAXK), hh((size_t)nb * HS), fac(nb);
-  std::vector<int> kused(nb);
-  auto Hc = [&](int i, int r, int c) -> double & { return H[((size_t)i * m + c) * (m + 1) + r]; };
+  // per instance: unrotated and rotated Hessenberg columns, Givens rotations,
+  // right-hand side before (gpre) and after (g) each rotation
+  std::vector<double> Hr((size_t)nb * (m + 1) * m), Rr((size_t)nb * (m + 1) * m), cs((size_t)nb * m),
+      sn((size_t)nb * m), gpre((size_t)nb * (m + 1)), g((size_t)nb * (m + 1)), y((size_t)nb * BMAXK), fac(nb);
+  std::vector<int> kused(nb), stop(nb);
+  double *hh = B->hpin;
+  auto Hc = [&](int i, int r, int c) -> double & { return Hr[((size_t)i * m + c) * (m + 1) + r]; };
+  auto Rc = [&](int i, int r, int c) -> double & { return Rr[((size_t)i * m + c) * (m + 1) + r]; };
+  auto rotate_column = [&](int i, int j) {
+    for (int r = 0; r <= j + 1; ++r) Rc(i, r, j) = Hc(i, r, j);
+    for (int r = 0; r < j; ++r) {
+      const double c = cs[(size_t)i * m + r], sr = sn[(size_t)i * m + r];
+      const double t = c * Rc(i, r, j) + sr * Rc(i, r + 1, j);
+      Rc(i, r + 1, j) = -sr * Rc(i, r, j) + c * Rc(i, r + 1, j);
+      Rc(i, r, j) = t;
+    }
+  };
+  auto make_rotation = [&](int i, int j) {
+    const double den = std::hypot(Rc(i, j, j), Rc(i, j + 1, j));
+    DPP_CHECK(std::isfinite(den), DPP_ERR_NUMERIC, "NaN/Inf in a batched Arnoldi step");
+    if (den == 0.0) return false;
+    double &c = cs[(size_t)i * m + j], &sr = sn[(size_t)i * m + j];
+    c = Rc(i, j, j) / den;
+    sr = Rc(i, j + 1, j) / den;
+    Rc(i, j, j) = den;
+    Rc(i, j + 1, j) = 0.0;
+    double *gp = &gpre[(size_t)i * (m + 1)];
+    g[(size_t)i * (m + 1) + j] = c * gp[j];
+    gp[j + 1] = -sr * gp[j];
+    return true;
+  };
+  auto enqueue = [&](int j) {
+    if (!use_graph) {
+      arnoldi_step_b<D>(B, j, fp32, s);
+      return;
+    }
+    auto key = std::make_pair(j, fp32 ? 1 : 0);
+    auto itg = B->graphs.find(key);
+    if (itg == B->graphs.end()) {
+      hipGraph_t graph;
+      DPP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      arnoldi_step_b<D>(B, j, fp32, s);
+      DPP_HIP(hipStreamEndCapture(s, &graph));
+      hipGraphExec_t ex;
+      const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      DPP_HIP(e);
+      itg = B->graphs.emplace(key, ex).first;
+    }
+    DPP_HIP(hipGraphLaunch(itg->second, s));
+  };
   int total_iters = 0;
   while (true) {
     // true residuals of the instances still running
@@ -712,59 +765,59 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
     DPP_HIP(hipMemcpyAsync(B->fac.ptr, fac.data(), sizeof(double) * nb, hipMemcpyHostToDevice, s));
     kb_scale<<<B->vd.blocks, BBS, 0, s>>>(B->vd.get(), B->vd.count, B->active.as<int>(), V, nullptr, 0,
                                           B->fac.as<double>());
-    std::fill(g.begin(), g.end(), 0.0);
     std::fill(kused.begin(), kused.end(), 0);
-    for (int i = 0; i < nb; ++i) g[(size_t)i * (m + 1)] = rn[i];
+    std::fill(stop.begin(), stop.end(), 0);
+    for (int i = 0; i < nb; ++i) gpre[(size_t)i * (m + 1)] = rn[i];
+    enqueue(0);
     for (int j = 0; j < m; ++j) {
-      if (use_graph) {
-        auto key = std::make_pair(j, fp32 ? 1 : 0);
-        auto itg = B->graphs.find(key);
-        if (itg == B->graphs.end()) {
-          hipGraph_t graph;
-          DPP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-          arnoldi_step_b<D>(B, j, fp32, s);
-          DPP_HIP(hipStreamEndCapture(s, &graph));
-          hipGraphExec_t ex;
-          DPP_HIP(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0));
-          (void)hipGraphDestroy(graph);
-          itg = B->graphs.emplace(key, ex).first;
-        }
-        DPP_HIP(hipGraphLaunch(itg->second, s));
-      } else {
-        arnoldi_step_b<D>(B, j, fp32, s);
+      // copy step j's reductions; queue step j + 1 behind them unless every
+      // running instance's residual trend says step j is its last
+      DPP_HIP(hipMemcpyAsync(hh, B->hb.ptr, sizeof(double) * (size_t)nb * HS, hipMemcpyDeviceToHost, s));
+      DPP_HIP(hipEventRecord(B->hev, s));
+      bool want = false;
+      for (int i = 0; i < nb; ++i) {
+        if (!act[i]) continue;
+        const double *gp = &gpre[(size_t)i * (m + 1)];
+        const double pred = j >= 1 ? gp[j] * gp[j] / std::fabs(gp[j - 1]) : gp[0];
+        if (its[i] + 1 < o.maxiter && std::fabs(pred) > 4.0 * o.rtol * bn[i]) want = true;
       }
-      DPP_HIP(hipMemcpyAsync(hh.data(), B->hb.ptr, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s));
-      DPP_HIP(hipStreamSynchronize(s));
+      const bool queued = j + 1 < m && want;
+      if (queued) enqueue(j + 1);
+      DPP_HIP(hipEventSynchronize(B->hev));
       ++total_iters;
       bool still = false, changed = false;
       for (int i = 0; i < nb; ++i) {
         if (!act[i]) continue;
         its[i]++;
         const double *h = &hh[(size_t)i * HS];
-        for (int r = 0; r <= j; ++r) Hc(i, r, j) = h[r] + h[BMAXK + 1 + r];
-        const double hn = std::sqrt(std::max(0.0, h[2 * BMAXK + 3]));
-        Hc(i, j + 1, j) = hn;
-        double *csi = &cs[(size_t)i * m], *sni = &sn[(size_t)i * m], *gi = &g[(size_t)i * (m + 1)];
-        for (int r = 0; r < j; ++r) {
-          const double t = csi[r] * Hc(i, r, j) + sni[r] * Hc(i, r + 1, j);
-          Hc(i, r + 1, j) = -sni[r] * Hc(i, r, j) + csi[r] * Hc(i, r + 1, j);
-          Hc(i, r, j) = t;
+        bool end = false;
+        if (j > 0) {
+          // correct column j-1 by a = V^T v~_j and the exact subdiagonal rho_j
+          const double rho = h[HB_RHO], alpha = h[HB_ALPHA + (j & 1)];
+          for (int r = 0; r < j; ++r) Hc(i, r, j - 1) += h[r];
+          Hc(i, j, j - 1) = rho;
+          rotate_column(i, j - 1);
+          if (!make_rotation(i, j - 1) || !(rho > 1e-2 * std::sqrt(alpha))) {
+            kused[i] = j;  // v~_j (almost) inside the basis: column j - 1 ends the cycle
+            end = true;
+          }
         }
-        const double den = std::hypot(Hc(i, j, j), Hc(i, j + 1, j));
-        DPP_CHECK(std::isfinite(den), DPP_ERR_NUMERIC, "NaN/Inf in a batched Arnoldi step");
-        if (den == 0.0) {
-          act[i] = 0;
-          changed = true;
-          continue;
+        if (!end) {
+          for (int r = 0; r < j; ++r) Hc(i, r, j) = h[j + r];
+          Hc(i, j, j) = h[HB_HJJ];
+          const double hn = std::sqrt(std::max(0.0, h[HB_ALPHA + ((j + 1) & 1)]));
+          Hc(i, j + 1, j) = hn;
+          rotate_column(i, j);
+          if (!make_rotation(i, j)) {
+            kused[i] = j;
+            end = true;
+          } else {
+            kused[i] = j + 1;
+            const double res = std::fabs(gpre[(size_t)i * (m + 1) + j + 1]);
+            end = res <= o.rtol * bn[i] || its[i] >= o.maxiter || hn <= 1e-300 || j + 1 == m;
+          }
         }
-        csi[j] = Hc(i, j, j) / den;
-        sni[j] = Hc(i, j + 1, j) / den;
-        Hc(i, j, j) = den;
-        Hc(i, j + 1, j) = 0.0;
-        gi[j + 1] = -sni[j] * gi[j];
-        gi[j] = csi[j] * gi[j];
-        kused[i] = j + 1;
-        if (std::fabs(gi[j + 1]) <= o.rtol * bn[i] || its[i] >= o.maxiter || hn <= 1e-300) {
+        if (end) {
           act[i] = 0;
           changed = true;
         } else {
@@ -773,8 +826,10 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
       }
       if (!still) break;
       if (changed) upload_active();
+      if (!queued) enqueue(j + 1);
     }
-    // x_i += Z_i y_i
+    // wait for a queued step that will not be used, then x_i += Z_i y_i
+    DPP_HIP(hipStreamSynchronize(s));
     std::vector<int> nk(nb, 0);
     for (int i = 0; i < nb; ++i) {
       const int k = kused[i];
@@ -783,8 +838,8 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
       const double *gi = &g[(size_t)i * (m + 1)];
       for (int r = k - 1; r >= 0; --r) {
         double t = gi[r];
-        for (int c = r + 1; c < k; ++c) t -= Hc(i, r, c) * yi[c];
-        yi[r] = t / Hc(i, r, r);
+        for (int c = r + 1; c < k; ++c) t -= Rc(i, r, c) * yi[c];
+        yi[r] = t / Rc(i, r, r);
       }
       if (k) rest[i]++;
     }
