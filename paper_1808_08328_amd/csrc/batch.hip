@@ -585,7 +585,7 @@ void batch_setup(dpp_batch B, hipStream_t s) {
   }
   B->kd.upload(kv, kb);
   B->vd.upload(vv, vb);
-  B->part.alloc(sizeof(double) * (size_t)(BMAXK + 2) * vb);
+  B->part.alloc(sizeof(double) * (size_t)MV_PART_ROWS * vb);
   std::vector<CDesc> cv;
   int cb = 0;
   for (int i = 0; i < nb; ++i) {
@@ -662,6 +662,9 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
   }
   const long n = B->ntot;
   const bool fp32 = o.precision == 2;
+  DPP_CHECK(2 * (m - 1) + 1 <= MV_PART_ROWS - 1 && m <= BMAXK - 1 &&
+                (size_t)B->vd.blocks * MV_PART_ROWS * sizeof(double) <= B->part.bytes,
+            DPP_ERR_ARG, "batched Krylov reduction buffer too small for the restart length");
   if (!B->hpin) DPP_HIP(hipHostMalloc((void **)&B->hpin, sizeof(double) * (size_t)nb * HS, hipHostMallocDefault));
   if (!B->hev) DPP_HIP(hipEventCreateWithFlags(&B->hev, hipEventDisableTiming));
   if (B->ws_m < m) {

@@ -143,7 +143,7 @@ void ensure_ws(dpp_precond pc, int m) {
 }  // namespace
 
 void ensure_reduction(dpp_precond pc) {
-  if (!pc->part.ptr) pc->part.alloc(sizeof(double) * (size_t)(MAXK + 2) * RED_MAX);
+  if (!pc->part.ptr) pc->part.alloc(sizeof(double) * (size_t)MV_PART_ROWS * RED_MAX);
 }
 
 void axpby(long n, double a, const double *x, double b, double *y, hipStream_t s) {
@@ -154,10 +154,10 @@ void axpby(long n, double a, const double *x, double b, double *y, hipStream_t s
 double norm2(const double *x, long n, double *scratch, hipStream_t s) {
   const int nb = red_blocks(n);
   k_mdot<1><<<nb, BS, 0, s>>>(x, n, 1, x, scratch);
-  k_finish<<<1, BS, 0, s>>>(scratch, nb, scratch + (size_t)(MAXK + 1) * RED_MAX);
+  k_finish<<<1, BS, 0, s>>>(scratch, nb, scratch + (size_t)(MV_PART_ROWS - 1) * RED_MAX);
   check_launch("norm2");
   double h = 0.0;
-  DPP_HIP(hipMemcpyAsync(&h, scratch + (size_t)(MAXK + 1) * RED_MAX, sizeof(double),
+  DPP_HIP(hipMemcpyAsync(&h, scratch + (size_t)(MV_PART_ROWS - 1) * RED_MAX, sizeof(double),
                          hipMemcpyDeviceToHost, s));
   DPP_HIP(hipStreamSynchronize(s));
   return std::sqrt(h);
@@ -185,6 +185,8 @@ SolveResult fgmres(dpp_problem P, dpp_precond pc, const dpp_solve_opts &o, const
   auto Rc = [&](int i, int j) -> double & { return Rr[(size_t)j * (m + 1) + i]; };
   // Step j (launches only, so it can be captured): z_j = M^-1 v~_j, w = K z_j,
   // DCGS2 passes A and B.
+  DPP_CHECK(2 * (m - 1) + 1 <= MV_PART_ROWS - 1 && (size_t)nb * MV_PART_ROWS * sizeof(double) <= pc->part.bytes,
+            DPP_ERR_ARG, "Krylov reduction buffer too small for the restart length");
   auto step = [&](int j) {
     double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
     precond_apply(pc, vj, zj, pre32, s);

@@ -17,6 +17,9 @@ namespace dpp {
 
 constexpr int MV_BS = 256;   // threads per block of every multi-vector kernel
 constexpr int MV_MAXK = 32;  // largest bucket (restart length <= 31)
+// Rows of the per-block partial-sum buffers: DCGS2 pass A reduces 2 nj + 1
+// values (nj <= MV_MAXK - 1), the other kernels at most MV_MAXK + 1.
+constexpr int MV_PART_ROWS = 2 * MV_MAXK + 2;
 
 template <int NKP>
 constexpr int mv_unroll() {

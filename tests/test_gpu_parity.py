@@ -291,6 +291,21 @@ def test_full_size_solve_oracle_residual(name):
             1e-13 * np.abs(S.K.data).max()
 
 
+def test_long_arnoldi_cycle_full_size():
+    """A solve whose restart cycles pass 17 steps on vectors long enough for
+    the full 2048-block reduction grid (941,192 DOF): every partial-sum row of
+    the Gram-Schmidt passes is in use.  Checked with the oracle's own K."""
+    print("long cycle 48^3", flush=True)
+    prob = I.mms_problem(3, 48, k1=1.0, k2=1e-2)
+    P = lib().assemble_problem(prob)
+    pc = P.setup_precond()
+    x, st = P.solve(pc, rtol=1e-11, restart=31, maxiter=200)
+    assert st.converged and st.iters > 20
+    S = odpp.assemble(prob)
+    xh = H(x)
+    assert np.linalg.norm(S.f - S.K @ xh) <= 1.05e-11 * np.linalg.norm(S.f)
+
+
 def test_adjoint_gradient_full_size_finite_differences():
     """48^3 log-normal workload: J = ||p1 - p1_obs||^2 with p1_obs from a solve
     with ln k perturbed by 0.1 x an independent field (seed 3003); the adjoint
