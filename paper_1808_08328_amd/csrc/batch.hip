@@ -231,12 +231,9 @@ __global__ __launch_bounds__(BBS) void kb_dcgs_a(const VDesc *__restrict__ vd, i
   const int di = find_desc(vd, nd, (int)blockIdx.x, &VDesc::blk0);
   const VDesc &v = vd[di];
   if (!active[v.inst]) return;
-  double aa[NKP], bb[NKP], tw = 0.0;
-#pragma unroll
-  for (int k = 0; k < NKP; ++k) aa[k] = bb[k] = 0.0;
-  mv_dot2<NKP>(V + v.off, ldv, nj, V + (size_t)nj * ldv + v.off, w + v.off,
-               (long)(blockIdx.x - v.blk0) * BBS + threadIdx.x, v.n, (long)v.nblk * BBS, aa, bb, tw);
-  mv_block_store2<NKP>(aa, bb, nj, tw, part, gridDim.x, blockIdx.x);
+  mv_dcgs_a_waves<NKP>(V + v.off, ldv, nj, V + (size_t)nj * ldv + v.off, w + v.off,
+                       (long)(blockIdx.x - v.blk0) * 64, v.n, (long)v.nblk * 64, part, gridDim.x,
+                       blockIdx.x);
 }
 
 // DCGS2 pass B per instance, coefficients from the instance's reduced sums in

@@ -74,12 +74,8 @@ __global__ __launch_bounds__(BS) void k_mdot(const double *__restrict__ V, long 
 template <int NKP>
 __global__ __launch_bounds__(BS) void k_dcgs_a(const double *__restrict__ V, long n, int nj,
                                                const double *__restrict__ w, double *__restrict__ part) {
-  double aa[NKP], bb[NKP], tw = 0.0;
-#pragma unroll
-  for (int k = 0; k < NKP; ++k) aa[k] = bb[k] = 0.0;
-  mv_dot2<NKP>(V, n, nj, V + (size_t)nj * n, w, (long)blockIdx.x * BS + threadIdx.x, n,
-               (long)gridDim.x * BS, aa, bb, tw);
-  mv_block_store2<NKP>(aa, bb, nj, tw, part, gridDim.x, blockIdx.x);
+  mv_dcgs_a_waves<NKP>(V, n, nj, V + (size_t)nj * n, w, (long)blockIdx.x * 64, n,
+                       (long)gridDim.x * 64, part, gridDim.x, blockIdx.x);
 }
 
 // DCGS2 pass B of step j = nj: coefficients from the reduced sums in h (and

@@ -141,26 +141,48 @@ __device__ inline void mv_update(const double *__restrict__ Z, long ldz, int nk,
   }
 }
 
-// Pass A of the delayed-reorthogonalisation Gram-Schmidt step (DCGS2):
-// aa[k] += V_k[i] t[i], bb[k] += V_k[i] w[i] (k < nj), tw += t[i] w[i].
-// nj = 0 is allowed (only tw is formed; row 0 is read and discarded).
+// Pass A of DCGS2 with the basis rows split over the block's waves: every
+// wave streams the same 64 elements per step (t and w: one HBM read, the
+// other waves hit in cache) and its own KG = NKP/4 rows, so each thread keeps
+// 2 KG accumulators.  Partial row k < nj: V_k . t, row nj + k: V_k . w, row 2nj:
+// t . w, one value per block (written by the owning wave, no block reduction).
+// Element i runs over i0 + lane, + stride, ... < n (i0, stride multiples of 64).
 template <int NKP>
-__device__ inline void mv_dot2(const double *__restrict__ V, long ldv, int nj,
-                               const double *__restrict__ t, const double *__restrict__ w, long i0,
-                               long n, long stride, double (&aa)[NKP], double (&bb)[NKP],
-                               double &tw) {
+__device__ inline void mv_dcgs_a_waves(const double *__restrict__ V, long ldv, int nj,
+                                       const double *__restrict__ t, const double *__restrict__ w,
+                                       long i0, long n, long stride, double *__restrict__ part,
+                                       long tb, long bid) {
+  constexpr int KG = (NKP + MV_BS / 64 - 1) / (MV_BS / 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int k0 = wv * KG;
   const int last = nj > 0 ? nj - 1 : 0;
-  for (long i = i0; i < n; i += stride) {
+  const double *rows[KG];
+#pragma unroll
+  for (int kk = 0; kk < KG; ++kk) rows[kk] = V + (size_t)min(k0 + kk, last) * ldv;
+  double aa[KG], bb[KG], tw = 0.0;
+#pragma unroll
+  for (int kk = 0; kk < KG; ++kk) aa[kk] = bb[kk] = 0.0;
+  for (long i = i0 + lane; i < n; i += stride) {
     const double ti = t[i], wi = w[i];
-    double vv[NKP];
 #pragma unroll
-    for (int k = 0; k < NKP; ++k) vv[k] = V[(size_t)min(k, last) * ldv + i];
-#pragma unroll
-    for (int k = 0; k < NKP; ++k) {
-      aa[k] += vv[k] * ti;
-      bb[k] += vv[k] * wi;
+    for (int kk = 0; kk < KG; ++kk) {
+      const double v = rows[kk][i];
+      aa[kk] += v * ti;
+      bb[kk] += v * wi;
     }
     tw += ti * wi;
+  }
+#pragma unroll
+  for (int kk = 0; kk < KG; ++kk) {
+    const double sa = mv_wave_sum(aa[kk]), sb = mv_wave_sum(bb[kk]);
+    if (lane == 0 && k0 + kk < nj) {
+      part[(size_t)(k0 + kk) * tb + bid] = sa;
+      part[(size_t)(nj + k0 + kk) * tb + bid] = sb;
+    }
+  }
+  if (wv == 0) {
+    const double st = mv_wave_sum(tw);
+    if (lane == 0) part[(size_t)(2 * nj) * tb + bid] = st;
   }
 }
 
@@ -221,35 +243,6 @@ __device__ inline void mv_dcgs_coefs(const double *__restrict__ h, double alpha,
   hjj = rho > 0.0 ? (tw - ab) / rho : 0.0;
 }
 
-// Block-reduce aa[0..nj), bb[0..nj) and tw into partial rows k, nj + k and 2 nj.
-template <int NKP>
-__device__ inline void mv_block_store2(const double (&aa)[NKP], const double (&bb)[NKP], int nj,
-                                       double tw, double *__restrict__ part, long tb, long bid) {
-  __shared__ double sh[MV_BS / 64][2 * NKP + 1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NKP; ++k) {
-    if (k < nj) {
-      const double va = mv_wave_sum(aa[k]);
-      const double vb = mv_wave_sum(bb[k]);
-      if (lane == 0) {
-        sh[wv][k] = va;
-        sh[wv][NKP + k] = vb;
-      }
-    }
-  }
-  const double vt = mv_wave_sum(tw);
-  if (lane == 0) sh[wv][2 * NKP] = vt;
-  __syncthreads();
-  const int r = threadIdx.x;
-  if (r < 2 * nj + 1) {
-    const int slot = r < nj ? r : (r < 2 * nj ? NKP + (r - nj) : 2 * NKP);
-    double s = 0.0;
-    for (int w = 0; w < MV_BS / 64; ++w) s += sh[w][slot];
-    part[(size_t)r * tb + bid] = s;
-  }
-}
-
 // Block-reduce acc[0..nk) (and `extra` when with_extra) into per-block
 // partials: part[k * tb + bid] for k < nk, the extra value in row nk.
 template <int NKP>
@@ -258,11 +251,13 @@ __device__ inline void mv_block_store(const double (&acc)[NKP], int nk, double e
                                       long bid) {
   __shared__ double sh[MV_BS / 64][NKP + 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (nk > 0) {
+    double v[NKP];
 #pragma unroll
-  for (int k = 0; k < NKP; ++k) {
-    if (k < nk) {
-      const double v = mv_wave_sum(acc[k]);
-      if (lane == 0) sh[wv][k] = v;
+    for (int k = 0; k < NKP; ++k) v[k] = mv_wave_sum(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < NKP; ++k) sh[wv][k] = v[k];
     }
   }
   if (with_extra) {
