@@ -93,8 +93,14 @@ typedef struct {
  *   coarse_max [1000]: coarsest multigrid level has at most this many nodes
  *     (1..4000).
  *   cheb_degree [2], cheb_lo_frac [0.3], cheb_hi_factor [1.1], power_iters [15]:
- *     Chebyshev smoother and its eigenvalue estimate.
- *   use_graph [0]: capture one Arnoldi step in a hipGraph and replay it. */
+ *     Chebyshev smoother (degree used where a level's degree below is -1) and
+ *     its eigenvalue estimate.
+ *   use_graph [0]: capture one Arnoldi step in a hipGraph and replay it.
+ *   cheb_pre_fine [0], cheb_post_fine [3], cheb_pre_coarse [0],
+ *   cheb_post_coarse [3]: Chebyshev degrees of the V-cycle's pre- and
+ *     post-smoothing on the finest level and on the coarser smoothing levels;
+ *     -1 = cheb_degree.  A pre degree of 0 skips pre-smoothing (the level
+ *     restricts its right-hand side directly); post degrees are >= 1. */
 typedef struct {
   int restart;
   int maxiter;
@@ -108,6 +114,7 @@ typedef struct {
   double cheb_hi_factor;
   int power_iters;
   int use_graph;
+  int cheb_pre_fine, cheb_post_fine, cheb_pre_coarse, cheb_post_coarse;
 } dpp_solve_opts;
 
 typedef struct {

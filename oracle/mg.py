@@ -14,7 +14,8 @@ one on the structured box, defined here in plain steps:
   * coarse operators: Galerkin A_{l+1} = P^T A_l P;
   * coarsest level (at most ``coarse_max`` nodes, or no further coarsening
     possible): exact dense solve;
-  * smoother: Chebyshev iteration of degree ``degree`` preconditioned by the
+  * smoother: Chebyshev iterations (pre and post degrees per level class, see
+    MGOptions) preconditioned by the
     diagonal D of A, on the interval [lo_frac*hi, hi], hi = hi_factor * lam,
     lam = ||D^-1 A x_k|| after ``power_iters`` normalised power steps from the
     integer-hash start vector x_0[i] = frac(i * 2654435761 / 2^32) - 1/2;
@@ -116,6 +117,20 @@ class MGOptions:
     lo_frac: float = 0.3
     hi_factor: float = 1.1
     power_iters: int = 15
+    # Chebyshev degrees of pre- and post-smoothing on the finest level and on
+    # the coarser smoothing levels (-1 = degree; pre 0 = no pre-smoothing)
+    pre_fine: int = 0
+    post_fine: int = 3
+    pre_coarse: int = 0
+    post_coarse: int = 3
+
+    def pre(self, l):
+        v = self.pre_fine if l == 0 else self.pre_coarse
+        return self.degree if v < 0 else v
+
+    def post(self, l):
+        v = self.post_fine if l == 0 else self.post_coarse
+        return self.degree if v < 0 else v
 
 
 @dataclass
@@ -160,14 +175,18 @@ def setup(A, dim, n, opts=None):
 
 
 def vcycle(H, b, l=0):
+    """V(pre, post) cycle: Chebyshev pre-smoothing from x = 0 (none when pre is
+    0, so the residual is b), coarse-grid correction with P and P^T, Chebyshev
+    post-smoothing; the coarsest level is solved exactly."""
     lev = H.levels[l]
     if l == len(H.levels) - 1:
         return np.linalg.solve(H.coarse_dense, b)
     o = H.opts
     x = np.zeros_like(b)
-    x = chebyshev(lev.A, lev.dinv, b, x, o.degree, lev.lo, lev.hi)
+    if o.pre(l) > 0:
+        x = chebyshev(lev.A, lev.dinv, b, x, o.pre(l), lev.lo, lev.hi)
     r = b - lev.A @ x
     e = vcycle(H, lev.P.T @ r, l + 1)
     x = x + lev.P @ e
-    x = chebyshev(lev.A, lev.dinv, b, x, o.degree, lev.lo, lev.hi)
+    x = chebyshev(lev.A, lev.dinv, b, x, o.post(l), lev.lo, lev.hi)
     return x

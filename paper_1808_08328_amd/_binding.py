@@ -34,7 +34,9 @@ class _Opts(C.Structure):
     _fields_ = [("restart", C.c_int), ("maxiter", C.c_int), ("rtol", C.c_double),
                 ("precision", C.c_int), ("inner_rtol", C.c_double), ("max_refine", C.c_int),
                 ("coarse_max", C.c_int), ("cheb_degree", C.c_int), ("cheb_lo_frac", C.c_double),
-                ("cheb_hi_factor", C.c_double), ("power_iters", C.c_int), ("use_graph", C.c_int)]
+                ("cheb_hi_factor", C.c_double), ("power_iters", C.c_int), ("use_graph", C.c_int),
+                ("cheb_pre_fine", C.c_int), ("cheb_post_fine", C.c_int),
+                ("cheb_pre_coarse", C.c_int), ("cheb_post_coarse", C.c_int)]
 
 
 class SolveStats(C.Structure):

@@ -42,6 +42,10 @@ void check_opts(const dpp_solve_opts &o) {
   DPP_CHECK(o.max_refine >= 1, DPP_ERR_ARG, "max_refine must be >= 1");
   DPP_CHECK(o.coarse_max >= 1 && o.coarse_max <= 4000, DPP_ERR_ARG, "coarse_max must be in 1..4000");
   DPP_CHECK(o.cheb_degree >= 1 && o.cheb_degree <= 8, DPP_ERR_ARG, "cheb_degree must be in 1..8");
+  for (int v : {o.cheb_pre_fine, o.cheb_pre_coarse})
+    DPP_CHECK(v >= -1 && v <= 8, DPP_ERR_ARG, "pre-smoothing degrees must be -1 or 0..8");
+  for (int v : {o.cheb_post_fine, o.cheb_post_coarse})
+    DPP_CHECK(v == -1 || (v >= 1 && v <= 8), DPP_ERR_ARG, "post-smoothing degrees must be -1 or 1..8");
   DPP_CHECK(o.cheb_lo_frac > 0.0 && o.cheb_lo_frac < 1.0, DPP_ERR_ARG, "cheb_lo_frac must be in (0,1)");
   DPP_CHECK(o.cheb_hi_factor >= 1.0, DPP_ERR_ARG, "cheb_hi_factor must be >= 1");
   DPP_CHECK(o.power_iters >= 1, DPP_ERR_ARG, "power_iters must be >= 1");
@@ -67,6 +71,11 @@ void dpp_default_opts(dpp_solve_opts *o) {
   o->max_refine = 20;
   o->coarse_max = 1000;
   o->cheb_degree = 2;
+  // V(0,3) on every level: post-smoothing only (measured fastest to 1e-8)
+  o->cheb_pre_fine = 0;
+  o->cheb_post_fine = 3;
+  o->cheb_pre_coarse = 0;
+  o->cheb_post_coarse = 3;
   o->cheb_lo_frac = 0.3;
   o->cheb_hi_factor = 1.1;
   o->power_iters = 15;
@@ -232,6 +241,10 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
       o.cheb_lo_frac = pc->opts.cheb_lo_frac;
       o.cheb_hi_factor = pc->opts.cheb_hi_factor;
       pc->opts.cheb_degree = o.cheb_degree;
+      pc->opts.cheb_pre_fine = o.cheb_pre_fine;
+      pc->opts.cheb_post_fine = o.cheb_post_fine;
+      pc->opts.cheb_pre_coarse = o.cheb_pre_coarse;
+      pc->opts.cheb_post_coarse = o.cheb_post_coarse;
     }
     check_opts(o);
     hipStream_t s = S(stream);
@@ -407,6 +420,10 @@ dpp_status dpp_solve_batch(dpp_batch B, const dpp_solve_opts *opts, double *x, d
     o.cheb_hi_factor = B->opts.cheb_hi_factor;
     o.power_iters = B->opts.power_iters;
     o.cheb_degree = B->opts.cheb_degree;
+    o.cheb_pre_fine = B->opts.cheb_pre_fine;
+    o.cheb_post_fine = B->opts.cheb_post_fine;
+    o.cheb_pre_coarse = B->opts.cheb_pre_coarse;
+    o.cheb_post_coarse = B->opts.cheb_post_coarse;
     check_opts(o);
     st.resize(B->nb);
     dpp::batch_solve(B, o, x, st.data(), S(stream));

@@ -156,22 +156,24 @@ __global__ __launch_bounds__(256, 4) void kb_cheb(const LDesc *__restrict__ ld, 
   lbuf<TX>(l, out_w)[ia] = (TX)((double)xin[ia] + dn);
 }
 
+// bc = R r (or R b when the level does not pre-smooth)
 template <int D, typename TX>
 __global__ __launch_bounds__(256) void kb_restrict(const LDesc *__restrict__ ld, int nd,
-                                                   const int *__restrict__ active) {
+                                                   const int *__restrict__ active, int from_b) {
   const int di = find_desc(ld, nd, (int)blockIdx.x, &LDesc::cblk0);
   const LDesc &l = ld[di];
   if (!active[l.inst]) return;
   const int q = blockIdx.y;
   const long C = (long)(blockIdx.x - l.cblk0) * blockDim.x + threadIdx.x;
   if (C >= l.gc.N) return;
-  ((TX *)l.bc)[(size_t)q * l.gc.N + C] =
-      (TX)restrict_node<D, TX>(l.g, l.gc, (const TX *)l.r + (size_t)q * l.g.N, C);
+  const TX *src = (const TX *)(from_b ? l.b : l.r);
+  ((TX *)l.bc)[(size_t)q * l.gc.N + C] = (TX)restrict_node<D, TX>(l.g, l.gc, src + (size_t)q * l.g.N, C);
 }
 
+// x += P ec (x = P ec when assign: the level did not pre-smooth)
 template <int D, typename TX>
 __global__ __launch_bounds__(256) void kb_prolong(const LDesc *__restrict__ ld, int nd,
-                                                  const int *__restrict__ active, int x_w) {
+                                                  const int *__restrict__ active, int x_w, int assign) {
   const int di = find_desc(ld, nd, (int)blockIdx.x, &LDesc::blk0);
   const LDesc &l = ld[di];
   if (!active[l.inst]) return;
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(256) void kb_prolong(const LDesc *__restrict__ ld, 
   if (f >= l.g.N) return;
   const double v = prolong_node<D, TX>(l.g, l.gc, (const TX *)l.ec + (size_t)q * l.gc.N, f);
   TX *x = lbuf<TX>(l, x_w);
-  x[(size_t)q * l.g.N + f] = (TX)((double)x[(size_t)q * l.g.N + f] + v);
+  x[(size_t)q * l.g.N + f] = (TX)(assign ? v : (double)x[(size_t)q * l.g.N + f] + v);
 }
 
 template <typename TX>
@@ -372,7 +374,7 @@ void build_level_tables(dpp_batch B, int l, int lanes, bool fp32, DTable<LDesc> 
       d.b = L.b.ptr; d.xa = L.xa.ptr; d.xb = L.xb.ptr; d.d = L.d.ptr; d.r = L.r.ptr; d.e = L.e.ptr;
       d.bc = C.b.ptr; d.ec = C.e.ptr;
     }
-    cheb_coefs_l(L, B->opts.cheb_degree, d);
+    cheb_coefs_l(L, 8, d);  // step k's coefficients do not depend on the degree
     v.push_back(d);
   }
   // restriction blocks are looked up through cblk0: keep both orders valid
@@ -408,36 +410,40 @@ void launch_cheb_b(dpp_batch B, int l, const DTable<LDesc> &t, hipStream_t s, in
 // are each instance's level-0 b and e buffers).
 template <int D, typename TV, typename TX>
 void vcycle_b(dpp_batch B, bool fp32, hipStream_t s) {
-  const int deg = B->opts.cheb_degree;
   const int *act = B->active.as<int>();
   auto &tabs = fp32 ? B->ld32 : B->ld;
   std::vector<int> cur_after_pre(B->nlev, 0);
   for (int l = 0; l < B->nlev; ++l) {
     const DTable<LDesc> &t = tabs[l];
     if (!t.count) continue;
+    const int pre = cheb_pre(B->opts, l);
     const dim3 g1(t.blocks, 2);
-    kb_cheb_first<TV, TX><<<g1, 256, 0, s>>>(t.get(), t.count, act, 0);
     int cur = 0, oth = 1;
-    for (int k = 1; k < deg; ++k) {
-      launch_cheb_b<D, TV, TX>(B, l, t, s, k, cur, oth, 0);
-      std::swap(cur, oth);
+    if (pre > 0) {
+      kb_cheb_first<TV, TX><<<g1, 256, 0, s>>>(t.get(), t.count, act, 0);
+      for (int k = 1; k < pre; ++k) {
+        launch_cheb_b<D, TV, TX>(B, l, t, s, k, cur, oth, 0);
+        std::swap(cur, oth);
+      }
+      launch_cheb_b<D, TV, TX>(B, l, t, s, 0, cur, 0, 1);  // r = b - A x
     }
     cur_after_pre[l] = cur;
-    launch_cheb_b<D, TV, TX>(B, l, t, s, 0, cur, 0, 1);  // r = b - A x
     const int cb = level_cblocks(B, l);
-    // restriction: grid over coarse-node blocks, descriptors found through cblk0
-    kb_restrict<D, TX><<<dim3(cb, 2), 256, 0, s>>>(t.get(), t.count, act);
+    // restriction of r (or of b without pre-smoothing): grid over coarse-node
+    // blocks, descriptors found through cblk0
+    kb_restrict<D, TX><<<dim3(cb, 2), 256, 0, s>>>(t.get(), t.count, act, pre > 0 ? 0 : 1);
   }
   const DTable<CDesc> &c = fp32 ? B->cd32 : B->cd;
   kb_coarse<TX><<<dim3(c.blocks, 2), 256, 0, s>>>(c.get(), c.count, act);
   for (int l = B->nlev - 1; l >= 0; --l) {
     const DTable<LDesc> &t = tabs[l];
     if (!t.count) continue;
+    const int pre = cheb_pre(B->opts, l), post = cheb_post(B->opts, l);
     const dim3 g1(t.blocks, 2);
     int cur = cur_after_pre[l], oth = 1 - cur;
-    kb_prolong<D, TX><<<g1, 256, 0, s>>>(t.get(), t.count, act, cur);
-    for (int k = 0; k < deg; ++k) {
-      const int out = (k == deg - 1) ? 2 : oth;
+    kb_prolong<D, TX><<<g1, 256, 0, s>>>(t.get(), t.count, act, cur, pre > 0 ? 0 : 1);
+    for (int k = 0; k < post; ++k) {
+      const int out = (k == post - 1) ? 2 : oth;
       launch_cheb_b<D, TV, TX>(B, l, t, s, k, cur, out, 0);
       oth = cur;
       cur = out;
@@ -721,7 +727,7 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
       arnoldi_step_b<D>(B, j, fp32, s);
       return;
     }
-    auto key = std::make_pair(j, fp32 ? 1 : 0);
+    auto key = std::make_pair(j, (fp32 ? 1 : 0) + 2 * cycle_code(B->opts));
     auto itg = B->graphs.find(key);
     if (itg == B->graphs.end()) {
       hipGraph_t graph;

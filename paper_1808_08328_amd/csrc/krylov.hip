@@ -203,7 +203,7 @@ SolveResult fgmres(dpp_problem P, dpp_precond pc, const dpp_solve_opts &o, const
       step(j);
       return;
     }
-    const auto key = std::make_tuple(j, mode, pc->opts.cheb_degree);
+    const auto key = std::make_tuple(j, mode, cycle_code(pc->opts));
     auto it = pc->graphs.find(key);
     if (it == pc->graphs.end()) {
       hipGraph_t gr;

@@ -243,16 +243,16 @@ __global__ __launch_bounds__(256) void k_restrict_first(GridDev gf, GridDev gc,
   xc[ic] = (TX)v;
 }
 
-// x(f) += (P e)(f)
+// x(f) += (P e)(f), or x(f) = (P e)(f) when assign (no pre-smoothing: x was 0)
 template <int D, typename TX>
 __global__ __launch_bounds__(256) void k_prolong(GridDev gf, GridDev gc, const TX *__restrict__ e,
-                                                 TX *__restrict__ x) {
+                                                 TX *__restrict__ x, int assign) {
   const long N = gf.N;
   const int q = blockIdx.y;
   const long f = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (f >= N) return;
   const double v = prolong_node<D, TX>(gf, gc, e + (size_t)q * gc.N, f);
-  x[(size_t)q * N + f] = (TX)((double)x[(size_t)q * N + f] + v);
+  x[(size_t)q * N + f] = (TX)(assign ? v : (double)x[(size_t)q * N + f] + v);
 }
 
 // Galerkin coarse operator A_c(C, C+t) = sum_{f, g} P(f,C) A(f,g) P(g,C+t).
@@ -668,9 +668,9 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s, bool firs
   }
   LevelBufs<TX> B = bufs<TX>(L);
   const TV *A = (const TV *)B.A, *di = (const TV *)B.dinv;
-  const int deg = pc->opts.cheb_degree;
+  const int pre = cheb_pre(pc->opts, l), post = cheb_post(pc->opts, l);
   std::vector<Sc2> c1, c2;
-  cheb_coefs(L, deg, c1, c2);
+  cheb_coefs(L, std::max(pre, post), c1, c2);  // step k's coefficients do not depend on the degree
   TX *cur = B.xa, *oth = B.xb;
   const bool fine = l == 0;
   const int fam_cheb = fine ? PF_CHEB_L0 : PF_COARSE;
@@ -681,43 +681,47 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s, bool firs
     return 2.0 * ((zero_x ? 0.0 : pairs * tv) + Nl * (tv + tx * (zero_x ? 3.0 : 4.0) +
                                                      (dread ? tx : 0.0)));
   };
-  // pre-smoothing from x = 0
   const Shape lpr = L.shape;
-  if (!first_done) {
-    ProfScope ps(fam_vec, cheb_bytes(true, false), s);
-    k_cheb_first<TV, TX><<<dim3(blocks_for(L.g.N, 256), 2), 256, 0, s>>>(L.g.N, di, b, cur, B.d, c2[0]);
-  }
-  for (int k = 1; k < deg; ++k) {
-    ProfScope ps(fam_cheb, cheb_bytes(false, true), s);
-    launch_cheb<D, TV, TX>(lpr, L.g, s, A, di, b, cur, oth, B.d, c1[k], c2[k], fine);
-    std::swap(cur, oth);
-  }
-  // residual, restriction, coarse correction
-  {
+  // what is restricted: the residual after pre-smoothing, or b itself (x = 0)
+  const TX *rr = b;
+  if (pre > 0) {
+    // pre-smoothing from x = 0
+    if (!first_done) {
+      ProfScope ps(fam_vec, cheb_bytes(true, false), s);
+      k_cheb_first<TV, TX><<<dim3(blocks_for(L.g.N, 256), 2), 256, 0, s>>>(L.g.N, di, b, cur, B.d, c2[0]);
+    }
+    for (int k = 1; k < pre; ++k) {
+      ProfScope ps(fam_cheb, cheb_bytes(false, true), s);
+      launch_cheb<D, TV, TX>(lpr, L.g, s, A, di, b, cur, oth, B.d, c1[k], c2[k], fine);
+      std::swap(cur, oth);
+    }
     ProfScope ps(fam_res, 2.0 * (pairs * tv + 3.0 * Nl * tx), s);
     launch_lspmv<D, TV, TX>(lpr, L.g, s, A, cur, B.r, b, (const TV *)nullptr, fine);
+    rr = B.r;
   }
+  // restriction and coarse correction
   Level &Cl = *pc->lv[l + 1];
   LevelBufs<TX> CB = bufs<TX>(Cl);
-  const bool fuse = l + 1 < nl - 1;  // the coarse level smooths: fuse its first step
+  // the coarse level pre-smooths: fuse its first step into the restriction
+  const bool fuse = l + 1 < nl - 1 && cheb_pre(pc->opts, l + 1) > 0;
   if (fuse) {
     std::vector<Sc2> cc1, cc2;
-    cheb_coefs(Cl, deg, cc1, cc2);
+    cheb_coefs(Cl, 1, cc1, cc2);
     ProfScope ps(fam_vec, 2.0 * (tx * (Nl + 3.0 * Cl.g.N) + tv * Cl.g.N), s);
     k_restrict_first<D, TV, TX><<<dim3(blocks_for(Cl.g.N, 256), 2), 256, 0, s>>>(
-        gd, dev(Cl.g), B.r, CB.b, (const TV *)CB.dinv, CB.xa, CB.d, cc2[0]);
+        gd, dev(Cl.g), rr, CB.b, (const TV *)CB.dinv, CB.xa, CB.d, cc2[0]);
   } else {
     ProfScope ps(fam_vec, 2.0 * tx * (Nl + Cl.g.N), s);
-    k_restrict<D, TX><<<dim3(blocks_for(Cl.g.N, 256), 2), 256, 0, s>>>(gd, dev(Cl.g), B.r, CB.b);
+    k_restrict<D, TX><<<dim3(blocks_for(Cl.g.N, 256), 2), 256, 0, s>>>(gd, dev(Cl.g), rr, CB.b);
   }
   vcyc<D, TX>(pc, l + 1, CB.b, CB.e, s, fuse);
   {
-    ProfScope ps(fam_vec, 2.0 * tx * (2.0 * Nl + Cl.g.N), s);
-    k_prolong<D, TX><<<grid, 256, 0, s>>>(gd, dev(Cl.g), CB.e, cur);
+    ProfScope ps(fam_vec, 2.0 * tx * ((pre > 0 ? 2.0 : 1.0) * Nl + Cl.g.N), s);
+    k_prolong<D, TX><<<grid, 256, 0, s>>>(gd, dev(Cl.g), CB.e, cur, pre > 0 ? 0 : 1);
   }
   // post-smoothing
-  for (int k = 0; k < deg; ++k) {
-    TX *out = (k == deg - 1) ? xout : oth;
+  for (int k = 0; k < post; ++k) {
+    TX *out = (k == post - 1) ? xout : oth;
     ProfScope ps(fam_cheb, cheb_bytes(false, k > 0), s);
     launch_cheb<D, TV, TX>(lpr, L.g, s, A, di, b, cur, out, B.d, c1[k], c2[k], fine);
     oth = cur;
@@ -771,11 +775,11 @@ void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStr
   Level &L0 = *pc->lv[0];
   // the Schur right-hand side kernel also writes the finest level's first
   // Chebyshev step when that level smooths
-  const bool fuse = pc->lv.size() > 1;
+  const bool fuse = pc->lv.size() > 1 && cheb_pre(pc->opts, 0) > 0;
   double c2q[2] = {0.0, 0.0};
   if (fuse) {
     std::vector<Sc2> c1, c2;
-    cheb_coefs(L0, pc->opts.cheb_degree, c1, c2);
+    cheb_coefs(L0, 1, c1, c2);
     c2q[0] = c2[0].v[0];
     c2q[1] = c2[0].v[1];
   }

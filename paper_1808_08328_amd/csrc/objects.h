@@ -106,8 +106,8 @@ struct dpp_precond_s {
   // Krylov workspace, kept across solves
   int ws_m = 0;
   dpp::DBuf V, Z, w, part, hdev, ydev, xtmp, rtmp;
-  // Arnoldi steps captured as graphs, keyed by (step j, mode, Chebyshev
-  // degree); they hold the workspace pointers above, so any reallocation or
+  // Arnoldi steps captured as graphs, keyed by (step j, mode, smoothing
+  // degrees); they hold the workspace pointers above, so any reallocation or
   // change of a level's kernel shape drops them.
   std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
   hipStream_t gstream = nullptr;  // capture/replay stream (default priority)
@@ -156,6 +156,20 @@ void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStr
 void vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s);  // FP64, [2][N] in/out
 void level_spmv(dpp_precond pc, int level, int net, const double *x, double *y, hipStream_t s);
 void precond_make32(dpp_precond pc, hipStream_t s);
+// Chebyshev degrees of level l's pre- and post-smoothing (the finest level or
+// a coarser one; -1 in the options means cheb_degree)
+inline int cheb_pre(const dpp_solve_opts &o, int l) {
+  const int v = l == 0 ? o.cheb_pre_fine : o.cheb_pre_coarse;
+  return v < 0 ? o.cheb_degree : v;
+}
+inline int cheb_post(const dpp_solve_opts &o, int l) {
+  const int v = l == 0 ? o.cheb_post_fine : o.cheb_post_coarse;
+  return v < 0 ? o.cheb_degree : v;
+}
+// identifies the V-cycle's smoothing degrees (part of a captured graph's key)
+inline int cycle_code(const dpp_solve_opts &o) {
+  return ((cheb_pre(o, 0) * 16 + cheb_post(o, 0)) * 16 + cheb_pre(o, 1)) * 16 + cheb_post(o, 1);
+}
 
 // --- krylov.hip
 struct SolveResult {

@@ -28,17 +28,20 @@ def uneven_2d(count=8, seed=77):
     return out
 
 
-def test_batch_operator_and_preconditioner_match_single_path():
+@pytest.mark.parametrize("cycle", [None, (2, 2, 1, 2)])
+def test_batch_operator_and_preconditioner_match_single_path(cycle):
     import paper_1808_08328_amd as dpp
     probs = uneven_2d()
-    B = dpp.assemble_batch(probs, coarse_max=30)
+    names = ("cheb_pre_fine", "cheb_post_fine", "cheb_pre_coarse", "cheb_post_coarse")
+    kw = dict(zip(names, cycle)) if cycle else {}
+    B = dpp.assemble_batch(probs, coarse_max=30, **kw)
     x = torch.as_tensor(I.random_vector(B.n_dof, 3), device="cuda")
     yb = [H(v) for v in B.split(B.spmv(x))]
     zb = [H(v) for v in B.split(B.precond_apply(x))]
     xs = B.split(x)
     for i, pr in enumerate(probs):
         P = dpp.assemble_problem(pr)
-        pc = P.setup_precond(coarse_max=30)
+        pc = P.setup_precond(coarse_max=30, **kw)
         ys = H(P.spmv(xs[i].contiguous()))
         assert np.abs(yb[i] - ys).max() <= 1e-13 * np.abs(ys).max(), ("spmv", i)
         zs = H(pc.apply(xs[i].contiguous()))
@@ -78,10 +81,12 @@ def test_batch_graph_replay_is_bit_identical():
     assert [s.iters for s in s1] == [s.iters for s in s2] == [s.iters for s in s3]
 
 
-def test_batch_fp32_preconditioner_and_3d():
+@pytest.mark.parametrize("cycle", [None, (2, 2, 1, 2)])
+def test_batch_fp32_preconditioner_and_3d(cycle):
     import paper_1808_08328_amd as dpp
     probs = [I.grf_problem(3, 5), I.mms_problem(3, (6, 4, 5), k2=1e-2), I.grf_problem(3, 7)]
-    B = dpp.assemble_batch(probs, coarse_max=40)
+    names = ("cheb_pre_fine", "cheb_post_fine", "cheb_pre_coarse", "cheb_post_coarse")
+    B = dpp.assemble_batch(probs, coarse_max=40, **(dict(zip(names, cycle)) if cycle else {}))
     for precision in (0, 2):
         x, st = B.solve(rtol=1e-10, precision=precision)
         assert all(s.converged for s in st)

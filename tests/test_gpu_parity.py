@@ -126,6 +126,33 @@ def test_multigrid_hierarchy_and_cycle_match_oracle(case, cmax):
     assert relmax(H(pc.apply(T(r))), F.apply(r)) <= 1e-11
 
 
+@pytest.mark.parametrize("cycle", [(2, 2, 2, 2), (1, 2, 2, 1), (0, 2, 1, 3), (3, 1, 0, 2)])
+def test_vcycle_variants_match_oracle(cycle):
+    """Pre/post smoothing degrees per level class (pre > 0 runs the fused
+    first Chebyshev steps, the residual and the fused restriction), against
+    the oracle's cycle of the same degrees: cycle, fieldsplit apply, solve."""
+    prob = CASES["3d_8_mms"]()
+    S = odpp.assemble(prob)
+    names = ("pre_fine", "post_fine", "pre_coarse", "post_coarse")
+    mo = omg.MGOptions(coarse_max=40, **dict(zip(names, cycle)))
+    P = lib().assemble_problem(prob)
+    pc = P.setup_precond(coarse_max=40, **{"cheb_" + k: v for k, v in zip(names, cycle)})
+    assert pc.info()["levels"] == 3
+    Hs = [omg.setup(sp_, 3, prob.n, mo) for sp_ in odpp.selfp(S)]
+    N = P.n_nodes
+    b = I.random_vector(2 * N, 31)
+    xg = H(pc.vcycle(T(b)))
+    for i in range(2):
+        assert relmax(xg[i * N:(i + 1) * N], omg.vcycle(Hs[i], b[i * N:(i + 1) * N])) <= 1e-11, i
+    F = osolver.FieldSplit(S, mo)
+    r = I.random_vector(P.n_dof, 32)
+    assert relmax(H(pc.apply(T(r))), F.apply(r)) <= 1e-11
+    xo = odpp.solve_direct(S.K, S.f)
+    x, st = P.solve(pc, rtol=1e-12)
+    assert st.converged
+    assert np.linalg.norm(H(x) - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
 @pytest.mark.parametrize("case", ["2d_ragged_grf", "3d_8_mms"])
 def test_every_level_kernel_shape_matches_oracle(case):
     """All lanes-per-row (0 = two rows per lane) / symmetric-storage variants

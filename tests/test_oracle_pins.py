@@ -338,22 +338,42 @@ def test_chebyshev_degree_one_is_damped_jacobi_and_converges():
 def test_vcycle_symmetric_and_contracting():
     S = dpp.assemble(I.mms_problem(3, 8, k2=1e-2))
     A = dpp.selfp(S)[1]
-    H = mg.setup(A, 3, (8, 8, 8), mg.MGOptions(coarse_max=50))
+    # equal pre- and post-smoothing: the cycle is a symmetric operator
+    sym = mg.MGOptions(coarse_max=50, pre_fine=2, post_fine=2, pre_coarse=2, post_coarse=2)
+    H = mg.setup(A, 3, (8, 8, 8), sym)
     assert len(H.levels) == 3
     x, y = I.random_vector(A.shape[0], 1), I.random_vector(A.shape[0], 2)
     assert abs(mg.vcycle(H, x) @ y - x @ mg.vcycle(H, y)) < 1e-11 * np.linalg.norm(x) ** 2
-    # error contraction of the stationary iteration e <- (I - V A) e
-    e = I.random_vector(A.shape[0], 3)
-    for _ in range(5):
+    # error contraction of the stationary iteration e <- (I - V A) e, for the
+    # symmetric cycle and the default post-smoothing-only cycle
+    for opts in (sym, mg.MGOptions(coarse_max=50)):
+        H = mg.setup(A, 3, (8, 8, 8), opts)
+        e = I.random_vector(A.shape[0], 3)
+        for _ in range(5):
+            e = e - mg.vcycle(H, A @ e)
+        e0 = e.copy()
         e = e - mg.vcycle(H, A @ e)
-    e0 = e.copy()
-    e = e - mg.vcycle(H, A @ e)
-    assert np.sqrt(e @ (A @ e)) < 0.5 * np.sqrt(e0 @ (A @ e0))
+        assert np.sqrt(e @ (A @ e)) < 0.5 * np.sqrt(e0 @ (A @ e0)), opts
     # one level = exact inverse
     H1 = mg.setup(A, 3, (8, 8, 8), mg.MGOptions(coarse_max=10 ** 6))
     assert len(H1.levels) == 1
     b = I.random_vector(A.shape[0], 4)
     assert np.linalg.norm(A @ mg.vcycle(H1, b) - b) < 1e-11 * np.linalg.norm(b)
+
+
+def test_post_only_two_grid_cycle_is_smoother_after_coarse_correction():
+    """Without pre-smoothing, a two-level cycle is x = S_post(b; x0 = P Ac^-1
+    P^T b): its error operator is E = M^post (I - P Ac^-1 P^T A), with the
+    Chebyshev error polynomial M of the post-smoother, so applying the cycle to
+    A e for e in range(P) (where the coarse correction is exact) leaves only
+    the smoother's action on a zero error: V A e = e."""
+    S = dpp.assemble(I.mms_problem(2, 12))
+    A = dpp.selfp(S)[0]
+    H = mg.setup(A, 2, (12, 12), mg.MGOptions(coarse_max=60))
+    assert len(H.levels) == 2
+    ec = I.random_vector(H.levels[1].A.shape[0], 8)
+    e = H.levels[0].P @ ec
+    assert np.linalg.norm(mg.vcycle(H, A @ e) - e) < 1e-11 * np.linalg.norm(e)
 
 
 def test_fieldsplit_with_exact_blocks_is_exact_inverse():
