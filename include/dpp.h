@@ -92,9 +92,11 @@ typedef struct {
  *   inner_rtol [1e-4], max_refine [20]: mixed mode only.
  *   coarse_max [1000]: coarsest multigrid level has at most this many nodes
  *     (1..4000).
- *   cheb_degree [2], cheb_lo_frac [0.3], cheb_hi_factor [1.1], power_iters [15]:
+ *   cheb_degree [2], cheb_lo_frac [0], cheb_hi_factor [1.1], power_iters [15]:
  *     Chebyshev smoother (degree used where a level's degree below is -1) and
- *     its eigenvalue estimate.
+ *     its interval [cheb_lo_frac hi, hi], hi = cheb_hi_factor x the estimate
+ *     from power_iters power steps; cheb_lo_frac 0 = by dimension (0.1 in 3D,
+ *     0.3 in 2D).
  *   use_graph [0]: capture one Arnoldi step in a hipGraph and replay it.
  *   cheb_pre_fine [0], cheb_post_fine [3], cheb_pre_coarse [0],
  *   cheb_post_coarse [3]: Chebyshev degrees of the V-cycle's pre- and

@@ -114,7 +114,7 @@ def chebyshev(A, dinv, b, x, degree, lo, hi):
 class MGOptions:
     coarse_max: int = 1000
     degree: int = 2
-    lo_frac: float = 0.3
+    lo_frac: float = 0.0   # 0 = by dimension: 0.1 in 3D, 0.3 in 2D
     hi_factor: float = 1.1
     power_iters: int = 15
     # Chebyshev degrees of pre- and post-smoothing on the finest level and on
@@ -166,7 +166,7 @@ def setup(A, dim, n, opts=None):
         lev.dinv = 1.0 / A.diagonal()
         lam = power_lambda(A, lev.dinv, opts.power_iters)
         lev.hi = opts.hi_factor * lam
-        lev.lo = opts.lo_frac * lev.hi
+        lev.lo = (opts.lo_frac if opts.lo_frac > 0 else (0.1 if dim == 3 else 0.3)) * lev.hi
         lev.P = interpolation(dim, n)
         A = (lev.P.T @ A @ lev.P).tocsr()
         n = nc

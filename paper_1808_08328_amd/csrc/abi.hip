@@ -46,7 +46,8 @@ void check_opts(const dpp_solve_opts &o) {
     DPP_CHECK(v >= -1 && v <= 8, DPP_ERR_ARG, "pre-smoothing degrees must be -1 or 0..8");
   for (int v : {o.cheb_post_fine, o.cheb_post_coarse})
     DPP_CHECK(v == -1 || (v >= 1 && v <= 8), DPP_ERR_ARG, "post-smoothing degrees must be -1 or 1..8");
-  DPP_CHECK(o.cheb_lo_frac > 0.0 && o.cheb_lo_frac < 1.0, DPP_ERR_ARG, "cheb_lo_frac must be in (0,1)");
+  DPP_CHECK(o.cheb_lo_frac >= 0.0 && o.cheb_lo_frac < 1.0, DPP_ERR_ARG,
+            "cheb_lo_frac must be 0 (by dimension) or in (0,1)");
   DPP_CHECK(o.cheb_hi_factor >= 1.0, DPP_ERR_ARG, "cheb_hi_factor must be >= 1");
   DPP_CHECK(o.power_iters >= 1, DPP_ERR_ARG, "power_iters must be >= 1");
 }
@@ -76,7 +77,7 @@ void dpp_default_opts(dpp_solve_opts *o) {
   o->cheb_post_fine = 3;
   o->cheb_pre_coarse = 0;
   o->cheb_post_coarse = 3;
-  o->cheb_lo_frac = 0.3;
+  o->cheb_lo_frac = 0.0;
   o->cheb_hi_factor = 1.1;
   o->power_iters = 15;
   o->use_graph = 0;

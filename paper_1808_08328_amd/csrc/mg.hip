@@ -569,7 +569,9 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
       DPP_CHECK(std::isfinite(lam[q]) && lam[q] > 0.0, DPP_ERR_NUMERIC,
                 "multigrid eigenvalue estimate failed");
       L.hi[q] = o.cheb_hi_factor * lam[q];
-      L.lo[q] = o.cheb_lo_frac * L.hi[q];
+      // lower end of the interval: given, or by dimension (0.1 in 3D, 0.3 in 2D)
+      const double lof = o.cheb_lo_frac > 0.0 ? o.cheb_lo_frac : (D == 3 ? 0.1 : 0.3);
+      L.lo[q] = lof * L.hi[q];
     }
     auto C = std::make_unique<Level>();
     C->g = gc;
