@@ -98,7 +98,7 @@ typedef struct {
  *     from power_iters power steps; cheb_lo_frac 0 = by dimension (0.1 in 3D,
  *     0.3 in 2D).
  *   use_graph [0]: capture one Arnoldi step in a hipGraph and replay it.
- *   cheb_pre_fine [0], cheb_post_fine [3], cheb_pre_coarse [0],
+ *   cheb_pre_fine [0], cheb_post_fine [2], cheb_pre_coarse [0],
  *   cheb_post_coarse [3]: Chebyshev degrees of the V-cycle's pre- and
  *     post-smoothing on the finest level and on the coarser smoothing levels;
  *     -1 = cheb_degree.  A pre degree of 0 skips pre-smoothing (the level

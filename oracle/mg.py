@@ -120,7 +120,7 @@ class MGOptions:
     # Chebyshev degrees of pre- and post-smoothing on the finest level and on
     # the coarser smoothing levels (-1 = degree; pre 0 = no pre-smoothing)
     pre_fine: int = 0
-    post_fine: int = 3
+    post_fine: int = 2
     pre_coarse: int = 0
     post_coarse: int = 3
 

@@ -126,7 +126,7 @@ def test_multigrid_hierarchy_and_cycle_match_oracle(case, cmax):
     assert relmax(H(pc.apply(T(r))), F.apply(r)) <= 1e-11
 
 
-@pytest.mark.parametrize("cycle", [(2, 2, 2, 2), (1, 2, 2, 1), (0, 2, 1, 3), (3, 1, 0, 2)])
+@pytest.mark.parametrize("cycle", [(2, 2, 2, 2), (1, 2, 2, 1), (0, 2, 1, 3), (3, 1, 0, 2), (0, 3, 0, 3)])
 def test_vcycle_variants_match_oracle(cycle):
     """Pre/post smoothing degrees per level class (pre > 0 runs the fused
     first Chebyshev steps, the residual and the fused restriction), against
