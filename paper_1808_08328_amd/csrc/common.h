@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -265,6 +266,41 @@ __device__ inline int xcd_block(int bid, int nblk) {
 }
 
 inline int blocks_for(long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// Column order of workgroups over node blocks [j*bs, (j+1)*bs), j < ceil(N/bs):
+// returns order[i] = the node block of workgroup i.  MI355X deals consecutive
+// workgroups round-robin to its 8 XCDs, each with its own 4 MB L2.  A stencil
+// product that reads values of the nodes a +- o (up to one node plane away)
+// finds them in L2 when both nodes are processed on the same XCD, so XCD x
+// (workgroups i with i % 8 == x) is given the blocks that start in the x-th
+// eighth of a node plane, in plane order.  Bands that hold more blocks than
+// their XCD's share pass the surplus to the free places.  plane = N gives one
+// contiguous range per XCD.
+inline std::vector<int> block_column_order(long N, int bs, long plane) {
+  const long nb = (N + bs - 1) / bs;
+  std::vector<std::vector<int>> band(8);
+  for (long j = 0; j < nb; ++j)
+    band[std::min(7L, ((j * bs) % plane) * 8 / plane)].push_back((int)j);
+  std::vector<int> order(nb, -1), rest;
+  std::vector<size_t> taken(8, 0);
+  for (long i = 0; i < nb; ++i) {
+    const size_t q = (size_t)(i / 8);
+    const std::vector<int> &b = band[i % 8];
+    if (q < b.size()) {
+      order[i] = b[q];
+      taken[i % 8] = q + 1;
+    }
+  }
+  for (int x = 0; x < 8; ++x) rest.insert(rest.end(), band[x].begin() + taken[x], band[x].end());
+  size_t k = 0;
+  for (long i = 0; i < nb; ++i)
+    if (order[i] < 0) {
+      DPP_CHECK(k < rest.size(), DPP_ERR_ARG, "internal: workgroup order is not a permutation");
+      order[i] = rest[k++];
+    }
+  DPP_CHECK(k == rest.size(), DPP_ERR_ARG, "internal: workgroup order is not a permutation");
+  return order;
+}
 
 // Two per-network pointers, passed by value.
 template <typename T>

@@ -160,28 +160,33 @@ __global__ __launch_bounds__(256, 4) void k_cheb(GridDev g, const TV *__restrict
     }                                                       \
   } while (0)
 
+// Level stencil kernels run in one-wave workgroups: at 64^3 the finest level
+// is a single round of workgroups, and small workgroups spread it (and the
+// much smaller coarse levels) evenly over the 256 CUs.
+constexpr int LBS = 64;
+
 // threads of a level launch: lpr lanes per row, or one thread per row pair (lpr = 0)
 inline long shape_threads(Shape sh, long N) { return sh.lpr > 0 ? N * sh.lpr : (N + 1) / 2; }
 
 template <int D, typename TV, typename TX>
 void launch_lspmv(Shape sh, const Grid &gl, hipStream_t s, const TV *A, const TX *x, TX *y,
                   const TX *b, const TV *dinv, bool fine = false) {
-  const dim3 grid(blocks_for(shape_threads(sh, gl.N), 256), 2);
+  const dim3 grid(blocks_for(shape_threads(sh, gl.N), LBS), 2);
   if (fine)
-    DPP_SHAPE_SWITCH(sh, (k_lspmv<D, TV, TX, L_, S_, true><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv)));
+    DPP_SHAPE_SWITCH(sh, (k_lspmv<D, TV, TX, L_, S_, true><<<grid, LBS, 0, s>>>(dev(gl), A, x, y, b, dinv)));
   else
-    DPP_SHAPE_SWITCH(sh, (k_lspmv<D, TV, TX, L_, S_, false><<<grid, 256, 0, s>>>(dev(gl), A, x, y, b, dinv)));
+    DPP_SHAPE_SWITCH(sh, (k_lspmv<D, TV, TX, L_, S_, false><<<grid, LBS, 0, s>>>(dev(gl), A, x, y, b, dinv)));
 }
 
 template <int D, typename TV, typename TX>
 void launch_cheb(Shape sh, const Grid &gl, hipStream_t s, const TV *A, const TV *di, const TX *b,
                  const TX *xin, TX *xout, TX *d, Sc2 c1, Sc2 c2, bool fine) {
-  const dim3 grid(blocks_for(shape_threads(sh, gl.N), 256), 2);
+  const dim3 grid(blocks_for(shape_threads(sh, gl.N), LBS), 2);
   if (fine)
-    DPP_SHAPE_SWITCH(sh, (k_cheb<D, TV, TX, L_, S_, true><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin,
+    DPP_SHAPE_SWITCH(sh, (k_cheb<D, TV, TX, L_, S_, true><<<grid, LBS, 0, s>>>(dev(gl), A, di, b, xin,
                                                                                 xout, d, c1, c2)));
   else
-    DPP_SHAPE_SWITCH(sh, (k_cheb<D, TV, TX, L_, S_, false><<<grid, 256, 0, s>>>(dev(gl), A, di, b, xin,
+    DPP_SHAPE_SWITCH(sh, (k_cheb<D, TV, TX, L_, S_, false><<<grid, LBS, 0, s>>>(dev(gl), A, di, b, xin,
                                                                                  xout, d, c1, c2)));
 }
 

@@ -62,6 +62,7 @@ struct dpp_problem_s {
   dpp::DBuf kvals;      // [nv][ns][N] FP64, every kind on every offset (assembly, selfp, export)
   dpp::DBuf kh;         // half storage (layout KH<dim>) read by the hot kernels
   dpp::DBuf kh32;       // FP32 copy of kh (mixed precision), made on demand
+  dpp::DBuf korder;     // [blocks] node block of each K-product workgroup (column order)
   dpp::DBuf f;          // [n_dof]
   dpp::DBuf dinv;       // [2][N] 1/diag(K_uu^i)
   dpp::DBuf k1, k2, betac;  // coefficient copies [n_cells] for the gradient

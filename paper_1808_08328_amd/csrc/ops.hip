@@ -8,6 +8,9 @@
 // and takes the other half from the neighbours' rows, which are at most one
 // node plane away and mostly served from L2.  Assembly, selfp and the CSR
 // export read the full node-pair storage.
+#include <algorithm>
+#include <vector>
+
 #include "objects.h"
 #include "profile.h"
 #include "stencil.h"
@@ -16,13 +19,18 @@ namespace dpp {
 
 namespace {
 
+// One workgroup per 64-node slice of kh (KBS threads); order[] gives the
+// slice of each workgroup (column order, below).
+constexpr int KBS = 64;
+
 template <int D, typename TV>
 __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict__ kv,
                                                 const double *__restrict__ x,
                                                 const double *__restrict__ bsub,
-                                                double *__restrict__ y) {
+                                                double *__restrict__ y,
+                                                const int *__restrict__ order) {
   const long N = g.N;
-  const long a = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const long a = (long)order[blockIdx.x] * KBS + threadIdx.x;
   if (a >= N) return;
   double au[2][D], ap[2];
   spmv_K_node<D, TV>(g, kv, x, a, au, ap);
@@ -221,18 +229,19 @@ static double kbytes(const Grid &g, bool fp32, bool resid) {
 
 void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32) {
   const Grid &g = P->g;
-  const int nb = blocks_for(g.N, 256);
+  const int nb = blocks_for(g.N, KBS);
+  const int *ord = P->korder.as<int>();
   ProfScope ps(PF_SPMV_K, kbytes(g, fp32, false), s);
   if (g.dim == 3) {
     if (fp32)
-      k_spmv_K<3, float><<<nb, 256, 0, s>>>(dev(g), P->kh32.as<float>(), x, nullptr, y);
+      k_spmv_K<3, float><<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, nullptr, y, ord);
     else
-      k_spmv_K<3, double><<<nb, 256, 0, s>>>(dev(g), P->kh.as<double>(), x, nullptr, y);
+      k_spmv_K<3, double><<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, nullptr, y, ord);
   } else {
     if (fp32)
-      k_spmv_K<2, float><<<nb, 256, 0, s>>>(dev(g), P->kh32.as<float>(), x, nullptr, y);
+      k_spmv_K<2, float><<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, nullptr, y, ord);
     else
-      k_spmv_K<2, double><<<nb, 256, 0, s>>>(dev(g), P->kh.as<double>(), x, nullptr, y);
+      k_spmv_K<2, double><<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, nullptr, y, ord);
   }
   check_launch("spmv_K");
 }
@@ -240,18 +249,19 @@ void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32)
 void residual_K(dpp_problem P, const double *b, const double *x, double *r, hipStream_t s,
                 bool fp32) {
   const Grid &g = P->g;
-  const int nb = blocks_for(g.N, 256);
+  const int nb = blocks_for(g.N, KBS);
+  const int *ord = P->korder.as<int>();
   ProfScope ps(PF_SPMV_K, kbytes(g, fp32, true), s);
   if (g.dim == 3) {
     if (fp32)
-      k_spmv_K<3, float><<<nb, 256, 0, s>>>(dev(g), P->kh32.as<float>(), x, b, r);
+      k_spmv_K<3, float><<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, b, r, ord);
     else
-      k_spmv_K<3, double><<<nb, 256, 0, s>>>(dev(g), P->kh.as<double>(), x, b, r);
+      k_spmv_K<3, double><<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, b, r, ord);
   } else {
     if (fp32)
-      k_spmv_K<2, float><<<nb, 256, 0, s>>>(dev(g), P->kh32.as<float>(), x, b, r);
+      k_spmv_K<2, float><<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, b, r, ord);
     else
-      k_spmv_K<2, double><<<nb, 256, 0, s>>>(dev(g), P->kh.as<double>(), x, b, r);
+      k_spmv_K<2, double><<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, b, r, ord);
   }
   check_launch("residual_K");
 }
@@ -296,6 +306,13 @@ void make_kh(dpp_problem P, hipStream_t s) {
   else
     k_pack_kh<2><<<blocks_for(work, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->kh.as<double>());
   check_launch("pack K half storage");
+  // K product workgroups in column order (block_column_order)
+  const long plane = g.dim == 3 ? (long)g.m[0] * g.m[1] : g.N;
+  const std::vector<int> order = block_column_order(g.N, KBS, plane);
+  const long nb = (long)order.size();
+  P->korder.alloc(sizeof(int) * nb);
+  DPP_HIP(hipMemcpyAsync(P->korder.ptr, order.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+  DPP_HIP(hipStreamSynchronize(s));
 }
 
 void make_k32(dpp_problem P, hipStream_t s) {
