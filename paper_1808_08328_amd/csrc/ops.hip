@@ -101,19 +101,22 @@ __global__ void k_pack_kh(GridDev g, const double *__restrict__ kv, double *__re
   if (idx >= (long)L::streams * N) return;
   const int st = (int)(idx / N);
   const long a = idx - (long)st * N;
-  int kind, t;
+  // st enumerates (sym kind, h) then (net, c, t); dst is its place in KH<D>
+  int kind, t, dst;
   if (st < L::NSYM * L::NH) {
-    const int k = st / L::NH;
-    t = st % L::NH + L::S0;
+    const int k = st / L::NH, h = st % L::NH;
+    t = h + L::S0;
     kind = k == L::UU0 ? kv_uu(D, 0) : k == L::UU1 ? kv_uu(D, 1) : k == L::PP0 ? kv_pp(D, 0)
          : k == L::PP1 ? kv_pp(D, 1) : kv_12(D);
+    dst = L::sym(k, h);
   } else {
     const int r = st - L::NSYM * L::NH;
     const int qc = r / L::NS;
     t = r % L::NS;
     kind = kv_up(D, qc / D, qc % D);
+    dst = L::up(qc / D, qc % D, t);
   }
-  kh[L::at(st, a)] = kv[kind * vs + (size_t)t * ld + a];
+  kh[L::at(dst, a)] = kv[kind * vs + (size_t)t * ld + a];
 }
 
 // selfp Schur block (eqs. S4_sp1, S4_sp2):
