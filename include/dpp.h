@@ -215,6 +215,24 @@ dpp_status dpp_solve_adjoint(dpp_problem prob, dpp_precond pc, const dpp_solve_o
 dpp_status dpp_param_grad(dpp_problem prob, const double *x, const double *lambda,
                           double *g_logk1, double *g_logk2, double *g_beta, void *stream);
 
+/* L2 errors ||u_h - u||_L2 (section "Performance spectrum modeling", mesh
+ * convergence) of a solution x [n_dof] (device) against the manufactured
+ * solution of the two- and three-dimensional studies (section "Representative
+ * numerical results") with parameters mms = {k1, k2, beta, mu} (host, all
+ * > 0), integrated over the problem's simplices with the q-point
+ * conical-product Gauss rule (q^d points per simplex, 1 <= q <= 16).  err
+ * (host, [4]) receives the errors of u1, p1, u2, p2.  The 3D micro-pressure
+ * uses mu/(beta k2) (the pair that solves the mass balances).  Synchronises
+ * the stream; allocates its scratch per call. */
+dpp_status dpp_mms_l2_errors(dpp_problem prob, const double *x, const double mms[4], int q,
+                             double err[4], void *stream);
+
+/* Host only (no GPU): the conical-product Gauss rule of dpp_mms_l2_errors on
+ * the reference simplex of dimension dim (2 or 3): lam [q^dim][dim+1]
+ * barycentric points and w [q^dim] weights (summing to 1/dim!), caller-owned
+ * host arrays. */
+dpp_status dpp_simplex_rule(int dim, int q, double *lam, double *w);
+
 /* Kernel-family timing (instrumentation, for benchmarks): while enabled,
  * launches of the families below are bracketed by HIP events on the stream
  * they run on, and the algorithmic bytes each launch must move (matrix

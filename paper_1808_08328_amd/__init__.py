@@ -10,5 +10,5 @@ library.  The binding fails loudly when the library is not built.
 from ._binding import (  # noqa: F401
     DppError, Problem, Precond, SolveStats, assemble, assemble_problem, default_opts,
     lib, lib_path, DppSolve, STATUS, profile_enable, profile_read, PROFILE_FAMILIES,
-    Batch, assemble_batch,
+    Batch, assemble_batch, simplex_rule,
 )

@@ -76,6 +76,8 @@ def lib():
         "dpp_solve": (C.c_int, [P, P, C.POINTER(_Opts), P, P, C.POINTER(SolveStats), P]),
         "dpp_solve_adjoint": (C.c_int, [P, P, C.POINTER(_Opts), P, P, C.POINTER(SolveStats), P]),
         "dpp_param_grad": (C.c_int, [P, P, P, P, P, P, P]),
+        "dpp_mms_l2_errors": (C.c_int, [P, P, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double), P]),
+        "dpp_simplex_rule": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "dpp_profile_enable": (C.c_int, [C.c_int]),
         "dpp_profile_read": (C.c_int, [C.c_int, I64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "dpp_assemble_batch": (C.c_int, [C.c_int, C.POINTER(_Box), C.POINTER(_Params),
@@ -255,6 +257,25 @@ class Problem:
                                     _stream(stream)))
         return g1, g2, gb
 
+    def mms_l2_errors(self, x, mms, q=4, stream=None):
+        """dpp_mms_l2_errors: {'u1', 'p1', 'u2', 'p2'} L2 errors of x against the
+        manufactured solution with mms = (k1, k2, beta, mu)."""
+        m = (C.c_double * 4)(*[float(v) for v in mms])
+        e = (C.c_double * 4)()
+        _check(lib().dpp_mms_l2_errors(self.handle, _ptr(x), m, int(q), e, _stream(stream)))
+        return dict(zip(("u1", "p1", "u2", "p2"), list(e)))
+
+
+
+def simplex_rule(dim, q):
+    """dpp_simplex_rule (host only): barycentric points [q^dim, dim+1] and
+    weights [q^dim] of the conical-product Gauss rule."""
+    import numpy as np
+    nq = q ** dim
+    lam = (C.c_double * (nq * (dim + 1)))()
+    w = (C.c_double * nq)()
+    _check(lib().dpp_simplex_rule(int(dim), int(q), lam, w))
+    return np.array(lam[:]).reshape(nq, dim + 1), np.array(w[:])
 
 def assemble(dim, n, k1, k2, p0_1, p0_2, beta=1.0, mu=1.0, L=None, body=None, beta_cells=None,
              stream=None):

@@ -356,6 +356,24 @@ dpp_status dpp_param_grad(dpp_problem P, const double *x, const double *lambda, 
   });
 }
 
+dpp_status dpp_mms_l2_errors(dpp_problem P, const double *x, const double mms[4], int q,
+                             double err[4], void *stream) {
+  return guard([&] {
+    DPP_CHECK(P && x && mms && err, DPP_ERR_ARG, "null argument");
+    dpp::mms_l2_errors(P, x, mms, q, err, S(stream));
+  });
+}
+
+dpp_status dpp_simplex_rule(int dim, int q, double *lam, double *w) {
+  return guard([&] {
+    DPP_CHECK(lam && w && (dim == 2 || dim == 3) && q >= 1 && q <= 16, DPP_ERR_ARG, "bad argument");
+    std::vector<double> l, ww;
+    dpp::simplex_rule(dim, q, l, ww);
+    std::copy(l.begin(), l.end(), lam);
+    std::copy(ww.begin(), ww.end(), w);
+  });
+}
+
 dpp_status dpp_assemble_batch(int nb, const dpp_box *boxes, const dpp_params *params,
                               const dpp_solve_opts *opts, void *stream, dpp_batch *out) {
   return guard([&] {

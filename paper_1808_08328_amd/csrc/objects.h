@@ -154,6 +154,11 @@ void schur_velocity(dpp_problem P, const double *r, const void *zp, bool fp32, d
 // --- mg.hip
 void precond_setup(dpp_precond pc, hipStream_t s);
 void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStream_t s);
+// L2 errors against the manufactured solution (err: u1, p1, u2, p2) and the
+// conical-product Gauss rule they use
+void mms_l2_errors(dpp_problem P, const double *x, const double mms[4], int q, double err[4],
+                   hipStream_t s);
+void simplex_rule(int dim, int q, std::vector<double> &lam, std::vector<double> &w);
 void vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s);  // FP64, [2][N] in/out
 void level_spmv(dpp_precond pc, int level, int net, const double *x, double *y, hipStream_t s);
 void precond_make32(dpp_precond pc, hipStream_t s);

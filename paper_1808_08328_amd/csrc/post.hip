@@ -1,0 +1,264 @@
+// Post-processing for the time-accuracy-size study (section "Performance
+// spectrum modeling"): L2 errors ||u_h - u||_L2 of a discrete solution against
+// the manufactured solutions of the two- and three-dimensional studies
+// (section "Representative numerical results"), per field u1, p1, u2, p2.
+//
+// The error integral is taken over the Kuhn simplices of the box (the cells of
+// the assembly) with a conical-product Gauss rule (Stroud 1971): Gauss-Legendre
+// nodes on [0, 1] in each collapsed coordinate of the simplex, q^d points per
+// simplex.  One thread per simplex loops over the points; per-workgroup partial
+// sums are added in a fixed order (bit-reproducible).
+#include <cmath>
+#include <vector>
+
+#include "objects.h"
+
+namespace dpp {
+
+namespace {
+
+constexpr int PBS = 256;   // threads per workgroup of the error kernel
+constexpr int QMAX = 16;   // largest rule order (16^3 points per simplex)
+
+struct MMS {
+  double k1, k2, beta, mu, eta;
+};
+
+// Manufactured solution at X: pressures p1, p2 and velocities u_i = -(k_i/mu)
+// grad p_i.  2D:  p_{1,2} = (mu/pi) e^{pi x} sin(pi y) -+ mu/(beta k_{1,2}) e^{eta y};
+// 3D:  p_{1,2} = (mu/pi) e^{pi x} (sin(pi y) + sin(pi z))
+//                -+ mu/(beta k_{1,2}) (e^{eta y} + e^{eta z}),
+// eta = sqrt(beta (k1 + k2) / (k1 k2)).  The 3D micro-pressure uses
+// mu/(beta k2), the value for which the pair solves the mass balances.
+template <int D>
+__device__ inline void mms_exact(const MMS &m, const double *X, double &p1, double &p2,
+                                 double *u1, double *u2) {
+  const double pi = 3.14159265358979323846;
+  const double ex = exp(pi * X[0]);
+  const double a1 = m.mu / (m.beta * m.k1), a2 = m.mu / (m.beta * m.k2);
+  double sy, cy, sz = 0.0, cz = 0.0;
+  sincos(pi * X[1], &sy, &cy);
+  const double ey = exp(m.eta * X[1]);
+  double ez = 0.0;
+  if constexpr (D == 3) {
+    sincos(pi * X[2], &sz, &cz);
+    ez = exp(m.eta * X[2]);
+  }
+  const double harm = ex * (sy + sz);
+  p1 = (m.mu / pi) * harm - a1 * (ey + ez);
+  p2 = (m.mu / pi) * harm + a2 * (ey + ez);
+  // grad p_i = mu [e^{pi x}(sy + sz), e^{pi x} cy -+ eta/(beta k_i) e^{eta y}, ...] / mu
+  u1[0] = -m.k1 * harm;
+  u2[0] = -m.k2 * harm;
+  u1[1] = -m.k1 * (ex * cy - m.eta / (m.beta * m.k1) * ey);
+  u2[1] = -m.k2 * (ex * cy + m.eta / (m.beta * m.k2) * ey);
+  if constexpr (D == 3) {
+    u1[2] = -m.k1 * (ex * cz - m.eta / (m.beta * m.k1) * ez);
+    u2[2] = -m.k2 * (ex * cz + m.eta / (m.beta * m.k2) * ez);
+  }
+}
+
+// Simplex s of box cell (ci, cj, ck) starts at the cell corner and steps along
+// the axes of permutation s (the ordering of the assembly).
+__device__ inline int perm_of(int D, int s, int k) {
+  if (D == 2) return (s == 0) ? k : 1 - k;
+  const int P[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  return P[s][k];
+}
+
+// Squared errors of simplex e, summed over the rule (lam: [nq][D+1], w: [nq]).
+template <int D>
+__global__ __launch_bounds__(PBS) void k_l2_error(GridDev g, const double *__restrict__ x,
+                                                  MMS m, const double *__restrict__ lam,
+                                                  const double *__restrict__ w, int nq,
+                                                  double hx, double hy, double hz,
+                                                  double *__restrict__ part) {
+  constexpr int NPER = D == 3 ? 6 : 2;
+  const long N = g.N;
+  const long ncell = (long)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1) * NPER;
+  const long e = (long)blockIdx.x * PBS + threadIdx.x;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // u1, p1, u2, p2
+  if (e < ncell) {
+    const int s = (int)(e % NPER);
+    long hex = e / NPER;
+    const int ci = (int)(hex % g.n[0]);
+    hex /= g.n[0];
+    const int cj = (int)(hex % g.n[1]);
+    const int ck = D == 3 ? (int)(hex / g.n[1]) : 0;
+    const double h[3] = {hx, hy, hz};
+    // vertices: node ids and coordinates
+    long vid[D + 1];
+    double vx[D + 1][D];
+    int ijk[3] = {ci, cj, ck};
+    for (int k = 0; k <= D; ++k) {
+      if (k > 0) ijk[perm_of(D, s, k - 1)] += 1;
+      vid[k] = ijk[0] + (long)g.m[0] * (ijk[1] + (long)g.m[1] * ijk[2]);
+      for (int c = 0; c < D; ++c) vx[k][c] = ijk[c] * h[c];
+    }
+    // nodal values of the discrete fields at the vertices
+    const long ou1 = off_u(D, N, 0), ou2 = off_u(D, N, 1);
+    const long op1 = off_p(D, N, 0), op2 = off_p(D, N, 1);
+    double vp1[D + 1], vp2[D + 1], vu1[D + 1][D], vu2[D + 1][D];
+    for (int k = 0; k <= D; ++k) {
+      vp1[k] = x[op1 + vid[k]];
+      vp2[k] = x[op2 + vid[k]];
+      for (int c = 0; c < D; ++c) {
+        vu1[k][c] = x[ou1 + D * vid[k] + c];
+        vu2[k][c] = x[ou2 + D * vid[k] + c];
+      }
+    }
+    for (int iq = 0; iq < nq; ++iq) {
+      const double *l = lam + (size_t)iq * (D + 1);
+      double X[D], hp1 = 0.0, hp2 = 0.0, hu1[D], hu2[D];
+      for (int c = 0; c < D; ++c) X[c] = hu1[c] = hu2[c] = 0.0;
+      for (int k = 0; k <= D; ++k) {
+        for (int c = 0; c < D; ++c) {
+          X[c] += l[k] * vx[k][c];
+          hu1[c] += l[k] * vu1[k][c];
+          hu2[c] += l[k] * vu2[k][c];
+        }
+        hp1 += l[k] * vp1[k];
+        hp2 += l[k] * vp2[k];
+      }
+      double p1, p2, u1[3], u2[3];
+      mms_exact<D>(m, X, p1, p2, u1, u2);
+      double e1 = 0.0, e2 = 0.0;
+      for (int c = 0; c < D; ++c) {
+        e1 += (hu1[c] - u1[c]) * (hu1[c] - u1[c]);
+        e2 += (hu2[c] - u2[c]) * (hu2[c] - u2[c]);
+      }
+      acc[0] += w[iq] * e1;
+      acc[1] += w[iq] * (hp1 - p1) * (hp1 - p1);
+      acc[2] += w[iq] * e2;
+      acc[3] += w[iq] * (hp2 - p2) * (hp2 - p2);
+    }
+    // |det J| of the simplex: the product of the cell sizes (the reference
+    // simplex has volume 1/d!, carried by the weights)
+    const double detj = D == 3 ? hx * hy * hz : hx * hy;
+    for (int f = 0; f < 4; ++f) acc[f] *= detj;
+  }
+  // fixed-order workgroup sum
+  __shared__ double red[4][PBS];
+  for (int f = 0; f < 4; ++f) red[f][threadIdx.x] = acc[f];
+  __syncthreads();
+  for (int st = PBS / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int f = 0; f < 4; ++f) red[f][threadIdx.x] += red[f][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
+}
+
+// out[f] = sum over workgroups of part[f][.], in a fixed order
+__global__ __launch_bounds__(PBS) void k_l2_finish(const double *__restrict__ part, int nb,
+                                                   double *__restrict__ out) {
+  __shared__ double red[PBS];
+  const int f = blockIdx.x;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nb; i += PBS) a += part[(size_t)f * nb + i];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int st = PBS / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[f] = red[0];
+}
+
+}  // namespace
+
+// Gauss-Legendre nodes and weights on [0, 1]: Newton iteration on P_q from the
+// Chebyshev-like guesses cos(pi (i + 3/4) / (q + 1/2)), with P_q and P_q' from
+// the three-term recurrence.
+static void gauss_legendre01(int q, std::vector<double> &t, std::vector<double> &w) {
+  t.assign(q, 0.0);
+  w.assign(q, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < q; ++i) {
+    double z = std::cos(pi * (i + 0.75) / (q + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= q; ++k) {
+        const double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      const double pq = q == 1 ? z : p1, pq1 = q == 1 ? 1.0 : p0;
+      dp = q * (z * pq - pq1) / (z * z - 1.0);
+      const double dz = pq / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    // recompute P_q' at the converged node for the weight
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= q; ++k) {
+      const double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = pk;
+    }
+    const double pq = q == 1 ? z : p1, pq1 = q == 1 ? 1.0 : p0;
+    dp = q * (z * pq - pq1) / (z * z - 1.0);
+    t[q - 1 - i] = 0.5 * (z + 1.0);                        // ascending on [0, 1]
+    w[q - 1 - i] = 1.0 / ((1.0 - z * z) * dp * dp);        // 2/((1-z^2)P'^2), halved
+  }
+}
+
+// Conical-product rule on the reference simplex {lambda_1 + ... + lambda_d <= 1}:
+// collapsed coordinates s = lambda_1 + .. + lambda_d, then the share of the
+// later vertices at each stage, with Jacobian s^(d-1) (and e in 3D).
+void simplex_rule(int dim, int q, std::vector<double> &lam, std::vector<double> &wt) {
+  std::vector<double> t, w;
+  gauss_legendre01(q, t, w);
+  lam.clear();
+  wt.clear();
+  if (dim == 2) {
+    for (int a = 0; a < q; ++a)
+      for (int b = 0; b < q; ++b) {
+        const double s = t[a], e = t[b];
+        lam.insert(lam.end(), {1.0 - s, s * (1.0 - e), s * e});
+        wt.push_back(w[a] * w[b] * s);
+      }
+    return;
+  }
+  for (int a = 0; a < q; ++a)
+    for (int b = 0; b < q; ++b)
+      for (int c = 0; c < q; ++c) {
+        const double s = t[a], e = t[b], gq = t[c];
+        lam.insert(lam.end(), {1.0 - s, s * (1.0 - e), s * e * (1.0 - gq), s * e * gq});
+        wt.push_back(w[a] * w[b] * w[c] * s * s * e);
+      }
+}
+
+void mms_l2_errors(dpp_problem P, const double *x, const double mms[4], int q, double err[4],
+                   hipStream_t s) {
+  const Grid &g = P->g;
+  DPP_CHECK(q >= 1 && q <= QMAX, DPP_ERR_ARG, "quadrature order must be in 1..16");
+  DPP_CHECK(mms[0] > 0.0 && mms[1] > 0.0 && mms[2] > 0.0 && mms[3] > 0.0, DPP_ERR_ARG,
+            "manufactured-solution parameters must be positive");
+  std::vector<double> lam, wt;
+  simplex_rule(g.dim, q, lam, wt);
+  const int nq = (int)wt.size();
+  const long ncell = (long)g.nc;
+  const int nb = (int)((ncell + PBS - 1) / PBS);
+  DBuf rule(sizeof(double) * (lam.size() + wt.size()));
+  DBuf part(sizeof(double) * 4 * (size_t)nb + sizeof(double) * 4);
+  double *dl = rule.as<double>(), *dw = dl + lam.size();
+  double *dp = part.as<double>(), *dout = dp + 4 * (size_t)nb;
+  DPP_HIP(hipMemcpyAsync(dl, lam.data(), sizeof(double) * lam.size(), hipMemcpyHostToDevice, s));
+  DPP_HIP(hipMemcpyAsync(dw, wt.data(), sizeof(double) * wt.size(), hipMemcpyHostToDevice, s));
+  MMS m{mms[0], mms[1], mms[2], mms[3], std::sqrt(mms[2] * (mms[0] + mms[1]) / (mms[0] * mms[1]))};
+  if (g.dim == 3)
+    k_l2_error<3><<<nb, PBS, 0, s>>>(dev(g), x, m, dl, dw, nq, g.h[0], g.h[1], g.h[2], dp);
+  else
+    k_l2_error<2><<<nb, PBS, 0, s>>>(dev(g), x, m, dl, dw, nq, g.h[0], g.h[1], 1.0, dp);
+  check_launch("l2 error");
+  k_l2_finish<<<4, PBS, 0, s>>>(dp, nb, dout);
+  check_launch("l2 error finish");
+  double h4[4];
+  DPP_HIP(hipMemcpyAsync(h4, dout, sizeof(h4), hipMemcpyDeviceToHost, s));
+  DPP_HIP(hipStreamSynchronize(s));
+  // field order of the result: u1, p1, u2, p2
+  for (int f = 0; f < 4; ++f) err[f] = std::sqrt(std::max(h4[f], 0.0));
+}
+
+}  // namespace dpp

@@ -1,0 +1,137 @@
+"""Time-accuracy-size (TAS) spectrum of the CG-VMS DPP solver on one GPU
+(section "Performance spectrum modeling").
+
+For a ladder of box sizes the manufactured-solution problem of the 2D or 3D
+study (section "Representative numerical results") is assembled, its
+preconditioner set up and the system solved on the GPU.  Per size it reports:
+  * DoF and DoS = log10(DoF);
+  * L2 errors of u1, p1, u2, p2 (dpp_mms_l2_errors) and DoA = -log10(error);
+  * DoE = -log10(error x time), for the solve time and for the total time
+    (assembly + setup + solve);
+  * static-scaling rates DoF/s of assembly, setup, solve and the total;
+  * FGMRES iterations.
+It also fits the slope of DoA against DoS per field (alpha/d for errors that
+decay as h^alpha) and the observed convergence rates between sizes.
+
+DoS is read as log10(DoF): the section states a positive DoA-vs-DoS slope of
+alpha/d, which holds for log10(DoF) (its printed definition carries a minus).
+
+Usage, from the repository root (the input generator is the repository's
+``dpp_inputs`` module):
+    python -m paper_1808_08328_amd.tas --dim 3 --n 8 16 32 64 96 [--json out.jsonl]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+
+def _inputs():
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import dpp_inputs
+    return dpp_inputs
+
+
+FIELDS = ("u1", "p1", "u2", "p2")
+
+
+def run_size(dpp, I, torch, dim, n, mms, rtol, q, reps):
+    prob = I.mms_problem(dim, n, k1=mms[0], k2=mms[1], beta=mms[2], mu=mms[3])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = dpp.assemble_problem(prob)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pc = P.setup_precond()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    P.solve(pc, rtol=rtol)  # warm-up (graphs, workspaces)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(reps):
+        x, st = P.solve(pc, rtol=rtol)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    err = P.mms_l2_errors(x, mms, q=q)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    ndof = P.n_dof
+    ta, ts, tv = t1 - t0, t2 - t1, (t4 - t3) / reps
+    tot = ta + ts + tv
+    row = {"dim": dim, "n": n, "dof": ndof, "DoS": math.log10(ndof), "iters": st.iters,
+           "converged": bool(st.converged), "assemble_s": ta, "setup_s": ts, "solve_s": tv,
+           "total_s": tot, "l2_error_s": t5 - t4,
+           "dofs_per_s": {"assemble": ndof / ta, "setup": ndof / ts, "solve": ndof / tv,
+                          "total": ndof / tot},
+           "error": err,
+           "DoA": {f: -math.log10(err[f]) for f in FIELDS},
+           "DoE_solve": {f: -math.log10(err[f] * tv) for f in FIELDS},
+           "DoE_total": {f: -math.log10(err[f] * tot) for f in FIELDS}}
+    del pc, P
+    torch.cuda.empty_cache()
+    return row
+
+
+def slopes(rows):
+    """Least-squares slope of DoA against DoS per field, and the observed
+    rates log(e_i / e_{i+1}) / log(h_i / h_{i+1}) between consecutive sizes."""
+    out = {}
+    xs = [r["DoS"] for r in rows]
+    mx = sum(xs) / len(xs)
+    for f in FIELDS:
+        ys = [r["DoA"][f] for r in rows]
+        my = sum(ys) / len(ys)
+        sxx = sum((x - mx) ** 2 for x in xs)
+        out[f] = {"DoA_vs_DoS": sum((x - mx) * (y - my) for x, y in zip(xs, ys)) / sxx if sxx else None,
+                  "rates": [math.log(a["error"][f] / b["error"][f]) / math.log(b["n"] / a["n"])
+                            for a, b in zip(rows[:-1], rows[1:])]}
+    return out
+
+
+def table(rows):
+    head = ("| n | DoF | DoS | iters | err u1 | err p1 | DoA p1 | DoE p1 (solve) | "
+            "assemble DoF/s | solve DoF/s | total DoF/s |")
+    lines = [head, "|" + "---|" * 11]
+    for r in rows:
+        lines.append("| %d | %d | %.2f | %d | %.3e | %.3e | %.2f | %.2f | %.3g | %.3g | %.3g |" % (
+            r["n"], r["dof"], r["DoS"], r["iters"], r["error"]["u1"], r["error"]["p1"],
+            r["DoA"]["p1"], r["DoE_solve"]["p1"], r["dofs_per_s"]["assemble"],
+            r["dofs_per_s"]["solve"], r["dofs_per_s"]["total"]))
+    return "\n".join(lines)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--dim", type=int, default=3, choices=(2, 3))
+    ap.add_argument("--n", type=int, nargs="+", default=None)
+    ap.add_argument("--mms", type=float, nargs=4, default=(1.0, 0.1, 1.0, 1.0),
+                    metavar=("K1", "K2", "BETA", "MU"))
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--q", type=int, default=4, help="quadrature points per collapsed direction")
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--json", default=None, help="also write one JSON line per size here")
+    a = ap.parse_args(argv)
+    ns = a.n or ([16, 32, 64, 128, 256, 512] if a.dim == 2 else [8, 16, 32, 64, 96])
+    import torch
+    import paper_1808_08328_amd as dpp
+    I = _inputs()
+    # load the library and its kernels once before timing
+    run_size(dpp, I, torch, a.dim, 4, tuple(a.mms), a.rtol, a.q, 1)
+    rows = []
+    for n in ns:
+        r = run_size(dpp, I, torch, a.dim, n, tuple(a.mms), a.rtol, a.q, a.reps)
+        rows.append(r)
+        print(json.dumps(r), flush=True)
+        if a.json:
+            with open(a.json, "a") as fh:
+                fh.write(json.dumps(r) + "\n")
+    print(table(rows))
+    print(json.dumps({"slopes": slopes(rows)}))
+
+
+if __name__ == "__main__":
+    main()
