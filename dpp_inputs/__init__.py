@@ -38,7 +38,12 @@ class Problem:
 
     k1, k2: per-cell permeabilities [n_cells]; beta: scalar or [n_cells];
     p0_1, p0_2: nodal pressures [n_nodes] (only boundary nodes are used);
-    body: gamma*b per cell [n_cells, dim] or None.
+    body: gamma*b per cell [n_cells, dim] or None;
+    face_bc: None (every box face a pressure boundary) or int8 [2, 2*dim]:
+      face_bc[i, 2a + s] = 1 makes face s (0: x_a = 0, 1: x_a = L_a) a velocity
+      boundary of network i, whose normal velocity is prescribed;
+    u_bc_1, u_bc_2: nodal velocities [n_nodes, dim] whose normal components are
+      imposed on the velocity faces (None for a network without one).
     """
     dim: int
     n: tuple
@@ -52,6 +57,9 @@ class Problem:
     body: object = None
     gamma: float = 1.0
     meta: dict = field(default_factory=dict)
+    face_bc: object = None
+    u_bc_1: object = None
+    u_bc_2: object = None
 
     @property
     def n_nodes(self):
@@ -116,23 +124,31 @@ def mms_fields(dim, X, k1, k2, beta, mu):
     return p1, p2, u1, u2
 
 
-def mms_problem(dim, n, k1=1.0, k2=0.1, beta=1.0, mu=1.0, L=None, bc_params=None):
+def mms_problem(dim, n, k1=1.0, k2=0.1, beta=1.0, mu=1.0, L=None, bc_params=None,
+                flux_faces=None):
     """Homogeneous manufactured-solution instance: constant k1, k2, beta.
 
     bc_params (k1, k2, beta, mu) overrides the parameters used for the boundary
     pressures (heterogeneous-permeability workloads keep the homogeneous MMS
-    boundary data).
+    boundary data).  flux_faces: None, or [2, 2*dim] face flags (see Problem)
+    whose velocity faces take the exact normal velocities.
     """
     n = tuple(int(v) for v in (n if np.ndim(n) else (n,) * dim))
     L = tuple(L or (1.0,) * dim)
     nc = cells_per_box(dim) * int(np.prod(n))
     X = node_coords(dim, n, L)
     bk1, bk2, bb, bmu = bc_params or (k1, k2, beta, mu)
-    p1, p2, _, _ = mms_fields(dim, X, bk1, bk2, bb, bmu)
-    return Problem(dim=dim, n=n, L=L, mu=float(mu),
+    p1, p2, u1, u2 = mms_fields(dim, X, bk1, bk2, bb, bmu)
+    prob = Problem(dim=dim, n=n, L=L, mu=float(mu),
                    k1=np.full(nc, float(k1)), k2=np.full(nc, float(k2)),
                    beta=float(beta), p0_1=p1, p0_2=p2,
                    meta=dict(mms=(bk1, bk2, bb, bmu)))
+    if flux_faces is not None:
+        fb = np.asarray(flux_faces, dtype=np.int8).reshape(2, 2 * dim)
+        prob.face_bc = fb
+        prob.u_bc_1 = u1 if fb[0].any() else None
+        prob.u_bc_2 = u2 if fb[1].any() else None
+    return prob
 
 
 def grf_log10(n, dim, seed, mean, std, ell=0.1, L=None):

@@ -147,7 +147,55 @@ def assemble(prob, msh=None):
                    _p(rowptr), _p(cols), _p(vals), _p(f), _p(k1), _p(k2), _p(beta),
                    float(prob.mu), _p(body) if body is not None else None, _p(p01), _p(p02))
     K = sp.csr_matrix((vals, cols, rowptr), shape=(ndof, ndof))
+    if getattr(prob, "face_bc", None) is not None and np.any(prob.face_bc):
+        K, f = velocity_bc(K, f, msh, prob)
     return System(msh, K, f, float(prob.mu))
+
+
+def velocity_dofs(msh, prob):
+    """Prescribed velocity DOFs and their values (section "Boundary
+    conditions", eq. DG_GE_vBC): on a velocity face of network i (normal along
+    axis a) the normal component u_i,a of every node of the face is given,
+    from the nodal data u_bc_i.  Returns (mask [n_dof] bool, values [n_dof])."""
+    d, N, n = msh.dim, msh.N, msh.n
+    fb = np.asarray(prob.face_bc, dtype=np.int8).reshape(2, 2 * d)
+    if fb[0].all() and fb[1].all():
+        raise NotImplementedError("both networks with flux boundaries only (singular K)")
+    ids = np.arange(N)
+    ax = []
+    r = ids.copy()
+    for a in range(d):
+        ax.append(r % (n[a] + 1))
+        r //= n[a] + 1
+    fixed = np.zeros((2 * d + 2) * N, dtype=bool)
+    g = np.zeros((2 * d + 2) * N)
+    F = fields(d, N)
+    for i, fu in enumerate(("u1", "u2")):
+        ub = prob.u_bc_1 if i == 0 else prob.u_bc_2
+        for a in range(d):
+            for side in range(2):
+                if not fb[i, 2 * a + side]:
+                    continue
+                nodes = ids[ax[a] == (n[a] if side else 0)]
+                dof = F[fu].start + d * nodes + a
+                fixed[dof] = True
+                g[dof] = np.asarray(ub, dtype=np.float64).reshape(N, d)[nodes, a]
+    return fixed, g
+
+
+def velocity_bc(K, f, msh, prob):
+    """Impose the prescribed normal velocities as essential conditions: the
+    test space has w.n = 0 on the velocity faces, so their rows become identity
+    rows with the data on the right, and the known values are moved out of the
+    other rows (f - K g, columns removed).  The weak pressure term of those
+    faces sits in exactly the rows that are replaced."""
+    fixed, g = velocity_dofs(msh, prob)
+    free = (~fixed).astype(np.float64)
+    f2 = np.where(fixed, g, f - K @ g)
+    Pf = sp.diags(free)
+    K2 = (Pf @ K @ Pf + sp.diags(fixed.astype(np.float64))).tocsr()
+    K2.sort_indices()
+    return K2, f2
 
 
 def spmv(K, x):

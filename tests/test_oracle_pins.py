@@ -443,3 +443,53 @@ def test_parameter_gradient_matches_finite_differences():
     eps = 1e-5
     fd = (J_of(prob.k1, prob.k2, prob.beta + eps) - J_of(prob.k1, prob.k2, prob.beta - eps)) / (2 * eps)
     assert gb == pytest.approx(fd, rel=1e-5)
+
+
+# ---- velocity (flux) boundaries: section "Boundary conditions", eq. DG_GE_vBC
+FLUX_FACES = {2: [[1, 1, 0, 0], [0, 0, 0, 1]], 3: [[1, 0, 0, 0, 0, 1], [0, 0, 1, 1, 0, 0]]}
+
+
+def test_velocity_bc_structure():
+    """Essential normal velocities: identity rows holding the data, columns
+    removed (D K stays symmetric, so the adjoint identity K^T = D K D holds),
+    one fixed DOF per (network, node on a velocity face, face normal)."""
+    import scipy.sparse as sp
+    pr = I.mms_problem(3, (4, 3, 2), k2=0.1, flux_faces=FLUX_FACES[3])
+    S = dpp.assemble(pr)
+    fixed, g = dpp.velocity_dofs(S.mesh, pr)
+    n = pr.n
+    face_nodes = {0: (n[1] + 1) * (n[2] + 1), 1: (n[0] + 1) * (n[2] + 1), 2: (n[0] + 1) * (n[1] + 1)}
+    expect = sum(face_nodes[f // 2] for i in range(2) for f in range(6) if FLUX_FACES[3][i][f])
+    assert fixed.sum() == expect
+    Dg = sp.diags(dpp.sign_matrix(3, S.N))
+    assert abs(Dg @ S.K - (Dg @ S.K).T).max() == 0.0
+    rows = S.K[np.flatnonzero(fixed)]
+    assert (rows != sp.csr_matrix((np.ones(fixed.sum()), (np.arange(fixed.sum()), np.flatnonzero(fixed))),
+                                  shape=rows.shape)).nnz == 0
+    assert np.array_equal(S.f[fixed], g[fixed])
+    x = dpp.solve_direct(S.K, S.f)
+    assert np.array_equal(x[fixed], g[fixed])
+    with pytest.raises(NotImplementedError):
+        dpp.assemble(I.mms_problem(2, 3, flux_faces=[[1, 1, 1, 1], [1, 1, 1, 1]]))
+
+
+@pytest.mark.parametrize("dim,ns", [(2, [8, 16, 32]), (3, [4, 8, 16])])
+def test_velocity_bc_mms_convergence(dim, ns):
+    """With the exact normal velocities prescribed on some faces and the exact
+    pressures weakly on the others, the errors still decay as h^2: a wrong
+    sign in the lifting f - K g, or a weak pressure term left on a velocity
+    face, breaks the rate."""
+    errs = []
+    for n in ns:
+        pr = I.mms_problem(dim, n, k1=1.0, k2=0.1, beta=1.0, mu=1.0, flux_faces=FLUX_FACES[dim])
+        S = dpp.assemble(pr)
+        if S.K.shape[0] < 20000:
+            x = dpp.solve_direct(S.K, S.f)
+        else:  # the oracle's FGMRES with its fieldsplit built on the same K
+            x = solver.solve(S, rtol=1e-12)[0]
+        errs.append(post.l2_errors(S, x, lambda X: I.mms_fields(dim, X, 1.0, 0.1, 1.0, 1.0), q=4))
+    hs = [1 / n for n in ns]
+    for f in ("p1", "p2"):
+        assert post.rates(hs, [e[f] for e in errs])[-1] > 1.9
+    for f in ("u1", "u2"):
+        assert post.rates(hs, [e[f] for e in errs])[-1] > 1.85
