@@ -158,6 +158,12 @@ def param_gradient(system, prob, x, lam):
     d, N, mu = msh.dim, msh.N, system.mu
     F = dpp.fields(d, N)
     cells = msh.cells
+    if getattr(prob, "face_bc", None) is not None and np.any(prob.face_bc):
+        # velocity faces: K~ = P_f K P_f + P_c and f~ = P_f (f - K P_c g) + P_c g
+        # both depend on theta; with x = g on the prescribed DOFs,
+        # dJ/dtheta = lam^T (df~ - dK~ x) = -(P_f lam)^T (dK/dtheta) x
+        fixed, _ = dpp.velocity_dofs(msh, prob)
+        lam = np.where(fixed, 0.0, lam)
     X = msh.X[cells]                                    # [nc, d+1, d]
     J = np.transpose(X[:, 1:, :] - X[:, :1, :], (0, 2, 1))  # columns X_a - X_0
     det = np.linalg.det(J)
