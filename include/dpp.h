@@ -66,9 +66,17 @@ typedef struct {
  * beta: scalar mass-transfer coefficient, used when beta_cells == NULL, else
  * beta_cells [n_cells].  body: gamma*b per cell [n_cells*dim] or NULL (b = 0).
  * p0_1, p0_2: nodal pressures [n_nodes]; only boundary nodes are read, and the
- * boundary integral -(w.n; p0) uses their P1 interpolant exactly.
- * facet_type must be NULL: velocity (flux) boundaries are not implemented and
- * a non-NULL value returns DPP_ERR_UNSUPPORTED. */
+ * boundary integral -(w.n; p0) uses their P1 interpolant exactly (on the
+ * pressure faces).
+ * Velocity (flux) boundaries (eq. DG_GE_vBC): face_bc (host, int8 [2][2*dim])
+ * or NULL (every box face a pressure boundary); face_bc[i][2a + s] = 1 makes
+ * face s (0: x_a = 0, 1: x_a = L_a) a velocity boundary of network i, 0 a
+ * pressure boundary.  On a velocity face the normal velocity component of
+ * each node is prescribed (essential: identity row holding the value, the
+ * value moved out of the other rows) from u_bc_i (device, [n_nodes*dim]
+ * nodal velocities, node-major; required when network i has a velocity face,
+ * else unread).  Velocity faces on every face of both networks (a singular
+ * K) return DPP_ERR_UNSUPPORTED; batches take no velocity faces. */
 typedef struct {
   double mu;
   const double *k1;
@@ -78,7 +86,9 @@ typedef struct {
   const double *body;
   const double *p0_1;
   const double *p0_2;
-  const int8_t *facet_type;
+  const int8_t *face_bc;
+  const double *u_bc_1;
+  const double *u_bc_2;
 } dpp_params;
 
 /* Solver options; dpp_default_opts() fills the defaults in brackets.

@@ -27,7 +27,8 @@ class _Box(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("mu", C.c_double), ("k1", C.c_void_p), ("k2", C.c_void_p), ("beta", C.c_double),
                 ("beta_cells", C.c_void_p), ("body", C.c_void_p), ("p0_1", C.c_void_p),
-                ("p0_2", C.c_void_p), ("facet_type", C.c_void_p)]
+                ("p0_2", C.c_void_p), ("face_bc", C.c_void_p), ("u_bc_1", C.c_void_p),
+                ("u_bc_2", C.c_void_p)]
 
 
 class _Opts(C.Structure):
@@ -278,8 +279,9 @@ def simplex_rule(dim, q):
     return np.array(lam[:]).reshape(nq, dim + 1), np.array(w[:])
 
 def assemble(dim, n, k1, k2, p0_1, p0_2, beta=1.0, mu=1.0, L=None, body=None, beta_cells=None,
-             stream=None):
-    """dpp_assemble on device tensors (float64, contiguous)."""
+             face_bc=None, u_bc_1=None, u_bc_2=None, stream=None):
+    """dpp_assemble on device tensors (float64, contiguous); face_bc is a host
+    int8 array [2, 2*dim] (velocity faces) or None."""
     lib()
     box = _Box()
     box.dim = dim
@@ -293,7 +295,14 @@ def assemble(dim, n, k1, k2, p0_1, p0_2, beta=1.0, mu=1.0, L=None, body=None, be
     p.beta_cells = _ptr(beta_cells)
     p.body = _ptr(body)
     p.p0_1, p.p0_2 = _ptr(p0_1), _ptr(p0_2)
-    p.facet_type = None
+    fb = None
+    if face_bc is not None:
+        import numpy as np
+        fb = np.ascontiguousarray(np.asarray(face_bc, dtype=np.int8).reshape(2, 2 * dim))
+        p.face_bc = fb.ctypes.data_as(C.c_void_p)
+    else:
+        p.face_bc = None
+    p.u_bc_1, p.u_bc_2 = _ptr(u_bc_1), _ptr(u_bc_2)
     h = C.c_void_p()
     _check(lib().dpp_assemble(C.byref(box), C.byref(p), _stream(stream), C.byref(h)))
     return Problem(h, dim, n, beta_per_cell=beta_cells is not None)
@@ -309,9 +318,12 @@ def assemble_problem(prob, device="cuda", stream=None):
     body = None if prob.body is None else dv(
         (torch.as_tensor(prob.body, dtype=torch.float64) * prob.gamma).expand(prob.n_cells, prob.dim)
         .contiguous())
+    fb = getattr(prob, "face_bc", None)
+    ub = [None if getattr(prob, k, None) is None else dv(getattr(prob, k)).reshape(-1)
+          for k in ("u_bc_1", "u_bc_2")]
     return assemble(prob.dim, prob.n, dv(prob.k1), dv(prob.k2), dv(prob.p0_1), dv(prob.p0_2),
                     beta=float(beta), mu=prob.mu, L=prob.L, body=body, beta_cells=beta_cells,
-                    stream=stream)
+                    face_bc=fb, u_bc_1=ub[0], u_bc_2=ub[1], stream=stream)
 
 
 class Batch:
@@ -379,7 +391,7 @@ def assemble_batch(problems, stream=None, **opts):
         p.beta = float(pr.beta)
         p.beta_cells = None
         p.body = None
-        p.facet_type = None
+        p.face_bc = p.u_bc_1 = p.u_bc_2 = None
     o = default_opts(**opts)
     h = C.c_void_p()
     _check(lib().dpp_assemble_batch(nb, boxes, params, C.byref(o), _stream(stream), C.byref(h)))

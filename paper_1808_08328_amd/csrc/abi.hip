@@ -392,6 +392,8 @@ dpp_status dpp_assemble_batch(int nb, const dpp_box *boxes, const dpp_params *pa
       set_device_of(params[0].k1);
       for (int i = 0; i < nb; ++i) {
         DPP_CHECK(boxes[i].dim == B->dim, DPP_ERR_ARG, "all instances of a batch share one dimension");
+        DPP_CHECK(params[i].face_bc == nullptr, DPP_ERR_UNSUPPORTED,
+                  "batched instances take no velocity (flux) faces");
         auto *P = new dpp_problem_s();
         B->P.push_back(P);
         dpp::assemble_problem(P, &boxes[i], &params[i], S(stream));

@@ -116,9 +116,36 @@ void flip_pressure_sign(dpp_problem P, const double *in, double *out, hipStream_
   check_launch("flip");
 }
 
+// lam with the prescribed velocity components zeroed (velocity faces)
+template <int D>
+__global__ void k_mask_fixed(GridDev g, const double *__restrict__ lam, double *__restrict__ out) {
+  const long N = g.N;
+  const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  int ia[3];
+  node_ijk(g, a, ia[0], ia[1], ia[2]);
+  for (int q = 0; q < 2; ++q) {
+    const long ou = off_u(D, N, q), op = off_p(D, N, q);
+    for (int c = 0; c < D; ++c) out[ou + D * a + c] = u_fixed(g, q, c, ia) ? 0.0 : lam[ou + D * a + c];
+    out[op + a] = lam[op + a];
+  }
+}
+
 void param_grad(dpp_problem P, const double *x, const double *lam, double *g1, double *g2,
                 double *gb, hipStream_t s) {
   const Grid &g = P->g;
+  // With velocity faces K~ = P_f K P_f + P_c and f~ = P_f (f - K P_c g) + P_c g,
+  // so dJ/dtheta = lam^T (df~ - dK~ x) = -(P_f lam)^T (dK/dtheta) x (x = g on
+  // the prescribed DOFs): the gradient takes lam with those entries zeroed.
+  DBuf lmask;
+  if (g.fix[0] | g.fix[1]) {
+    lmask.alloc(sizeof(double) * P->ndof());
+    if (g.dim == 3)
+      k_mask_fixed<3><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), lam, lmask.as<double>());
+    else
+      k_mask_fixed<2><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), lam, lmask.as<double>());
+    lam = lmask.as<double>();
+  }
   DBuf tmp;
   double *gbc = gb;
   if (!P->beta_per_cell || !gb) {

@@ -225,7 +225,75 @@ __global__ __launch_bounds__(256) void k_rhs(GridDev g, Coef cf, const double *_
   }
 }
 
+// Velocity faces (section "Boundary conditions", eq. DG_GE_vBC): the
+// prescribed normal velocities are essential conditions (w.n = 0 in the test
+// space), imposed by elimination.  k_lift moves the known values out of the
+// other rows, f -= K g over the prescribed DOFs (K_uu couples equal
+// components, K_pu every component), and writes the data into their rows; it
+// reads K before k_mask_bc.  One thread per node.
+template <int D>
+__global__ void k_lift(GridDev g, const double *__restrict__ kv, const double *__restrict__ ub1,
+                       const double *__restrict__ ub2, double *__restrict__ f) {
+  constexpr int NS = Tabs<D>::NS;
+  const long N = g.N;
+  const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  int ia[3];
+  node_ijk(g, a, ia[0], ia[1], ia[2]);
+  const size_t vs = (size_t)NS * g.ld;
+  for (int q = 0; q < 2; ++q) {
+    if (!g.fix[q]) continue;
+    const double *ub = q ? ub2 : ub1;
+    const long ou = off_u(D, N, q), op = off_p(D, N, q);
+    double fp = 0.0, fu[3] = {0.0, 0.0, 0.0};
+    for (int t = 0; t < NS; ++t) {
+      const int *o = TAB<D>.so[t];
+      const int ib[3] = {ia[0] + o[0], ia[1] + o[1], ia[2] + o[2]};
+      if (!inside(g, ib[0], ib[1], ib[2])) continue;
+      const long b = a + lin(g, o[0], o[1], o[2]);
+      for (int c = 0; c < D; ++c) {
+        if (!u_fixed(g, q, c, ib)) continue;
+        const double gv = ub[(long)D * b + c];
+        fu[c] += kv[kv_uu(D, q) * vs + (size_t)t * g.ld + a] * gv;
+        fp += kv[kv_pu(D, q, c) * vs + (size_t)t * g.ld + a] * gv;
+      }
+    }
+    for (int c = 0; c < D; ++c)
+      f[ou + D * a + c] = u_fixed(g, q, c, ia) ? ub[(long)D * a + c] : f[ou + D * a + c] - fu[c];
+    f[op + a] -= fp;
+  }
+}
+
+// Removes the prescribed velocity DOFs from the coupling blocks of the stored
+// K: their K_up rows and K_pu columns become zeros (K_pu = -K_up^T still
+// holds), so the Schur blocks, selfp and the half storage see the masked
+// operator.  K_uu keeps its values (one scalar per node pair serves every
+// component); the kernels that apply it mask the prescribed components.
+template <int D>
+__global__ void k_mask_bc(GridDev g, double *__restrict__ kv) {
+  constexpr int NS = Tabs<D>::NS;
+  const long N = g.N;
+  const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  int ia[3];
+  node_ijk(g, a, ia[0], ia[1], ia[2]);
+  const size_t vs = (size_t)NS * g.ld;
+  for (int q = 0; q < 2; ++q) {
+    if (!g.fix[q]) continue;
+    for (int t = 0; t < NS; ++t) {
+      const int *o = TAB<D>.so[t];
+      const int ib[3] = {ia[0] + o[0], ia[1] + o[1], ia[2] + o[2]};
+      for (int c = 0; c < D; ++c) {
+        if (u_fixed(g, q, c, ia)) kv[kv_up(D, q, c) * vs + (size_t)t * g.ld + a] = 0.0;
+        if (u_fixed(g, q, c, ib)) kv[kv_pu(D, q, c) * vs + (size_t)t * g.ld + a] = 0.0;
+      }
+    }
+  }
+}
+
 // CSR export (test hook): one thread per node writes all 2d+2 rows of it.
+// Prescribed velocity DOFs have identity rows and zero K_uu columns (their
+// coupling values are stored zeros).
 template <int D>
 __global__ void k_export(GridDev g, const double *__restrict__ kv, const int64_t *__restrict__ rowptr,
                          int32_t *__restrict__ cols, double *__restrict__ vals) {
@@ -248,8 +316,17 @@ __global__ void k_export(GridDev g, const double *__restrict__ kv, const int64_t
       long row = off_u(D, N, q) + (long)D * a + c;
       int64_t w = rowptr[row];
       long b;
+      const bool fixed_row = u_fixed(g, q, c, ia);
       for (int t = 0; t < NS; ++t)
-        if (nb(t, b)) { cols[w] = (int32_t)(off_u(D, N, q) + D * b + c); vals[w++] = val(kv_uu(D, q), t); }
+        if (nb(t, b)) {
+          const int *o = TAB<D>.so[t];
+          const int ib[3] = {ia[0] + o[0], ia[1] + o[1], ia[2] + o[2]};
+          double v = val(kv_uu(D, q), t);
+          if (fixed_row) v = (b == a) ? 1.0 : 0.0;
+          else if (u_fixed(g, q, c, ib)) v = 0.0;
+          cols[w] = (int32_t)(off_u(D, N, q) + D * b + c);
+          vals[w++] = v;
+        }
       for (int t = 0; t < NS; ++t)
         if (nb(t, b)) { cols[w] = (int32_t)(off_p(D, N, q) + b); vals[w++] = val(kv_up(D, q, c), t); }
     }
@@ -337,8 +414,6 @@ void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, 
     DPP_CHECK(box->n[a] >= 1 && box->n[a] <= 4096, DPP_ERR_ARG, "cells per axis must be in 1..4096");
     DPP_CHECK(box->L[a] > 0.0, DPP_ERR_ARG, "box extent must be positive");
   }
-  DPP_CHECK(prm->facet_type == nullptr, DPP_ERR_UNSUPPORTED,
-            "velocity (flux) boundary facets are not supported: facet_type must be NULL");
   DPP_CHECK(prm->k1 && prm->k2 && prm->p0_1 && prm->p0_2, DPP_ERR_ARG, "null coefficient array");
   DPP_CHECK(prm->mu > 0.0, DPP_ERR_ARG, "mu must be positive");
   Grid g = make_grid(box->dim, box->n, box->L);
@@ -353,6 +428,21 @@ void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, 
   if (prm->body) check_input(prm->body, g.nc * D, false, "body", s);
   DPP_CHECK(std::isfinite(prm->beta) && prm->beta >= 0.0, DPP_ERR_ARG, "beta must be >= 0");
 
+  if (prm->face_bc) {
+    for (int q = 0; q < 2; ++q)
+      for (int fa = 0; fa < 2 * D; ++fa) {
+        const int8_t v = prm->face_bc[q * 2 * D + fa];
+        DPP_CHECK(v == 0 || v == 1, DPP_ERR_ARG, "face_bc entries must be 0 or 1");
+        g.fix[q] |= v << fa;
+      }
+    const int all = (1 << (2 * D)) - 1;
+    DPP_CHECK(!(g.fix[0] == all && g.fix[1] == all), DPP_ERR_UNSUPPORTED,
+              "velocity boundaries on every face of both networks (singular K) are not supported");
+    DPP_CHECK((!g.fix[0] || prm->u_bc_1) && (!g.fix[1] || prm->u_bc_2), DPP_ERR_ARG,
+              "u_bc_i is required for a network with velocity faces");
+    if (g.fix[0]) check_input(prm->u_bc_1, g.N * D, false, "u_bc_1", s);
+    if (g.fix[1]) check_input(prm->u_bc_2, g.N * D, false, "u_bc_2", s);
+  }
   P->g = g;
   P->mu = prm->mu;
   P->beta = prm->beta;
@@ -385,6 +475,19 @@ void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, 
                                                  P->f.as<double>());
   }
   check_launch("assemble");
+  if (g.fix[0] | g.fix[1]) {
+    // essential normal velocities: lift with the full K, then mask its couplings
+    if (D == 3) {
+      k_lift<3><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, P->kvals.as<double>(), prm->u_bc_1,
+                                                    prm->u_bc_2, P->f.as<double>());
+      k_mask_bc<3><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, P->kvals.as<double>());
+    } else {
+      k_lift<2><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, P->kvals.as<double>(), prm->u_bc_1,
+                                                    prm->u_bc_2, P->f.as<double>());
+      k_mask_bc<2><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, P->kvals.as<double>());
+    }
+    check_launch("velocity boundaries");
+  }
   make_dinv(P, s);
   make_kh(P, s);
 }

@@ -48,6 +48,9 @@ struct Grid {
   double h[3] = {1, 1, 1};
   long N = 0;   // nodes
   long nc = 0;  // simplices
+  // velocity (flux) faces of network q: bit 2a + s set when face s (0: x_a = 0,
+  // 1: x_a = L_a) prescribes the normal velocity (finest grid only)
+  int fix[2] = {0, 0};
 };
 
 inline Grid make_grid(int dim, const int *n, const double *L) {
@@ -75,6 +78,7 @@ inline Grid make_grid(int dim, const int *n, const double *L) {
 inline Grid coarse_grid(const Grid &f) {
   Grid g = f;
   g.N = 1;
+  g.fix[0] = g.fix[1] = 0;
   for (int a = 0; a < f.dim; ++a) {
     g.n[a] = (f.n[a] + 1) / 2;
     g.m[a] = g.n[a] + 1;
@@ -93,9 +97,18 @@ struct GridDev {
   int m[3];
   long N;
   long ld;
+  int fix[2];
 };
 inline GridDev dev(const Grid &g) {
-  return GridDev{{g.n[0], g.n[1], g.n[2]}, {g.m[0], g.m[1], g.m[2]}, g.N, padded(g.N)};
+  return GridDev{{g.n[0], g.n[1], g.n[2]}, {g.m[0], g.m[1], g.m[2]}, g.N, padded(g.N),
+                 {g.fix[0], g.fix[1]}};
+}
+
+// Velocity component c of the node with indices ijk is prescribed for
+// network q: the node lies on a velocity face of q whose normal is axis c.
+__host__ __device__ inline bool u_fixed(const GridDev &g, int q, int c, const int *ijk) {
+  const int bits = g.fix[q] >> (2 * c);
+  return ((bits & 1) && ijk[c] == 0) || ((bits & 2) && ijk[c] == g.n[c]);
 }
 
 // ---------------------------------------------------------- stencils ----

@@ -23,7 +23,9 @@ namespace {
 // slice of each workgroup (column order, below).
 constexpr int KBS = 64;
 
-template <int D, typename TV>
+// BC: the problem has velocity faces; their prescribed components have
+// identity rows (y_u = x_u there).
+template <int D, typename TV, bool BC>
 __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict__ kv,
                                                 const double *__restrict__ x,
                                                 const double *__restrict__ bsub,
@@ -33,14 +35,19 @@ __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict_
   const long a = (long)order[blockIdx.x] * KBS + threadIdx.x;
   if (a >= N) return;
   double au[2][D], ap[2];
-  spmv_K_node<D, TV>(g, kv, x, a, au, ap);
+  spmv_K_node<D, TV, BC>(g, kv, x, a, au, ap);
+  int ia[3] = {0, 0, 0};
+  if constexpr (BC) node_ijk(g, a, ia[0], ia[1], ia[2]);
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const long ou = off_u(D, N, q), op = off_p(D, N, q);
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       const long r = ou + D * a + c;
-      y[r] = bsub ? bsub[r] - au[q][c] : au[q][c];
+      double v = au[q][c];
+      if constexpr (BC)
+        if (u_fixed(g, q, c, ia)) v = x[r];
+      y[r] = bsub ? bsub[r] - v : v;
     }
     y[op + a] = bsub ? bsub[op + a] - ap[q] : ap[q];
   }
@@ -185,7 +192,9 @@ __global__ __launch_bounds__(256) void k_schur_rhs(GridDev g, const TV *__restri
   }
 }
 
-template <int D, typename TV, typename TX>
+// BC: prescribed velocity components (velocity faces) keep z_u = r_u, the
+// identity rows of the masked velocity block.
+template <int D, typename TV, typename TX, bool BC>
 __global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restrict__ kv,
                                                    const double *__restrict__ dinv,
                                                    const double *__restrict__ r,
@@ -199,6 +208,16 @@ __global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restri
   if (a + 1 < N) {
     double out[2 * D];
     schur_vel_node2<D, TV, TX>(g, kv, dinv, r, zp, q, a, out);
+    if constexpr (BC) {
+      int ia[3], ib[3];
+      node_ijk(g, a, ia[0], ia[1], ia[2]);
+      node_ijk(g, a + 1, ib[0], ib[1], ib[2]);
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        if (u_fixed(g, q, c, ia)) out[c] = r[ou + D * a + c];
+        if (u_fixed(g, q, c, ib)) out[D + c] = r[ou + D * (a + 1) + c];
+      }
+    }
 #pragma unroll
     for (int k = 0; k < D; ++k) st2(z + ou + D * a + 2 * k, out[2 * k], out[2 * k + 1]);
     TX p0, p1;
@@ -207,6 +226,13 @@ __global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restri
   } else {
     double out[D];
     schur_vel_node<D, TV, TX>(g, kv, dinv, r, zp, q, a, out);
+    if constexpr (BC) {
+      int ia[3];
+      node_ijk(g, a, ia[0], ia[1], ia[2]);
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        if (u_fixed(g, q, c, ia)) out[c] = r[ou + D * a + c];
+    }
 #pragma unroll
     for (int c = 0; c < D; ++c) z[ou + D * a + c] = out[c];
     z[off_p(D, N, q) + a] = (double)zp[q * N + a];
@@ -234,17 +260,18 @@ void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32)
   const Grid &g = P->g;
   const int nb = blocks_for(g.N, KBS);
   const int *ord = P->korder.as<int>();
+  const bool bc = (g.fix[0] | g.fix[1]) != 0;
   ProfScope ps(PF_SPMV_K, kbytes(g, fp32, false), s);
   if (g.dim == 3) {
     if (fp32)
-      k_spmv_K<3, float><<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, nullptr, y, ord);
+      (bc ? k_spmv_K<3, float, true> : k_spmv_K<3, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, nullptr, y, ord);
     else
-      k_spmv_K<3, double><<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, nullptr, y, ord);
+      (bc ? k_spmv_K<3, double, true> : k_spmv_K<3, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, nullptr, y, ord);
   } else {
     if (fp32)
-      k_spmv_K<2, float><<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, nullptr, y, ord);
+      (bc ? k_spmv_K<2, float, true> : k_spmv_K<2, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, nullptr, y, ord);
     else
-      k_spmv_K<2, double><<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, nullptr, y, ord);
+      (bc ? k_spmv_K<2, double, true> : k_spmv_K<2, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, nullptr, y, ord);
   }
   check_launch("spmv_K");
 }
@@ -254,17 +281,18 @@ void residual_K(dpp_problem P, const double *b, const double *x, double *r, hipS
   const Grid &g = P->g;
   const int nb = blocks_for(g.N, KBS);
   const int *ord = P->korder.as<int>();
+  const bool bc = (g.fix[0] | g.fix[1]) != 0;
   ProfScope ps(PF_SPMV_K, kbytes(g, fp32, true), s);
   if (g.dim == 3) {
     if (fp32)
-      k_spmv_K<3, float><<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, b, r, ord);
+      (bc ? k_spmv_K<3, float, true> : k_spmv_K<3, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, b, r, ord);
     else
-      k_spmv_K<3, double><<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, b, r, ord);
+      (bc ? k_spmv_K<3, double, true> : k_spmv_K<3, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, b, r, ord);
   } else {
     if (fp32)
-      k_spmv_K<2, float><<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, b, r, ord);
+      (bc ? k_spmv_K<2, float, true> : k_spmv_K<2, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, b, r, ord);
     else
-      k_spmv_K<2, double><<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, b, r, ord);
+      (bc ? k_spmv_K<2, double, true> : k_spmv_K<2, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, b, r, ord);
   }
   check_launch("residual_K");
 }
@@ -364,16 +392,17 @@ void schur_velocity(dpp_problem P, const double *r, const void *zp, bool fp32, d
                       g.N * (fp32 ? 4.0 : 8.0)), s);
   dim3 grid(blocks_for((g.N + 1) / 2, 256), 2);
   const double *di = P->dinv.as<double>();
+  const bool bc = (g.fix[0] | g.fix[1]) != 0;
   if (g.dim == 3) {
     if (fp32)
-      k_schur_vel<3, float, float><<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (const float *)zp, z);
+      (bc ? k_schur_vel<3, float, float, true> : k_schur_vel<3, float, float, false>)<<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (const float *)zp, z);
     else
-      k_schur_vel<3, double, double><<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (const double *)zp, z);
+      (bc ? k_schur_vel<3, double, double, true> : k_schur_vel<3, double, double, false>)<<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (const double *)zp, z);
   } else {
     if (fp32)
-      k_schur_vel<2, float, float><<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (const float *)zp, z);
+      (bc ? k_schur_vel<2, float, float, true> : k_schur_vel<2, float, float, false>)<<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (const float *)zp, z);
     else
-      k_schur_vel<2, double, double><<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (const double *)zp, z);
+      (bc ? k_schur_vel<2, double, double, true> : k_schur_vel<2, double, double, false>)<<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (const double *)zp, z);
   }
   check_launch("schur_velocity");
 }

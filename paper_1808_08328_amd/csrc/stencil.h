@@ -190,7 +190,7 @@ constexpr int stored_offsets() {
 // index is clamped, not guarded); neighbour-row values are masked when the
 // neighbour's linear index falls outside [0, N) (a wrapped index inside
 // [0, N) reads a pair that leaves the box from that node, a stored zero).
-template <int D, typename TV>
+template <int D, typename TV, bool BC = false>
 __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
                                    const double *__restrict__ x, long a, double au[2][D],
                                    double ap[2]) {
@@ -204,6 +204,11 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
   }
   const long ou[2] = {off_u(D, N, 0), off_u(D, N, 1)};
   const long op[2] = {off_p(D, N, 0), off_p(D, N, 1)};
+  // with velocity faces (BC): prescribed velocity components are removed from
+  // the columns (K_up / K_pu values of those DOFs are stored zeros; the K_uu
+  // values are masked here through x)
+  int ia[3] = {0, 0, 0};
+  if constexpr (BC) node_ijk(g, a, ia[0], ia[1], ia[2]);
 #pragma unroll 1
   for (int h = 0; h < L::NH; ++h) {
     const int tp = L::S0 + h, tn = L::S0 - h;
@@ -227,6 +232,12 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
     for (int q = 0; q < 2; ++q) {
 #pragma unroll
       for (int c = 0; c < D; ++c) xu[c] = x[ou[q] + D * bp + c];
+      if constexpr (BC) {
+        const int pb[3] = {ia[0] + o[0], ia[1] + o[1], ia[2] + o[2]};
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+          if (u_fixed(g, q, c, pb)) xu[c] = 0.0;
+      }
       const double uu = q ? uu1 : uu0, pp = q ? pp1 : pp0;
 #pragma unroll
       for (int c = 0; c < D; ++c) {
@@ -252,6 +263,12 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
     for (int q = 0; q < 2; ++q) {
 #pragma unroll
       for (int c = 0; c < D; ++c) xu[c] = x[ou[q] + D * bn + c];
+      if constexpr (BC) {
+        const int nb[3] = {ia[0] - o[0], ia[1] - o[1], ia[2] - o[2]};
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+          if (u_fixed(g, q, c, nb)) xu[c] = 0.0;
+      }
       const double uu = q ? vuu1 : vuu0, pp = q ? vpp1 : vpp0;
 #pragma unroll
       for (int c = 0; c < D; ++c) {
