@@ -30,6 +30,9 @@ WORKLOADS = {
                    "per-hex k1, k2 (Gaussian random field, correlation length 0.1, seeds 1001/1002)",
     "c5_3d48_grf": "3D unit cube 48^3 x 6 tetrahedra (49^3 nodes) = 941,192 DOF; log-normal k1, k2",
     "c1_2d16": "2D unit square 16^2 x 2 triangles (289 nodes) = 1,734 DOF; k1=1, k2=0.1, beta=mu=1",
+    "c2f_3d64_flux": "the 64^3 workload with velocity (flux) faces: network 1 prescribes u.n on the "
+                     "x faces, network 2 on the y faces and z = 0 (essential), pressures weakly "
+                     "on the rest",
     "c4_batch64": "64 independent 2D unit-square instances, n ~ U{32..256} cells per side (seed 2024), "
                   "beta ~ logU[0.1,10], k2/k1 ~ logU[1e-3,1]; one batched launch per phase",
 }

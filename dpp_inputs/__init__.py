@@ -232,6 +232,10 @@ CONFIGS = {
     "c3_3d96_grf": dict(kind="grf", dim=3, n=96),
     "c4_batch64": dict(kind="batch", count=64, seed=2024),
     "c5_3d48_grf": dict(kind="grf", dim=3, n=48),
+    # the 64^3 manufactured solution with velocity faces: network 1 prescribes
+    # u.n on the x faces, network 2 on the y and z = 0 faces
+    "c2f_3d64_flux": dict(kind="mms", dim=3, n=64, k1=1.0, k2=1e-2, beta=1.0, mu=1.0,
+                          flux_faces=[[1, 1, 0, 0, 0, 0], [0, 0, 1, 1, 1, 0]]),
 }
 
 
@@ -240,7 +244,7 @@ def make_config(name, n=None):
     c = CONFIGS[name]
     if c["kind"] == "mms":
         return mms_problem(c["dim"], n or c["n"], k1=c["k1"], k2=c["k2"],
-                           beta=c["beta"], mu=c["mu"])
+                           beta=c["beta"], mu=c["mu"], flux_faces=c.get("flux_faces"))
     if c["kind"] == "grf":
         return grf_problem(c["dim"], n or c["n"])
     raise ValueError("batch workloads are built with batch_configs()")
