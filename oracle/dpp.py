@@ -159,8 +159,6 @@ def velocity_dofs(msh, prob):
     from the nodal data u_bc_i.  Returns (mask [n_dof] bool, values [n_dof])."""
     d, N, n = msh.dim, msh.N, msh.n
     fb = np.asarray(prob.face_bc, dtype=np.int8).reshape(2, 2 * d)
-    if fb[0].all() and fb[1].all():
-        raise NotImplementedError("both networks with flux boundaries only (singular K)")
     ids = np.arange(N)
     ax = []
     r = ids.copy()
@@ -259,3 +257,63 @@ def sign_matrix(dim, N):
     s[F["p1"]] = -1.0
     s[F["p2"]] = -1.0
     return s
+
+
+def pure_flux(prob):
+    """Velocity faces on every face of both networks: K is singular."""
+    fb = getattr(prob, "face_bc", None)
+    return fb is not None and bool(np.all(np.asarray(fb) != 0))
+
+
+def nullspace(dim, N):
+    """Kernel of K in the pure-flux case: u = 0, p1 = p2 = constant.  The
+    test functions have w.n = 0 on the whole boundary, so -(div w; c) = 0,
+    the pressure-gradient terms vanish on constants and the mass transfer
+    beta (p1 - p2) pins p1 = p2.  Since K^T = D K D, it spans the left kernel
+    as well."""
+    F = fields(dim, N)
+    n = np.zeros((2 * dim + 2) * N)
+    n[F["p1"]] = 1.0
+    n[F["p2"]] = 1.0
+    return n
+
+
+def consistent_rhs(f, dim, N):
+    """The part of f in the range of K (f minus its component along the
+    kernel): the nodal boundary data satisfy the compatibility condition of
+    the continuous problem only up to the discretisation error."""
+    n = nullspace(dim, N)
+    return f - (n @ f) / (n @ n) * n
+
+
+def pressure_mean(msh, p):
+    """(1/|Omega|) int_Omega p_h for a P1 nodal vector p (exact for P1)."""
+    V = msh.X[msh.cells]
+    J = np.transpose(V[:, 1:, :] - V[:, :1, :], (0, 2, 1))
+    vol = np.abs(np.linalg.det(J)) / (2.0 if msh.dim == 2 else 6.0)
+    return float(np.sum(vol * p[msh.cells].mean(1)) / vol.sum())
+
+
+def normalize_pressures(msh, x):
+    """Pure-flux case: the solution is fixed up to the kernel; the function
+    space Q asks (int p1)(int p2) = 0, of which this takes int p1 = 0 (shift
+    both pressures by the same constant)."""
+    F = fields(msh.dim, msh.N)
+    c = pressure_mean(msh, x[F["p1"]])
+    y = x.copy()
+    y[F["p1"]] -= c
+    y[F["p2"]] -= c
+    return y
+
+
+def solve_pure_flux(S, f=None, transpose=False):
+    """Solve the singular pure-flux system: the consistent part of the
+    right-hand side, the solution orthogonal to the kernel (bordered system),
+    then the pressure normalisation."""
+    d, N = S.dim, S.N
+    n = nullspace(d, N)
+    b = consistent_rhs(S.f if f is None else f, d, N)
+    K = S.K.T if transpose else S.K
+    A = sp.bmat([[K, sp.csr_matrix(n[:, None])], [sp.csr_matrix(n[None, :]), None]]).tocsc()
+    z = spla.spsolve(A, np.concatenate([b, [0.0]]))
+    return normalize_pressures(S.mesh, z[:-1])

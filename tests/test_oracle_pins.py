@@ -469,8 +469,6 @@ def test_velocity_bc_structure():
     assert np.array_equal(S.f[fixed], g[fixed])
     x = dpp.solve_direct(S.K, S.f)
     assert np.array_equal(x[fixed], g[fixed])
-    with pytest.raises(NotImplementedError):
-        dpp.assemble(I.mms_problem(2, 3, flux_faces=[[1, 1, 1, 1], [1, 1, 1, 1]]))
 
 
 @pytest.mark.parametrize("dim,ns", [(2, [8, 16, 32]), (3, [4, 8, 16])])
@@ -530,3 +528,46 @@ def test_velocity_bc_gradient_matches_finite_differences():
             km[which] = km[which] * np.exp(-eps * d)
             fd = (J_of(*kp) - J_of(*km)) / (2 * eps)
             assert grad @ d == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+def _pure_flux_problem(dim, n):
+    return I.mms_problem(dim, n, k1=1.0, k2=0.1, beta=1.0, mu=1.0,
+                         flux_faces=[[1] * (2 * dim), [1] * (2 * dim)])
+
+
+def test_pure_flux_kernel_and_compatibility():
+    """Velocity faces everywhere: K has the kernel p1 = p2 = const (and, as
+    K^T = D K D, the same left kernel); the interpolated boundary fluxes are
+    compatible only up to the discretisation error, which decays as h^2."""
+    incons = []
+    for n in (8, 16, 32):
+        S = dpp.assemble(_pure_flux_problem(2, n))
+        nv = dpp.nullspace(2, S.N)
+        scale = abs(S.K).max()
+        assert np.abs(S.K @ nv).max() <= 1e-14 * scale * S.N
+        assert np.abs(S.K.T @ nv).max() <= 1e-14 * scale * S.N
+        incons.append(abs(nv @ S.f) / np.linalg.norm(S.f))
+        x = dpp.solve_pure_flux(S)
+        b = dpp.consistent_rhs(S.f, 2, S.N)
+        assert np.linalg.norm(b - S.K @ x) <= 1e-11 * np.linalg.norm(b)
+        assert abs(dpp.pressure_mean(S.mesh, x[dpp.fields(2, S.N)["p1"]])) < 1e-12
+    assert post.rates([1 / 8, 1 / 16, 1 / 32], incons).min() > 1.8
+
+
+@pytest.mark.parametrize("dim,ns", [(2, [8, 16, 32]), (3, [4, 8])])
+def test_pure_flux_convergence(dim, ns):
+    """The normalised discrete solution (int p1 = 0) against the manufactured
+    solution normalised the same way converges at h^2 in the pressures."""
+    errs = []
+    for n in ns:
+        S = dpp.assemble(_pure_flux_problem(dim, n))
+        x = dpp.solve_pure_flux(S)
+        p1e = I.mms_fields(dim, S.mesh.X, 1.0, 0.1, 1.0, 1.0)[0]
+        ce = dpp.pressure_mean(S.mesh, p1e)
+        ex = lambda Y: (lambda t: (t[0] - ce, t[1] - ce, t[2], t[3]))(I.mms_fields(dim, Y, 1.0, 0.1, 1.0, 1.0))
+        errs.append(post.l2_errors(S, x, ex, q=4))
+    hs = [1 / n for n in ns]
+    for f in ("p1", "p2"):
+        assert post.rates(hs, [e[f] for e in errs])[-1] > 1.9
+    for f in ("u1", "u2"):
+        assert post.rates(hs, [e[f] for e in errs])[-1] > 1.7
