@@ -264,6 +264,14 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
     }
     const double *b = rhs ? rhs : P->f.as<double>();
     const long n = P->ndof();
+    const bool singular = dpp::pure_flux(P->g);
+    if (singular) {
+      // pure flux: K is singular; solve for the consistent part of b
+      if (!pc->bproj.ptr) pc->bproj.alloc(sizeof(double) * n);
+      DPP_HIP(hipMemcpyAsync(pc->bproj.ptr, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      dpp::consistent_rhs(P, pc->bproj.as<double>(), s);
+      b = pc->bproj.as<double>();
+    }
     dpp::ensure_reduction(pc);
     const double bn = dpp::norm2(b, n, pc->part.as<double>(), s);
     DPP_CHECK(std::isfinite(bn), DPP_ERR_NUMERIC, "right-hand side holds NaN/Inf");
@@ -303,6 +311,7 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
         ++refine;
       }
     }
+    if (singular) dpp::normalize_pressures(P, x, s);  // int p1 = 0
     DPP_HIP(hipStreamSynchronize(s));
     if (res.status != DPP_OK) {
       throw dpp::Error(res.status, res.status == DPP_ERR_NOT_CONVERGED

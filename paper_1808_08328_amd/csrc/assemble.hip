@@ -435,9 +435,6 @@ void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, 
         DPP_CHECK(v == 0 || v == 1, DPP_ERR_ARG, "face_bc entries must be 0 or 1");
         g.fix[q] |= v << fa;
       }
-    const int all = (1 << (2 * D)) - 1;
-    DPP_CHECK(!(g.fix[0] == all && g.fix[1] == all), DPP_ERR_UNSUPPORTED,
-              "velocity boundaries on every face of both networks (singular K) are not supported");
     DPP_CHECK((!g.fix[0] || prm->u_bc_1) && (!g.fix[1] || prm->u_bc_2), DPP_ERR_ARG,
               "u_bc_i is required for a network with velocity faces");
     if (g.fix[0]) check_input(prm->u_bc_1, g.N * D, false, "u_bc_1", s);

@@ -101,6 +101,7 @@ struct dpp_precond_s {
   dpp::DBuf cinv;   // [2][nc][nc] FP64 inverse of the coarsest operator
   int ncoarse = 0;
   dpp::DBuf rhat;   // [2][N] level-0 right-hand side of the V-cycle
+  dpp::DBuf bproj;  // [n_dof] consistent right-hand side (pure-flux problems)
   dpp::DBuf rhat32;
   dpp::DBuf red;    // reduction scratch
   bool has32 = false;
@@ -159,6 +160,10 @@ void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStr
 void mms_l2_errors(dpp_problem P, const double *x, const double mms[4], int q, double err[4],
                    hipStream_t s);
 void simplex_rule(int dim, int q, std::vector<double> &lam, std::vector<double> &w);
+// pure-flux case: velocity faces everywhere in both networks (singular K)
+bool pure_flux(const Grid &g);
+void consistent_rhs(dpp_problem P, double *b, hipStream_t s);
+void normalize_pressures(dpp_problem P, double *x, hipStream_t s);
 void vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s);  // FP64, [2][N] in/out
 void level_spmv(dpp_precond pc, int level, int net, const double *x, double *y, hipStream_t s);
 void precond_make32(dpp_precond pc, hipStream_t s);

@@ -149,6 +149,58 @@ __global__ __launch_bounds__(PBS) void k_l2_error(GridDev g, const double *__res
   if (threadIdx.x < 4) part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
 }
 
+// Pure-flux case (velocity faces on every face of both networks): K has the
+// kernel u = 0, p1 = p2 = const, which is also its left kernel (K^T = D K D).
+// mode 0: per-workgroup sums of p1 + p2 over the nodes (the right-hand side's
+// component along the kernel); mode 1: of the simplex means of p1 (int p1,
+// up to the constant simplex volume of the box).
+template <int D>
+__global__ __launch_bounds__(PBS) void k_pressure_sums(GridDev g, const double *__restrict__ v,
+                                                       int mode, double *__restrict__ part) {
+  constexpr int NPER = D == 3 ? 6 : 2;
+  const long N = g.N;
+  double acc = 0.0;
+  if (mode == 0) {
+    const long op1 = off_p(D, N, 0), op2 = off_p(D, N, 1);
+    for (long a = (long)blockIdx.x * PBS + threadIdx.x; a < N; a += (long)gridDim.x * PBS)
+      acc += v[op1 + a] + v[op2 + a];
+  } else {
+    const long ncell = (long)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1) * NPER;
+    const long op1 = off_p(D, N, 0);
+    for (long e = (long)blockIdx.x * PBS + threadIdx.x; e < ncell; e += (long)gridDim.x * PBS) {
+      const int s = (int)(e % NPER);
+      long hex = e / NPER;
+      int ijk[3] = {(int)(hex % g.n[0]), 0, 0};
+      hex /= g.n[0];
+      ijk[1] = (int)(hex % g.n[1]);
+      ijk[2] = D == 3 ? (int)(hex / g.n[1]) : 0;
+      double sv = 0.0;
+      for (int k = 0; k <= D; ++k) {
+        if (k > 0) ijk[perm_of(D, s, k - 1)] += 1;
+        sv += v[op1 + ijk[0] + (long)g.m[0] * (ijk[1] + (long)g.m[1] * ijk[2])];
+      }
+      acc += sv / (D + 1);
+    }
+  }
+  __shared__ double red[PBS];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = PBS / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+template <int D>
+__global__ void k_shift_pressures(GridDev g, double *__restrict__ v, double c) {
+  const long N = g.N;
+  const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  v[off_p(D, N, 0) + a] -= c;
+  v[off_p(D, N, 1) + a] -= c;
+}
+
 // out[f] = sum over workgroups of part[f][.], in a fixed order
 __global__ __launch_bounds__(PBS) void k_l2_finish(const double *__restrict__ part, int nb,
                                                    double *__restrict__ out) {
@@ -166,6 +218,51 @@ __global__ __launch_bounds__(PBS) void k_l2_finish(const double *__restrict__ pa
 }
 
 }  // namespace
+
+bool pure_flux(const Grid &g) {
+  const int all = (1 << (2 * g.dim)) - 1;
+  return g.fix[0] == all && g.fix[1] == all;
+}
+
+// sum of p1 + p2 over the nodes (mode 0) or the mean of p1 over the box
+// (mode 1), reduced in a fixed order; synchronises the stream
+static double pressure_reduce(dpp_problem P, const double *v, int mode, hipStream_t s) {
+  const Grid &g = P->g;
+  constexpr int NB = 512;
+  DBuf part(sizeof(double) * (NB + 1));
+  double *dp = part.as<double>();
+  if (g.dim == 3)
+    k_pressure_sums<3><<<NB, PBS, 0, s>>>(dev(g), v, mode, dp);
+  else
+    k_pressure_sums<2><<<NB, PBS, 0, s>>>(dev(g), v, mode, dp);
+  k_l2_finish<<<1, PBS, 0, s>>>(dp, NB, dp + NB);
+  check_launch("pressure sums");
+  double h = 0.0;
+  DPP_HIP(hipMemcpyAsync(&h, dp + NB, sizeof(double), hipMemcpyDeviceToHost, s));
+  DPP_HIP(hipStreamSynchronize(s));
+  return mode == 0 ? h : h / (double)g.nc;
+}
+
+static void shift_pressures(dpp_problem P, double *v, double c, hipStream_t s) {
+  const Grid &g = P->g;
+  if (g.dim == 3)
+    k_shift_pressures<3><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), v, c);
+  else
+    k_shift_pressures<2><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), v, c);
+  check_launch("shift pressures");
+}
+
+// The part of b in the range of K: b minus its component along the kernel
+// (the interpolated boundary fluxes are compatible only up to O(h^2)).
+void consistent_rhs(dpp_problem P, double *b, hipStream_t s) {
+  shift_pressures(P, b, pressure_reduce(P, b, 0, s) / (2.0 * P->g.N), s);
+}
+
+// The pressure space Q asks (int p1)(int p2) = 0; of its two branches the
+// solution is normalised to int p1 = 0 (both pressures shifted alike).
+void normalize_pressures(dpp_problem P, double *x, hipStream_t s) {
+  shift_pressures(P, x, pressure_reduce(P, x, 1, s), s);
+}
 
 // Gauss-Legendre nodes and weights on [0, 1]: Newton iteration on P_q from the
 // Chebyshev-like guesses cos(pi (i + 3/4) / (q + 1/2)), with P_q and P_q' from
