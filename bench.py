@@ -33,6 +33,9 @@ WORKLOADS = {
     "c2f_3d64_flux": "the 64^3 workload with velocity (flux) faces: network 1 prescribes u.n on the "
                      "x faces, network 2 on the y faces and z = 0 (essential), pressures weakly "
                      "on the rest",
+    "c2p_3d64_pureflux": "the 64^3 workload with velocity faces on every face of both networks "
+                         "(singular K: consistent right-hand side, pressures normalised to "
+                         "int p1 = 0)",
     "c4_batch64": "64 independent 2D unit-square instances, n ~ U{32..256} cells per side (seed 2024), "
                   "beta ~ logU[0.1,10], k2/k1 ~ logU[1e-3,1]; one batched launch per phase",
 }

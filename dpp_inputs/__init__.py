@@ -236,6 +236,9 @@ CONFIGS = {
     # u.n on the x faces, network 2 on the y and z = 0 faces
     "c2f_3d64_flux": dict(kind="mms", dim=3, n=64, k1=1.0, k2=1e-2, beta=1.0, mu=1.0,
                           flux_faces=[[1, 1, 0, 0, 0, 0], [0, 0, 1, 1, 1, 0]]),
+    # pure flux: velocity faces everywhere in both networks (singular K)
+    "c2p_3d64_pureflux": dict(kind="mms", dim=3, n=64, k1=1.0, k2=1e-2, beta=1.0, mu=1.0,
+                              flux_faces=[[1] * 6, [1] * 6]),
 }
 
 
