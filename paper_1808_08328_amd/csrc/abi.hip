@@ -40,7 +40,7 @@ void check_opts(const dpp_solve_opts &o) {
   DPP_CHECK(o.precision >= 0 && o.precision <= 2, DPP_ERR_ARG, "precision must be 0, 1 or 2");
   DPP_CHECK(o.inner_rtol > 0.0 && o.inner_rtol < 1.0, DPP_ERR_ARG, "inner_rtol must be in (0, 1)");
   DPP_CHECK(o.max_refine >= 1, DPP_ERR_ARG, "max_refine must be >= 1");
-  DPP_CHECK(o.coarse_max >= 1 && o.coarse_max <= 4000, DPP_ERR_ARG, "coarse_max must be in 1..4000");
+  DPP_CHECK(o.coarse_max >= 0 && o.coarse_max <= 4000, DPP_ERR_ARG, "coarse_max must be in 0..4000");
   DPP_CHECK(o.cheb_degree >= 1 && o.cheb_degree <= 8, DPP_ERR_ARG, "cheb_degree must be in 1..8");
   for (int v : {o.cheb_pre_fine, o.cheb_pre_coarse})
     DPP_CHECK(v >= -1 && v <= 8, DPP_ERR_ARG, "pre-smoothing degrees must be -1 or 0..8");
@@ -70,7 +70,7 @@ void dpp_default_opts(dpp_solve_opts *o) {
   o->precision = 0;
   o->inner_rtol = 1e-4;
   o->max_refine = 20;
-  o->coarse_max = 1000;
+  o->coarse_max = 0;  // by dimension: 1000 nodes in 3D, 400 in 2D
   o->cheb_degree = 2;
   // post-smoothing only, V(0,2) on the finest level and V(0,3) below it
   // (measured fastest to 1e-8 in 2D and 3D)

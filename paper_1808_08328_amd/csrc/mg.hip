@@ -549,7 +549,10 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
     check_launch("diag_inv");
     for (DBuf *b : {&L.b, &L.xa, &L.xb, &L.d, &L.r, &L.e}) b->alloc(sizeof(double) * 2 * gl.N);
     Grid gc = coarse_grid(gl);
-    const bool last = gl.N <= o.coarse_max || gc.N == gl.N || (int)pc->lv.size() >= 16;
+    // coarsest size: given, or by dimension (in 2D the dense coarse inverses of
+    // ~1000-node levels cost more than one more cheap level)
+    const long cmax = o.coarse_max > 0 ? o.coarse_max : (D == 3 ? 1000 : 400);
+    const bool last = gl.N <= cmax || gc.N == gl.N || (int)pc->lv.size() >= 16;
     if (last) break;
     // Chebyshev bounds from normalised power steps on D^-1 A
     double ss[2];

@@ -37,7 +37,7 @@ def test_default_options():
     import paper_1808_08328_amd as dpp
     o = dpp.default_opts()
     assert o.restart == 30 and o.rtol == 1e-8 and o.precision == 0
-    assert o.cheb_degree == 2 and o.coarse_max == 1000
+    assert o.cheb_degree == 2 and o.coarse_max == 0
     with pytest.raises(TypeError):
         dpp.default_opts(nonsense=1)
 
