@@ -55,14 +55,16 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def kernel_name(family, dim, pc):
-    """rocprofv3 name of a single-kernel family's FP64 kernel."""
+def kernel_name(family, dim, pc, flux=False):
+    """rocprofv3 name of a single-kernel family's FP64 kernel (flux: the
+    instances for problems with velocity faces)."""
     if family in ("cheb_S_l0", "resid_S_l0"):
         lanes, sym = pc.shape(0)
         k = "k_cheb" if family == "cheb_S_l0" else "k_lspmv"
         return "%s<%d, double, double, %d, %s, true>" % (k, dim, lanes, "true" if sym else "false")
-    return {"spmv_K": "k_spmv_K<%d, double>", "schur_rhs": "k_schur_rhs<%d, double, double>",
-            "schur_vel": "k_schur_vel<%d, double, double>"}[family] % dim
+    bc = "true" if flux else "false"
+    return {"spmv_K": "k_spmv_K<%d, double, " + bc + ">", "schur_rhs": "k_schur_rhs<%d, double, double>",
+            "schur_vel": "k_schur_vel<%d, double, double, " + bc + ">"}[family] % dim
 
 
 def measured_traffic(family, launches_bytes):
@@ -261,7 +263,8 @@ def main():
         tr = measured_traffic(dom, per_launch)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": tr, "kernel": dom,
-                "kernel_name": kernel_name(dom, prob.dim, pc),
+                "kernel_name": kernel_name(dom, prob.dim, pc,
+                                           flux=getattr(prob, "face_bc", None) is not None),
                 "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": 1e3 * t / n}
 
     line = {
