@@ -75,7 +75,8 @@ typedef struct {
  * each node is prescribed (essential: identity row holding the value, the
  * value moved out of the other rows) from u_bc_i (device, [n_nodes*dim]
  * nodal velocities, node-major; required when network i has a velocity face,
- * else unread).  Batches take no velocity faces.  With velocity faces on every
+ * else unread).  Batched instances take velocity faces, but not on every face
+ * of both networks (DPP_ERR_UNSUPPORTED).  With velocity faces on every
  * face of both networks K is singular (kernel u = 0, p1 = p2 = const, also
  * its left kernel): the solves take the part of the right-hand side in the
  * range of K (its component along the kernel removed) and return pressures

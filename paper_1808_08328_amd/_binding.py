@@ -384,7 +384,6 @@ def assemble_batch(problems, stream=None, **opts):
             boxes[i].n[a] = int(pr.n[a]) if a < pr.dim else 0
             boxes[i].L[a] = float(pr.L[a]) if a < pr.dim else 0.0
         arrs = [dv(pr.k1), dv(pr.k2), dv(pr.p0_1), dv(pr.p0_2)]
-        keep.append(arrs)
         p = params[i]
         p.mu = float(pr.mu)
         p.k1, p.k2, p.p0_1, p.p0_2 = (_ptr(t) for t in arrs)
@@ -392,6 +391,15 @@ def assemble_batch(problems, stream=None, **opts):
         p.beta_cells = None
         p.body = None
         p.face_bc = p.u_bc_1 = p.u_bc_2 = None
+        if getattr(pr, "face_bc", None) is not None:
+            import numpy as np
+            fb = np.ascontiguousarray(np.asarray(pr.face_bc, dtype=np.int8).reshape(2, 2 * pr.dim))
+            ub = [None if getattr(pr, k, None) is None else dv(getattr(pr, k)).reshape(-1)
+                  for k in ("u_bc_1", "u_bc_2")]
+            arrs += [fb] + [u for u in ub if u is not None]
+            p.face_bc = fb.ctypes.data_as(C.c_void_p)
+            p.u_bc_1, p.u_bc_2 = _ptr(ub[0]), _ptr(ub[1])
+        keep.append(arrs)
     o = default_opts(**opts)
     h = C.c_void_p()
     _check(lib().dpp_assemble_batch(nb, boxes, params, C.byref(o), _stream(stream), C.byref(h)))

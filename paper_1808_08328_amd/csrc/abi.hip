@@ -401,11 +401,13 @@ dpp_status dpp_assemble_batch(int nb, const dpp_box *boxes, const dpp_params *pa
       set_device_of(params[0].k1);
       for (int i = 0; i < nb; ++i) {
         DPP_CHECK(boxes[i].dim == B->dim, DPP_ERR_ARG, "all instances of a batch share one dimension");
-        DPP_CHECK(params[i].face_bc == nullptr, DPP_ERR_UNSUPPORTED,
-                  "batched instances take no velocity (flux) faces");
+
         auto *P = new dpp_problem_s();
         B->P.push_back(P);
         dpp::assemble_problem(P, &boxes[i], &params[i], S(stream));
+        DPP_CHECK(!dpp::pure_flux(P->g), DPP_ERR_UNSUPPORTED,
+                  "batched instances with velocity faces everywhere (singular K) are not supported");
+        B->any_bc = B->any_bc || (P->g.fix[0] | P->g.fix[1]) != 0;
         auto *pc = new dpp_precond_s();
         B->pc.push_back(pc);
         pc->prob = P;

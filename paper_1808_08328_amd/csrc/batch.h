@@ -67,6 +67,7 @@ struct DTable {
 
 struct dpp_batch_s {
   int nb = 0, dim = 3;
+  bool any_bc = false;                   // some instance has velocity faces
   std::vector<dpp_problem> P;
   std::vector<dpp_precond> pc;
   std::vector<long> doff;

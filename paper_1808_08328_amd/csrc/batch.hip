@@ -44,7 +44,9 @@ __device__ inline double bwave_sum(double v) {
 namespace {
 
 // ---------------------------------------------------------------- K level --
-template <int D, typename TV>
+// BC: some instance has velocity faces (masked velocity gathers, identity rows
+// on the prescribed components; the face bits of each instance are in k.g).
+template <int D, typename TV, bool BC>
 __global__ __launch_bounds__(256) void kb_spmv_K(const KDesc *__restrict__ kd, int nd,
                                                  const int *__restrict__ active,
                                                  const double *__restrict__ x,
@@ -57,13 +59,18 @@ __global__ __launch_bounds__(256) void kb_spmv_K(const KDesc *__restrict__ kd, i
   const GridDev g = k.g;
   if (a >= g.N) return;
   double au[2][D], ap[2];
-  spmv_K_node<D, TV>(g, (const TV *)k.kv, x + k.off, a, au, ap);
+  spmv_K_node<D, TV, BC>(g, (const TV *)k.kv, x + k.off, a, au, ap);
   const long N = g.N;
+  int ia[3] = {0, 0, 0};
+  if constexpr (BC) node_ijk(g, a, ia[0], ia[1], ia[2]);
   for (int q = 0; q < 2; ++q) {
     const long ou = k.off + off_u(D, N, q), op = k.off + off_p(D, N, q);
     for (int c = 0; c < D; ++c) {
       const long r = ou + D * a + c;
-      y[r] = bsub ? bsub[r] - au[q][c] : au[q][c];
+      double v = au[q][c];
+      if constexpr (BC)
+        if (u_fixed(g, q, c, ia)) v = x[r];
+      y[r] = bsub ? bsub[r] - v : v;
     }
     y[op + a] = bsub ? bsub[op + a] - ap[q] : ap[q];
   }
@@ -82,7 +89,7 @@ __global__ __launch_bounds__(256) void kb_schur_rhs(const KDesc *__restrict__ kd
   ((TX *)k.rhat)[q * k.g.N + b] = (TX)schur_rhs_node<D, TV>(k.g, (const TV *)k.kv, k.dinv, r + k.off, q, b);
 }
 
-template <int D, typename TV, typename TX>
+template <int D, typename TV, typename TX, bool BC>
 __global__ __launch_bounds__(256) void kb_schur_vel(const KDesc *__restrict__ kd, int nd,
                                                     const int *__restrict__ active,
                                                     const double *__restrict__ r,
@@ -98,6 +105,12 @@ __global__ __launch_bounds__(256) void kb_schur_vel(const KDesc *__restrict__ kd
   const TX *zp = (const TX *)k.zp;
   schur_vel_node<D, TV, TX>(k.g, (const TV *)k.kv, k.dinv, r + k.off, zp, q, a, out);
   const long ou = k.off + off_u(D, N, q);
+  if constexpr (BC) {
+    int ia[3];
+    node_ijk(k.g, a, ia[0], ia[1], ia[2]);
+    for (int c = 0; c < D; ++c)
+      if (u_fixed(k.g, q, c, ia)) out[c] = r[ou + D * a + c];  // identity rows
+  }
   for (int c = 0; c < D; ++c) z[ou + D * a + c] = out[c];
   z[k.off + off_p(D, N, q) + a] = (double)zp[q * N + a];
 }
@@ -460,18 +473,21 @@ void precond_b(dpp_batch B, const double *r, double *z, bool fp32, hipStream_t s
   if (fp32) {
     kb_schur_rhs<D, double, float><<<g, 256, 0, s>>>(k.get(), k.count, act, r);
     vcycle_b<D, float, float>(B, true, s);
-    kb_schur_vel<D, double, float><<<g, 256, 0, s>>>(k.get(), k.count, act, r, z);
+    (B->any_bc ? kb_schur_vel<D, double, float, true> : kb_schur_vel<D, double, float, false>)
+        <<<g, 256, 0, s>>>(k.get(), k.count, act, r, z);
   } else {
     kb_schur_rhs<D, double, double><<<g, 256, 0, s>>>(k.get(), k.count, act, r);
     vcycle_b<D, double, double>(B, false, s);
-    kb_schur_vel<D, double, double><<<g, 256, 0, s>>>(k.get(), k.count, act, r, z);
+    (B->any_bc ? kb_schur_vel<D, double, double, true> : kb_schur_vel<D, double, double, false>)
+        <<<g, 256, 0, s>>>(k.get(), k.count, act, r, z);
   }
   check_launch("batched precond");
 }
 
 template <int D>
 void spmv_b(dpp_batch B, const double *x, const double *bsub, double *y, hipStream_t s) {
-  kb_spmv_K<D, double><<<B->kd.blocks, 256, 0, s>>>(B->kd.get(), B->kd.count, B->active.as<int>(), x, bsub, y);
+  (B->any_bc ? kb_spmv_K<D, double, true> : kb_spmv_K<D, double, false>)
+      <<<B->kd.blocks, 256, 0, s>>>(B->kd.get(), B->kd.count, B->active.as<int>(), x, bsub, y);
   check_launch("batched spmv");
 }
 

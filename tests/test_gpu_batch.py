@@ -106,3 +106,45 @@ def test_batch_masks_converged_instances_and_reports_unconverged():
     assert e.value.status == 4
     x, st = B.solve(rtol=1e-10, maxiter=3, allow_unconverged=True)
     assert st[1].converged == 0 and st[1].iters == 3
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batch_velocity_faces_match_single_path_and_oracle(dim):
+    """Instances with and without velocity faces in one batch: masked products
+    and preconditioner as in the single-instance path, solutions as the
+    oracle's; a pure-flux instance (singular K) is refused."""
+    import paper_1808_08328_amd as dpp
+    if dim == 2:
+        probs = [I.mms_problem(2, 9, k2=0.3, flux_faces=[[1, 1, 0, 0], [0, 0, 1, 0]]),
+                 I.mms_problem(2, (12, 7), k2=0.1),
+                 I.mms_problem(2, 10, k2=0.2, beta=2.0, flux_faces=[[0, 0, 0, 1], [1, 0, 0, 0]]),
+                 I.mms_problem(2, 8, k2=0.1, flux_faces=[[1, 1, 1, 1], [0, 0, 0, 0]])]
+    else:
+        probs = [I.mms_problem(3, (4, 3, 4), k2=0.1, flux_faces=[[1, 0, 0, 0, 0, 1], [0, 0, 1, 1, 0, 0]]),
+                 I.mms_problem(3, 5, k2=0.1),
+                 I.mms_problem(3, (3, 5, 4), k2=0.05, flux_faces=[[0, 1, 1, 0, 0, 0], [1, 1, 0, 0, 0, 0]])]
+    B = dpp.assemble_batch(probs, coarse_max=30)
+    x = torch.as_tensor(I.random_vector(B.n_dof, 3), device="cuda")
+    yb = [H(v) for v in B.split(B.spmv(x))]
+    zb = [H(v) for v in B.split(B.precond_apply(x))]
+    xs = B.split(x)
+    for i, pr in enumerate(probs):
+        P = dpp.assemble_problem(pr)
+        pc = P.setup_precond(coarse_max=30)
+        ys = H(P.spmv(xs[i].contiguous()))
+        assert np.abs(yb[i] - ys).max() <= 1e-13 * np.abs(ys).max(), ("spmv", i)
+        zs = H(pc.apply(xs[i].contiguous()))
+        assert np.abs(zb[i] - zs).max() <= 1e-11 * np.abs(zs).max(), ("precond", i)
+    xsol, st = B.solve(rtol=1e-13)
+    assert all(s.converged for s in st)
+    for i, pr in enumerate(probs):
+        S = odpp.assemble(pr)
+        xo = odpp.solve_direct(S.K, S.f)
+        xi = H(B.split(xsol)[i])
+        F = odpp.fields(dim, S.N)
+        for f in ("u1", "p1", "u2", "p2"):
+            assert np.linalg.norm(xi[F[f]] - xo[F[f]]) <= 1e-10 * np.linalg.norm(xo[F[f]]), (i, f)
+    pure = I.mms_problem(dim, 4, flux_faces=[[1] * (2 * dim), [1] * (2 * dim)])
+    with pytest.raises(dpp.DppError) as e:
+        dpp.assemble_batch([probs[0], pure], coarse_max=30)
+    assert e.value.status == 7
