@@ -116,6 +116,20 @@ def cpu_baseline(prob, gpu_iters, max_iters):
     }
 
 
+def field_errors(P, pc, x, opts):
+    """Per-field relative error of the mixed-precision solution x (solved to
+    1e-8) against an FP64 solve of the same system to 1e-12, next to the error
+    of an FP64 solve to 1e-8 against the same reference (untimed)."""
+    import torch
+    ref, _ = P.solve(pc, **{**opts, "precision": 0, "rtol": 1e-12, "use_graph": 0})
+    x64, _ = P.solve(pc, **{**opts, "precision": 0, "use_graph": 0})
+    R, M, D = P.fields(ref), P.fields(x), P.fields(x64)
+    rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+    return {"reference": "FP64 GPU solve to rel. residual 1e-12",
+            "mixed": {f: rel(M[f], R[f]) for f in R},
+            "fp64_at_1e-8": {f: rel(D[f], R[f]) for f in R}}
+
+
 def bench_batch(args, torch, I, dpp):
     """64 uneven 2D instances: batched solve vs the same instances solved one
     after another with the single-problem path."""
@@ -279,6 +293,8 @@ def main():
         "assemble_ms": (t1 - t0) * 1e3, "setup_ms": (t2 - t1) * 1e3,
         "roofline": roof, "kernels": kernels,
     }
+    if args.precision:
+        line["field_error_vs_fp64"] = field_errors(P, pc, x, opts)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, iters, args.cpu_max_iters)
     print(json.dumps(line), flush=True)

@@ -219,6 +219,12 @@ class Problem:
         _check(lib().dpp_export_csr(self.handle, _ptr(rp), _ptr(ci), _ptr(vv), _stream(stream)))
         return rp, ci, vv
 
+    def fields(self, x):
+        """Views of u1, p1, u2, p2 in a vector laid out as [u1 | p1 | u2 | p2]."""
+        N, d = self.n_nodes, self.dim
+        cuts = [0, d * N, (d + 1) * N, (2 * d + 1) * N, 2 * (d + 1) * N]
+        return {f: x[cuts[i]:cuts[i + 1]] for i, f in enumerate(("u1", "p1", "u2", "p2"))}
+
     def spmv(self, x, which=0, stream=None):
         N, d = self.n_nodes, self.dim
         out = {0: self.n_dof, 1: d * N, 2: d * N, 3: N, 4: N}[which]
