@@ -472,6 +472,7 @@ void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, 
                                                  P->f.as<double>());
   }
   check_launch("assemble");
+  make_up_table(P, s);
   if (g.fix[0] | g.fix[1]) {
     // essential normal velocities: lift with the full K, then mask its couplings
     if (D == 3) {

@@ -20,6 +20,7 @@ struct KDesc {
   GridDev g;
   int blk0, nblk;           // node blocks (one network per grid row)
   const void *kv;           // K storage (FP64 or FP32 copy)
+  const double *upt;        // K_up class table (UPT<dim>)
   const double *dinv;       // [2][N]
   long off;                 // offset of the instance in concatenated vectors
   void *rhat;               // finest-level V-cycle input  [2][N]

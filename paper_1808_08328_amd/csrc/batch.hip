@@ -44,6 +44,13 @@ __device__ inline double bwave_sum(double v) {
 namespace {
 
 // ---------------------------------------------------------------- K level --
+// The instance's K_up class table (UPT<D>) copied into LDS.
+template <int D, typename TV>
+__device__ inline void stage_upt_b(TV *sut, const double *__restrict__ upt) {
+  for (int i = threadIdx.x; i < UPT<D>::size; i += blockDim.x) sut[i] = (TV)upt[i];
+  __syncthreads();
+}
+
 // BC: some instance has velocity faces (masked velocity gathers, identity rows
 // on the prescribed components; the face bits of each instance are in k.g).
 template <int D, typename TV, bool BC>
@@ -54,12 +61,14 @@ __global__ __launch_bounds__(256) void kb_spmv_K(const KDesc *__restrict__ kd, i
                                                  double *__restrict__ y) {
   const int di = find_desc(kd, nd, (int)blockIdx.x, &KDesc::blk0);
   const KDesc &k = kd[di];
-  if (!active[k.inst]) return;
+  if (!active[k.inst]) return;  // uniform over the workgroup
+  __shared__ TV sut[UPT<D>::size];
+  stage_upt_b<D>(sut, k.upt);
   const long a = (long)(blockIdx.x - k.blk0) * blockDim.x + threadIdx.x;
   const GridDev g = k.g;
   if (a >= g.N) return;
   double au[2][D], ap[2];
-  spmv_K_node<D, TV, BC>(g, (const TV *)k.kv, x + k.off, a, au, ap);
+  spmv_K_node<D, TV, BC>(g, (const TV *)k.kv, sut, x + k.off, a, au, ap);
   const long N = g.N;
   int ia[3] = {0, 0, 0};
   if constexpr (BC) node_ijk(g, a, ia[0], ia[1], ia[2]);
@@ -76,17 +85,20 @@ __global__ __launch_bounds__(256) void kb_spmv_K(const KDesc *__restrict__ kd, i
   }
 }
 
-template <int D, typename TV, typename TX>
+template <int D, typename TV, typename TX, bool BC>
 __global__ __launch_bounds__(256) void kb_schur_rhs(const KDesc *__restrict__ kd, int nd,
                                                     const int *__restrict__ active,
                                                     const double *__restrict__ r) {
   const int di = find_desc(kd, nd, (int)blockIdx.x, &KDesc::blk0);
   const KDesc &k = kd[di];
-  if (!active[k.inst]) return;
+  if (!active[k.inst]) return;  // uniform over the workgroup
+  __shared__ TV sut[UPT<D>::size];
+  stage_upt_b<D>(sut, k.upt);
   const int q = blockIdx.y;
   const long b = (long)(blockIdx.x - k.blk0) * blockDim.x + threadIdx.x;
   if (b >= k.g.N) return;
-  ((TX *)k.rhat)[q * k.g.N + b] = (TX)schur_rhs_node<D, TV>(k.g, (const TV *)k.kv, k.dinv, r + k.off, q, b);
+  ((TX *)k.rhat)[q * k.g.N + b] =
+      (TX)schur_rhs_node<D, TV, BC>(k.g, sut, k.dinv, r + k.off, q, b);
 }
 
 template <int D, typename TV, typename TX, bool BC>
@@ -96,14 +108,16 @@ __global__ __launch_bounds__(256) void kb_schur_vel(const KDesc *__restrict__ kd
                                                     double *__restrict__ z) {
   const int di = find_desc(kd, nd, (int)blockIdx.x, &KDesc::blk0);
   const KDesc &k = kd[di];
-  if (!active[k.inst]) return;
+  if (!active[k.inst]) return;  // uniform over the workgroup
+  __shared__ TV sut[UPT<D>::size];
+  stage_upt_b<D>(sut, k.upt);
   const int q = blockIdx.y;
   const long a = (long)(blockIdx.x - k.blk0) * blockDim.x + threadIdx.x;
   const long N = k.g.N;
   if (a >= N) return;
   double out[D];
   const TX *zp = (const TX *)k.zp;
-  schur_vel_node<D, TV, TX>(k.g, (const TV *)k.kv, k.dinv, r + k.off, zp, q, a, out);
+  schur_vel_node<D, TV, TX>(k.g, sut, k.dinv, r + k.off, zp, q, a, out);
   const long ou = k.off + off_u(D, N, q);
   if constexpr (BC) {
     int ia[3];
@@ -471,12 +485,14 @@ void precond_b(dpp_batch B, const double *r, double *z, bool fp32, hipStream_t s
   const int *act = B->active.as<int>();
   const dim3 g(k.blocks, 2);
   if (fp32) {
-    kb_schur_rhs<D, double, float><<<g, 256, 0, s>>>(k.get(), k.count, act, r);
+    (B->any_bc ? kb_schur_rhs<D, double, float, true> : kb_schur_rhs<D, double, float, false>)
+        <<<g, 256, 0, s>>>(k.get(), k.count, act, r);
     vcycle_b<D, float, float>(B, true, s);
     (B->any_bc ? kb_schur_vel<D, double, float, true> : kb_schur_vel<D, double, float, false>)
         <<<g, 256, 0, s>>>(k.get(), k.count, act, r, z);
   } else {
-    kb_schur_rhs<D, double, double><<<g, 256, 0, s>>>(k.get(), k.count, act, r);
+    (B->any_bc ? kb_schur_rhs<D, double, double, true> : kb_schur_rhs<D, double, double, false>)
+        <<<g, 256, 0, s>>>(k.get(), k.count, act, r);
     vcycle_b<D, double, double>(B, false, s);
     (B->any_bc ? kb_schur_vel<D, double, double, true> : kb_schur_vel<D, double, double, false>)
         <<<g, 256, 0, s>>>(k.get(), k.count, act, r, z);
@@ -587,6 +603,7 @@ void batch_setup(dpp_batch B, hipStream_t s) {
     k.nblk = blocks_for(P->g.N, 256);
     kb += k.nblk;
     k.kv = P->kh.ptr;
+    k.upt = P->upt.as<double>();
     k.dinv = P->dinv.as<double>();
     k.off = B->doff[i];
     k.rhat = L0.b.ptr;

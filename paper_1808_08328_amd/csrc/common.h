@@ -112,6 +112,9 @@ __host__ __device__ inline bool u_fixed(const GridDev &g, int q, int c, const in
 }
 
 // ---------------------------------------------------------- stencils ----
+// Boundary class of a node: per axis 0 (first node), 1 (interior) or 2 (last
+// node); class = cx + 3 cy (+ 9 cz).
+__host__ __device__ inline int axis_class(int i, int n) { return i == 0 ? 0 : (i == n ? 2 : 1); }
 // K couples node a with node a + o for o in the Kuhn node stencil St: 0 and
 // +-every nonzero binary vector (15 offsets in 3D, 7 in 2D).  The pressure
 // operators (selfp Schur blocks and every Galerkin coarse level) share the
@@ -195,42 +198,29 @@ __host__ __device__ constexpr int kv_pp(int dim, int net) { return net * (2 * di
 __host__ __device__ constexpr int kv_12(int dim) { return 4 * dim + 4; }
 
 // Half storage of K used by the hot kernels.  D K is symmetric (D = diag(I_u,
-// -I_p)): K_uu^i, K_pp^i and K12 are symmetric and K_pu^i = -(K_up^i)^T.  So
-// per node a it keeps
-//   sym kinds (kuu0, kuu1, kpp0, kpp1, k12) for the zero offset and the
-//     positive half of St (t >= s0; NH = NS - s0 offsets), stream
-//     sym(kind, t - s0);
-//   kup^i[c] for every offset t of St, stream up(i, c, t);
-// and reads the rest from the neighbour's row: for t < s0 the sym value of
-// (a, a + o_t) is the one stored at a + o_t for the mirrored offset, and
-// K_pu^i(a, (a + o_t, c)) = -kup^i[c] stored at a + o_t for the mirror of t.
-// St is sorted by linear offset and symmetric, so the mirror of t is NS-1-t.
-// 130 of the 255 streams in 3D.  The storage is sliced: the values of 64
-// consecutive nodes form one run per stream and the runs of all streams of a
-// slice are contiguous, so a wave reads one contiguous block of DRAM pages
-// instead of one page per stream (and node pairs 2i, 2i + 1 stay adjacent).
-// Streams are ordered by trip h = |t - s0| of the K product: the 5 sym kinds
-// of h, then kup^i[c] at t = s0 + h, then (h > 0) kup^i[c] at t = s0 - h, so
-// the values one trip reads from a row sit within a few KB of each other and
-// share one address register (13.5% less K-product time at 64^3 than the
-// kind-major order).
+// -I_p)): K_uu^i, K_pp^i and K12 are symmetric and K_pu^i = -(K_up^i)^T.  The
+// K_up values come from the class table UPT<D> (below), so per node a the
+// half storage keeps only the symmetric kinds (kuu0, kuu1, kpp0, kpp1, k12)
+// for the zero offset and the positive half of St (t >= s0; NH = NS - s0
+// offsets), stream sym(kind, t - s0); for t < s0 the value of (a, a + o_t) is
+// the one stored at a + o_t for the mirrored offset (St is sorted by linear
+// offset and symmetric, so the mirror of t is NS-1-t).  40 streams in 3D, 20
+// in 2D.  The storage is sliced: the values of 64 consecutive nodes form one
+// run per stream and the runs of all streams of a slice are contiguous, so a
+// wave reads one contiguous block of DRAM pages instead of one page per
+// stream.  Streams are ordered by trip h = |t - s0| of the K product (the 5
+// kinds of h together), so the values one trip reads from a row sit next to
+// each other and share one address register.
 template <int D>
 struct KH {
   static constexpr int NS = D == 3 ? 15 : 7;
   static constexpr int S0 = (NS - 1) / 2;
   static constexpr int NH = NS - S0;
   static constexpr int NSYM = 5;
-  static constexpr int streams = NSYM * NH + 2 * D * NS;
+  static constexpr int streams = NSYM * NH;
   // sym kind ids
   static constexpr int UU0 = 0, UU1 = 1, PP0 = 2, PP1 = 3, K12 = 4;
-  // first stream of trip h (h = 0 holds 5 + 2D streams, the others 5 + 4D)
-  __host__ __device__ static constexpr int tb(int h) {
-    return h == 0 ? 0 : (NSYM + 2 * D) + (h - 1) * (NSYM + 4 * D);
-  }
-  __host__ __device__ static constexpr int sym(int kind, int h) { return tb(h) + kind; }
-  __host__ __device__ static constexpr int up(int net, int c, int t) {
-    return t >= S0 ? tb(t - S0) + NSYM + net * D + c : tb(S0 - t) + NSYM + 2 * D + net * D + c;
-  }
+  __host__ __device__ static constexpr int sym(int kind, int h) { return h * NSYM + kind; }
   static constexpr int SLICE = 64;
   // element of stream s at node a
   __host__ __device__ static size_t at(int s, long a) {
@@ -239,6 +229,22 @@ struct KH {
   __host__ __device__ static size_t size(long N) {
     return (size_t)((N + SLICE - 1) / SLICE) * streams * SLICE;
   }
+};
+
+// Table of the K_up values by boundary class.  The velocity-pressure
+// couplings of the CG-VMS form carry no coefficient: the Galerkin term
+// -(div w; p) has none and in the stabilisation -1/2 (mu k^-1 w; (k/mu) grad p)
+// the permeabilities cancel (eq. CG_VMS_Weak_form).  On the uniform box the
+// value of K_up^i((a, c), a + o_t) is then a sum over the cells around a that
+// exist, i.e. a function of (class of a, t, c), the same for both networks
+// and bit-identical for every node of a class (the cell sums run in the same
+// order).  UPT<D> lays the table out as [class][t][c].
+template <int D>
+struct UPT {
+  static constexpr int NS = D == 3 ? 15 : 7;
+  static constexpr int NCLS = D == 3 ? 27 : 9;
+  static constexpr int size = NCLS * NS * D;
+  __host__ __device__ static constexpr int at(int cls, int t, int c) { return (cls * NS + t) * D + c; }
 };
 
 template <int D>
@@ -256,9 +262,6 @@ constexpr bool kh_streams_bijective() {
   int seen[L::streams] = {};
   for (int k = 0; k < L::NSYM; ++k)
     for (int h = 0; h < L::NH; ++h) seen[L::sym(k, h)] += 1;
-  for (int q = 0; q < 2; ++q)
-    for (int c = 0; c < D; ++c)
-      for (int t = 0; t < L::NS; ++t) seen[L::up(q, c, t)] += 1;
   for (int s = 0; s < L::streams; ++s)
     if (seen[s] != 1) return false;
   return true;
@@ -287,6 +290,13 @@ __device__ inline bool inside(const GridDev &g, int i, int j, int k) {
 
 __device__ inline long lin(const GridDev &g, int dx, int dy, int dz) {
   return (long)dx + (long)g.m[0] * ((long)dy + (long)g.m[1] * dz);
+}
+
+// Boundary class (UPT) of the node with indices i, j, k (inside the box).
+template <int D>
+__device__ inline int node_class(const GridDev &g, int i, int j, int k) {
+  const int c = axis_class(i, g.n[0]) + 3 * axis_class(j, g.n[1]);
+  return D == 3 ? c + 9 * axis_class(k, g.n[2]) : c;
 }
 
 // --------------------------------------------------------- XCD mapping ----

@@ -63,6 +63,7 @@ struct dpp_problem_s {
   dpp::DBuf kh;         // half storage (layout KH<dim>) read by the hot kernels
   dpp::DBuf kh32;       // FP32 copy of kh (mixed precision), made on demand
   dpp::DBuf korder;     // [blocks] node block of each K-product workgroup (column order)
+  dpp::DBuf upt, upt32; // K_up class table (UPT<dim>), FP64 and FP32 copies
   dpp::DBuf f;          // [n_dof]
   dpp::DBuf dinv;       // [2][N] 1/diag(K_uu^i)
   dpp::DBuf k1, k2, betac;  // coefficient copies [n_cells] for the gradient
@@ -142,6 +143,7 @@ void spmv_block(dpp_problem P, int which, const double *x, double *y, hipStream_
 void make_dinv(dpp_problem P, hipStream_t s);
 void make_selfp(dpp_problem P, double *S, hipStream_t s);
 void make_kh(dpp_problem P, hipStream_t s);
+void make_up_table(dpp_problem P, hipStream_t s);
 void make_k32(dpp_problem P, hipStream_t s);
 // Schur fieldsplit pieces: rhat_i = r_p_i - K_pu^i diag^-1 r_u_i ; z_u = diag^-1 (r_u - K_up z_p)
 // With ldinv non-null it also writes the finest level's first Chebyshev step

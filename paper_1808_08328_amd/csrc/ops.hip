@@ -2,12 +2,14 @@
 // the block views K_up^i / K_pu^i, the selfp Schur blocks and the two
 // velocity-side steps of the Schur fieldsplit.
 //
-// The K product is bandwidth bound (about 0.2 flop per byte).  It reads the
-// half storage of K (the symmetric kinds on the zero offset and the positive
-// half of the stencil, kup on every offset; structure-of-arrays, coalesced)
-// and takes the other half from the neighbours' rows, which are at most one
-// node plane away and mostly served from L2.  Assembly, selfp and the CSR
-// export read the full node-pair storage.
+// The K product is bandwidth bound.  It reads the half storage of K (the
+// symmetric kinds on the zero offset and the positive half of the stencil;
+// structure-of-arrays, coalesced), takes the other half from the neighbours'
+// rows, which are at most one node plane away and mostly served from L2, and
+// takes every K_up / K_pu value from the class table (UPT), which each
+// workgroup stages in LDS.  The two velocity-side steps of the fieldsplit read
+// only that table for their K blocks.  Assembly, selfp and the CSR export
+// read the full node-pair storage.
 #include <algorithm>
 #include <vector>
 
@@ -19,23 +21,33 @@ namespace dpp {
 
 namespace {
 
-// One workgroup per 64-node slice of kh (KBS threads); order[] gives the
-// slice of each workgroup (column order, below).
-constexpr int KBS = 64;
+// One workgroup per KBS-node block of kh (KBS threads); order[] gives the
+// block of each workgroup (column order, below).
+constexpr int KBS = 128;
+
+// The K_up class table (UPT<D>) copied into LDS by every workgroup.
+template <int D, typename TV>
+__device__ inline void stage_upt(TV *sut, const TV *__restrict__ upt) {
+  for (int i = threadIdx.x; i < UPT<D>::size; i += blockDim.x) sut[i] = upt[i];
+  __syncthreads();
+}
 
 // BC: the problem has velocity faces; their prescribed components have
 // identity rows (y_u = x_u there).
 template <int D, typename TV, bool BC>
 __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict__ kv,
+                                                const TV *__restrict__ upt,
                                                 const double *__restrict__ x,
                                                 const double *__restrict__ bsub,
                                                 double *__restrict__ y,
                                                 const int *__restrict__ order) {
+  __shared__ TV sut[UPT<D>::size];
+  stage_upt<D>(sut, upt);
   const long N = g.N;
   const long a = (long)order[blockIdx.x] * KBS + threadIdx.x;
   if (a >= N) return;
   double au[2][D], ap[2];
-  spmv_K_node<D, TV, BC>(g, kv, x, a, au, ap);
+  spmv_K_node<D, TV, BC>(g, kv, sut, x, a, au, ap);
   int ia[3] = {0, 0, 0};
   if constexpr (BC) node_ijk(g, a, ia[0], ia[1], ia[2]);
 #pragma unroll
@@ -97,8 +109,9 @@ __global__ void k_dinv(GridDev g, const double *__restrict__ kv, double *__restr
   for (int q = 0; q < 2; ++q) dinv[q * N + a] = 1.0 / kv[kv_uu(D, q) * vs + (size_t)t0 * g.ld + a];
 }
 
-// Half storage of K (layout KH<D>) from the full node-pair storage.  One
-// thread per (stream, node).
+// Half storage of K (layout KH<D>: the symmetric kinds on the zero offset and
+// the positive half of St) from the full node-pair storage.  One thread per
+// (stream, node).
 template <int D>
 __global__ void k_pack_kh(GridDev g, const double *__restrict__ kv, double *__restrict__ kh) {
   using L = KH<D>;
@@ -108,22 +121,33 @@ __global__ void k_pack_kh(GridDev g, const double *__restrict__ kv, double *__re
   if (idx >= (long)L::streams * N) return;
   const int st = (int)(idx / N);
   const long a = idx - (long)st * N;
-  // st enumerates (sym kind, h) then (net, c, t); dst is its place in KH<D>
-  int kind, t, dst;
-  if (st < L::NSYM * L::NH) {
-    const int k = st / L::NH, h = st % L::NH;
-    t = h + L::S0;
-    kind = k == L::UU0 ? kv_uu(D, 0) : k == L::UU1 ? kv_uu(D, 1) : k == L::PP0 ? kv_pp(D, 0)
-         : k == L::PP1 ? kv_pp(D, 1) : kv_12(D);
-    dst = L::sym(k, h);
-  } else {
-    const int r = st - L::NSYM * L::NH;
-    const int qc = r / L::NS;
-    t = r % L::NS;
-    kind = kv_up(D, qc / D, qc % D);
-    dst = L::up(qc / D, qc % D, t);
+  const int k = st / L::NH, h = st % L::NH;
+  const int kind = k == L::UU0 ? kv_uu(D, 0) : k == L::UU1 ? kv_uu(D, 1) : k == L::PP0 ? kv_pp(D, 0)
+                 : k == L::PP1 ? kv_pp(D, 1) : kv_12(D);
+  kh[L::at(L::sym(k, h), a)] = kv[kind * vs + (size_t)(h + L::S0) * ld + a];
+}
+
+// K_up class table (UPT<D>) read from the assembled values of one node of
+// each class (first network; both networks hold the same values).  Classes with
+// no node (an axis with a single cell has no interior node) are zero.  Must
+// run before the velocity faces mask K.
+template <int D>
+__global__ void k_up_table(GridDev g, const double *__restrict__ kv, double *__restrict__ upt) {
+  using U = UPT<D>;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= U::size) return;
+  const int c = idx % D, t = (idx / D) % U::NS, cls = idx / (D * U::NS);
+  int ijk[3] = {0, 0, 0}, cc = cls;
+  bool exists = true;
+  for (int ax = 0; ax < D; ++ax) {
+    const int k = cc % 3;
+    cc /= 3;
+    ijk[ax] = k == 0 ? 0 : (k == 2 ? g.n[ax] : 1);
+    if (k == 1 && g.n[ax] < 2) exists = false;
   }
-  kh[L::at(dst, a)] = kv[kind * vs + (size_t)t * ld + a];
+  const long a = ijk[0] + (long)g.m[0] * (ijk[1] + (long)g.m[1] * ijk[2]);
+  const size_t vs = (size_t)U::NS * g.ld;
+  upt[idx] = exists ? kv[kv_up(D, 0, c) * vs + (size_t)t * g.ld + a] : 0.0;
 }
 
 // selfp Schur block (eqs. S4_sp1, S4_sp2):
@@ -171,19 +195,21 @@ __global__ __launch_bounds__(256) void k_selfp(GridDev g, const double *__restri
 
 // rhat = r_p - K_pu D^-1 r_u; with ldinv non-null also the multigrid's first
 // Chebyshev step on rhat (pointwise): xa = d = c2 ldinv rhat.
-template <int D, typename TV, typename TX>
-__global__ __launch_bounds__(256) void k_schur_rhs(GridDev g, const TV *__restrict__ kv,
+template <int D, typename TV, typename TX, bool BC>
+__global__ __launch_bounds__(256) void k_schur_rhs(GridDev g, const TV *__restrict__ upt,
                                                    const double *__restrict__ dinv,
                                                    const double *__restrict__ r,
                                                    TX *__restrict__ rhat,
                                                    const TX *__restrict__ ldinv,
                                                    TX *__restrict__ xa, TX *__restrict__ dd,
                                                    Sc2 c2) {
+  __shared__ TV sut[UPT<D>::size];
+  stage_upt<D>(sut, upt);
   const int q = blockIdx.y;
   const long b = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (b >= g.N) return;
   const size_t ib = (size_t)q * g.N + b;
-  const TX v = (TX)schur_rhs_node<D, TV>(g, kv, dinv, r, q, b);
+  const TX v = (TX)schur_rhs_node<D, TV, BC>(g, sut, dinv, r, q, b);
   rhat[ib] = v;
   if (ldinv) {
     const double x0 = c2.v[q] * (double)ldinv[ib] * (double)v;
@@ -195,11 +221,13 @@ __global__ __launch_bounds__(256) void k_schur_rhs(GridDev g, const TV *__restri
 // BC: prescribed velocity components (velocity faces) keep z_u = r_u, the
 // identity rows of the masked velocity block.
 template <int D, typename TV, typename TX, bool BC>
-__global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restrict__ kv,
+__global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restrict__ upt,
                                                    const double *__restrict__ dinv,
                                                    const double *__restrict__ r,
                                                    const TX *__restrict__ zp,
                                                    double *__restrict__ z) {
+  __shared__ TV sut[UPT<D>::size];
+  stage_upt<D>(sut, upt);
   const long N = g.N;
   const int q = blockIdx.y;
   const long a = 2 * ((long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
@@ -207,7 +235,7 @@ __global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restri
   const long ou = off_u(D, N, q);
   if (a + 1 < N) {
     double out[2 * D];
-    schur_vel_node2<D, TV, TX>(g, kv, dinv, r, zp, q, a, out);
+    schur_vel_node2<D, TV, TX>(g, sut, dinv, r, zp, q, a, out);
     if constexpr (BC) {
       int ia[3], ib[3];
       node_ijk(g, a, ia[0], ia[1], ia[2]);
@@ -225,7 +253,7 @@ __global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restri
     st2(z + off_p(D, N, q) + a, (double)p0, (double)p1);
   } else {
     double out[D];
-    schur_vel_node<D, TV, TX>(g, kv, dinv, r, zp, q, a, out);
+    schur_vel_node<D, TV, TX>(g, sut, dinv, r, zp, q, a, out);
     if constexpr (BC) {
       int ia[3];
       node_ijk(g, a, ia[0], ia[1], ia[2]);
@@ -246,14 +274,17 @@ __global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, si
 
 }  // namespace
 
-// Algorithmic bytes of y = K x (or r = b - K x) from the half storage: the
-// stored own-row values (kup on every in-box St pair, the five symmetric
-// kinds on the zero offset and the positive half) once, and the vectors.
+// Algorithmic bytes of y = K x (or r = b - K x): the five symmetric kinds of
+// the half storage (zero offset and positive half) once, the K_up class
+// table once, and the vectors.
+static double upt_bytes(const Grid &g, bool fp32) {
+  return (g.dim == 3 ? UPT<3>::size : UPT<2>::size) * (fp32 ? 4.0 : 8.0);
+}
 static double kbytes(const Grid &g, bool fp32, bool resid) {
   const double pairs = g.dim == 3 ? valid_pairs<3, false>(g) : valid_pairs<2, false>(g);
   const double half = 0.5 * (pairs + g.N);
   const double nd = (2.0 * g.dim + 2.0) * g.N;
-  return (pairs * 2.0 * g.dim + half * 5.0) * (fp32 ? 4.0 : 8.0) + nd * 8.0 * (resid ? 3.0 : 2.0);
+  return half * 5.0 * (fp32 ? 4.0 : 8.0) + upt_bytes(g, fp32) + nd * 8.0 * (resid ? 3.0 : 2.0);
 }
 
 void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32) {
@@ -264,14 +295,14 @@ void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32)
   ProfScope ps(PF_SPMV_K, kbytes(g, fp32, false), s);
   if (g.dim == 3) {
     if (fp32)
-      (bc ? k_spmv_K<3, float, true> : k_spmv_K<3, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, nullptr, y, ord);
+      (bc ? k_spmv_K<3, float, true> : k_spmv_K<3, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), P->upt32.as<float>(), x, nullptr, y, ord);
     else
-      (bc ? k_spmv_K<3, double, true> : k_spmv_K<3, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, nullptr, y, ord);
+      (bc ? k_spmv_K<3, double, true> : k_spmv_K<3, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), P->upt.as<double>(), x, nullptr, y, ord);
   } else {
     if (fp32)
-      (bc ? k_spmv_K<2, float, true> : k_spmv_K<2, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, nullptr, y, ord);
+      (bc ? k_spmv_K<2, float, true> : k_spmv_K<2, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), P->upt32.as<float>(), x, nullptr, y, ord);
     else
-      (bc ? k_spmv_K<2, double, true> : k_spmv_K<2, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, nullptr, y, ord);
+      (bc ? k_spmv_K<2, double, true> : k_spmv_K<2, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), P->upt.as<double>(), x, nullptr, y, ord);
   }
   check_launch("spmv_K");
 }
@@ -285,14 +316,14 @@ void residual_K(dpp_problem P, const double *b, const double *x, double *r, hipS
   ProfScope ps(PF_SPMV_K, kbytes(g, fp32, true), s);
   if (g.dim == 3) {
     if (fp32)
-      (bc ? k_spmv_K<3, float, true> : k_spmv_K<3, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, b, r, ord);
+      (bc ? k_spmv_K<3, float, true> : k_spmv_K<3, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), P->upt32.as<float>(), x, b, r, ord);
     else
-      (bc ? k_spmv_K<3, double, true> : k_spmv_K<3, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, b, r, ord);
+      (bc ? k_spmv_K<3, double, true> : k_spmv_K<3, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), P->upt.as<double>(), x, b, r, ord);
   } else {
     if (fp32)
-      (bc ? k_spmv_K<2, float, true> : k_spmv_K<2, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), x, b, r, ord);
+      (bc ? k_spmv_K<2, float, true> : k_spmv_K<2, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), P->upt32.as<float>(), x, b, r, ord);
     else
-      (bc ? k_spmv_K<2, double, true> : k_spmv_K<2, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), x, b, r, ord);
+      (bc ? k_spmv_K<2, double, true> : k_spmv_K<2, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), P->upt.as<double>(), x, b, r, ord);
   }
   check_launch("residual_K");
 }
@@ -327,6 +358,17 @@ void make_selfp(dpp_problem P, double *S, hipStream_t s) {
   check_launch("selfp");
 }
 
+void make_up_table(dpp_problem P, hipStream_t s) {
+  const Grid &g = P->g;
+  const int n = g.dim == 3 ? UPT<3>::size : UPT<2>::size;
+  P->upt.alloc(sizeof(double) * n);
+  if (g.dim == 3)
+    k_up_table<3><<<blocks_for(n, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->upt.as<double>());
+  else
+    k_up_table<2><<<blocks_for(n, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->upt.as<double>());
+  check_launch("K_up class table");
+}
+
 void make_kh(dpp_problem P, hipStream_t s) {
   const Grid &g = P->g;
   const int streams = g.dim == 3 ? KH<3>::streams : KH<2>::streams;
@@ -351,34 +393,39 @@ void make_k32(dpp_problem P, hipStream_t s) {
   size_t n = P->kh.bytes / sizeof(double);
   P->kh32.alloc(n * sizeof(float));
   k_to_f32<<<2048, 256, 0, s>>>(P->kh.as<double>(), P->kh32.as<float>(), n);
+  n = P->upt.bytes / sizeof(double);
+  P->upt32.alloc(n * sizeof(float));
+  k_to_f32<<<blocks_for((long)n, 256), 256, 0, s>>>(P->upt.as<double>(), P->upt32.as<float>(), n);
   check_launch("k32");
 }
 
 void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_t s,
                const void *ldinv, void *xa, void *dd, const double *c2) {
   const Grid &g = P->g;
-  const double pairs = g.dim == 3 ? valid_pairs<3, false>(g) : valid_pairs<2, false>(g);
   const double tx = fp32 ? 4.0 : 8.0;
   ProfScope ps(PF_SCHUR_RHS,
-               2.0 * (pairs * g.dim * tx + g.N * (g.dim + 2.0) * 8.0 + g.N * tx +
+               2.0 * (upt_bytes(g, fp32) + g.N * (g.dim + 2.0) * 8.0 + g.N * tx +
                       (ldinv ? 3.0 * g.N * tx : 0.0)), s);
   dim3 grid(blocks_for(g.N, 256), 2);
   const double *di = P->dinv.as<double>();
   const Sc2 c{{c2 ? c2[0] : 0.0, c2 ? c2[1] : 0.0}};
+  const bool bc = (g.fix[0] | g.fix[1]) != 0;
+  const float *u32 = P->upt32.as<float>();
+  const double *u64 = P->upt.as<double>();
   if (g.dim == 3) {
     if (fp32)
-      k_schur_rhs<3, float, float><<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (float *)rhat,
-                                                        (const float *)ldinv, (float *)xa, (float *)dd, c);
+      (bc ? k_schur_rhs<3, float, float, true> : k_schur_rhs<3, float, float, false>)<<<grid, 256, 0, s>>>(
+          dev(g), u32, di, r, (float *)rhat, (const float *)ldinv, (float *)xa, (float *)dd, c);
     else
-      k_schur_rhs<3, double, double><<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (double *)rhat,
-                                                          (const double *)ldinv, (double *)xa, (double *)dd, c);
+      (bc ? k_schur_rhs<3, double, double, true> : k_schur_rhs<3, double, double, false>)<<<grid, 256, 0, s>>>(
+          dev(g), u64, di, r, (double *)rhat, (const double *)ldinv, (double *)xa, (double *)dd, c);
   } else {
     if (fp32)
-      k_schur_rhs<2, float, float><<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (float *)rhat,
-                                                        (const float *)ldinv, (float *)xa, (float *)dd, c);
+      (bc ? k_schur_rhs<2, float, float, true> : k_schur_rhs<2, float, float, false>)<<<grid, 256, 0, s>>>(
+          dev(g), u32, di, r, (float *)rhat, (const float *)ldinv, (float *)xa, (float *)dd, c);
     else
-      k_schur_rhs<2, double, double><<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (double *)rhat,
-                                                          (const double *)ldinv, (double *)xa, (double *)dd, c);
+      (bc ? k_schur_rhs<2, double, double, true> : k_schur_rhs<2, double, double, false>)<<<grid, 256, 0, s>>>(
+          dev(g), u64, di, r, (double *)rhat, (const double *)ldinv, (double *)xa, (double *)dd, c);
   }
   check_launch("schur_rhs");
 }
@@ -386,23 +433,22 @@ void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_
 void schur_velocity(dpp_problem P, const double *r, const void *zp, bool fp32, double *z,
                     hipStream_t s) {
   const Grid &g = P->g;
-  const double pairs = g.dim == 3 ? valid_pairs<3, false>(g) : valid_pairs<2, false>(g);
   ProfScope ps(PF_SCHUR_VEL,
-               2.0 * (pairs * g.dim * (fp32 ? 4.0 : 8.0) + g.N * (2.0 * g.dim + 2.0) * 8.0 +
+               2.0 * (upt_bytes(g, fp32) + g.N * (2.0 * g.dim + 2.0) * 8.0 +
                       g.N * (fp32 ? 4.0 : 8.0)), s);
   dim3 grid(blocks_for((g.N + 1) / 2, 256), 2);
   const double *di = P->dinv.as<double>();
   const bool bc = (g.fix[0] | g.fix[1]) != 0;
   if (g.dim == 3) {
     if (fp32)
-      (bc ? k_schur_vel<3, float, float, true> : k_schur_vel<3, float, float, false>)<<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (const float *)zp, z);
+      (bc ? k_schur_vel<3, float, float, true> : k_schur_vel<3, float, float, false>)<<<grid, 256, 0, s>>>(dev(g), P->upt32.as<float>(), di, r, (const float *)zp, z);
     else
-      (bc ? k_schur_vel<3, double, double, true> : k_schur_vel<3, double, double, false>)<<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (const double *)zp, z);
+      (bc ? k_schur_vel<3, double, double, true> : k_schur_vel<3, double, double, false>)<<<grid, 256, 0, s>>>(dev(g), P->upt.as<double>(), di, r, (const double *)zp, z);
   } else {
     if (fp32)
-      (bc ? k_schur_vel<2, float, float, true> : k_schur_vel<2, float, float, false>)<<<grid, 256, 0, s>>>(dev(g), P->kh32.as<float>(), di, r, (const float *)zp, z);
+      (bc ? k_schur_vel<2, float, float, true> : k_schur_vel<2, float, float, false>)<<<grid, 256, 0, s>>>(dev(g), P->upt32.as<float>(), di, r, (const float *)zp, z);
     else
-      (bc ? k_schur_vel<2, double, double, true> : k_schur_vel<2, double, double, false>)<<<grid, 256, 0, s>>>(dev(g), P->kh.as<double>(), di, r, (const double *)zp, z);
+      (bc ? k_schur_vel<2, double, double, true> : k_schur_vel<2, double, double, false>)<<<grid, 256, 0, s>>>(dev(g), P->upt.as<double>(), di, r, (const double *)zp, z);
   }
   check_launch("schur_velocity");
 }

@@ -179,22 +179,26 @@ constexpr int stored_offsets() {
 // (distinct kernel names in profiles); the code is the same.
 
 // y for the 2d+2 unknowns of node a: au[i][c] (velocity rows), ap[i]
-// (pressure rows), from the half storage kh of K.
+// (pressure rows), from the half storage kh of K (symmetric kinds) and the
+// K_up class table ut (UPT<D>, staged in LDS by the caller).
 //
 // One trip per stored offset o = o_{s0+h} (h = 0 .. NH-1) covers the pairs
-// (a, a + o) and (a, a - o).  The values of (a, a - o) are the ones node
-// a - o stores for +o, and K_pu(a, (a +- o, c)) = -kup[c] stored at a +- o for
-// -+o: every value read from a neighbour's row is one that the neighbour reads
-// as its own in the same trip, so with all waves in step those reads hit L2.
-// Own-row values of pairs that leave the box are stored zeros (the neighbour
-// index is clamped, not guarded); neighbour-row values are masked when the
-// neighbour's linear index falls outside [0, N) (a wrapped index inside
-// [0, N) reads a pair that leaves the box from that node, a stored zero).
+// (a, a + o) and (a, a - o).  The symmetric values of (a, a - o) are the ones
+// node a - o stores for +o: every value read from a neighbour's row is one
+// that the neighbour reads as its own in the same trip, so with all waves in
+// step those reads hit L2.  K_up((a,c), a +- o) is ut at a's class and
+// K_pu(a, (a +- o, c)) = -K_up((a +- o, c), a) is ut at the neighbour's class
+// for -+o (zero when the neighbour is outside the box).  Own-row symmetric
+// values of pairs that leave the box are stored zeros (the neighbour index is
+// clamped, not guarded); neighbour-row values are masked when the neighbour's
+// linear index falls outside [0, N) (a wrapped index inside [0, N) reads a
+// pair that leaves the box from that node, a stored zero).
 template <int D, typename TV, bool BC = false>
-__device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
+__device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh, const TV *ut,
                                    const double *__restrict__ x, long a, double au[2][D],
                                    double ap[2]) {
   using L = KH<D>;
+  using U = UPT<D>;
   const long N = g.N;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
@@ -205,10 +209,10 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
   const long ou[2] = {off_u(D, N, 0), off_u(D, N, 1)};
   const long op[2] = {off_p(D, N, 0), off_p(D, N, 1)};
   // with velocity faces (BC): prescribed velocity components are removed from
-  // the columns (K_up / K_pu values of those DOFs are stored zeros; the K_uu
-  // values are masked here through x)
-  int ia[3] = {0, 0, 0};
-  if constexpr (BC) node_ijk(g, a, ia[0], ia[1], ia[2]);
+  // the columns, here through x (the table and kh hold the unmasked values)
+  int ia[3];
+  node_ijk(g, a, ia[0], ia[1], ia[2]);
+  const int ca = node_class<D>(g, ia[0], ia[1], ia[2]);
 #pragma unroll 1
   for (int h = 0; h < L::NH; ++h) {
     const int tp = L::S0 + h, tn = L::S0 - h;
@@ -217,10 +221,23 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
     const long bp = min(a + lo, N - 1);     // a + o (own-row values guard it)
     const long bnr = a - lo;
     const long bn = max(bnr, 0L);           // a - o
-    const double mp = (a + lo < N) ? 1.0 : 0.0, mn = (bnr >= 0) ? 1.0 : 0.0;
-    // pair (a, a + o): symmetric kinds own, kup own at tp, kup of a + o at tn
+    const double mn = (bnr >= 0) ? 1.0 : 0.0;
+    // K_up((a,c), a+o), K_up((a,c), a-o), and the neighbours' K_up toward a
+    const int pb[3] = {ia[0] + o[0], ia[1] + o[1], ia[2] + o[2]};
+    const int nb[3] = {ia[0] - o[0], ia[1] - o[1], ia[2] - o[2]};
+    const bool ip = inside(g, pb[0], pb[1], pb[2]), im = inside(g, nb[0], nb[1], nb[2]);
+    const int cp = ip ? node_class<D>(g, pb[0], pb[1], pb[2]) : 0;
+    const int cm = im ? node_class<D>(g, nb[0], nb[1], nb[2]) : 0;
+    double utp[D], utn[D], ptn[D], mtp[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      utp[c] = (double)ut[U::at(ca, tp, c)];
+      utn[c] = (double)ut[U::at(ca, tn, c)];
+      ptn[c] = ip ? (double)ut[U::at(cp, tn, c)] : 0.0;
+      mtp[c] = im ? (double)ut[U::at(cm, tp, c)] : 0.0;
+    }
+    // pair (a, a + o): symmetric kinds own
     double xu[D], xp[2], xo[2];
-    // symmetric kinds
     const double uu0 = (double)kh[L::at(L::sym(L::UU0, h), a)];
     const double uu1 = (double)kh[L::at(L::sym(L::UU1, h), a)];
     const double pp0 = (double)kh[L::at(L::sym(L::PP0, h), a)];
@@ -233,7 +250,6 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
 #pragma unroll
       for (int c = 0; c < D; ++c) xu[c] = x[ou[q] + D * bp + c];
       if constexpr (BC) {
-        const int pb[3] = {ia[0] + o[0], ia[1] + o[1], ia[2] + o[2]};
 #pragma unroll
         for (int c = 0; c < D; ++c)
           if (u_fixed(g, q, c, pb)) xu[c] = 0.0;
@@ -241,17 +257,15 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
       const double uu = q ? uu1 : uu0, pp = q ? pp1 : pp0;
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        const double up = (double)kh[L::at(L::up(q, c, tp), a)];
-        const double pu = -mp * (double)kh[L::at(L::up(q, c, tn), bp)];
-        au[q][c] += uu * xu[c] + up * xp[q];
-        ap[q] += pu * xu[c];
+        au[q][c] += uu * xu[c] + utp[c] * xp[q];
+        ap[q] -= ptn[c] * xu[c];
       }
       ap[q] += pp * xp[q];
     }
     ap[0] += s12 * xp[1];
     ap[1] += s12 * xp[0];
     if (h == 0) continue;  // the zero offset has no mirror pair
-    // pair (a, a - o): symmetric kinds stored at a - o, kup own at tn, kup of a - o at tp
+    // pair (a, a - o): symmetric kinds stored at a - o
     const double vuu0 = mn * (double)kh[L::at(L::sym(L::UU0, h), bn)];
     const double vuu1 = mn * (double)kh[L::at(L::sym(L::UU1, h), bn)];
     const double vpp0 = mn * (double)kh[L::at(L::sym(L::PP0, h), bn)];
@@ -264,7 +278,6 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
 #pragma unroll
       for (int c = 0; c < D; ++c) xu[c] = x[ou[q] + D * bn + c];
       if constexpr (BC) {
-        const int nb[3] = {ia[0] - o[0], ia[1] - o[1], ia[2] - o[2]};
 #pragma unroll
         for (int c = 0; c < D; ++c)
           if (u_fixed(g, q, c, nb)) xu[c] = 0.0;
@@ -272,10 +285,8 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
       const double uu = q ? vuu1 : vuu0, pp = q ? vpp1 : vpp0;
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        const double up = (double)kh[L::at(L::up(q, c, tn), a)];
-        const double pu = -mn * (double)kh[L::at(L::up(q, c, tp), bn)];
-        au[q][c] += uu * xu[c] + up * xo[q];
-        ap[q] += pu * xu[c];
+        au[q][c] += uu * xu[c] + utn[c] * xo[q];
+        ap[q] -= mtp[c] * xu[c];
       }
       ap[q] += pp * xo[q];
     }
@@ -285,49 +296,63 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh,
 }
 
 // rhat_i(b) = r_p_i(b) - sum_t sum_c K_pu^i(b, (b+o_t, c)) dinv_i(b+o_t) r_u_i(b+o_t, c)
-// with K_pu^i(b, (a, c)) = -kup^i[c] stored at a = b + o_t for the mirror of t.
-template <int D, typename TV>
-__device__ inline double schur_rhs_node(const GridDev &g, const TV *__restrict__ kh,
+// with K_pu^i(b, (a, c)) = -K_up^i((a, c), b), ut at a's class for the mirror
+// of t.  With BC the columns of prescribed velocity components are masked.
+template <int D, typename TV, bool BC = false>
+__device__ inline double schur_rhs_node(const GridDev &g, const TV *ut,
                                         const double *__restrict__ dinv,
                                         const double *__restrict__ r, int q, long b) {
-  using L = KH<D>;
+  using U = UPT<D>;
+  constexpr int NS = U::NS;
   const long N = g.N;
   const long ou = off_u(D, N, q);
   double acc = r[off_p(D, N, q) + b];
+  int ib[3];
+  node_ijk(g, b, ib[0], ib[1], ib[2]);
   // offsets in unrolled groups of 5 (loads of a group in flight together)
 #pragma unroll 5
-  for (int t = 0; t < L::NS; ++t) {
+  for (int t = 0; t < NS; ++t) {
     const int *o = TAB<D>.so[t];
-    const long araw = b + lin(g, o[0], o[1], o[2]);
-    const long a = min(max(araw, 0L), N - 1);
-    const double di = (araw == a) ? dinv[q * N + a] : 0.0;
+    const long a = min(max(b + lin(g, o[0], o[1], o[2]), 0L), N - 1);
+    const int pa[3] = {ib[0] + o[0], ib[1] + o[1], ib[2] + o[2]};
+    const bool in = inside(g, pa[0], pa[1], pa[2]);
+    const int ca = in ? node_class<D>(g, pa[0], pa[1], pa[2]) : 0;
+    const double di = in ? dinv[q * N + a] : 0.0;
     double s = 0.0;
 #pragma unroll
-    for (int c = 0; c < D; ++c)
-      s += (double)kh[L::at(L::up(q, c, L::NS - 1 - t), a)] * r[ou + D * a + c];
+    for (int c = 0; c < D; ++c) {
+      double rv = r[ou + D * a + c];
+      if constexpr (BC)
+        if (u_fixed(g, q, c, pa)) rv = 0.0;
+      s += (double)ut[U::at(ca, NS - 1 - t, c)] * rv;
+    }
     acc += s * di;
   }
   return acc;
 }
 
-// z_u_i(a, c) = dinv_i(a) (r_u_i(a, c) - sum_t K_up^i((a,c), a+o_t) z_p_i(a+o_t))
+// z_u_i(a, c) = dinv_i(a) (r_u_i(a, c) - sum_t K_up^i((a,c), a+o_t) z_p_i(a+o_t)),
+// K_up from the class table ut.
 template <int D, typename TV, typename TX>
-__device__ inline void schur_vel_node(const GridDev &g, const TV *__restrict__ kh,
+__device__ inline void schur_vel_node(const GridDev &g, const TV *ut,
                                       const double *__restrict__ dinv,
                                       const double *__restrict__ r, const TX *__restrict__ zp,
                                       int q, long a, double out[D]) {
-  using L = KH<D>;
+  using U = UPT<D>;
   const long N = g.N;
   const long ou = off_u(D, N, q);
+  int i, j, k;
+  node_ijk(g, a, i, j, k);
+  const int ca = node_class<D>(g, i, j, k);
 #pragma unroll
   for (int c = 0; c < D; ++c) out[c] = r[ou + D * a + c];
 #pragma unroll
-  for (int t = 0; t < L::NS; ++t) {
+  for (int t = 0; t < U::NS; ++t) {
     const int *o = TAB<D>.so[t];
     const long b = min(max(a + lin(g, o[0], o[1], o[2]), 0L), N - 1);
     const double zb = (double)zp[q * N + b];
 #pragma unroll
-    for (int c = 0; c < D; ++c) out[c] -= (double)kh[L::at(L::up(q, c, t), a)] * zb;
+    for (int c = 0; c < D; ++c) out[c] -= (double)ut[U::at(ca, t, c)] * zb;
   }
   const double di = dinv[q * N + a];
 #pragma unroll
@@ -336,39 +361,42 @@ __device__ inline void schur_vel_node(const GridDev &g, const TV *__restrict__ k
 
 // schur_vel_node for rows a and a + 1 (a even, a + 1 < N), paired loads.
 template <int D, typename TV, typename TX>
-__device__ inline void schur_vel_node2(const GridDev &g, const TV *__restrict__ kh,
+__device__ inline void schur_vel_node2(const GridDev &g, const TV *ut,
                                        const double *__restrict__ dinv,
                                        const double *__restrict__ r, const TX *__restrict__ zp,
                                        int q, long a, double out[2 * D]) {
-  using L = KH<D>;
+  using U = UPT<D>;
   const long N = g.N;
   const long ou = off_u(D, N, q);
+  int i, j, k;
+  node_ijk(g, a, i, j, k);
+  const int c0 = node_class<D>(g, i, j, k);
+  node_ijk(g, a + 1, i, j, k);
+  const int c1 = node_class<D>(g, i, j, k);
 #pragma unroll
-  for (int k = 0; k < D; ++k) ld2(r + ou + D * a + 2 * k, out[2 * k], out[2 * k + 1]);
+  for (int k2 = 0; k2 < D; ++k2) ld2(r + ou + D * a + 2 * k2, out[2 * k2], out[2 * k2 + 1]);
 #pragma unroll 5
-  for (int t = 0; t < L::NS; ++t) {
+  for (int t = 0; t < U::NS; ++t) {
     const int *o = TAB<D>.so[t];
     const long b = a + lin(g, o[0], o[1], o[2]);
     const long c = min(max(b, 0L), N - 2);
     const long d = b - c;
     TX z0, z1;
     ld2(zp + q * N + c, z0, z1);
-    // own-row kup of pairs that leave the box are stored zeros
+    // the table is zero for pairs that leave the box, so a clamped z is harmless
     const double za = (double)(d > 0 ? z1 : z0), zb = (double)(d < 0 ? z0 : z1);
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      TV u0, u1;
-      ld2(kh + L::at(L::up(q, k, t), a), u0, u1);
-      out[k] -= (double)u0 * za;
-      out[D + k] -= (double)u1 * zb;
+    for (int k2 = 0; k2 < D; ++k2) {
+      out[k2] -= (double)ut[U::at(c0, t, k2)] * za;
+      out[D + k2] -= (double)ut[U::at(c1, t, k2)] * zb;
     }
   }
   double di0, di1;
   ld2(dinv + q * N + a, di0, di1);
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    out[k] *= di0;
-    out[D + k] *= di1;
+  for (int k2 = 0; k2 < D; ++k2) {
+    out[k2] *= di0;
+    out[D + k2] *= di1;
   }
 }
 

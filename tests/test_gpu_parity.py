@@ -98,6 +98,28 @@ def test_operator_products_match_oracle(case):
         assert relmax(H(P.spmv(T(xu), which=3 + i)), B["Kpu"][i] @ xu) <= 1e-13
 
 
+@pytest.mark.parametrize("dim,n", [(3, (1, 3, 2)), (3, (2, 1, 1)), (3, (1, 1, 1)), (3, (2, 2, 2)),
+                                   (2, (1, 4)), (2, (3, 1)), (2, (2, 2))])
+def test_thin_boxes_products_and_fieldsplit_match_oracle(dim, n):
+    """Boxes one or two cells thick: the K_up values come from a table by
+    boundary class (first / interior / last node per axis), and here an axis
+    has no interior node or a single interior layer.  K product and fieldsplit
+    apply (single-level multigrid) against the oracle, coefficients varying
+    per cell."""
+    prob = I.mms_problem(dim, n, k1=1.0, k2=0.1, beta=1.3, mu=0.9)
+    rng = np.random.default_rng(7)
+    prob.k1 = 10 ** rng.uniform(-1, 1, prob.n_cells)
+    prob.k2 = 10 ** rng.uniform(-2, 0, prob.n_cells)
+    S = odpp.assemble(prob)
+    P = lib().assemble_problem(prob)
+    x = I.random_vector(P.n_dof, 11)
+    assert relmax(H(P.spmv(T(x))), S.K @ x) <= 1e-13
+    pc = P.setup_precond()
+    F = osolver.FieldSplit(S)
+    r = I.random_vector(P.n_dof, 12)
+    assert relmax(H(pc.apply(T(r))), F.apply(r)) <= 1e-11
+
+
 @pytest.mark.parametrize("case,cmax", [("c1_2d16", 30), ("2d_ragged_grf", 10),
                                        ("3d_ragged_body", 8), ("3d_8_mms", 40)])
 def test_multigrid_hierarchy_and_cycle_match_oracle(case, cmax):
