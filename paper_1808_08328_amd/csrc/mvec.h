@@ -21,6 +21,19 @@ constexpr int MV_MAXK = 32;  // largest bucket (restart length <= 31)
 // values (nj <= MV_MAXK - 1), the other kernels at most MV_MAXK + 1.
 constexpr int MV_PART_ROWS = 2 * MV_MAXK + 2;
 
+// 16-byte loads and stores of two consecutive doubles (the DCGS2 passes
+// stream element pairs: every vector starts 16-byte aligned and has even
+// length, (2d + 2) N unknowns per instance; an odd tail is still handled).
+__device__ inline double2 mv_ld2(const double *p) {
+  double2 t;
+  __builtin_memcpy(&t, p, sizeof(t));
+  return t;
+}
+__device__ inline void mv_st2(double *p, double v0, double v1) {
+  const double2 t = {v0, v1};
+  __builtin_memcpy(p, &t, sizeof(t));
+}
+
 template <int NKP>
 constexpr int mv_unroll() {
   return NKP <= 2 ? 4 : (NKP <= 4 ? 2 : 1);
@@ -146,7 +159,8 @@ __device__ inline void mv_update(const double *__restrict__ Z, long ldz, int nk,
 // other waves hit in cache) and its own KG = NKP/4 rows, so each thread keeps
 // 2 KG accumulators.  Partial row k < nj: V_k . t, row nj + k: V_k . w, row 2nj:
 // t . w, one value per block (written by the owning wave, no block reduction).
-// Element i runs over i0 + lane, + stride, ... < n (i0, stride multiples of 64).
+// Element pair p (elements 2p, 2p + 1) runs over i0 + lane, + stride, ...
+// (i0, stride multiples of 64, in pairs).
 template <int NKP>
 __device__ inline void mv_dcgs_a_waves(const double *__restrict__ V, long ldv, int nj,
                                        const double *__restrict__ t, const double *__restrict__ w,
@@ -162,15 +176,25 @@ __device__ inline void mv_dcgs_a_waves(const double *__restrict__ V, long ldv, i
   double aa[KG], bb[KG], tw = 0.0;
 #pragma unroll
   for (int kk = 0; kk < KG; ++kk) aa[kk] = bb[kk] = 0.0;
-  for (long i = i0 + lane; i < n; i += stride) {
-    const double ti = t[i], wi = w[i];
+  // element pairs (2p, 2p + 1), p = i0 + lane, + stride, ...
+  for (long p = i0 + lane; 2 * p + 1 < n; p += stride) {
+    const double2 ti = mv_ld2(t + 2 * p), wi = mv_ld2(w + 2 * p);
 #pragma unroll
     for (int kk = 0; kk < KG; ++kk) {
-      const double v = rows[kk][i];
-      aa[kk] += v * ti;
-      bb[kk] += v * wi;
+      const double2 v = mv_ld2(rows[kk] + 2 * p);
+      aa[kk] += v.x * ti.x + v.y * ti.y;
+      bb[kk] += v.x * wi.x + v.y * wi.y;
     }
-    tw += ti * wi;
+    tw += ti.x * wi.x + ti.y * wi.y;
+  }
+  if ((n & 1) && i0 + lane == 0) {  // odd tail: the block's first lane
+    const long i = n - 1;
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk) {
+      aa[kk] += rows[kk][i] * t[i];
+      bb[kk] += rows[kk][i] * w[i];
+    }
+    tw += t[i] * w[i];
   }
 #pragma unroll
   for (int kk = 0; kk < KG; ++kk) {
@@ -196,19 +220,38 @@ __device__ inline void mv_dcgs_update(const double *__restrict__ V, long ldv, in
                                       const double *__restrict__ w, double *__restrict__ wout,
                                       long i0, long n, long stride, double &nrm) {
   const int last = nj > 0 ? nj - 1 : 0;
-  for (long i = i0; i < n; i += stride) {
-    const double ti = t[i], wi = w[i];
-    double vv[NKP];
+  // element pairs (2p, 2p + 1), p = i0, + stride, ...
+  for (long p = i0; 2 * p + 1 < n; p += stride) {
+    const long i = 2 * p;
+    const double2 ti = mv_ld2(t + i), wi = mv_ld2(w + i);
+    double2 vv[NKP];
 #pragma unroll
-    for (int k = 0; k < NKP; ++k) vv[k] = V[(size_t)min(k, last) * ldv + i];
+    for (int k = 0; k < NKP; ++k) vv[k] = mv_ld2(V + (size_t)min(k, last) * ldv + i);
+    double sa0 = 0.0, sb0 = 0.0, sa1 = 0.0, sb1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NKP; ++k) {
+      sa0 += a[k] * vv[k].x;
+      sb0 += b[k] * vv[k].x;
+      sa1 += a[k] * vv[k].y;
+      sb1 += b[k] * vv[k].y;
+    }
+    const double v0 = (ti.x - sa0) * inv, v1 = (ti.y - sa1) * inv;
+    const double w0 = wi.x - sb0 - hjj * v0, w1 = wi.y - sb1 - hjj * v1;
+    if (nj > 0) mv_st2(t + i, v0, v1);
+    mv_st2(wout + i, w0, w1);
+    nrm += w0 * w0 + w1 * w1;
+  }
+  if ((n & 1) && i0 == 0) {  // odd tail: the first thread
+    const long i = n - 1;
     double sa = 0.0, sb = 0.0;
 #pragma unroll
     for (int k = 0; k < NKP; ++k) {
-      sa += a[k] * vv[k];
-      sb += b[k] * vv[k];
+      const double vk = V[(size_t)min(k, last) * ldv + i];
+      sa += a[k] * vk;
+      sb += b[k] * vk;
     }
-    const double v = (ti - sa) * inv;
-    const double wp = wi - sb - hjj * v;
+    const double v = (t[i] - sa) * inv;
+    const double wp = w[i] - sb - hjj * v;
     if (nj > 0) t[i] = v;
     wout[i] = wp;
     nrm += wp * wp;
