@@ -75,13 +75,13 @@ typedef struct {
  * each node is prescribed (essential: identity row holding the value, the
  * value moved out of the other rows) from u_bc_i (device, [n_nodes*dim]
  * nodal velocities, node-major; required when network i has a velocity face,
- * else unread).  Batched instances take velocity faces, but not on every face
- * of both networks (DPP_ERR_UNSUPPORTED).  With velocity faces on every
- * face of both networks K is singular (kernel u = 0, p1 = p2 = const, also
- * its left kernel): the solves take the part of the right-hand side in the
- * range of K (its component along the kernel removed) and return pressures
- * normalised to int p1 = 0, the branch of the constraint of the pressure
- * space Q (int p1)(int p2) = 0 that this library takes. */
+ * else unread).  Batched instances take velocity faces too.  With velocity
+ * faces on every face of both networks K is singular (kernel u = 0, p1 = p2 =
+ * const, also its left kernel): the solves (single and batched) take the part
+ * of the right-hand side in the range of K (its component along the kernel
+ * removed) and return pressures normalised to int p1 = 0, the branch of the
+ * constraint of the pressure space Q (int p1)(int p2) = 0 that this library
+ * takes. */
 typedef struct {
   double mu;
   const double *k1;

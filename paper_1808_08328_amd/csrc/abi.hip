@@ -405,8 +405,6 @@ dpp_status dpp_assemble_batch(int nb, const dpp_box *boxes, const dpp_params *pa
         auto *P = new dpp_problem_s();
         B->P.push_back(P);
         dpp::assemble_problem(P, &boxes[i], &params[i], S(stream));
-        DPP_CHECK(!dpp::pure_flux(P->g), DPP_ERR_UNSUPPORTED,
-                  "batched instances with velocity faces everywhere (singular K) are not supported");
         B->any_bc = B->any_bc || (P->g.fix[0] | P->g.fix[1]) != 0;
         auto *pc = new dpp_precond_s();
         B->pc.push_back(pc);

@@ -713,10 +713,13 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
     B->graphs.clear();
   }
   double *V = B->V.as<double>(), *f = B->rtmp.as<double>();
-  // concatenated right-hand side
-  for (int i = 0; i < nb; ++i)
+  // concatenated right-hand side; a pure-flux instance (singular K) solves
+  // for the consistent part of its f, as the single-instance solve does
+  for (int i = 0; i < nb; ++i) {
     DPP_HIP(hipMemcpyAsync(f + B->doff[i], B->P[i]->f.ptr, sizeof(double) * B->P[i]->ndof(),
                            hipMemcpyDeviceToDevice, s));
+    if (pure_flux(B->P[i]->g)) consistent_rhs(B->P[i], f + B->doff[i], s);
+  }
   std::vector<int> act(nb, 1), conv(nb, 0), its(nb, 0), rest(nb, 0);
   std::vector<double> bn, rn(nb, 0.0);
   auto upload_active = [&]() {
@@ -903,6 +906,9 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
       break;
     }
   }
+  // pure-flux instances: normalise the pressures (int p1 = 0)
+  for (int i = 0; i < nb; ++i)
+    if (pure_flux(B->P[i]->g)) normalize_pressures(B->P[i], x + B->doff[i], s);
   DPP_HIP(hipStreamSynchronize(s));
   if (use_graph) DPP_HIP(hipStreamSynchronize(caller));
   for (int i = 0; i < nb; ++i) {

@@ -112,7 +112,7 @@ def test_batch_masks_converged_instances_and_reports_unconverged():
 def test_batch_velocity_faces_match_single_path_and_oracle(dim):
     """Instances with and without velocity faces in one batch: masked products
     and preconditioner as in the single-instance path, solutions as the
-    oracle's; a pure-flux instance (singular K) is refused."""
+    oracle's."""
     import paper_1808_08328_amd as dpp
     if dim == 2:
         probs = [I.mms_problem(2, 9, k2=0.3, flux_faces=[[1, 1, 0, 0], [0, 0, 1, 0]]),
@@ -144,7 +144,34 @@ def test_batch_velocity_faces_match_single_path_and_oracle(dim):
         F = odpp.fields(dim, S.N)
         for f in ("u1", "p1", "u2", "p2"):
             assert np.linalg.norm(xi[F[f]] - xo[F[f]]) <= 1e-10 * np.linalg.norm(xo[F[f]]), (i, f)
-    pure = I.mms_problem(dim, 4, flux_faces=[[1] * (2 * dim), [1] * (2 * dim)])
-    with pytest.raises(dpp.DppError) as e:
-        dpp.assemble_batch([probs[0], pure], coarse_max=30)
-    assert e.value.status == 7
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batch_pure_flux_instances_match_oracle(dim):
+    """Pure-flux instances (velocity faces everywhere, singular K) in a batch
+    with regular ones: each takes the consistent part of its f and returns
+    int p1 = 0, as the oracle's bordered solve; FP64 and FP32 preconditioner."""
+    import paper_1808_08328_amd as dpp
+    full = [[1] * (2 * dim), [1] * (2 * dim)]
+    if dim == 2:
+        probs = [I.mms_problem(2, 8, k2=0.1, flux_faces=full),
+                 I.mms_problem(2, (9, 6), k2=0.2, beta=2.0),
+                 I.mms_problem(2, (7, 10), k2=0.3, beta=0.5, mu=1.3, flux_faces=full)]
+    else:
+        probs = [I.mms_problem(3, (4, 3, 5), k2=0.1, mu=0.8, flux_faces=full),
+                 I.mms_problem(3, 4, k2=0.1)]
+    B = dpp.assemble_batch(probs, coarse_max=30)
+    refs = []
+    for pr in probs:
+        S = odpp.assemble(pr)
+        refs.append((S, odpp.solve_pure_flux(S) if odpp.pure_flux(pr) else odpp.solve_direct(S.K, S.f)))
+    for precision, tol in ((0, 1e-9), (2, 1e-9)):
+        xsol, st = B.solve(rtol=1e-13, precision=precision)
+        assert all(s.converged for s in st), precision
+        for i, (S, xo) in enumerate(refs):
+            xi = H(B.split(xsol)[i])
+            F = odpp.fields(dim, S.N)
+            if odpp.pure_flux(probs[i]):
+                assert abs(odpp.pressure_mean(S.mesh, xi[F["p1"]])) <= 1e-12 * np.abs(xi[F["p1"]]).max()
+            for f in ("u1", "p1", "u2", "p2"):
+                assert np.linalg.norm(xi[F[f]] - xo[F[f]]) <= tol * np.linalg.norm(xo[F[f]]), (precision, i, f)
