@@ -431,12 +431,19 @@ __global__ __launch_bounds__(256) void k_sumsq2(const double *__restrict__ x, lo
   if (threadIdx.x == 0) part[q * gridDim.x + blockIdx.x] = w[0] + w[1] + w[2] + w[3];
 }
 
-__global__ void k_sum2(const double *__restrict__ part, int nb, double *__restrict__ out) {
-  if (threadIdx.x < 2) {
+// out[q] = sum of the nb partials of network q; one 256-thread block,
+// fixed order (strided per-thread sums, wave trees, then the four waves).
+__global__ __launch_bounds__(256) void k_sum2(const double *__restrict__ part, int nb,
+                                              double *__restrict__ out) {
+  __shared__ double w[2][4];
+  for (int q = 0; q < 2; ++q) {
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[threadIdx.x * nb + b];
-    out[threadIdx.x] = s;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[q * nb + b];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) w[q][threadIdx.x >> 6] = s;
   }
+  __syncthreads();
+  if (threadIdx.x < 2) out[threadIdx.x] = w[threadIdx.x][0] + w[threadIdx.x][1] + w[threadIdx.x][2] + w[threadIdx.x][3];
 }
 
 __global__ void k_hash_start(double *__restrict__ x, long n) {
@@ -522,7 +529,7 @@ template <int D>
 void sumsq2(dpp_precond pc, const double *x, long n, double *out_host, hipStream_t s) {
   double *part = pc->red.as<double>();
   k_sumsq2<<<dim3(RED_BLOCKS, 2), 256, 0, s>>>(x, n, part);
-  k_sum2<<<1, 64, 0, s>>>(part, RED_BLOCKS, part + 2 * RED_BLOCKS);
+  k_sum2<<<1, 256, 0, s>>>(part, RED_BLOCKS, part + 2 * RED_BLOCKS);
   check_launch("sumsq2");
   DPP_HIP(hipMemcpyAsync(out_host, part + 2 * RED_BLOCKS, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   DPP_HIP(hipStreamSynchronize(s));
