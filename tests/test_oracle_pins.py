@@ -115,6 +115,45 @@ def test_block_identities():
     assert np.abs(B["Kpp"][1] @ one + B["K21"] @ one).max() < 1e-14
 
 
+@pytest.mark.parametrize("dim,n", [(3, (4, 3, 5)), (3, (1, 2, 3)), (2, (6, 5)), (2, (1, 4))])
+def test_velocity_pressure_blocks_carry_no_coefficient(dim, n):
+    """K_up^i has no permeability, beta or mu in it: in eq. CG_VMS_Weak_form the
+    Galerkin term -(div w; p) has none and the stabilisation's mu k^-1 and k/mu
+    cancel.  So with per-cell random k1, k2, beta and any mu, K_up^1 = K_up^2
+    exactly, and on the box each entry (row node a, offset o, component c)
+    depends only on a's boundary class (per axis: first, interior or last
+    node).  Checked on the oracle's assembled K against the same box with
+    unit coefficients; within a class the offsets agree exactly and the values
+    to rounding (the oracle builds each cell's geometry from node coordinates,
+    so differences like (i + 1) h - i h round differently across the box)."""
+    rng = np.random.default_rng(11)
+    prob = I.mms_problem(dim, n, k1=1.0, k2=0.1, beta=1.0, mu=1.7)
+    prob.k1 = 10 ** rng.uniform(-2, 2, prob.n_cells)
+    prob.k2 = 10 ** rng.uniform(-3, 1, prob.n_cells)
+    prob.beta = 10 ** rng.uniform(-1, 1, prob.n_cells)
+    S = dpp.assemble(prob)
+    B = dpp.blocks(S)
+    assert abs(B["Kup"][0] - B["Kup"][1]).max() == 0.0
+    ref = dpp.assemble(I.mms_problem(dim, n, k1=1.0, k2=1.0, beta=1.0, mu=1.0))
+    assert abs(dpp.blocks(ref)["Kup"][0] - B["Kup"][0]).max() <= 1e-15 * abs(B["Kup"][0]).max()
+    # per boundary class: every node's row of K_up, arranged by offset, is the same
+    m = [k + 1 for k in n]
+    ijk = np.stack(np.unravel_index(np.arange(S.N), m[::-1])[::-1], axis=1)
+    cls = sum(np.where(ijk[:, a] == 0, 0, np.where(ijk[:, a] == n[a], 2, 1)) * 3 ** a for a in range(dim))
+    K = B["Kup"][0].tocsr()
+    scale = abs(K).max()
+    first = {}
+    for a in range(S.N):
+        for c in range(dim):
+            r = dim * a + c
+            cols = K.indices[K.indptr[r]:K.indptr[r + 1]]
+            row = {tuple(ijk[b] - ijk[a]): v for b, v in zip(cols, K.data[K.indptr[r]:K.indptr[r + 1]])}
+            ref_row = first.setdefault((cls[a], c), row)
+            assert row.keys() == ref_row.keys(), (a, c)
+            assert max(abs(row[o] - ref_row[o]) for o in row) <= 1e-13 * scale, (a, c)
+    assert len({k[0] for k in first}) == np.unique(cls).size
+
+
 def test_velocity_mass_and_boundary_identities():
     prob = I.mms_problem(3, 3, k1=2.0, k2=0.25, beta=1.0, mu=1.5)
     S = dpp.assemble(prob)
