@@ -175,3 +175,32 @@ def test_batch_pure_flux_instances_match_oracle(dim):
                 assert abs(odpp.pressure_mean(S.mesh, xi[F["p1"]])) <= 1e-12 * np.abs(xi[F["p1"]]).max()
             for f in ("u1", "p1", "u2", "p2"):
                 assert np.linalg.norm(xi[F[f]] - xo[F[f]]) <= tol * np.linalg.norm(xo[F[f]]), (precision, i, f)
+
+
+def test_full_size_batch_oracle_residuals():
+    """The benchmark's batch at full size (64 uneven 2D instances, 32^2..256^2
+    cells, 9,131,268 DOF) in the benchmark's launch configuration (hipGraph
+    replay of the Arnoldi steps; FP64 and FP32 preconditioner): every
+    instance's solution against the oracle's own K and f of that instance, and
+    the batched K product against the oracle's K on a random vector."""
+    import paper_1808_08328_amd as dpp
+    print("full-size batch c4_batch64", flush=True)
+    probs = I.batch_configs(64, seed=2024)
+    B = dpp.assemble_batch(probs)
+    assert B.n_dof == 9131268
+    x = torch.as_tensor(I.random_vector(B.n_dof, 21), device="cuda")
+    yb = [H(v) for v in B.split(B.spmv(x))]
+    xs = [H(v) for v in B.split(x)]
+    sols = {}
+    for precision in (0, 2):
+        xsol, st = B.solve(rtol=1e-8, precision=precision, use_graph=1)
+        assert all(s.converged for s in st), precision
+        sols[precision] = [H(v) for v in B.split(xsol)]
+    for i, pr in enumerate(probs):
+        S = odpp.assemble(pr)
+        ref = S.K @ xs[i]
+        assert np.abs(yb[i] - ref).max() <= 1e-13 * np.abs(ref).max(), ("spmv", i)
+        fn = np.linalg.norm(S.f)
+        for precision in (0, 2):
+            r = S.f - S.K @ sols[precision][i]
+            assert np.linalg.norm(r) <= 1.05e-8 * fn, (precision, i, np.linalg.norm(r) / fn)
