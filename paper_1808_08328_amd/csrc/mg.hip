@@ -357,46 +357,103 @@ __global__ void k_dense_fill(GridDev g, const double *__restrict__ A, double *__
   }
 }
 
-// In-place Gauss-Jordan inversion without pivoting (the coarse operators are
-// symmetric positive definite), one launch per pivot k over all n^2 entries
-// of both networks.  Row k and column k of the current matrix are read from
-// a double buffer that the previous step filled (k_gj_init for k = 0).
-__global__ void k_gj_init(const double *__restrict__ M, int n, double *__restrict__ rowb,
-                          double *__restrict__ colb) {
+// In-place Gauss-Jordan inversion of the coarsest operators, without pivoting
+// (they are symmetric positive definite), blocked: the pivots of block
+// I = [k0, k0 + nb) in one step of three launches over both networks.  With
+// P = A[I,I] and the snapshots R = A[I,:], C = A[:,I] of the current matrix,
+// the nb scalar steps amount to
+//   A[I,I] = P^-1,  A[I,J] = P^-1 R[:,J],  A[J,I] = -C[J,:] P^-1,
+//   A[J,J] = A[J,J] - C[J,:] P^-1 R[:,J]       (J = the other indices).
+constexpr int GJB = 32;
+
+// (1) snapshots R, C and the inverse of P (scalar Gauss-Jordan in LDS, block 0).
+__global__ __launch_bounds__(256) void k_bgj_panel(const double *__restrict__ M, int n, int k0,
+                                                   int nb, double *__restrict__ rbuf,
+                                                   double *__restrict__ cbuf,
+                                                   double *__restrict__ pinv) {
   const int q = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
   const double *A = M + (size_t)q * n * n;
-  rowb[(size_t)q * n + i] = A[i];
-  colb[(size_t)q * n + i] = A[(size_t)i * n];
+  if (blockIdx.x == 0) {
+    __shared__ double P[GJB][GJB + 1];
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x)
+      P[e / nb][e % nb] = A[(size_t)(k0 + e / nb) * n + k0 + e % nb];
+    __syncthreads();
+    constexpr int PER = GJB * GJB / 256;
+    for (int k = 0; k < nb; ++k) {
+      double v[PER];
+      const double ip = 1.0 / P[k][k];
+      for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * 256, i = e / nb, j = e % nb;
+        if (e >= nb * nb) continue;
+        v[u] = (i == k && j == k) ? ip
+             : (i == k) ? P[k][j] * ip
+             : (j == k) ? -P[i][k] * ip
+             : P[i][j] - P[i][k] * P[k][j] * ip;
+      }
+      __syncthreads();
+      for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * 256;
+        if (e < nb * nb) P[e / nb][e % nb] = v[u];
+      }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x)
+      pinv[(size_t)q * GJB * GJB + e] = P[e / nb][e % nb];
+    return;
+  }
+  // the other blocks copy the block rows and columns
+  const long tot = 2L * nb * n;
+  for (long e = (long)(blockIdx.x - 1) * blockDim.x + threadIdx.x; e < tot;
+       e += (long)(gridDim.x - 1) * blockDim.x) {
+    if (e < (long)nb * n) {
+      const int m = (int)(e / n), j = (int)(e % n);
+      rbuf[(size_t)q * GJB * n + (size_t)m * n + j] = A[(size_t)(k0 + m) * n + j];
+    } else {
+      const long f = e - (long)nb * n;
+      const int i = (int)(f / nb), m = (int)(f % nb);
+      cbuf[(size_t)q * n * GJB + (size_t)i * GJB + m] = A[(size_t)i * n + k0 + m];
+    }
+  }
 }
 
-__global__ __launch_bounds__(256) void k_gj_step(double *__restrict__ M, int n, int k,
-                                                 double *__restrict__ rowb,
-                                                 double *__restrict__ colb) {
+// (2) T = P^-1 R  (nb x n), into tbuf.
+__global__ __launch_bounds__(256) void k_bgj_rows(int n, int nb, const double *__restrict__ rbuf,
+                                                  const double *__restrict__ pinv,
+                                                  double *__restrict__ tbuf) {
+  const int q = blockIdx.y;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)nb * n) return;
+  const int m = (int)(e / n), j = (int)(e % n);
+  const double *R = rbuf + (size_t)q * GJB * n, *Pi = pinv + (size_t)q * GJB * GJB;
+  double acc = 0.0;
+  for (int l = 0; l < nb; ++l) acc += Pi[m * nb + l] * R[(size_t)l * n + j];
+  tbuf[(size_t)q * GJB * n + (size_t)m * n + j] = acc;
+}
+
+// (3) every entry of the matrix from the snapshots, P^-1 and T.
+__global__ __launch_bounds__(256) void k_bgj_update(double *__restrict__ M, int n, int k0, int nb,
+                                                    const double *__restrict__ cbuf,
+                                                    const double *__restrict__ pinv,
+                                                    const double *__restrict__ tbuf) {
   const int q = blockIdx.y;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)n * n) return;
-  const int i = (int)(e / n), j = (int)(e - (long)i * n);
-  const int p = k & 1;
-  const double *rk = rowb + ((size_t)p * 2 + q) * n, *ck = colb + ((size_t)p * 2 + q) * n;
+  const int i = (int)(e / n), j = (int)(e % n);
   double *A = M + (size_t)q * n * n;
-  const double ip = 1.0 / rk[k];
+  const double *C = cbuf + (size_t)q * n * GJB + (size_t)i * GJB;
+  const double *Pi = pinv + (size_t)q * GJB * GJB, *T = tbuf + (size_t)q * GJB * n;
+  const bool ii = i >= k0 && i < k0 + nb, jj = j >= k0 && j < k0 + nb;
   double v;
-  if (i == k && j == k)
-    v = ip;
-  else if (i == k)
-    v = rk[j] * ip;
-  else if (j == k)
-    v = -ck[i] * ip;
-  else
-    v = A[e] - ck[i] * rk[j] * ip;
-  A[e] = v;
-  if (k + 1 < n) {
-    double *rn = rowb + ((size_t)(p ^ 1) * 2 + q) * n, *cn = colb + ((size_t)(p ^ 1) * 2 + q) * n;
-    if (i == k + 1) rn[j] = v;
-    if (j == k + 1) cn[i] = v;
+  if (ii) {
+    v = jj ? Pi[(i - k0) * nb + (j - k0)] : T[(size_t)(i - k0) * n + j];
+  } else if (jj) {
+    v = 0.0;
+    for (int m = 0; m < nb; ++m) v -= C[m] * Pi[m * nb + (j - k0)];
+  } else {
+    v = A[e];
+    for (int m = 0; m < nb; ++m) v -= C[m] * T[(size_t)m * n + j];
   }
+  A[e] = v;
 }
 
 // x = Cinv b on the coarsest level (FP64 arithmetic); one wavefront per row.
@@ -608,12 +665,19 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
   k_dense_fill<D><<<dim3(blocks_for(n, 64), 2), 64, 0, s>>>(dev(Lc.g), Lc.A.as<double>(),
                                                              pc->cinv.as<double>());
   {
-    DBuf rowb(sizeof(double) * 4 * n), colb(sizeof(double) * 4 * n);
-    k_gj_init<<<dim3(blocks_for(n, 256), 2), 256, 0, s>>>(pc->cinv.as<double>(), n,
-                                                           rowb.as<double>(), colb.as<double>());
-    const dim3 gg(blocks_for((long)n * n, 256), 2);
-    for (int k = 0; k < n; ++k)
-      k_gj_step<<<gg, 256, 0, s>>>(pc->cinv.as<double>(), n, k, rowb.as<double>(), colb.as<double>());
+    // blocked Gauss-Jordan, GJB pivots per step
+    DBuf rb(sizeof(double) * 2 * GJB * n), cb(sizeof(double) * 2 * GJB * n),
+        tb(sizeof(double) * 2 * GJB * n), pb(sizeof(double) * 2 * GJB * GJB);
+    const dim3 gp(1 + std::min(1024, blocks_for(2L * GJB * n, 256)), 2);
+    const dim3 gr(blocks_for((long)GJB * n, 256), 2), gu(blocks_for((long)n * n, 256), 2);
+    for (int k0 = 0; k0 < n; k0 += GJB) {
+      const int nb = std::min(GJB, n - k0);
+      k_bgj_panel<<<gp, 256, 0, s>>>(pc->cinv.as<double>(), n, k0, nb, rb.as<double>(),
+                                     cb.as<double>(), pb.as<double>());
+      k_bgj_rows<<<gr, 256, 0, s>>>(n, nb, rb.as<double>(), pb.as<double>(), tb.as<double>());
+      k_bgj_update<<<gu, 256, 0, s>>>(pc->cinv.as<double>(), n, k0, nb, cb.as<double>(),
+                                      pb.as<double>(), tb.as<double>());
+    }
     check_launch("coarse inverse");
     DPP_HIP(hipStreamSynchronize(s));
   }
