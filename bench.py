@@ -99,6 +99,15 @@ def cpu_baseline(prob, gpu_iters, max_iters):
         t2 = time.perf_counter()
         x, its, res = osolver.fgmres(S.K, S.f, F.apply, restart=30, rtol=1e-8, maxiter=max_iters)
         t3 = time.perf_counter()
+    # context: the oracle's OpenMP CSR product of the same K on all host threads
+    # (CSR bytes: values, int32 columns, int64 row pointers, x and y once)
+    xv = np.ones(S.K.shape[0])
+    odpp.spmv(S.K, xv)
+    ts = time.perf_counter()
+    for _ in range(3):
+        odpp.spmv(S.K, xv)
+    t_spmv = (time.perf_counter() - ts) / 3
+    csr_bytes = S.K.nnz * 12.0 + (S.K.shape[0] + 1) * 8.0 + 2.0 * S.K.shape[0] * 8.0
     n_dof = S.K.shape[0]
     t_solve = t3 - t2
     full = res <= 1e-8
@@ -113,7 +122,27 @@ def cpu_baseline(prob, gpu_iters, max_iters):
                   ("first %d oracle FGMRES iterations on the same %d-DOF system (%.2f s), "
                    "scaled to the %d iterations the solve needs" % (its, n_dof, t_solve, gpu_iters)),
         "solve_s": t_est,
+        "spmv_GBps": csr_bytes / t_spmv / 1e9, "spmv_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
     }
+
+
+def measured_copy_gbs(torch):
+    """HBM bandwidth of a plain device copy (1 GiB read + 1 GiB written), the
+    practical ceiling next to the 8 TB/s peak."""
+    src = torch.ones(128 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * src.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e6)
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def field_errors(P, pc, x, opts):
@@ -256,6 +285,7 @@ def main():
     value = P.n_dof / (ms / 1e3)
 
     kernels, roof = {}, None
+    copy_gbs = measured_copy_gbs(torch)
     if not args.no_profile:
         dpp.profile_enable(True)
         for _ in range(args.steps):
@@ -279,7 +309,8 @@ def main():
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": tr, "kernel": dom,
                 "kernel_name": kernel_name(dom, prob.dim, pc,
                                            flux=getattr(prob, "face_bc", None) is not None),
-                "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": 1e3 * t / n}
+                "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": 1e3 * t / n,
+                "copy_ceiling": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 
     line = {
         "metric": METRIC, "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
