@@ -1,0 +1,52 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU contract, the lookup of
+the committed HBM counter figures by kernel-source hash, and the profiler
+names of the single-kernel families."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+
+
+def test_counter_traffic_follows_the_kernel_sources(monkeypatch, tmp_path):
+    import json
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic_counters.json").write_text(json.dumps(
+        {"source_sha": "abc", "families": {"cheb_S_l0": {"bytes_per_launch": 1.5e8}}}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_sha", lambda: "abc")
+    assert bench.measured_traffic("cheb_S_l0", 1.0) == 1.5e8
+    assert bench.measured_traffic("no_such_family", 1.0) is None
+    # figures taken on other kernel sources are not reported
+    monkeypatch.setattr(bench, "kernel_source_sha", lambda: "def")
+    assert bench.measured_traffic("cheb_S_l0", 1.0) is None
+
+
+def test_kernel_source_hash_covers_the_stencil_and_krylov_sources():
+    assert len(bench.kernel_source_sha()) == 16
+
+
+class _Shape:
+    def shape(self, level):
+        return (0, True)
+
+
+def test_kernel_names_of_single_kernel_families():
+    pc = _Shape()
+    assert bench.kernel_name("cheb_S_l0", 3, pc) == "k_cheb<3, double, double, 0, true, true>"
+    assert bench.kernel_name("resid_S_l0", 3, pc) == "k_lspmv<3, double, double, 0, true, true>"
+    assert bench.kernel_name("spmv_K", 3, pc) == "k_spmv_K<3, double, false>"
+    assert bench.kernel_name("spmv_K", 2, pc, flux=True) == "k_spmv_K<2, double, true>"
+    assert bench.kernel_name("schur_rhs", 3, pc) == "k_schur_rhs<3, double, double, false>"
+    assert bench.kernel_name("schur_vel", 3, pc, flux=True) == "k_schur_vel<3, double, double, true>"
+    assert set(bench.SINGLE_KERNEL_FAMILIES) == {"spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "schur_vel"}
