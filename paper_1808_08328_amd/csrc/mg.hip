@@ -582,14 +582,13 @@ void pack_half(Level &L, hipStream_t s) {
   check_launch("pack_half");
 }
 
+// Per-network sums of squares of x into red[2 RED_BLOCKS .. +2) (device only).
 template <int D>
-void sumsq2(dpp_precond pc, const double *x, long n, double *out_host, hipStream_t s) {
+void sumsq2(dpp_precond pc, const double *x, long n, hipStream_t s) {
   double *part = pc->red.as<double>();
   k_sumsq2<<<dim3(RED_BLOCKS, 2), 256, 0, s>>>(x, n, part);
   k_sum2<<<1, 256, 0, s>>>(part, RED_BLOCKS, part + 2 * RED_BLOCKS);
   check_launch("sumsq2");
-  DPP_HIP(hipMemcpyAsync(out_host, part + 2 * RED_BLOCKS, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  DPP_HIP(hipStreamSynchronize(s));
 }
 
 template <int D>
@@ -618,24 +617,25 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
     const long cmax = o.coarse_max > 0 ? o.coarse_max : (D == 3 ? 1000 : 400);
     const bool last = gl.N <= cmax || gc.N == gl.N || (int)pc->lv.size() >= 16;
     if (last) break;
-    // Chebyshev bounds from normalised power steps on D^-1 A
-    double ss[2];
+    // Chebyshev bounds from normalised power steps on D^-1 A; the norms stay
+    // on the device, only the last one comes back to the host
     double *x = L.xa.as<double>(), *y = L.xb.as<double>();
+    const double *ssd = pc->red.as<double>() + 2 * RED_BLOCKS;
     k_hash_start<<<grid, 256, 0, s>>>(x, gl.N);
-    sumsq2<D>(pc, x, gl.N, ss, s);
-    DPP_HIP(hipMemcpyAsync(pc->red.as<double>() + 2 * RED_BLOCKS + 2, ss, 2 * sizeof(double),
-                           hipMemcpyHostToDevice, s));
-    k_scale2<<<grid, 256, 0, s>>>(x, gl.N, pc->red.as<double>() + 2 * RED_BLOCKS + 2);
-    double lam[2] = {0, 0};
+    sumsq2<D>(pc, x, gl.N, s);
+    k_scale2<<<grid, 256, 0, s>>>(x, gl.N, ssd);
     for (int it = 0; it < o.power_iters; ++it) {
       launch_lspmv<D, double, double>(Shape{}, gl, s, L.A.as<double>(), x, y, nullptr, L.dinv.as<double>());
-      sumsq2<D>(pc, y, gl.N, ss, s);
+      sumsq2<D>(pc, y, gl.N, s);
+      k_scale2<<<grid, 256, 0, s>>>(y, gl.N, ssd);
+      std::swap(x, y);
+    }
+    double ss[2] = {0.0, 0.0}, lam[2] = {0.0, 0.0};
+    if (o.power_iters > 0) {
+      DPP_HIP(hipMemcpyAsync(ss, ssd, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      DPP_HIP(hipStreamSynchronize(s));
       lam[0] = std::sqrt(ss[0]);
       lam[1] = std::sqrt(ss[1]);
-      DPP_HIP(hipMemcpyAsync(pc->red.as<double>() + 2 * RED_BLOCKS + 2, ss, 2 * sizeof(double),
-                             hipMemcpyHostToDevice, s));
-      k_scale2<<<grid, 256, 0, s>>>(y, gl.N, pc->red.as<double>() + 2 * RED_BLOCKS + 2);
-      std::swap(x, y);
     }
     for (int q = 0; q < 2; ++q) {
       DPP_CHECK(std::isfinite(lam[q]) && lam[q] > 0.0, DPP_ERR_NUMERIC,
