@@ -410,6 +410,7 @@ dpp_status dpp_assemble_batch(int nb, const dpp_box *boxes, const dpp_params *pa
         B->pc.push_back(pc);
         pc->prob = P;
         pc->opts = B->opts;
+        pc->tune_shapes = false;
         dpp::precond_setup(pc, S(stream));
       }
       dpp::batch_setup(B, S(stream));

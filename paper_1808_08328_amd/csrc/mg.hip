@@ -655,7 +655,9 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
   }
   for (size_t l = 0; l + 1 < pc->lv.size(); ++l) {
     pack_half<D>(*pc->lv[l], s);
-    pc->lv[l]->shape = tune_shape<D>(*pc->lv[l], s);
+    // members of a batch run the batched kernels, whose lanes are tuned over
+    // the whole batch: their own shapes are never used
+    pc->lv[l]->shape = pc->tune_shapes ? tune_shape<D>(*pc->lv[l], s) : Shape{};
   }
   Level &Lc = *pc->lv.back();
   const int n = (int)Lc.g.N;

@@ -106,6 +106,7 @@ struct dpp_precond_s {
   dpp::DBuf rhat32;
   dpp::DBuf red;    // reduction scratch
   bool has32 = false;
+  bool tune_shapes = true;  // autotune the level kernel shapes (off for batch members)
   // Krylov workspace, kept across solves
   int ws_m = 0;
   dpp::DBuf V, Z, w, part, hdev, ydev, xtmp, rtmp;
