@@ -54,7 +54,8 @@ typedef struct dpp_problem_s *dpp_problem;
 typedef struct dpp_precond_s *dpp_precond;
 typedef struct dpp_batch_s *dpp_batch;
 
-/* Structured box: dim 2 or 3, n[a] >= 1 cells per axis, L[a] > 0 extent. */
+/* Structured box: dim 2 or 3, 1 <= n[a] <= 4096 cells per axis, L[a] > 0
+ * extent; (2 dim + 2) x nodes must stay below 2^31 (DPP_ERR_ARG otherwise). */
 typedef struct {
   int dim;
   int n[3];

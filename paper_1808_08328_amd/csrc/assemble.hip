@@ -418,6 +418,9 @@ void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, 
   DPP_CHECK(prm->mu > 0.0, DPP_ERR_ARG, "mu must be positive");
   Grid g = make_grid(box->dim, box->n, box->L);
   const int D = g.dim;
+  // the stencil kernels index nodes and unknowns with 32-bit integers
+  DPP_CHECK((2L * D + 2L) * g.N <= 2147483647L, DPP_ERR_ARG,
+            "box too large: (2 dim + 2) x nodes must stay below 2^31");
   const int NS = (D == 3) ? Tabs<3>::NS : Tabs<2>::NS;
   DPP_CHECK((double)g.N * (2 * D + 2) < 2.0e9, DPP_ERR_ARG, "problem too large for 32-bit indices");
   check_input(prm->k1, g.nc, true, "k1", s);

@@ -119,15 +119,17 @@ __device__ inline void row_product2(const GridDev &g, const TV *__restrict__ Aq,
   constexpr int NT = Tabs<D>::NT;
   constexpr int T0 = TAB<D>.t0;
   constexpr int NH = NT - T0;
-  const long N = g.N, ld = g.ld;
+  // 32-bit node indices (N < 2^31) keep the per-offset index arithmetic short
+  const int N = (int)g.N, ai = (int)a;
+  const long ld = g.ld;
   double acc0 = 0.0, acc1 = 0.0;
   if constexpr (!SYM) {
 #pragma unroll 8
     for (int t = 0; t < NT; ++t) {
       const int *o = TAB<D>.to[t];
-      const long b = a + lin(g, o[0], o[1], o[2]);
-      const long c = min(max(b, 0L), N - 2);
-      const long d = b - c;
+      const int b = ai + (int)lin(g, o[0], o[1], o[2]);
+      const int c = min(max(b, 0), N - 2);
+      const int d = b - c;
       TV a0, a1;
       TX x0, x1;
       ld2(Aq + (size_t)t * ld + a, a0, a1);
@@ -139,10 +141,10 @@ __device__ inline void row_product2(const GridDev &g, const TV *__restrict__ Aq,
 #pragma unroll 8
     for (int h = 0; h < NH; ++h) {
       const int *o = TAB<D>.to[T0 + h];
-      const long lo = lin(g, o[0], o[1], o[2]);
-      const long b = a + lo;
-      const long c = min(b, N - 2);
-      const long d = b - c;
+      const int lo = (int)lin(g, o[0], o[1], o[2]);
+      const int b = ai + lo;
+      const int c = min(b, N - 2);
+      const int d = b - c;
       TV a0, a1;
       TX x0, x1;
       ld2(Aq + (size_t)h * ld + a, a0, a1);
@@ -152,9 +154,9 @@ __device__ inline void row_product2(const GridDev &g, const TV *__restrict__ Aq,
       acc1 += (double)a1 * (double)x1;
       if (h > 0) {
         // rows a - o and a + 1 - o hold the negative-half entries
-        const long bm = a - lo;
-        const long cm = min(max(bm, 0L), N - 2);
-        const long dm = bm - cm;
+        const int bm = ai - lo;
+        const int cm = min(max(bm, 0), N - 2);
+        const int dm = bm - cm;
         TV m0, m1;
         TX y0, y1;
         ld2(Aq + (size_t)h * ld + cm, m0, m1);
