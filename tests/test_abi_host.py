@@ -51,3 +51,21 @@ def test_null_arguments_are_rejected_without_a_gpu():
     assert b"null" in L.dpp_last_error()
     st = L.dpp_solve(None, None, None, None, None, None, None)
     assert st == 1
+
+
+def test_oversized_boxes_are_rejected_without_a_gpu():
+    """Boxes with 2^31 or more unknowns (the stencil kernels index with 32-bit
+    integers) and boxes beyond 4096 cells per axis are argument errors,
+    reported before any device work."""
+    import paper_1808_08328_amd as dpp
+    from paper_1808_08328_amd._binding import _Box, _Params
+    L = dpp.lib()
+    dummy = (C.c_double * 4)()
+    prm = _Params(mu=1.0, k1=C.cast(dummy, C.c_void_p), k2=C.cast(dummy, C.c_void_p), beta=1.0,
+                  p0_1=C.cast(dummy, C.c_void_p), p0_2=C.cast(dummy, C.c_void_p))
+    h = C.c_void_p()
+    for n, msg in (((1024, 1024, 1024), b"2^31"), ((4097, 2, 2), b"4096")):
+        box = _Box(dim=3, n=(C.c_int * 3)(*n), L=(C.c_double * 3)(1.0, 1.0, 1.0))
+        st = L.dpp_assemble(C.byref(box), C.byref(prm), None, C.byref(h))
+        assert st == 1, n
+        assert msg in L.dpp_last_error(), (n, L.dpp_last_error())
