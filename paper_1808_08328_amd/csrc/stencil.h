@@ -44,7 +44,9 @@ __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq
   constexpr int NT = Tabs<D>::NT;
   constexpr int T0 = TAB<D>.t0;
   constexpr int NH = NT - T0;  // zero offset + positive half
-  const long N = g.N, ld = g.ld;
+  // 32-bit node indices (N < 2^31)
+  const int N = (int)g.N, ai = (int)a;
+  const long ld = g.ld;
   (void)i; (void)j; (void)k;
   double acc = 0.0;
   // Offsets are processed in unrolled groups of 8: each group's loads are
@@ -55,7 +57,7 @@ __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq
       const int t = tt * LPR + (LPR == 1 ? 0 : sub);
       if (LPR > 1 && t >= NT) continue;
       const int *o = TAB<D>.to[t];
-      const long b = min(max(a + lin(g, o[0], o[1], o[2]), 0L), N - 1);
+      const int b = min(max(ai + (int)lin(g, o[0], o[1], o[2]), 0), N - 1);
       acc += (double)Aq[(size_t)t * ld + a] * (double)xq[b];
     }
   } else {
@@ -64,12 +66,12 @@ __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq
       const int h = hh * LPR + (LPR == 1 ? 0 : sub);
       if (LPR > 1 && h >= NH) continue;
       const int *o = TAB<D>.to[T0 + h];
-      const long lo = lin(g, o[0], o[1], o[2]);
-      const long bp = min(a + lo, N - 1);
+      const int lo = (int)lin(g, o[0], o[1], o[2]);
+      const int bp = min(ai + lo, N - 1);
       acc += (double)Aq[(size_t)h * ld + a] * (double)xq[bp];
       if (h > 0) {
-        const long bm = a - lo;
-        const long bc = max(bm, 0L);
+        const int bm = ai - lo;
+        const int bc = max(bm, 0);
         const double v = (double)Aq[(size_t)h * ld + bc] * (double)xq[bc];
         acc += (bm >= 0) ? v : 0.0;
       }
