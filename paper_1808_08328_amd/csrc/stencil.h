@@ -412,7 +412,7 @@ __device__ inline double restrict_node(const GridDev &gf, const GridDev &gc,
   node_ijk(gc, C, cc[0], cc[1], cc[2]);
   int ex[3];
   for (int ax = 0; ax < 3; ++ax) ex[ax] = exact_fine(cc[ax], gf.n[ax], gc.m[ax]);
-  auto fid = [&](const int *f) { return f[0] + (long)gf.m[0] * (f[1] + (long)gf.m[1] * f[2]); };
+  auto fid = [&](const int *f) { return f[0] + gf.m[0] * (f[1] + gf.m[1] * f[2]); };  // < 2^31
   double acc = (double)rq[fid(ex)];
   for (int mask = 1; mask < (1 << D); ++mask) {
     int fu[3] = {ex[0], ex[1], ex[2]}, fd[3] = {ex[0], ex[1], ex[2]};
@@ -442,10 +442,11 @@ __device__ inline double prolong_node(const GridDev &gf, const GridDev &gc,
     fine_to_coarse(fi[ax], gf.n[ax], gc.m[ax], lo[ax], od[ax]);
     any = any || od[ax];
   }
-  const long c0 = lo[0] + (long)gc.m[0] * (lo[1] + (long)gc.m[1] * lo[2]);
+  // 32-bit node indices (the assembly keeps every level below 2^31 nodes)
+  const int c0 = lo[0] + gc.m[0] * (lo[1] + gc.m[1] * lo[2]);
   double v = (double)eq[c0];
   if (any) {
-    const long c1 = (lo[0] + od[0]) + (long)gc.m[0] * ((lo[1] + od[1]) + (long)gc.m[1] * (lo[2] + od[2]));
+    const int c1 = (lo[0] + od[0]) + gc.m[0] * ((lo[1] + od[1]) + gc.m[1] * (lo[2] + od[2]));
     v = 0.5 * (v + (double)eq[c1]);
   }
   return v;
