@@ -308,16 +308,17 @@ __device__ inline double schur_rhs_node(const GridDev &g, const TV *ut,
                                         const double *__restrict__ r, int q, long b) {
   using U = UPT<D>;
   constexpr int NS = U::NS;
-  const long N = g.N;
-  const long ou = off_u(D, N, q);
-  double acc = r[off_p(D, N, q) + b];
+  // 32-bit node and unknown indices (the assembly keeps them below 2^31)
+  const int N = (int)g.N, bi = (int)b;
+  const int ou = (int)off_u(D, N, q);
+  double acc = r[off_p(D, N, q) + bi];
   int ib[3];
   node_ijk(g, b, ib[0], ib[1], ib[2]);
   // offsets in unrolled groups of 5 (loads of a group in flight together)
 #pragma unroll 5
   for (int t = 0; t < NS; ++t) {
     const int *o = TAB<D>.so[t];
-    const long a = min(max(b + lin(g, o[0], o[1], o[2]), 0L), N - 1);
+    const int a = min(max(bi + (int)lin(g, o[0], o[1], o[2]), 0), N - 1);
     const int pa[3] = {ib[0] + o[0], ib[1] + o[1], ib[2] + o[2]};
     const bool in = inside(g, pa[0], pa[1], pa[2]);
     const int ca = in ? node_class<D>(g, pa[0], pa[1], pa[2]) : 0;
@@ -370,21 +371,22 @@ __device__ inline void schur_vel_node2(const GridDev &g, const TV *ut,
                                        const double *__restrict__ r, const TX *__restrict__ zp,
                                        int q, long a, double out[2 * D]) {
   using U = UPT<D>;
-  const long N = g.N;
-  const long ou = off_u(D, N, q);
+  // 32-bit node and unknown indices (the assembly keeps them below 2^31)
+  const int N = (int)g.N, ai = (int)a;
+  const int ou = (int)off_u(D, N, q);
   int i, j, k;
   node_ijk(g, a, i, j, k);
   const int c0 = node_class<D>(g, i, j, k);
   node_ijk(g, a + 1, i, j, k);
   const int c1 = node_class<D>(g, i, j, k);
 #pragma unroll
-  for (int k2 = 0; k2 < D; ++k2) ld2(r + ou + D * a + 2 * k2, out[2 * k2], out[2 * k2 + 1]);
+  for (int k2 = 0; k2 < D; ++k2) ld2(r + ou + D * ai + 2 * k2, out[2 * k2], out[2 * k2 + 1]);
 #pragma unroll 5
   for (int t = 0; t < U::NS; ++t) {
     const int *o = TAB<D>.so[t];
-    const long b = a + lin(g, o[0], o[1], o[2]);
-    const long c = min(max(b, 0L), N - 2);
-    const long d = b - c;
+    const int b = ai + (int)lin(g, o[0], o[1], o[2]);
+    const int c = min(max(b, 0), N - 2);
+    const int d = b - c;
     TX z0, z1;
     ld2(zp + q * N + c, z0, z1);
     // the table is zero for pairs that leave the box, so a clamped z is harmless
@@ -396,7 +398,7 @@ __device__ inline void schur_vel_node2(const GridDev &g, const TV *ut,
     }
   }
   double di0, di1;
-  ld2(dinv + q * N + a, di0, di1);
+  ld2(dinv + q * N + ai, di0, di1);
 #pragma unroll
   for (int k2 = 0; k2 < D; ++k2) {
     out[k2] *= di0;
