@@ -25,9 +25,11 @@ one on the structured box, defined here in plain steps:
 
 This module is pinned by invariants (interpolation reproduces linear
 functions, Galerkin coarse operators equal re-discretised ones on nested
-meshes, the V-cycle is symmetric, a one-level cycle is the exact inverse);
-its numerical values are otherwise "parity unpinned" by the paper, which
-prints none.
+meshes, the power steps equal M^k x_0 through the eigendecomposition of
+M = D^-1 A, k Chebyshev steps multiply the error by the scaled Chebyshev
+polynomial p_k(M), the V-cycle is symmetric, a one-level cycle is the exact
+inverse); the values of the cycle as a whole are otherwise "parity unpinned"
+by the paper, which prints none for its multigrid.
 """
 from __future__ import annotations
 

@@ -374,6 +374,100 @@ def test_chebyshev_degree_one_is_damped_jacobi_and_converges():
     assert np.linalg.norm(A @ x - b) < 1e-10 * np.linalg.norm(b)
 
 
+def test_power_lambda_matches_dense_eigenvalue():
+    """The smoother's upper bound.  After k normalised power steps from the
+    hash start x_0 the estimate is ||M^k x_0|| / ||M^(k-1) x_0|| with
+    M = D^-1 A; M^k is evaluated here through the eigendecomposition of M
+    (real spectrum: M is similar to the SPD D^-1/2 A D^-1/2), so a dropped
+    D^-1, a missing normalisation or an off-by-one step count fails it.  The
+    estimate tends to the largest eigenvalue and the 15-step value the setup
+    uses is within 10% of it."""
+    for dim, n in ((2, 7), (3, 3)):
+        S = dpp.assemble(I.grf_problem(dim, n))
+        for A in dpp.selfp(S):
+            dinv = 1.0 / A.diagonal()
+            lam, Vec = np.linalg.eig(np.diag(dinv) @ A.toarray())
+            assert np.abs(lam.imag).max() < 1e-10 * np.abs(lam.real).max()
+            lam, Vec = lam.real, Vec.real
+            lmax = lam.max()
+            c0 = np.linalg.solve(Vec, mg.hash_start(A.shape[0]))
+            for k in (1, 2, 15, 60):
+                est = mg.power_lambda(A, dinv, k)
+                ref = np.linalg.norm(Vec @ (lam ** k * c0)) / np.linalg.norm(Vec @ (lam ** (k - 1) * c0))
+                assert abs(est - ref) < 1e-10 * ref, (dim, k, est, ref)
+            assert abs(mg.power_lambda(A, dinv, 2000) - lmax) < 1e-3 * lmax
+            assert 0.9 * lmax < mg.power_lambda(A, dinv, 15) < 1.1 * lmax
+            # the undivided operator has a different spectrum (the D^-1 matters)
+            assert abs(np.abs(np.linalg.eigvals(A.toarray())).max() - lmax) > 0.1 * lmax
+
+
+@pytest.mark.parametrize("degree", [2, 3, 4])
+def test_chebyshev_error_is_the_scaled_chebyshev_polynomial(degree):
+    """k Chebyshev steps on [lo, hi] with diagonal preconditioning multiply the
+    error by p_k(D^-1 A), p_k(t) = T_k((theta - t)/delta) / T_k(theta/delta)
+    (theta, delta: centre and half-width of the interval).  The polynomial is
+    evaluated on the eigenvalues of D^-1 A from numpy's Chebyshev basis, not
+    from the three-term recurrence the smoother runs, so a wrong rho update or
+    step coefficient fails it, on an interval that is not the spectrum's."""
+    S = dpp.assemble(I.grf_problem(2, 5))
+    A = dpp.selfp(S)[0]
+    dinv = 1.0 / A.diagonal()
+    Ad = A.toarray()
+    lam, Vec = np.linalg.eig(np.diag(dinv) @ Ad)
+    lam, Vec = lam.real, Vec.real
+    lmax = lam.max()
+    b = I.random_vector(A.shape[0], 11)
+    xs = np.linalg.solve(Ad, b)
+    x0 = I.random_vector(A.shape[0], 12)
+    for lo, hi in ((0.3 * lmax, 1.1 * lmax), (0.05 * lmax, 0.9 * lmax)):
+        theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+        Tk = np.polynomial.chebyshev.Chebyshev.basis(degree)
+        pk = Tk((theta - lam) / delta) / Tk(theta / delta)
+        e_pred = Vec @ (pk * np.linalg.solve(Vec, x0 - xs))
+        x = mg.chebyshev(A, dinv, b, x0, degree, lo, hi)
+        assert np.linalg.norm((x - xs) - e_pred) < 1e-10 * np.linalg.norm(x0 - xs), (lo, hi)
+
+
+def test_interp_errors_pinned():
+    """The interpolant-based error measure ||u_h - I_h u||_L2: zero on the nodal
+    interpolant of any field; for linear exact fields (I_h u = u) it equals the
+    quadrature-based true L2 error of random nodal data (a wrong mass matrix,
+    volume or velocity reshape fails it); a constant pressure offset c gives
+    |c| |Omega|^(1/2)."""
+    for dim, n, L in ((2, (5, 4), (1.0, 0.7)), (3, (3, 2, 4), (1.0, 0.6, 0.8))):
+        S = dpp.assemble(I.mms_problem(dim, n, L=L))
+        msh = S.mesh
+        N = msh.N
+        F = dpp.fields(dim, N)
+
+        def mms(X):
+            return I.mms_fields(dim, X, 1.0, 0.1, 1.0, 1.0)
+
+        x = np.zeros(S.K.shape[0])
+        p1, p2, u1, u2 = mms(msh.X)
+        x[F["p1"]], x[F["p2"]] = p1, p2
+        x[F["u1"]], x[F["u2"]] = u1.reshape(-1), u2.reshape(-1)
+        e = post.interp_errors(S, x, mms)
+        assert max(e.values()) < 1e-13, e
+        c = 0.37
+        xc = x.copy()
+        xc[F["p1"]] += c
+        e = post.interp_errors(S, xc, mms)
+        assert abs(e["p1"] - c * np.sqrt(np.prod(L))) < 1e-13 and e["p2"] < 1e-13
+
+        a = np.array([0.4, -1.3, 0.8][:dim])
+
+        def linear(X):
+            s = X @ a
+            return (s + 1.0, 2.0 * s - 0.5, np.outer(s, [1.0, -2.0, 0.5][:dim]) + 0.3,
+                    np.outer(s, [-0.7, 0.2, 1.1][:dim]))
+
+        xr = I.random_vector(S.K.shape[0], 21)
+        ei, el = post.interp_errors(S, xr, linear), post.l2_errors(S, xr, linear, q=4)
+        for f in ("u1", "p1", "u2", "p2"):
+            assert abs(ei[f] - el[f]) < 1e-12 * el[f], (f, ei[f], el[f])
+
+
 def test_vcycle_symmetric_and_contracting():
     S = dpp.assemble(I.mms_problem(3, 8, k2=1e-2))
     A = dpp.selfp(S)[1]
