@@ -5,8 +5,14 @@ One step = one solve of the assembled CG-VMS four-field system from a zero
 initial guess to ||f - K x|| <= 1e-8 ||f|| (flexible GMRES with the Schur
 fieldsplit / multigrid preconditioner).  Assembly and preconditioner setup are
 timed separately, as the paper reports assembly and solver times separately.
-Inputs are synthetic (manufactured-solution boundary data of the paper's 3D
-study), already resident in HBM when the timed region starts.
+Inputs are synthetic (seeded log-normal permeability fields and the
+manufactured-solution boundary data of the paper's 3D study), already resident
+in HBM when the timed region starts.
+
+Default workload: the 96^3 log-normal box (7,301,384 DOF), FP64; the same line
+carries the mixed-precision (FP32 inner solve, FP64 refinement) timing, every
+field's error against the CPU oracle's solution of the same system, the
+roofline of the dominant kernel and the oracle's own solve rate on the host.
 
 Prints one JSON line (metric, value, ..., roofline, cpu_baseline).
 """
@@ -83,47 +89,95 @@ def measured_traffic(family, launches_bytes):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def cpu_baseline(prob, gpu_iters, max_iters):
-    """The CPU oracle (FP64 numpy/scipy, its own assembly and preconditioner of
-    the same definition) solving the same system; BLAS pinned to one thread."""
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def oracle_leg(prob, gpu_iters, sample_iters, solutions, ref_rtol=1e-11):
+    """The CPU oracle (FP64 numpy/scipy + its OpenMP C loops; its own
+    assembly, fieldsplit and flexible GMRES of the same definition) on the
+    same system.
+
+    cpu_baseline: the oracle's FGMRES from x = 0 toward 1e-8 with its OpenMP
+    CSR product as the operator, timed over at most `sample_iters` iterations
+    (a bounded sample), scaled to the iterations it needs when it stops early.
+    Reference: the same FGMRES continued (restarted from its iterate) to
+    ref_rtol; each GPU solution in `solutions` gets its per-field error against
+    it and the oracle's own residual ||f - K_oracle x|| / ||f||."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
 
     from oracle import dpp as odpp
     from oracle import solver as osolver
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        S = odpp.assemble(prob)
-        t1 = time.perf_counter()
-        F = osolver.FieldSplit(S)
-        t2 = time.perf_counter()
-        x, its, res = osolver.fgmres(S.K, S.f, F.apply, restart=30, rtol=1e-8, maxiter=max_iters)
-        t3 = time.perf_counter()
-    # context: the oracle's OpenMP CSR product of the same K on all host threads
-    # (CSR bytes: values, int32 columns, int64 row pointers, x and y once)
-    xv = np.ones(S.K.shape[0])
-    odpp.spmv(S.K, xv)
-    ts = time.perf_counter()
-    for _ in range(3):
-        odpp.spmv(S.K, xv)
-    t_spmv = (time.perf_counter() - ts) / 3
-    csr_bytes = S.K.nnz * 12.0 + (S.K.shape[0] + 1) * 8.0 + 2.0 * S.K.shape[0] * 8.0
-    n_dof = S.K.shape[0]
-    t_solve = t3 - t2
+    t0 = time.perf_counter()
+    S = odpp.assemble(prob)
+    t1 = time.perf_counter()
+    F = osolver.FieldSplit(S)
+    t2 = time.perf_counter()
+    log("oracle assembly %.1f s, fieldsplit setup %.1f s" % (t1 - t0, t2 - t1))
+    mv = lambda v: odpp.spmv(S.K, v)
+    x, its, res = osolver.fgmres(S.K, S.f, F.apply, restart=30, rtol=1e-8, maxiter=sample_iters,
+                                 matvec=mv)
+    t3 = time.perf_counter()
+    t_sample = t3 - t2
     full = res <= 1e-8
-    # when the sample stops before convergence, scale its per-iteration time
-    # to the iteration count the same preconditioner needs on the GPU
-    t_est = t_solve if full else t_solve / max(its, 1) * gpu_iters
-    return {
-        "value": n_dof / t_est, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-        "sample": ("oracle FGMRES solve of the same %d-DOF system to 1e-8 (%d iterations, "
-                   "%.2f s; assembly %.2f s and preconditioner setup %.2f s not counted)"
-                   % (n_dof, its, t_solve, t1 - t0, t2 - t1)) if full else
-                  ("first %d oracle FGMRES iterations on the same %d-DOF system (%.2f s), "
-                   "scaled to the %d iterations the solve needs" % (its, n_dof, t_solve, gpu_iters)),
-        "solve_s": t_est,
-        "spmv_GBps": csr_bytes / t_spmv / 1e9, "spmv_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
+    n_dof = S.K.shape[0]
+    log("oracle sample: %d iterations in %.1f s (rel. residual %.2e)" % (its, t_sample, res))
+    xr, its2, res2 = osolver.fgmres(S.K, S.f, F.apply, restart=30, rtol=ref_rtol, maxiter=600,
+                                    x0=x, matvec=mv)
+    log("oracle reference: %d more iterations, rel. residual %.2e" % (its2, res2))
+    # a sample stopped at its bound is scaled to the iteration count of the
+    # GPU solve (the same preconditioner definition; the oracle orthogonalises
+    # by modified Gram-Schmidt, so the counts can differ by rounding)
+    its_full = its if full else gpu_iters
+    t_est = t_sample if full else t_sample / max(its, 1) * its_full
+    fs = odpp.fields(prob.dim, S.N)
+    fn = np.linalg.norm(S.f)
+    errs = {"reference": "CPU oracle FGMRES (FP64) to rel. residual %.0e (reached %.2e)"
+                         % (ref_rtol, res2)}
+    for name, xg in solutions.items():
+        errs[name] = {f: float(np.linalg.norm(xg[fs[f]] - xr[fs[f]]) / np.linalg.norm(xr[fs[f]]))
+                      for f in ("u1", "p1", "u2", "p2")}
+        errs[name]["oracle_residual"] = float(np.linalg.norm(S.f - mv(xg)) / fn)
+    threads = odpp.threads()
+    base = {
+        "value": n_dof / t_est, "unit": "DOF/s", "cores": threads, "kind": "oracle",
+        "sample": ("oracle FGMRES solve of the same %d-DOF system to 1e-8 from x = 0: %d iterations "
+                   "in %.2f s (assembly %.1f s and fieldsplit setup %.1f s not counted); CSR "
+                   "products on %d OpenMP threads, V-cycles and vector updates in numpy/scipy"
+                   % (n_dof, its, t_sample, t1 - t0, t2 - t1, threads)) if full else
+                  ("first %d oracle FGMRES iterations on the same %d-DOF system (%.2f s), scaled to "
+                   "the %d iterations of the GPU solve to 1e-8; CSR products on %d OpenMP threads, "
+                   "V-cycles and vector updates in numpy/scipy"
+                   % (its, n_dof, t_sample, its_full, threads)),
+        "solve_s": t_est, "iters": its_full, "gpu_iters": gpu_iters,
     }
+    return base, errs
+
+
+def oracle_batch_leg(probs, budget_s):
+    """cpu_baseline of the batch: the oracle solves instances one after
+    another (FGMRES to 1e-8 with its OpenMP CSR product) until `budget_s` of
+    solve time is spent; DOF/s over the instances it finished."""
+    from oracle import dpp as odpp
+    from oracle import solver as osolver
+    dof, t, done = 0, 0.0, 0
+    for pr in probs:
+        S = odpp.assemble(pr)
+        F = osolver.FieldSplit(S)
+        t0 = time.perf_counter()
+        x, its, res = osolver.fgmres(S.K, S.f, F.apply, restart=30, rtol=1e-8, maxiter=400,
+                                     matvec=lambda v: odpp.spmv(S.K, v))
+        t += time.perf_counter() - t0
+        dof += S.K.shape[0]
+        done += 1
+        if t >= budget_s:
+            break
+    threads = odpp.threads()
+    return {"value": dof / t, "unit": "DOF/s", "cores": threads, "kind": "oracle",
+            "sample": ("the first %d of the %d instances solved one after another by the oracle's "
+                       "FGMRES to 1e-8 (%d DOF, %.2f s of solve time; assembly and setup not "
+                       "counted); CSR products on %d OpenMP threads" % (done, len(probs), dof, t, threads)),
+            "solve_s": t}
 
 
 def measured_copy_gbs(torch):
@@ -145,18 +199,58 @@ def measured_copy_gbs(torch):
     return gbs
 
 
-def field_errors(P, pc, x, opts):
-    """Per-field relative error of the mixed-precision solution x (solved to
-    1e-8) against an FP64 solve of the same system to 1e-12, next to the error
-    of an FP64 solve to 1e-8 against the same reference (untimed)."""
+def profiled(dpp, run, steps):
+    """Per-family HIP-event timings of `steps` runs -> {family: stats}."""
+    dpp.profile_enable(True)
+    for _ in range(steps):
+        run()
     import torch
-    ref, _ = P.solve(pc, **{**opts, "precision": 0, "rtol": 1e-12, "use_graph": 0})
-    x64, _ = P.solve(pc, **{**opts, "precision": 0, "use_graph": 0})
-    R, M, D = P.fields(ref), P.fields(x), P.fields(x64)
-    rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
-    return {"reference": "FP64 GPU solve to rel. residual 1e-12",
-            "mixed": {f: rel(M[f], R[f]) for f in R},
-            "fp64_at_1e-8": {f: rel(D[f], R[f]) for f in R}}
+    torch.cuda.synchronize()
+    prof = dpp.profile_read()
+    dpp.profile_enable(False)
+    tot_ms = sum(v[1] for v in prof.values())
+    kernels = {}
+    for name, (n, t, by) in prof.items():
+        if n:
+            kernels[name] = {"launches_per_solve": n / steps, "ms_per_solve": t / steps,
+                             "avg_us": 1e3 * t / n, "GBps": by / (t * 1e6) if t > 0 else None,
+                             "share": t / tot_ms if tot_ms else None,
+                             "_raw": (n, t, by)}
+    return kernels
+
+
+def roofline(kernels, candidates, copy_gbs, name_of):
+    """Roofline object of the candidate family with the largest time share."""
+    dom = max((k for k in kernels if k in candidates), key=lambda k: kernels[k]["ms_per_solve"])
+    n, t, by = kernels[dom]["_raw"]
+    achieved = by / (t * 1e6)
+    per_launch = by / n
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(dom, per_launch),
+            "kernel": dom, "kernel_name": name_of(dom),
+            "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": 1e3 * t / n,
+            "copy_ceiling": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
+
+
+def strip_raw(kernels):
+    return {k: {a: b for a, b in v.items() if a != "_raw"} for k, v in kernels.items()}
+
+
+def timed(torch, run, steps, warmup):
+    """Mean wall time (ms) of `steps` runs after `warmup` untimed ones, with
+    a device synchronisation on both sides; returns (ms, last result)."""
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = run()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - tb) * 1e3 / steps, out
+
+
+BATCH_FAMILIES = ("batch_spmv_K", "batch_cheb_S_l0")
 
 
 def bench_batch(args, torch, I, dpp):
@@ -169,14 +263,31 @@ def bench_batch(args, torch, I, dpp):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     opts = dict(rtol=1e-8, precision=args.precision, use_graph=1)
-    for _ in range(args.warmup):
-        B.solve(**opts)
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    for _ in range(args.steps):
-        x, st = B.solve(**opts)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - tb) * 1e3 / args.steps
+    ms, (x, st) = timed(torch, lambda: B.solve(**opts), args.steps, args.warmup)
+    log("batched solve %.2f ms" % ms)
+    line = {
+        "metric": METRIC, "value": B.n_dof / (ms / 1e3), "unit": "DOF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64/f32",
+        "data": "synthetic",
+        "config": {"workload": "c4_batch64", "description": WORKLOADS["c4_batch64"],
+                   "n_dof": B.n_dof, "instances": len(probs), "rtol": 1e-8,
+                   "precision": PRECISION[args.precision], "graph": True},
+        "iters_max": max(s.iters for s in st), "iters_min": min(s.iters for s in st),
+        "all_converged": all(s.converged for s in st),
+        "setup_ms": (t1 - t0) * 1e3, "lanes_per_level": B.lanes(),
+    }
+    if args.precision == 0:
+        # the other precisions of the same batch, timed the same way
+        for prec in (2, 1):
+            try:
+                msp, (_, stp) = timed(torch, lambda: B.solve(**{**opts, "precision": prec}),
+                                      args.steps, args.warmup)
+                line["precision_%d" % prec] = {
+                    "precision": PRECISION[prec], "ms_per_step": msp, "value": B.n_dof / (msp / 1e3),
+                    "iters_max": max(s.iters for s in stp), "refinements_max": max(s.refinements for s in stp)}
+            except dpp.DppError as e:
+                line["precision_%d" % prec] = {"error": str(e)}
     # reference: the single-problem FP64 path, instance by instance
     singles = []
     for pr in probs:
@@ -190,21 +301,23 @@ def bench_batch(args, torch, I, dpp):
         P.solve(pc, rtol=1e-8)
     torch.cuda.synchronize()
     seq_ms = (time.perf_counter() - ts) * 1e3
-    line = {
-        "metric": METRIC, "value": B.n_dof / (ms / 1e3), "unit": "DOF/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64/f32",
-        "data": "synthetic",
-        "config": {"workload": "c4_batch64", "description": WORKLOADS["c4_batch64"],
-                   "n_dof": B.n_dof, "instances": len(probs), "rtol": 1e-8,
-                   "precision": PRECISION[args.precision], "graph": True},
-        "iters_max": max(s.iters for s in st), "iters_min": min(s.iters for s in st),
-        "all_converged": all(s.converged for s in st),
-        "setup_ms": (t1 - t0) * 1e3, "lanes_per_level": B.lanes(),
-        "sequential_single_fp64_ms": seq_ms,
-        "speedup_vs_sequential": seq_ms / ms,
-        "roofline": None,
-    }
+    del singles
+    line["sequential_single_fp64_ms"] = seq_ms
+    line["speedup_vs_sequential"] = seq_ms / ms
+    if not args.no_profile:
+        copy_gbs = measured_copy_gbs(torch)
+        # the profiled runs replay no graphs (each launch is bracketed by events)
+        kernels = profiled(dpp, lambda: B.solve(**{**opts, "use_graph": 0}), args.steps)
+        line["roofline"] = roofline(kernels, BATCH_FAMILIES, copy_gbs,
+                                    lambda k: {"batch_spmv_K": "kb_spmv_K<2, double, false>",
+                                               "batch_cheb_S_l0": "kb_cheb<2, double, double, L> "
+                                               "(finest levels; L = lanes per row)"}[k])
+        line["kernels"] = strip_raw(kernels)
+    else:
+        line["roofline"] = None
+    if not args.no_cpu_baseline:
+        log("oracle batch sample")
+        line["cpu_baseline"] = oracle_batch_leg(probs, args.cpu_budget)
     print(json.dumps(line), flush=True)
 
 
@@ -213,10 +326,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2_3d64", choices=sorted(WORKLOADS))
+    ap.add_argument("--config", default="c3_3d96_grf", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", type=int, default=0, choices=[0, 1, 2])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-max-iters", type=int, default=60)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision timing carried next to the FP64 line")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline and the per-field errors against it)")
+    ap.add_argument("--cpu-sample-iters", type=int, default=12,
+                    help="oracle FGMRES iterations timed for the CPU baseline")
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds of oracle solve time for the batch's CPU baseline")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--shapes", default=None,
                     help="JSON file of per-level kernel shapes: written after autotuning when "
@@ -270,47 +389,11 @@ def main():
             json.dump({"workload": args.config, "shapes": [list(pc.shape(lvl)) for lvl in range(nlev - 1)]},
                       open(args.shapes, "w"))
     opts = dict(rtol=1e-8, precision=args.precision, use_graph=args.graph)
-    for _ in range(args.warmup):
-        P.solve(pc, **opts)
-    torch.cuda.synchronize()
-    stats = []
-    tb = time.perf_counter()
-    for _ in range(args.steps):
-        x, st = P.solve(pc, **opts)
-        stats.append(st.as_dict())
-    torch.cuda.synchronize()
-    te = time.perf_counter()
-    ms = (te - tb) * 1e3 / args.steps
-    iters = stats[-1]["iters"]
+    ms, (x, st) = timed(torch, lambda: P.solve(pc, **opts), args.steps, args.warmup)
+    iters = st.iters
     value = P.n_dof / (ms / 1e3)
-
-    kernels, roof = {}, None
-    copy_gbs = measured_copy_gbs(torch)
-    if not args.no_profile:
-        dpp.profile_enable(True)
-        for _ in range(args.steps):
-            P.solve(pc, **opts)
-        torch.cuda.synchronize()
-        prof = dpp.profile_read()
-        dpp.profile_enable(False)
-        tot_ms = sum(v[1] for v in prof.values())
-        for name, (n, t, by) in prof.items():
-            if n:
-                kernels[name] = {"launches_per_solve": n / args.steps, "ms_per_solve": t / args.steps,
-                                 "avg_us": 1e3 * t / n, "GBps": by / (t * 1e6) if t > 0 else None,
-                                 "share": t / tot_ms if tot_ms else None}
-        dom = max((k for k in kernels if k in SINGLE_KERNEL_FAMILIES),
-                  key=lambda k: kernels[k]["ms_per_solve"])
-        n, t, by = prof[dom]
-        achieved = by / (t * 1e6)
-        per_launch = by / n
-        tr = measured_traffic(dom, per_launch)
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": tr, "kernel": dom,
-                "kernel_name": kernel_name(dom, prob.dim, pc,
-                                           flux=getattr(prob, "face_bc", None) is not None),
-                "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": 1e3 * t / n,
-                "copy_ceiling": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
+    log("%s precision %d: %.3f ms per solve, %d iterations" % (args.config, args.precision, ms, iters))
+    solutions = {"precision_%d" % args.precision: x.cpu().numpy()}
 
     line = {
         "metric": METRIC, "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
@@ -320,14 +403,35 @@ def main():
         "config": {"workload": args.config, "description": WORKLOADS[args.config],
                    "n_dof": P.n_dof, "rtol": 1e-8, "precision": PRECISION[args.precision],
                    "graph": bool(args.graph)},
-        "iters": iters, "rel_residual": stats[-1]["rel_residual"],
+        "iters": iters, "rel_residual": st.rel_residual,
         "assemble_ms": (t1 - t0) * 1e3, "setup_ms": (t2 - t1) * 1e3,
-        "roofline": roof, "kernels": kernels,
     }
-    if args.precision:
-        line["field_error_vs_fp64"] = field_errors(P, pc, x, opts)
+    if args.precision == 0 and not args.no_mixed:
+        # the mixed-precision solve of the same system, timed the same way
+        msm, (xm, stm) = timed(torch, lambda: P.solve(pc, **{**opts, "precision": 1}),
+                               args.steps, args.warmup)
+        log("precision 1: %.3f ms per solve, %d inner iterations" % (msm, stm.iters))
+        line["mixed"] = {"precision": PRECISION[1], "ms_per_step": msm, "value": P.n_dof / (msm / 1e3),
+                         "iters": stm.iters, "refinements": stm.refinements,
+                         "rel_residual": stm.rel_residual, "speedup_vs_fp64": ms / msm}
+        solutions["precision_1"] = xm.cpu().numpy()
+
+    copy_gbs = measured_copy_gbs(torch)
+    if not args.no_profile:
+        kernels = profiled(dpp, lambda: P.solve(pc, **opts), args.steps)
+        line["roofline"] = roofline(kernels, SINGLE_KERNEL_FAMILIES, copy_gbs,
+                                    lambda k: kernel_name(k, prob.dim, pc,
+                                                          flux=getattr(prob, "face_bc", None) is not None))
+        line["kernels"] = strip_raw(kernels)
+    else:
+        line["roofline"] = None
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(prob, iters, args.cpu_max_iters)
+        del pc, P
+        torch.cuda.empty_cache()
+        log("oracle leg")
+        base, errs = oracle_leg(prob, iters, args.cpu_sample_iters, solutions)
+        line["cpu_baseline"] = base
+        line["field_error_vs_oracle"] = errs
     print(json.dumps(line), flush=True)
 
 

@@ -64,8 +64,9 @@ typedef struct {
 
 /* Coefficients and boundary data (section "Boundary conditions"; parameters of
  * the paper's data tables).  k1, k2: per-cell permeabilities [n_cells] (> 0).
- * beta: scalar mass-transfer coefficient, used when beta_cells == NULL, else
- * beta_cells [n_cells].  body: gamma*b per cell [n_cells*dim] or NULL (b = 0).
+ * beta: scalar mass-transfer coefficient (>= 0), used when beta_cells == NULL,
+ * else beta_cells [n_cells] (>= 0; DPP_ERR_NUMERIC for a negative or
+ * non-finite entry, as for k1, k2 <= 0).  body: gamma*b per cell [n_cells*dim] or NULL (b = 0).
  * p0_1, p0_2: nodal pressures [n_nodes]; only boundary nodes are read, and the
  * boundary integral -(w.n; p0) uses their P1 interpolant exactly (on the
  * pressure faces).
@@ -82,7 +83,9 @@ typedef struct {
  * of the right-hand side in the range of K (its component along the kernel
  * removed) and return pressures normalised to int p1 = 0, the branch of the
  * constraint of the pressure space Q (int p1)(int p2) = 0 that this library
- * takes. */
+ * takes.  Such a box needs beta > 0 in some cell (without mass transfer each
+ * network has its own constant-pressure kernel): DPP_ERR_UNSUPPORTED
+ * otherwise. */
 typedef struct {
   double mu;
   const double *k1;
@@ -259,6 +262,12 @@ dpp_status dpp_simplex_rule(int dim, int q, double *lam, double *w);
  *   4 D^-1 (r_u - K_up z_p)          5 coarser multigrid levels + coarse solve
  *   6 finest-level vector steps (first Chebyshev step, restriction,
  *     prolongation)                  7 Arnoldi (CGS2 passes, norms, scaling)
+ * and of batched solves (bytes summed over the instances still running):
+ *   8 K products                     9 Chebyshev steps with the S_p products
+ *                                      of the instances' finest levels
+ *  10 Schur right-hand side and      11 coarser levels, grid transfers and
+ *     velocity step                     coarse solves
+ *  12 Arnoldi passes
  * dpp_profile_read synchronises on the recorded events and returns the launch
  * count, total milliseconds and total algorithmic bytes of one family. */
 dpp_status dpp_profile_enable(int on);

@@ -44,7 +44,14 @@ def lib():
                                      P, P, P, C.c_double, P, P, P]
         _lib.or_spmv.restype = None
         _lib.or_spmv.argtypes = [C.c_long, P, P, P, P, P]
+        _lib.or_max_threads.restype = C.c_int
+        _lib.or_max_threads.argtypes = []
     return _lib
+
+
+def threads():
+    """Threads of the oracle's OpenMP loops (assembly, CSR product)."""
+    return int(lib().or_max_threads())
 
 
 def _p(a):
@@ -216,14 +223,29 @@ def blocks(sys_or_K, dim=None, N=None):
         K = sys_or_K
     F = fields(dim, N)
     K = K.tocsr()
+    # a block is the rows of one field (a contiguous row range) restricted to
+    # the columns of another: a selection of stored entries, no arithmetic
+    def block(a, b):
+        ra, cb = F[a], F[b]
+        lo, hi = K.indptr[ra.start], K.indptr[ra.stop]
+        cols = K.indices[lo:hi]
+        keep = (cols >= cb.start) & (cols < cb.stop)
+        counts = np.add.reduceat(keep.astype(np.int64), K.indptr[ra.start:ra.stop] - lo) \
+            if hi > lo else np.zeros(ra.stop - ra.start, dtype=np.int64)
+        # reduceat repeats the next value for empty rows: zero them
+        counts[np.diff(K.indptr[ra.start:ra.stop + 1]) == 0] = 0
+        indptr = np.concatenate([[0], np.cumsum(counts)])
+        return sp.csr_matrix((K.data[lo:hi][keep], cols[keep] - cb.start, indptr),
+                             shape=(ra.stop - ra.start, cb.stop - cb.start))
+
     out = dict(Kuu=[], Kup=[], Kpu=[], Kpp=[])
     for u, p in (("u1", "p1"), ("u2", "p2")):
-        out["Kuu"].append(K[F[u], :][:, F[u]].tocsr())
-        out["Kup"].append(K[F[u], :][:, F[p]].tocsr())
-        out["Kpu"].append(K[F[p], :][:, F[u]].tocsr())
-        out["Kpp"].append(K[F[p], :][:, F[p]].tocsr())
-    out["K12"] = K[F["p1"], :][:, F["p2"]].tocsr()
-    out["K21"] = K[F["p2"], :][:, F["p1"]].tocsr()
+        out["Kuu"].append(block(u, u))
+        out["Kup"].append(block(u, p))
+        out["Kpu"].append(block(p, u))
+        out["Kpp"].append(block(p, p))
+    out["K12"] = block("p1", "p2")
+    out["K21"] = block("p2", "p1")
     return out
 
 

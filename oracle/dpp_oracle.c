@@ -26,6 +26,7 @@
  * contributions of its incident cells into its own rows (deterministic).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -334,6 +335,17 @@ void or_assemble(int d, const int *n, long N, long nc, const double *X, const in
       }
     }
   }
+}
+
+/* Threads the OpenMP loops of this file use. */
+int or_max_threads(void) {
+  int t = 1;
+#pragma omp parallel
+  {
+#pragma omp single
+    t = omp_get_num_threads();
+  }
+  return t;
 }
 
 /* y = A x for a CSR matrix (OpenMP over rows). */

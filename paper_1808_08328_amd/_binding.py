@@ -122,7 +122,8 @@ def _stream(stream=None):
 
 
 PROFILE_FAMILIES = ["spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "schur_vel", "coarse_levels",
-                    "vector_l0", "arnoldi"]
+                    "vector_l0", "arnoldi", "batch_spmv_K", "batch_cheb_S_l0", "batch_schur",
+                    "batch_levels", "batch_arnoldi"]
 
 
 def profile_enable(on=True):
@@ -417,16 +418,25 @@ class DppSolve(torch.autograd.Function):
 
     forward: dpp_assemble + dpp_setup_precond + dpp_solve; backward:
     dpp_solve_adjoint (K^T lambda = dJ/dx) + dpp_param_grad.  Boundary data
-    are held fixed (df/dtheta = 0)."""
+    are held fixed (df/dtheta = 0).  beta is one scalar (a tensor of one
+    element; its gradient has the same shape).  spec: dim, n, p0_1, p0_2
+    (device tensors), optional mu and L; body forces and velocity faces are
+    not differentiated here and are rejected."""
 
     @staticmethod
     def forward(ctx, logk1, logk2, beta, spec, opts):
+        bad = [k for k in ("body", "beta_cells", "face_bc", "u_bc_1", "u_bc_2")
+               if spec.get(k) is not None]
+        if bad:
+            raise ValueError("DppSolve does not support %s" % ", ".join(bad))
+        if not torch.is_tensor(beta) or beta.numel() != 1:
+            raise ValueError("beta must be a tensor holding one scalar")
         prob = assemble(spec["dim"], spec["n"], torch.exp(logk1).contiguous(),
                         torch.exp(logk2).contiguous(), spec["p0_1"], spec["p0_2"],
-                        beta=float(beta), mu=spec.get("mu", 1.0), L=spec.get("L"))
+                        beta=float(beta.reshape(())), mu=spec.get("mu", 1.0), L=spec.get("L"))
         pc = prob.setup_precond(**(opts or {}))
         x, _ = prob.solve(pc, **(opts or {}))
-        ctx.prob, ctx.pc, ctx.opts = prob, pc, opts
+        ctx.prob, ctx.pc, ctx.opts, ctx.beta_shape = prob, pc, opts, beta.shape
         ctx.save_for_backward(x)
         return x
 
@@ -435,4 +445,4 @@ class DppSolve(torch.autograd.Function):
         (x,) = ctx.saved_tensors
         lam, _ = ctx.prob.solve_adjoint(ctx.pc, gx.contiguous(), **(ctx.opts or {}))
         g1, g2, gb = ctx.prob.param_grad(x, lam)
-        return g1, g2, gb.reshape(()), None, None
+        return g1, g2, gb.reshape(ctx.beta_shape), None, None

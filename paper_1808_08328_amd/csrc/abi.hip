@@ -242,13 +242,14 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
       o.power_iters = pc->opts.power_iters;
       o.cheb_lo_frac = pc->opts.cheb_lo_frac;
       o.cheb_hi_factor = pc->opts.cheb_hi_factor;
-      pc->opts.cheb_degree = o.cheb_degree;
-      pc->opts.cheb_pre_fine = o.cheb_pre_fine;
-      pc->opts.cheb_post_fine = o.cheb_post_fine;
-      pc->opts.cheb_pre_coarse = o.cheb_pre_coarse;
-      pc->opts.cheb_post_coarse = o.cheb_post_coarse;
     }
+    // a rejected call leaves the handle as it was
     check_opts(o);
+    pc->opts.cheb_degree = o.cheb_degree;
+    pc->opts.cheb_pre_fine = o.cheb_pre_fine;
+    pc->opts.cheb_post_fine = o.cheb_post_fine;
+    pc->opts.cheb_pre_coarse = o.cheb_pre_coarse;
+    pc->opts.cheb_post_coarse = o.cheb_post_coarse;
     hipStream_t s = S(stream);
     if (o.use_graph && !dpp::prof_on()) {
       // Graphs are captured and replayed on a stream the library owns (the
@@ -339,16 +340,19 @@ dpp_status dpp_solve(dpp_problem P, dpp_precond pc, const dpp_solve_opts *opts, 
 
 dpp_status dpp_solve_adjoint(dpp_problem P, dpp_precond pc, const dpp_solve_opts *opts,
                              const double *g, double *lambda, dpp_solve_stats *stats, void *stream) {
-  dpp::DBuf dg;
+  double *dg = nullptr;
   dpp_status st = guard([&] {
     DPP_CHECK(P && pc && g && lambda && g != lambda, DPP_ERR_ARG, "bad argument");
+    DPP_CHECK(pc->prob == P, DPP_ERR_ARG, "preconditioner belongs to another problem");
     const long n = P->ndof();
-    dg.alloc(sizeof(double) * n);
-    dpp::flip_pressure_sign(P, g, dg.as<double>(), S(stream));
+    // allocated on the first adjoint solve of this preconditioner, then reused
+    if (!pc->adjrhs.ptr) pc->adjrhs.alloc(sizeof(double) * n);
+    dg = pc->adjrhs.as<double>();
+    dpp::flip_pressure_sign(P, g, dg, S(stream));
     DPP_HIP(hipMemsetAsync(lambda, 0, sizeof(double) * n, S(stream)));
   });
   if (st != DPP_OK) return st;
-  st = solve_common(P, pc, opts, dg.as<double>(), lambda, stats, stream);
+  st = solve_common(P, pc, opts, dg, lambda, stats, stream);
   if (st != DPP_OK && st != DPP_ERR_NOT_CONVERGED) return st;
   dpp_status st2 = guard([&] {
     dpp::flip_pressure_sign(P, lambda, lambda, S(stream));

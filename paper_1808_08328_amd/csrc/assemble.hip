@@ -366,14 +366,13 @@ int count_neighbours_host(const Grid &g, long a) {
   return cnt;
 }
 
-__global__ void k_check_positive(const double *v, long n, int *bad) {
+// bad[0] = 1 when an entry is not finite, or (kind 1) not > 0, or (kind 2) < 0
+__global__ void k_check_values(const double *v, long n, int kind, int *bad) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && !(v[i] > 0.0 && v[i] < INFINITY)) bad[0] = 1;
-}
-
-__global__ void k_check_finite(const double *v, long n, int *bad) {
-  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && !(fabs(v[i]) < INFINITY)) bad[0] = 1;
+  if (i >= n) return;
+  const double x = v[i];
+  const bool ok = fabs(x) < INFINITY && (kind != 1 || x > 0.0) && (kind != 2 || x >= 0.0);
+  if (!ok) bad[0] = 1;
 }
 
 }  // namespace
@@ -393,18 +392,35 @@ long count_nnz(const Grid &g) {
   return pairs * (g.dim == 3 ? 22 : 16);
 }
 
-static void check_input(const double *p, long n, bool positive, const char *name, hipStream_t s) {
+__global__ void k_any_positive(const double *v, long n, int *hit) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && v[i] > 0.0) hit[0] = 1;
+}
+
+static bool any_positive(const double *p, long n, hipStream_t s) {
   DBuf flag(sizeof(int));
   DPP_HIP(hipMemsetAsync(flag.ptr, 0, sizeof(int), s));
-  if (positive)
-    k_check_positive<<<blocks_for(n, 256), 256, 0, s>>>(p, n, flag.as<int>());
-  else
-    k_check_finite<<<blocks_for(n, 256), 256, 0, s>>>(p, n, flag.as<int>());
+  k_any_positive<<<blocks_for(n, 256), 256, 0, s>>>(p, n, flag.as<int>());
+  check_launch("any_positive");
+  int h = 0;
+  DPP_HIP(hipMemcpyAsync(&h, flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+  DPP_HIP(hipStreamSynchronize(s));
+  return h != 0;
+}
+
+enum CheckKind { FINITE = 0, POSITIVE = 1, NONNEGATIVE = 2 };
+
+static void check_input(const double *p, long n, CheckKind kind, const char *name, hipStream_t s) {
+  DBuf flag(sizeof(int));
+  DPP_HIP(hipMemsetAsync(flag.ptr, 0, sizeof(int), s));
+  k_check_values<<<blocks_for(n, 256), 256, 0, s>>>(p, n, (int)kind, flag.as<int>());
   check_launch("check_input");
   int h = 0;
   DPP_HIP(hipMemcpyAsync(&h, flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
   DPP_HIP(hipStreamSynchronize(s));
-  DPP_CHECK(!h, DPP_ERR_NUMERIC, std::string(name) + " holds a non-finite or non-positive value");
+  static const char *what[] = {"a non-finite value", "a non-finite or non-positive value",
+                               "a non-finite or negative value"};
+  DPP_CHECK(!h, DPP_ERR_NUMERIC, std::string(name) + " holds " + what[kind]);
 }
 
 void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, hipStream_t s) {
@@ -423,12 +439,12 @@ void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, 
             "box too large: (2 dim + 2) x nodes must stay below 2^31");
   const int NS = (D == 3) ? Tabs<3>::NS : Tabs<2>::NS;
   DPP_CHECK((double)g.N * (2 * D + 2) < 2.0e9, DPP_ERR_ARG, "problem too large for 32-bit indices");
-  check_input(prm->k1, g.nc, true, "k1", s);
-  check_input(prm->k2, g.nc, true, "k2", s);
-  check_input(prm->p0_1, g.N, false, "p0_1", s);
-  check_input(prm->p0_2, g.N, false, "p0_2", s);
-  if (prm->beta_cells) check_input(prm->beta_cells, g.nc, false, "beta_cells", s);
-  if (prm->body) check_input(prm->body, g.nc * D, false, "body", s);
+  check_input(prm->k1, g.nc, POSITIVE, "k1", s);
+  check_input(prm->k2, g.nc, POSITIVE, "k2", s);
+  check_input(prm->p0_1, g.N, FINITE, "p0_1", s);
+  check_input(prm->p0_2, g.N, FINITE, "p0_2", s);
+  if (prm->beta_cells) check_input(prm->beta_cells, g.nc, NONNEGATIVE, "beta_cells", s);
+  if (prm->body) check_input(prm->body, g.nc * D, FINITE, "body", s);
   DPP_CHECK(std::isfinite(prm->beta) && prm->beta >= 0.0, DPP_ERR_ARG, "beta must be >= 0");
 
   if (prm->face_bc) {
@@ -440,8 +456,16 @@ void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, 
       }
     DPP_CHECK((!g.fix[0] || prm->u_bc_1) && (!g.fix[1] || prm->u_bc_2), DPP_ERR_ARG,
               "u_bc_i is required for a network with velocity faces");
-    if (g.fix[0]) check_input(prm->u_bc_1, g.N * D, false, "u_bc_1", s);
-    if (g.fix[1]) check_input(prm->u_bc_2, g.N * D, false, "u_bc_2", s);
+    if (g.fix[0]) check_input(prm->u_bc_1, g.N * D, FINITE, "u_bc_1", s);
+    if (g.fix[1]) check_input(prm->u_bc_2, g.N * D, FINITE, "u_bc_2", s);
+    // With velocity faces everywhere and no mass transfer the two networks
+    // decouple and K has a constant-pressure kernel per network; the
+    // pure-flux solve removes one shared constant only.
+    if (pure_flux(g)) {
+      const bool coupled = prm->beta_cells ? any_positive(prm->beta_cells, g.nc, s) : prm->beta > 0.0;
+      DPP_CHECK(coupled, DPP_ERR_UNSUPPORTED,
+                "velocity faces on every face of both networks need beta > 0 somewhere");
+    }
   }
   P->g = g;
   P->mu = prm->mu;

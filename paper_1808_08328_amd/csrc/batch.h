@@ -81,6 +81,7 @@ struct dpp_batch_s {
   dpp::DTable<dpp::CDesc> cd, cd32;
   dpp::DTable<dpp::VDesc> vd;
   dpp::DBuf active, fac, nks, ydev;
+  std::vector<int> hact;                 // host copy of the active flags (profiling bytes)
   dpp::DBuf V, Z, w, part, hb, rtmp;
   int ws_m = 0;
   bool has32 = false;

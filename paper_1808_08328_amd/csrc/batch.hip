@@ -419,10 +419,73 @@ int level_cblocks(dpp_batch B, int l) {
   return c;
 }
 
+// Algorithmic bytes of the batched launches, summed over the running
+// instances (instrumentation only): stored matrix entries inside each box
+// once, each vector read or written once, as for the single-instance kernels.
+bool running(dpp_batch B, int i) { return i < (int)B->hact.size() && B->hact[i]; }
+
+double bytes_spmv(dpp_batch B, bool resid) {
+  double t = 0.0;
+  for (int i = 0; i < B->nb; ++i)
+    if (running(B, i)) t += kbytes(B->P[i]->g, false, resid);
+  return t;
+}
+
+template <int D>
+double bytes_cheb(dpp_batch B, int l, double tx, int step, bool resid_only) {
+  double t = 0.0;
+  for (int i = 0; i < B->nb; ++i) {
+    dpp_precond pc = B->pc[i];
+    if (!running(B, i) || (int)pc->lv.size() - 1 <= l) continue;
+    const Grid &g = pc->lv[l]->g;
+    const double N = (double)g.N, pairs = 0.5 * (valid_pairs<D, true>(g) + N);
+    t += resid_only ? 2.0 * (pairs * tx + 3.0 * N * tx)
+                    : 2.0 * (pairs * tx + N * (5.0 * tx + (step > 0 ? tx : 0.0)));
+  }
+  return t;
+}
+
+// restriction (w = 0), prolongation (w = 1) or the coarse solves (w = 2)
+double bytes_transfer(dpp_batch B, int l, double tx, int w, bool assign) {
+  double t = 0.0;
+  for (int i = 0; i < B->nb; ++i) {
+    dpp_precond pc = B->pc[i];
+    if (!running(B, i)) continue;
+    if (w == 2) {
+      const double n = pc->ncoarse;
+      t += 2.0 * n * (n * 8.0 + 2.0 * tx);
+      continue;
+    }
+    if ((int)pc->lv.size() - 1 <= l) continue;
+    const double N = (double)pc->lv[l]->g.N, Nc = (double)pc->lv[l + 1]->g.N;
+    t += w == 0 ? 2.0 * tx * (N + Nc) : 2.0 * tx * ((assign ? 1.0 : 2.0) * N + Nc);
+  }
+  return t;
+}
+
+double bytes_schur(dpp_batch B, double tx, bool vel) {
+  double t = 0.0;
+  for (int i = 0; i < B->nb; ++i) {
+    if (!running(B, i)) continue;
+    const Grid &g = B->P[i]->g;
+    t += 2.0 * (upt_bytes(g, tx == 4.0) + g.N * (vel ? 2.0 * g.dim + 2.0 : g.dim + 2.0) * 8.0 + g.N * tx);
+  }
+  return t;
+}
+
+double running_dof(dpp_batch B) {
+  double t = 0.0;
+  for (int i = 0; i < B->nb; ++i)
+    if (running(B, i)) t += (double)B->P[i]->ndof();
+  return t;
+}
+
 template <int D, typename TV, typename TX>
 void launch_cheb_b(dpp_batch B, int l, const DTable<LDesc> &t, hipStream_t s, int step, int in_w,
                    int out_w, int resid_only) {
   if (!t.count) return;
+  ProfScope ps(l == 0 ? PF_B_CHEB_L0 : PF_B_LEVELS,
+               prof_on() ? bytes_cheb<D>(B, l, sizeof(TX), step, resid_only != 0) : 0.0, s);
   const dim3 grid(t.blocks, 2);
   const int *act = B->active.as<int>();
   switch (B->lpr[l]) {
@@ -447,7 +510,10 @@ void vcycle_b(dpp_batch B, bool fp32, hipStream_t s) {
     const dim3 g1(t.blocks, 2);
     int cur = 0, oth = 1;
     if (pre > 0) {
-      kb_cheb_first<TV, TX><<<g1, 256, 0, s>>>(t.get(), t.count, act, 0);
+      {
+        ProfScope ps(PF_B_LEVELS, prof_on() ? bytes_transfer(B, l, sizeof(TX), 1, false) : 0.0, s);
+        kb_cheb_first<TV, TX><<<g1, 256, 0, s>>>(t.get(), t.count, act, 0);
+      }
       for (int k = 1; k < pre; ++k) {
         launch_cheb_b<D, TV, TX>(B, l, t, s, k, cur, oth, 0);
         std::swap(cur, oth);
@@ -458,17 +524,24 @@ void vcycle_b(dpp_batch B, bool fp32, hipStream_t s) {
     const int cb = level_cblocks(B, l);
     // restriction of r (or of b without pre-smoothing): grid over coarse-node
     // blocks, descriptors found through cblk0
+    ProfScope ps(PF_B_LEVELS, prof_on() ? bytes_transfer(B, l, sizeof(TX), 0, false) : 0.0, s);
     kb_restrict<D, TX><<<dim3(cb, 2), 256, 0, s>>>(t.get(), t.count, act, pre > 0 ? 0 : 1);
   }
   const DTable<CDesc> &c = fp32 ? B->cd32 : B->cd;
-  kb_coarse<TX><<<dim3(c.blocks, 2), 256, 0, s>>>(c.get(), c.count, act);
+  {
+    ProfScope ps(PF_B_LEVELS, prof_on() ? bytes_transfer(B, 0, sizeof(TX), 2, false) : 0.0, s);
+    kb_coarse<TX><<<dim3(c.blocks, 2), 256, 0, s>>>(c.get(), c.count, act);
+  }
   for (int l = B->nlev - 1; l >= 0; --l) {
     const DTable<LDesc> &t = tabs[l];
     if (!t.count) continue;
     const int pre = cheb_pre(B->opts, l), post = cheb_post(B->opts, l);
     const dim3 g1(t.blocks, 2);
     int cur = cur_after_pre[l], oth = 1 - cur;
-    kb_prolong<D, TX><<<g1, 256, 0, s>>>(t.get(), t.count, act, cur, pre > 0 ? 0 : 1);
+    {
+      ProfScope ps(PF_B_LEVELS, prof_on() ? bytes_transfer(B, l, sizeof(TX), 1, pre == 0) : 0.0, s);
+      kb_prolong<D, TX><<<g1, 256, 0, s>>>(t.get(), t.count, act, cur, pre > 0 ? 0 : 1);
+    }
     for (int k = 0; k < post; ++k) {
       const int out = (k == post - 1) ? 2 : oth;
       launch_cheb_b<D, TV, TX>(B, l, t, s, k, cur, out, 0);
@@ -484,16 +557,25 @@ void precond_b(dpp_batch B, const double *r, double *z, bool fp32, hipStream_t s
   const DTable<KDesc> &k = fp32 ? B->kd32 : B->kd;
   const int *act = B->active.as<int>();
   const dim3 g(k.blocks, 2);
+  const double tx = fp32 ? 4.0 : 8.0;
   if (fp32) {
-    (B->any_bc ? kb_schur_rhs<D, double, float, true> : kb_schur_rhs<D, double, float, false>)
-        <<<g, 256, 0, s>>>(k.get(), k.count, act, r);
+    {
+      ProfScope ps(PF_B_SCHUR, prof_on() ? bytes_schur(B, tx, false) : 0.0, s);
+      (B->any_bc ? kb_schur_rhs<D, double, float, true> : kb_schur_rhs<D, double, float, false>)
+          <<<g, 256, 0, s>>>(k.get(), k.count, act, r);
+    }
     vcycle_b<D, float, float>(B, true, s);
+    ProfScope ps(PF_B_SCHUR, prof_on() ? bytes_schur(B, tx, true) : 0.0, s);
     (B->any_bc ? kb_schur_vel<D, double, float, true> : kb_schur_vel<D, double, float, false>)
         <<<g, 256, 0, s>>>(k.get(), k.count, act, r, z);
   } else {
-    (B->any_bc ? kb_schur_rhs<D, double, double, true> : kb_schur_rhs<D, double, double, false>)
-        <<<g, 256, 0, s>>>(k.get(), k.count, act, r);
+    {
+      ProfScope ps(PF_B_SCHUR, prof_on() ? bytes_schur(B, tx, false) : 0.0, s);
+      (B->any_bc ? kb_schur_rhs<D, double, double, true> : kb_schur_rhs<D, double, double, false>)
+          <<<g, 256, 0, s>>>(k.get(), k.count, act, r);
+    }
     vcycle_b<D, double, double>(B, false, s);
+    ProfScope ps(PF_B_SCHUR, prof_on() ? bytes_schur(B, tx, true) : 0.0, s);
     (B->any_bc ? kb_schur_vel<D, double, double, true> : kb_schur_vel<D, double, double, false>)
         <<<g, 256, 0, s>>>(k.get(), k.count, act, r, z);
   }
@@ -502,6 +584,7 @@ void precond_b(dpp_batch B, const double *r, double *z, bool fp32, hipStream_t s
 
 template <int D>
 void spmv_b(dpp_batch B, const double *x, const double *bsub, double *y, hipStream_t s) {
+  ProfScope ps(PF_B_SPMV_K, prof_on() ? bytes_spmv(B, bsub != nullptr) : 0.0, s);
   (B->any_bc ? kb_spmv_K<D, double, true> : kb_spmv_K<D, double, false>)
       <<<B->kd.blocks, 256, 0, s>>>(B->kd.get(), B->kd.count, B->active.as<int>(), x, bsub, y);
   check_launch("batched spmv");
@@ -519,6 +602,9 @@ void arnoldi_step_b(dpp_batch B, int j, bool fp32, hipStream_t s) {
   const int nvd = B->vd.count, tb = B->vd.blocks;
   precond_b<D>(B, V + (size_t)j * n, Z + (size_t)j * n, fp32, s);
   spmv_b<D>(B, Z + (size_t)j * n, nullptr, w, s);
+  // A reads V_0..V_j and w; B reads them again, writes v_j (j > 0) and v~_{j+1}
+  ProfScope ps(PF_B_ARNOLDI, prof_on() ? 8.0 * running_dof(B) * (2.0 * j + 4.0 + (j > 0 ? 2.0 : 1.0)) : 0.0,
+               s);
   DPP_NK_SWITCH(std::max(j, 1), kb_dcgs_a<NKP><<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, j, w, part));
   kb_finish<<<dim3(2 * j + 1, nvd), BBS, 0, s>>>(vd, act, part, tb, hb, 0);
   DPP_NK_SWITCH(std::max(j, 1), kb_dcgs_b<NKP><<<tb, BBS, 0, s>>>(vd, nvd, act, V, n, j, w, hb, part));
@@ -723,6 +809,7 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
   std::vector<int> act(nb, 1), conv(nb, 0), its(nb, 0), rest(nb, 0);
   std::vector<double> bn, rn(nb, 0.0);
   auto upload_active = [&]() {
+    B->hact = act;
     DPP_HIP(hipMemcpyAsync(B->active.ptr, act.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
   };
   upload_active();
@@ -924,6 +1011,7 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
 
 void batch_apply(dpp_batch B, int what, const double *x, double *y, hipStream_t s) {
   std::vector<int> ones(B->nb, 1);
+  B->hact = ones;
   DPP_HIP(hipMemcpyAsync(B->active.ptr, ones.data(), sizeof(int) * B->nb, hipMemcpyHostToDevice, s));
   DPP_HIP(hipStreamSynchronize(s));
   if (B->dim == 3) {

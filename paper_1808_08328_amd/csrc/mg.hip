@@ -370,7 +370,8 @@ constexpr int GJB = 32;
 __global__ __launch_bounds__(256) void k_bgj_panel(const double *__restrict__ M, int n, int k0,
                                                    int nb, double *__restrict__ rbuf,
                                                    double *__restrict__ cbuf,
-                                                   double *__restrict__ pinv) {
+                                                   double *__restrict__ pinv,
+                                                   int *__restrict__ bad) {
   const int q = blockIdx.y;
   const double *A = M + (size_t)q * n * n;
   if (blockIdx.x == 0) {
@@ -381,6 +382,8 @@ __global__ __launch_bounds__(256) void k_bgj_panel(const double *__restrict__ M,
     constexpr int PER = GJB * GJB / 256;
     for (int k = 0; k < nb; ++k) {
       double v[PER];
+      // an SPD matrix has positive pivots; anything else is reported
+      if (threadIdx.x == 0 && !(P[k][k] > 0.0 && P[k][k] < INFINITY)) bad[q] = 1;
       const double ip = 1.0 / P[k][k];
       for (int u = 0; u < PER; ++u) {
         const int e = threadIdx.x + u * 256, i = e / nb, j = e % nb;
@@ -669,19 +672,25 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
   {
     // blocked Gauss-Jordan, GJB pivots per step
     DBuf rb(sizeof(double) * 2 * GJB * n), cb(sizeof(double) * 2 * GJB * n),
-        tb(sizeof(double) * 2 * GJB * n), pb(sizeof(double) * 2 * GJB * GJB);
+        tb(sizeof(double) * 2 * GJB * n), pb(sizeof(double) * 2 * GJB * GJB), bad(sizeof(int) * 2);
+    DPP_HIP(hipMemsetAsync(bad.ptr, 0, sizeof(int) * 2, s));
     const dim3 gp(1 + std::min(1024, blocks_for(2L * GJB * n, 256)), 2);
     const dim3 gr(blocks_for((long)GJB * n, 256), 2), gu(blocks_for((long)n * n, 256), 2);
     for (int k0 = 0; k0 < n; k0 += GJB) {
       const int nb = std::min(GJB, n - k0);
       k_bgj_panel<<<gp, 256, 0, s>>>(pc->cinv.as<double>(), n, k0, nb, rb.as<double>(),
-                                     cb.as<double>(), pb.as<double>());
+                                     cb.as<double>(), pb.as<double>(), bad.as<int>());
       k_bgj_rows<<<gr, 256, 0, s>>>(n, nb, rb.as<double>(), pb.as<double>(), tb.as<double>());
       k_bgj_update<<<gu, 256, 0, s>>>(pc->cinv.as<double>(), n, k0, nb, cb.as<double>(),
                                       pb.as<double>(), tb.as<double>());
     }
     check_launch("coarse inverse");
+    int hbad[2] = {0, 0};
+    DPP_HIP(hipMemcpyAsync(hbad, bad.ptr, sizeof(hbad), hipMemcpyDeviceToHost, s));
     DPP_HIP(hipStreamSynchronize(s));
+    DPP_CHECK(!hbad[0] && !hbad[1], DPP_ERR_NUMERIC,
+              "coarsest multigrid operator is not positive definite (non-positive or "
+              "non-finite pivot in its inverse)");
   }
   pc->rhat.alloc(sizeof(double) * 2 * P->g.N);
   DPP_HIP(hipStreamSynchronize(s));

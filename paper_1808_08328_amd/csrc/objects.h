@@ -103,6 +103,7 @@ struct dpp_precond_s {
   int ncoarse = 0;
   dpp::DBuf rhat;   // [2][N] level-0 right-hand side of the V-cycle
   dpp::DBuf bproj;  // [n_dof] consistent right-hand side (pure-flux problems)
+  dpp::DBuf adjrhs; // [n_dof] D g of the adjoint solve, kept across calls
   dpp::DBuf rhat32;
   dpp::DBuf red;    // reduction scratch
   bool has32 = false;
@@ -146,6 +147,9 @@ void make_selfp(dpp_problem P, double *S, hipStream_t s);
 void make_kh(dpp_problem P, hipStream_t s);
 void make_up_table(dpp_problem P, hipStream_t s);
 void make_k32(dpp_problem P, hipStream_t s);
+// algorithmic bytes of one K product (resid: r = b - K x) and of the K_up class table
+double kbytes(const Grid &g, bool fp32, bool resid);
+double upt_bytes(const Grid &g, bool fp32);
 // Schur fieldsplit pieces: rhat_i = r_p_i - K_pu^i diag^-1 r_u_i ; z_u = diag^-1 (r_u - K_up z_p)
 // With ldinv non-null it also writes the finest level's first Chebyshev step
 // x = d = c2 ldinv rhat into xa and d (ldinv, xa, d in the level's precision).

@@ -277,10 +277,10 @@ __global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, si
 // Algorithmic bytes of y = K x (or r = b - K x): the five symmetric kinds of
 // the half storage (zero offset and positive half) once, the K_up class
 // table once, and the vectors.
-static double upt_bytes(const Grid &g, bool fp32) {
+double upt_bytes(const Grid &g, bool fp32) {
   return (g.dim == 3 ? UPT<3>::size : UPT<2>::size) * (fp32 ? 4.0 : 8.0);
 }
-static double kbytes(const Grid &g, bool fp32, bool resid) {
+double kbytes(const Grid &g, bool fp32, bool resid) {
   const double pairs = g.dim == 3 ? valid_pairs<3, false>(g) : valid_pairs<2, false>(g);
   const double half = 0.5 * (pairs + g.N);
   const double nd = (2.0 * g.dim + 2.0) * g.N;

@@ -16,7 +16,13 @@ enum ProfFamily {
   PF_COARSE = 5,     // every kernel of the coarser levels and the coarse solve
   PF_VECTOR_L0 = 6,  // finest level: first Chebyshev step (no product), restriction, prolongation
   PF_ARNOLDI = 7,    // CGS2 passes, norms, scaling, solution update
-  PF_COUNT = 8
+  // batched solves (every running instance in one launch)
+  PF_B_SPMV_K = 8,   // y = K x, r = b - K x
+  PF_B_CHEB_L0 = 9,  // Chebyshev step (or residual) with the S_p product, finest levels
+  PF_B_SCHUR = 10,   // Schur right-hand side and velocity step
+  PF_B_LEVELS = 11,  // coarser levels, restriction, prolongation, coarse solves
+  PF_B_ARNOLDI = 12, // DCGS2 passes and their finish kernels
+  PF_COUNT = 13
 };
 
 bool prof_on();

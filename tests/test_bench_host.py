@@ -51,3 +51,33 @@ def test_kernel_names_of_single_kernel_families():
     assert bench.kernel_name("schur_rhs", 3, pc) == "k_schur_rhs<3, double, double, false>"
     assert bench.kernel_name("schur_vel", 3, pc, flux=True) == "k_schur_vel<3, double, double, true>"
     assert set(bench.SINGLE_KERNEL_FAMILIES) == {"spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "schur_vel"}
+
+
+def test_oracle_leg_reference_and_baseline_on_a_small_box():
+    """The oracle leg on a 3D n = 6 log-normal box: its reference solution
+    agrees with a direct solve, so a solution handed in as the direct solve
+    gets per-field errors at the reference's accuracy and an oracle residual
+    near zero; the CPU baseline names its sample and thread count."""
+    import numpy as np
+
+    import dpp_inputs as I
+    from oracle import dpp as odpp
+    prob = I.grf_problem(3, 6)
+    S = odpp.assemble(prob)
+    xd = odpp.solve_direct(S.K, S.f)
+    base, errs = bench.oracle_leg(prob, gpu_iters=20, sample_iters=5,
+                                  solutions={"direct": xd, "zero": np.zeros_like(xd)})
+    assert base["kind"] == "oracle" and base["unit"] == "DOF/s" and base["value"] > 0
+    assert base["cores"] >= 1 and "first 5 oracle FGMRES iterations" in base["sample"]
+    assert all(errs["direct"][f] <= 1e-9 for f in ("u1", "p1", "u2", "p2"))
+    assert errs["direct"]["oracle_residual"] <= 1e-12
+    assert errs["zero"]["oracle_residual"] == 1.0
+    base, _ = bench.oracle_leg(prob, gpu_iters=20, sample_iters=200, solutions={})
+    assert "to 1e-8 from x = 0" in base["sample"]
+
+
+def test_oracle_batch_leg_stops_at_its_budget():
+    import dpp_inputs as I
+    probs = I.batch_configs(3, seed=7, nmin=4, nmax=8)
+    base = bench.oracle_batch_leg(probs, budget_s=0.0)
+    assert base["value"] > 0 and "the first 1 of the 3 instances" in base["sample"]

@@ -36,6 +36,16 @@ def relmax(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
+def _fields_within(prob, S, x, xo, tol):
+    """Per-field relative difference of x from the oracle's xo, printed, then
+    bounded by tol."""
+    F = odpp.fields(prob.dim, S.N)
+    e = {f: np.linalg.norm(x[F[f]] - xo[F[f]]) / np.linalg.norm(xo[F[f]]) for f in F}
+    print(" ".join("%s %.2e" % fe for fe in e.items()), flush=True)
+    for f, v in e.items():
+        assert v <= tol, (f, e)
+
+
 def _ragged3d():
     q = I.mms_problem(3, (5, 3, 4), k1=1.0, k2=0.1, beta=1.0, mu=0.8, L=(1.0, 0.6, 0.8),
                       flux_faces=[[1, 0, 0, 1, 0, 0], [0, 1, 1, 0, 0, 1]])
@@ -140,7 +150,7 @@ def test_thin_boxes_with_velocity_faces_match_oracle(case):
     xs, st = P.solve(pc, rtol=1e-13)
     assert st.converged
     xo = odpp.solve_pure_flux(S) if odpp.pure_flux(prob) else odpp.solve_direct(S.K, S.f)
-    assert np.linalg.norm(H(xs) - xo) <= 1e-9 * np.linalg.norm(xo)
+    _fields_within(prob, S, H(xs), xo, 1e-10)
 
 
 def test_flux_adjoint_and_gradient_match_oracle():
@@ -221,8 +231,7 @@ def test_pure_flux_solve_matches_oracle(case):
     xg = H(x)
     F = odpp.fields(prob.dim, S.N)
     assert abs(odpp.pressure_mean(S.mesh, xg[F["p1"]])) <= 1e-12 * np.abs(xg[F["p1"]]).max()
-    for f in ("u1", "p1", "u2", "p2"):
-        assert np.linalg.norm(xg[F[f]] - xo[F[f]]) <= 1e-9 * np.linalg.norm(xo[F[f]]), f
+    _fields_within(prob, S, xg, xo, 1e-10)
     for precision in (1, 2):
         xm, st = P.solve(pc, rtol=1e-10, precision=precision)
         assert st.converged
@@ -243,7 +252,7 @@ def test_pure_flux_adjoint_and_gradient_match_oracle():
     lam, st = P.solve_adjoint(pc, T(g), rtol=1e-13)
     assert st.converged
     lo = odpp.solve_pure_flux(S, g, transpose=True)
-    assert np.linalg.norm(H(lam) - lo) <= 1e-9 * np.linalg.norm(lo)
+    _fields_within(prob, S, H(lam), lo, 1e-10)
     g1, g2, gb = P.param_grad(x, lam)
     r1, r2, rb = osolver.param_gradient(S, prob, xh, H(lam))
     assert relmax(H(g1), r1) <= 1e-10 and relmax(H(g2), r2) <= 1e-10

@@ -365,6 +365,13 @@ def test_full_size_mixed_precision_fields_vs_oracle():
     xo, its, res = osolver.solve(S, rtol=1e-11, maxiter=400)
     assert res <= 1e-11
     F = odpp.fields(3, S.N)
+    # the contract's metric check for every mode at 1e-8: the oracle's own K
+    # applied to the GPU solution
+    fn = np.linalg.norm(S.f)
+    for precision in (0, 1, 2):
+        rr = np.linalg.norm(S.f - odpp.spmv(S.K, sols[precision, 1e-8])) / fn
+        print("precision %d rtol 1e-8: oracle residual %.3e" % (precision, rr), flush=True)
+        assert rr <= 1.05e-8, precision
     err = {k: {f: float(np.linalg.norm(v[F[f]] - xo[F[f]]) / np.linalg.norm(xo[F[f]])) for f in F}
            for k, v in sols.items()}
     for k, e in sorted(err.items()):
