@@ -332,7 +332,7 @@ def main():
                     help="skip the mixed-precision timing carried next to the FP64 line")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (CPU baseline and the per-field errors against it)")
-    ap.add_argument("--cpu-sample-iters", type=int, default=12,
+    ap.add_argument("--cpu-sample-iters", type=int, default=40,
                     help="oracle FGMRES iterations timed for the CPU baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle solve time for the batch's CPU baseline")

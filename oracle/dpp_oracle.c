@@ -91,11 +91,12 @@ static int cmp_i32(const void *a, const void *b) {
   return (x > y) - (x < y);
 }
 
-/* node -> cell incidence (incptr[N+1], inc[nc*(d+1)]) and sorted node adjacency
- * (nodes sharing at least one cell, the node itself included). */
-void or_adjacency(int d, long N, long nc, const int32_t *cells, int64_t *incptr,
+/* node -> cell incidence (incptr[N+1], inc[nc*nv]) and sorted node adjacency
+ * (nodes sharing at least one cell, the node itself included); nv vertices per
+ * cell (d + 1 for simplices, 2^d for box cells). */
+void or_adjacency(int d, int nv, long N, long nc, const int32_t *cells, int64_t *incptr,
                   int32_t *inc, int32_t *adjcnt, int32_t *adj) {
-  int nv = d + 1;
+  (void)d;
   memset(incptr, 0, sizeof(int64_t) * (N + 1));
   for (long e = 0; e < nc; ++e)
     for (int a = 0; a < nv; ++a) incptr[cells[e * nv + a] + 1]++;
@@ -332,6 +333,177 @@ void or_assemble(int d, const int *n, long N, long nc, const double *X, const in
             f[dof_u(d, N, 1, a, ax)] -= nrm * s2;
           }
         }
+      }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * Q1 elements on box cells (the [Q1 + Q1]^2 rows of the element table: the
+ * same CG-VMS forms on quadrilaterals / hexahedra with (bi/tri)linear
+ * functions).  Cell h = i + n_x(j + n_y k) is the box itself; its local
+ * vertex v (bits v_a for the axes) is the node corner + sum_a v_a e_a.
+ * ------------------------------------------------------------------------ */
+long or_num_cells_q1(int d, const int *n) {
+  long c = 1;
+  for (int a = 0; a < d; ++a) c *= (long)n[a];
+  return c;
+}
+
+void or_mesh_q1(int d, const int *n, const double *L, double *X, int32_t *cells) {
+  long N = or_num_nodes(d, n);
+  int s1[3] = {1, n[0] + 1, (d == 3) ? (n[0] + 1) * (n[1] + 1) : 0};
+  for (long id = 0; id < N; ++id) {
+    long r = id;
+    for (int a = 0; a < d; ++a) {
+      long ia = r % (n[a] + 1);
+      r /= (n[a] + 1);
+      X[id * d + a] = (double)ia * (L[a] / n[a]);
+    }
+  }
+  long nbox = or_num_cells_q1(d, n);
+  int nv = 1 << d;
+  for (long h = 0; h < nbox; ++h) {
+    long r = h, corner = 0;
+    for (int a = 0; a < d; ++a) {
+      corner += (r % n[a]) * s1[a];
+      r /= n[a];
+    }
+    for (int v = 0; v < nv; ++v) {
+      long id = corner;
+      for (int a = 0; a < d; ++a)
+        if ((v >> a) & 1) id += s1[a];
+      cells[h * nv + v] = (int32_t)id;
+    }
+  }
+}
+
+/* One-dimensional integrals on an interval of length h with the linear
+ * functions phi_0 = 1 - t, phi_1 = t (t = (x - x_0)/h):
+ *   mass      int phi_i phi_j     = h (1 + delta_ij) / 6
+ *   stiffness int phi_i' phi_j'   = (2 delta_ij - 1) / h
+ *   mixed     int phi_i' phi_j    = (2 i - 1) / 2        (no h)
+ *   mean      int phi_i           = h / 2
+ *   slope     int phi_i'          = 2 i - 1 */
+static double m1(int i, int j, double h) { return h * (i == j ? 2.0 : 1.0) / 6.0; }
+static double s1d(int i, int j, double h) { return (i == j ? 1.0 : -1.0) / h; }
+static double c1d(int i) { return i ? 0.5 : -0.5; }
+
+/* Tensor-product integrals over the cell of local vertices a, b (bits per axis). */
+static double q1_mass(int d, int a, int b, const double *h) {
+  double v = 1.0;
+  for (int x = 0; x < d; ++x) v *= m1((a >> x) & 1, (b >> x) & 1, h[x]);
+  return v;
+}
+static double q1_stiff(int d, int a, int b, const double *h) {
+  double v = 0.0;
+  for (int c = 0; c < d; ++c) {
+    double t = s1d((a >> c) & 1, (b >> c) & 1, h[c]);
+    for (int x = 0; x < d; ++x)
+      if (x != c) t *= m1((a >> x) & 1, (b >> x) & 1, h[x]);
+    v += t;
+  }
+  return v;
+}
+/* int (d_c psi_a) psi_b */
+static double q1_dmix(int d, int c, int a, int b, const double *h) {
+  double v = c1d((a >> c) & 1);
+  for (int x = 0; x < d; ++x)
+    if (x != c) v *= m1((a >> x) & 1, (b >> x) & 1, h[x]);
+  return v;
+}
+static double q1_mean(int d, const double *h) {
+  double v = 1.0;
+  for (int x = 0; x < d; ++x) v *= 0.5 * h[x];
+  return v;
+}
+/* int d_c psi_a */
+static double q1_dmean(int d, int c, int a, const double *h) {
+  double v = ((a >> c) & 1) ? 1.0 : -1.0;
+  for (int x = 0; x < d; ++x)
+    if (x != c) v *= 0.5 * h[x];
+  return v;
+}
+
+/*
+ * Assemble K and f for Q1 box cells into the pattern of or_rowptr / or_cols
+ * (same block entries as or_assemble, eq. S4_cg_stiffness_matrix and
+ * eq. S4_cg_rhs, integrated exactly); p0 enters through its Q1 interpolant on
+ * the boundary faces.  k1, k2, beta: per box cell; body: [nc*d] or NULL.
+ */
+void or_assemble_q1(int d, const int *n, const double *L, long N, const int32_t *cells,
+                    const int64_t *incptr, const int32_t *inc, const int64_t *rowptr,
+                    const int32_t *cols, double *vals, double *f, const double *k1,
+                    const double *k2, const double *beta, double mu, const double *body,
+                    const double *p0_1, const double *p0_2) {
+  int nv = 1 << d;
+  double h[3] = {1.0, 1.0, 1.0};
+  for (int a = 0; a < d; ++a) h[a] = L[a] / n[a];
+  memset(vals, 0, sizeof(double) * rowptr[(long)(2 * d + 2) * N]);
+  memset(f, 0, sizeof(double) * (long)(2 * d + 2) * N);
+  const double mean = q1_mean(d, h);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (long a = 0; a < N; ++a) {
+    for (int64_t q = incptr[a]; q < incptr[a + 1]; ++q) {
+      long e = inc[q];
+      const int32_t *cv = cells + e * nv;
+      int la = 0;
+      while (cv[la] != a) ++la;
+      double bm = beta[e] / mu;
+      for (int net = 0; net < 2; ++net) {
+        double k = (net == 0) ? k1[e] : k2[e];
+        for (int lb = 0; lb < nv; ++lb) {
+          long b = cv[lb];
+          double M = q1_mass(d, la, lb, h), St = q1_stiff(d, la, lb, h);
+          for (int c = 0; c < d; ++c) {
+            long ra = dof_u(d, N, net, a, c);
+            /* (w; mu/k u) - 1/2 (mu/k w; k/mu mu/k u) */
+            add_entry(rowptr, cols, vals, ra, dof_u(d, N, net, b, c), 0.5 * (mu / k) * M);
+            /* -(div w; p) - 1/2 (w; grad p) */
+            add_entry(rowptr, cols, vals, ra, dof_p(d, N, net, b),
+                      -q1_dmix(d, c, la, lb, h) - 0.5 * q1_dmix(d, c, lb, la, h));
+          }
+          long rp = dof_p(d, N, net, a);
+          for (int c = 0; c < d; ++c)
+            /* (q; div u) + 1/2 (grad q; u) */
+            add_entry(rowptr, cols, vals, rp, dof_u(d, N, net, b, c),
+                      q1_dmix(d, c, lb, la, h) + 0.5 * q1_dmix(d, c, la, lb, h));
+          /* (q; beta/mu p) + 1/2 (grad q; k/mu grad p); cross -beta/mu M */
+          add_entry(rowptr, cols, vals, rp, dof_p(d, N, net, b), bm * M + 0.5 * (k / mu) * St);
+          add_entry(rowptr, cols, vals, rp, dof_p(d, N, 1 - net, b), -bm * M);
+        }
+        if (body) {
+          double fp = 0.0;
+          for (int c = 0; c < d; ++c) {
+            double gb = body[e * d + c];
+            f[dof_u(d, N, net, a, c)] += 0.5 * gb * mean;
+            fp += 0.5 * (k / mu) * q1_dmean(d, c, la, h) * gb;
+          }
+          f[dof_p(d, N, net, a)] += fp;
+        }
+      }
+      /* -(w.n; p0) over the faces of this cell on the box boundary holding a:
+       * face (axis ax, side s) = local vertices with bit ax equal to s */
+      long r = e;
+      int ce[3] = {0, 0, 0};
+      for (int x = 0; x < d; ++x) {
+        ce[x] = (int)(r % n[x]);
+        r /= n[x];
+      }
+      for (int ax = 0; ax < d; ++ax) {
+        int s = (la >> ax) & 1;
+        if (ce[ax] != (s ? n[ax] - 1 : 0)) continue;
+        double nrm = s ? 1.0 : -1.0, t1 = 0.0, t2 = 0.0;
+        for (int lb = 0; lb < nv; ++lb) {
+          if (((lb >> ax) & 1) != s) continue;
+          double w = 1.0;   /* int_F psi_a psi_b: the mass of the other axes */
+          for (int x = 0; x < d; ++x)
+            if (x != ax) w *= m1((la >> x) & 1, (lb >> x) & 1, h[x]);
+          t1 += w * p0_1[cv[lb]];
+          t2 += w * p0_2[cv[lb]];
+        }
+        f[dof_u(d, N, 0, a, ax)] -= nrm * t1;
+        f[dof_u(d, N, 1, a, ax)] -= nrm * t2;
       }
     }
   }
