@@ -246,6 +246,23 @@ dpp_status dpp_param_grad(dpp_problem prob, const double *x, const double *lambd
 dpp_status dpp_mms_l2_errors(dpp_problem prob, const double *x, const double mms[4], int q,
                              double err[4], void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): dpp_mms_l2_errors without
+ * any device or host allocation.  The quadrature rule and the partial sums
+ * live in one fixed device array of DPP_NOALLOC_SCRATCH_BYTES per GPU, which
+ * the library holds on every GPU it runs on until the process ends (its
+ * address is looked up once per device, on the first call there).  Same
+ * arguments and result as dpp_mms_l2_errors; at most 2048 workgroups take
+ * the simplices in a grid-stride loop, so the sums are grouped differently
+ * and agree with dpp_mms_l2_errors up to rounding.  q > 16 is DPP_ERR_ARG;
+ * a device index of 64 or more is DPP_ERR_UNSUPPORTED.  Every call on a GPU
+ * uses that GPU's one array and leaves its contents there: calls that
+ * overlap on one GPU (other host threads, other streams) race and must be
+ * serialised by the caller.  Synchronises the stream. */
+#define DPP_NOALLOC_SCRATCH_BYTES (256 * 1024)
+dpp_status dpp_mms_l2_errors_noalloc(dpp_problem prob, const double *x, const double mms[4], int q,
+                                     double err[4], void *stream);
+
 /* Host only (no GPU): the conical-product Gauss rule of dpp_mms_l2_errors on
  * the reference simplex of dimension dim (2 or 3): lam [q^dim][dim+1]
  * barycentric points and w [q^dim] weights (summing to 1/dim!), caller-owned

@@ -377,6 +377,14 @@ dpp_status dpp_mms_l2_errors(dpp_problem P, const double *x, const double mms[4]
   });
 }
 
+dpp_status dpp_mms_l2_errors_noalloc(dpp_problem P, const double *x, const double mms[4], int q,
+                                     double err[4], void *stream) {
+  return guard([&] {
+    DPP_CHECK(P && x && mms && err, DPP_ERR_ARG, "null argument");
+    dpp::mms_l2_errors_noalloc(P, x, mms, q, err, S(stream));
+  });
+}
+
 dpp_status dpp_simplex_rule(int dim, int q, double *lam, double *w) {
   return guard([&] {
     DPP_CHECK(lam && w && (dim == 2 || dim == 3) && q >= 1 && q <= 16, DPP_ERR_ARG, "bad argument");

@@ -13,6 +13,11 @@
 
 #include "../../include/dpp.h"
 
+// fixed scratch of the allocation-free entry point, per GPU, and the largest
+// device index it keeps an address for
+constexpr size_t NOALLOC_SCRATCH_BYTES = DPP_NOALLOC_SCRATCH_BYTES;
+constexpr int MAX_DEVICES = 64;
+
 namespace dpp {
 
 struct Error : std::runtime_error {

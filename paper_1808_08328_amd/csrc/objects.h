@@ -166,6 +166,9 @@ void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStr
 // conical-product Gauss rule they use
 void mms_l2_errors(dpp_problem P, const double *x, const double mms[4], int q, double err[4],
                    hipStream_t s);
+// the same without allocating: rule and partial sums in the fixed device array
+void mms_l2_errors_noalloc(dpp_problem P, const double *x, const double mms[4], int q,
+                           double err[4], hipStream_t s);
 void simplex_rule(int dim, int q, std::vector<double> &lam, std::vector<double> &w);
 // pure-flux case: velocity faces everywhere in both networks (singular K)
 bool pure_flux(const Grid &g);

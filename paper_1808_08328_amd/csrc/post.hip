@@ -9,6 +9,7 @@
 // simplex.  One thread per simplex loops over the points; per-workgroup partial
 // sums are added in a fixed order (bit-reproducible).
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "objects.h"
@@ -76,9 +77,10 @@ __global__ __launch_bounds__(PBS) void k_l2_error(GridDev g, const double *__res
   constexpr int NPER = D == 3 ? 6 : 2;
   const long N = g.N;
   const long ncell = (long)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1) * NPER;
-  const long e = (long)blockIdx.x * PBS + threadIdx.x;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // u1, p1, u2, p2
-  if (e < ncell) {
+  // grid-stride over the simplices (one pass when the grid covers them all)
+  for (long e = (long)blockIdx.x * PBS + threadIdx.x; e < ncell; e += (long)gridDim.x * PBS) {
+    double se[4] = {0.0, 0.0, 0.0, 0.0};
     const int s = (int)(e % NPER);
     long hex = e / NPER;
     const int ci = (int)(hex % g.n[0]);
@@ -127,15 +129,15 @@ __global__ __launch_bounds__(PBS) void k_l2_error(GridDev g, const double *__res
         e1 += (hu1[c] - u1[c]) * (hu1[c] - u1[c]);
         e2 += (hu2[c] - u2[c]) * (hu2[c] - u2[c]);
       }
-      acc[0] += w[iq] * e1;
-      acc[1] += w[iq] * (hp1 - p1) * (hp1 - p1);
-      acc[2] += w[iq] * e2;
-      acc[3] += w[iq] * (hp2 - p2) * (hp2 - p2);
+      se[0] += w[iq] * e1;
+      se[1] += w[iq] * (hp1 - p1) * (hp1 - p1);
+      se[2] += w[iq] * e2;
+      se[3] += w[iq] * (hp2 - p2) * (hp2 - p2);
     }
     // |det J| of the simplex: the product of the cell sizes (the reference
     // simplex has volume 1/d!, carried by the weights)
     const double detj = D == 3 ? hx * hy * hz : hx * hy;
-    for (int f = 0; f < 4; ++f) acc[f] *= detj;
+    for (int f = 0; f < 4; ++f) acc[f] += se[f] * detj;
   }
   // fixed-order workgroup sum
   __shared__ double red[4][PBS];
@@ -267,9 +269,7 @@ void normalize_pressures(dpp_problem P, double *x, hipStream_t s) {
 // Gauss-Legendre nodes and weights on [0, 1]: Newton iteration on P_q from the
 // Chebyshev-like guesses cos(pi (i + 3/4) / (q + 1/2)), with P_q and P_q' from
 // the three-term recurrence.
-static void gauss_legendre01(int q, std::vector<double> &t, std::vector<double> &w) {
-  t.assign(q, 0.0);
-  w.assign(q, 0.0);
+static void gauss_legendre01(int q, double *t, double *w) {
   const double pi = 3.14159265358979323846;
   for (int i = 0; i < q; ++i) {
     double z = std::cos(pi * (i + 0.75) / (q + 0.5)), dp = 1.0;
@@ -303,46 +303,51 @@ static void gauss_legendre01(int q, std::vector<double> &t, std::vector<double> 
 // Conical-product rule on the reference simplex {lambda_1 + ... + lambda_d <= 1}:
 // collapsed coordinates s = lambda_1 + .. + lambda_d, then the share of the
 // later vertices at each stage, with Jacobian s^(d-1) (and e in 3D).
-void simplex_rule(int dim, int q, std::vector<double> &lam, std::vector<double> &wt) {
-  std::vector<double> t, w;
+// Writes q^dim points: lam [q^dim][dim+1] and wt [q^dim] (caller-sized).
+static void simplex_rule_into(int dim, int q, double *lam, double *wt) {
+  double t[QMAX], w[QMAX];
   gauss_legendre01(q, t, w);
-  lam.clear();
-  wt.clear();
+  int k = 0;
   if (dim == 2) {
     for (int a = 0; a < q; ++a)
-      for (int b = 0; b < q; ++b) {
+      for (int b = 0; b < q; ++b, ++k) {
         const double s = t[a], e = t[b];
-        lam.insert(lam.end(), {1.0 - s, s * (1.0 - e), s * e});
-        wt.push_back(w[a] * w[b] * s);
+        double *l = lam + 3 * k;
+        l[0] = 1.0 - s;
+        l[1] = s * (1.0 - e);
+        l[2] = s * e;
+        wt[k] = w[a] * w[b] * s;
       }
     return;
   }
   for (int a = 0; a < q; ++a)
     for (int b = 0; b < q; ++b)
-      for (int c = 0; c < q; ++c) {
+      for (int c = 0; c < q; ++c, ++k) {
         const double s = t[a], e = t[b], gq = t[c];
-        lam.insert(lam.end(), {1.0 - s, s * (1.0 - e), s * e * (1.0 - gq), s * e * gq});
-        wt.push_back(w[a] * w[b] * w[c] * s * s * e);
+        double *l = lam + 4 * k;
+        l[0] = 1.0 - s;
+        l[1] = s * (1.0 - e);
+        l[2] = s * e * (1.0 - gq);
+        l[3] = s * e * gq;
+        wt[k] = w[a] * w[b] * w[c] * s * s * e;
       }
 }
 
-void mms_l2_errors(dpp_problem P, const double *x, const double mms[4], int q, double err[4],
-                   hipStream_t s) {
+void simplex_rule(int dim, int q, std::vector<double> &lam, std::vector<double> &wt) {
+  int nq = 1;
+  for (int a = 0; a < dim; ++a) nq *= q;
+  lam.assign((size_t)nq * (dim + 1), 0.0);
+  wt.assign(nq, 0.0);
+  simplex_rule_into(dim, q, lam.data(), wt.data());
+}
+
+// The error integral with the rule at dl/dw (device), nb workgroups writing
+// their partial sums to dp (device, 4 nb + 4 doubles); err on the host.
+static void l2_errors_on(dpp_problem P, const double *x, const double mms[4], int nq,
+                         const double *dl, const double *dw, int nb, double *dp, double err[4],
+                         hipStream_t s) {
   const Grid &g = P->g;
-  DPP_CHECK(q >= 1 && q <= QMAX, DPP_ERR_ARG, "quadrature order must be in 1..16");
-  DPP_CHECK(mms[0] > 0.0 && mms[1] > 0.0 && mms[2] > 0.0 && mms[3] > 0.0, DPP_ERR_ARG,
-            "manufactured-solution parameters must be positive");
-  std::vector<double> lam, wt;
-  simplex_rule(g.dim, q, lam, wt);
-  const int nq = (int)wt.size();
-  const long ncell = (long)g.nc;
-  const int nb = (int)((ncell + PBS - 1) / PBS);
-  DBuf rule(sizeof(double) * (lam.size() + wt.size()));
-  DBuf part(sizeof(double) * 4 * (size_t)nb + sizeof(double) * 4);
-  double *dl = rule.as<double>(), *dw = dl + lam.size();
-  double *dp = part.as<double>(), *dout = dp + 4 * (size_t)nb;
-  DPP_HIP(hipMemcpyAsync(dl, lam.data(), sizeof(double) * lam.size(), hipMemcpyHostToDevice, s));
-  DPP_HIP(hipMemcpyAsync(dw, wt.data(), sizeof(double) * wt.size(), hipMemcpyHostToDevice, s));
+  double *dout = dp + 4 * (size_t)nb;
   MMS m{mms[0], mms[1], mms[2], mms[3], std::sqrt(mms[2] * (mms[0] + mms[1]) / (mms[0] * mms[1]))};
   if (g.dim == 3)
     k_l2_error<3><<<nb, PBS, 0, s>>>(dev(g), x, m, dl, dw, nq, g.h[0], g.h[1], g.h[2], dp);
@@ -356,6 +361,109 @@ void mms_l2_errors(dpp_problem P, const double *x, const double mms[4], int q, d
   DPP_HIP(hipStreamSynchronize(s));
   // field order of the result: u1, p1, u2, p2
   for (int f = 0; f < 4; ++f) err[f] = std::sqrt(std::max(h4[f], 0.0));
+}
+
+static void check_mms_args(int q, const double mms[4]) {
+  DPP_CHECK(q >= 1 && q <= QMAX, DPP_ERR_ARG, "quadrature order must be in 1..16");
+  DPP_CHECK(mms[0] > 0.0 && mms[1] > 0.0 && mms[2] > 0.0 && mms[3] > 0.0, DPP_ERR_ARG,
+            "manufactured-solution parameters must be positive");
+}
+
+void mms_l2_errors(dpp_problem P, const double *x, const double mms[4], int q, double err[4],
+                   hipStream_t s) {
+  check_mms_args(q, mms);
+  const Grid &g = P->g;
+  std::vector<double> lam, wt;
+  simplex_rule(g.dim, q, lam, wt);
+  const int nq = (int)wt.size();
+  const long ncell = (long)g.nc;
+  const int nb = (int)((ncell + PBS - 1) / PBS);  // one simplex per thread
+  DBuf rule(sizeof(double) * (lam.size() + wt.size()));
+  DBuf part(sizeof(double) * 4 * (size_t)nb + sizeof(double) * 4);
+  double *dl = rule.as<double>(), *dw = dl + lam.size();
+  DPP_HIP(hipMemcpyAsync(dl, lam.data(), sizeof(double) * lam.size(), hipMemcpyHostToDevice, s));
+  DPP_HIP(hipMemcpyAsync(dw, wt.data(), sizeof(double) * wt.size(), hipMemcpyHostToDevice, s));
+  l2_errors_on(P, x, mms, nq, dl, dw, nb, part.as<double>(), err, s);
+}
+
+// ---- the same integral with no allocation: the rule and the partial sums
+// live in one fixed device array per GPU (`scratch`), whose address is taken
+// once per device with hipGetSymbolAddress and used from then on.
+namespace {
+constexpr int NA_BLOCKS = 2048;                              // workgroups (grid-stride)
+constexpr size_t NA_RULE = (size_t)QMAX * QMAX * QMAX * 5;   // lam [q^3][4] + w [q^3]
+constexpr size_t NA_DOUBLES = NA_RULE + 4 * (size_t)NA_BLOCKS + 4;
+static_assert(NA_DOUBLES * sizeof(double) <= NOALLOC_SCRATCH_BYTES, "scratch too small");
+__device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+std::mutex na_mu;
+double *na_ptr[MAX_DEVICES] = {};
+
+// Gauss-Legendre nodes and weights on [0, 1], passed by value
+struct GL01 {
+  double t[QMAX], w[QMAX];
+};
+
+// The conical-product rule of simplex_rule_into, expanded on the device from
+// the one-dimensional nodes (same products in the same order).
+__global__ void k_expand_rule(int dim, int q, GL01 gl, double *__restrict__ lam,
+                              double *__restrict__ wt) {
+  const int nq = dim == 2 ? q * q : q * q * q;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nq) return;
+  if (dim == 2) {
+    const int a = k / q, b = k % q;
+    const double s = gl.t[a], e = gl.t[b];
+    lam[3 * k] = 1.0 - s;
+    lam[3 * k + 1] = s * (1.0 - e);
+    lam[3 * k + 2] = s * e;
+    wt[k] = gl.w[a] * gl.w[b] * s;
+    return;
+  }
+  const int a = k / (q * q), b = (k / q) % q, c = k % q;
+  const double s = gl.t[a], e = gl.t[b], gq = gl.t[c];
+  lam[4 * k] = 1.0 - s;
+  lam[4 * k + 1] = s * (1.0 - e);
+  lam[4 * k + 2] = s * e * (1.0 - gq);
+  lam[4 * k + 3] = s * e * gq;
+  wt[k] = gl.w[a] * gl.w[b] * gl.w[c] * s * s * e;
+}
+
+double *scratch_of_current_device() {
+  int dv = 0;
+  DPP_HIP(hipGetDevice(&dv));
+  DPP_CHECK(dv >= 0 && dv < MAX_DEVICES, DPP_ERR_UNSUPPORTED, "device index beyond the table");
+  std::lock_guard<std::mutex> lk(na_mu);
+  if (!na_ptr[dv]) {
+    void *p = nullptr;
+    DPP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    na_ptr[dv] = static_cast<double *>(p);
+  }
+  return na_ptr[dv];
+}
+}  // namespace
+
+void mms_l2_errors_noalloc(dpp_problem P, const double *x, const double mms[4], int q,
+                           double err[4], hipStream_t s) {
+  check_mms_args(q, mms);
+  const Grid &g = P->g;
+  int nq = 1;
+  for (int a = 0; a < g.dim; ++a) nq *= q;
+  const size_t nl = (size_t)nq * (g.dim + 1);
+  DPP_CHECK(nl + nq <= NA_RULE, DPP_ERR_ARG, "quadrature rule larger than the fixed scratch");
+  const long ncell = (long)g.nc;
+  const int nb = (int)std::min<long>(NA_BLOCKS, (ncell + PBS - 1) / PBS);
+  DPP_CHECK(4 * (size_t)nb + 4 <= NA_DOUBLES - NA_RULE, DPP_ERR_ARG,
+            "partial sums larger than the fixed scratch");
+  double *base = scratch_of_current_device();
+  double *dl = base, *dw = base + nl, *dp = base + NA_RULE;
+  GL01 gl{};
+  gauss_legendre01(q, gl.t, gl.w);
+  k_expand_rule<<<(nq + 255) / 256, 256, 0, s>>>(g.dim, q, gl, dl, dw);
+  check_launch("quadrature rule");
+  // every workgroup writes its partial sums and the finish kernel the result,
+  // so nothing left by an earlier call is read
+  l2_errors_on(P, x, mms, nq, dl, dw, nb, dp, err, s);
 }
 
 }  // namespace dpp
