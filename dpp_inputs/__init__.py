@@ -12,7 +12,9 @@ Numbering spec (both sides implement it independently):
     coordinates (i h_x, j h_y, k h_z), x fastest;
   * 3D cells: hexahedron h = i + n_x(j + n_y k) is split into 6 tetrahedra
     6h+s, s indexing the permutations of the axes in lexicographic order;
-  * 2D cells: square h = i + n_x j is split into triangles 2h and 2h+1.
+  * 2D cells: square h = i + n_x j is split into triangles 2h and 2h+1;
+  * with Q1 elements (elem = "q1") the cells are the boxes themselves: cell h
+    is hexahedron / square h.
 
 Manufactured solutions: Section "Two-dimensional study" and "Three-dimensional
 study" of the paper (the 3D micro-pressure carries mu/(beta k2); the printed
@@ -43,7 +45,8 @@ class Problem:
       face_bc[i, 2a + s] = 1 makes face s (0: x_a = 0, 1: x_a = L_a) a velocity
       boundary of network i, whose normal velocity is prescribed;
     u_bc_1, u_bc_2: nodal velocities [n_nodes, dim] whose normal components are
-      imposed on the velocity faces (None for a network without one).
+      imposed on the velocity faces (None for a network without one);
+    elem: "p1" (Kuhn simplices, P1) or "q1" (box cells, Q1).
     """
     dim: int
     n: tuple
@@ -60,6 +63,7 @@ class Problem:
     face_bc: object = None
     u_bc_1: object = None
     u_bc_2: object = None
+    elem: str = "p1"
 
     @property
     def n_nodes(self):
@@ -67,14 +71,16 @@ class Problem:
 
     @property
     def n_cells(self):
-        return cells_per_box(self.dim) * int(np.prod(self.n))
+        return cells_per_box(self.dim, self.elem) * int(np.prod(self.n))
 
     @property
     def n_dof(self):
         return (2 * self.dim + 2) * self.n_nodes
 
 
-def cells_per_box(dim: int) -> int:
+def cells_per_box(dim: int, elem: str = "p1") -> int:
+    if elem == "q1":
+        return 1
     return 6 if dim == 3 else 2
 
 
@@ -125,24 +131,24 @@ def mms_fields(dim, X, k1, k2, beta, mu):
 
 
 def mms_problem(dim, n, k1=1.0, k2=0.1, beta=1.0, mu=1.0, L=None, bc_params=None,
-                flux_faces=None):
+                flux_faces=None, elem="p1"):
     """Homogeneous manufactured-solution instance: constant k1, k2, beta.
 
     bc_params (k1, k2, beta, mu) overrides the parameters used for the boundary
     pressures (heterogeneous-permeability workloads keep the homogeneous MMS
     boundary data).  flux_faces: None, or [2, 2*dim] face flags (see Problem)
-    whose velocity faces take the exact normal velocities.
+    whose velocity faces take the exact normal velocities.  elem: "p1" or "q1".
     """
     n = tuple(int(v) for v in (n if np.ndim(n) else (n,) * dim))
     L = tuple(L or (1.0,) * dim)
-    nc = cells_per_box(dim) * int(np.prod(n))
+    nc = cells_per_box(dim, elem) * int(np.prod(n))
     X = node_coords(dim, n, L)
     bk1, bk2, bb, bmu = bc_params or (k1, k2, beta, mu)
     p1, p2, u1, u2 = mms_fields(dim, X, bk1, bk2, bb, bmu)
     prob = Problem(dim=dim, n=n, L=L, mu=float(mu),
                    k1=np.full(nc, float(k1)), k2=np.full(nc, float(k2)),
                    beta=float(beta), p0_1=p1, p0_2=p2,
-                   meta=dict(mms=(bk1, bk2, bb, bmu)))
+                   meta=dict(mms=(bk1, bk2, bb, bmu)), elem=elem)
     if flux_faces is not None:
         fb = np.asarray(flux_faces, dtype=np.int8).reshape(2, 2 * dim)
         prob.face_bc = fb
@@ -182,19 +188,20 @@ def grf_log10(n, dim, seed, mean, std, ell=0.1, L=None):
     return mean + std * crop.reshape(-1)
 
 
-def hex_to_cells(values_per_hex, dim):
-    """Give each simplex of a hex/square the value of its hex/square."""
-    return np.repeat(np.asarray(values_per_hex, dtype=np.float64), cells_per_box(dim))
+def hex_to_cells(values_per_hex, dim, elem="p1"):
+    """Give each cell of a hex/square (its simplices, or the box itself with
+    Q1 elements) the value of its hex/square."""
+    return np.repeat(np.asarray(values_per_hex, dtype=np.float64), cells_per_box(dim, elem))
 
 
 def grf_problem(dim, n, seeds=(1001, 1002), means=(0.0, -2.0), std=1.0, ell=0.1,
-                beta=1.0, mu=1.0, bc_params=(1.0, 1e-2, 1.0, 1.0)):
+                beta=1.0, mu=1.0, bc_params=(1.0, 1e-2, 1.0, 1.0), elem="p1"):
     """Log-normal heterogeneous permeabilities, homogeneous-MMS boundary data."""
-    base = mms_problem(dim, n, k1=1.0, k2=1e-2, beta=beta, mu=mu, bc_params=bc_params)
+    base = mms_problem(dim, n, k1=1.0, k2=1e-2, beta=beta, mu=mu, bc_params=bc_params, elem=elem)
     l1 = grf_log10(base.n, dim, seeds[0], means[0], std, ell)
     l2 = grf_log10(base.n, dim, seeds[1], means[1], std, ell)
-    base.k1 = hex_to_cells(10.0 ** l1, dim)
-    base.k2 = hex_to_cells(10.0 ** l2, dim)
+    base.k1 = hex_to_cells(10.0 ** l1, dim, elem)
+    base.k2 = hex_to_cells(10.0 ** l2, dim, elem)
     base.meta.update(grf=dict(seeds=seeds, means=means, std=std, ell=ell))
     return base
 
@@ -239,6 +246,10 @@ CONFIGS = {
     # pure flux: velocity faces everywhere in both networks (singular K)
     "c2p_3d64_pureflux": dict(kind="mms", dim=3, n=64, k1=1.0, k2=1e-2, beta=1.0, mu=1.0,
                               flux_faces=[[1] * 6, [1] * 6]),
+    # Q1 hexahedra (the HEX columns of the 3D study): the 64^3 manufactured
+    # solution and the 96^3 log-normal box on box cells
+    "h2_3d64_q1": dict(kind="mms", dim=3, n=64, k1=1.0, k2=1e-2, beta=1.0, mu=1.0, elem="q1"),
+    "h3_3d96_grf_q1": dict(kind="grf", dim=3, n=96, elem="q1"),
 }
 
 
@@ -247,7 +258,8 @@ def make_config(name, n=None):
     c = CONFIGS[name]
     if c["kind"] == "mms":
         return mms_problem(c["dim"], n or c["n"], k1=c["k1"], k2=c["k2"],
-                           beta=c["beta"], mu=c["mu"], flux_faces=c.get("flux_faces"))
+                           beta=c["beta"], mu=c["mu"], flux_faces=c.get("flux_faces"),
+                           elem=c.get("elem", "p1"))
     if c["kind"] == "grf":
-        return grf_problem(c["dim"], n or c["n"])
+        return grf_problem(c["dim"], n or c["n"], elem=c.get("elem", "p1"))
     raise ValueError("batch workloads are built with batch_configs()")

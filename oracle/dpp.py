@@ -34,7 +34,14 @@ def lib():
         _lib.or_mesh.restype = None
         _lib.or_mesh.argtypes = [C.c_int, P, P, P, P]
         _lib.or_adjacency.restype = None
-        _lib.or_adjacency.argtypes = [C.c_int, C.c_long, C.c_long, P, P, P, P, P]
+        _lib.or_adjacency.argtypes = [C.c_int, C.c_int, C.c_long, C.c_long, P, P, P, P, P]
+        _lib.or_num_cells_q1.restype = C.c_long
+        _lib.or_num_cells_q1.argtypes = [C.c_int, P]
+        _lib.or_mesh_q1.restype = None
+        _lib.or_mesh_q1.argtypes = [C.c_int, P, P, P, P]
+        _lib.or_assemble_q1.restype = None
+        _lib.or_assemble_q1.argtypes = [C.c_int, P, P, C.c_long, P, P, P, P, P, P, P, P, P,
+                                        P, C.c_double, P, P, P]
         _lib.or_rowptr.restype = C.c_int64
         _lib.or_rowptr.argtypes = [C.c_int, C.c_long, P, P]
         _lib.or_cols.restype = None
@@ -64,11 +71,12 @@ class Mesh:
     n: tuple
     L: tuple
     X: np.ndarray        # [N, d]
-    cells: np.ndarray    # [nc, d+1]
+    cells: np.ndarray    # [nc, d+1] simplices, or [nc, 2^d] box cells (Q1)
     incptr: np.ndarray
     inc: np.ndarray
     adjcnt: np.ndarray
     adj: np.ndarray
+    elem: str = "p1"
 
     @property
     def N(self):
@@ -79,23 +87,31 @@ class Mesh:
         return self.cells.shape[0]
 
 
-def mesh(dim, n, L=None):
-    """Structured Kuhn box mesh (spec in the module docstring of dpp_inputs)."""
+def mesh(dim, n, L=None, elem="p1"):
+    """Structured box mesh (spec in the module docstring of dpp_inputs): Kuhn
+    simplices for P1, the box cells themselves for Q1."""
     n = np.ascontiguousarray(n, dtype=np.int32)
     L = np.ascontiguousarray(L if L is not None else [1.0] * dim, dtype=np.float64)
     lb = lib()
     N = lb.or_num_nodes(dim, _p(n))
-    nc = lb.or_num_cells(dim, _p(n))
     X = np.empty((N, dim))
-    cells = np.empty((nc, dim + 1), dtype=np.int32)
-    lb.or_mesh(dim, _p(n), _p(L), _p(X), _p(cells))
+    if elem == "q1":
+        nv = 2 ** dim
+        nc = lb.or_num_cells_q1(dim, _p(n))
+        cells = np.empty((nc, nv), dtype=np.int32)
+        lb.or_mesh_q1(dim, _p(n), _p(L), _p(X), _p(cells))
+    else:
+        nv = dim + 1
+        nc = lb.or_num_cells(dim, _p(n))
+        cells = np.empty((nc, nv), dtype=np.int32)
+        lb.or_mesh(dim, _p(n), _p(L), _p(X), _p(cells))
     incptr = np.empty(N + 1, dtype=np.int64)
-    inc = np.empty(nc * (dim + 1), dtype=np.int32)
+    inc = np.empty(nc * nv, dtype=np.int32)
     adjcnt = np.empty(N, dtype=np.int32)
     adj = np.zeros((N, MAXADJ), dtype=np.int32)
-    lb.or_adjacency(dim, N, nc, _p(cells), _p(incptr), _p(inc), _p(adjcnt), _p(adj))
+    lb.or_adjacency(dim, nv, N, nc, _p(cells), _p(incptr), _p(inc), _p(adjcnt), _p(adj))
     return Mesh(dim, tuple(int(v) for v in n), tuple(float(v) for v in L), X, cells, incptr,
-                inc, adjcnt, adj)
+                inc, adjcnt, adj, elem)
 
 
 @dataclass
@@ -126,11 +142,14 @@ def assemble(prob, msh=None):
 
     Follows eq. S4_cg_stiffness_matrix / eq. S4_cg_rhs; pressure boundary data
     enter weakly through -(w.n; p0) (eq. VMS_classical_mixed_formulation and the
-    linear functional of the appendix CG-VMS listing), with p0 the P1 nodal
-    interpolant integrated exactly on each boundary facet.
+    linear functional of the appendix CG-VMS listing), with p0 the nodal
+    interpolant (P1, or Q1 on box cells) integrated exactly on each boundary
+    facet.  Q1 box cells (prob.elem == "q1") are the [Q1 + Q1]^2 rows of the
+    element table: the same forms, integrated exactly cell by cell.
     """
     d = prob.dim
-    msh = msh or mesh(d, prob.n, prob.L)
+    elem = getattr(prob, "elem", "p1")
+    msh = msh or mesh(d, prob.n, prob.L, elem)
     lb = lib()
     N, nc = msh.N, msh.nc
     ndof = (2 * d + 2) * N
@@ -150,9 +169,17 @@ def assemble(prob, msh=None):
     p01 = np.ascontiguousarray(prob.p0_1, dtype=np.float64)
     p02 = np.ascontiguousarray(prob.p0_2, dtype=np.float64)
     nn = np.ascontiguousarray(msh.n, dtype=np.int32)
-    lb.or_assemble(d, _p(nn), N, nc, _p(msh.X), _p(msh.cells), _p(msh.incptr), _p(msh.inc),
-                   _p(rowptr), _p(cols), _p(vals), _p(f), _p(k1), _p(k2), _p(beta),
-                   float(prob.mu), _p(body) if body is not None else None, _p(p01), _p(p02))
+    if elem == "q1":
+        LL = np.ascontiguousarray(msh.L, dtype=np.float64)
+        lb.or_assemble_q1(d, _p(nn), _p(LL), N, _p(msh.cells), _p(msh.incptr), _p(msh.inc),
+                          _p(rowptr), _p(cols), _p(vals), _p(f), _p(k1), _p(k2), _p(beta),
+                          float(prob.mu), _p(body) if body is not None else None, _p(p01),
+                          _p(p02))
+    else:
+        lb.or_assemble(d, _p(nn), N, nc, _p(msh.X), _p(msh.cells), _p(msh.incptr),
+                       _p(msh.inc), _p(rowptr), _p(cols), _p(vals), _p(f), _p(k1), _p(k2),
+                       _p(beta), float(prob.mu), _p(body) if body is not None else None,
+                       _p(p01), _p(p02))
     K = sp.csr_matrix((vals, cols, rowptr), shape=(ndof, ndof))
     if getattr(prob, "face_bc", None) is not None and np.any(prob.face_bc):
         K, f = velocity_bc(K, f, msh, prob)

@@ -11,6 +11,8 @@ one on the structured box, defined here in plain steps:
     per axis (coarse node C sits at fine index 2C, the last one at n when n is
     odd) -- a fine node with odd indices on the axes in set O lies on the Kuhn
     edge between coarse nodes lo and lo + 1_O and takes the mean of the two;
+    with Q1 box cells, (bi/tri)linear interpolation: the tensor product of the
+    one-dimensional linear interpolation of each axis;
   * coarse operators: Galerkin A_{l+1} = P^T A_l P;
   * coarsest level (at most ``coarse_max`` nodes, or no further coarsening
     possible): exact dense solve;
@@ -73,6 +75,27 @@ def interpolation(dim, n):
     cols = np.concatenate([c0, c1[has]])
     vals = np.concatenate([np.where(has, 0.5, 1.0), np.full(has.sum(), 0.5)])
     return sp.csr_matrix((vals, (rows, cols)), shape=(nf, int(np.prod(mc))))
+
+
+def interpolation_1d(n):
+    """Linear interpolation on one axis (n + 1 fine nodes from the coarse
+    nodes of axis_map): an odd fine node takes the mean of its two coarse
+    neighbours, the others the value of the coarse node at their place."""
+    lo, odd, m = axis_map(n)
+    i = np.arange(n + 1)
+    rows = np.concatenate([i, i[odd == 1]])
+    cols = np.concatenate([lo, lo[odd == 1] + 1])
+    vals = np.concatenate([np.where(odd == 1, 0.5, 1.0), np.full(int(odd.sum()), 0.5)])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n + 1, m))
+
+
+def interpolation_q1(dim, n):
+    """Q1 interpolation (N_fine x N_coarse) on box cells: the Kronecker
+    product of the axes' linear interpolations, x fastest."""
+    P = interpolation_1d(int(n[0]))
+    for a in range(1, dim):
+        P = sp.kron(interpolation_1d(int(n[a])), P)
+    return P.tocsr()
 
 
 def hash_start(size):
@@ -152,8 +175,9 @@ class Hierarchy:
     opts: MGOptions = None
 
 
-def setup(A, dim, n, opts=None):
-    """Build the level list: Galerkin operators, smoother bounds, coarse matrix."""
+def setup(A, dim, n, opts=None, elem="p1"):
+    """Build the level list: Galerkin operators, smoother bounds, coarse matrix
+    (elem "q1": the interpolation of box cells)."""
     opts = opts or MGOptions()
     H = Hierarchy(opts=opts)
     A = A.tocsr()
@@ -170,7 +194,7 @@ def setup(A, dim, n, opts=None):
         lam = power_lambda(A, lev.dinv, opts.power_iters)
         lev.hi = opts.hi_factor * lam
         lev.lo = (opts.lo_frac if opts.lo_frac > 0 else (0.1 if dim == 3 else 0.3)) * lev.hi
-        lev.P = interpolation(dim, n)
+        lev.P = interpolation_q1(dim, n) if elem == "q1" else interpolation(dim, n)
         A = (lev.P.T @ A @ lev.P).tocsr()
         n = nc
     H.coarse_dense = H.levels[-1].A.toarray()

@@ -43,7 +43,8 @@ class FieldSplit:
         if velocity == "exact" or inner == "exact_schur":
             self.Ainv = [np.linalg.inv(self.B["Kuu"][i].toarray()) for i in range(2)]
         if inner == "vcycle":
-            self.H = [mg.setup(self.Sp[i], self.dim, system.mesh.n, mg_opts) for i in range(2)]
+            self.H = [mg.setup(self.Sp[i], self.dim, system.mesh.n, mg_opts, system.mesh.elem)
+                      for i in range(2)]
         elif inner == "exact_selfp":
             self.lu = [spla.splu(self.Sp[i].tocsc()) for i in range(2)]
         elif inner == "exact_schur":
