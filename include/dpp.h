@@ -55,11 +55,19 @@ typedef struct dpp_precond_s *dpp_precond;
 typedef struct dpp_batch_s *dpp_batch;
 
 /* Structured box: dim 2 or 3, 1 <= n[a] <= 4096 cells per axis, L[a] > 0
- * extent; (2 dim + 2) x nodes must stay below 2^31 (DPP_ERR_ARG otherwise). */
+ * extent; (2 dim + 2) x nodes must stay below 2^31 (DPP_ERR_ARG otherwise).
+ * elem selects the element family of the element table (section "Finite
+ * element discretizations", CG-VMS rows): 0 = P1 on the Kuhn simplices (the
+ * numbering above), 1 = Q1 on the box cells themselves (quadrilaterals /
+ * hexahedra; cell h = i + n_x(j + n_y k) is box h, and per-cell arrays have
+ * one entry per box).  With Q1 the solver, mixed precision and velocity
+ * faces are available; the parameter gradient, the L2-error integrals and
+ * batched solves are P1 only (DPP_ERR_UNSUPPORTED). */
 typedef struct {
   int dim;
   int n[3];
   double L[3];
+  int elem;
 } dpp_box;
 
 /* Coefficients and boundary data (section "Boundary conditions"; parameters of

@@ -21,7 +21,10 @@ class DppError(RuntimeError):
 
 
 class _Box(C.Structure):
-    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3)]
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3), ("elem", C.c_int)]
+
+
+ELEM = {"p1": 0, "q1": 1}
 
 
 class _Params(C.Structure):
@@ -196,8 +199,8 @@ class Precond:
 class Problem:
     """An assembled DPP system (handle over dpp_problem)."""
 
-    def __init__(self, handle, dim, n, beta_per_cell=False):
-        self.handle, self.dim, self.n = handle, dim, tuple(n)
+    def __init__(self, handle, dim, n, beta_per_cell=False, elem="p1"):
+        self.handle, self.dim, self.n, self.elem = handle, dim, tuple(n), elem
         self.beta_per_cell = beta_per_cell
         nd, nn, nc, nz = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
         _check(lib().dpp_problem_sizes(handle, C.byref(nd), C.byref(nn), C.byref(nc), C.byref(nz)))
@@ -286,12 +289,14 @@ def simplex_rule(dim, q):
     return np.array(lam[:]).reshape(nq, dim + 1), np.array(w[:])
 
 def assemble(dim, n, k1, k2, p0_1, p0_2, beta=1.0, mu=1.0, L=None, body=None, beta_cells=None,
-             face_bc=None, u_bc_1=None, u_bc_2=None, stream=None):
+             face_bc=None, u_bc_1=None, u_bc_2=None, stream=None, elem="p1"):
     """dpp_assemble on device tensors (float64, contiguous); face_bc is a host
-    int8 array [2, 2*dim] (velocity faces) or None."""
+    int8 array [2, 2*dim] (velocity faces) or None; elem "p1" (Kuhn simplices)
+    or "q1" (box cells)."""
     lib()
     box = _Box()
     box.dim = dim
+    box.elem = ELEM[elem]
     for a in range(3):
         box.n[a] = int(n[a]) if a < dim else 0
         box.L[a] = float(L[a]) if (L is not None and a < dim) else (1.0 if a < dim else 0.0)
@@ -312,7 +317,7 @@ def assemble(dim, n, k1, k2, p0_1, p0_2, beta=1.0, mu=1.0, L=None, body=None, be
     p.u_bc_1, p.u_bc_2 = _ptr(u_bc_1), _ptr(u_bc_2)
     h = C.c_void_p()
     _check(lib().dpp_assemble(C.byref(box), C.byref(p), _stream(stream), C.byref(h)))
-    return Problem(h, dim, n, beta_per_cell=beta_cells is not None)
+    return Problem(h, dim, n, beta_per_cell=beta_cells is not None, elem=elem)
 
 
 def assemble_problem(prob, device="cuda", stream=None):
@@ -330,7 +335,8 @@ def assemble_problem(prob, device="cuda", stream=None):
           for k in ("u_bc_1", "u_bc_2")]
     return assemble(prob.dim, prob.n, dv(prob.k1), dv(prob.k2), dv(prob.p0_1), dv(prob.p0_2),
                     beta=float(beta), mu=prob.mu, L=prob.L, body=body, beta_cells=beta_cells,
-                    face_bc=fb, u_bc_1=ub[0], u_bc_2=ub[1], stream=stream)
+                    face_bc=fb, u_bc_1=ub[0], u_bc_2=ub[1], stream=stream,
+                    elem=getattr(prob, "elem", "p1"))
 
 
 class Batch:
@@ -387,6 +393,7 @@ def assemble_batch(problems, stream=None, **opts):
     dv = lambda a: torch.as_tensor(a, dtype=torch.float64).contiguous().to("cuda")
     for i, pr in enumerate(problems):
         boxes[i].dim = pr.dim
+        boxes[i].elem = ELEM[getattr(pr, "elem", "p1")]
         for a in range(3):
             boxes[i].n[a] = int(pr.n[a]) if a < pr.dim else 0
             boxes[i].L[a] = float(pr.L[a]) if a < pr.dim else 0.0

@@ -414,6 +414,8 @@ dpp_status dpp_assemble_batch(int nb, const dpp_box *boxes, const dpp_params *pa
       for (int i = 0; i < nb; ++i) {
         DPP_CHECK(boxes[i].dim == B->dim, DPP_ERR_ARG, "all instances of a batch share one dimension");
 
+        DPP_CHECK(boxes[i].elem == dpp::ELEM_P1, DPP_ERR_UNSUPPORTED,
+                  "batched instances use P1 simplices");
         auto *P = new dpp_problem_s();
         B->P.push_back(P);
         dpp::assemble_problem(P, &boxes[i], &params[i], S(stream));

@@ -225,6 +225,156 @@ __global__ __launch_bounds__(256) void k_rhs(GridDev g, Coef cf, const double *_
   }
 }
 
+// ---- Q1 elements on box cells (stencil tags 12, 13): the [Q1 + Q1]^2 rows
+// of the element table with the same block entries, integrated exactly.  The
+// integrals over a cell are products of one-dimensional integrals on its
+// edges (length h, phi_0 = 1 - t, phi_1 = t): mass h (1 + delta_ij)/6,
+// stiffness (2 delta_ij - 1)/h, int phi_i' phi_j = i - 1/2, int phi_i = h/2,
+// int phi_i' = 2i - 1.  A node's local coordinate in a cell is one bit per axis.
+__device__ inline double q1_mass1(int i, int j, double h) { return h * (i == j ? 2.0 : 1.0) / 6.0; }
+__device__ inline double q1_stiff1(int i, int j, double h) { return (i == j ? 1.0 : -1.0) / h; }
+
+template <int D>
+__global__ __launch_bounds__(256) void k_assemble_q1(GridDev g, Coef cf, double *__restrict__ kv) {
+  constexpr int d = dim_of(D);
+  constexpr int NS = Tabs<D>::NS;
+  const long N = g.N;
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * NS) return;
+  const int t = (int)(idx / N);
+  const long a = idx - (long)t * N;
+  int ia[3];
+  node_ijk(g, a, ia[0], ia[1], ia[2]);
+  const int *o = TAB<D>.so[t];
+  double uu[2] = {0, 0}, up[2][d], pu[2][d], pp[2] = {0, 0}, k12 = 0.0;
+  for (int q = 0; q < 2; ++q)
+    for (int c = 0; c < d; ++c) up[q][c] = pu[q][c] = 0.0;
+  if (inside(g, ia[0] + o[0], ia[1] + o[1], ia[2] + o[2])) {
+    for (int sb = 0; sb < (1 << d); ++sb) {  // box cells around a, fixed order
+      int cc[3] = {0, 0, 0}, la[3] = {0, 0, 0}, lb[3] = {0, 0, 0};
+      bool ok = true;
+      for (int ax = 0; ax < d; ++ax) {
+        la[ax] = (sb >> ax) & 1;          // a's local coordinate in the cell
+        cc[ax] = ia[ax] - la[ax];
+        lb[ax] = la[ax] + o[ax];          // the neighbour's
+        if (cc[ax] < 0 || cc[ax] >= g.n[ax] || lb[ax] < 0 || lb[ax] > 1) ok = false;
+      }
+      if (!ok) continue;
+      const long e = cc[0] + (long)g.n[0] * (cc[1] + (long)g.n[1] * cc[2]);
+      double m1[3], M = 1.0;
+      for (int ax = 0; ax < d; ++ax) {
+        m1[ax] = q1_mass1(la[ax], lb[ax], cf.h[ax]);
+        M *= m1[ax];
+      }
+      double St = 0.0, cab[d], cba[d];
+      for (int c = 0; c < d; ++c) {
+        double rest = 1.0;
+        for (int x = 0; x < d; ++x)
+          if (x != c) rest *= m1[x];
+        St += q1_stiff1(la[c], lb[c], cf.h[c]) * rest;
+        cab[c] = (la[c] ? 0.5 : -0.5) * rest;   // int (d_c psi_a) psi_b
+        cba[c] = (lb[c] ? 0.5 : -0.5) * rest;   // int psi_a (d_c psi_b)
+      }
+      const double bm = (cf.betac ? cf.betac[e] : cf.beta) / cf.mu;
+      for (int q = 0; q < 2; ++q) {
+        const double kk = q ? cf.k2[e] : cf.k1[e];
+        uu[q] += 0.5 * (cf.mu / kk) * M;                 // 1/2 (w; mu/k u)
+        for (int c = 0; c < d; ++c) {
+          up[q][c] += -cab[c] - 0.5 * cba[c];            // -(div w;p) - 1/2 (w;grad p)
+          pu[q][c] += cba[c] + 0.5 * cab[c];             // (q;div u) + 1/2 (grad q;u)
+        }
+        pp[q] += 0.5 * (kk / cf.mu) * St + bm * M;       // 1/2 (grad q;k/mu grad p) + (q;beta/mu p)
+      }
+      k12 += -bm * M;                                    // -(q1; beta/mu p2)
+    }
+  }
+  const size_t vs = (size_t)NS * g.ld;
+  double *base = kv + (size_t)t * g.ld + a;
+  for (int q = 0; q < 2; ++q) {
+    base[kv_uu(d, q) * vs] = uu[q];
+    for (int c = 0; c < d; ++c) {
+      base[kv_up(d, q, c) * vs] = up[q][c];
+      base[kv_pu(d, q, c) * vs] = pu[q][c];
+    }
+    base[kv_pp(d, q) * vs] = pp[q];
+  }
+  base[kv_12(d) * vs] = k12;
+}
+
+// Right-hand side with Q1 box cells, one thread per node: body-force terms
+// 1/2 (w; gamma b) and 1/2 (grad q; k/mu gamma b) over the cells around the
+// node, and -(w.n; p0) over the cell faces on the box boundary that hold it
+// (p0 by its Q1 interpolant on the face: the face mass of the other axes).
+template <int D>
+__global__ __launch_bounds__(256) void k_rhs_q1(GridDev g, Coef cf, const double *__restrict__ body,
+                                                const double *__restrict__ p01,
+                                                const double *__restrict__ p02,
+                                                double *__restrict__ f) {
+  constexpr int d = dim_of(D);
+  const long N = g.N;
+  long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  int ia[3];
+  node_ijk(g, a, ia[0], ia[1], ia[2]);
+  double fu[2][d], fp[2] = {0, 0};
+  for (int q = 0; q < 2; ++q)
+    for (int c = 0; c < d; ++c) fu[q][c] = 0.0;
+  const long stride[3] = {1, (long)g.m[0], (long)g.m[0] * g.m[1]};
+  double mean = 1.0;  // int psi_a over a cell
+  for (int ax = 0; ax < d; ++ax) mean *= 0.5 * cf.h[ax];
+  for (int sb = 0; sb < (1 << d); ++sb) {
+    int cc[3] = {0, 0, 0}, la[3] = {0, 0, 0};
+    bool ok = true;
+    for (int ax = 0; ax < d; ++ax) {
+      la[ax] = (sb >> ax) & 1;
+      cc[ax] = ia[ax] - la[ax];
+      if (cc[ax] < 0 || cc[ax] >= g.n[ax]) ok = false;
+    }
+    if (!ok) continue;
+    const long e = cc[0] + (long)g.n[0] * (cc[1] + (long)g.n[1] * cc[2]);
+    if (body) {
+      for (int q = 0; q < 2; ++q) {
+        const double kk = q ? cf.k2[e] : cf.k1[e];
+        double acc = 0.0;
+        for (int c = 0; c < d; ++c) {
+          const double gb = body[e * d + c];
+          fu[q][c] += 0.5 * gb * mean;                   // (w;gb) - 1/2 (mu/k w; k/mu gb)
+          double dm = la[c] ? 1.0 : -1.0;                // int d_c psi_a
+          for (int x = 0; x < d; ++x)
+            if (x != c) dm *= 0.5 * cf.h[x];
+          acc += dm * gb;
+        }
+        fp[q] += 0.5 * (kk / cf.mu) * acc;               // 1/2 (grad q; k/mu gb)
+      }
+    }
+    const long corner = a - la[0] * stride[0] - la[1] * stride[1] - la[2] * stride[2];
+    for (int ax = 0; ax < d; ++ax) {
+      const int side = la[ax];
+      if (cc[ax] != (side ? g.n[ax] - 1 : 0)) continue;  // face not on the box boundary
+      const double nrm = side ? 1.0 : -1.0;
+      double s1 = 0.0, s2 = 0.0;
+      for (int vb = 0; vb < (1 << d); ++vb) {
+        if (((vb >> ax) & 1) != side) continue;          // vertices of that face
+        double w = 1.0;
+        long b = corner;
+        for (int x = 0; x < d; ++x) {
+          const int lbx = (vb >> x) & 1;
+          b += lbx * stride[x];
+          if (x != ax) w *= q1_mass1(la[x], lbx, cf.h[x]);
+        }
+        s1 += w * p01[b];
+        s2 += w * p02[b];
+      }
+      fu[0][ax] -= nrm * s1;
+      fu[1][ax] -= nrm * s2;
+    }
+  }
+  for (int q = 0; q < 2; ++q) {
+    for (int c = 0; c < d; ++c) f[off_u(d, N, q) + (long)d * a + c] = fu[q][c];
+    f[off_p(d, N, q) + a] = fp[q];
+  }
+}
+
 // Velocity faces (section "Boundary conditions", eq. DG_GE_vBC): the
 // prescribed normal velocities are essential conditions (w.n = 0 in the test
 // space), imposed by elimination.  k_lift moves the known values out of the
@@ -234,6 +384,7 @@ __global__ __launch_bounds__(256) void k_rhs(GridDev g, Coef cf, const double *_
 template <int D>
 __global__ void k_lift(GridDev g, const double *__restrict__ kv, const double *__restrict__ ub1,
                        const double *__restrict__ ub2, double *__restrict__ f) {
+  constexpr int d = dim_of(D);
   constexpr int NS = Tabs<D>::NS;
   const long N = g.N;
   const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -244,22 +395,22 @@ __global__ void k_lift(GridDev g, const double *__restrict__ kv, const double *_
   for (int q = 0; q < 2; ++q) {
     if (!g.fix[q]) continue;
     const double *ub = q ? ub2 : ub1;
-    const long ou = off_u(D, N, q), op = off_p(D, N, q);
+    const long ou = off_u(d, N, q), op = off_p(d, N, q);
     double fp = 0.0, fu[3] = {0.0, 0.0, 0.0};
     for (int t = 0; t < NS; ++t) {
       const int *o = TAB<D>.so[t];
       const int ib[3] = {ia[0] + o[0], ia[1] + o[1], ia[2] + o[2]};
       if (!inside(g, ib[0], ib[1], ib[2])) continue;
       const long b = a + lin(g, o[0], o[1], o[2]);
-      for (int c = 0; c < D; ++c) {
+      for (int c = 0; c < d; ++c) {
         if (!u_fixed(g, q, c, ib)) continue;
-        const double gv = ub[(long)D * b + c];
-        fu[c] += kv[kv_uu(D, q) * vs + (size_t)t * g.ld + a] * gv;
-        fp += kv[kv_pu(D, q, c) * vs + (size_t)t * g.ld + a] * gv;
+        const double gv = ub[(long)d * b + c];
+        fu[c] += kv[kv_uu(d, q) * vs + (size_t)t * g.ld + a] * gv;
+        fp += kv[kv_pu(d, q, c) * vs + (size_t)t * g.ld + a] * gv;
       }
     }
-    for (int c = 0; c < D; ++c)
-      f[ou + D * a + c] = u_fixed(g, q, c, ia) ? ub[(long)D * a + c] : f[ou + D * a + c] - fu[c];
+    for (int c = 0; c < d; ++c)
+      f[ou + d * a + c] = u_fixed(g, q, c, ia) ? ub[(long)d * a + c] : f[ou + d * a + c] - fu[c];
     f[op + a] -= fp;
   }
 }
@@ -271,6 +422,7 @@ __global__ void k_lift(GridDev g, const double *__restrict__ kv, const double *_
 // component); the kernels that apply it mask the prescribed components.
 template <int D>
 __global__ void k_mask_bc(GridDev g, double *__restrict__ kv) {
+  constexpr int d = dim_of(D);
   constexpr int NS = Tabs<D>::NS;
   const long N = g.N;
   const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -283,9 +435,9 @@ __global__ void k_mask_bc(GridDev g, double *__restrict__ kv) {
     for (int t = 0; t < NS; ++t) {
       const int *o = TAB<D>.so[t];
       const int ib[3] = {ia[0] + o[0], ia[1] + o[1], ia[2] + o[2]};
-      for (int c = 0; c < D; ++c) {
-        if (u_fixed(g, q, c, ia)) kv[kv_up(D, q, c) * vs + (size_t)t * g.ld + a] = 0.0;
-        if (u_fixed(g, q, c, ib)) kv[kv_pu(D, q, c) * vs + (size_t)t * g.ld + a] = 0.0;
+      for (int c = 0; c < d; ++c) {
+        if (u_fixed(g, q, c, ia)) kv[kv_up(d, q, c) * vs + (size_t)t * g.ld + a] = 0.0;
+        if (u_fixed(g, q, c, ib)) kv[kv_pu(d, q, c) * vs + (size_t)t * g.ld + a] = 0.0;
       }
     }
   }
@@ -297,6 +449,7 @@ __global__ void k_mask_bc(GridDev g, double *__restrict__ kv) {
 template <int D>
 __global__ void k_export(GridDev g, const double *__restrict__ kv, const int64_t *__restrict__ rowptr,
                          int32_t *__restrict__ cols, double *__restrict__ vals) {
+  constexpr int d = dim_of(D);
   constexpr int NS = Tabs<D>::NS;
   const long N = g.N;
   long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -312,8 +465,8 @@ __global__ void k_export(GridDev g, const double *__restrict__ kv, const int64_t
     return true;
   };
   for (int q = 0; q < 2; ++q) {
-    for (int c = 0; c < D; ++c) {
-      long row = off_u(D, N, q) + (long)D * a + c;
+    for (int c = 0; c < d; ++c) {
+      long row = off_u(d, N, q) + (long)d * a + c;
       int64_t w = rowptr[row];
       long b;
       const bool fixed_row = u_fixed(g, q, c, ia);
@@ -321,32 +474,32 @@ __global__ void k_export(GridDev g, const double *__restrict__ kv, const int64_t
         if (nb(t, b)) {
           const int *o = TAB<D>.so[t];
           const int ib[3] = {ia[0] + o[0], ia[1] + o[1], ia[2] + o[2]};
-          double v = val(kv_uu(D, q), t);
+          double v = val(kv_uu(d, q), t);
           if (fixed_row) v = (b == a) ? 1.0 : 0.0;
           else if (u_fixed(g, q, c, ib)) v = 0.0;
-          cols[w] = (int32_t)(off_u(D, N, q) + D * b + c);
+          cols[w] = (int32_t)(off_u(d, N, q) + d * b + c);
           vals[w++] = v;
         }
       for (int t = 0; t < NS; ++t)
-        if (nb(t, b)) { cols[w] = (int32_t)(off_p(D, N, q) + b); vals[w++] = val(kv_up(D, q, c), t); }
+        if (nb(t, b)) { cols[w] = (int32_t)(off_p(d, N, q) + b); vals[w++] = val(kv_up(d, q, c), t); }
     }
-    long row = off_p(D, N, q) + a;
+    long row = off_p(d, N, q) + a;
     int64_t w = rowptr[row];
     long b;
     if (q == 1)
       for (int t = 0; t < NS; ++t)
-        if (nb(t, b)) { cols[w] = (int32_t)(off_p(D, N, 0) + b); vals[w++] = val(kv_12(D), t); }
+        if (nb(t, b)) { cols[w] = (int32_t)(off_p(d, N, 0) + b); vals[w++] = val(kv_12(d), t); }
     for (int t = 0; t < NS; ++t)
       if (nb(t, b))
-        for (int c = 0; c < D; ++c) {
-          cols[w] = (int32_t)(off_u(D, N, q) + D * b + c);
-          vals[w++] = val(kv_pu(D, q, c), t);
+        for (int c = 0; c < d; ++c) {
+          cols[w] = (int32_t)(off_u(d, N, q) + d * b + c);
+          vals[w++] = val(kv_pu(d, q, c), t);
         }
     for (int t = 0; t < NS; ++t)
-      if (nb(t, b)) { cols[w] = (int32_t)(off_p(D, N, q) + b); vals[w++] = val(kv_pp(D, q), t); }
+      if (nb(t, b)) { cols[w] = (int32_t)(off_p(d, N, q) + b); vals[w++] = val(kv_pp(d, q), t); }
     if (q == 0)
       for (int t = 0; t < NS; ++t)
-        if (nb(t, b)) { cols[w] = (int32_t)(off_p(D, N, 1) + b); vals[w++] = val(kv_12(D), t); }
+        if (nb(t, b)) { cols[w] = (int32_t)(off_p(d, N, 1) + b); vals[w++] = val(kv_12(d), t); }
   }
 }
 
@@ -385,10 +538,7 @@ long count_nnz(const Grid &g) {
     for (int ax = 0; ax < g.dim; ++ax) c *= (g.m[ax] - std::abs(o[ax]));
     return c;
   };
-  if (g.dim == 3)
-    for (int t = 0; t < Tabs<3>::NS; ++t) pairs += count(TAB<3>.so[t]);
-  else
-    for (int t = 0; t < Tabs<2>::NS; ++t) pairs += count(TAB<2>.so[t]);
+  DPP_TAG_SWITCH(g, (({ for (int t = 0; t < Tabs<D_>::NS; ++t) pairs += count(TAB<D_>.so[t]); })));
   return pairs * (g.dim == 3 ? 22 : 16);
 }
 
@@ -426,18 +576,21 @@ static void check_input(const double *p, long n, CheckKind kind, const char *nam
 void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, hipStream_t s) {
   DPP_CHECK(box && prm, DPP_ERR_ARG, "null box or params");
   DPP_CHECK(box->dim == 2 || box->dim == 3, DPP_ERR_ARG, "dim must be 2 or 3");
+  DPP_CHECK(box->elem == ELEM_P1 || box->elem == ELEM_Q1, DPP_ERR_ARG,
+            "elem must be 0 (P1 simplices) or 1 (Q1 box cells)");
   for (int a = 0; a < box->dim; ++a) {
     DPP_CHECK(box->n[a] >= 1 && box->n[a] <= 4096, DPP_ERR_ARG, "cells per axis must be in 1..4096");
     DPP_CHECK(box->L[a] > 0.0, DPP_ERR_ARG, "box extent must be positive");
   }
   DPP_CHECK(prm->k1 && prm->k2 && prm->p0_1 && prm->p0_2, DPP_ERR_ARG, "null coefficient array");
   DPP_CHECK(prm->mu > 0.0, DPP_ERR_ARG, "mu must be positive");
-  Grid g = make_grid(box->dim, box->n, box->L);
+  Grid g = make_grid(box->dim, box->n, box->L, box->elem);
   const int D = g.dim;
   // the stencil kernels index nodes and unknowns with 32-bit integers
   DPP_CHECK((2L * D + 2L) * g.N <= 2147483647L, DPP_ERR_ARG,
             "box too large: (2 dim + 2) x nodes must stay below 2^31");
-  const int NS = (D == 3) ? Tabs<3>::NS : Tabs<2>::NS;
+  int NS = 0;
+  DPP_TAG_SWITCH(g, (NS = Tabs<D_>::NS));
   DPP_CHECK((double)g.N * (2 * D + 2) < 2.0e9, DPP_ERR_ARG, "problem too large for 32-bit indices");
   check_input(prm->k1, g.nc, POSITIVE, "k1", s);
   check_input(prm->k2, g.nc, POSITIVE, "k2", s);
@@ -489,28 +642,33 @@ void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, 
           {g.h[0], g.h[1], g.h[2]}};
   GridDev gd = dev(g);
   long work = g.N * NS;
-  if (D == 3) {
-    k_assemble<3><<<blocks_for(work, 256), 256, 0, s>>>(gd, cf, P->kvals.as<double>());
-    k_rhs<3><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, cf, prm->body, prm->p0_1, prm->p0_2,
-                                                 P->f.as<double>());
-  } else {
-    k_assemble<2><<<blocks_for(work, 256), 256, 0, s>>>(gd, cf, P->kvals.as<double>());
-    k_rhs<2><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, cf, prm->body, prm->p0_1, prm->p0_2,
-                                                 P->f.as<double>());
+  const int wb = blocks_for(work, 256), nbk = blocks_for(g.N, 256);
+  double *kv = P->kvals.as<double>(), *fv = P->f.as<double>();
+  switch (g.elem == ELEM_Q1 ? 10 + D : D) {
+    case 3:
+      k_assemble<3><<<wb, 256, 0, s>>>(gd, cf, kv);
+      k_rhs<3><<<nbk, 256, 0, s>>>(gd, cf, prm->body, prm->p0_1, prm->p0_2, fv);
+      break;
+    case 2:
+      k_assemble<2><<<wb, 256, 0, s>>>(gd, cf, kv);
+      k_rhs<2><<<nbk, 256, 0, s>>>(gd, cf, prm->body, prm->p0_1, prm->p0_2, fv);
+      break;
+    case 13:
+      k_assemble_q1<13><<<wb, 256, 0, s>>>(gd, cf, kv);
+      k_rhs_q1<13><<<nbk, 256, 0, s>>>(gd, cf, prm->body, prm->p0_1, prm->p0_2, fv);
+      break;
+    default:
+      k_assemble_q1<12><<<wb, 256, 0, s>>>(gd, cf, kv);
+      k_rhs_q1<12><<<nbk, 256, 0, s>>>(gd, cf, prm->body, prm->p0_1, prm->p0_2, fv);
+      break;
   }
   check_launch("assemble");
   make_up_table(P, s);
   if (g.fix[0] | g.fix[1]) {
     // essential normal velocities: lift with the full K, then mask its couplings
-    if (D == 3) {
-      k_lift<3><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, P->kvals.as<double>(), prm->u_bc_1,
-                                                    prm->u_bc_2, P->f.as<double>());
-      k_mask_bc<3><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, P->kvals.as<double>());
-    } else {
-      k_lift<2><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, P->kvals.as<double>(), prm->u_bc_1,
-                                                    prm->u_bc_2, P->f.as<double>());
-      k_mask_bc<2><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, P->kvals.as<double>());
-    }
+    DPP_TAG_SWITCH(g, (k_lift<D_><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, P->kvals.as<double>(), prm->u_bc_1,
+                                                                    prm->u_bc_2, P->f.as<double>())));
+    DPP_TAG_SWITCH(g, (k_mask_bc<D_><<<blocks_for(g.N, 256), 256, 0, s>>>(gd, P->kvals.as<double>())));
     check_launch("velocity boundaries");
   }
   make_dinv(P, s);
@@ -523,7 +681,7 @@ void export_csr(dpp_problem P, int64_t *rowptr, int32_t *cols, double *vals, hip
   const long N = g.N, nd = P->ndof();
   std::vector<int64_t> rp(nd + 1, 0);
   std::vector<int> m(N);
-  for (long a = 0; a < N; ++a) m[a] = (D == 3) ? count_neighbours_host<3>(g, a) : count_neighbours_host<2>(g, a);
+  DPP_TAG_SWITCH(g, (({ for (long a = 0; a < N; ++a) m[a] = count_neighbours_host<D_>(g, a); })));
   long row = 0;
   for (int q = 0; q < 2; ++q) {
     for (long a = 0; a < N; ++a)
@@ -533,10 +691,8 @@ void export_csr(dpp_problem P, int64_t *rowptr, int32_t *cols, double *vals, hip
   DPP_CHECK(rp[nd] == P->nnz, DPP_ERR_HIP, "internal: CSR size mismatch");
   DPP_HIP(hipMemcpyAsync(rowptr, rp.data(), sizeof(int64_t) * (nd + 1), hipMemcpyHostToDevice, s));
   GridDev gd = dev(g);
-  if (D == 3)
-    k_export<3><<<blocks_for(N, 256), 256, 0, s>>>(gd, P->kvals.as<double>(), rowptr, cols, vals);
-  else
-    k_export<2><<<blocks_for(N, 256), 256, 0, s>>>(gd, P->kvals.as<double>(), rowptr, cols, vals);
+  DPP_TAG_SWITCH(g, (k_export<D_><<<blocks_for(N, 256), 256, 0, s>>>(gd, P->kvals.as<double>(), rowptr,
+                                                                   cols, vals)));
   check_launch("export_csr");
   DPP_HIP(hipStreamSynchronize(s));
 }

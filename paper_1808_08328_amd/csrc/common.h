@@ -20,6 +20,14 @@ constexpr int MAX_DEVICES = 64;
 
 namespace dpp {
 
+// Template tag of the stencil code: D = 2, 3 for the Kuhn simplices with P1
+// elements, D = 12, 13 for box cells (quadrilaterals, hexahedra) with Q1
+// elements -- the [P1 + P1]^2 and [Q1 + Q1]^2 rows of the paper's element
+// table for CG-VMS.  dim_of(D) is the spatial dimension.
+__host__ __device__ constexpr int dim_of(int D) { return D % 10; }
+__host__ __device__ constexpr bool is_q1(int D) { return D >= 10; }
+enum Elem { ELEM_P1 = 0, ELEM_Q1 = 1 };
+
 struct Error : std::runtime_error {
   dpp_status status;
   Error(dpp_status s, const std::string &m) : std::runtime_error(m), status(s) {}
@@ -48,21 +56,23 @@ inline void check_launch(const char *what) {
 // n = 0, m = 1).
 struct Grid {
   int dim = 3;
+  int elem = ELEM_P1;  // element family (ELEM_P1: Kuhn simplices, ELEM_Q1: box cells)
   int n[3] = {1, 1, 0};
   int m[3] = {2, 2, 1};
   double h[3] = {1, 1, 1};
   long N = 0;   // nodes
-  long nc = 0;  // simplices
+  long nc = 0;  // cells (simplices, or boxes with Q1)
   // velocity (flux) faces of network q: bit 2a + s set when face s (0: x_a = 0,
   // 1: x_a = L_a) prescribes the normal velocity (finest grid only)
   int fix[2] = {0, 0};
 };
 
-inline Grid make_grid(int dim, const int *n, const double *L) {
+inline Grid make_grid(int dim, const int *n, const double *L, int elem = ELEM_P1) {
   Grid g;
   g.dim = dim;
+  g.elem = elem;
   g.N = 1;
-  g.nc = (dim == 3) ? 6 : 2;
+  g.nc = elem == ELEM_Q1 ? 1 : (dim == 3) ? 6 : 2;
   for (int a = 0; a < 3; ++a) {
     if (a < dim) {
       g.n[a] = n[a];
@@ -120,16 +130,18 @@ __host__ __device__ inline bool u_fixed(const GridDev &g, int q, int c, const in
 // Boundary class of a node: per axis 0 (first node), 1 (interior) or 2 (last
 // node); class = cx + 3 cy (+ 9 cz).
 __host__ __device__ inline int axis_class(int i, int n) { return i == 0 ? 0 : (i == n ? 2 : 1); }
-// K couples node a with node a + o for o in the Kuhn node stencil St: 0 and
-// +-every nonzero binary vector (15 offsets in 3D, 7 in 2D).  The pressure
-// operators (selfp Schur blocks and every Galerkin coarse level) share the
-// stencil T = St - St (65 offsets in 3D, 19 in 2D, components in [-2, 2]).
-// Both lists are ordered by (dz, dy, dx), i.e. by linear node offset, so valid
-// neighbours of a node come out in ascending node id.
+// K couples node a with node a + o for o in the node stencil St.  With P1 on
+// the Kuhn simplices: 0 and +-every nonzero binary vector (15 offsets in 3D, 7
+// in 2D); with Q1 on box cells: the full 3 x 3 (x 3) box of offsets (27, 9).
+// The pressure operators (selfp Schur blocks and every Galerkin coarse level)
+// share the stencil T = St - St (components in [-2, 2]: 65 and 19 offsets for
+// P1, the full 5 x 5 (x 5) box, 125 and 25, for Q1).  Both lists are ordered
+// by (dz, dy, dx), i.e. by linear node offset, so valid neighbours of a node
+// come out in ascending node id.
 template <int D>
 struct Tabs {
-  static constexpr int NS = D == 3 ? 15 : 7;
-  static constexpr int NT = D == 3 ? 65 : 19;
+  static constexpr int NS = is_q1(D) ? (dim_of(D) == 3 ? 27 : 9) : (dim_of(D) == 3 ? 15 : 7);
+  static constexpr int NT = is_q1(D) ? (dim_of(D) == 3 ? 125 : 25) : (dim_of(D) == 3 ? 65 : 19);
   int so[NS][3];
   int to[NT][3];
   int sidx[27];   // (dx+1) + 3(dy+1) + 9(dz+1) -> index in St or -1
@@ -144,17 +156,24 @@ constexpr bool in_st(int dx, int dy, int dz) {
   return pos || neg;
 }
 
+// membership of St for the element family of tag D
+template <int D>
+constexpr bool st_member(int dx, int dy, int dz) {
+  const bool box = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+  return (is_q1(D) ? box : in_st(dx, dy, dz)) && (dim_of(D) == 3 || dz == 0);
+}
+
 template <int D>
 constexpr Tabs<D> make_tabs() {
   Tabs<D> t{};
-  const int zr = (D == 3) ? 1 : 0;
+  const int zr = (dim_of(D) == 3) ? 1 : 0;
   int k = 0;
   for (int i = 0; i < 27; ++i) t.sidx[i] = -1;
   for (int i = 0; i < 125; ++i) t.tidx[i] = -1;
   for (int dz = -zr; dz <= zr; ++dz)
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx)
-        if (in_st(dx, dy, dz)) {
+        if (st_member<D>(dx, dy, dz)) {
           t.so[k][0] = dx;
           t.so[k][1] = dy;
           t.so[k][2] = dz;
@@ -163,7 +182,7 @@ constexpr Tabs<D> make_tabs() {
           ++k;
         }
   int q = 0;
-  const int z2 = (D == 3) ? 2 : 0;
+  const int z2 = (dim_of(D) == 3) ? 2 : 0;
   for (int dz = -z2; dz <= z2; ++dz)
     for (int dy = -2; dy <= 2; ++dy)
       for (int dx = -2; dx <= 2; ++dx) {
@@ -171,7 +190,7 @@ constexpr Tabs<D> make_tabs() {
         for (int s = 0; s < Tabs<D>::NS; ++s) {
           int ex = dx + t.so[s][0], ey = dy + t.so[s][1], ez = dz + t.so[s][2];
           // t = s1 - s2 with s1 = t + s2 in St
-          if (in_st(ex, ey, ez) && (D == 3 || ez == 0)) any = true;
+          if (st_member<D>(ex, ey, ez)) any = true;
         }
         if (any) {
           t.to[q][0] = dx;
@@ -218,7 +237,7 @@ __host__ __device__ constexpr int kv_12(int dim) { return 4 * dim + 4; }
 // each other and share one address register.
 template <int D>
 struct KH {
-  static constexpr int NS = D == 3 ? 15 : 7;
+  static constexpr int NS = Tabs<D>::NS;
   static constexpr int S0 = (NS - 1) / 2;
   static constexpr int NH = NS - S0;
   static constexpr int NSYM = 5;
@@ -246,10 +265,11 @@ struct KH {
 // order).  UPT<D> lays the table out as [class][t][c].
 template <int D>
 struct UPT {
-  static constexpr int NS = D == 3 ? 15 : 7;
-  static constexpr int NCLS = D == 3 ? 27 : 9;
-  static constexpr int size = NCLS * NS * D;
-  __host__ __device__ static constexpr int at(int cls, int t, int c) { return (cls * NS + t) * D + c; }
+  static constexpr int d = dim_of(D);
+  static constexpr int NS = Tabs<D>::NS;
+  static constexpr int NCLS = d == 3 ? 27 : 9;
+  static constexpr int size = NCLS * NS * d;
+  __host__ __device__ static constexpr int at(int cls, int t, int c) { return (cls * NS + t) * d + c; }
 };
 
 template <int D>
@@ -259,7 +279,8 @@ constexpr bool kh_layout_ok() {
       if (TAB<D>.so[KH<D>::NS - 1 - t][a] != -TAB<D>.so[t][a]) return false;
   return TAB<D>.s0 == KH<D>::S0 && Tabs<D>::NS == KH<D>::NS;
 }
-static_assert(kh_layout_ok<2>() && kh_layout_ok<3>(), "St must be symmetric and sorted");
+static_assert(kh_layout_ok<2>() && kh_layout_ok<3>() && kh_layout_ok<12>() && kh_layout_ok<13>(),
+              "St must be symmetric and sorted");
 
 template <int D>
 constexpr bool kh_streams_bijective() {
@@ -271,7 +292,9 @@ constexpr bool kh_streams_bijective() {
     if (seen[s] != 1) return false;
   return true;
 }
-static_assert(kh_streams_bijective<2>() && kh_streams_bijective<3>(), "kh streams must be a bijection");
+static_assert(kh_streams_bijective<2>() && kh_streams_bijective<3>() && kh_streams_bijective<12>() &&
+                  kh_streams_bijective<13>(),
+              "kh streams must be a bijection");
 
 // Field offsets of the ABI vector layout [u1 | p1 | u2 | p2].
 __host__ __device__ inline long off_u(int dim, long N, int net) {
@@ -301,7 +324,7 @@ __device__ inline long lin(const GridDev &g, int dx, int dy, int dz) {
 template <int D>
 __device__ inline int node_class(const GridDev &g, int i, int j, int k) {
   const int c = axis_class(i, g.n[0]) + 3 * axis_class(j, g.n[1]);
-  return D == 3 ? c + 9 * axis_class(k, g.n[2]) : c;
+  return dim_of(D) == 3 ? c + 9 * axis_class(k, g.n[2]) : c;
 }
 
 // --------------------------------------------------------- XCD mapping ----
@@ -318,6 +341,18 @@ __device__ inline int xcd_block(int bid, int nblk) {
 }
 
 inline int blocks_for(long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// Runs KCALL with `constexpr int D_` set to the stencil tag of grid g (its
+// dimension, plus 10 for Q1 box cells).
+#define DPP_TAG_SWITCH(g, KCALL)                                        \
+  do {                                                                  \
+    switch (((g).elem == ::dpp::ELEM_Q1 ? 10 : 0) + (g).dim) {          \
+      case 2: { constexpr int D_ = 2; KCALL; } break;                   \
+      case 3: { constexpr int D_ = 3; KCALL; } break;                   \
+      case 12: { constexpr int D_ = 12; KCALL; } break;                 \
+      default: { constexpr int D_ = 13; KCALL; } break;                 \
+    }                                                                   \
+  } while (0)
 
 // Column order of workgroups over node blocks [j*bs, (j+1)*bs), j < ceil(N/bs):
 // returns order[i] = the node block of workgroup i.  MI355X deals consecutive

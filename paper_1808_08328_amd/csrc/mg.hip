@@ -264,15 +264,31 @@ __global__ __launch_bounds__(256) void k_prolong(GridDev gf, GridDev gc, const T
 template <int D>
 __device__ inline int fine_support(const GridDev &gf, const GridDev &gc, const int *cc, int fs[][3],
                                    double *w) {
+  if constexpr (is_q1(D)) {
+    // box cells: the tensor product of the axes' supports (at most 27 nodes)
+    int f[3][3], k[3];
+    double wa[3][3];
+    for (int ax = 0; ax < 3; ++ax) k[ax] = axis_support(cc[ax], gf.n[ax], gc.m[ax], f[ax], wa[ax]);
+    int n = 0;
+    for (int z = 0; z < k[2]; ++z)
+      for (int y = 0; y < k[1]; ++y)
+        for (int x = 0; x < k[0]; ++x, ++n) {
+          fs[n][0] = f[0][x];
+          fs[n][1] = f[1][y];
+          fs[n][2] = f[2][z];
+          w[n] = wa[0][x] * wa[1][y] * wa[2][z];
+        }
+    return n;
+  }
   int ex[3];
   for (int ax = 0; ax < 3; ++ax) ex[ax] = exact_fine(cc[ax], gf.n[ax], gc.m[ax]);
   int k = 0;
   for (int ax = 0; ax < 3; ++ax) fs[0][ax] = ex[ax];
   w[k++] = 1.0;
-  for (int mask = 1; mask < (1 << D); ++mask) {
+  for (int mask = 1; mask < (1 << dim_of(D)); ++mask) {
     int fu[3] = {ex[0], ex[1], ex[2]}, fd[3] = {ex[0], ex[1], ex[2]};
     bool uok = true, dok = true;
-    for (int ax = 0; ax < D; ++ax) {
+    for (int ax = 0; ax < dim_of(D); ++ax) {
       if (!((mask >> ax) & 1)) continue;
       fu[ax] = 2 * cc[ax] + 1;
       fd[ax] = 2 * cc[ax] - 1;
@@ -617,7 +633,7 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
     Grid gc = coarse_grid(gl);
     // coarsest size: given, or by dimension (in 2D the dense coarse inverses of
     // ~1000-node levels cost more than one more cheap level)
-    const long cmax = o.coarse_max > 0 ? o.coarse_max : (D == 3 ? 1000 : 400);
+    const long cmax = o.coarse_max > 0 ? o.coarse_max : (dim_of(D) == 3 ? 1000 : 400);
     const bool last = gl.N <= cmax || gc.N == gl.N || (int)pc->lv.size() >= 16;
     if (last) break;
     // Chebyshev bounds from normalised power steps on D^-1 A; the norms stay
@@ -645,7 +661,7 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
                 "multigrid eigenvalue estimate failed");
       L.hi[q] = o.cheb_hi_factor * lam[q];
       // lower end of the interval: given, or by dimension (0.1 in 3D, 0.3 in 2D)
-      const double lof = o.cheb_lo_frac > 0.0 ? o.cheb_lo_frac : (D == 3 ? 0.1 : 0.3);
+      const double lof = o.cheb_lo_frac > 0.0 ? o.cheb_lo_frac : (dim_of(D) == 3 ? 0.1 : 0.3);
       L.lo[q] = lof * L.hi[q];
     }
     auto C = std::make_unique<Level>();
@@ -825,10 +841,7 @@ void vcyc(dpp_precond pc, int l, const TX *b, TX *xout, hipStream_t s, bool firs
 }  // namespace
 
 void precond_setup(dpp_precond pc, hipStream_t s) {
-  if (pc->prob->g.dim == 3)
-    setup_impl<3>(pc, s);
-  else
-    setup_impl<2>(pc, s);
+  DPP_TAG_SWITCH(pc->prob->g, (setup_impl<D_>(pc, s)));
 }
 
 void precond_make32(dpp_precond pc, hipStream_t s) {
@@ -856,10 +869,7 @@ void precond_make32(dpp_precond pc, hipStream_t s) {
 }
 
 void vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s) {
-  if (pc->prob->g.dim == 3)
-    vcyc<3, double>(pc, 0, b, x, s);
-  else
-    vcyc<2, double>(pc, 0, b, x, s);
+  DPP_TAG_SWITCH(pc->prob->g, (vcyc<D_, double>(pc, 0, b, x, s)));
 }
 
 void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStream_t s) {
@@ -868,6 +878,7 @@ void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStr
   // the Schur right-hand side kernel also writes the finest level's first
   // Chebyshev step when that level smooths
   const bool fuse = pc->lv.size() > 1 && cheb_pre(pc->opts, 0) > 0;
+  const Grid &g = P->g;
   double c2q[2] = {0.0, 0.0};
   if (fuse) {
     std::vector<Sc2> c1, c2;
@@ -877,17 +888,11 @@ void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStr
   }
   if (fp32) {
     schur_rhs(P, r, pc->rhat32.ptr, true, s, fuse ? L0.dinv32.ptr : nullptr, L0.xa32.ptr, L0.d32.ptr, c2q);
-    if (P->g.dim == 3)
-      vcyc<3, float>(pc, 0, pc->rhat32.as<float>(), L0.e32.as<float>(), s, fuse);
-    else
-      vcyc<2, float>(pc, 0, pc->rhat32.as<float>(), L0.e32.as<float>(), s, fuse);
+    DPP_TAG_SWITCH(g, (vcyc<D_, float>(pc, 0, pc->rhat32.as<float>(), L0.e32.as<float>(), s, fuse)));
     schur_velocity(P, r, L0.e32.ptr, true, z, s);
   } else {
     schur_rhs(P, r, pc->rhat.ptr, false, s, fuse ? L0.dinv.ptr : nullptr, L0.xa.ptr, L0.d.ptr, c2q);
-    if (P->g.dim == 3)
-      vcyc<3, double>(pc, 0, pc->rhat.as<double>(), L0.e.as<double>(), s, fuse);
-    else
-      vcyc<2, double>(pc, 0, pc->rhat.as<double>(), L0.e.as<double>(), s, fuse);
+    DPP_TAG_SWITCH(g, (vcyc<D_, double>(pc, 0, pc->rhat.as<double>(), L0.e.as<double>(), s, fuse)));
     schur_velocity(P, r, L0.e.ptr, false, z, s);
   }
 }
@@ -899,12 +904,8 @@ void level_spmv(dpp_precond pc, int level, int net, const double *x, double *y, 
   DPP_HIP(hipMemsetAsync(L.r.ptr, 0, sizeof(double) * 2 * N, s));
   DPP_HIP(hipMemcpyAsync(L.r.as<double>() + net * N, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
   const double *A = L.shape.sym ? L.Ah.as<double>() : L.A.as<double>();
-  if (pc->prob->g.dim == 3)
-    launch_lspmv<3, double, double>(L.shape, L.g, s, A, L.r.as<double>(), L.d.as<double>(),
-                                    nullptr, nullptr);
-  else
-    launch_lspmv<2, double, double>(L.shape, L.g, s, A, L.r.as<double>(), L.d.as<double>(),
-                                    nullptr, nullptr);
+  DPP_TAG_SWITCH(L.g, (launch_lspmv<D_, double, double>(L.shape, L.g, s, A, L.r.as<double>(),
+                                                        L.d.as<double>(), nullptr, nullptr)));
   check_launch("level_spmv");
   DPP_HIP(hipMemcpyAsync(y, L.d.as<double>() + net * N, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
 }

@@ -41,21 +41,22 @@ __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict_
                                                 const double *__restrict__ bsub,
                                                 double *__restrict__ y,
                                                 const int *__restrict__ order) {
+  constexpr int d = dim_of(D);
   __shared__ TV sut[UPT<D>::size];
   stage_upt<D>(sut, upt);
   const long N = g.N;
   const long a = (long)order[blockIdx.x] * KBS + threadIdx.x;
   if (a >= N) return;
-  double au[2][D], ap[2];
+  double au[2][d], ap[2];
   spmv_K_node<D, TV, BC>(g, kv, sut, x, a, au, ap);
   int ia[3] = {0, 0, 0};
   if constexpr (BC) node_ijk(g, a, ia[0], ia[1], ia[2]);
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const long ou = off_u(D, N, q), op = off_p(D, N, q);
+    const long ou = off_u(d, N, q), op = off_p(d, N, q);
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
-      const long r = ou + D * a + c;
+    for (int c = 0; c < d; ++c) {
+      const long r = ou + d * a + c;
       double v = au[q][c];
       if constexpr (BC)
         if (u_fixed(g, q, c, ia)) v = x[r];
@@ -69,6 +70,7 @@ __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict_
 template <int D>
 __global__ void k_spmv_block(GridDev g, const double *__restrict__ kv, int which,
                              const double *__restrict__ x, double *__restrict__ y) {
+  constexpr int d = dim_of(D);
   constexpr int NS = Tabs<D>::NS;
   const long N = g.N;
   const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,35 +80,36 @@ __global__ void k_spmv_block(GridDev g, const double *__restrict__ kv, int which
   const int q = (which - 1) & 1;
   const bool up = which <= 2;
   const size_t vs = (size_t)NS * g.ld;
-  double acc[D], accp = 0.0;
-  for (int c = 0; c < D; ++c) acc[c] = 0.0;
+  double acc[d], accp = 0.0;
+  for (int c = 0; c < d; ++c) acc[c] = 0.0;
   for (int t = 0; t < NS; ++t) {
     const int *o = TAB<D>.so[t];
     if (!inside(g, i + o[0], j + o[1], k + o[2])) continue;
     const long b = a + lin(g, o[0], o[1], o[2]);
     const double *base = kv + (size_t)t * g.ld + a;
-    for (int c = 0; c < D; ++c) {
+    for (int c = 0; c < d; ++c) {
       if (up)
-        acc[c] += base[kv_up(D, q, c) * vs] * x[b];
+        acc[c] += base[kv_up(d, q, c) * vs] * x[b];
       else
-        accp += base[kv_pu(D, q, c) * vs] * x[D * b + c];
+        accp += base[kv_pu(d, q, c) * vs] * x[d * b + c];
     }
   }
   if (up)
-    for (int c = 0; c < D; ++c) y[D * a + c] = acc[c];
+    for (int c = 0; c < d; ++c) y[d * a + c] = acc[c];
   else
     y[a] = accp;
 }
 
 template <int D>
 __global__ void k_dinv(GridDev g, const double *__restrict__ kv, double *__restrict__ dinv) {
+  constexpr int d = dim_of(D);
   constexpr int NS = Tabs<D>::NS;
   const long N = g.N;
   const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= N) return;
   const size_t vs = (size_t)NS * g.ld;
   const int t0 = TAB<D>.s0;
-  for (int q = 0; q < 2; ++q) dinv[q * N + a] = 1.0 / kv[kv_uu(D, q) * vs + (size_t)t0 * g.ld + a];
+  for (int q = 0; q < 2; ++q) dinv[q * N + a] = 1.0 / kv[kv_uu(d, q) * vs + (size_t)t0 * g.ld + a];
 }
 
 // Half storage of K (layout KH<D>: the symmetric kinds on the zero offset and
@@ -114,6 +117,7 @@ __global__ void k_dinv(GridDev g, const double *__restrict__ kv, double *__restr
 // (stream, node).
 template <int D>
 __global__ void k_pack_kh(GridDev g, const double *__restrict__ kv, double *__restrict__ kh) {
+  constexpr int d = dim_of(D);
   using L = KH<D>;
   const long N = g.N;
   const size_t ld = g.ld, vs = (size_t)L::NS * ld;
@@ -122,8 +126,8 @@ __global__ void k_pack_kh(GridDev g, const double *__restrict__ kv, double *__re
   const int st = (int)(idx / N);
   const long a = idx - (long)st * N;
   const int k = st / L::NH, h = st % L::NH;
-  const int kind = k == L::UU0 ? kv_uu(D, 0) : k == L::UU1 ? kv_uu(D, 1) : k == L::PP0 ? kv_pp(D, 0)
-                 : k == L::PP1 ? kv_pp(D, 1) : kv_12(D);
+  const int kind = k == L::UU0 ? kv_uu(d, 0) : k == L::UU1 ? kv_uu(d, 1) : k == L::PP0 ? kv_pp(d, 0)
+                 : k == L::PP1 ? kv_pp(d, 1) : kv_12(d);
   kh[L::at(L::sym(k, h), a)] = kv[kind * vs + (size_t)(h + L::S0) * ld + a];
 }
 
@@ -133,13 +137,14 @@ __global__ void k_pack_kh(GridDev g, const double *__restrict__ kv, double *__re
 // run before the velocity faces mask K.
 template <int D>
 __global__ void k_up_table(GridDev g, const double *__restrict__ kv, double *__restrict__ upt) {
+  constexpr int d = dim_of(D);
   using U = UPT<D>;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= U::size) return;
-  const int c = idx % D, t = (idx / D) % U::NS, cls = idx / (D * U::NS);
+  const int c = idx % d, t = (idx / d) % U::NS, cls = idx / (d * U::NS);
   int ijk[3] = {0, 0, 0}, cc = cls;
   bool exists = true;
-  for (int ax = 0; ax < D; ++ax) {
+  for (int ax = 0; ax < d; ++ax) {
     const int k = cc % 3;
     cc /= 3;
     ijk[ax] = k == 0 ? 0 : (k == 2 ? g.n[ax] : 1);
@@ -147,7 +152,7 @@ __global__ void k_up_table(GridDev g, const double *__restrict__ kv, double *__r
   }
   const long a = ijk[0] + (long)g.m[0] * (ijk[1] + (long)g.m[1] * ijk[2]);
   const size_t vs = (size_t)U::NS * g.ld;
-  upt[idx] = exists ? kv[kv_up(D, 0, c) * vs + (size_t)t * g.ld + a] : 0.0;
+  upt[idx] = exists ? kv[kv_up(d, 0, c) * vs + (size_t)t * g.ld + a] : 0.0;
 }
 
 // selfp Schur block (eqs. S4_sp1, S4_sp2):
@@ -157,6 +162,7 @@ template <int D>
 __global__ __launch_bounds__(256) void k_selfp(GridDev g, const double *__restrict__ kv,
                                                const double *__restrict__ dinv,
                                                double *__restrict__ S) {
+  constexpr int d = dim_of(D);
   constexpr int NS = Tabs<D>::NS;
   constexpr int NT = Tabs<D>::NT;
   const long N = g.N;
@@ -171,10 +177,10 @@ __global__ __launch_bounds__(256) void k_selfp(GridDev g, const double *__restri
   double acc = 0.0;
   if (inside(g, ib[0] + to[0], ib[1] + to[1], ib[2] + to[2])) {
     const size_t vs = (size_t)NS * g.ld;
-    const int st = TAB<D>.sidx[(to[0] + 1) + 3 * (to[1] + 1) + 9 * (to[2] + 1)];
     const bool small = to[0] >= -1 && to[0] <= 1 && to[1] >= -1 && to[1] <= 1 && to[2] >= -1 &&
                        to[2] <= 1;
-    if (small && st >= 0) acc = kv[kv_pp(D, q) * vs + (size_t)st * g.ld + b];
+    const int st = small ? TAB<D>.sidx[(to[0] + 1) + 3 * (to[1] + 1) + 9 * (to[2] + 1)] : -1;
+    if (st >= 0) acc = kv[kv_pp(d, q) * vs + (size_t)st * g.ld + b];
     for (int s = 0; s < NS; ++s) {
       const int *so = TAB<D>.so[s];
       if (!inside(g, ib[0] + so[0], ib[1] + so[1], ib[2] + so[2])) continue;
@@ -184,9 +190,9 @@ __global__ __launch_bounds__(256) void k_selfp(GridDev g, const double *__restri
       if (r < 0) continue;
       const long a = b + lin(g, so[0], so[1], so[2]);
       double sum = 0.0;
-      for (int c = 0; c < D; ++c)
-        sum += kv[kv_pu(D, q, c) * vs + (size_t)s * g.ld + b] *
-               kv[kv_up(D, q, c) * vs + (size_t)r * g.ld + a];
+      for (int c = 0; c < d; ++c)
+        sum += kv[kv_pu(d, q, c) * vs + (size_t)s * g.ld + b] *
+               kv[kv_up(d, q, c) * vs + (size_t)r * g.ld + a];
       acc -= sum * dinv[q * N + a];
     }
   }
@@ -203,6 +209,7 @@ __global__ __launch_bounds__(256) void k_schur_rhs(GridDev g, const TV *__restri
                                                    const TX *__restrict__ ldinv,
                                                    TX *__restrict__ xa, TX *__restrict__ dd,
                                                    Sc2 c2) {
+  constexpr int d = dim_of(D);
   __shared__ TV sut[UPT<D>::size];
   stage_upt<D>(sut, upt);
   const int q = blockIdx.y;
@@ -226,44 +233,45 @@ __global__ __launch_bounds__(256) void k_schur_vel(GridDev g, const TV *__restri
                                                    const double *__restrict__ r,
                                                    const TX *__restrict__ zp,
                                                    double *__restrict__ z) {
+  constexpr int d = dim_of(D);
   __shared__ TV sut[UPT<D>::size];
   stage_upt<D>(sut, upt);
   const long N = g.N;
   const int q = blockIdx.y;
   const long a = 2 * ((long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
   if (a >= N) return;
-  const long ou = off_u(D, N, q);
+  const long ou = off_u(d, N, q);
   if (a + 1 < N) {
-    double out[2 * D];
+    double out[2 * d];
     schur_vel_node2<D, TV, TX>(g, sut, dinv, r, zp, q, a, out);
     if constexpr (BC) {
       int ia[3], ib[3];
       node_ijk(g, a, ia[0], ia[1], ia[2]);
       node_ijk(g, a + 1, ib[0], ib[1], ib[2]);
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
-        if (u_fixed(g, q, c, ia)) out[c] = r[ou + D * a + c];
-        if (u_fixed(g, q, c, ib)) out[D + c] = r[ou + D * (a + 1) + c];
+      for (int c = 0; c < d; ++c) {
+        if (u_fixed(g, q, c, ia)) out[c] = r[ou + d * a + c];
+        if (u_fixed(g, q, c, ib)) out[d + c] = r[ou + d * (a + 1) + c];
       }
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) st2(z + ou + D * a + 2 * k, out[2 * k], out[2 * k + 1]);
+    for (int k = 0; k < d; ++k) st2(z + ou + d * a + 2 * k, out[2 * k], out[2 * k + 1]);
     TX p0, p1;
     ld2(zp + q * N + a, p0, p1);
-    st2(z + off_p(D, N, q) + a, (double)p0, (double)p1);
+    st2(z + off_p(d, N, q) + a, (double)p0, (double)p1);
   } else {
-    double out[D];
+    double out[d];
     schur_vel_node<D, TV, TX>(g, sut, dinv, r, zp, q, a, out);
     if constexpr (BC) {
       int ia[3];
       node_ijk(g, a, ia[0], ia[1], ia[2]);
 #pragma unroll
-      for (int c = 0; c < D; ++c)
-        if (u_fixed(g, q, c, ia)) out[c] = r[ou + D * a + c];
+      for (int c = 0; c < d; ++c)
+        if (u_fixed(g, q, c, ia)) out[c] = r[ou + d * a + c];
     }
 #pragma unroll
-    for (int c = 0; c < D; ++c) z[ou + D * a + c] = out[c];
-    z[off_p(D, N, q) + a] = (double)zp[q * N + a];
+    for (int c = 0; c < d; ++c) z[ou + d * a + c] = out[c];
+    z[off_p(d, N, q) + a] = (double)zp[q * N + a];
   }
 }
 
@@ -278,106 +286,86 @@ __global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, si
 // the half storage (zero offset and positive half) once, the K_up class
 // table once, and the vectors.
 double upt_bytes(const Grid &g, bool fp32) {
-  return (g.dim == 3 ? UPT<3>::size : UPT<2>::size) * (fp32 ? 4.0 : 8.0);
+  int n = 0;
+  DPP_TAG_SWITCH(g, (n = UPT<D_>::size));
+  return n * (fp32 ? 4.0 : 8.0);
 }
 double kbytes(const Grid &g, bool fp32, bool resid) {
-  const double pairs = g.dim == 3 ? valid_pairs<3, false>(g) : valid_pairs<2, false>(g);
+  double pairs = 0.0;
+  DPP_TAG_SWITCH(g, (pairs = valid_pairs<D_, false>(g)));
   const double half = 0.5 * (pairs + g.N);
   const double nd = (2.0 * g.dim + 2.0) * g.N;
   return half * 5.0 * (fp32 ? 4.0 : 8.0) + upt_bytes(g, fp32) + nd * 8.0 * (resid ? 3.0 : 2.0);
 }
 
-void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32) {
+// y = K x, or y = bsub - K x when bsub is non-null
+static void launch_K(dpp_problem P, const double *x, const double *bsub, double *y, hipStream_t s,
+                     bool fp32) {
   const Grid &g = P->g;
   const int nb = blocks_for(g.N, KBS);
   const int *ord = P->korder.as<int>();
   const bool bc = (g.fix[0] | g.fix[1]) != 0;
-  ProfScope ps(PF_SPMV_K, kbytes(g, fp32, false), s);
-  if (g.dim == 3) {
-    if (fp32)
-      (bc ? k_spmv_K<3, float, true> : k_spmv_K<3, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), P->upt32.as<float>(), x, nullptr, y, ord);
-    else
-      (bc ? k_spmv_K<3, double, true> : k_spmv_K<3, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), P->upt.as<double>(), x, nullptr, y, ord);
-  } else {
-    if (fp32)
-      (bc ? k_spmv_K<2, float, true> : k_spmv_K<2, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), P->upt32.as<float>(), x, nullptr, y, ord);
-    else
-      (bc ? k_spmv_K<2, double, true> : k_spmv_K<2, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), P->upt.as<double>(), x, nullptr, y, ord);
-  }
+  if (fp32)
+    DPP_TAG_SWITCH(g, ((bc ? k_spmv_K<D_, float, true> : k_spmv_K<D_, float, false>)<<<nb, KBS, 0, s>>>(
+                          dev(g), P->kh32.as<float>(), P->upt32.as<float>(), x, bsub, y, ord)));
+  else
+    DPP_TAG_SWITCH(g, ((bc ? k_spmv_K<D_, double, true> : k_spmv_K<D_, double, false>)<<<nb, KBS, 0, s>>>(
+                          dev(g), P->kh.as<double>(), P->upt.as<double>(), x, bsub, y, ord)));
+}
+
+void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32) {
+  ProfScope ps(PF_SPMV_K, kbytes(P->g, fp32, false), s);
+  launch_K(P, x, nullptr, y, s, fp32);
   check_launch("spmv_K");
 }
 
 void residual_K(dpp_problem P, const double *b, const double *x, double *r, hipStream_t s,
                 bool fp32) {
-  const Grid &g = P->g;
-  const int nb = blocks_for(g.N, KBS);
-  const int *ord = P->korder.as<int>();
-  const bool bc = (g.fix[0] | g.fix[1]) != 0;
-  ProfScope ps(PF_SPMV_K, kbytes(g, fp32, true), s);
-  if (g.dim == 3) {
-    if (fp32)
-      (bc ? k_spmv_K<3, float, true> : k_spmv_K<3, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), P->upt32.as<float>(), x, b, r, ord);
-    else
-      (bc ? k_spmv_K<3, double, true> : k_spmv_K<3, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), P->upt.as<double>(), x, b, r, ord);
-  } else {
-    if (fp32)
-      (bc ? k_spmv_K<2, float, true> : k_spmv_K<2, float, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh32.as<float>(), P->upt32.as<float>(), x, b, r, ord);
-    else
-      (bc ? k_spmv_K<2, double, true> : k_spmv_K<2, double, false>)<<<nb, KBS, 0, s>>>(dev(g), P->kh.as<double>(), P->upt.as<double>(), x, b, r, ord);
-  }
+  ProfScope ps(PF_SPMV_K, kbytes(P->g, fp32, true), s);
+  launch_K(P, x, b, r, s, fp32);
   check_launch("residual_K");
 }
 
 void spmv_block(dpp_problem P, int which, const double *x, double *y, hipStream_t s) {
   const Grid &g = P->g;
-  if (g.dim == 3)
-    k_spmv_block<3><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), which, x, y);
-  else
-    k_spmv_block<2><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), which, x, y);
+  DPP_TAG_SWITCH(g, (k_spmv_block<D_><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(),
+                                                                        which, x, y)));
   check_launch("spmv_block");
 }
 
 void make_dinv(dpp_problem P, hipStream_t s) {
   const Grid &g = P->g;
-  if (g.dim == 3)
-    k_dinv<3><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->dinv.as<double>());
-  else
-    k_dinv<2><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->dinv.as<double>());
+  DPP_TAG_SWITCH(g, (k_dinv<D_><<<blocks_for(g.N, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(),
+                                                                  P->dinv.as<double>())));
   check_launch("dinv");
 }
 
 void make_selfp(dpp_problem P, double *S, hipStream_t s) {
   const Grid &g = P->g;
-  if (g.dim == 3) {
-    dim3 grid(blocks_for(g.N * Tabs<3>::NT, 256), 2);
-    k_selfp<3><<<grid, 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->dinv.as<double>(), S);
-  } else {
-    dim3 grid(blocks_for(g.N * Tabs<2>::NT, 256), 2);
-    k_selfp<2><<<grid, 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->dinv.as<double>(), S);
-  }
+  DPP_TAG_SWITCH(g, (k_selfp<D_><<<dim3(blocks_for(g.N * Tabs<D_>::NT, 256), 2), 256, 0, s>>>(
+                        dev(g), P->kvals.as<double>(), P->dinv.as<double>(), S)));
   check_launch("selfp");
 }
 
 void make_up_table(dpp_problem P, hipStream_t s) {
   const Grid &g = P->g;
-  const int n = g.dim == 3 ? UPT<3>::size : UPT<2>::size;
+  int n = 0;
+  DPP_TAG_SWITCH(g, (n = UPT<D_>::size));
   P->upt.alloc(sizeof(double) * n);
-  if (g.dim == 3)
-    k_up_table<3><<<blocks_for(n, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->upt.as<double>());
-  else
-    k_up_table<2><<<blocks_for(n, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->upt.as<double>());
+  DPP_TAG_SWITCH(g, (k_up_table<D_><<<blocks_for(n, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(),
+                                                                    P->upt.as<double>())));
   check_launch("K_up class table");
 }
 
 void make_kh(dpp_problem P, hipStream_t s) {
   const Grid &g = P->g;
-  const int streams = g.dim == 3 ? KH<3>::streams : KH<2>::streams;
-  P->kh.alloc(sizeof(double) * (g.dim == 3 ? KH<3>::size(g.N) : KH<2>::size(g.N)));
+  int streams = 0;
+  size_t size = 0;
+  DPP_TAG_SWITCH(g, (streams = KH<D_>::streams, size = KH<D_>::size(g.N)));
+  P->kh.alloc(sizeof(double) * size);
   const long work = (long)streams * g.N;
-  if (g.dim == 3)
-    k_pack_kh<3><<<blocks_for(work, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->kh.as<double>());
-  else
-    k_pack_kh<2><<<blocks_for(work, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(), P->kh.as<double>());
+  DPP_TAG_SWITCH(g, (k_pack_kh<D_><<<blocks_for(work, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(),
+                                                                      P->kh.as<double>())));
   check_launch("pack K half storage");
   // K product workgroups in column order (block_column_order)
   const long plane = g.dim == 3 ? (long)g.m[0] * g.m[1] : g.N;
@@ -412,21 +400,14 @@ void schur_rhs(dpp_problem P, const double *r, void *rhat, bool fp32, hipStream_
   const bool bc = (g.fix[0] | g.fix[1]) != 0;
   const float *u32 = P->upt32.as<float>();
   const double *u64 = P->upt.as<double>();
-  if (g.dim == 3) {
-    if (fp32)
-      (bc ? k_schur_rhs<3, float, float, true> : k_schur_rhs<3, float, float, false>)<<<grid, 256, 0, s>>>(
-          dev(g), u32, di, r, (float *)rhat, (const float *)ldinv, (float *)xa, (float *)dd, c);
-    else
-      (bc ? k_schur_rhs<3, double, double, true> : k_schur_rhs<3, double, double, false>)<<<grid, 256, 0, s>>>(
-          dev(g), u64, di, r, (double *)rhat, (const double *)ldinv, (double *)xa, (double *)dd, c);
-  } else {
-    if (fp32)
-      (bc ? k_schur_rhs<2, float, float, true> : k_schur_rhs<2, float, float, false>)<<<grid, 256, 0, s>>>(
-          dev(g), u32, di, r, (float *)rhat, (const float *)ldinv, (float *)xa, (float *)dd, c);
-    else
-      (bc ? k_schur_rhs<2, double, double, true> : k_schur_rhs<2, double, double, false>)<<<grid, 256, 0, s>>>(
-          dev(g), u64, di, r, (double *)rhat, (const double *)ldinv, (double *)xa, (double *)dd, c);
-  }
+  if (fp32)
+    DPP_TAG_SWITCH(g, ((bc ? k_schur_rhs<D_, float, float, true> : k_schur_rhs<D_, float, float, false>)
+                          <<<grid, 256, 0, s>>>(dev(g), u32, di, r, (float *)rhat, (const float *)ldinv,
+                                                (float *)xa, (float *)dd, c)));
+  else
+    DPP_TAG_SWITCH(g, ((bc ? k_schur_rhs<D_, double, double, true> : k_schur_rhs<D_, double, double, false>)
+                          <<<grid, 256, 0, s>>>(dev(g), u64, di, r, (double *)rhat, (const double *)ldinv,
+                                                (double *)xa, (double *)dd, c)));
   check_launch("schur_rhs");
 }
 
@@ -439,17 +420,12 @@ void schur_velocity(dpp_problem P, const double *r, const void *zp, bool fp32, d
   dim3 grid(blocks_for((g.N + 1) / 2, 256), 2);
   const double *di = P->dinv.as<double>();
   const bool bc = (g.fix[0] | g.fix[1]) != 0;
-  if (g.dim == 3) {
-    if (fp32)
-      (bc ? k_schur_vel<3, float, float, true> : k_schur_vel<3, float, float, false>)<<<grid, 256, 0, s>>>(dev(g), P->upt32.as<float>(), di, r, (const float *)zp, z);
-    else
-      (bc ? k_schur_vel<3, double, double, true> : k_schur_vel<3, double, double, false>)<<<grid, 256, 0, s>>>(dev(g), P->upt.as<double>(), di, r, (const double *)zp, z);
-  } else {
-    if (fp32)
-      (bc ? k_schur_vel<2, float, float, true> : k_schur_vel<2, float, float, false>)<<<grid, 256, 0, s>>>(dev(g), P->upt32.as<float>(), di, r, (const float *)zp, z);
-    else
-      (bc ? k_schur_vel<2, double, double, true> : k_schur_vel<2, double, double, false>)<<<grid, 256, 0, s>>>(dev(g), P->upt.as<double>(), di, r, (const double *)zp, z);
-  }
+  if (fp32)
+    DPP_TAG_SWITCH(g, ((bc ? k_schur_vel<D_, float, float, true> : k_schur_vel<D_, float, float, false>)
+                          <<<grid, 256, 0, s>>>(dev(g), P->upt32.as<float>(), di, r, (const float *)zp, z)));
+  else
+    DPP_TAG_SWITCH(g, ((bc ? k_schur_vel<D_, double, double, true> : k_schur_vel<D_, double, double, false>)
+                          <<<grid, 256, 0, s>>>(dev(g), P->upt.as<double>(), di, r, (const double *)zp, z)));
   check_launch("schur_velocity");
 }
 

@@ -154,11 +154,13 @@ __global__ __launch_bounds__(PBS) void k_l2_error(GridDev g, const double *__res
 // Pure-flux case (velocity faces on every face of both networks): K has the
 // kernel u = 0, p1 = p2 = const, which is also its left kernel (K^T = D K D).
 // mode 0: per-workgroup sums of p1 + p2 over the nodes (the right-hand side's
-// component along the kernel); mode 1: of the simplex means of p1 (int p1,
-// up to the constant simplex volume of the box).
+// component along the kernel); mode 1: of the cell means of p1 (int p1, up to
+// the constant cell volume of the box; cells are the Kuhn simplices, or the
+// boxes themselves with Q1 elements, where a cell's mean is its vertex mean).
 template <int D>
 __global__ __launch_bounds__(PBS) void k_pressure_sums(GridDev g, const double *__restrict__ v,
-                                                       int mode, double *__restrict__ part) {
+                                                       int mode, int boxcells,
+                                                       double *__restrict__ part) {
   constexpr int NPER = D == 3 ? 6 : 2;
   const long N = g.N;
   double acc = 0.0;
@@ -166,6 +168,20 @@ __global__ __launch_bounds__(PBS) void k_pressure_sums(GridDev g, const double *
     const long op1 = off_p(D, N, 0), op2 = off_p(D, N, 1);
     for (long a = (long)blockIdx.x * PBS + threadIdx.x; a < N; a += (long)gridDim.x * PBS)
       acc += v[op1 + a] + v[op2 + a];
+  } else if (boxcells) {
+    const long ncell = (long)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
+    const long op1 = off_p(D, N, 0);
+    for (long e = (long)blockIdx.x * PBS + threadIdx.x; e < ncell; e += (long)gridDim.x * PBS) {
+      long r = e;
+      const int i = (int)(r % g.n[0]);
+      r /= g.n[0];
+      const int j = (int)(r % g.n[1]);
+      const int k = D == 3 ? (int)(r / g.n[1]) : 0;
+      double sv = 0.0;
+      for (int vb = 0; vb < (1 << D); ++vb)
+        sv += v[op1 + (i + (vb & 1)) + (long)g.m[0] * ((j + ((vb >> 1) & 1)) + (long)g.m[1] * (k + ((vb >> 2) & 1)))];
+      acc += sv / (1 << D);
+    }
   } else {
     const long ncell = (long)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1) * NPER;
     const long op1 = off_p(D, N, 0);
@@ -233,10 +249,11 @@ static double pressure_reduce(dpp_problem P, const double *v, int mode, hipStrea
   constexpr int NB = 512;
   DBuf part(sizeof(double) * (NB + 1));
   double *dp = part.as<double>();
+  const int box = g.elem == ELEM_Q1 ? 1 : 0;
   if (g.dim == 3)
-    k_pressure_sums<3><<<NB, PBS, 0, s>>>(dev(g), v, mode, dp);
+    k_pressure_sums<3><<<NB, PBS, 0, s>>>(dev(g), v, mode, box, dp);
   else
-    k_pressure_sums<2><<<NB, PBS, 0, s>>>(dev(g), v, mode, dp);
+    k_pressure_sums<2><<<NB, PBS, 0, s>>>(dev(g), v, mode, box, dp);
   k_l2_finish<<<1, PBS, 0, s>>>(dp, NB, dp + NB);
   check_launch("pressure sums");
   double h = 0.0;
@@ -372,6 +389,7 @@ static void check_mms_args(int q, const double mms[4]) {
 void mms_l2_errors(dpp_problem P, const double *x, const double mms[4], int q, double err[4],
                    hipStream_t s) {
   check_mms_args(q, mms);
+  DPP_CHECK(P->g.elem == ELEM_P1, DPP_ERR_UNSUPPORTED, "L2 errors are integrated over simplex cells only");
   const Grid &g = P->g;
   std::vector<double> lam, wt;
   simplex_rule(g.dim, q, lam, wt);
@@ -446,6 +464,7 @@ double *scratch_of_current_device() {
 void mms_l2_errors_noalloc(dpp_problem P, const double *x, const double mms[4], int q,
                            double err[4], hipStream_t s) {
   check_mms_args(q, mms);
+  DPP_CHECK(P->g.elem == ELEM_P1, DPP_ERR_UNSUPPORTED, "L2 errors are integrated over simplex cells only");
   const Grid &g = P->g;
   int nq = 1;
   for (int a = 0; a < g.dim; ++a) nq *= q;

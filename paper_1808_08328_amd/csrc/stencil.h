@@ -199,8 +199,9 @@ constexpr int stored_offsets() {
 // pair that leaves the box from that node, a stored zero).
 template <int D, typename TV, bool BC = false>
 __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh, const TV *ut,
-                                   const double *__restrict__ x, long a, double au[2][D],
+                                   const double *__restrict__ x, long a, double au[2][dim_of(D)],
                                    double ap[2]) {
+  constexpr int d = dim_of(D);
   using L = KH<D>;
   using U = UPT<D>;
   const long N = g.N;
@@ -208,10 +209,10 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh, 
   for (int q = 0; q < 2; ++q) {
     ap[q] = 0.0;
 #pragma unroll
-    for (int c = 0; c < D; ++c) au[q][c] = 0.0;
+    for (int c = 0; c < d; ++c) au[q][c] = 0.0;
   }
-  const long ou[2] = {off_u(D, N, 0), off_u(D, N, 1)};
-  const long op[2] = {off_p(D, N, 0), off_p(D, N, 1)};
+  const long ou[2] = {off_u(d, N, 0), off_u(d, N, 1)};
+  const long op[2] = {off_p(d, N, 0), off_p(d, N, 1)};
   // with velocity faces (BC): prescribed velocity components are removed from
   // the columns, here through x (the table and kh hold the unmasked values)
   int ia[3];
@@ -232,16 +233,16 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh, 
     const bool ip = inside(g, pb[0], pb[1], pb[2]), im = inside(g, nb[0], nb[1], nb[2]);
     const int cp = ip ? node_class<D>(g, pb[0], pb[1], pb[2]) : 0;
     const int cm = im ? node_class<D>(g, nb[0], nb[1], nb[2]) : 0;
-    double utp[D], utn[D], ptn[D], mtp[D];
+    double utp[d], utn[d], ptn[d], mtp[d];
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
+    for (int c = 0; c < d; ++c) {
       utp[c] = (double)ut[U::at(ca, tp, c)];
       utn[c] = (double)ut[U::at(ca, tn, c)];
       ptn[c] = ip ? (double)ut[U::at(cp, tn, c)] : 0.0;
       mtp[c] = im ? (double)ut[U::at(cm, tp, c)] : 0.0;
     }
     // pair (a, a + o): symmetric kinds own
-    double xu[D], xp[2], xo[2];
+    double xu[d], xp[2], xo[2];
     const double uu0 = (double)kh[L::at(L::sym(L::UU0, h), a)];
     const double uu1 = (double)kh[L::at(L::sym(L::UU1, h), a)];
     const double pp0 = (double)kh[L::at(L::sym(L::PP0, h), a)];
@@ -252,15 +253,15 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh, 
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) xu[c] = x[ou[q] + D * bp + c];
+      for (int c = 0; c < d; ++c) xu[c] = x[ou[q] + d * bp + c];
       if constexpr (BC) {
 #pragma unroll
-        for (int c = 0; c < D; ++c)
+        for (int c = 0; c < d; ++c)
           if (u_fixed(g, q, c, pb)) xu[c] = 0.0;
       }
       const double uu = q ? uu1 : uu0, pp = q ? pp1 : pp0;
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
+      for (int c = 0; c < d; ++c) {
         au[q][c] += uu * xu[c] + utp[c] * xp[q];
         ap[q] -= ptn[c] * xu[c];
       }
@@ -280,15 +281,15 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh, 
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) xu[c] = x[ou[q] + D * bn + c];
+      for (int c = 0; c < d; ++c) xu[c] = x[ou[q] + d * bn + c];
       if constexpr (BC) {
 #pragma unroll
-        for (int c = 0; c < D; ++c)
+        for (int c = 0; c < d; ++c)
           if (u_fixed(g, q, c, nb)) xu[c] = 0.0;
       }
       const double uu = q ? vuu1 : vuu0, pp = q ? vpp1 : vpp0;
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
+      for (int c = 0; c < d; ++c) {
         au[q][c] += uu * xu[c] + utn[c] * xo[q];
         ap[q] -= mtp[c] * xu[c];
       }
@@ -306,12 +307,13 @@ template <int D, typename TV, bool BC = false>
 __device__ inline double schur_rhs_node(const GridDev &g, const TV *ut,
                                         const double *__restrict__ dinv,
                                         const double *__restrict__ r, int q, long b) {
+  constexpr int d = dim_of(D);
   using U = UPT<D>;
   constexpr int NS = U::NS;
   // 32-bit node and unknown indices (the assembly keeps them below 2^31)
   const int N = (int)g.N, bi = (int)b;
-  const int ou = (int)off_u(D, N, q);
-  double acc = r[off_p(D, N, q) + bi];
+  const int ou = (int)off_u(d, N, q);
+  double acc = r[off_p(d, N, q) + bi];
   int ib[3];
   node_ijk(g, b, ib[0], ib[1], ib[2]);
   // offsets in unrolled groups of 5 (loads of a group in flight together)
@@ -325,8 +327,8 @@ __device__ inline double schur_rhs_node(const GridDev &g, const TV *ut,
     const double di = in ? dinv[q * N + a] : 0.0;
     double s = 0.0;
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
-      double rv = r[ou + D * a + c];
+    for (int c = 0; c < d; ++c) {
+      double rv = r[ou + d * a + c];
       if constexpr (BC)
         if (u_fixed(g, q, c, pa)) rv = 0.0;
       s += (double)ut[U::at(ca, NS - 1 - t, c)] * rv;
@@ -342,26 +344,27 @@ template <int D, typename TV, typename TX>
 __device__ inline void schur_vel_node(const GridDev &g, const TV *ut,
                                       const double *__restrict__ dinv,
                                       const double *__restrict__ r, const TX *__restrict__ zp,
-                                      int q, long a, double out[D]) {
+                                      int q, long a, double out[dim_of(D)]) {
+  constexpr int d = dim_of(D);
   using U = UPT<D>;
   const long N = g.N;
-  const long ou = off_u(D, N, q);
+  const long ou = off_u(d, N, q);
   int i, j, k;
   node_ijk(g, a, i, j, k);
   const int ca = node_class<D>(g, i, j, k);
 #pragma unroll
-  for (int c = 0; c < D; ++c) out[c] = r[ou + D * a + c];
+  for (int c = 0; c < d; ++c) out[c] = r[ou + d * a + c];
 #pragma unroll
   for (int t = 0; t < U::NS; ++t) {
     const int *o = TAB<D>.so[t];
     const long b = min(max(a + lin(g, o[0], o[1], o[2]), 0L), N - 1);
     const double zb = (double)zp[q * N + b];
 #pragma unroll
-    for (int c = 0; c < D; ++c) out[c] -= (double)ut[U::at(ca, t, c)] * zb;
+    for (int c = 0; c < d; ++c) out[c] -= (double)ut[U::at(ca, t, c)] * zb;
   }
   const double di = dinv[q * N + a];
 #pragma unroll
-  for (int c = 0; c < D; ++c) out[c] *= di;
+  for (int c = 0; c < d; ++c) out[c] *= di;
 }
 
 // schur_vel_node for rows a and a + 1 (a even, a + 1 < N), paired loads.
@@ -369,18 +372,19 @@ template <int D, typename TV, typename TX>
 __device__ inline void schur_vel_node2(const GridDev &g, const TV *ut,
                                        const double *__restrict__ dinv,
                                        const double *__restrict__ r, const TX *__restrict__ zp,
-                                       int q, long a, double out[2 * D]) {
+                                       int q, long a, double out[2 * dim_of(D)]) {
+  constexpr int d = dim_of(D);
   using U = UPT<D>;
   // 32-bit node and unknown indices (the assembly keeps them below 2^31)
   const int N = (int)g.N, ai = (int)a;
-  const int ou = (int)off_u(D, N, q);
+  const int ou = (int)off_u(d, N, q);
   int i, j, k;
   node_ijk(g, a, i, j, k);
   const int c0 = node_class<D>(g, i, j, k);
   node_ijk(g, a + 1, i, j, k);
   const int c1 = node_class<D>(g, i, j, k);
 #pragma unroll
-  for (int k2 = 0; k2 < D; ++k2) ld2(r + ou + D * ai + 2 * k2, out[2 * k2], out[2 * k2 + 1]);
+  for (int k2 = 0; k2 < d; ++k2) ld2(r + ou + d * ai + 2 * k2, out[2 * k2], out[2 * k2 + 1]);
 #pragma unroll 5
   for (int t = 0; t < U::NS; ++t) {
     const int *o = TAB<D>.so[t];
@@ -392,26 +396,61 @@ __device__ inline void schur_vel_node2(const GridDev &g, const TV *ut,
     // the table is zero for pairs that leave the box, so a clamped z is harmless
     const double za = (double)(d > 0 ? z1 : z0), zb = (double)(d < 0 ? z0 : z1);
 #pragma unroll
-    for (int k2 = 0; k2 < D; ++k2) {
+    for (int k2 = 0; k2 < d; ++k2) {
       out[k2] -= (double)ut[U::at(c0, t, k2)] * za;
-      out[D + k2] -= (double)ut[U::at(c1, t, k2)] * zb;
+      out[d + k2] -= (double)ut[U::at(c1, t, k2)] * zb;
     }
   }
   double di0, di1;
   ld2(dinv + q * N + ai, di0, di1);
 #pragma unroll
-  for (int k2 = 0; k2 < D; ++k2) {
+  for (int k2 = 0; k2 < d; ++k2) {
     out[k2] *= di0;
-    out[D + k2] *= di1;
+    out[d + k2] *= di1;
   }
 }
 
-// b_c(C) = sum_f P(f, C) r(f) for one coarse node (one network's slice rq)
+// Fine nodes f of one axis that coarse index c interpolates to (P(f, c) != 0)
+// and their weights: the fine node at c's place (1), and the odd fine nodes
+// beside it (1/2) -- at most 3.  Unused axes (n = 0) give the single node 0.
+__device__ inline int axis_support(int c, int n, int mc, int *f, double *w) {
+  int k = 0;
+  f[k] = exact_fine(c, n, mc);
+  w[k++] = 1.0;
+  if (2 * c + 1 <= n - 1) {
+    f[k] = 2 * c + 1;
+    w[k++] = 0.5;
+  }
+  if (2 * c - 1 >= 1 && 2 * c - 1 <= n - 1) {
+    f[k] = 2 * c - 1;
+    w[k++] = 0.5;
+  }
+  return k;
+}
+
+// b_c(C) = sum_f P(f, C) r(f) for one coarse node (one network's slice rq).
+// P1 (Kuhn simplices): a fine node with odd indices on the axes O lies on the
+// Kuhn edge between lo and lo + 1_O and takes half of each; Q1 (box cells):
+// the tensor product of the axes' linear interpolation.
 template <int D, typename TX>
 __device__ inline double restrict_node(const GridDev &gf, const GridDev &gc,
                                        const TX *__restrict__ rq, long C) {
   int cc[3];
   node_ijk(gc, C, cc[0], cc[1], cc[2]);
+  if constexpr (is_q1(D)) {
+    int f[3][3], k[3];
+    double w[3][3];
+    for (int ax = 0; ax < 3; ++ax) k[ax] = axis_support(cc[ax], gf.n[ax], gc.m[ax], f[ax], w[ax]);
+    double acc = 0.0;
+    for (int z = 0; z < k[2]; ++z)
+      for (int y = 0; y < k[1]; ++y) {
+        const int row = gf.m[0] * (f[1][y] + gf.m[1] * f[2][z]);  // < 2^31
+        double s = 0.0;
+        for (int x = 0; x < k[0]; ++x) s += w[0][x] * (double)rq[f[0][x] + row];
+        acc += w[2][z] * w[1][y] * s;
+      }
+    return acc;
+  }
   int ex[3];
   for (int ax = 0; ax < 3; ++ax) ex[ax] = exact_fine(cc[ax], gf.n[ax], gc.m[ax]);
   auto fid = [&](const int *f) { return f[0] + gf.m[0] * (f[1] + gf.m[1] * f[2]); };  // < 2^31
@@ -443,6 +482,15 @@ __device__ inline double prolong_node(const GridDev &gf, const GridDev &gc,
   for (int ax = 0; ax < 3; ++ax) {
     fine_to_coarse(fi[ax], gf.n[ax], gc.m[ax], lo[ax], od[ax]);
     any = any || od[ax];
+  }
+  if constexpr (is_q1(D)) {
+    // tensor product: half of each end on every axis where f is odd
+    double v = 0.0;
+    for (int z = 0; z <= od[2]; ++z)
+      for (int y = 0; y <= od[1]; ++y)
+        for (int x = 0; x <= od[0]; ++x)
+          v += (double)eq[(lo[0] + x) + gc.m[0] * ((lo[1] + y) + gc.m[1] * (lo[2] + z))];
+    return v * (od[0] ? 0.5 : 1.0) * (od[1] ? 0.5 : 1.0) * (od[2] ? 0.5 : 1.0);
   }
   // 32-bit node indices (the assembly keeps every level below 2^31 nodes)
   const int c0 = lo[0] + gc.m[0] * (lo[1] + gc.m[1] * lo[2]);
