@@ -390,11 +390,11 @@ __device__ inline void schur_vel_node2(const GridDev &g, const TV *ut,
     const int *o = TAB<D>.so[t];
     const int b = ai + (int)lin(g, o[0], o[1], o[2]);
     const int c = min(max(b, 0), N - 2);
-    const int d = b - c;
+    const int sh = b - c;
     TX z0, z1;
     ld2(zp + q * N + c, z0, z1);
     // the table is zero for pairs that leave the box, so a clamped z is harmless
-    const double za = (double)(d > 0 ? z1 : z0), zb = (double)(d < 0 ? z0 : z1);
+    const double za = (double)(sh > 0 ? z1 : z0), zb = (double)(sh < 0 ? z0 : z1);
 #pragma unroll
     for (int k2 = 0; k2 < d; ++k2) {
       out[k2] -= (double)ut[U::at(c0, t, k2)] * za;
