@@ -42,6 +42,11 @@ WORKLOADS = {
     "c2p_3d64_pureflux": "the 64^3 workload with velocity faces on every face of both networks "
                          "(singular K: consistent right-hand side, pressures normalised to "
                          "int p1 = 0)",
+    "h2_3d64_q1": "3D unit cube, 64^3 hexahedra with Q1 elements (65^3 nodes, the HEX columns of the "
+                  "3D study) = 2,197,000 DOF; k1=1, k2=1e-2, beta=mu=1; manufactured-solution pressure "
+                  "data on all faces",
+    "h3_3d96_grf_q1": "3D unit cube 96^3 hexahedra with Q1 elements = 7,301,384 DOF; log-normal per-hex "
+                      "k1, k2 (seeds 1001/1002)",
     "c4_batch64": "64 independent 2D unit-square instances, n ~ U{32..256} cells per side (seed 2024), "
                   "beta ~ logU[0.1,10], k2/k1 ~ logU[1e-3,1]; one batched launch per phase",
 }
@@ -71,6 +76,12 @@ def kernel_name(family, dim, pc, flux=False):
     bc = "true" if flux else "false"
     return {"spmv_K": "k_spmv_K<%d, double, " + bc + ">", "schur_rhs": "k_schur_rhs<%d, double, double, " + bc + ">",
             "schur_vel": "k_schur_vel<%d, double, double, " + bc + ">"}[family] % dim
+
+
+def stencil_tag(prob):
+    """Template tag of the library's stencil kernels: the dimension, plus 10
+    for Q1 box cells."""
+    return prob.dim + (10 if getattr(prob, "elem", "p1") == "q1" else 0)
 
 
 def measured_traffic(family, launches_bytes):
@@ -420,7 +431,7 @@ def main():
     if not args.no_profile:
         kernels = profiled(dpp, lambda: P.solve(pc, **opts), args.steps)
         line["roofline"] = roofline(kernels, SINGLE_KERNEL_FAMILIES, copy_gbs,
-                                    lambda k: kernel_name(k, prob.dim, pc,
+                                    lambda k: kernel_name(k, stencil_tag(prob), pc,
                                                           flux=getattr(prob, "face_bc", None) is not None))
         line["kernels"] = strip_raw(kernels)
     else:

@@ -143,13 +143,16 @@ def test_q1_fp64_solve_matches_oracle_direct_solve(case):
     xo = odpp.solve_direct(S.K, S.f)
     P = lib().assemble_problem(prob)
     pc = P.setup_precond(coarse_max=40)
-    x, st = P.solve(pc, rtol=1e-12, maxiter=600)
+    # the boxes one cell thick have cond(K) ~ 1e3 (measured: 1.4e3 at 1x3x2),
+    # so the residual bar that gives 1e-10 per field is 1e-14 there
+    rtol = 1e-14 if P.n_dof < 2000 else 1e-12
+    x, st = P.solve(pc, rtol=rtol, maxiter=600)
     x = H(x)
-    assert st.converged == 1 and st.rel_residual <= 1e-12
+    assert st.converged == 1 and st.rel_residual <= rtol
     F = odpp.fields(prob.dim, S.N)
     for f in ("u1", "p1", "u2", "p2"):
         assert np.linalg.norm(x[F[f]] - xo[F[f]]) <= 1e-10 * np.linalg.norm(xo[F[f]]), f
-    assert np.linalg.norm(S.f - S.K @ x) <= 1.05e-12 * np.linalg.norm(S.f)
+    assert np.linalg.norm(S.f - S.K @ x) <= 1.05 * rtol * np.linalg.norm(S.f)
 
 
 @pytest.mark.parametrize("precision", [1, 2])
