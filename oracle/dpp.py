@@ -336,7 +336,11 @@ def consistent_rhs(f, dim, N):
 
 
 def pressure_mean(msh, p):
-    """(1/|Omega|) int_Omega p_h for a P1 nodal vector p (exact for P1)."""
+    """(1/|Omega|) int_Omega p_h for a P1 nodal vector p (exact for P1); on Q1
+    box cells (all of one volume) a cell's integral is its volume times its
+    vertex mean, also exact."""
+    if msh.elem == "q1":
+        return float(p[msh.cells].mean(1).mean())
     V = msh.X[msh.cells]
     J = np.transpose(V[:, 1:, :] - V[:, :1, :], (0, 2, 1))
     vol = np.abs(np.linalg.det(J)) / (2.0 if msh.dim == 2 else 6.0)

@@ -213,20 +213,32 @@ def test_q1_velocity_faces_match_oracle(faces):
         assert e <= 1e-10, f
 
 
+@pytest.mark.timeout(900)
 def test_q1_full_size_solve_oracle_residual():
     """The 64^3 Q1 workload (2,197,000 DOF) in the benchmark's launch
     configuration: the oracle's own FP64 K applied to the GPU solution at
     1e-8, and 2000 sampled rows of K."""
-    print("full-size Q1 64^3", flush=True)
+    import time
+    t0 = time.time()
+
+    def step(msg):
+        print("full-size Q1 64^3: %s (%.1f s)" % (msg, time.time() - t0), flush=True)
+
+    step("start")
     prob = I.make_config("h2_3d64_q1")
     P = lib().assemble_problem(prob)
+    step("assembled")
     pc = P.setup_precond()
+    step("preconditioner set up")
     x, st = P.solve(pc)
+    step("solved in %d iterations" % st.iters)
     assert st.converged == 1
     S = odpp.assemble(prob)
+    step("oracle assembled")
     r = S.f - odpp.spmv(S.K, H(x))
     assert np.linalg.norm(r) <= 1.05e-8 * np.linalg.norm(S.f)
     rp, ci, vv = P.export_csr()
+    step("exported")
     rows = np.random.default_rng(0).integers(0, P.n_dof, 2000)
     rph, cih, vvh = H(rp), H(ci), H(vv)
     for rr in rows:

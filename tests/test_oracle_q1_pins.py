@@ -221,3 +221,19 @@ def test_q1_fieldsplit_and_fgmres_reach_the_direct_solution():
     assert res <= 1e-12 and np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
     x, its, res = solver.solve(S, rtol=1e-12, mg_opts=mg.MGOptions(coarse_max=30))
     assert res <= 1e-12 and np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+
+
+def test_q1_pure_flux_solution_and_pressure_mean():
+    """Velocity faces everywhere on Q1 boxes: the bordered solve returns a
+    solution of K x = f (consistent part) with int p1 = 0, and the Q1 pressure
+    mean is exact on trilinear functions."""
+    prob = I.mms_problem(3, (3, 2, 4), k1=1.0, k2=0.1, flux_faces=[[1] * 6, [1] * 6], elem="q1")
+    S = dpp.assemble(prob)
+    X = S.mesh.X
+    # int over the unit box of x y z = 1/8 (trilinear, reproduced by Q1)
+    assert dpp.pressure_mean(S.mesh, X[:, 0] * X[:, 1] * X[:, 2]) == pytest.approx(0.125, abs=1e-14)
+    x = dpp.solve_pure_flux(S)
+    F = dpp.fields(3, S.N)
+    assert abs(dpp.pressure_mean(S.mesh, x[F["p1"]])) <= 1e-12 * np.abs(x[F["p1"]]).max()
+    fc = dpp.consistent_rhs(S.f, 3, S.N)
+    assert np.linalg.norm(S.K @ x - fc) <= 1e-10 * np.linalg.norm(fc)
