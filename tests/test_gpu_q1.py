@@ -202,7 +202,8 @@ def test_q1_velocity_faces_match_oracle(faces):
     F = osolver.FieldSplit(S, omg.MGOptions(coarse_max=30))
     r = I.random_vector(P.n_dof, 22)
     assert relmax(H(pc.apply(T(r))), F.apply(r)) <= 1e-11
-    xs, st = P.solve(pc, rtol=1e-13, maxiter=600)
+    # cond(K) of these small boxes is ~1e3: solve to 1e-14 for the 1e-10 bar
+    xs, st = P.solve(pc, rtol=1e-14, maxiter=600)
     assert st.converged
     xo = odpp.solve_pure_flux(S) if odpp.pure_flux(prob) else odpp.solve_direct(S.K, S.f)
     Fd = odpp.fields(3, S.N)
@@ -241,11 +242,11 @@ def test_q1_full_size_solve_oracle_residual():
     step("exported")
     rows = np.random.default_rng(0).integers(0, P.n_dof, 2000)
     rph, cih, vvh = H(rp), H(ci), H(vv)
+    scale = np.abs(S.K.data).max()
     for rr in rows:
         a, b = rph[rr], rph[rr + 1]
         assert np.array_equal(cih[a:b], S.K.indices[S.K.indptr[rr]:S.K.indptr[rr + 1]])
-        assert np.abs(vvh[a:b] - S.K.data[S.K.indptr[rr]:S.K.indptr[rr + 1]]).max() <= \
-            1e-13 * np.abs(S.K.data).max()
+        assert np.abs(vvh[a:b] - S.K.data[S.K.indptr[rr]:S.K.indptr[rr + 1]]).max() <= 1e-13 * scale
 
 
 def test_q1_p1_only_calls_are_refused():
