@@ -50,7 +50,7 @@ inline double valid_pairs(const Grid &g) {
   for (int t = 0; t < n; ++t) {
     const int *o = PRESSURE ? TAB<D>.to[t] : TAB<D>.so[t];
     double c = 1.0;
-    for (int a = 0; a < D; ++a) c *= std::max(0, g.m[a] - std::abs(o[a]));
+    for (int a = 0; a < dim_of(D); ++a) c *= std::max(0, g.m[a] - std::abs(o[a]));
     tot += c;
   }
   return tot;

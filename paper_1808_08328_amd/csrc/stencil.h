@@ -455,10 +455,10 @@ __device__ inline double restrict_node(const GridDev &gf, const GridDev &gc,
   for (int ax = 0; ax < 3; ++ax) ex[ax] = exact_fine(cc[ax], gf.n[ax], gc.m[ax]);
   auto fid = [&](const int *f) { return f[0] + gf.m[0] * (f[1] + gf.m[1] * f[2]); };  // < 2^31
   double acc = (double)rq[fid(ex)];
-  for (int mask = 1; mask < (1 << D); ++mask) {
+  for (int mask = 1; mask < (1 << dim_of(D)); ++mask) {
     int fu[3] = {ex[0], ex[1], ex[2]}, fd[3] = {ex[0], ex[1], ex[2]};
     bool uok = true, dok = true;
-    for (int ax = 0; ax < D; ++ax) {
+    for (int ax = 0; ax < dim_of(D); ++ax) {
       if (!((mask >> ax) & 1)) continue;
       fu[ax] = 2 * cc[ax] + 1;
       fd[ax] = 2 * cc[ax] - 1;
