@@ -66,14 +66,17 @@ __device__ inline double row_product(const GridDev &g, const TV *__restrict__ Aq
       const int h = hh * LPR + (LPR == 1 ? 0 : sub);
       if (LPR > 1 && h >= NH) continue;
       const int *o = TAB<D>.to[T0 + h];
+      // the linear offset of a stored offset is positive except on grids
+      // with fewer than 3 nodes along an axis, where a Q1 offset such as
+      // (-2, -2, 1) wraps to a negative one: clamp both ways
       const int lo = (int)lin(g, o[0], o[1], o[2]);
-      const int bp = min(ai + lo, N - 1);
+      const int bp = min(max(ai + lo, 0), N - 1);
       acc += (double)Aq[(size_t)h * ld + a] * (double)xq[bp];
       if (h > 0) {
         const int bm = ai - lo;
-        const int bc = max(bm, 0);
+        const int bc = min(max(bm, 0), N - 1);
         const double v = (double)Aq[(size_t)h * ld + bc] * (double)xq[bc];
-        acc += (bm >= 0) ? v : 0.0;
+        acc += (bm >= 0 && bm < N) ? v : 0.0;
       }
     }
   }
@@ -145,13 +148,16 @@ __device__ inline void row_product2(const GridDev &g, const TV *__restrict__ Aq,
       const int *o = TAB<D>.to[T0 + h];
       const int lo = (int)lin(g, o[0], o[1], o[2]);
       const int b = ai + lo;
-      const int c = min(b, N - 2);
+      // b < 0 only for a wrapped (negative) linear offset, whose pairs leave
+      // the box for both rows (stored zeros): the clamp keeps the loads in range
+      const int c = min(max(b, 0), N - 2);
       const int d = b - c;
       TV a0, a1;
       TX x0, x1;
       ld2(Aq + (size_t)h * ld + a, a0, a1);
       ld2(xq + c, x0, x1);
-      // b >= a >= 0; b + 1 >= N means row a + 1's pair leaves the box (a1 = 0)
+      // b >= a >= 0 but for wrapped offsets (both pairs leave the box); b + 1 >= N
+      // means row a + 1's pair leaves the box (a1 = 0)
       acc0 += (double)a0 * (double)(d > 0 ? x1 : x0);
       acc1 += (double)a1 * (double)x1;
       if (h > 0) {

@@ -111,15 +111,18 @@ def test_q1_hierarchy_cycle_and_fieldsplit_match_oracle(case, cmax):
     assert relmax(H(pc.apply(T(r))), F.apply(r)) <= 1e-11
 
 
-@pytest.mark.parametrize("case", ["2d_ragged_body", "3d_8_mms"])
-def test_q1_every_level_kernel_shape_matches_oracle(case):
+@pytest.mark.parametrize("case,cmax", [("2d_ragged_body", 10), ("3d_8_mms", 10), ("3d_ragged_body", 8)])
+def test_q1_every_level_kernel_shape_matches_oracle(case, cmax):
     """All lanes-per-row / symmetric-storage variants on the 125-point (25 in
-    2D) Q1 level stencils; 3d_8_mms has an odd node count on every level."""
+    2D) Q1 level stencils; 3d_8_mms has an odd node count on every level, and
+    3d_ragged_body a level with two nodes along y and z, where stored offsets
+    such as (-2, -2, 1) have a negative linear offset (the mirror reads of the
+    symmetric storage must stay masked there)."""
     prob = CASES[case]()
     S = odpp.assemble(prob)
     P = lib().assemble_problem(prob)
-    pc = P.setup_precond(coarse_max=10)
-    Hs = [omg.setup(sp_, prob.dim, prob.n, omg.MGOptions(coarse_max=10), elem="q1")
+    pc = P.setup_precond(coarse_max=cmax)
+    Hs = [omg.setup(sp_, prob.dim, prob.n, omg.MGOptions(coarse_max=cmax), elem="q1")
           for sp_ in odpp.selfp(S)]
     nlev = pc.info()["levels"]
     assert nlev >= 3
