@@ -245,14 +245,11 @@ struct KH {
   // sym kind ids
   static constexpr int UU0 = 0, UU1 = 1, PP0 = 2, PP1 = 3, K12 = 4;
   __host__ __device__ static constexpr int sym(int kind, int h) { return h * NSYM + kind; }
-  static constexpr int SLICE = 64;
-  // element of stream s at node a
-  __host__ __device__ static size_t at(int s, long a) {
-    return ((size_t)(a / SLICE) * streams + s) * SLICE + (size_t)(a % SLICE);
-  }
-  __host__ __device__ static size_t size(long N) {
-    return (size_t)((N + SLICE - 1) / SLICE) * streams * SLICE;
-  }
+  // element of stream s at node a: structure of arrays with the leading
+  // dimension ld = padded(N) of the operator storage, so that the values of
+  // two consecutive nodes are adjacent in every stream (paired loads)
+  __host__ __device__ static size_t at(int s, long a, long ld) { return (size_t)s * ld + a; }
+  __host__ __device__ static size_t size(long N) { return (size_t)streams * padded(N); }
 };
 
 // Table of the K_up values by boundary class.  The velocity-pressure

@@ -21,8 +21,8 @@ namespace dpp {
 
 namespace {
 
-// One workgroup per KBS-node block of kh (KBS threads); order[] gives the
-// block of each workgroup (column order, below).
+// One workgroup of KBS threads per block of 2 KBS nodes (a node pair per
+// thread); order[] gives the node block of each workgroup (band order, below).
 constexpr int KBS = 128;
 
 // The K_up class table (UPT<D>) copied into LDS by every workgroup.
@@ -45,24 +45,49 @@ __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict_
   __shared__ TV sut[UPT<D>::size];
   stage_upt<D>(sut, upt);
   const long N = g.N;
-  const long a = (long)order[blockIdx.x] * KBS + threadIdx.x;
+  const long a = 2 * ((long)order[blockIdx.x] * KBS + threadIdx.x);
   if (a >= N) return;
-  double au[2][d], ap[2];
-  spmv_K_node<D, TV, BC>(g, kv, sut, x, a, au, ap);
-  int ia[3] = {0, 0, 0};
-  if constexpr (BC) node_ijk(g, a, ia[0], ia[1], ia[2]);
+  double au[2][2][d], ap[2][2];
+  spmv_K_node2<D, TV, BC>(g, kv, sut, x, a, au, ap);
+  const int nr = a + 1 < N ? 2 : 1;  // node a + 1 = N has no row
+  int ia[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  if constexpr (BC) {
+    node_ijk(g, a, ia[0][0], ia[0][1], ia[0][2]);
+    if (nr == 2) node_ijk(g, a + 1, ia[1][0], ia[1][1], ia[1][2]);
+  }
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const long ou = off_u(d, N, q), op = off_p(d, N, q);
+    double v[2 * d], pv[2];
 #pragma unroll
-    for (int c = 0; c < d; ++c) {
-      const long r = ou + d * a + c;
-      double v = au[q][c];
-      if constexpr (BC)
-        if (u_fixed(g, q, c, ia)) v = x[r];
-      y[r] = bsub ? bsub[r] - v : v;
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+      for (int c = 0; c < d; ++c) {
+        v[d * r + c] = au[r][q][c];
+        if constexpr (BC)
+          if (r < nr && u_fixed(g, q, c, ia[r])) v[d * r + c] = x[ou + d * (a + r) + c];
+      }
+      pv[r] = ap[r][q];
     }
-    y[op + a] = bsub ? bsub[op + a] - ap[q] : ap[q];
+    if (nr == 2) {
+#pragma unroll
+      for (int e = 0; e < d; ++e) {
+        double b0 = 0.0, b1 = 0.0;
+        if (bsub) ld2(bsub + ou + d * a + 2 * e, b0, b1);
+        st2(y + ou + d * a + 2 * e, bsub ? b0 - v[2 * e] : v[2 * e],
+            bsub ? b1 - v[2 * e + 1] : v[2 * e + 1]);
+      }
+      double b0 = 0.0, b1 = 0.0;
+      if (bsub) ld2(bsub + op + a, b0, b1);
+      st2(y + op + a, bsub ? b0 - pv[0] : pv[0], bsub ? b1 - pv[1] : pv[1]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < d; ++c) {
+        const long r = ou + d * a + c;
+        y[r] = bsub ? bsub[r] - v[c] : v[c];
+      }
+      y[op + a] = bsub ? bsub[op + a] - pv[0] : pv[0];
+    }
   }
 }
 
@@ -128,7 +153,7 @@ __global__ void k_pack_kh(GridDev g, const double *__restrict__ kv, double *__re
   const int k = st / L::NH, h = st % L::NH;
   const int kind = k == L::UU0 ? kv_uu(d, 0) : k == L::UU1 ? kv_uu(d, 1) : k == L::PP0 ? kv_pp(d, 0)
                  : k == L::PP1 ? kv_pp(d, 1) : kv_12(d);
-  kh[L::at(L::sym(k, h), a)] = kv[kind * vs + (size_t)(h + L::S0) * ld + a];
+  kh[L::at(L::sym(k, h), a, ld)] = kv[kind * vs + (size_t)(h + L::S0) * ld + a];
 }
 
 // K_up class table (UPT<D>) read from the assembled values of one node of
@@ -302,7 +327,7 @@ double kbytes(const Grid &g, bool fp32, bool resid) {
 static void launch_K(dpp_problem P, const double *x, const double *bsub, double *y, hipStream_t s,
                      bool fp32) {
   const Grid &g = P->g;
-  const int nb = blocks_for(g.N, KBS);
+  const int nb = blocks_for(g.N, 2 * KBS);
   const int *ord = P->korder.as<int>();
   const bool bc = (g.fix[0] | g.fix[1]) != 0;
   if (fp32)
@@ -363,13 +388,15 @@ void make_kh(dpp_problem P, hipStream_t s) {
   size_t size = 0;
   DPP_TAG_SWITCH(g, (streams = KH<D_>::streams, size = KH<D_>::size(g.N)));
   P->kh.alloc(sizeof(double) * size);
+  // the stream padding is read (never used) by the pair loads of the last node
+  DPP_HIP(hipMemsetAsync(P->kh.ptr, 0, sizeof(double) * size, s));
   const long work = (long)streams * g.N;
   DPP_TAG_SWITCH(g, (k_pack_kh<D_><<<blocks_for(work, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(),
                                                                       P->kh.as<double>())));
   check_launch("pack K half storage");
-  // K product workgroups in column order (block_column_order)
+  // K product workgroups in band order (block_column_order), 2 KBS nodes each
   const long plane = g.dim == 3 ? (long)g.m[0] * g.m[1] : g.N;
-  const std::vector<int> order = block_column_order(g.N, KBS, plane);
+  const std::vector<int> order = block_column_order(g.N, 2 * KBS, plane);
   const long nb = (long)order.size();
   P->korder.alloc(sizeof(int) * nb);
   DPP_HIP(hipMemcpyAsync(P->korder.ptr, order.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));

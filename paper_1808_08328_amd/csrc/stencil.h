@@ -249,11 +249,11 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh, 
     }
     // pair (a, a + o): symmetric kinds own
     double xu[d], xp[2], xo[2];
-    const double uu0 = (double)kh[L::at(L::sym(L::UU0, h), a)];
-    const double uu1 = (double)kh[L::at(L::sym(L::UU1, h), a)];
-    const double pp0 = (double)kh[L::at(L::sym(L::PP0, h), a)];
-    const double pp1 = (double)kh[L::at(L::sym(L::PP1, h), a)];
-    const double s12 = (double)kh[L::at(L::sym(L::K12, h), a)];
+    const double uu0 = (double)kh[L::at(L::sym(L::UU0, h), a, g.ld)];
+    const double uu1 = (double)kh[L::at(L::sym(L::UU1, h), a, g.ld)];
+    const double pp0 = (double)kh[L::at(L::sym(L::PP0, h), a, g.ld)];
+    const double pp1 = (double)kh[L::at(L::sym(L::PP1, h), a, g.ld)];
+    const double s12 = (double)kh[L::at(L::sym(L::K12, h), a, g.ld)];
     xp[0] = x[op[0] + bp];
     xp[1] = x[op[1] + bp];
 #pragma unroll
@@ -277,11 +277,11 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh, 
     ap[1] += s12 * xp[0];
     if (h == 0) continue;  // the zero offset has no mirror pair
     // pair (a, a - o): symmetric kinds stored at a - o
-    const double vuu0 = mn * (double)kh[L::at(L::sym(L::UU0, h), bn)];
-    const double vuu1 = mn * (double)kh[L::at(L::sym(L::UU1, h), bn)];
-    const double vpp0 = mn * (double)kh[L::at(L::sym(L::PP0, h), bn)];
-    const double vpp1 = mn * (double)kh[L::at(L::sym(L::PP1, h), bn)];
-    const double v12 = mn * (double)kh[L::at(L::sym(L::K12, h), bn)];
+    const double vuu0 = mn * (double)kh[L::at(L::sym(L::UU0, h), bn, g.ld)];
+    const double vuu1 = mn * (double)kh[L::at(L::sym(L::UU1, h), bn, g.ld)];
+    const double vpp0 = mn * (double)kh[L::at(L::sym(L::PP0, h), bn, g.ld)];
+    const double vpp1 = mn * (double)kh[L::at(L::sym(L::PP1, h), bn, g.ld)];
+    const double v12 = mn * (double)kh[L::at(L::sym(L::K12, h), bn, g.ld)];
     xo[0] = x[op[0] + bn];
     xo[1] = x[op[1] + bn];
 #pragma unroll
@@ -303,6 +303,179 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh, 
     }
     ap[0] += v12 * xo[1];
     ap[1] += v12 * xo[0];
+  }
+}
+
+// spmv_K_node for the two nodes a and a + 1 (a even), with paired loads: the
+// half-storage streams hold consecutive nodes next to each other, and the
+// unknowns of two consecutive nodes are adjacent in x (2d velocity values, two
+// pressures), so every value the product reads comes with one 16-byte load per
+// pair of nodes (8 bytes for FP32 streams) instead of two narrow ones; the
+// product issues half the load instructions, its limit.  The neighbour pair
+// starting at b = a + o (b > a) is read from c = min(b, N - 2) and picked by
+// b - c, the mirror pair starting at a - o from max(a - o, 0) and masked when
+// it lies before node 0 (as in row_product2).  Node a + 1 may be N (N odd): its
+// result is meaningless and must not be stored; all loads stay inside the
+// arrays (streams have the leading dimension padded(N) > N for odd N).
+template <int D, typename TV, bool BC = false>
+__device__ inline void spmv_K_node2(const GridDev &g, const TV *__restrict__ kh, const TV *ut,
+                                    const double *__restrict__ x, long a,
+                                    double au[2][2][dim_of(D)], double ap[2][2]) {
+  constexpr int d = dim_of(D);
+  using L = KH<D>;
+  using U = UPT<D>;
+  // 32-bit node and unknown indices (the assembly keeps them below 2^31)
+  const int N = (int)g.N, ai = (int)a;
+  const long ld = g.ld;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      ap[r][q] = 0.0;
+#pragma unroll
+      for (int c = 0; c < d; ++c) au[r][q][c] = 0.0;
+    }
+  const int ou[2] = {(int)off_u(d, N, 0), (int)off_u(d, N, 1)};
+  const int op[2] = {(int)off_p(d, N, 0), (int)off_p(d, N, 1)};
+  int ia[2][3];
+  node_ijk(g, a, ia[0][0], ia[0][1], ia[0][2]);
+  node_ijk(g, a + 1, ia[1][0], ia[1][1], ia[1][2]);
+  const int ca[2] = {node_class<D>(g, ia[0][0], ia[0][1], ia[0][2]),
+                     node_class<D>(g, ia[1][0], ia[1][1], ia[1][2])};
+#pragma unroll 1
+  for (int h = 0; h < L::NH; ++h) {
+    const int tp = L::S0 + h, tn = L::S0 - h;
+    const int *o = TAB<D>.so[tp];
+    const int lo = (int)lin(g, o[0], o[1], o[2]);
+    // neighbour classes and the K_up / K_pu table values of both nodes
+    double utp[2][d], utn[2][d], ptn[2][d], mtp[2][d];
+    int pb[2][3], nb[2][3];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        pb[r][e] = ia[r][e] + o[e];
+        nb[r][e] = ia[r][e] - o[e];
+      }
+      const bool ip = inside(g, pb[r][0], pb[r][1], pb[r][2]);
+      const bool im = inside(g, nb[r][0], nb[r][1], nb[r][2]);
+      const int cp = ip ? node_class<D>(g, pb[r][0], pb[r][1], pb[r][2]) : 0;
+      const int cm = im ? node_class<D>(g, nb[r][0], nb[r][1], nb[r][2]) : 0;
+#pragma unroll
+      for (int c = 0; c < d; ++c) {
+        utp[r][c] = (double)ut[U::at(ca[r], tp, c)];
+        utn[r][c] = (double)ut[U::at(ca[r], tn, c)];
+        ptn[r][c] = ip ? (double)ut[U::at(cp, tn, c)] : 0.0;
+        mtp[r][c] = im ? (double)ut[U::at(cm, tp, c)] : 0.0;
+      }
+    }
+    // pairs (a, a + o) and (a + 1, a + 1 + o): symmetric kinds own
+    {
+      const int b = ai + lo;
+      const int c0 = min(b, N - 2);
+      const bool sh = b > c0;  // node a's neighbour is lane 1
+      TV kv[5][2];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) ld2(kh + L::at(L::sym(k, h), ai, ld), kv[k][0], kv[k][1]);
+      double xp[2][2], xu[2][2][d];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        double v0, v1;
+        ld2(x + op[q] + c0, v0, v1);
+        xp[q][0] = sh ? v1 : v0;
+        xp[q][1] = v1;
+        double w[2 * d];
+#pragma unroll
+        for (int e = 0; e < d; ++e) ld2(x + ou[q] + d * c0 + 2 * e, w[2 * e], w[2 * e + 1]);
+#pragma unroll
+        for (int c = 0; c < d; ++c) {
+          xu[0][q][c] = sh ? w[d + c] : w[c];
+          xu[1][q][c] = w[d + c];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        if constexpr (BC) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int c = 0; c < d; ++c)
+              if (u_fixed(g, q, c, pb[r])) xu[r][q][c] = 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const double uu = (double)kv[q ? L::UU1 : L::UU0][r], pp = (double)kv[q ? L::PP1 : L::PP0][r];
+#pragma unroll
+          for (int c = 0; c < d; ++c) {
+            au[r][q][c] += uu * xu[r][q][c] + utp[r][c] * xp[q][r];
+            ap[r][q] -= ptn[r][c] * xu[r][q][c];
+          }
+          ap[r][q] += pp * xp[q][r];
+        }
+        const double s12 = (double)kv[L::K12][r];
+        ap[r][0] += s12 * xp[1][r];
+        ap[r][1] += s12 * xp[0][r];
+      }
+    }
+    if (h == 0) continue;  // the zero offset has no mirror pair
+    // pairs (a, a - o) and (a + 1, a + 1 - o): symmetric kinds stored at the
+    // mirror nodes a - o and a + 1 - o (masked before node 0)
+    {
+      const int bm = ai - lo;          // <= N - 2
+      const int cm = max(bm, 0);
+      const int dm = bm - cm;          // 0, or < 0 before node 0
+      const double m0 = dm == 0 ? 1.0 : 0.0;
+      TV kv[5][2];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        TV w0, w1;
+        ld2(kh + L::at(L::sym(k, h), cm, ld), w0, w1);
+        kv[k][0] = w0;
+        kv[k][1] = dm == 0 ? w1 : (dm == -1 ? w0 : (TV)0);
+      }
+      double xo[2][2], xu[2][2][d];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        double v0, v1;
+        ld2(x + op[q] + cm, v0, v1);
+        xo[q][0] = v0;
+        xo[q][1] = dm == 0 ? v1 : v0;
+        double w[2 * d];
+#pragma unroll
+        for (int e = 0; e < d; ++e) ld2(x + ou[q] + d * cm + 2 * e, w[2 * e], w[2 * e + 1]);
+#pragma unroll
+        for (int c = 0; c < d; ++c) {
+          xu[0][q][c] = w[c];
+          xu[1][q][c] = dm == 0 ? w[d + c] : w[c];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        if constexpr (BC) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int c = 0; c < d; ++c)
+              if (u_fixed(g, q, c, nb[r])) xu[r][q][c] = 0.0;
+        }
+        // node a's mirror exists iff dm == 0; node a + 1's iff dm >= -1
+        const double mr = r == 0 ? m0 : (dm >= -1 ? 1.0 : 0.0);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const double uu = mr * (double)kv[q ? L::UU1 : L::UU0][r];
+          const double pp = mr * (double)kv[q ? L::PP1 : L::PP0][r];
+#pragma unroll
+          for (int c = 0; c < d; ++c) {
+            au[r][q][c] += uu * xu[r][q][c] + utn[r][c] * xo[q][r];
+            ap[r][q] -= mtp[r][c] * xu[r][q][c];
+          }
+          ap[r][q] += pp * xo[q][r];
+        }
+        const double v12 = mr * (double)kv[L::K12][r];
+        ap[r][0] += v12 * xo[1][r];
+        ap[r][1] += v12 * xo[0][r];
+      }
+    }
   }
 }
 
