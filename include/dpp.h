@@ -118,7 +118,7 @@ typedef struct {
  *     Arnoldi with the FP32 preconditioner (FP64 coarse solve).
  *   inner_rtol [1e-4], max_refine [20]: mixed mode only.
  *   coarse_max [0]: coarsest multigrid level has at most this many nodes
- *     (1..4000); 0 = by dimension (1000 in 3D, 400 in 2D).
+ *     (1..4000); 0 = by dimension (2200 in 3D, 400 in 2D).
  *   cheb_degree [2], cheb_lo_frac [0], cheb_hi_factor [1.1], power_iters [15]:
  *     Chebyshev smoother (degree used where a level's degree below is -1) and
  *     its interval [cheb_lo_frac hi, hi], hi = cheb_hi_factor x the estimate

@@ -137,7 +137,7 @@ def chebyshev(A, dinv, b, x, degree, lo, hi):
 
 @dataclass
 class MGOptions:
-    coarse_max: int = 0    # 0 = by dimension: 1000 nodes in 3D, 400 in 2D
+    coarse_max: int = 0    # 0 = by dimension: 2200 nodes in 3D, 400 in 2D
     degree: int = 2
     lo_frac: float = 0.0   # 0 = by dimension: 0.1 in 3D, 0.3 in 2D
     hi_factor: float = 1.1
@@ -187,7 +187,7 @@ def setup(A, dim, n, opts=None, elem="p1"):
         H.levels.append(lev)
         nodes = int(np.prod([v + 1 for v in n]))
         nc = coarse_cells(n)
-        cmax = opts.coarse_max if opts.coarse_max > 0 else (1000 if len(n) == 3 else 400)
+        cmax = opts.coarse_max if opts.coarse_max > 0 else (2200 if len(n) == 3 else 400)
         if nodes <= cmax or nc == n:
             break
         lev.dinv = 1.0 / A.diagonal()

@@ -70,7 +70,7 @@ void dpp_default_opts(dpp_solve_opts *o) {
   o->precision = 0;
   o->inner_rtol = 1e-4;
   o->max_refine = 20;
-  o->coarse_max = 0;  // by dimension: 1000 nodes in 3D, 400 in 2D
+  o->coarse_max = 0;  // by dimension: 2200 nodes in 3D, 400 in 2D
   o->cheb_degree = 2;
   // post-smoothing only, V(0,2) on the finest level and V(0,3) below it
   // (measured fastest to 1e-8 in 2D and 3D)

@@ -631,9 +631,12 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
     check_launch("diag_inv");
     for (DBuf *b : {&L.b, &L.xa, &L.xb, &L.d, &L.r, &L.e}) b->alloc(sizeof(double) * 2 * gl.N);
     Grid gc = coarse_grid(gl);
-    // coarsest size: given, or by dimension (in 2D the dense coarse inverses of
-    // ~1000-node levels cost more than one more cheap level)
-    const long cmax = o.coarse_max > 0 ? o.coarse_max : (dim_of(D) == 3 ? 1000 : 400);
+    // coarsest size: given, or by dimension.  In 3D an exact solve on a level
+    // of up to 2200 nodes (13^3 below 97^3) applies its dense inverse faster
+    // than the V-cycle over the two levels under it, and being exact one level
+    // higher also saves FGMRES iterations (96^3 log-normal: 27 -> 23); in 2D
+    // the dense inverses of ~1000-node levels cost more than one more cheap level.
+    const long cmax = o.coarse_max > 0 ? o.coarse_max : (dim_of(D) == 3 ? 2200 : 400);
     const bool last = gl.N <= cmax || gc.N == gl.N || (int)pc->lv.size() >= 16;
     if (last) break;
     // Chebyshev bounds from normalised power steps on D^-1 A; the norms stay
