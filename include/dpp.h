@@ -47,7 +47,9 @@ typedef enum {
   DPP_ERR_NOT_CONVERGED = 4, /* iteration limit reached; x holds the last iterate */
   DPP_ERR_NUMERIC = 5,       /* NaN/Inf met in the input or the iteration */
   DPP_ERR_BREAKDOWN = 6,     /* Krylov breakdown without convergence */
-  DPP_ERR_UNSUPPORTED = 7    /* valid request this version does not implement */
+  DPP_ERR_UNSUPPORTED = 7,   /* valid request this version does not implement */
+  DPP_ERR_STAGNATED = 8      /* restart cycles stopped reducing the residual (stag_cycles);
+                                x holds the last iterate */
 } dpp_status;
 
 typedef struct dpp_problem_s *dpp_problem;
@@ -129,7 +131,18 @@ typedef struct {
  *   cheb_post_coarse [3]: Chebyshev degrees of the V-cycle's pre- and
  *     post-smoothing on the finest level and on the coarser smoothing levels;
  *     -1 = cheb_degree.  A pre degree of 0 skips pre-smoothing (the level
- *     restricts its right-hand side directly); post degrees are >= 1. */
+ *     restricts its right-hand side directly); post degrees are >= 1.
+ *   inner_maxiter [0]: mixed mode: iteration limit of one inner solve
+ *     (0 = what is left of maxiter).
+ *   schedule [-1]: kernel schedule of the multigrid levels, fixed at setup:
+ *     -1 = autotuned per level (timed candidates); s in 0..9 = one shape on
+ *     every level: lanes per stencil row {two rows per lane, 1, 2, 4, 8}[s % 5],
+ *     symmetric half storage when s >= 5.
+ *   stag_cycles [3], stag_ratio [0.999]: the solve stops with
+ *     DPP_ERR_STAGNATED once stag_cycles restart cycles in a row have each
+ *     ended with the true residual above stag_ratio times its value at the
+ *     start of the cycle (0 = no stagnation test; stag_ratio in (0, 1]).  In
+ *     mixed mode the test applies to the refinement sweeps. */
 typedef struct {
   int restart;
   int maxiter;
@@ -144,6 +157,10 @@ typedef struct {
   int power_iters;
   int use_graph;
   int cheb_pre_fine, cheb_post_fine, cheb_pre_coarse, cheb_post_coarse;
+  int inner_maxiter;
+  int schedule;
+  int stag_cycles;
+  double stag_ratio;
 } dpp_solve_opts;
 
 typedef struct {
@@ -153,6 +170,7 @@ typedef struct {
   int converged;    /* 1 when the rtol test on the true residual passed */
   double rel_residual; /* ||f - K x|| / ||f|| in FP64 at exit */
   double ms_solve;  /* wall time of the call, milliseconds */
+  double ms_setup;  /* wall time of the preconditioner's setup (dpp_setup_precond) */
 } dpp_solve_stats;
 
 void dpp_default_opts(dpp_solve_opts *opts);
@@ -222,7 +240,8 @@ dpp_status dpp_level_spmv(dpp_precond pc, int level, int net, const double *x, d
  * preconditioned with pc (the outer GMRES picks up the inter-network coupling
  * the preconditioner drops).  x: in = initial guess, out = solution.  stats may
  * be NULL.  Returns DPP_ERR_NOT_CONVERGED (x = last iterate, stats filled)
- * when maxiter is reached. */
+ * when maxiter is reached, DPP_ERR_STAGNATED (likewise) when the restart
+ * cycles stop reducing the residual (stag_cycles, stag_ratio). */
 dpp_status dpp_solve(dpp_problem prob, dpp_precond pc, const dpp_solve_opts *opts,
                      const double *rhs, double *x, dpp_solve_stats *stats, void *stream);
 
@@ -316,9 +335,13 @@ dpp_status dpp_batch_sizes(dpp_batch b, int64_t *total_dof, int64_t *offsets);
 /* Lanes per row chosen by the autotuner per multigrid level index (host, [16]). */
 dpp_status dpp_batch_lanes(dpp_batch b, int *n_levels, int *lanes);
 /* Solve every instance: x_concat (device [total_dof]) in = initial guess,
- * out = solution; stats: host array [nb] or NULL.  precision 0 or 2 (the FP32
- * preconditioner); returns DPP_ERR_NOT_CONVERGED when an instance stopped at
- * maxiter. */
+ * out = solution; stats: host array [nb] or NULL.  precision 0, 1 (FP64
+ * iterative refinement on every instance's true residual around one batched
+ * inner FGMRES with the FP32 K product and FP32 preconditioner per sweep) or 2
+ * (the FP32 preconditioner); the stagnation test applies per instance (to the
+ * refinement sweeps with precision 1).  Returns DPP_ERR_STAGNATED when an
+ * instance was stopped by it, else DPP_ERR_NOT_CONVERGED when an instance
+ * stopped at maxiter (or max_refine). */
 dpp_status dpp_solve_batch(dpp_batch b, const dpp_solve_opts *opts, double *x_concat,
                            dpp_solve_stats *stats, void *stream);
 /* Test hooks on concatenated vectors (device [total_dof]): y = K x and

@@ -11,7 +11,7 @@ lib_path = os.path.join(_HERE, "libdpp.so")
 _lib = None
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "ERR_NOT_CONVERGED",
-          5: "ERR_NUMERIC", 6: "ERR_BREAKDOWN", 7: "ERR_UNSUPPORTED"}
+          5: "ERR_NUMERIC", 6: "ERR_BREAKDOWN", 7: "ERR_UNSUPPORTED", 8: "ERR_STAGNATED"}
 
 
 class DppError(RuntimeError):
@@ -40,12 +40,15 @@ class _Opts(C.Structure):
                 ("coarse_max", C.c_int), ("cheb_degree", C.c_int), ("cheb_lo_frac", C.c_double),
                 ("cheb_hi_factor", C.c_double), ("power_iters", C.c_int), ("use_graph", C.c_int),
                 ("cheb_pre_fine", C.c_int), ("cheb_post_fine", C.c_int),
-                ("cheb_pre_coarse", C.c_int), ("cheb_post_coarse", C.c_int)]
+                ("cheb_pre_coarse", C.c_int), ("cheb_post_coarse", C.c_int),
+                ("inner_maxiter", C.c_int), ("schedule", C.c_int), ("stag_cycles", C.c_int),
+                ("stag_ratio", C.c_double)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("refinements", C.c_int),
-                ("converged", C.c_int), ("rel_residual", C.c_double), ("ms_solve", C.c_double)]
+                ("converged", C.c_int), ("rel_residual", C.c_double), ("ms_solve", C.c_double),
+                ("ms_setup", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -247,7 +250,7 @@ class Problem:
         x = torch.zeros(self.n_dof, dtype=torch.float64, device="cuda") if x0 is None else x0.clone()
         st = SolveStats()
         _check(lib().dpp_solve(self.handle, pc.handle, C.byref(o), _ptr(rhs), _ptr(x), C.byref(st),
-                               _stream(stream)), allow=(4,) if allow_unconverged else ())
+                               _stream(stream)), allow=(4, 8) if allow_unconverged else ())
         return x, st
 
     def solve_adjoint(self, pc, g, stream=None, **opts):
@@ -366,7 +369,7 @@ class Batch:
         x = torch.zeros(self.n_dof, dtype=torch.float64, device="cuda") if x0 is None else x0.clone()
         st = (SolveStats * self.nb)()
         _check(lib().dpp_solve_batch(self.handle, C.byref(o), _ptr(x), st, _stream(stream)),
-               allow=(4,) if allow_unconverged else ())
+               allow=(4, 8) if allow_unconverged else ())
         return x, [st[i] for i in range(self.nb)]
 
     def spmv(self, x, stream=None):

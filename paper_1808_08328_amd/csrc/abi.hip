@@ -50,6 +50,10 @@ void check_opts(const dpp_solve_opts &o) {
             "cheb_lo_frac must be 0 (by dimension) or in (0,1)");
   DPP_CHECK(o.cheb_hi_factor >= 1.0, DPP_ERR_ARG, "cheb_hi_factor must be >= 1");
   DPP_CHECK(o.power_iters >= 1, DPP_ERR_ARG, "power_iters must be >= 1");
+  DPP_CHECK(o.inner_maxiter >= 0, DPP_ERR_ARG, "inner_maxiter must be >= 0");
+  DPP_CHECK(o.schedule >= -1 && o.schedule <= 9, DPP_ERR_ARG, "schedule must be -1 or 0..9");
+  DPP_CHECK(o.stag_cycles >= 0, DPP_ERR_ARG, "stag_cycles must be >= 0");
+  DPP_CHECK(o.stag_ratio > 0.0 && o.stag_ratio <= 1.0, DPP_ERR_ARG, "stag_ratio must be in (0, 1]");
 }
 
 void set_device_of(const void *p) {
@@ -82,6 +86,10 @@ void dpp_default_opts(dpp_solve_opts *o) {
   o->cheb_hi_factor = 1.1;
   o->power_iters = 15;
   o->use_graph = 0;
+  o->inner_maxiter = 0;
+  o->schedule = -1;
+  o->stag_cycles = 3;
+  o->stag_ratio = 0.999;
 }
 
 const char *dpp_last_error(void) { return g_last_error.c_str(); }
@@ -156,7 +164,11 @@ dpp_status dpp_setup_precond(dpp_problem P, const dpp_solve_opts *opts, void *st
       dpp_default_opts(&pc->opts);
     try {
       check_opts(pc->opts);
+      const auto t0 = std::chrono::steady_clock::now();
       dpp::precond_setup(pc, S(stream));
+      DPP_HIP(hipStreamSynchronize(S(stream)));
+      pc->ms_setup =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     } catch (...) {
       delete pc;
       throw;
@@ -242,6 +254,7 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
       o.power_iters = pc->opts.power_iters;
       o.cheb_lo_frac = pc->opts.cheb_lo_frac;
       o.cheb_hi_factor = pc->opts.cheb_hi_factor;
+      o.schedule = pc->opts.schedule;
     }
     // a rejected call leaves the handle as it was
     check_opts(o);
@@ -286,6 +299,11 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
         pc->rtmp.alloc(sizeof(double) * n);
       }
       double *e = pc->xtmp.as<double>(), *r = pc->rtmp.as<double>();
+      dpp::Stagnation stag(o.stag_cycles, o.stag_ratio);
+      // the inner solves stop at their own tolerance; stagnation is judged on
+      // the refinement sweeps
+      dpp_solve_opts oi = o;
+      oi.stag_cycles = 0;
       while (true) {
         dpp::residual_K(P, b, x, r, s);
         const double rn = dpp::norm2(r, n, pc->part.as<double>(), s);
@@ -300,8 +318,14 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
           res.status = DPP_ERR_NOT_CONVERGED;
           break;
         }
+        if (stag.stalled(rn)) {
+          res.status = DPP_ERR_STAGNATED;
+          break;
+        }
         DPP_HIP(hipMemsetAsync(e, 0, sizeof(double) * n, s));
-        dpp::SolveResult in = dpp::fgmres(P, pc, o, r, e, 1, o.inner_rtol, o.maxiter - res.iters, rn, s);
+        const int left = o.maxiter - res.iters;
+        const int lim = o.inner_maxiter > 0 ? std::min(o.inner_maxiter, left) : left;
+        dpp::SolveResult in = dpp::fgmres(P, pc, oi, r, e, 1, o.inner_rtol, lim, rn, s);
         if (in.status == DPP_ERR_NUMERIC) {
           res.status = in.status;
           break;
@@ -315,10 +339,11 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
     if (singular) dpp::normalize_pressures(P, x, s);  // int p1 = 0
     DPP_HIP(hipStreamSynchronize(s));
     if (res.status != DPP_OK) {
-      throw dpp::Error(res.status, res.status == DPP_ERR_NOT_CONVERGED
-                                       ? "iteration limit reached before the tolerance"
-                                       : res.status == DPP_ERR_NUMERIC ? "NaN/Inf in the iteration"
-                                                                      : "Krylov breakdown");
+      throw dpp::Error(res.status,
+                       res.status == DPP_ERR_NOT_CONVERGED ? "iteration limit reached before the tolerance"
+                       : res.status == DPP_ERR_STAGNATED   ? "restart cycles stopped reducing the residual"
+                       : res.status == DPP_ERR_NUMERIC     ? "NaN/Inf in the iteration"
+                                                           : "Krylov breakdown");
     }
   });
   if (stats) {
@@ -329,6 +354,7 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
     stats->rel_residual = res.rel;
     stats->ms_solve =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    stats->ms_setup = pc ? pc->ms_setup : 0.0;
   }
   return st;
 }
@@ -473,6 +499,9 @@ dpp_status dpp_solve_batch(dpp_batch B, const dpp_solve_opts *opts, double *x, d
     check_opts(o);
     st.resize(B->nb);
     dpp::batch_solve(B, o, x, st.data(), S(stream));
+    for (int i = 0; i < B->nb; ++i)
+      if (!st[i].converged && B->stalled.size() == st.size() && B->stalled[i])
+        throw dpp::Error(DPP_ERR_STAGNATED, "an instance's restart cycles stopped reducing its residual");
     for (auto &s : st)
       if (!s.converged) throw dpp::Error(DPP_ERR_NOT_CONVERGED, "an instance reached maxiter");
   });
@@ -482,6 +511,7 @@ dpp_status dpp_solve_batch(dpp_batch B, const dpp_solve_opts *opts, double *x, d
     for (int i = 0; i < (int)st.size(); ++i) {
       stats[i] = st[i];
       stats[i].ms_solve = ms;
+      stats[i].ms_setup = 0.0;
     }
   return status;
 }

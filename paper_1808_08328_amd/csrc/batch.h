@@ -83,6 +83,8 @@ struct dpp_batch_s {
   dpp::DBuf active, fac, nks, ydev;
   std::vector<int> hact;                 // host copy of the active flags (profiling bytes)
   dpp::DBuf V, Z, w, part, hb, rtmp;
+  dpp::DBuf fref, rref, eref;            // iterative refinement: f, residual, correction
+  std::vector<int> stalled;              // instances the last solve stopped for stagnation
   int ws_m = 0;
   bool has32 = false;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;

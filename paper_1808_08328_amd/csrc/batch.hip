@@ -424,10 +424,10 @@ int level_cblocks(dpp_batch B, int l) {
 // once, each vector read or written once, as for the single-instance kernels.
 bool running(dpp_batch B, int i) { return i < (int)B->hact.size() && B->hact[i]; }
 
-double bytes_spmv(dpp_batch B, bool resid) {
+double bytes_spmv(dpp_batch B, bool resid, bool fp32) {
   double t = 0.0;
   for (int i = 0; i < B->nb; ++i)
-    if (running(B, i)) t += kbytes(B->P[i]->g, false, resid);
+    if (running(B, i)) t += kbytes(B->P[i]->g, fp32, resid);
   return t;
 }
 
@@ -582,18 +582,25 @@ void precond_b(dpp_batch B, const double *r, double *z, bool fp32, hipStream_t s
   check_launch("batched precond");
 }
 
+// y = K x (or bsub - K x) for the active instances; op32 reads the FP32 copy
+// of the half storage (the inner solves of iterative refinement)
 template <int D>
-void spmv_b(dpp_batch B, const double *x, const double *bsub, double *y, hipStream_t s) {
-  ProfScope ps(PF_B_SPMV_K, prof_on() ? bytes_spmv(B, bsub != nullptr) : 0.0, s);
-  (B->any_bc ? kb_spmv_K<D, double, true> : kb_spmv_K<D, double, false>)
-      <<<B->kd.blocks, 256, 0, s>>>(B->kd.get(), B->kd.count, B->active.as<int>(), x, bsub, y);
+void spmv_b(dpp_batch B, const double *x, const double *bsub, double *y, hipStream_t s,
+            bool op32 = false) {
+  ProfScope ps(PF_B_SPMV_K, prof_on() ? bytes_spmv(B, bsub != nullptr, op32) : 0.0, s);
+  if (op32)
+    (B->any_bc ? kb_spmv_K<D, float, true> : kb_spmv_K<D, float, false>)
+        <<<B->kd32.blocks, 256, 0, s>>>(B->kd32.get(), B->kd32.count, B->active.as<int>(), x, bsub, y);
+  else
+    (B->any_bc ? kb_spmv_K<D, double, true> : kb_spmv_K<D, double, false>)
+        <<<B->kd.blocks, 256, 0, s>>>(B->kd.get(), B->kd.count, B->active.as<int>(), x, bsub, y);
   check_launch("batched spmv");
 }
 
 // one Arnoldi step j for every active instance: z_j = M^-1 v~_j, w = K z_j and
 // the two DCGS2 passes (graph-capturable: launches only)
 template <int D>
-void arnoldi_step_b(dpp_batch B, int j, bool fp32, hipStream_t s) {
+void arnoldi_step_b(dpp_batch B, int j, bool fp32, bool op32, hipStream_t s) {
   const long n = B->ntot;
   double *V = B->V.as<double>(), *Z = B->Z.as<double>(), *w = B->w.as<double>();
   double *part = B->part.as<double>(), *hb = B->hb.as<double>();
@@ -601,7 +608,7 @@ void arnoldi_step_b(dpp_batch B, int j, bool fp32, hipStream_t s) {
   const VDesc *vd = B->vd.get();
   const int nvd = B->vd.count, tb = B->vd.blocks;
   precond_b<D>(B, V + (size_t)j * n, Z + (size_t)j * n, fp32, s);
-  spmv_b<D>(B, Z + (size_t)j * n, nullptr, w, s);
+  spmv_b<D>(B, Z + (size_t)j * n, nullptr, w, s, op32);
   // A reads V_0..V_j and w; B reads them again, writes v_j (j > 0) and v~_{j+1}
   ProfScope ps(PF_B_ARNOLDI, prof_on() ? 8.0 * running_dof(B) * (2.0 * j + 4.0 + (j > 0 ? 2.0 : 1.0)) : 0.0,
                s);
@@ -744,6 +751,7 @@ void batch_make32(dpp_batch B, hipStream_t s) {
     DPP_HIP(hipMemcpy(&k, B->kd.get() + i, sizeof(KDesc), hipMemcpyDeviceToHost));
     k.rhat = B->pc[i]->lv[0]->b32.ptr;
     k.zp = B->pc[i]->lv[0]->e32.ptr;
+    k.kv = B->P[i]->kh32.ptr;  // FP32 half storage (made by precond_make32)
     kv.push_back(k);
   }
   B->kd32.upload(kv, B->kd.blocks);
@@ -764,9 +772,16 @@ void batch_make32(dpp_batch B, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- solve --
+// Batched flexible GMRES(m) on K x = rhs (rhs NULL: the assembled f, with the
+// consistent part for pure-flux instances) to rtol, at most maxiter iterations
+// per instance.  mode 0: FP64 operator and preconditioner; 1: FP32 operator
+// and preconditioner (inner solves of iterative refinement); 2: FP64 operator,
+// FP32 preconditioner.  Instances with skip[i] set do not run (x_i unchanged).
+// stall[i] is set for instances stopped by the stagnation test.
 template <int D>
-void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_stats *st,
-                  hipStream_t s) {
+void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, const double *rhs, double *x,
+                  dpp_solve_stats *st, double rtol, int maxiter, int mode,
+                  const std::vector<int> *skip, std::vector<int> &stall, hipStream_t s) {
   const int nb = B->nb, m = o.restart;
   const bool use_graph = o.use_graph != 0 && !prof_on();
   // Graphs are captured on a stream the library owns (the caller's stream may
@@ -783,7 +798,7 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
     s = B->gstream;
   }
   const long n = B->ntot;
-  const bool fp32 = o.precision == 2;
+  const bool fp32 = mode != 0, op32 = mode == 1;
   DPP_CHECK(2 * (m - 1) + 1 <= MV_PART_ROWS - 1 && m <= BMAXK - 1 &&
                 (size_t)B->vd.blocks * MV_PART_ROWS * sizeof(double) <= B->part.bytes,
             DPP_ERR_ARG, "batched Krylov reduction buffer too small for the restart length");
@@ -798,15 +813,25 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
     for (auto &g : B->graphs) (void)hipGraphExecDestroy(g.second);
     B->graphs.clear();
   }
-  double *V = B->V.as<double>(), *f = B->rtmp.as<double>();
-  // concatenated right-hand side; a pure-flux instance (singular K) solves
-  // for the consistent part of its f, as the single-instance solve does
-  for (int i = 0; i < nb; ++i) {
-    DPP_HIP(hipMemcpyAsync(f + B->doff[i], B->P[i]->f.ptr, sizeof(double) * B->P[i]->ndof(),
-                           hipMemcpyDeviceToDevice, s));
-    if (pure_flux(B->P[i]->g)) consistent_rhs(B->P[i], f + B->doff[i], s);
+  double *V = B->V.as<double>();
+  const double *f = rhs;
+  if (!f) {
+    // concatenated right-hand side; a pure-flux instance (singular K) solves
+    // for the consistent part of its f, as the single-instance solve does
+    double *fc = B->rtmp.as<double>();
+    for (int i = 0; i < nb; ++i) {
+      DPP_HIP(hipMemcpyAsync(fc + B->doff[i], B->P[i]->f.ptr, sizeof(double) * B->P[i]->ndof(),
+                             hipMemcpyDeviceToDevice, s));
+      if (pure_flux(B->P[i]->g)) consistent_rhs(B->P[i], fc + B->doff[i], s);
+    }
+    f = fc;
   }
   std::vector<int> act(nb, 1), conv(nb, 0), its(nb, 0), rest(nb, 0);
+  std::vector<Stagnation> stg(nb, Stagnation(o.stag_cycles, o.stag_ratio));
+  stall.assign(nb, 0);
+  // skipped instances count as finished from the start
+  if (skip)
+    for (int i = 0; i < nb; ++i) conv[i] = (*skip)[i] ? 1 : 0;
   std::vector<double> bn, rn(nb, 0.0);
   auto upload_active = [&]() {
     B->hact = act;
@@ -847,15 +872,15 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
   };
   auto enqueue = [&](int j) {
     if (!use_graph) {
-      arnoldi_step_b<D>(B, j, fp32, s);
+      arnoldi_step_b<D>(B, j, fp32, op32, s);
       return;
     }
-    auto key = std::make_pair(j, (fp32 ? 1 : 0) + 2 * cycle_code(B->opts));
+    auto key = std::make_pair(j, mode + 3 * cycle_code(B->opts));
     auto itg = B->graphs.find(key);
     if (itg == B->graphs.end()) {
       hipGraph_t graph;
       DPP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      arnoldi_step_b<D>(B, j, fp32, s);
+      arnoldi_step_b<D>(B, j, fp32, op32, s);
       DPP_HIP(hipStreamEndCapture(s, &graph));
       hipGraphExec_t ex;
       const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
@@ -869,20 +894,22 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
   while (true) {
     // true residuals of the instances still running
     for (int i = 0; i < nb; ++i) act[i] = !conv[i];
+    for (int i = 0; i < nb; ++i)
+      if (stall[i]) act[i] = 0;
     upload_active();
-    spmv_b<D>(B, x, f, V, s);
+    spmv_b<D>(B, x, f, V, s, op32);
     norms_b(B, V, 1, rn, s);
-    if (getenv("DPP_BATCH_VERBOSE"))
-      for (int i = 0; i < nb; ++i)
-        fprintf(stderr, "batch cycle: inst %d its %d bn %.6e rn %.6e conv %d\n", i, its[i], bn[i], rn[i], conv[i]);
     bool any = false;
     for (int i = 0; i < nb; ++i) {
-      if (conv[i]) continue;
+      if (conv[i] || stall[i]) continue;
       DPP_CHECK(std::isfinite(rn[i]), DPP_ERR_NUMERIC, "NaN/Inf in a batched residual");
-      if (bn[i] == 0.0 || rn[i] <= o.rtol * bn[i]) {
+      if (bn[i] == 0.0 || rn[i] <= rtol * bn[i]) {
         conv[i] = 1;
         act[i] = 0;
-      } else if (its[i] >= o.maxiter) {
+      } else if (its[i] >= maxiter) {
+        act[i] = 0;
+      } else if (stg[i].stalled(rn[i])) {
+        stall[i] = 1;
         act[i] = 0;
       } else {
         any = true;
@@ -908,7 +935,7 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
         if (!act[i]) continue;
         const double *gp = &gpre[(size_t)i * (m + 1)];
         const double pred = j >= 1 ? gp[j] * gp[j] / std::fabs(gp[j - 1]) : gp[0];
-        if (its[i] + 1 < o.maxiter && std::fabs(pred) > 4.0 * o.rtol * bn[i]) want = true;
+        if (its[i] + 1 < maxiter && std::fabs(pred) > 4.0 * rtol * bn[i]) want = true;
       }
       const bool queued = j + 1 < m && want;
       if (queued) enqueue(j + 1);
@@ -943,7 +970,7 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
           } else {
             kused[i] = j + 1;
             const double res = std::fabs(gpre[(size_t)i * (m + 1) + j + 1]);
-            end = res <= o.rtol * bn[i] || its[i] >= o.maxiter || hn <= 1e-300 || j + 1 == m;
+            end = res <= rtol * bn[i] || its[i] >= maxiter || hn <= 1e-300 || j + 1 == m;
           }
         }
         if (end) {
@@ -981,15 +1008,15 @@ void batch_fgmres(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_sta
     check_launch("batched update");
     bool progress = false;
     for (int i = 0; i < nb; ++i)
-      if (!conv[i] && its[i] < o.maxiter) progress = true;
+      if (!conv[i] && !stall[i] && its[i] < maxiter) progress = true;
     if (!progress) {
       // final residuals for the report
       for (int i = 0; i < nb; ++i) act[i] = 1;
       upload_active();
-      spmv_b<D>(B, x, f, V, s);
+      spmv_b<D>(B, x, f, V, s, op32);
       norms_b(B, V, 1, rn, s);
       for (int i = 0; i < nb; ++i)
-        if (!conv[i] && bn[i] > 0 && rn[i] <= o.rtol * bn[i]) conv[i] = 1;
+        if (!conv[i] && bn[i] > 0 && rn[i] <= rtol * bn[i]) conv[i] = 1;
       break;
     }
   }
@@ -1022,14 +1049,99 @@ void batch_apply(dpp_batch B, int what, const double *x, double *y, hipStream_t 
   DPP_HIP(hipStreamSynchronize(s));
 }
 
+// Iterative refinement of the batch (precision 1): FP64 true residuals of
+// every instance, inner batched FGMRES with the FP32 operator and FP32
+// preconditioner to inner_rtol on the instances still running, x += e.
+template <int D>
+void batch_refine(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_stats *st,
+                  std::vector<int> &stall, hipStream_t s) {
+  const int nb = B->nb;
+  const long n = B->ntot;
+  if (!B->fref.ptr) {
+    B->fref.alloc(sizeof(double) * n);
+    B->rref.alloc(sizeof(double) * n);
+    B->eref.alloc(sizeof(double) * n);
+  }
+  double *f = B->fref.as<double>(), *r = B->rref.as<double>(), *e = B->eref.as<double>();
+  for (int i = 0; i < nb; ++i) {
+    DPP_HIP(hipMemcpyAsync(f + B->doff[i], B->P[i]->f.ptr, sizeof(double) * B->P[i]->ndof(),
+                           hipMemcpyDeviceToDevice, s));
+    if (pure_flux(B->P[i]->g)) consistent_rhs(B->P[i], f + B->doff[i], s);
+  }
+  std::vector<int> ones(nb, 1);
+  B->hact = ones;
+  DPP_HIP(hipMemcpyAsync(B->active.ptr, ones.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+  std::vector<double> bn, rn;
+  norms_b(B, f, 0, bn, s);
+  std::vector<int> conv(nb, 0), done(nb, 0), its(nb, 0), rest(nb, 0), refs(nb, 0), inner_stall;
+  std::vector<Stagnation> stg(nb, Stagnation(o.stag_cycles, o.stag_ratio));
+  std::vector<dpp_solve_stats> sti(nb);
+  stall.assign(nb, 0);
+  // the inner solves stop at their own tolerance; stagnation is judged on
+  // the refinement sweeps
+  dpp_solve_opts oi = o;
+  oi.stag_cycles = 0;
+  for (int sweep = 0;; ++sweep) {
+    B->hact = ones;
+    DPP_HIP(hipMemcpyAsync(B->active.ptr, ones.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+    spmv_b<D>(B, x, f, r, s);
+    norms_b(B, r, 1, rn, s);
+    bool any = false;
+    for (int i = 0; i < nb; ++i) {
+      if (done[i]) continue;
+      DPP_CHECK(std::isfinite(rn[i]), DPP_ERR_NUMERIC, "NaN/Inf in a batched refinement residual");
+      if (bn[i] == 0.0 || rn[i] <= o.rtol * bn[i]) {
+        conv[i] = 1;
+        done[i] = 1;
+      } else if (its[i] >= o.maxiter || sweep >= o.max_refine) {
+        done[i] = 1;
+      } else if (stg[i].stalled(rn[i])) {
+        stall[i] = 1;
+        done[i] = 1;
+      } else {
+        any = true;
+      }
+    }
+    if (!any) break;
+    DPP_HIP(hipMemsetAsync(e, 0, sizeof(double) * n, s));
+    const int lim = o.inner_maxiter > 0 ? o.inner_maxiter : o.maxiter;
+    batch_fgmres<D>(B, oi, r, e, sti.data(), o.inner_rtol, lim, 1, &done, inner_stall, s);
+    axpby(n, 1.0, e, 1.0, x, s);
+    for (int i = 0; i < nb; ++i)
+      if (!done[i]) {
+        its[i] += sti[i].iters;
+        rest[i] += sti[i].restarts;
+        refs[i]++;
+      }
+  }
+  for (int i = 0; i < nb; ++i)
+    if (pure_flux(B->P[i]->g)) normalize_pressures(B->P[i], x + B->doff[i], s);
+  DPP_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < nb; ++i) {
+    st[i].iters = its[i];
+    st[i].restarts = rest[i];
+    st[i].refinements = refs[i];
+    st[i].converged = conv[i];
+    st[i].rel_residual = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
+    st[i].ms_solve = 0.0;
+  }
+}
+
 void batch_solve(dpp_batch B, const dpp_solve_opts &o, double *x, dpp_solve_stats *st, hipStream_t s) {
-  if (o.precision == 2) batch_make32(B, s);
-  DPP_CHECK(o.precision != 1, DPP_ERR_UNSUPPORTED,
-            "batched solves support precision 0 (FP64) and 2 (FP32 preconditioner)");
+  if (o.precision != 0) batch_make32(B, s);
+  std::vector<int> &stall = B->stalled;
+  if (o.precision == 1) {
+    if (B->dim == 3)
+      batch_refine<3>(B, o, x, st, stall, s);
+    else
+      batch_refine<2>(B, o, x, st, stall, s);
+    return;
+  }
+  const int mode = o.precision == 2 ? 2 : 0;
   if (B->dim == 3)
-    batch_fgmres<3>(B, o, x, st, s);
+    batch_fgmres<3>(B, o, nullptr, x, st, o.rtol, o.maxiter, mode, nullptr, stall, s);
   else
-    batch_fgmres<2>(B, o, x, st, s);
+    batch_fgmres<2>(B, o, nullptr, x, st, o.rtol, o.maxiter, mode, nullptr, stall, s);
 }
 
 }  // namespace dpp

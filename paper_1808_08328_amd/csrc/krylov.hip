@@ -246,6 +246,7 @@ SolveResult fgmres(dpp_problem P, dpp_precond pc, const dpp_solve_opts &o, const
     return res;
   }
   hipEvent_t ev = pc->hev;
+  Stagnation stag(o.stag_cycles, o.stag_ratio);
   while (true) {
     // true residual r = b - K x into V_0
     residual_K(P, b, x, V, s, op32);
@@ -261,6 +262,10 @@ SolveResult fgmres(dpp_problem P, dpp_precond pc, const dpp_solve_opts &o, const
     }
     if (res.iters >= maxiter) {
       res.status = DPP_ERR_NOT_CONVERGED;
+      return res;
+    }
+    if (stag.stalled(beta)) {
+      res.status = DPP_ERR_STAGNATED;
       return res;
     }
     k_scale<<<std::min(2048, blocks_for(n, 256)), 256, 0, s>>>(V, n, 1.0 / beta);

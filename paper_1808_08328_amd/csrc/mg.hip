@@ -678,8 +678,17 @@ void setup_impl(dpp_precond pc, hipStream_t s) {
   for (size_t l = 0; l + 1 < pc->lv.size(); ++l) {
     pack_half<D>(*pc->lv[l], s);
     // members of a batch run the batched kernels, whose lanes are tuned over
-    // the whole batch: their own shapes are never used
-    pc->lv[l]->shape = pc->tune_shapes ? tune_shape<D>(*pc->lv[l], s) : Shape{};
+    // the whole batch: their own shapes are never used.  A fixed schedule
+    // s in 0..9 puts lanes {pairs, 1, 2, 4, 8}[s % 5] (symmetric half storage
+    // for s >= 5) on every level.
+    static constexpr int kLanes[5] = {0, 1, 2, 4, 8};
+    const int sch = pc->opts.schedule;
+    if (!pc->tune_shapes)
+      pc->lv[l]->shape = Shape{};
+    else if (sch >= 0)
+      pc->lv[l]->shape = Shape{kLanes[sch % 5], sch >= 5};
+    else
+      pc->lv[l]->shape = tune_shape<D>(*pc->lv[l], s);
   }
   Level &Lc = *pc->lv.back();
   const int n = (int)Lc.g.N;

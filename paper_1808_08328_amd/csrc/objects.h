@@ -6,6 +6,7 @@
 #include <tuple>
 
 #include "common.h"
+#include "stagnation.h"
 
 namespace dpp {
 
@@ -108,6 +109,7 @@ struct dpp_precond_s {
   dpp::DBuf red;    // reduction scratch
   bool has32 = false;
   bool tune_shapes = true;  // autotune the level kernel shapes (off for batch members)
+  double ms_setup = 0.0;    // wall time of dpp_setup_precond
   // Krylov workspace, kept across solves
   int ws_m = 0;
   dpp::DBuf V, Z, w, part, hdev, ydev, xtmp, rtmp;

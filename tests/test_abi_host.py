@@ -38,6 +38,8 @@ def test_default_options():
     o = dpp.default_opts()
     assert o.restart == 30 and o.rtol == 1e-8 and o.precision == 0
     assert o.cheb_degree == 2 and o.coarse_max == 0
+    assert o.inner_maxiter == 0 and o.schedule == -1
+    assert o.stag_cycles == 3 and o.stag_ratio == 0.999
     with pytest.raises(TypeError):
         dpp.default_opts(nonsense=1)
 

@@ -87,7 +87,7 @@ def test_batch_fp32_preconditioner_and_3d(cycle):
     probs = [I.grf_problem(3, 5), I.mms_problem(3, (6, 4, 5), k2=1e-2), I.grf_problem(3, 7)]
     names = ("cheb_pre_fine", "cheb_post_fine", "cheb_pre_coarse", "cheb_post_coarse")
     B = dpp.assemble_batch(probs, coarse_max=40, **(dict(zip(names, cycle)) if cycle else {}))
-    for precision in (0, 2):
+    for precision in (0, 1, 2):
         x, st = B.solve(rtol=1e-10, precision=precision)
         assert all(s.converged for s in st)
         for i, pr in enumerate(probs):
@@ -165,7 +165,7 @@ def test_batch_pure_flux_instances_match_oracle(dim):
     for pr in probs:
         S = odpp.assemble(pr)
         refs.append((S, odpp.solve_pure_flux(S) if odpp.pure_flux(pr) else odpp.solve_direct(S.K, S.f)))
-    for precision, tol in ((0, 1e-9), (2, 1e-9)):
+    for precision, tol in ((0, 1e-9), (1, 1e-9), (2, 1e-9)):
         xsol, st = B.solve(rtol=1e-13, precision=precision)
         assert all(s.converged for s in st), precision
         for i, (S, xo) in enumerate(refs):
@@ -180,7 +180,8 @@ def test_batch_pure_flux_instances_match_oracle(dim):
 def test_full_size_batch_oracle_residuals():
     """The benchmark's batch at full size (64 uneven 2D instances, 32^2..256^2
     cells, 9,131,268 DOF) in the benchmark's launch configuration (hipGraph
-    replay of the Arnoldi steps; FP64 and FP32 preconditioner): every
+    replay of the Arnoldi steps; FP64, iterative refinement with FP32 inner
+    solves, and the FP32 preconditioner): every
     instance's solution against the oracle's own K and f of that instance, and
     the batched K product against the oracle's K on a random vector."""
     import paper_1808_08328_amd as dpp
@@ -192,7 +193,7 @@ def test_full_size_batch_oracle_residuals():
     yb = [H(v) for v in B.split(B.spmv(x))]
     xs = [H(v) for v in B.split(x)]
     sols = {}
-    for precision in (0, 2):
+    for precision in (0, 1, 2):
         xsol, st = B.solve(rtol=1e-8, precision=precision, use_graph=1)
         assert all(s.converged for s in st), precision
         sols[precision] = [H(v) for v in B.split(xsol)]
@@ -201,6 +202,6 @@ def test_full_size_batch_oracle_residuals():
         ref = S.K @ xs[i]
         assert np.abs(yb[i] - ref).max() <= 1e-13 * np.abs(ref).max(), ("spmv", i)
         fn = np.linalg.norm(S.f)
-        for precision in (0, 2):
+        for precision in (0, 1, 2):
             r = S.f - S.K @ sols[precision][i]
             assert np.linalg.norm(r) <= 1.05e-8 * fn, (precision, i, np.linalg.norm(r) / fn)
