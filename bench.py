@@ -84,8 +84,9 @@ def stencil_tag(prob):
     return prob.dim + (10 if getattr(prob, "elem", "p1") == "q1" else 0)
 
 
-def measured_traffic(family, launches_bytes):
-    """HBM traffic per launch from a committed rocprofv3 counter summary, if it
+def measured_traffic(workload, family):
+    """HBM bytes per launch of a single-kernel family on a workload, from the
+    committed rocprofv3 counter summary (profiles/traffic_counters.json), if it
     was taken on the current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
@@ -96,7 +97,7 @@ def measured_traffic(family, launches_bytes):
         return None
     if d.get("source_sha") != kernel_source_sha():
         return None
-    ent = d.get("families", {}).get(family)
+    ent = d.get("workloads", {}).get(workload, {}).get("families", {}).get(family)
     return None if ent is None else ent.get("bytes_per_launch")
 
 
@@ -230,14 +231,17 @@ def profiled(dpp, run, steps):
     return kernels
 
 
-def roofline(kernels, candidates, copy_gbs, name_of):
-    """Roofline object of the candidate family with the largest time share."""
+def roofline(kernels, candidates, copy_gbs, name_of, workload):
+    """Roofline object of the candidate family with the largest time share;
+    traffic: its measured HBM bytes per launch on this workload (counters)."""
     dom = max((k for k in kernels if k in candidates), key=lambda k: kernels[k]["ms_per_solve"])
     n, t, by = kernels[dom]["_raw"]
     achieved = by / (t * 1e6)
     per_launch = by / n
+    traffic = measured_traffic(workload, dom)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(dom, per_launch),
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "traffic_over_algorithmic": round(traffic / per_launch, 3) if traffic else None,
             "kernel": dom, "kernel_name": name_of(dom),
             "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": 1e3 * t / n,
             "copy_ceiling": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
@@ -322,7 +326,7 @@ def bench_batch(args, torch, I, dpp):
         line["roofline"] = roofline(kernels, BATCH_FAMILIES, copy_gbs,
                                     lambda k: {"batch_spmv_K": "kb_spmv_K<2, double, false>",
                                                "batch_cheb_S_l0": "kb_cheb<2, double, double, L> "
-                                               "(finest levels; L = lanes per row)"}[k])
+                                               "(finest levels; L = lanes per row)"}[k], args.config)
         line["kernels"] = strip_raw(kernels)
     else:
         line["roofline"] = None
@@ -432,7 +436,8 @@ def main():
         kernels = profiled(dpp, lambda: P.solve(pc, **opts), args.steps)
         line["roofline"] = roofline(kernels, SINGLE_KERNEL_FAMILIES, copy_gbs,
                                     lambda k: kernel_name(k, stencil_tag(prob), pc,
-                                                          flux=getattr(prob, "face_bc", None) is not None))
+                                                          flux=getattr(prob, "face_bc", None) is not None),
+                                    args.config)
         line["kernels"] = strip_raw(kernels)
     else:
         line["roofline"] = None

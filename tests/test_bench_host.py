@@ -18,18 +18,21 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in p.stderr
 
 
-def test_counter_traffic_follows_the_kernel_sources(monkeypatch, tmp_path):
+def test_counter_traffic_follows_the_kernel_sources_and_workload(monkeypatch, tmp_path):
     import json
     (tmp_path / "profiles").mkdir()
     (tmp_path / "profiles" / "traffic_counters.json").write_text(json.dumps(
-        {"source_sha": "abc", "families": {"cheb_S_l0": {"bytes_per_launch": 1.5e8}}}))
+        {"source_sha": "abc",
+         "workloads": {"c3_3d96_grf": {"families": {"cheb_S_l0": {"bytes_per_launch": 1.5e8}}}}}))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_sha", lambda: "abc")
-    assert bench.measured_traffic("cheb_S_l0", 1.0) == 1.5e8
-    assert bench.measured_traffic("no_such_family", 1.0) is None
+    assert bench.measured_traffic("c3_3d96_grf", "cheb_S_l0") == 1.5e8
+    assert bench.measured_traffic("c3_3d96_grf", "no_such_family") is None
+    # figures taken on another workload are not reported for this one
+    assert bench.measured_traffic("c2_3d64", "cheb_S_l0") is None
     # figures taken on other kernel sources are not reported
     monkeypatch.setattr(bench, "kernel_source_sha", lambda: "def")
-    assert bench.measured_traffic("cheb_S_l0", 1.0) is None
+    assert bench.measured_traffic("c3_3d96_grf", "cheb_S_l0") is None
 
 
 def test_kernel_source_hash_is_deterministic_hex():
