@@ -22,8 +22,11 @@ namespace dpp {
 namespace {
 
 // One workgroup of KBS threads per block of 2 KBS nodes (a node pair per
-// thread); order[] gives the node block of each workgroup (band order, below).
+// thread), or of KBS nodes with velocity faces (one node per thread: the
+// masked pair form needs 170 registers and ran 30% slower at 64^3); order[]
+// gives the node block of each workgroup (band order, below).
 constexpr int KBS = 128;
+inline int k_block_nodes(const Grid &g) { return (g.fix[0] | g.fix[1]) != 0 ? KBS : 2 * KBS; }
 
 // The K_up class table (UPT<D>) copied into LDS by every workgroup.
 template <int D, typename TV>
@@ -32,9 +35,40 @@ __device__ inline void stage_upt(TV *sut, const TV *__restrict__ upt) {
   __syncthreads();
 }
 
-// BC: the problem has velocity faces; their prescribed components have
-// identity rows (y_u = x_u there).
-template <int D, typename TV, bool BC>
+// One node per thread, for problems with velocity faces (BC): their
+// prescribed components have identity rows (y_u = x_u there).
+template <int D, typename TV>
+__global__ __launch_bounds__(256) void k_spmv_K1(GridDev g, const TV *__restrict__ kv,
+                                                 const TV *__restrict__ upt,
+                                                 const double *__restrict__ x,
+                                                 const double *__restrict__ bsub,
+                                                 double *__restrict__ y,
+                                                 const int *__restrict__ order) {
+  constexpr int d = dim_of(D);
+  __shared__ TV sut[UPT<D>::size];
+  stage_upt<D>(sut, upt);
+  const long N = g.N;
+  const long a = (long)order[blockIdx.x] * KBS + threadIdx.x;
+  if (a >= N) return;
+  double au[2][d], ap[2];
+  spmv_K_node<D, TV, true>(g, kv, sut, x, a, au, ap);
+  int ia[3];
+  node_ijk(g, a, ia[0], ia[1], ia[2]);
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const long ou = off_u(d, N, q), op = off_p(d, N, q);
+#pragma unroll
+    for (int c = 0; c < d; ++c) {
+      const long r = ou + d * a + c;
+      const double v = u_fixed(g, q, c, ia) ? x[r] : au[q][c];
+      y[r] = bsub ? bsub[r] - v : v;
+    }
+    y[op + a] = bsub ? bsub[op + a] - ap[q] : ap[q];
+  }
+}
+
+// Node pairs, for problems without velocity faces.
+template <int D, typename TV>
 __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict__ kv,
                                                 const TV *__restrict__ upt,
                                                 const double *__restrict__ x,
@@ -48,45 +82,29 @@ __global__ __launch_bounds__(256) void k_spmv_K(GridDev g, const TV *__restrict_
   const long a = 2 * ((long)order[blockIdx.x] * KBS + threadIdx.x);
   if (a >= N) return;
   double au[2][2][d], ap[2][2];
-  spmv_K_node2<D, TV, BC>(g, kv, sut, x, a, au, ap);
-  const int nr = a + 1 < N ? 2 : 1;  // node a + 1 = N has no row
-  int ia[2][3] = {{0, 0, 0}, {0, 0, 0}};
-  if constexpr (BC) {
-    node_ijk(g, a, ia[0][0], ia[0][1], ia[0][2]);
-    if (nr == 2) node_ijk(g, a + 1, ia[1][0], ia[1][1], ia[1][2]);
-  }
+  spmv_K_node2<D, TV>(g, kv, sut, x, a, au, ap);
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const long ou = off_u(d, N, q), op = off_p(d, N, q);
-    double v[2 * d], pv[2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-#pragma unroll
-      for (int c = 0; c < d; ++c) {
-        v[d * r + c] = au[r][q][c];
-        if constexpr (BC)
-          if (r < nr && u_fixed(g, q, c, ia[r])) v[d * r + c] = x[ou + d * (a + r) + c];
-      }
-      pv[r] = ap[r][q];
-    }
-    if (nr == 2) {
+    if (a + 1 < N) {
 #pragma unroll
       for (int e = 0; e < d; ++e) {
+        // values 2e, 2e + 1 of the pair's 2d velocity unknowns
+        const double v0 = au[(2 * e) / d][q][(2 * e) % d], v1 = au[(2 * e + 1) / d][q][(2 * e + 1) % d];
         double b0 = 0.0, b1 = 0.0;
         if (bsub) ld2(bsub + ou + d * a + 2 * e, b0, b1);
-        st2(y + ou + d * a + 2 * e, bsub ? b0 - v[2 * e] : v[2 * e],
-            bsub ? b1 - v[2 * e + 1] : v[2 * e + 1]);
+        st2(y + ou + d * a + 2 * e, bsub ? b0 - v0 : v0, bsub ? b1 - v1 : v1);
       }
       double b0 = 0.0, b1 = 0.0;
       if (bsub) ld2(bsub + op + a, b0, b1);
-      st2(y + op + a, bsub ? b0 - pv[0] : pv[0], bsub ? b1 - pv[1] : pv[1]);
-    } else {
+      st2(y + op + a, bsub ? b0 - ap[0][q] : ap[0][q], bsub ? b1 - ap[1][q] : ap[1][q]);
+    } else {  // node a + 1 = N has no row
 #pragma unroll
       for (int c = 0; c < d; ++c) {
         const long r = ou + d * a + c;
-        y[r] = bsub ? bsub[r] - v[c] : v[c];
+        y[r] = bsub ? bsub[r] - au[0][q][c] : au[0][q][c];
       }
-      y[op + a] = bsub ? bsub[op + a] - pv[0] : pv[0];
+      y[op + a] = bsub ? bsub[op + a] - ap[0][q] : ap[0][q];
     }
   }
 }
@@ -327,14 +345,14 @@ double kbytes(const Grid &g, bool fp32, bool resid) {
 static void launch_K(dpp_problem P, const double *x, const double *bsub, double *y, hipStream_t s,
                      bool fp32) {
   const Grid &g = P->g;
-  const int nb = blocks_for(g.N, 2 * KBS);
+  const int nb = blocks_for(g.N, k_block_nodes(g));
   const int *ord = P->korder.as<int>();
   const bool bc = (g.fix[0] | g.fix[1]) != 0;
   if (fp32)
-    DPP_TAG_SWITCH(g, ((bc ? k_spmv_K<D_, float, true> : k_spmv_K<D_, float, false>)<<<nb, KBS, 0, s>>>(
+    DPP_TAG_SWITCH(g, ((bc ? k_spmv_K1<D_, float> : k_spmv_K<D_, float>)<<<nb, KBS, 0, s>>>(
                           dev(g), P->kh32.as<float>(), P->upt32.as<float>(), x, bsub, y, ord)));
   else
-    DPP_TAG_SWITCH(g, ((bc ? k_spmv_K<D_, double, true> : k_spmv_K<D_, double, false>)<<<nb, KBS, 0, s>>>(
+    DPP_TAG_SWITCH(g, ((bc ? k_spmv_K1<D_, double> : k_spmv_K<D_, double>)<<<nb, KBS, 0, s>>>(
                           dev(g), P->kh.as<double>(), P->upt.as<double>(), x, bsub, y, ord)));
 }
 
@@ -394,9 +412,9 @@ void make_kh(dpp_problem P, hipStream_t s) {
   DPP_TAG_SWITCH(g, (k_pack_kh<D_><<<blocks_for(work, 256), 256, 0, s>>>(dev(g), P->kvals.as<double>(),
                                                                       P->kh.as<double>())));
   check_launch("pack K half storage");
-  // K product workgroups in band order (block_column_order), 2 KBS nodes each
+  // K product workgroups in band order (block_column_order)
   const long plane = g.dim == 3 ? (long)g.m[0] * g.m[1] : g.N;
-  const std::vector<int> order = block_column_order(g.N, 2 * KBS, plane);
+  const std::vector<int> order = block_column_order(g.N, k_block_nodes(g), plane);
   const long nb = (long)order.size();
   P->korder.alloc(sizeof(int) * nb);
   DPP_HIP(hipMemcpyAsync(P->korder.ptr, order.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));

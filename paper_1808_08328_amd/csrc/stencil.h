@@ -317,7 +317,8 @@ __device__ inline void spmv_K_node(const GridDev &g, const TV *__restrict__ kh, 
 // it lies before node 0 (as in row_product2).  Node a + 1 may be N (N odd): its
 // result is meaningless and must not be stored; all loads stay inside the
 // arrays (streams have the leading dimension padded(N) > N for odd N).
-template <int D, typename TV, bool BC = false>
+// Problems without velocity faces only (their masks stay in spmv_K_node).
+template <int D, typename TV>
 __device__ inline void spmv_K_node2(const GridDev &g, const TV *__restrict__ kh, const TV *ut,
                                     const double *__restrict__ x, long a,
                                     double au[2][2][dim_of(D)], double ap[2][2]) {
@@ -395,13 +396,6 @@ __device__ inline void spmv_K_node2(const GridDev &g, const TV *__restrict__ kh,
       }
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
-        if constexpr (BC) {
-#pragma unroll
-          for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int c = 0; c < d; ++c)
-              if (u_fixed(g, q, c, pb[r])) xu[r][q][c] = 0.0;
-        }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const double uu = (double)kv[q ? L::UU1 : L::UU0][r], pp = (double)kv[q ? L::PP1 : L::PP0][r];
@@ -451,13 +445,6 @@ __device__ inline void spmv_K_node2(const GridDev &g, const TV *__restrict__ kh,
       }
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
-        if constexpr (BC) {
-#pragma unroll
-          for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int c = 0; c < d; ++c)
-              if (u_fixed(g, q, c, nb[r])) xu[r][q][c] = 0.0;
-        }
         // node a's mirror exists iff dm == 0; node a + 1's iff dm >= -1
         const double mr = r == 0 ? m0 : (dm >= -1 ? 1.0 : 0.0);
 #pragma unroll
