@@ -15,6 +15,13 @@ Numbering spec (both sides implement it independently):
   * 2D cells: square h = i + n_x j is split into triangles 2h and 2h+1;
   * with Q1 elements (elem = "q1") the cells are the boxes themselves: cell h
     is hexahedron / square h.
+  * the local vertices of the simplex of permutation pi at hex corner c (the
+    hex's node with the smallest indices) are v_0 = c and v_k = v_(k-1) +
+    e_(pi(k-1)) (a path through the box along the permuted axes);
+  * DG-VMS (elem = "dg", discontinuous P1 on those simplices): every simplex
+    e owns its d + 1 vertex slots, slot e(d+1) + v for local vertex v; the
+    unknown vector is [u1 | p1 | u2 | p2] over slots (velocities slot-major,
+    components interleaved), as over nodes for P1.
 
 Manufactured solutions: Section "Two-dimensional study" and "Three-dimensional
 study" of the paper (the 3D micro-pressure carries mu/(beta k2); the printed
@@ -46,7 +53,9 @@ class Problem:
       boundary of network i, whose normal velocity is prescribed;
     u_bc_1, u_bc_2: nodal velocities [n_nodes, dim] whose normal components are
       imposed on the velocity faces (None for a network without one);
-    elem: "p1" (Kuhn simplices, P1) or "q1" (box cells, Q1).
+    elem: "p1" (Kuhn simplices, P1), "q1" (box cells, Q1) or "dg" (Kuhn
+    simplices, discontinuous P1 of the DG-VMS form: every simplex owns its
+    d + 1 vertex slots; nodal p0 data are read at the boundary vertices).
     """
     dim: int
     n: tuple
@@ -74,8 +83,13 @@ class Problem:
         return cells_per_box(self.dim, self.elem) * int(np.prod(self.n))
 
     @property
+    def n_slots(self):
+        """Unknown positions per field component: nodes, or (DG) simplex vertex slots."""
+        return (self.dim + 1) * self.n_cells if self.elem == "dg" else self.n_nodes
+
+    @property
     def n_dof(self):
-        return (2 * self.dim + 2) * self.n_nodes
+        return (2 * self.dim + 2) * self.n_slots
 
 
 def cells_per_box(dim: int, elem: str = "p1") -> int:
@@ -250,6 +264,10 @@ CONFIGS = {
     # solution and the 96^3 log-normal box on box cells
     "h2_3d64_q1": dict(kind="mms", dim=3, n=64, k1=1.0, k2=1e-2, beta=1.0, mu=1.0, elem="q1"),
     "h3_3d96_grf_q1": dict(kind="grf", dim=3, n=96, elem="q1"),
+    # DG-VMS (discontinuous P1 on the Kuhn simplices): the appendix DG-VMS
+    # listing's data (k1 = 1, k2 = 0.1, beta = mu = 1), 3D and 2D
+    "g2_3d32_dg": dict(kind="mms", dim=3, n=32, k1=1.0, k2=0.1, beta=1.0, mu=1.0, elem="dg"),
+    "g1_2d256_dg": dict(kind="mms", dim=2, n=256, k1=1.0, k2=0.1, beta=1.0, mu=1.0, elem="dg"),
 }
 
 
