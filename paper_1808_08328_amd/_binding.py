@@ -24,7 +24,7 @@ class _Box(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3), ("elem", C.c_int)]
 
 
-ELEM = {"p1": 0, "q1": 1}
+ELEM = {"p1": 0, "q1": 1, "dg": 2}
 
 
 class _Params(C.Structure):

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdpp.so")
 SOURCES = ["assemble.hip", "ops.hip", "mg.hip", "krylov.hip", "adjoint.hip", "batch.hip",
-           "profile.hip", "post.hip", "abi.hip"]
+           "profile.hip", "post.hip", "dg.hip", "abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Wno-unused-variable",

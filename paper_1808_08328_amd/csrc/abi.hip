@@ -118,7 +118,7 @@ dpp_status dpp_problem_sizes(dpp_problem P, int64_t *n_dof, int64_t *n_nodes, in
   return guard([&] {
     DPP_CHECK(P, DPP_ERR_ARG, "null problem");
     if (n_dof) *n_dof = P->ndof();
-    if (n_nodes) *n_nodes = P->g.N;
+    if (n_nodes) *n_nodes = P->npos();
     if (n_cells) *n_cells = P->g.nc;
     if (nnz) *nnz = P->nnz;
   });
@@ -135,7 +135,10 @@ dpp_status dpp_rhs(dpp_problem P, double *f_out, void *stream) {
 dpp_status dpp_export_csr(dpp_problem P, int64_t *rowptr, int32_t *cols, double *vals, void *stream) {
   return guard([&] {
     DPP_CHECK(P && rowptr && cols && vals, DPP_ERR_ARG, "null argument");
-    dpp::export_csr(P, rowptr, cols, vals, S(stream));
+    if (P->dg)
+      dpp::dg_export_csr(P, rowptr, cols, vals, S(stream));
+    else
+      dpp::export_csr(P, rowptr, cols, vals, S(stream));
   });
 }
 
@@ -144,6 +147,7 @@ dpp_status dpp_spmv(dpp_problem P, int which, const double *x, double *y, void *
     DPP_CHECK(P && x && y, DPP_ERR_ARG, "null argument");
     DPP_CHECK(which >= 0 && which <= 4, DPP_ERR_ARG, "which must be 0..4");
     DPP_CHECK(x != y, DPP_ERR_ARG, "x and y must not alias");
+    DPP_CHECK(!P->dg || which == 0, DPP_ERR_UNSUPPORTED, "DG-VMS problems have the full product only");
     if (which == 0)
       dpp::spmv_K(P, x, y, S(stream));
     else
@@ -370,6 +374,7 @@ dpp_status dpp_solve_adjoint(dpp_problem P, dpp_precond pc, const dpp_solve_opts
   dpp_status st = guard([&] {
     DPP_CHECK(P && pc && g && lambda && g != lambda, DPP_ERR_ARG, "bad argument");
     DPP_CHECK(pc->prob == P, DPP_ERR_ARG, "preconditioner belongs to another problem");
+    DPP_CHECK(!P->dg, DPP_ERR_UNSUPPORTED, "the adjoint solve is implemented for CG-VMS problems");
     const long n = P->ndof();
     // allocated on the first adjoint solve of this preconditioner, then reused
     if (!pc->adjrhs.ptr) pc->adjrhs.alloc(sizeof(double) * n);

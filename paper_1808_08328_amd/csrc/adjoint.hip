@@ -133,8 +133,8 @@ __global__ void k_mask_fixed(GridDev g, const double *__restrict__ lam, double *
 
 void param_grad(dpp_problem P, const double *x, const double *lam, double *g1, double *g2,
                 double *gb, hipStream_t s) {
-  DPP_CHECK(P->g.elem == ELEM_P1, DPP_ERR_UNSUPPORTED,
-            "the parameter gradient is implemented for P1 simplices");
+  DPP_CHECK(P->g.elem == ELEM_P1 && !P->dg, DPP_ERR_UNSUPPORTED,
+            "the parameter gradient is implemented for CG-VMS P1 simplices");
   const Grid &g = P->g;
   // With velocity faces K~ = P_f K P_f + P_c and f~ = P_f (f - K P_c g) + P_c g,
   // so dJ/dtheta = lam^T (df~ - dK~ x) = -(P_f lam)^T (dK/dtheta) x (x = g on

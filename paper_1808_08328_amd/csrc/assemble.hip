@@ -576,15 +576,17 @@ static void check_input(const double *p, long n, CheckKind kind, const char *nam
 void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, hipStream_t s) {
   DPP_CHECK(box && prm, DPP_ERR_ARG, "null box or params");
   DPP_CHECK(box->dim == 2 || box->dim == 3, DPP_ERR_ARG, "dim must be 2 or 3");
-  DPP_CHECK(box->elem == ELEM_P1 || box->elem == ELEM_Q1, DPP_ERR_ARG,
-            "elem must be 0 (P1 simplices) or 1 (Q1 box cells)");
+  DPP_CHECK(box->elem == ELEM_P1 || box->elem == ELEM_Q1 || box->elem == ELEM_DG, DPP_ERR_ARG,
+            "elem must be 0 (P1 simplices), 1 (Q1 box cells) or 2 (DG-VMS on simplices)");
   for (int a = 0; a < box->dim; ++a) {
     DPP_CHECK(box->n[a] >= 1 && box->n[a] <= 4096, DPP_ERR_ARG, "cells per axis must be in 1..4096");
     DPP_CHECK(box->L[a] > 0.0, DPP_ERR_ARG, "box extent must be positive");
   }
   DPP_CHECK(prm->k1 && prm->k2 && prm->p0_1 && prm->p0_2, DPP_ERR_ARG, "null coefficient array");
   DPP_CHECK(prm->mu > 0.0, DPP_ERR_ARG, "mu must be positive");
-  Grid g = make_grid(box->dim, box->n, box->L, box->elem);
+  const bool dg = box->elem == ELEM_DG;
+  // DG-VMS keeps the node grid of the simplices (boundary data, coefficients)
+  Grid g = make_grid(box->dim, box->n, box->L, dg ? ELEM_P1 : box->elem);
   const int D = g.dim;
   // the stencil kernels index nodes and unknowns with 32-bit integers
   DPP_CHECK((2L * D + 2L) * g.N <= 2147483647L, DPP_ERR_ARG,
@@ -600,6 +602,20 @@ void assemble_problem(dpp_problem P, const dpp_box *box, const dpp_params *prm, 
   if (prm->body) check_input(prm->body, g.nc * D, FINITE, "body", s);
   DPP_CHECK(std::isfinite(prm->beta) && prm->beta >= 0.0, DPP_ERR_ARG, "beta must be >= 0");
 
+  if (dg) {
+    if (prm->face_bc)
+      for (int i = 0; i < 4 * D; ++i)
+        DPP_CHECK(prm->face_bc[i] == 0, DPP_ERR_UNSUPPORTED, "DG-VMS problems take pressure faces only");
+    // unknowns on vertex slots, 32-bit indices in the block kernels
+    DPP_CHECK((2L * D + 2L) * (D + 1) * g.nc <= 2147483647L, DPP_ERR_ARG,
+              "box too large: (2 dim + 2) x slots must stay below 2^31");
+    P->g = g;
+    P->mu = prm->mu;
+    P->beta = prm->beta;
+    P->beta_per_cell = prm->beta_cells != nullptr;
+    dg_assemble(P, prm, s);
+    return;
+  }
   if (prm->face_bc) {
     for (int q = 0; q < 2; ++q)
       for (int fa = 0; fa < 2 * D; ++fa) {

@@ -26,7 +26,9 @@ namespace dpp {
 // table for CG-VMS.  dim_of(D) is the spatial dimension.
 __host__ __device__ constexpr int dim_of(int D) { return D % 10; }
 __host__ __device__ constexpr bool is_q1(int D) { return D >= 10; }
-enum Elem { ELEM_P1 = 0, ELEM_Q1 = 1 };
+// ELEM_DG: the DG-VMS form, discontinuous P1 on the Kuhn simplices (its own
+// element-block storage, not the stencil code)
+enum Elem { ELEM_P1 = 0, ELEM_Q1 = 1, ELEM_DG = 2 };
 
 struct Error : std::runtime_error {
   dpp_status status;

@@ -68,7 +68,14 @@ struct dpp_problem_s {
   dpp::DBuf f;          // [n_dof]
   dpp::DBuf dinv;       // [2][N] 1/diag(K_uu^i)
   dpp::DBuf k1, k2, betac;  // coefficient copies [n_cells] for the gradient
-  long ndof() const { return (long)(2 * g.dim + 2) * g.N; }
+  // DG-VMS (g is the node grid of the simplices; unknowns sit on vertex slots)
+  int dg = 0;
+  long nslot = 0;       // simplices x (dim + 1)
+  dpp::DBuf dgA;        // [2][n_cells][dim+2][SB][SB] element blocks (SB = (dim+1)^2)
+  dpp::DBuf dgB;        // [n_cells][dim+1][dim+1] inter-network transfer -(beta/mu) M
+  dpp::DBuf dgnb;       // [n_cells][dim+1] facet neighbours (-1: boundary)
+  long npos() const { return dg ? nslot : g.N; }  // positions per field component
+  long ndof() const { return (long)(2 * g.dim + 2) * npos(); }
 };
 
 namespace dpp {
@@ -174,6 +181,10 @@ void mms_l2_errors_noalloc(dpp_problem P, const double *x, const double mms[4], 
 void simplex_rule(int dim, int q, std::vector<double> &lam, std::vector<double> &w);
 // pure-flux case: velocity faces everywhere in both networks (singular K)
 bool pure_flux(const Grid &g);
+// DG-VMS (dg.hip)
+void dg_assemble(dpp_problem P, const dpp_params *prm, hipStream_t s);
+void dg_spmv(dpp_problem P, const double *x, const double *bsub, double *y, hipStream_t s);
+void dg_export_csr(dpp_problem P, int64_t *rowptr, int32_t *cols, double *vals, hipStream_t s);
 void consistent_rhs(dpp_problem P, double *b, hipStream_t s);
 void normalize_pressures(dpp_problem P, double *x, hipStream_t s);
 void vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s);  // FP64, [2][N] in/out

@@ -357,6 +357,11 @@ static void launch_K(dpp_problem P, const double *x, const double *bsub, double 
 }
 
 void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32) {
+  if (P->dg) {
+    DPP_CHECK(!fp32, DPP_ERR_UNSUPPORTED, "DG-VMS problems are solved in FP64");
+    dg_spmv(P, x, nullptr, y, s);
+    return;
+  }
   ProfScope ps(PF_SPMV_K, kbytes(P->g, fp32, false), s);
   launch_K(P, x, nullptr, y, s, fp32);
   check_launch("spmv_K");
@@ -364,6 +369,11 @@ void spmv_K(dpp_problem P, const double *x, double *y, hipStream_t s, bool fp32)
 
 void residual_K(dpp_problem P, const double *b, const double *x, double *r, hipStream_t s,
                 bool fp32) {
+  if (P->dg) {
+    DPP_CHECK(!fp32, DPP_ERR_UNSUPPORTED, "DG-VMS problems are solved in FP64");
+    dg_spmv(P, x, b, r, s);
+    return;
+  }
   ProfScope ps(PF_SPMV_K, kbytes(P->g, fp32, true), s);
   launch_K(P, x, b, r, s, fp32);
   check_launch("residual_K");

@@ -389,7 +389,7 @@ static void check_mms_args(int q, const double mms[4]) {
 void mms_l2_errors(dpp_problem P, const double *x, const double mms[4], int q, double err[4],
                    hipStream_t s) {
   check_mms_args(q, mms);
-  DPP_CHECK(P->g.elem == ELEM_P1, DPP_ERR_UNSUPPORTED, "L2 errors are integrated over simplex cells only");
+  DPP_CHECK(P->g.elem == ELEM_P1 && !P->dg, DPP_ERR_UNSUPPORTED, "L2 errors are integrated for CG-VMS P1 simplices only");
   const Grid &g = P->g;
   std::vector<double> lam, wt;
   simplex_rule(g.dim, q, lam, wt);
@@ -464,7 +464,7 @@ double *scratch_of_current_device() {
 void mms_l2_errors_noalloc(dpp_problem P, const double *x, const double mms[4], int q,
                            double err[4], hipStream_t s) {
   check_mms_args(q, mms);
-  DPP_CHECK(P->g.elem == ELEM_P1, DPP_ERR_UNSUPPORTED, "L2 errors are integrated over simplex cells only");
+  DPP_CHECK(P->g.elem == ELEM_P1 && !P->dg, DPP_ERR_UNSUPPORTED, "L2 errors are integrated for CG-VMS P1 simplices only");
   const Grid &g = P->g;
   int nq = 1;
   for (int a = 0; a < g.dim; ++a) nq *= q;
