@@ -250,3 +250,120 @@ def l2_errors(S_sys, x, exact):
         ref = np.sqrt(np.sum(w[:, :, None] * ex ** 2))
         out[f] = err / ref if ref > 0 else err
     return out
+
+
+VEL_DEGREE = 8       # Chebyshev steps of the velocity-block solve
+VEL_LO_FRAC = 0.01   # its interval [0.01 hi, hi]
+
+
+def power_bound(apply_A, apply_M, size, iters):
+    """lam = ||M A x_k|| after ``iters`` normalised power steps from the
+    integer-hash start vector (as oracle.mg.power_lambda, M any linear map)."""
+    from . import mg
+    x = mg.hash_start(size)
+    x = x / np.linalg.norm(x)
+    lam = 0.0
+    for _ in range(iters):
+        y = apply_M(apply_A(x))
+        lam = np.linalg.norm(y)
+        x = y / lam
+    return lam
+
+
+def chebyshev_op(apply_A, apply_M, b, x, degree, lo, hi):
+    """Chebyshev iteration for A x = b preconditioned by M on [lo, hi]
+    (Saad, Alg. 12.1; oracle.mg.chebyshev with a general M)."""
+    theta = 0.5 * (hi + lo)
+    delta = 0.5 * (hi - lo)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    r = apply_M(b - apply_A(x))
+    d = r / theta
+    x = x + d
+    for _ in range(1, degree):
+        r = apply_M(b - apply_A(x))
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * r
+        x = x + d
+        rho = rho_new
+    return x
+
+
+class FieldSplitDG:
+    """Schur fieldsplit of the solver section (Method 2, selfp) on the DG-VMS
+    blocks, the appendix listing's splitting of velocities and pressures
+    (pressure blocks additive per network), per network i:
+
+      y_u = V_i(r_u),  rhat = r_p - K_pu y_u,  z_p = B_i(rhat),  z_u = V_i(r_u - K_up z_p)
+
+    * V_i approximates K_uu^-1: VEL_DEGREE Chebyshev steps from zero,
+      preconditioned by the inverses of K_uu's diagonal blocks (one per
+      simplex, its (d+1) d velocity unknowns), on [VEL_LO_FRAC hi, hi] with
+      hi = hi_factor x the power-step estimate.  The velocity-jump penalty
+      couples neighbouring simplices as strongly as the mass term couples a
+      simplex's own unknowns, so the diagonal of K_uu (enough for CG-VMS)
+      needs hundreds of outer iterations here; the listing's block Jacobi
+      with ILU sub-blocks plays this part there.
+    * S_i = K_pp - K_pu diag(K_uu)^-1 K_up (selfp), and B_i a two-level cycle
+      whose coarse level is the nodal CG-VMS problem of the same box and
+      coefficients (its selfp block and multigrid hierarchy, oracle.mg):
+      restrict by summing the slot values on each node (R), one V-cycle,
+      copy the node values back to the slots (R^T), then Chebyshev
+      post-smoothing on S_i with its diagonal (the nodal levels' smoother:
+      power-step bound, interval [lo_frac hi, hi], the finest level's degree)."""
+
+    def __init__(self, system, prob, mg_opts=None):
+        from dataclasses import replace
+
+        from . import mg, solver
+        d, S = system.dim, system.S
+        F = fields(d, S)
+        self.F = F
+        K = system.K.tocsr()
+        nc = system.mesh.cells.shape[0]
+        NU = (d + 1) * d
+        o = mg_opts or mg.MGOptions()
+        self.opts = o
+        self.Kuu, self.Kup, self.Kpu, self.Binv, self.Sp, self.dS = [], [], [], [], [], []
+        self.vhi, self.vlo = [], []
+        for u, p in (("u1", "p1"), ("u2", "p2")):
+            Kuu = K[F[u], F[u]].tocsr()
+            dinv = 1.0 / Kuu.diagonal()
+            Kup, Kpu, Kpp = K[F[u], F[p]], K[F[p], F[u]], K[F[p], F[p]]
+            Sp = (Kpp - Kpu @ sp.diags(dinv) @ Kup).tocsr()
+            blocks = [np.linalg.inv(Kuu[e * NU:(e + 1) * NU, e * NU:(e + 1) * NU].toarray()) for e in range(nc)]
+            Binv = sp.block_diag(blocks).tocsr()
+            lam = power_bound(lambda v, A=Kuu: A @ v, lambda v, B=Binv: B @ v, Kuu.shape[0], o.power_iters)
+            self.vhi.append(o.hi_factor * lam)
+            self.vlo.append(VEL_LO_FRAC * o.hi_factor * lam)
+            self.Kuu.append(Kuu)
+            self.Kup.append(Kup)
+            self.Kpu.append(Kpu)
+            self.Binv.append(Binv)
+            self.Sp.append(Sp)
+            self.dS.append(1.0 / Sp.diagonal())
+        lo_frac = o.lo_frac if o.lo_frac > 0 else (0.1 if d == 3 else 0.3)
+        self.hi = [o.hi_factor * mg.power_lambda(self.Sp[i], self.dS[i], o.power_iters) for i in range(2)]
+        self.lo = [lo_frac * h for h in self.hi]
+        self.deg = o.post(0)
+        cg = odpp.assemble(replace(prob, elem="p1"))
+        self.H = solver.FieldSplit(cg, o).H
+        msh = system.mesh
+        self.R = sp.csr_matrix((np.ones(S), (msh.cells.ravel(), np.arange(S))), shape=(msh.N, S))
+
+    def velocity(self, i, b):
+        return chebyshev_op(lambda v: self.Kuu[i] @ v, lambda v: self.Binv[i] @ v, b, np.zeros_like(b),
+                            VEL_DEGREE, self.vlo[i], self.vhi[i])
+
+    def apply(self, r):
+        from . import mg
+        F = self.F
+        z = np.empty_like(r)
+        for i, (u, p) in enumerate((("u1", "p1"), ("u2", "p2"))):
+            ru, rp = r[F[u]], r[F[p]]
+            rhat = rp - self.Kpu[i] @ self.velocity(i, ru)
+            zp = self.R.T @ mg.vcycle(self.H[i], self.R @ rhat)
+            zp = mg.chebyshev(self.Sp[i], self.dS[i], rhat, zp, self.deg, self.lo[i], self.hi[i])
+            z[F[p]] = zp
+            z[F[u]] = self.velocity(i, ru - self.Kup[i] @ zp)
+        return z

@@ -169,7 +169,10 @@ dpp_status dpp_setup_precond(dpp_problem P, const dpp_solve_opts *opts, void *st
     try {
       check_opts(pc->opts);
       const auto t0 = std::chrono::steady_clock::now();
-      dpp::precond_setup(pc, S(stream));
+      if (P->dg)
+        dpp::dg_precond_setup(pc, S(stream));
+      else
+        dpp::precond_setup(pc, S(stream));
       DPP_HIP(hipStreamSynchronize(S(stream)));
       pc->ms_setup =
           std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -228,6 +231,7 @@ dpp_status dpp_precond_apply(dpp_precond pc, const double *r, double *z, void *s
 dpp_status dpp_vcycle(dpp_precond pc, const double *b, double *x, void *stream) {
   return guard([&] {
     DPP_CHECK(pc && b && x && b != x, DPP_ERR_ARG, "bad argument");
+    DPP_CHECK(!pc->prob->dg, DPP_ERR_UNSUPPORTED, "a DG-VMS preconditioner has no nodal V-cycle of its own");
     dpp::vcycle(pc, b, x, S(stream));
   });
 }
@@ -262,6 +266,7 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
     }
     // a rejected call leaves the handle as it was
     check_opts(o);
+    DPP_CHECK(!P->dg || o.precision == 0, DPP_ERR_UNSUPPORTED, "DG-VMS problems are solved in FP64 (precision 0)");
     pc->opts.cheb_degree = o.cheb_degree;
     pc->opts.cheb_pre_fine = o.cheb_pre_fine;
     pc->opts.cheb_post_fine = o.cheb_post_fine;

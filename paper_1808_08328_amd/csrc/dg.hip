@@ -359,6 +359,348 @@ __global__ void k_dg_export(long nc, long nslot, const double *__restrict__ A, c
   }
 }
 
+// ------------------------------------------------------------ fieldsplit --
+// The Schur fieldsplit of the solver section (Method 2, selfp) on the DG
+// blocks, per network q (both networks in one launch, blockIdx.y = q):
+//   rhat = r_p - K_pu D_u^-1 r_u,  z_p ~ S_q^-1 rhat,  z_u = D_u^-1 (r_u - K_up z_p)
+// with D_u = diag(K_uu) and S_q = K_pp - K_pu D_u^-1 K_up applied without
+// forming it.  z_p comes from a two-level cycle: the nodal CG-VMS hierarchy
+// of the same box and coefficients corrects the restricted residual (node
+// values = sums over the node's slots; back by copying node values to the
+// slots), then Chebyshev steps on S_q with its diagonal smooth on the slots.
+
+// 1 / diag(K_uu): one thread per (network, simplex, velocity row)
+template <int d>
+__global__ void k_dg_diag_u(long nc, const double *__restrict__ A, double *__restrict__ du) {
+  constexpr int SB = dg_sb(d), NB = d + 2, NU = (d + 1) * d;
+  const int q = blockIdx.y;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * NU) return;
+  const long e = t / NU;
+  const int r = (int)(t % NU);
+  du[(size_t)q * nc * NU + t] = 1.0 / A[(((size_t)q * nc + e) * NB * SB + r) * SB + r];
+}
+
+// 1 / diag(S_q) = 1 / (K_pp[i][i] + sum_j K_pu[i][j]^2 / K_uu[j][j]) (K_up = -K_pu^T)
+template <int d>
+__global__ void k_dg_diag_s(long nc, const double *__restrict__ A, const int *__restrict__ nbr,
+                            const double *__restrict__ du, double *__restrict__ ds) {
+  constexpr int SB = dg_sb(d), NB = d + 2, NU = (d + 1) * d;
+  const int q = blockIdx.y;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * (d + 1)) return;
+  const long e = t / (d + 1);
+  const int a = (int)(t % (d + 1));
+  const double *Ar = A + (((size_t)q * nc + e) * NB * SB + NU + a) * SB;
+  const double *duq = du + (size_t)q * nc * NU;
+  double v = Ar[NU + a];
+  for (int b = 0; b < NB; ++b) {
+    const long s2 = b == 0 ? e : nbr[e * (d + 1) + b - 1];
+    if (s2 < 0) continue;
+    for (int c = 0; c < NU; ++c) {
+      const double w = Ar[(size_t)b * SB * SB + c];
+      v += w * w * duq[s2 * NU + c];
+    }
+  }
+  ds[(size_t)q * nc * (d + 1) + t] = 1.0 / v;
+}
+
+// rhat = r_p - K_pu y_u (y_u [2][n_cells NU], the velocity solve's output):
+// one thread per (network, simplex, pressure row)
+template <int d>
+__global__ void k_dg_rhat(long nc, long nslot, const double *__restrict__ A, const int *__restrict__ nbr,
+                          const double *__restrict__ yu, const double *__restrict__ r, double *__restrict__ rh) {
+  constexpr int SB = dg_sb(d), NB = d + 2, NU = (d + 1) * d;
+  const int q = blockIdx.y;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * (d + 1)) return;
+  const long e = t / (d + 1);
+  const int a = (int)(t % (d + 1));
+  const double *Ar = A + (((size_t)q * nc + e) * NB * SB + NU + a) * SB;
+  const double *yq = yu + (size_t)q * nc * NU;
+  double acc = 0.0;
+  for (int b = 0; b < NB; ++b) {
+    const long s2 = b == 0 ? e : nbr[e * (d + 1) + b - 1];
+    if (s2 < 0) continue;
+    for (int c = 0; c < NU; ++c) acc += Ar[(size_t)b * SB * SB + c] * yq[s2 * NU + c];
+  }
+  rh[(size_t)q * nslot + t] = r[off_p(d, nslot, q) + t] - acc;
+}
+
+// tu = K_up zp: one thread per (network, simplex, velocity row)
+template <int d>
+__global__ void k_dg_tu(long nc, long nslot, const double *__restrict__ A, const int *__restrict__ nbr,
+                        const double *__restrict__ zp, double *__restrict__ tu) {
+  constexpr int SB = dg_sb(d), NB = d + 2, NU = (d + 1) * d;
+  const int q = blockIdx.y;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * NU) return;
+  const long e = t / NU;
+  const int r = (int)(t % NU);
+  const double *Ar = A + (((size_t)q * nc + e) * NB * SB + r) * SB;
+  const double *z = zp + (size_t)q * nslot;
+  double acc = 0.0;
+  for (int b = 0; b < NB; ++b) {
+    const long s2 = b == 0 ? e : nbr[e * (d + 1) + b - 1];
+    if (s2 < 0) continue;
+    for (int c = 0; c <= d; ++c) acc += Ar[(size_t)b * SB * SB + NU + c] * z[s2 * (d + 1) + c];
+  }
+  tu[(size_t)q * nc * NU + t] = acc;
+}
+
+// y = S_q x = K_pp x - K_pu (D_u^-1 tu) with tu = K_up x; with cheb, one
+// Chebyshev step instead: r = D_S^-1 (b - S_q x), dd = c1 dd + c2 r, xout = x + dd
+template <int d>
+__global__ void k_dg_sp(long nc, long nslot, const double *__restrict__ A, const int *__restrict__ nbr,
+                        const double *__restrict__ du, const double *__restrict__ tu,
+                        const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ ds,
+                        const double *__restrict__ b, double *__restrict__ dd, Sc2 c1, Sc2 c2, bool cheb) {
+  constexpr int SB = dg_sb(d), NB = d + 2, NU = (d + 1) * d;
+  const int q = blockIdx.y;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * (d + 1)) return;
+  const long e = t / (d + 1);
+  const int a = (int)(t % (d + 1));
+  const double *Ar = A + (((size_t)q * nc + e) * NB * SB + NU + a) * SB;
+  const double *duq = du + (size_t)q * nc * NU, *tq = tu + (size_t)q * nc * NU;
+  const double *xq = x + (size_t)q * nslot;
+  double acc = 0.0;
+  for (int bb = 0; bb < NB; ++bb) {
+    const long s2 = bb == 0 ? e : nbr[e * (d + 1) + bb - 1];
+    if (s2 < 0) continue;
+    const double *Ab = Ar + (size_t)bb * SB * SB;
+    for (int c = 0; c < NU; ++c) acc -= Ab[c] * duq[s2 * NU + c] * tq[s2 * NU + c];
+    for (int c = 0; c <= d; ++c) acc += Ab[NU + c] * xq[s2 * (d + 1) + c];
+  }
+  const size_t i = (size_t)q * nslot + t;
+  if (!cheb) {
+    y[i] = ds ? ds[i] * acc : acc;
+    return;
+  }
+  const double rr = ds[i] * (b[i] - acc);
+  const double dn = (c1.v[q] != 0.0 ? c1.v[q] * dd[i] : 0.0) + c2.v[q] * rr;
+  dd[i] = dn;
+  y[i] = xq[t] + dn;
+}
+
+// Inverses of the diagonal velocity blocks of K_uu (one per simplex and
+// network, NU x NU, symmetric positive definite): Gauss-Jordan without
+// pivoting, one thread per (network, simplex).
+template <int d>
+__global__ void k_dg_binv(long nc, const double *__restrict__ A, double *__restrict__ Bi) {
+  constexpr int SB = dg_sb(d), NB = d + 2, NU = (d + 1) * d;
+  const int q = blockIdx.y;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nc) return;
+  double M[NU][NU], X[NU][NU];
+  const double *Ae = A + ((size_t)q * nc + e) * NB * SB * SB;
+  for (int r = 0; r < NU; ++r)
+    for (int c = 0; c < NU; ++c) {
+      M[r][c] = Ae[r * SB + c];
+      X[r][c] = r == c ? 1.0 : 0.0;
+    }
+  for (int k = 0; k < NU; ++k) {
+    const double piv = 1.0 / M[k][k];
+    for (int c = 0; c < NU; ++c) {
+      M[k][c] *= piv;
+      X[k][c] *= piv;
+    }
+    for (int r = 0; r < NU; ++r) {
+      if (r == k) continue;
+      const double f = M[r][k];
+      for (int c = 0; c < NU; ++c) {
+        M[r][c] -= f * M[k][c];
+        X[r][c] -= f * X[k][c];
+      }
+    }
+  }
+  double *Be = Bi + ((size_t)q * nc + e) * NU * NU;
+  for (int r = 0; r < NU; ++r)
+    for (int c = 0; c < NU; ++c) Be[r * NU + c] = X[r][c];
+}
+
+// Strided view of per-network velocity vectors: network q's value of
+// simplex e, row r sits at base[q * stride + e NU + r].
+struct DGVec {
+  const double *base;
+  long stride;
+};
+struct DGOut {
+  double *base;
+  long stride;
+};
+
+// Velocity-block Chebyshev step with the simplex-block Jacobi (Saad, Alg.
+// 12.1): res = b - K_uu x (b less tu when given; x = 0 when xin is null),
+// r' = Binv res, dd = c1 dd + c2 r', xout = x + dd.  power: xout = Binv (K_uu x)
+// (the power steps of the interval).  Workgroups of whole simplices
+// (192 threads: 16 in 3D, 32 in 2D); the simplex's residual goes through LDS.
+constexpr int DGV_BS = 192;
+template <int d>
+__global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(long nc, const double *__restrict__ A,
+                                                     const int *__restrict__ nbr, const double *__restrict__ Bi,
+                                                     DGVec b, const double *__restrict__ tu, DGVec xin,
+                                                     DGOut xout, double *__restrict__ dd, Sc2 c1, Sc2 c2,
+                                                     bool power) {
+  constexpr int SB = dg_sb(d), NB = d + 2, NU = (d + 1) * d;
+  constexpr int EPB = DGV_BS / NU;
+  __shared__ double sh[DGV_BS];
+  const int q = blockIdx.y;
+  const int loc = threadIdx.x / NU, r = threadIdx.x % NU;
+  const long e = (long)blockIdx.x * EPB + loc;
+  const bool live = loc < EPB && e < nc;
+  double res = 0.0, xr = 0.0;
+  if (live) {
+    double acc = 0.0;
+    if (xin.base) {
+      const double *Ar = A + (((size_t)q * nc + e) * NB * SB + r) * SB;
+      const double *xq = xin.base + (size_t)q * xin.stride;
+      for (int bb = 0; bb < NB; ++bb) {
+        const long s2 = bb == 0 ? e : nbr[e * (d + 1) + bb - 1];
+        if (s2 < 0) continue;
+        const double *Ab = Ar + (size_t)bb * SB * SB;
+        for (int c = 0; c < NU; ++c) acc += Ab[c] * xq[s2 * NU + c];
+      }
+      xr = xq[e * NU + r];
+    }
+    if (power) {
+      res = acc;
+    } else {
+      const double bv = b.base[(size_t)q * b.stride + e * NU + r] - (tu ? tu[(size_t)q * nc * NU + e * NU + r] : 0.0);
+      res = bv - acc;
+    }
+  }
+  sh[threadIdx.x] = res;
+  __syncthreads();
+  if (!live) return;
+  const double *Be = Bi + (((size_t)q * nc + e) * NU + r) * NU;
+  double rp = 0.0;
+  for (int c = 0; c < NU; ++c) rp += Be[c] * sh[loc * NU + c];
+  double *out = xout.base + (size_t)q * xout.stride + e * NU + r;
+  if (power) {
+    *out = rp;
+    return;
+  }
+  const size_t i = (size_t)q * nc * NU + e * NU + r;
+  const double dn = (c1.v[q] != 0.0 ? c1.v[q] * dd[i] : 0.0) + c2.v[q] * rp;
+  dd[i] = dn;
+  *out = xr + dn;
+}
+
+// z_p = zp (the pressure part of the fieldsplit's output)
+template <int d>
+__global__ void k_dg_copyp(long nslot, const double *__restrict__ zp, double *__restrict__ z) {
+  const int q = blockIdx.y;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nslot) return;
+  z[off_p(d, nslot, q) + i] = zp[(size_t)q * nslot + i];
+}
+
+// node value = sum over the slots on the node: for each box around the node
+// and each simplex of it, the node is local vertex |delta| when the axes of
+// its offset delta from the box corner are the first |delta| axes of pi
+template <int d>
+__global__ void k_dg_restrict(GridDev g, long nslot, const double *__restrict__ xs, double *__restrict__ xn) {
+  constexpr int NP = dg_nper(d);
+  const int q = blockIdx.y;
+  const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= g.N) return;
+  int ia[3];
+  node_ijk(g, a, ia[0], ia[1], ia[2]);
+  double acc = 0.0;
+  for (int m = 0; m < (1 << d); ++m) {  // delta bits: the node sits at corner + delta
+    int cell[3];
+    bool ok = true;
+    for (int ax = 0; ax < d; ++ax) {
+      cell[ax] = ia[ax] - ((m >> ax) & 1);
+      ok = ok && cell[ax] >= 0 && cell[ax] < g.n[ax];
+    }
+    if (!ok) continue;
+    long box = 0, mul = 1;
+    for (int ax = 0; ax < d; ++ax) {
+      box += cell[ax] * mul;
+      mul *= g.n[ax];
+    }
+    const int v = __popc(m);
+    for (int s = 0; s < NP; ++s) {
+      int p[3];
+      dg_perm(d, s, p);
+      int pre = 0;
+      for (int j = 0; j < v; ++j) pre |= 1 << p[j];
+      if (pre == m) acc += xs[(size_t)q * nslot + (box * NP + s) * (d + 1) + v];
+    }
+  }
+  xn[(size_t)q * g.N + a] = acc;
+}
+
+// slot value = value of its node
+template <int d>
+__global__ void k_dg_prolong(GridDev g, long nc, long nslot, const double *__restrict__ xn, double *__restrict__ xs) {
+  constexpr int NP = dg_nper(d);
+  const int q = blockIdx.y;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nslot) return;
+  const long e = t / (d + 1);
+  const int v = (int)(t % (d + 1));
+  const long box = e / NP;
+  int p[3];
+  dg_perm(d, (int)(e % NP), p);
+  long r = box, node = 0;
+  const long stride[3] = {1, g.m[0], (long)g.m[0] * g.m[1]};
+  for (int ax = 0; ax < d; ++ax) {
+    node += (r % g.n[ax]) * stride[ax];
+    r /= g.n[ax];
+  }
+  for (int j = 0; j < v; ++j) node += stride[p[j]];
+  xs[(size_t)q * nslot + t] = xn[(size_t)q * g.N + node];
+}
+
+__global__ void k_dg_hash(double *__restrict__ x, long n) {
+  const int q = blockIdx.y;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned long long h = ((unsigned long long)i * 2654435761ull) & 0xffffffffull;
+  x[(size_t)q * n + i] = (double)h / 4294967296.0 - 0.5;
+}
+
+// per-network sums of squares in a fixed order: partials, then one block
+constexpr int DG_RB = 256;
+__global__ __launch_bounds__(256) void k_dg_sumsq(const double *__restrict__ x, long n, double *__restrict__ part) {
+  const int q = blockIdx.y;
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double v = x[(size_t)q * n + i];
+    acc += v * v;
+  }
+  __shared__ double sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[q * DG_RB + blockIdx.x] = sh[0];
+}
+__global__ __launch_bounds__(256) void k_dg_sumsq_fin(const double *__restrict__ part, double *__restrict__ ss) {
+  __shared__ double sh[256];
+  for (int q = 0; q < 2; ++q) {
+    sh[threadIdx.x] = part[q * DG_RB + threadIdx.x];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) ss[q] = sh[0];
+    __syncthreads();
+  }
+}
+__global__ void k_dg_scale(double *__restrict__ x, long n, const double *__restrict__ ss) {
+  const int q = blockIdx.y;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[(size_t)q * n + i] /= sqrt(ss[q]);
+}
+
 }  // namespace
 
 void dg_assemble(dpp_problem P, const dpp_params *prm, hipStream_t s) {
@@ -373,6 +715,16 @@ void dg_assemble(dpp_problem P, const dpp_params *prm, hipStream_t s) {
   P->dgB.alloc(sizeof(double) * (size_t)nc * (d + 1) * (d + 1));
   P->dgnb.alloc(sizeof(int) * (size_t)nc * (d + 1));
   P->f.alloc(sizeof(double) * P->ndof());
+  // coefficient copies: the preconditioner assembles the nodal problem of the
+  // same box and coefficients
+  P->k1.alloc(sizeof(double) * nc);
+  P->k2.alloc(sizeof(double) * nc);
+  DPP_HIP(hipMemcpyAsync(P->k1.ptr, prm->k1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+  DPP_HIP(hipMemcpyAsync(P->k2.ptr, prm->k2, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+  if (prm->beta_cells) {
+    P->betac.alloc(sizeof(double) * nc);
+    DPP_HIP(hipMemcpyAsync(P->betac.ptr, prm->beta_cells, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+  }
   const dim3 grid(blocks_for(nc, 128), 2);
   if (d == 3)
     k_dg_assemble<3><<<grid, 128, 0, s>>>(dev(g), g.h[0], g.h[1], g.h[2], prm->k1, prm->k2, prm->beta, prm->beta_cells,
@@ -444,6 +796,232 @@ void dg_export_csr(dpp_problem P, int64_t *rowptr, int32_t *cols, double *vals, 
                                         rowptr, cols, vals);
   check_launch("DG export");
   DPP_HIP(hipStreamSynchronize(s));
+}
+
+
+// ------------------------------------------------------------ fieldsplit --
+namespace {
+
+template <int d>
+void dg_s_apply(dpp_precond pc, const double *x, double *y, const double *ds, hipStream_t s) {
+  dpp_problem P = pc->prob;
+  const long nc = P->g.nc, nslot = P->nslot, NU = (d + 1) * d;
+  k_dg_tu<d><<<dim3(blocks_for(nc * NU, 256), 2), 256, 0, s>>>(nc, nslot, P->dgA.as<double>(), P->dgnb.as<int>(),
+                                                               x, pc->dgtu.as<double>());
+  k_dg_sp<d><<<dim3(blocks_for(nslot, 256), 2), 256, 0, s>>>(
+      nc, nslot, P->dgA.as<double>(), P->dgnb.as<int>(), pc->dgdu.as<double>(), pc->dgtu.as<double>(), x, y, ds,
+      nullptr, nullptr, Sc2{{0, 0}}, Sc2{{0, 0}}, false);
+}
+
+constexpr int DG_VEL_DEGREE = 8;      // Chebyshev steps of the velocity-block solve
+constexpr double DG_VEL_LO_FRAC = 0.01;  // its interval [0.01 hi, hi]
+
+// out ~ K_uu^-1 (b - tu) per network: DG_VEL_DEGREE Chebyshev steps from
+// zero with the simplex-block Jacobi (intermediate iterates in dgva / dgvb)
+template <int d>
+void dg_vsolve(dpp_precond pc, DGVec b, const double *tu, DGOut out, hipStream_t s) {
+  dpp_problem P = pc->prob;
+  const long nc = P->g.nc, NU = (d + 1) * d;
+  const dim3 gv(blocks_for(nc, DGV_BS / NU), 2);
+  double th[2], de[2], sig[2], rho[2];
+  for (int q = 0; q < 2; ++q) {
+    th[q] = 0.5 * (pc->dgvhi[q] + pc->dgvlo[q]);
+    de[q] = 0.5 * (pc->dgvhi[q] - pc->dgvlo[q]);
+    sig[q] = th[q] / de[q];
+    rho[q] = 1.0 / sig[q];
+  }
+  double *buf[2] = {pc->dgva.as<double>(), pc->dgvb.as<double>()};
+  DGVec xin{nullptr, 0};
+  for (int k = 0; k < DG_VEL_DEGREE; ++k) {
+    Sc2 c1{{0, 0}}, c2{{0, 0}};
+    for (int q = 0; q < 2; ++q) {
+      if (k == 0) {
+        c2.v[q] = 1.0 / th[q];
+      } else {
+        const double rn = 1.0 / (2.0 * sig[q] - rho[q]);
+        c1.v[q] = rn * rho[q];
+        c2.v[q] = 2.0 * rn / de[q];
+        rho[q] = rn;
+      }
+    }
+    const DGOut o = k + 1 == DG_VEL_DEGREE ? out : DGOut{buf[k & 1], nc * NU};
+    k_dg_vcheb<d><<<gv, DGV_BS, 0, s>>>(nc, P->dgA.as<double>(), P->dgnb.as<int>(), pc->dgbinv.as<double>(), b,
+                                        tu, xin, o, pc->dgvd.as<double>(), c1, c2, false);
+    xin = DGVec{o.base, o.stride};
+  }
+  check_launch("DG velocity solve");
+}
+
+void dg_sumsq(dpp_precond pc, const double *x, long n, double *ssd, hipStream_t s) {
+  k_dg_sumsq<<<dim3(DG_RB, 2), 256, 0, s>>>(x, n, pc->dgpart.as<double>());
+  k_dg_sumsq_fin<<<1, 256, 0, s>>>(pc->dgpart.as<double>(), ssd);
+}
+
+template <int d>
+void dg_setup_impl(dpp_precond pc, hipStream_t s) {
+  dpp_problem P = pc->prob;
+  const Grid &g = P->g;
+  const long nc = g.nc, nslot = P->nslot, NU = (d + 1) * d;
+  // the nodal CG-VMS problem of the same box and coefficients (pressure data
+  // do not enter the operator) and its preconditioner: the coarse level
+  dpp_box box{};
+  box.dim = d;
+  for (int a = 0; a < d; ++a) {
+    box.n[a] = g.n[a];
+    box.L[a] = g.h[a] * g.n[a];
+  }
+  box.elem = ELEM_P1;
+  pc->dgzero.alloc(sizeof(double) * g.N);
+  DPP_HIP(hipMemsetAsync(pc->dgzero.ptr, 0, sizeof(double) * g.N, s));
+  dpp_params prm{};
+  prm.mu = P->mu;
+  prm.k1 = P->k1.as<double>();
+  prm.k2 = P->k2.as<double>();
+  prm.beta = P->beta;
+  prm.beta_cells = P->beta_per_cell ? P->betac.as<double>() : nullptr;
+  prm.p0_1 = prm.p0_2 = pc->dgzero.as<double>();
+  pc->dgcg.reset(new dpp_problem_s());
+  assemble_problem(pc->dgcg.get(), &box, &prm, s);
+  pc->dgpc = new dpp_precond_s();
+  pc->dgpc->prob = pc->dgcg.get();
+  pc->dgpc->opts = pc->opts;
+  precond_setup(pc->dgpc, s);
+  // DG level: diagonals, work vectors, Chebyshev bounds from power steps
+  pc->dgdu.alloc(sizeof(double) * 2 * nc * NU);
+  pc->dgds.alloc(sizeof(double) * 2 * nslot);
+  for (DBuf *b : {&pc->dgrh, &pc->dgza, &pc->dgzb, &pc->dgd}) b->alloc(sizeof(double) * 2 * nslot);
+  pc->dgtu.alloc(sizeof(double) * 2 * nc * NU);
+  for (DBuf *b : {&pc->dgva, &pc->dgvb, &pc->dgvd, &pc->dgyu}) b->alloc(sizeof(double) * 2 * nc * NU);
+  pc->dgbinv.alloc(sizeof(double) * 2 * nc * NU * NU);
+  pc->dgcb.alloc(sizeof(double) * 2 * g.N);
+  pc->dgcx.alloc(sizeof(double) * 2 * g.N);
+  pc->dgpart.alloc(sizeof(double) * 2 * DG_RB + 2 * sizeof(double));
+  k_dg_diag_u<d><<<dim3(blocks_for(nc * NU, 256), 2), 256, 0, s>>>(nc, P->dgA.as<double>(), pc->dgdu.as<double>());
+  k_dg_diag_s<d><<<dim3(blocks_for(nslot, 256), 2), 256, 0, s>>>(nc, P->dgA.as<double>(), P->dgnb.as<int>(),
+                                                                pc->dgdu.as<double>(), pc->dgds.as<double>());
+  check_launch("DG diagonals");
+  double *x = pc->dgza.as<double>(), *y = pc->dgzb.as<double>();
+  double *ssd = pc->dgpart.as<double>() + 2 * DG_RB;
+  const dim3 gv(blocks_for(nslot, 256), 2);
+  k_dg_hash<<<gv, 256, 0, s>>>(x, nslot);
+  dg_sumsq(pc, x, nslot, ssd, s);
+  k_dg_scale<<<gv, 256, 0, s>>>(x, nslot, ssd);
+  const dpp_solve_opts &o = pc->opts;
+  for (int it = 0; it < o.power_iters; ++it) {
+    dg_s_apply<d>(pc, x, y, pc->dgds.as<double>(), s);
+    dg_sumsq(pc, y, nslot, ssd, s);
+    k_dg_scale<<<gv, 256, 0, s>>>(y, nslot, ssd);
+    std::swap(x, y);
+  }
+  check_launch("DG power steps");
+  double ss[2] = {0.0, 0.0};
+  DPP_HIP(hipMemcpyAsync(ss, ssd, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  DPP_HIP(hipStreamSynchronize(s));
+  // velocity block: simplex-block inverses and the interval of Binv K_uu
+  k_dg_binv<d><<<dim3(blocks_for(nc, 64), 2), 64, 0, s>>>(nc, P->dgA.as<double>(), pc->dgbinv.as<double>());
+  check_launch("DG velocity blocks");
+  {
+    const long nu = nc * NU;
+    double *vx = pc->dgva.as<double>(), *vy = pc->dgvb.as<double>();
+    const dim3 gu(blocks_for(nu, 256), 2), gb(blocks_for(nc, DGV_BS / NU), 2);
+    k_dg_hash<<<gu, 256, 0, s>>>(vx, nu);
+    dg_sumsq(pc, vx, nu, ssd, s);
+    k_dg_scale<<<gu, 256, 0, s>>>(vx, nu, ssd);
+    for (int it = 0; it < o.power_iters; ++it) {
+      k_dg_vcheb<d><<<gb, DGV_BS, 0, s>>>(nc, P->dgA.as<double>(), P->dgnb.as<int>(), pc->dgbinv.as<double>(),
+                                          DGVec{nullptr, 0}, nullptr, DGVec{vx, nu}, DGOut{vy, nu}, nullptr,
+                                          Sc2{{0, 0}}, Sc2{{0, 0}}, true);
+      dg_sumsq(pc, vy, nu, ssd, s);
+      k_dg_scale<<<gu, 256, 0, s>>>(vy, nu, ssd);
+      std::swap(vx, vy);
+    }
+    check_launch("DG velocity power steps");
+    double sv[2] = {0.0, 0.0};
+    DPP_HIP(hipMemcpyAsync(sv, ssd, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    DPP_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < 2; ++q) {
+      pc->dgvhi[q] = o.cheb_hi_factor * std::sqrt(sv[q]);
+      pc->dgvlo[q] = DG_VEL_LO_FRAC * pc->dgvhi[q];
+      DPP_CHECK(std::isfinite(pc->dgvhi[q]) && pc->dgvhi[q] > 0.0, DPP_ERR_NUMERIC,
+                "DG velocity-block eigenvalue estimate is not positive");
+    }
+  }
+  const double lo_frac = o.cheb_lo_frac > 0.0 ? o.cheb_lo_frac : (d == 3 ? 0.1 : 0.3);
+  for (int q = 0; q < 2; ++q) {
+    pc->dghi[q] = o.cheb_hi_factor * std::sqrt(ss[q]);
+    pc->dglo[q] = lo_frac * pc->dghi[q];
+    DPP_CHECK(std::isfinite(pc->dghi[q]) && pc->dghi[q] > 0.0, DPP_ERR_NUMERIC,
+              "DG Schur eigenvalue estimate is not positive");
+  }
+}
+
+template <int d>
+void dg_apply_impl(dpp_precond pc, const double *r, double *z, hipStream_t s) {
+  dpp_problem P = pc->prob;
+  const Grid &g = P->g;
+  const long nc = g.nc, nslot = P->nslot;
+  const int SB = (d + 1) * (d + 1);
+  const double *A = P->dgA.as<double>(), *du = pc->dgdu.as<double>(), *ds = pc->dgds.as<double>();
+  const int *nb = P->dgnb.as<int>();
+  const dim3 gp(blocks_for(nslot, 256), 2);
+  double *rh = pc->dgrh.as<double>();
+  const long NU = (d + 1) * d, vstride = (d + 1) * nslot;  // network stride of the ABI vector
+  dg_vsolve<d>(pc, DGVec{r + off_u(d, nslot, 0), vstride}, nullptr, DGOut{pc->dgyu.as<double>(), nc * NU}, s);
+  k_dg_rhat<d><<<gp, 256, 0, s>>>(nc, nslot, A, nb, pc->dgyu.as<double>(), r, rh);
+  // coarse correction on the nodes, back to the slots
+  k_dg_restrict<d><<<dim3(blocks_for(g.N, 256), 2), 256, 0, s>>>(dev(g), nslot, rh, pc->dgcb.as<double>());
+  vcycle(pc->dgpc, pc->dgcb.as<double>(), pc->dgcx.as<double>(), s);
+  double *cur = pc->dgza.as<double>(), *oth = pc->dgzb.as<double>();
+  k_dg_prolong<d><<<gp, 256, 0, s>>>(dev(g), nc, nslot, pc->dgcx.as<double>(), cur);
+  // Chebyshev post-smoothing on S_q (Saad, Alg. 12.1 with the diagonal of S_q)
+  const int deg = pc->opts.cheb_post_fine >= 1 ? pc->opts.cheb_post_fine : pc->opts.cheb_degree;
+  double sig[2], rho[2], th[2], de[2];
+  for (int q = 0; q < 2; ++q) {
+    th[q] = 0.5 * (pc->dghi[q] + pc->dglo[q]);
+    de[q] = 0.5 * (pc->dghi[q] - pc->dglo[q]);
+    sig[q] = th[q] / de[q];
+    rho[q] = 1.0 / sig[q];
+  }
+  for (int k = 0; k < deg; ++k) {
+    Sc2 c1{{0, 0}}, c2{{0, 0}};
+    for (int q = 0; q < 2; ++q) {
+      if (k == 0) {
+        c2.v[q] = 1.0 / th[q];
+      } else {
+        const double rn = 1.0 / (2.0 * sig[q] - rho[q]);
+        c1.v[q] = rn * rho[q];
+        c2.v[q] = 2.0 * rn / de[q];
+        rho[q] = rn;
+      }
+    }
+    k_dg_tu<d><<<dim3(blocks_for(nc * (d + 1) * d, 256), 2), 256, 0, s>>>(nc, nslot, A, nb, cur,
+                                                                           pc->dgtu.as<double>());
+    k_dg_sp<d><<<gp, 256, 0, s>>>(nc, nslot, A, nb, du, pc->dgtu.as<double>(), cur, oth, ds, rh,
+                                  pc->dgd.as<double>(), c1, c2, true);
+    std::swap(cur, oth);
+  }
+  // z_u ~ K_uu^-1 (r_u - K_up z_p), z_p
+  k_dg_tu<d><<<dim3(blocks_for(nc * NU, 256), 2), 256, 0, s>>>(nc, nslot, A, nb, cur, pc->dgtu.as<double>());
+  dg_vsolve<d>(pc, DGVec{r + off_u(d, nslot, 0), vstride}, pc->dgtu.as<double>(),
+               DGOut{z + off_u(d, nslot, 0), vstride}, s);
+  k_dg_copyp<d><<<gp, 256, 0, s>>>(nslot, cur, z);
+  check_launch("DG fieldsplit");
+}
+
+}  // namespace
+
+void dg_precond_setup(dpp_precond pc, hipStream_t s) {
+  if (pc->prob->g.dim == 3)
+    dg_setup_impl<3>(pc, s);
+  else
+    dg_setup_impl<2>(pc, s);
+}
+
+void dg_precond_apply(dpp_precond pc, const double *r, double *z, hipStream_t s) {
+  if (pc->prob->g.dim == 3)
+    dg_apply_impl<3>(pc, r, z, s);
+  else
+    dg_apply_impl<2>(pc, r, z, s);
 }
 
 }  // namespace dpp

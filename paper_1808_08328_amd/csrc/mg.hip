@@ -886,6 +886,11 @@ void vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s) {
 
 void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStream_t s) {
   dpp_problem P = pc->prob;
+  if (P->dg) {
+    DPP_CHECK(!fp32, DPP_ERR_UNSUPPORTED, "DG-VMS problems are solved in FP64");
+    dg_precond_apply(pc, r, z, s);
+    return;
+  }
   Level &L0 = *pc->lv[0];
   // the Schur right-hand side kernel also writes the finest level's first
   // Chebyshev step when that level smooths

@@ -127,11 +127,21 @@ struct dpp_precond_s {
   hipStream_t gstream = nullptr;  // capture/replay stream (default priority)
   double *hpin = nullptr;         // pinned host copy of one step's reductions
   hipEvent_t hev = nullptr;       // marks that copy
+  // DG-VMS: the nodal CG-VMS problem of the same box and coefficients with its
+  // own preconditioner (coarse level of the pressure blocks), and the DG
+  // level's diagonals, Chebyshev bounds and work vectors
+  std::unique_ptr<dpp_problem_s> dgcg;
+  dpp_precond_s *dgpc = nullptr;
+  dpp::DBuf dgzero, dgdu, dgds, dgrh, dgza, dgzb, dgd, dgtu, dgcb, dgcx, dgpart;
+  dpp::DBuf dgbinv, dgva, dgvb, dgvd, dgyu;  // velocity block: simplex-block inverses, Chebyshev work
+  double dghi[2] = {0.0, 0.0}, dglo[2] = {0.0, 0.0};    // pressure-block Chebyshev interval
+  double dgvhi[2] = {0.0, 0.0}, dgvlo[2] = {0.0, 0.0};  // velocity-block Chebyshev interval
   void drop_graphs() {
     for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
     graphs.clear();
   }
   ~dpp_precond_s() {
+    delete dgpc;  // before dgcg, the problem it belongs to
     drop_graphs();
     if (gstream) (void)hipStreamDestroy(gstream);
     if (hev) (void)hipEventDestroy(hev);
@@ -185,6 +195,8 @@ bool pure_flux(const Grid &g);
 void dg_assemble(dpp_problem P, const dpp_params *prm, hipStream_t s);
 void dg_spmv(dpp_problem P, const double *x, const double *bsub, double *y, hipStream_t s);
 void dg_export_csr(dpp_problem P, int64_t *rowptr, int32_t *cols, double *vals, hipStream_t s);
+void dg_precond_setup(dpp_precond pc, hipStream_t s);
+void dg_precond_apply(dpp_precond pc, const double *r, double *z, hipStream_t s);
 void consistent_rhs(dpp_problem P, double *b, hipStream_t s);
 void normalize_pressures(dpp_problem P, double *x, hipStream_t s);
 void vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s);  // FP64, [2][N] in/out
