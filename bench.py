@@ -47,6 +47,11 @@ WORKLOADS = {
                   "data on all faces",
     "h3_3d96_grf_q1": "3D unit cube 96^3 hexahedra with Q1 elements = 7,301,384 DOF; log-normal per-hex "
                       "k1, k2 (seeds 1001/1002)",
+    "g2_3d20_dg": "3D unit cube 20^3 x 6 tetrahedra with DG-VMS (discontinuous P1, 4 vertex slots per "
+                  "simplex) = 1,536,000 DOF (the largest TET row of the DG h-size study); k1=1, k2=0.1, "
+                  "beta=mu=1; manufactured-solution pressure data on all faces",
+    "g1_2d160_dg": "2D unit square 160^2 x 2 triangles with DG-VMS = 921,600 DOF (the largest TRI row of "
+                   "the DG h-size study); k1=1, k2=0.1, beta=mu=1",
     "c4_batch64": "64 independent 2D unit-square instances, n ~ U{32..256} cells per side (seed 2024), "
                   "beta ~ logU[0.1,10], k2/k1 ~ logU[1e-3,1]; one batched launch per phase",
 }
@@ -55,7 +60,7 @@ PRECISION = {0: "f64", 1: "f64+f32 refinement", 2: "f64 Krylov, f32 precondition
 
 # profiling families that are one kernel each (the roofline reports the one
 # with the largest share of the solve; the others group several kernels)
-SINGLE_KERNEL_FAMILIES = ("spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "schur_vel")
+SINGLE_KERNEL_FAMILIES = ("spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "schur_vel", "dg_vel")
 
 
 def kernel_source_sha():
@@ -66,9 +71,11 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def kernel_name(family, dim, pc, flux=False):
+def kernel_name(family, dim, pc, flux=False, dg=False):
     """rocprofv3 name of a single-kernel family's FP64 kernel (flux: the
-    instances for problems with velocity faces)."""
+    instances for problems with velocity faces; dg: DG-VMS problems)."""
+    if dg:
+        return {"spmv_K": "k_dg_spmv<%d>", "dg_vel": "k_dg_vcheb<%d>"}[family] % dim
     if family in ("cheb_S_l0", "resid_S_l0"):
         lanes, sym = pc.shape(0)
         k = "k_cheb" if family == "cheb_S_l0" else "k_lspmv"
@@ -120,10 +127,19 @@ def oracle_leg(prob, gpu_iters, sample_iters, solutions, ref_rtol=1e-11):
 
     from oracle import dpp as odpp
     from oracle import solver as osolver
+    dg = getattr(prob, "elem", "p1") == "dg"
     t0 = time.perf_counter()
-    S = odpp.assemble(prob)
-    t1 = time.perf_counter()
-    F = osolver.FieldSplit(S)
+    if dg:
+        from oracle import dg as odg
+        S = odg.assemble(prob)
+        t1 = time.perf_counter()
+        F = odg.FieldSplitDG(S, prob)
+        fs = odg.fields(prob.dim, S.S)
+    else:
+        S = odpp.assemble(prob)
+        t1 = time.perf_counter()
+        F = osolver.FieldSplit(S)
+        fs = odpp.fields(prob.dim, S.N)
     t2 = time.perf_counter()
     log("oracle assembly %.1f s, fieldsplit setup %.1f s" % (t1 - t0, t2 - t1))
     mv = lambda v: odpp.spmv(S.K, v)
@@ -134,15 +150,21 @@ def oracle_leg(prob, gpu_iters, sample_iters, solutions, ref_rtol=1e-11):
     full = res <= 1e-8
     n_dof = S.K.shape[0]
     log("oracle sample: %d iterations in %.1f s (rel. residual %.2e)" % (its, t_sample, res))
-    xr, its2, res2 = osolver.fgmres(S.K, S.f, F.apply, restart=30, rtol=ref_rtol, maxiter=600,
-                                    x0=x, matvec=mv)
-    log("oracle reference: %d more iterations, rel. residual %.2e" % (its2, res2))
+    # the reference continues restart cycle by restart cycle (the same
+    # iteration as one call), with a line after each
+    xr, its2, res2 = x, 0, res
+    while res2 > ref_rtol and its2 < 600:
+        xr, k, res2 = osolver.fgmres(S.K, S.f, F.apply, restart=30, rtol=ref_rtol, maxiter=30,
+                                     x0=xr, matvec=mv)
+        its2 += k
+        log("oracle reference: %d more iterations, rel. residual %.2e" % (its2, res2))
+        if k == 0:
+            break
     # a sample stopped at its bound is scaled to the iteration count of the
     # GPU solve (the same preconditioner definition; the oracle orthogonalises
     # by modified Gram-Schmidt, so the counts can differ by rounding)
     its_full = its if full else gpu_iters
     t_est = t_sample if full else t_sample / max(its, 1) * its_full
-    fs = odpp.fields(prob.dim, S.N)
     fn = np.linalg.norm(S.f)
     errs = {"reference": "CPU oracle FGMRES (FP64) to rel. residual %.0e (reached %.2e)"
                          % (ref_rtol, res2)}
@@ -151,16 +173,17 @@ def oracle_leg(prob, gpu_iters, sample_iters, solutions, ref_rtol=1e-11):
                       for f in ("u1", "p1", "u2", "p2")}
         errs[name]["oracle_residual"] = float(np.linalg.norm(S.f - mv(xg)) / fn)
     threads = odpp.threads()
+    pc_kind = "block-Jacobi Chebyshev, S_q steps, V-cycles" if dg else "V-cycles"
     base = {
         "value": n_dof / t_est, "unit": "DOF/s", "cores": threads, "kind": "oracle",
         "sample": ("oracle FGMRES solve of the same %d-DOF system to 1e-8 from x = 0: %d iterations "
                    "in %.2f s (assembly %.1f s and fieldsplit setup %.1f s not counted); CSR "
-                   "products on %d OpenMP threads, V-cycles and vector updates in numpy/scipy"
-                   % (n_dof, its, t_sample, t1 - t0, t2 - t1, threads)) if full else
+                   "products on %d OpenMP threads, %s and vector updates in numpy/scipy"
+                   % (n_dof, its, t_sample, t1 - t0, t2 - t1, threads, pc_kind)) if full else
                   ("first %d oracle FGMRES iterations on the same %d-DOF system (%.2f s), scaled to "
                    "the %d iterations of the GPU solve to 1e-8; CSR products on %d OpenMP threads, "
-                   "V-cycles and vector updates in numpy/scipy"
-                   % (its, n_dof, t_sample, its_full, threads)),
+                   "%s and vector updates in numpy/scipy"
+                   % (its, n_dof, t_sample, its_full, threads, pc_kind)),
         "solve_s": t_est, "iters": its_full, "gpu_iters": gpu_iters,
     }
     return base, errs
@@ -382,9 +405,14 @@ def main():
     if args.config == "c4_batch64":
         return bench_batch(args, torch, I, dpp)
     prob = I.make_config(args.config)
+    dg = prob.elem == "dg"
+    if dg and (args.precision != 0 or args.shapes):
+        print("bench.py: DG-VMS solves run in FP64 with the default shapes (no --precision, --shapes)",
+              file=sys.stderr)
+        sys.exit(2)
     # load the library's code objects on a small box first, so that the
     # assembly and setup times below are the work itself
-    Pw = dpp.assemble_problem(I.mms_problem(prob.dim, 4))
+    Pw = dpp.assemble_problem(I.mms_problem(prob.dim, 4, elem=prob.elem))
     Pw.solve(Pw.setup_precond(), rtol=1e-6)
     del Pw
     torch.cuda.synchronize()
@@ -421,7 +449,7 @@ def main():
         "iters": iters, "rel_residual": st.rel_residual,
         "assemble_ms": (t1 - t0) * 1e3, "setup_ms": (t2 - t1) * 1e3,
     }
-    if args.precision == 0 and not args.no_mixed:
+    if args.precision == 0 and not args.no_mixed and not dg:
         # the mixed-precision solve of the same system, timed the same way
         msm, (xm, stm) = timed(torch, lambda: P.solve(pc, **{**opts, "precision": 1}),
                                args.steps, args.warmup)
@@ -436,7 +464,8 @@ def main():
         kernels = profiled(dpp, lambda: P.solve(pc, **opts), args.steps)
         line["roofline"] = roofline(kernels, SINGLE_KERNEL_FAMILIES, copy_gbs,
                                     lambda k: kernel_name(k, stencil_tag(prob), pc,
-                                                          flux=getattr(prob, "face_bc", None) is not None),
+                                                          flux=getattr(prob, "face_bc", None) is not None,
+                                                          dg=dg),
                                     args.config)
         line["kernels"] = strip_raw(kernels)
     else:

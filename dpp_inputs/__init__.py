@@ -151,7 +151,8 @@ def mms_problem(dim, n, k1=1.0, k2=0.1, beta=1.0, mu=1.0, L=None, bc_params=None
     bc_params (k1, k2, beta, mu) overrides the parameters used for the boundary
     pressures (heterogeneous-permeability workloads keep the homogeneous MMS
     boundary data).  flux_faces: None, or [2, 2*dim] face flags (see Problem)
-    whose velocity faces take the exact normal velocities.  elem: "p1" or "q1".
+    whose velocity faces take the exact normal velocities.  elem: "p1", "q1" or
+    "dg".
     """
     n = tuple(int(v) for v in (n if np.ndim(n) else (n,) * dim))
     L = tuple(L or (1.0,) * dim)
@@ -265,9 +266,11 @@ CONFIGS = {
     "h2_3d64_q1": dict(kind="mms", dim=3, n=64, k1=1.0, k2=1e-2, beta=1.0, mu=1.0, elem="q1"),
     "h3_3d96_grf_q1": dict(kind="grf", dim=3, n=96, elem="q1"),
     # DG-VMS (discontinuous P1 on the Kuhn simplices): the appendix DG-VMS
-    # listing's data (k1 = 1, k2 = 0.1, beta = mu = 1), 3D and 2D
-    "g2_3d32_dg": dict(kind="mms", dim=3, n=32, k1=1.0, k2=0.1, beta=1.0, mu=1.0, elem="dg"),
-    "g1_2d256_dg": dict(kind="mms", dim=2, n=256, k1=1.0, k2=0.1, beta=1.0, mu=1.0, elem="dg"),
+    # listing's data (k1 = 1, k2 = 0.1, beta = mu = 1), 3D and 2D;
+    # the largest DG-VMS rows of the h-size tables: TET h = 1/20 (1,536,000
+    # DOF) and TRI h = 1/160 (921,600 DOF)
+    "g2_3d20_dg": dict(kind="mms", dim=3, n=20, k1=1.0, k2=0.1, beta=1.0, mu=1.0, elem="dg"),
+    "g1_2d160_dg": dict(kind="mms", dim=2, n=160, k1=1.0, k2=0.1, beta=1.0, mu=1.0, elem="dg"),
 }
 
 

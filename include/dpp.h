@@ -312,6 +312,10 @@ dpp_status dpp_simplex_rule(int dim, int q, double *lam, double *w);
  *  10 Schur right-hand side and      11 coarser levels, grid transfers and
  *     velocity step                     coarse solves
  *  12 Arnoldi passes
+ * and of the DG-VMS fieldsplit:
+ *  13 velocity-block Chebyshev steps 14 pressure side (K_up products, S_q
+ *     with the simplex-block Jacobi     Chebyshev steps, r_p - K_pu y_u)
+ *  15 slot/node transfers around the nodal cycle
  * dpp_profile_read synchronises on the recorded events and returns the launch
  * count, total milliseconds and total algorithmic bytes of one family. */
 dpp_status dpp_profile_enable(int on);

@@ -129,7 +129,7 @@ def _stream(stream=None):
 
 PROFILE_FAMILIES = ["spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "schur_vel", "coarse_levels",
                     "vector_l0", "arnoldi", "batch_spmv_K", "batch_cheb_S_l0", "batch_schur",
-                    "batch_levels", "batch_arnoldi"]
+                    "batch_levels", "batch_arnoldi", "dg_vel", "dg_pres", "dg_transfer"]
 
 
 def profile_enable(on=True):

@@ -744,7 +744,8 @@ void dg_assemble(dpp_problem P, const dpp_params *prm, hipStream_t s) {
     DPP_HIP(hipStreamSynchronize(s));
     for (int v : nb) interior += v >= 0;
   }
-  P->nnz = 2 * ((nc + interior) * (long)SB * SB + nc * (long)(d + 1) * (d + 1));
+  P->dgcoupled = nc + interior;
+  P->nnz = 2 * (P->dgcoupled * (long)SB * SB + nc * (long)(d + 1) * (d + 1));
 }
 
 void dg_spmv(dpp_problem P, const double *x, const double *bsub, double *y, hipStream_t s) {
@@ -753,8 +754,10 @@ void dg_spmv(dpp_problem P, const double *x, const double *bsub, double *y, hipS
   const long nc = g.nc;
   const int SB = (d + 1) * (d + 1);
   const dim3 grid(blocks_for(nc * SB, 256), 2);
-  ProfScope ps(PF_SPMV_K, 2.0 * 8.0 * ((double)nc * (d + 2) * SB * SB + (double)nc * (d + 1) * (d + 1)) +
-                              8.0 * P->ndof() * (bsub ? 3.0 : 2.0), s);
+  // algorithmic bytes: the coupled blocks and transfer blocks once, the
+  // neighbour table, x and y (and b) once
+  ProfScope ps(PF_SPMV_K, 2.0 * 8.0 * ((double)P->dgcoupled * SB * SB + (double)nc * (d + 1) * (d + 1)) +
+                              4.0 * nc * (d + 1) + 8.0 * P->ndof() * (bsub ? 3.0 : 2.0), s);
   if (d == 3)
     k_dg_spmv<3><<<grid, 256, 0, s>>>(nc, P->nslot, P->dgA.as<double>(), P->dgB.as<double>(), P->dgnb.as<int>(),
                                       x, bsub, y);
@@ -845,6 +848,12 @@ void dg_vsolve(dpp_precond pc, DGVec b, const double *tu, DGOut out, hipStream_t
       }
     }
     const DGOut o = k + 1 == DG_VEL_DEGREE ? out : DGOut{buf[k & 1], nc * NU};
+    // bytes: K_uu of the coupled blocks (not on the first step, x = 0), the
+    // block inverses, b (less tu), x and dd read, dd and x' written
+    const double vecs = 2.0 + (tu ? 1.0 : 0.0) + (k > 0 ? 2.0 : 0.0) + 1.0;
+    ProfScope ps(PF_DG_VEL,
+                 2.0 * 8.0 * ((k > 0 ? (double)P->dgcoupled * NU * NU : 0.0) + (double)nc * NU * NU +
+                              vecs * nc * NU) + (k > 0 ? 4.0 * nc * (d + 1) : 0.0), s);
     k_dg_vcheb<d><<<gv, DGV_BS, 0, s>>>(nc, P->dgA.as<double>(), P->dgnb.as<int>(), pc->dgbinv.as<double>(), b,
                                         tu, xin, o, pc->dgvd.as<double>(), c1, c2, false);
     xin = DGVec{o.base, o.stride};
@@ -967,12 +976,25 @@ void dg_apply_impl(dpp_precond pc, const double *r, double *z, hipStream_t s) {
   double *rh = pc->dgrh.as<double>();
   const long NU = (d + 1) * d, vstride = (d + 1) * nslot;  // network stride of the ABI vector
   dg_vsolve<d>(pc, DGVec{r + off_u(d, nslot, 0), vstride}, nullptr, DGOut{pc->dgyu.as<double>(), nc * NU}, s);
-  k_dg_rhat<d><<<gp, 256, 0, s>>>(nc, nslot, A, nb, pc->dgyu.as<double>(), r, rh);
+  // algorithmic bytes of the pressure-side launches (2 networks): K_pu or
+  // K_up of the coupled blocks, the neighbour table, vectors once
+  const double cp = (double)P->dgcoupled, nbr_b = 4.0 * nc * (d + 1);
+  const double b_tu = 2.0 * 8.0 * (cp * NU * (d + 1) + (double)nslot + (double)nc * NU) + nbr_b;
+  {
+    ProfScope ps(PF_DG_PRES, 2.0 * 8.0 * (cp * NU * (d + 1) + (double)nc * NU + 2.0 * nslot) + nbr_b, s);
+    k_dg_rhat<d><<<gp, 256, 0, s>>>(nc, nslot, A, nb, pc->dgyu.as<double>(), r, rh);
+  }
   // coarse correction on the nodes, back to the slots
-  k_dg_restrict<d><<<dim3(blocks_for(g.N, 256), 2), 256, 0, s>>>(dev(g), nslot, rh, pc->dgcb.as<double>());
+  {
+    ProfScope ps(PF_DG_TRANSFER, 2.0 * 8.0 * ((double)nslot + (double)g.N), s);
+    k_dg_restrict<d><<<dim3(blocks_for(g.N, 256), 2), 256, 0, s>>>(dev(g), nslot, rh, pc->dgcb.as<double>());
+  }
   vcycle(pc->dgpc, pc->dgcb.as<double>(), pc->dgcx.as<double>(), s);
   double *cur = pc->dgza.as<double>(), *oth = pc->dgzb.as<double>();
-  k_dg_prolong<d><<<gp, 256, 0, s>>>(dev(g), nc, nslot, pc->dgcx.as<double>(), cur);
+  {
+    ProfScope ps(PF_DG_TRANSFER, 2.0 * 8.0 * ((double)nslot + (double)g.N), s);
+    k_dg_prolong<d><<<gp, 256, 0, s>>>(dev(g), nc, nslot, pc->dgcx.as<double>(), cur);
+  }
   // Chebyshev post-smoothing on S_q (Saad, Alg. 12.1 with the diagonal of S_q)
   const int deg = pc->opts.cheb_post_fine >= 1 ? pc->opts.cheb_post_fine : pc->opts.cheb_degree;
   double sig[2], rho[2], th[2], de[2];
@@ -994,17 +1016,31 @@ void dg_apply_impl(dpp_precond pc, const double *r, double *z, hipStream_t s) {
         rho[q] = rn;
       }
     }
-    k_dg_tu<d><<<dim3(blocks_for(nc * (d + 1) * d, 256), 2), 256, 0, s>>>(nc, nslot, A, nb, cur,
-                                                                           pc->dgtu.as<double>());
-    k_dg_sp<d><<<gp, 256, 0, s>>>(nc, nslot, A, nb, du, pc->dgtu.as<double>(), cur, oth, ds, rh,
-                                  pc->dgd.as<double>(), c1, c2, true);
+    {
+      ProfScope ps(PF_DG_PRES, b_tu, s);
+      k_dg_tu<d><<<dim3(blocks_for(nc * NU, 256), 2), 256, 0, s>>>(nc, nslot, A, nb, cur, pc->dgtu.as<double>());
+    }
+    {
+      // S_q rows: K_pu and K_pp of the coupled blocks; D_u^-1 and tu of the
+      // neighbours; x, diag, b, dd (read after the first step), dd, x' written
+      ProfScope ps(PF_DG_PRES,
+                   2.0 * 8.0 * (cp * (d + 1) * SB + 2.0 * nc * NU + (k > 0 ? 6.0 : 5.0) * nslot) + nbr_b, s);
+      k_dg_sp<d><<<gp, 256, 0, s>>>(nc, nslot, A, nb, du, pc->dgtu.as<double>(), cur, oth, ds, rh,
+                                    pc->dgd.as<double>(), c1, c2, true);
+    }
     std::swap(cur, oth);
   }
   // z_u ~ K_uu^-1 (r_u - K_up z_p), z_p
-  k_dg_tu<d><<<dim3(blocks_for(nc * NU, 256), 2), 256, 0, s>>>(nc, nslot, A, nb, cur, pc->dgtu.as<double>());
+  {
+    ProfScope ps(PF_DG_PRES, b_tu, s);
+    k_dg_tu<d><<<dim3(blocks_for(nc * NU, 256), 2), 256, 0, s>>>(nc, nslot, A, nb, cur, pc->dgtu.as<double>());
+  }
   dg_vsolve<d>(pc, DGVec{r + off_u(d, nslot, 0), vstride}, pc->dgtu.as<double>(),
                DGOut{z + off_u(d, nslot, 0), vstride}, s);
-  k_dg_copyp<d><<<gp, 256, 0, s>>>(nslot, cur, z);
+  {
+    ProfScope ps(PF_DG_PRES, 2.0 * 2.0 * 8.0 * nslot, s);
+    k_dg_copyp<d><<<gp, 256, 0, s>>>(nslot, cur, z);
+  }
   check_launch("DG fieldsplit");
 }
 

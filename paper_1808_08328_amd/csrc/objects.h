@@ -74,6 +74,7 @@ struct dpp_problem_s {
   dpp::DBuf dgA;        // [2][n_cells][dim+2][SB][SB] element blocks (SB = (dim+1)^2)
   dpp::DBuf dgB;        // [n_cells][dim+1][dim+1] inter-network transfer -(beta/mu) M
   dpp::DBuf dgnb;       // [n_cells][dim+1] facet neighbours (-1: boundary)
+  long dgcoupled = 0;   // (simplex, simplex) blocks per network: self plus interior facets
   long npos() const { return dg ? nslot : g.N; }  // positions per field component
   long ndof() const { return (long)(2 * g.dim + 2) * npos(); }
 };

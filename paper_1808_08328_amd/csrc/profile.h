@@ -22,7 +22,11 @@ enum ProfFamily {
   PF_B_SCHUR = 10,   // Schur right-hand side and velocity step
   PF_B_LEVELS = 11,  // coarser levels, restriction, prolongation, coarse solves
   PF_B_ARNOLDI = 12, // DCGS2 passes and their finish kernels
-  PF_COUNT = 13
+  // DG-VMS fieldsplit (both networks in one launch)
+  PF_DG_VEL = 13,    // velocity-block Chebyshev step with the simplex-block Jacobi
+  PF_DG_PRES = 14,   // pressure side: K_up products, S_q Chebyshev steps, r_p - K_pu y_u, z_p copy
+  PF_DG_TRANSFER = 15,  // slots to nodes and back around the nodal cycle
+  PF_COUNT = 16
 };
 
 bool prof_on();

@@ -53,7 +53,10 @@ def test_kernel_names_of_single_kernel_families():
     assert bench.kernel_name("spmv_K", 2, pc, flux=True) == "k_spmv_K<2, double, true>"
     assert bench.kernel_name("schur_rhs", 3, pc) == "k_schur_rhs<3, double, double, false>"
     assert bench.kernel_name("schur_vel", 3, pc, flux=True) == "k_schur_vel<3, double, double, true>"
-    assert set(bench.SINGLE_KERNEL_FAMILIES) == {"spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "schur_vel"}
+    assert bench.kernel_name("spmv_K", 3, pc, dg=True) == "k_dg_spmv<3>"
+    assert bench.kernel_name("dg_vel", 2, pc, dg=True) == "k_dg_vcheb<2>"
+    assert set(bench.SINGLE_KERNEL_FAMILIES) == {"spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "schur_vel",
+                                                 "dg_vel"}
 
 
 def test_oracle_leg_reference_and_baseline_on_a_small_box():
@@ -77,6 +80,23 @@ def test_oracle_leg_reference_and_baseline_on_a_small_box():
     assert errs["zero"]["oracle_residual"] == 1.0
     base, _ = bench.oracle_leg(prob, gpu_iters=20, sample_iters=200, solutions={})
     assert "to 1e-8 from x = 0" in base["sample"]
+
+
+def test_oracle_leg_on_a_dg_box():
+    """The DG-VMS oracle leg (its own assembly and fieldsplit) on a 2D 6^2
+    box: the reference agrees with a direct solve on every field."""
+    import numpy as np
+
+    import dpp_inputs as I
+    from oracle import dg as odg
+    from oracle import dpp as odpp
+    prob = I.mms_problem(2, 6, elem="dg")
+    S = odg.assemble(prob)
+    xd = odpp.solve_direct(S.K, S.f)
+    base, errs = bench.oracle_leg(prob, gpu_iters=30, sample_iters=4, solutions={"direct": xd})
+    assert base["value"] > 0 and "block-Jacobi Chebyshev" in base["sample"]
+    assert all(errs["direct"][f] <= 1e-9 for f in ("u1", "p1", "u2", "p2"))
+    assert errs["direct"]["oracle_residual"] <= 1e-12
 
 
 def test_oracle_batch_leg_stops_at_its_budget():

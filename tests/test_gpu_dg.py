@@ -128,3 +128,52 @@ def test_dg_solves_in_fp64_only():
         assert e.value.status == 7
     with pytest.raises(dpp.DppError):
         P.solve_adjoint(pc, torch.zeros(P.n_dof, dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("workload", ["g1_2d160_dg", "g2_3d20_dg"])
+def test_dg_full_size_solve_oracle_residual(workload):
+    """The largest DG rows of the h-size study (921,600 and 1,536,000 DOF) in
+    the benchmark's launch configuration: the oracle's own FP64 K applied to
+    the GPU solution at 1e-8, and 2000 sampled rows of K against the oracle's."""
+    import time
+
+    import paper_1808_08328_amd as dpp
+    from oracle import dpp as odpp
+    t0 = time.time()
+
+    def step(msg):
+        print("full-size DG %s: %s (%.1f s)" % (workload, msg, time.time() - t0), flush=True)
+
+    step("start")
+    prob = I.make_config(workload)
+    P = dpp.assemble_problem(prob)
+    step("assembled")
+    pc = P.setup_precond()
+    step("preconditioner set up")
+    x, st = P.solve(pc)
+    step("solved in %d iterations" % st.iters)
+    assert st.converged == 1
+    xg = H(x)
+    rows = np.random.default_rng(0).integers(0, P.n_dof, 2000)
+    rp, ci, vv = (H(t) for t in P.export_csr())
+    del pc, P
+    torch.cuda.empty_cache()
+    step("exported")
+    S = odg.assemble(prob)
+    step("oracle assembled")
+    r = S.f - odpp.spmv(S.K, xg)
+    rel = np.linalg.norm(r) / np.linalg.norm(S.f)
+    step("oracle residual %.3e" % rel)
+    assert rel <= 1.05e-8
+    # the export lists every entry of the coupled blocks, the oracle only the
+    # entries its assembly touched: compare row values, absent = 0
+    scale = np.abs(S.K.data).max()
+    for rr in rows:
+        a, b = rp[rr], rp[rr + 1]
+        lo, hi = S.K.indptr[rr], S.K.indptr[rr + 1]
+        g = dict(zip(ci[a:b].tolist(), vv[a:b].tolist()))
+        assert len(g) == b - a
+        o = dict(zip(S.K.indices[lo:hi].tolist(), S.K.data[lo:hi].tolist()))
+        assert set(o) <= set(g), rr
+        assert max(abs(g[c] - o.get(c, 0.0)) for c in g) <= 1e-13 * scale, rr
