@@ -274,53 +274,228 @@ __global__ __launch_bounds__(128) void k_dg_assemble(GridDev g, double hx, doubl
   }
 }
 
-// y = K x (bsub null) or y = bsub - K x: one thread per (network, simplex,
-// local unknown); row r of every block is SB contiguous values.
+// ------------------------------------------------------ matrix-free rows --
+// The solve applies K and its blocks from the simplex geometry and the
+// coefficients instead of reading the stored blocks: on the uniform Kuhn
+// mesh a simplex's barycentric gradients, facet normals and facet areas
+// follow from its axis permutation and the box sizes, and every term of
+// eq. S4_dg_stiffness_matrix is a short sum over the simplex's vertices
+// (volume terms) or over the vertices of one facet (jump and average terms).
+// A product then moves the vectors, the coefficients and the neighbour
+// table instead of (d + 2) SB^2 block values per simplex.  The entries are
+// those of the assembly above, summed in another order.
+
+struct DGGeo {
+  double h[3];
+  double hd;  // twice the circumradius (the box-cell diagonal)
+  double mu;
+};
+
 template <int d>
-__global__ __launch_bounds__(256) void k_dg_spmv(long nc, long nslot, const double *__restrict__ A,
-                                                 const double *__restrict__ B, const int *__restrict__ nbr,
+struct DGShape {
+  double G[d + 1][d];    // barycentric gradients
+  double nrm[d + 1][d];  // outward unit normal of the facet opposite each vertex
+  double wf[d + 1];      // facet mass weight: Mf[a][b] = wf (1 + delta_ab)
+  double mc, vm, vol;    // M[a][b] = mc (1 + delta_ab); vm = vol / (d + 1)
+};
+
+// Shape data of simplex e (its type is e mod the simplices per box; the
+// permutation is formed without a lookup table so that it stays in registers)
+template <int d>
+__device__ inline void dg_shape(const DGGeo &geo, long e, DGShape<d> &S) {
+  const int s = (int)(e % dg_nper(d));
+  int p[d];
+  if constexpr (d == 2) {
+    p[0] = s;
+    p[1] = 1 - s;
+  } else {  // lexicographic permutations of {0, 1, 2}
+    const int f = s >> 1, lo = f == 0 ? 1 : 0, hi = f == 2 ? 1 : 2;
+    p[0] = f;
+    p[1] = (s & 1) ? hi : lo;
+    p[2] = (s & 1) ? lo : hi;
+  }
+#pragma unroll
+  for (int c = 0; c < d; ++c) {
+    const double ih = 1.0 / geo.h[c];
+    S.G[0][c] = p[0] == c ? -ih : 0.0;
+#pragma unroll
+    for (int k = 1; k < d; ++k) S.G[k][c] = p[k - 1] == c ? ih : (p[k] == c ? -ih : 0.0);
+    S.G[d][c] = p[d - 1] == c ? ih : 0.0;
+  }
+  double v = 1.0;
+#pragma unroll
+  for (int a = 0; a < d; ++a) v *= geo.h[a];
+  S.vol = v / (d == 3 ? 6.0 : 2.0);
+  S.mc = S.vol / ((d + 1) * (d + 2));
+  S.vm = S.vol / (d + 1);
+  const double mf0 = 1.0 / (d * (d + 1));
+#pragma unroll
+  for (int k = 0; k <= d; ++k) {
+    double gn = 0.0;
+#pragma unroll
+    for (int c = 0; c < d; ++c) gn += S.G[k][c] * S.G[k][c];
+    gn = sqrt(gn);
+    S.wf[k] = d * S.vol * gn * mf0;
+#pragma unroll
+    for (int c = 0; c < d; ++c) S.nrm[k][c] = -S.G[k][c] / gn;
+  }
+}
+
+// Volume terms of the selected blocks of one simplex: yu += K_uu xu (UU) +
+// K_up xp (UP), yp += K_pu xu (PU) + K_pp xp (PP, without the transfer).
+template <int d, bool UU, bool UP, bool PU, bool PP>
+__device__ inline void dg_volume(const DGShape<d> &S, double alpha, double kappa, double bm, const double *xu,
+                                 const double *xp, double *yu, double *yp) {
+  double su[d], gp[d], sp = 0.0, divu = 0.0;
+#pragma unroll
+  for (int c = 0; c < d; ++c) su[c] = gp[c] = 0.0;
+  if constexpr (UU || PU) {
+#pragma unroll
+    for (int b = 0; b <= d; ++b)
+#pragma unroll
+      for (int c = 0; c < d; ++c) {
+        su[c] += xu[b * d + c];
+        if constexpr (PU) divu += S.G[b][c] * xu[b * d + c];
+      }
+  }
+  if constexpr (UP || PP) {
+#pragma unroll
+    for (int b = 0; b <= d; ++b) {
+      sp += xp[b];
+#pragma unroll
+      for (int c = 0; c < d; ++c) gp[c] += S.G[b][c] * xp[b];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a <= d; ++a) {
+#pragma unroll
+    for (int c = 0; c < d; ++c) {
+      if constexpr (UU) yu[a * d + c] += 0.5 * alpha * S.mc * (xu[a * d + c] + su[c]);
+      if constexpr (UP) yu[a * d + c] -= S.vm * (S.G[a][c] * sp + 0.5 * gp[c]);
+    }
+    if constexpr (PU) {
+      double g = 0.0;
+#pragma unroll
+      for (int c = 0; c < d; ++c) g += S.G[a][c] * su[c];
+      yp[a] += S.vm * (divu + 0.5 * g);
+    }
+    if constexpr (PP) {
+      double g = 0.0;
+#pragma unroll
+      for (int c = 0; c < d; ++c) g += S.G[a][c] * gp[c];
+      yp[a] += 0.5 * kappa * S.vol * g + bm * S.mc * (xp[a] + sp);
+    }
+  }
+}
+
+// Terms of the interior facet opposite own vertex k, with the neighbour's
+// values nu, np in its own numbering (own vertex b is its vertex m(b)):
+// cu = ETA_U hd {mu/k}, cp = (ETA_P / hd) {k/mu} (averages over the facet).
+// With the normal jump [x_u.n], the pressure jump [x_p] and the pressure sum
+// at the facet vertices, own rows a != k take
+//   y_u(a, c) += cu n_c (Mf [x_u.n])_a + (1/2) n_c (Mf (x_p + x_p'))_a
+//   y_p(a)    += -(1/2) (Mf [x_u.n])_a + cp (Mf [x_p])_a
+template <int d, bool UU, bool UP, bool PU, bool PP>
+__device__ inline void dg_facet(const DGShape<d> &S, int k, double cu, double cp, const double *xu, const double *xp,
+                                const double *nu, const double *np, double *yu, double *yp) {
+  double Jn[d + 1], Jp[d + 1], Sp[d + 1], sJn = 0.0, sJp = 0.0, sSp = 0.0;
+#pragma unroll
+  for (int b = 0; b <= d; ++b) {
+    Jn[b] = Jp[b] = Sp[b] = 0.0;
+    if (b == k) continue;
+    const int m = k == 0 ? b - 1 : (k == d ? b + 1 : b);
+    if constexpr (UU || PU) {
+      double j = 0.0;
+#pragma unroll
+      for (int c = 0; c < d; ++c) j += S.nrm[k][c] * (xu[b * d + c] - nu[m * d + c]);
+      Jn[b] = j;
+      sJn += j;
+    }
+    if constexpr (PP) {
+      Jp[b] = xp[b] - np[m];
+      sJp += Jp[b];
+    }
+    if constexpr (UP) {
+      Sp[b] = xp[b] + np[m];
+      sSp += Sp[b];
+    }
+  }
+  const double w = S.wf[k];
+#pragma unroll
+  for (int a = 0; a <= d; ++a) {
+    if (a == k) continue;
+    const double mjn = w * (Jn[a] + sJn), mjp = w * (Jp[a] + sJp), msp = w * (Sp[a] + sSp);
+#pragma unroll
+    for (int c = 0; c < d; ++c) {
+      if constexpr (UU) yu[a * d + c] += cu * S.nrm[k][c] * mjn;
+      if constexpr (UP) yu[a * d + c] += 0.5 * S.nrm[k][c] * msp;
+    }
+    if constexpr (PU) yp[a] -= 0.5 * mjn;
+    if constexpr (PP) yp[a] += cp * mjp;
+  }
+}
+
+template <int n>
+__device__ inline void dg_ld(const double *__restrict__ p, double *v) {
+#pragma unroll
+  for (int j = 0; j < n; ++j) v[j] = p[j];
+}
+template <int n>
+__device__ inline void dg_ldi(const int *__restrict__ p, int *v) {
+#pragma unroll
+  for (int j = 0; j < n; ++j) v[j] = p[j];
+}
+
+// y = K x (bsub null) or y = bsub - K x: one thread per (network, simplex)
+// computes the (d + 1)^2 rows of its simplex.
+template <int d>
+__global__ __launch_bounds__(256) void k_dg_spmv(DGGeo geo, long nc, long nslot, const double *__restrict__ k1,
+                                                 const double *__restrict__ k2, const double *__restrict__ betac,
+                                                 double beta, const int *__restrict__ nbr,
                                                  const double *__restrict__ x, const double *__restrict__ bsub,
                                                  double *__restrict__ y) {
-  constexpr int SB = dg_sb(d);
-  constexpr int NB = d + 2;
-  constexpr int NU = (d + 1) * d;
+  constexpr int NU = (d + 1) * d, NV = d + 1;
   const int q = blockIdx.y;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nc * SB) return;
-  const long e = t / SB;
-  const int r = (int)(t % SB);
-  const long ou = off_u(d, nslot, q), op = off_p(d, nslot, q);
-  const double *Ar = A + ((size_t)q * nc + e) * NB * SB * SB + (size_t)r * SB;
-  double acc = 0.0;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nc) return;
+  DGShape<d> S;
+  dg_shape<d>(geo, e, S);
+  const double *kq = q ? k2 : k1;
+  const double ke = kq[e], alpha = geo.mu / ke, kappa = ke / geo.mu;
+  const double bm = (betac ? betac[e] : beta) / geo.mu;
+  const double *xuq = x + off_u(d, nslot, q), *xpq = x + off_p(d, nslot, q);
+  double xu[NU], xp[NV], xo[NV], yu[NU], yp[NV];
+  dg_ld<NU>(xuq + e * NU, xu);
+  dg_ld<NV>(xpq + e * NV, xp);
+  dg_ld<NV>(x + off_p(d, nslot, 1 - q) + e * NV, xo);
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const long s = b == 0 ? e : nbr[e * (d + 1) + b - 1];
-    if (s < 0) continue;
-    const double *Ab = Ar + (size_t)b * SB * SB;
-    const double *xu = x + ou + s * NU, *xp = x + op + s * (d + 1);
+  for (int j = 0; j < NU; ++j) yu[j] = 0.0;
 #pragma unroll
-    for (int c = 0; c < NU; c += 2) {
-      double a0, a1, x0, x1;
-      ld2(Ab + c, a0, a1);
-      ld2(xu + c, x0, x1);
-      acc += a0 * x0 + a1 * x1;
-    }
+  for (int j = 0; j < NV; ++j) yp[j] = 0.0;
+  dg_volume<d, true, true, true, true>(S, alpha, kappa, bm, xu, xp, yu, yp);
+  // transfer -(beta/mu) M to the other network's pressures
+  double so = 0.0;
 #pragma unroll
-    for (int c = 0; c <= d; ++c) acc += Ab[NU + c] * xp[c];
+  for (int b = 0; b <= d; ++b) so += xo[b];
+#pragma unroll
+  for (int a = 0; a <= d; ++a) yp[a] -= bm * S.mc * (xo[a] + so);
+  int nb[NV];
+  dg_ldi<NV>(nbr + e * NV, nb);
+#pragma unroll
+  for (int k = 0; k <= d; ++k) {
+    if (nb[k] < 0) continue;
+    double nu[NU], np[NV];
+    dg_ld<NU>(xuq + (long)nb[k] * NU, nu);
+    dg_ld<NV>(xpq + (long)nb[k] * NV, np);
+    const double kn = kq[nb[k]];
+    dg_facet<d, true, true, true, true>(S, k, ETA_U * geo.hd * 0.5 * (alpha + geo.mu / kn),
+                                        (ETA_P / geo.hd) * 0.5 * (kappa + kn / geo.mu), xu, xp, nu, np, yu, yp);
   }
-  long row;
-  if (r < NU) {
-    row = ou + e * NU + r;
-  } else {
-    const int a = r - NU;
-    row = op + e * (d + 1) + a;
-    // transfer to the other network's pressures of the same simplex
-    const double *Be = B + (size_t)e * (d + 1) * (d + 1) + a * (d + 1);
-    const double *xo = x + off_p(d, nslot, 1 - q) + e * (d + 1);
+  const long ou = off_u(d, nslot, q) + e * NU, op = off_p(d, nslot, q) + e * NV;
 #pragma unroll
-    for (int c = 0; c <= d; ++c) acc += Be[c] * xo[c];
-  }
-  y[row] = bsub ? bsub[row] - acc : acc;
+  for (int j = 0; j < NU; ++j) y[ou + j] = bsub ? bsub[ou + j] - yu[j] : yu[j];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) y[op + j] = bsub ? bsub[op + j] - yp[j] : yp[j];
 }
 
 // CSR export: row r of simplex e lists its blocks' columns (self, then the
@@ -406,81 +581,130 @@ __global__ void k_dg_diag_s(long nc, const double *__restrict__ A, const int *__
 }
 
 // rhat = r_p - K_pu y_u (y_u [2][n_cells NU], the velocity solve's output):
-// one thread per (network, simplex, pressure row)
+// one thread per (network, simplex)
 template <int d>
-__global__ void k_dg_rhat(long nc, long nslot, const double *__restrict__ A, const int *__restrict__ nbr,
-                          const double *__restrict__ yu, const double *__restrict__ r, double *__restrict__ rh) {
-  constexpr int SB = dg_sb(d), NB = d + 2, NU = (d + 1) * d;
+__global__ __launch_bounds__(256) void k_dg_rhat(DGGeo geo, long nc, long nslot, const int *__restrict__ nbr,
+                                                 const double *__restrict__ yu, const double *__restrict__ r,
+                                                 double *__restrict__ rh) {
+  constexpr int NU = (d + 1) * d, NV = d + 1;
   const int q = blockIdx.y;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nc * (d + 1)) return;
-  const long e = t / (d + 1);
-  const int a = (int)(t % (d + 1));
-  const double *Ar = A + (((size_t)q * nc + e) * NB * SB + NU + a) * SB;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nc) return;
+  DGShape<d> S;
+  dg_shape<d>(geo, e, S);
   const double *yq = yu + (size_t)q * nc * NU;
-  double acc = 0.0;
-  for (int b = 0; b < NB; ++b) {
-    const long s2 = b == 0 ? e : nbr[e * (d + 1) + b - 1];
-    if (s2 < 0) continue;
-    for (int c = 0; c < NU; ++c) acc += Ar[(size_t)b * SB * SB + c] * yq[s2 * NU + c];
+  double xu[NU], yp[NV];
+  dg_ld<NU>(yq + e * NU, xu);
+#pragma unroll
+  for (int j = 0; j < NV; ++j) yp[j] = 0.0;
+  dg_volume<d, false, false, true, false>(S, 0.0, 0.0, 0.0, xu, nullptr, nullptr, yp);
+  int nb[NV];
+  dg_ldi<NV>(nbr + e * NV, nb);
+#pragma unroll
+  for (int k = 0; k <= d; ++k) {
+    if (nb[k] < 0) continue;
+    double nu[NU];
+    dg_ld<NU>(yq + (long)nb[k] * NU, nu);
+    dg_facet<d, false, false, true, false>(S, k, 0.0, 0.0, xu, nullptr, nu, nullptr, nullptr, yp);
   }
-  rh[(size_t)q * nslot + t] = r[off_p(d, nslot, q) + t] - acc;
+  const double *rp = r + off_p(d, nslot, q) + e * NV;
+  double *o = rh + (size_t)q * nslot + e * NV;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) o[j] = rp[j] - yp[j];
 }
 
-// tu = K_up zp: one thread per (network, simplex, velocity row)
+// tu = K_up zp, or w = D_u^-1 K_up zp when du is given: one thread per
+// (network, simplex)
 template <int d>
-__global__ void k_dg_tu(long nc, long nslot, const double *__restrict__ A, const int *__restrict__ nbr,
-                        const double *__restrict__ zp, double *__restrict__ tu) {
-  constexpr int SB = dg_sb(d), NB = d + 2, NU = (d + 1) * d;
+__global__ __launch_bounds__(256) void k_dg_tu(DGGeo geo, long nc, long nslot, const int *__restrict__ nbr,
+                                               const double *__restrict__ zp, const double *__restrict__ du,
+                                               double *__restrict__ tu) {
+  constexpr int NU = (d + 1) * d, NV = d + 1;
   const int q = blockIdx.y;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nc * NU) return;
-  const long e = t / NU;
-  const int r = (int)(t % NU);
-  const double *Ar = A + (((size_t)q * nc + e) * NB * SB + r) * SB;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nc) return;
+  DGShape<d> S;
+  dg_shape<d>(geo, e, S);
   const double *z = zp + (size_t)q * nslot;
-  double acc = 0.0;
-  for (int b = 0; b < NB; ++b) {
-    const long s2 = b == 0 ? e : nbr[e * (d + 1) + b - 1];
-    if (s2 < 0) continue;
-    for (int c = 0; c <= d; ++c) acc += Ar[(size_t)b * SB * SB + NU + c] * z[s2 * (d + 1) + c];
+  double xp[NV], yu[NU];
+  dg_ld<NV>(z + e * NV, xp);
+#pragma unroll
+  for (int j = 0; j < NU; ++j) yu[j] = 0.0;
+  dg_volume<d, false, true, false, false>(S, 0.0, 0.0, 0.0, nullptr, xp, yu, nullptr);
+  int nb[NV];
+  dg_ldi<NV>(nbr + e * NV, nb);
+#pragma unroll
+  for (int k = 0; k <= d; ++k) {
+    if (nb[k] < 0) continue;
+    double np[NV];
+    dg_ld<NV>(z + (long)nb[k] * NV, np);
+    dg_facet<d, false, true, false, false>(S, k, 0.0, 0.0, nullptr, xp, nullptr, np, yu, nullptr);
   }
-  tu[(size_t)q * nc * NU + t] = acc;
+  const size_t o = (size_t)q * nc * NU + e * NU;
+  if (du) {
+#pragma unroll
+    for (int j = 0; j < NU; ++j) tu[o + j] = du[o + j] * yu[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < NU; ++j) tu[o + j] = yu[j];
+  }
 }
 
-// y = S_q x = K_pp x - K_pu (D_u^-1 tu) with tu = K_up x; with cheb, one
-// Chebyshev step instead: r = D_S^-1 (b - S_q x), dd = c1 dd + c2 r, xout = x + dd
+// y = S_q x = K_pp x - K_pu w with w = D_u^-1 K_up x (from k_dg_tu); with
+// cheb, one Chebyshev step instead: r = D_S^-1 (b - S_q x), dd = c1 dd + c2 r,
+// xout = x + dd.  One thread per (network, simplex).
 template <int d>
-__global__ void k_dg_sp(long nc, long nslot, const double *__restrict__ A, const int *__restrict__ nbr,
-                        const double *__restrict__ du, const double *__restrict__ tu,
-                        const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ ds,
-                        const double *__restrict__ b, double *__restrict__ dd, Sc2 c1, Sc2 c2, bool cheb) {
-  constexpr int SB = dg_sb(d), NB = d + 2, NU = (d + 1) * d;
+__global__ __launch_bounds__(256) void k_dg_sp(DGGeo geo, long nc, long nslot, const double *__restrict__ k1,
+                                               const double *__restrict__ k2, const double *__restrict__ betac,
+                                               double beta, const int *__restrict__ nbr,
+                                               const double *__restrict__ w, const double *__restrict__ x,
+                                               double *__restrict__ y, const double *__restrict__ ds,
+                                               const double *__restrict__ b, double *__restrict__ dd, Sc2 c1, Sc2 c2,
+                                               bool cheb) {
+  constexpr int NU = (d + 1) * d, NV = d + 1;
   const int q = blockIdx.y;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nc * (d + 1)) return;
-  const long e = t / (d + 1);
-  const int a = (int)(t % (d + 1));
-  const double *Ar = A + (((size_t)q * nc + e) * NB * SB + NU + a) * SB;
-  const double *duq = du + (size_t)q * nc * NU, *tq = tu + (size_t)q * nc * NU;
-  const double *xq = x + (size_t)q * nslot;
-  double acc = 0.0;
-  for (int bb = 0; bb < NB; ++bb) {
-    const long s2 = bb == 0 ? e : nbr[e * (d + 1) + bb - 1];
-    if (s2 < 0) continue;
-    const double *Ab = Ar + (size_t)bb * SB * SB;
-    for (int c = 0; c < NU; ++c) acc -= Ab[c] * duq[s2 * NU + c] * tq[s2 * NU + c];
-    for (int c = 0; c <= d; ++c) acc += Ab[NU + c] * xq[s2 * (d + 1) + c];
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nc) return;
+  DGShape<d> S;
+  dg_shape<d>(geo, e, S);
+  const double *kq = q ? k2 : k1;
+  const double ke = kq[e], alpha = geo.mu / ke, kappa = ke / geo.mu;
+  const double bm = (betac ? betac[e] : beta) / geo.mu;
+  const double *xq = x + (size_t)q * nslot, *wq = w + (size_t)q * nc * NU;
+  double xp[NV], wu[NU], ypp[NV], ypu[NV];
+  dg_ld<NV>(xq + e * NV, xp);
+  dg_ld<NU>(wq + e * NU, wu);
+#pragma unroll
+  for (int j = 0; j < NV; ++j) ypp[j] = ypu[j] = 0.0;
+  dg_volume<d, false, false, false, true>(S, alpha, kappa, bm, nullptr, xp, nullptr, ypp);
+  dg_volume<d, false, false, true, false>(S, alpha, kappa, bm, wu, nullptr, nullptr, ypu);
+  int nb[NV];
+  dg_ldi<NV>(nbr + e * NV, nb);
+#pragma unroll
+  for (int k = 0; k <= d; ++k) {
+    if (nb[k] < 0) continue;
+    double np[NV], nw[NU];
+    dg_ld<NV>(xq + (long)nb[k] * NV, np);
+    dg_ld<NU>(wq + (long)nb[k] * NU, nw);
+    const double kn = kq[nb[k]];
+    dg_facet<d, false, false, false, true>(S, k, 0.0, (ETA_P / geo.hd) * 0.5 * (kappa + kn / geo.mu), nullptr, xp,
+                                           nullptr, np, nullptr, ypp);
+    dg_facet<d, false, false, true, false>(S, k, 0.0, 0.0, wu, nullptr, nw, nullptr, nullptr, ypu);
   }
-  const size_t i = (size_t)q * nslot + t;
-  if (!cheb) {
-    y[i] = ds ? ds[i] * acc : acc;
-    return;
+  const size_t i0 = (size_t)q * nslot + e * NV;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const size_t i = i0 + j;
+    const double acc = ypp[j] - ypu[j];
+    if (!cheb) {
+      y[i] = ds ? ds[i] * acc : acc;
+      continue;
+    }
+    const double rr = ds[i] * (b[i] - acc);
+    const double dn = (c1.v[q] != 0.0 ? c1.v[q] * dd[i] : 0.0) + c2.v[q] * rr;
+    dd[i] = dn;
+    y[i] = xp[j] + dn;
   }
-  const double rr = ds[i] * (b[i] - acc);
-  const double dn = (c1.v[q] != 0.0 ? c1.v[q] * dd[i] : 0.0) + c2.v[q] * rr;
-  dd[i] = dn;
-  y[i] = xq[t] + dn;
 }
 
 // Inverses of the diagonal velocity blocks of K_uu (one per simplex and
@@ -533,36 +757,70 @@ struct DGOut {
 // Velocity-block Chebyshev step with the simplex-block Jacobi (Saad, Alg.
 // 12.1): res = b - K_uu x (b less tu when given; x = 0 when xin is null),
 // r' = Binv res, dd = c1 dd + c2 r', xout = x + dd.  power: xout = Binv (K_uu x)
-// (the power steps of the interval).  Workgroups of whole simplices
-// (192 threads: 16 in 3D, 32 in 2D); the simplex's residual goes through LDS.
+// (the power steps of the interval).  Workgroups of whole simplices (192
+// threads: 16 simplices in 3D, 32 in 2D): every thread stages one value of
+// its simplex and of each facet neighbour in LDS, one thread per simplex
+// forms the K_uu x rows, and one thread per row applies its row of Binv.
 constexpr int DGV_BS = 192;
 template <int d>
-__global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(long nc, const double *__restrict__ A,
-                                                     const int *__restrict__ nbr, const double *__restrict__ Bi,
-                                                     DGVec b, const double *__restrict__ tu, DGVec xin,
-                                                     DGOut xout, double *__restrict__ dd, Sc2 c1, Sc2 c2,
-                                                     bool power) {
-  constexpr int SB = dg_sb(d), NB = d + 2, NU = (d + 1) * d;
+__global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, long nc, const int *__restrict__ nbr,
+                                                     const double *__restrict__ k1, const double *__restrict__ k2,
+                                                     const double *__restrict__ Bi, DGVec b,
+                                                     const double *__restrict__ tu, DGVec xin, DGOut xout,
+                                                     double *__restrict__ dd, Sc2 c1, Sc2 c2, bool power) {
+  constexpr int NU = (d + 1) * d, NV = d + 1;
   constexpr int EPB = DGV_BS / NU;
+  static_assert(EPB * NU == DGV_BS, "whole simplices per workgroup");
+  __shared__ double xs[EPB][NV + 1][NU];
   __shared__ double sh[DGV_BS];
   const int q = blockIdx.y;
   const int loc = threadIdx.x / NU, r = threadIdx.x % NU;
   const long e = (long)blockIdx.x * EPB + loc;
-  const bool live = loc < EPB && e < nc;
+  const bool live = e < nc;
+  const double *xq = xin.base ? xin.base + (size_t)q * xin.stride : nullptr;
+  if (xq) {  // uniform over the launch
+    if (live) {
+      xs[loc][0][r] = xq[e * NU + r];
+#pragma unroll
+      for (int k = 0; k <= d; ++k) {
+        const int nb = nbr[e * NV + k];
+        xs[loc][1 + k][r] = nb >= 0 ? xq[(long)nb * NU + r] : 0.0;
+      }
+    }
+    __syncthreads();
+    const long es = (long)blockIdx.x * EPB + threadIdx.x;
+    if (threadIdx.x < EPB && es < nc) {
+      DGShape<d> S;
+      dg_shape<d>(geo, es, S);
+      const double *kq = q ? k2 : k1;
+      const double alpha = geo.mu / kq[es];
+      double xu[NU], yu[NU];
+#pragma unroll
+      for (int j = 0; j < NU; ++j) {
+        xu[j] = xs[threadIdx.x][0][j];
+        yu[j] = 0.0;
+      }
+      dg_volume<d, true, false, false, false>(S, alpha, 0.0, 0.0, xu, nullptr, yu, nullptr);
+      int nb[NV];
+      dg_ldi<NV>(nbr + es * NV, nb);
+#pragma unroll
+      for (int k = 0; k <= d; ++k) {
+        if (nb[k] < 0) continue;
+        double nu[NU];
+#pragma unroll
+        for (int j = 0; j < NU; ++j) nu[j] = xs[threadIdx.x][1 + k][j];
+        dg_facet<d, true, false, false, false>(S, k, ETA_U * geo.hd * 0.5 * (alpha + geo.mu / kq[nb[k]]), 0.0, xu,
+                                               nullptr, nu, nullptr, yu, nullptr);
+      }
+#pragma unroll
+      for (int j = 0; j < NU; ++j) sh[threadIdx.x * NU + j] = yu[j];
+    }
+    __syncthreads();
+  }
   double res = 0.0, xr = 0.0;
   if (live) {
-    double acc = 0.0;
-    if (xin.base) {
-      const double *Ar = A + (((size_t)q * nc + e) * NB * SB + r) * SB;
-      const double *xq = xin.base + (size_t)q * xin.stride;
-      for (int bb = 0; bb < NB; ++bb) {
-        const long s2 = bb == 0 ? e : nbr[e * (d + 1) + bb - 1];
-        if (s2 < 0) continue;
-        const double *Ab = Ar + (size_t)bb * SB * SB;
-        for (int c = 0; c < NU; ++c) acc += Ab[c] * xq[s2 * NU + c];
-      }
-      xr = xq[e * NU + r];
-    }
+    const double acc = xq ? sh[threadIdx.x] : 0.0;
+    if (xq) xr = xs[loc][0][r];
     if (power) {
       res = acc;
     } else {
@@ -570,11 +828,13 @@ __global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(long nc, const double *__re
       res = bv - acc;
     }
   }
+  __syncthreads();
   sh[threadIdx.x] = res;
   __syncthreads();
   if (!live) return;
   const double *Be = Bi + (((size_t)q * nc + e) * NU + r) * NU;
   double rp = 0.0;
+#pragma unroll
   for (int c = 0; c < NU; ++c) rp += Be[c] * sh[loc * NU + c];
   double *out = xout.base + (size_t)q * xout.stride + e * NU + r;
   if (power) {
@@ -703,6 +963,23 @@ __global__ void k_dg_scale(double *__restrict__ x, long n, const double *__restr
 
 }  // namespace
 
+namespace {
+DGGeo dg_geo(dpp_problem P) {
+  DGGeo geo{};
+  double hd = 0.0;
+  for (int a = 0; a < P->g.dim; ++a) {
+    geo.h[a] = P->g.h[a];
+    hd += P->g.h[a] * P->g.h[a];
+  }
+  geo.hd = std::sqrt(hd);
+  geo.mu = P->mu;
+  return geo;
+}
+const double *dg_betac(dpp_problem P) { return P->beta_per_cell ? P->betac.as<double>() : nullptr; }
+// coefficient bytes a product reads per network: k (and beta per simplex)
+double dg_coef_bytes(dpp_problem P) { return 8.0 * P->g.nc * (P->beta_per_cell ? 2.0 : 1.0); }
+}  // namespace
+
 void dg_assemble(dpp_problem P, const dpp_params *prm, hipStream_t s) {
   const Grid &g = P->g;
   const int d = g.dim;
@@ -752,18 +1029,17 @@ void dg_spmv(dpp_problem P, const double *x, const double *bsub, double *y, hipS
   const Grid &g = P->g;
   const int d = g.dim;
   const long nc = g.nc;
-  const int SB = (d + 1) * (d + 1);
-  const dim3 grid(blocks_for(nc * SB, 256), 2);
-  // algorithmic bytes: the coupled blocks and transfer blocks once, the
-  // neighbour table, x and y (and b) once
-  ProfScope ps(PF_SPMV_K, 2.0 * 8.0 * ((double)P->dgcoupled * SB * SB + (double)nc * (d + 1) * (d + 1)) +
-                              4.0 * nc * (d + 1) + 8.0 * P->ndof() * (bsub ? 3.0 : 2.0), s);
+  const dim3 grid(blocks_for(nc, 256), 2);
+  // algorithmic bytes (matrix-free): x and y (and b) once, the coefficients
+  // of both networks, the neighbour table
+  ProfScope ps(PF_SPMV_K, 8.0 * P->ndof() * (bsub ? 3.0 : 2.0) + 2.0 * dg_coef_bytes(P) + 4.0 * nc * (d + 1), s);
+  const DGGeo geo = dg_geo(P);
   if (d == 3)
-    k_dg_spmv<3><<<grid, 256, 0, s>>>(nc, P->nslot, P->dgA.as<double>(), P->dgB.as<double>(), P->dgnb.as<int>(),
-                                      x, bsub, y);
+    k_dg_spmv<3><<<grid, 256, 0, s>>>(geo, nc, P->nslot, P->k1.as<double>(), P->k2.as<double>(), dg_betac(P),
+                                      P->beta, P->dgnb.as<int>(), x, bsub, y);
   else
-    k_dg_spmv<2><<<grid, 256, 0, s>>>(nc, P->nslot, P->dgA.as<double>(), P->dgB.as<double>(), P->dgnb.as<int>(),
-                                      x, bsub, y);
+    k_dg_spmv<2><<<grid, 256, 0, s>>>(geo, nc, P->nslot, P->k1.as<double>(), P->k2.as<double>(), dg_betac(P),
+                                      P->beta, P->dgnb.as<int>(), x, bsub, y);
   check_launch("DG spmv");
 }
 
@@ -808,12 +1084,13 @@ namespace {
 template <int d>
 void dg_s_apply(dpp_precond pc, const double *x, double *y, const double *ds, hipStream_t s) {
   dpp_problem P = pc->prob;
-  const long nc = P->g.nc, nslot = P->nslot, NU = (d + 1) * d;
-  k_dg_tu<d><<<dim3(blocks_for(nc * NU, 256), 2), 256, 0, s>>>(nc, nslot, P->dgA.as<double>(), P->dgnb.as<int>(),
-                                                               x, pc->dgtu.as<double>());
-  k_dg_sp<d><<<dim3(blocks_for(nslot, 256), 2), 256, 0, s>>>(
-      nc, nslot, P->dgA.as<double>(), P->dgnb.as<int>(), pc->dgdu.as<double>(), pc->dgtu.as<double>(), x, y, ds,
-      nullptr, nullptr, Sc2{{0, 0}}, Sc2{{0, 0}}, false);
+  const long nc = P->g.nc, nslot = P->nslot;
+  const DGGeo geo = dg_geo(P);
+  const dim3 gs(blocks_for(nc, 256), 2);
+  k_dg_tu<d><<<gs, 256, 0, s>>>(geo, nc, nslot, P->dgnb.as<int>(), x, pc->dgdu.as<double>(), pc->dgtu.as<double>());
+  k_dg_sp<d><<<gs, 256, 0, s>>>(geo, nc, nslot, P->k1.as<double>(), P->k2.as<double>(), dg_betac(P), P->beta,
+                                P->dgnb.as<int>(), pc->dgtu.as<double>(), x, y, ds, nullptr, nullptr, Sc2{{0, 0}},
+                                Sc2{{0, 0}}, false);
 }
 
 constexpr int DG_VEL_DEGREE = 8;      // Chebyshev steps of the velocity-block solve
@@ -826,6 +1103,7 @@ void dg_vsolve(dpp_precond pc, DGVec b, const double *tu, DGOut out, hipStream_t
   dpp_problem P = pc->prob;
   const long nc = P->g.nc, NU = (d + 1) * d;
   const dim3 gv(blocks_for(nc, DGV_BS / NU), 2);
+  const DGGeo geo = dg_geo(P);
   double th[2], de[2], sig[2], rho[2];
   for (int q = 0; q < 2; ++q) {
     th[q] = 0.5 * (pc->dgvhi[q] + pc->dgvlo[q]);
@@ -848,14 +1126,16 @@ void dg_vsolve(dpp_precond pc, DGVec b, const double *tu, DGOut out, hipStream_t
       }
     }
     const DGOut o = k + 1 == DG_VEL_DEGREE ? out : DGOut{buf[k & 1], nc * NU};
-    // bytes: K_uu of the coupled blocks (not on the first step, x = 0), the
-    // block inverses, b (less tu), x and dd read, dd and x' written
+    // bytes: the block inverses; b (less tu), dd and x' written; after the
+    // first step (x = 0) also x and dd read, the coefficients and the
+    // neighbour table
     const double vecs = 2.0 + (tu ? 1.0 : 0.0) + (k > 0 ? 2.0 : 0.0) + 1.0;
     ProfScope ps(PF_DG_VEL,
-                 2.0 * 8.0 * ((k > 0 ? (double)P->dgcoupled * NU * NU : 0.0) + (double)nc * NU * NU +
-                              vecs * nc * NU) + (k > 0 ? 4.0 * nc * (d + 1) : 0.0), s);
-    k_dg_vcheb<d><<<gv, DGV_BS, 0, s>>>(nc, P->dgA.as<double>(), P->dgnb.as<int>(), pc->dgbinv.as<double>(), b,
-                                        tu, xin, o, pc->dgvd.as<double>(), c1, c2, false);
+                 2.0 * 8.0 * ((double)nc * NU * NU + vecs * nc * NU) +
+                     (k > 0 ? 2.0 * 8.0 * nc + 4.0 * nc * (d + 1) : 0.0), s);
+    k_dg_vcheb<d><<<gv, DGV_BS, 0, s>>>(geo, nc, P->dgnb.as<int>(), P->k1.as<double>(), P->k2.as<double>(),
+                                        pc->dgbinv.as<double>(), b, tu, xin, o, pc->dgvd.as<double>(), c1, c2,
+                                        false);
     xin = DGVec{o.base, o.stride};
   }
   check_launch("DG velocity solve");
@@ -937,9 +1217,9 @@ void dg_setup_impl(dpp_precond pc, hipStream_t s) {
     dg_sumsq(pc, vx, nu, ssd, s);
     k_dg_scale<<<gu, 256, 0, s>>>(vx, nu, ssd);
     for (int it = 0; it < o.power_iters; ++it) {
-      k_dg_vcheb<d><<<gb, DGV_BS, 0, s>>>(nc, P->dgA.as<double>(), P->dgnb.as<int>(), pc->dgbinv.as<double>(),
-                                          DGVec{nullptr, 0}, nullptr, DGVec{vx, nu}, DGOut{vy, nu}, nullptr,
-                                          Sc2{{0, 0}}, Sc2{{0, 0}}, true);
+      k_dg_vcheb<d><<<gb, DGV_BS, 0, s>>>(dg_geo(P), nc, P->dgnb.as<int>(), P->k1.as<double>(), P->k2.as<double>(),
+                                          pc->dgbinv.as<double>(), DGVec{nullptr, 0}, nullptr, DGVec{vx, nu},
+                                          DGOut{vy, nu}, nullptr, Sc2{{0, 0}}, Sc2{{0, 0}}, true);
       dg_sumsq(pc, vy, nu, ssd, s);
       k_dg_scale<<<gu, 256, 0, s>>>(vy, nu, ssd);
       std::swap(vx, vy);
@@ -969,20 +1249,21 @@ void dg_apply_impl(dpp_precond pc, const double *r, double *z, hipStream_t s) {
   dpp_problem P = pc->prob;
   const Grid &g = P->g;
   const long nc = g.nc, nslot = P->nslot;
-  const int SB = (d + 1) * (d + 1);
-  const double *A = P->dgA.as<double>(), *du = pc->dgdu.as<double>(), *ds = pc->dgds.as<double>();
+  const double *du = pc->dgdu.as<double>(), *ds = pc->dgds.as<double>();
+  const double *k1 = P->k1.as<double>(), *k2 = P->k2.as<double>(), *bc = dg_betac(P);
   const int *nb = P->dgnb.as<int>();
-  const dim3 gp(blocks_for(nslot, 256), 2);
+  const DGGeo geo = dg_geo(P);
+  const dim3 gp(blocks_for(nslot, 256), 2), gs(blocks_for(nc, 256), 2);
   double *rh = pc->dgrh.as<double>();
   const long NU = (d + 1) * d, vstride = (d + 1) * nslot;  // network stride of the ABI vector
   dg_vsolve<d>(pc, DGVec{r + off_u(d, nslot, 0), vstride}, nullptr, DGOut{pc->dgyu.as<double>(), nc * NU}, s);
-  // algorithmic bytes of the pressure-side launches (2 networks): K_pu or
-  // K_up of the coupled blocks, the neighbour table, vectors once
-  const double cp = (double)P->dgcoupled, nbr_b = 4.0 * nc * (d + 1);
-  const double b_tu = 2.0 * 8.0 * (cp * NU * (d + 1) + (double)nslot + (double)nc * NU) + nbr_b;
+  // algorithmic bytes of the pressure-side launches (2 networks, matrix-free):
+  // vectors once, the neighbour table, the coefficients where they enter
+  const double nbr_b = 4.0 * nc * (d + 1);
+  const double b_tu = 2.0 * 8.0 * ((double)nslot + (double)nc * NU) + nbr_b;  // zp in, tu out
   {
-    ProfScope ps(PF_DG_PRES, 2.0 * 8.0 * (cp * NU * (d + 1) + (double)nc * NU + 2.0 * nslot) + nbr_b, s);
-    k_dg_rhat<d><<<gp, 256, 0, s>>>(nc, nslot, A, nb, pc->dgyu.as<double>(), r, rh);
+    ProfScope ps(PF_DG_PRES, 2.0 * 8.0 * ((double)nc * NU + 2.0 * nslot) + nbr_b, s);
+    k_dg_rhat<d><<<gs, 256, 0, s>>>(geo, nc, nslot, nb, pc->dgyu.as<double>(), r, rh);
   }
   // coarse correction on the nodes, back to the slots
   {
@@ -1017,15 +1298,16 @@ void dg_apply_impl(dpp_precond pc, const double *r, double *z, hipStream_t s) {
       }
     }
     {
-      ProfScope ps(PF_DG_PRES, b_tu, s);
-      k_dg_tu<d><<<dim3(blocks_for(nc * NU, 256), 2), 256, 0, s>>>(nc, nslot, A, nb, cur, pc->dgtu.as<double>());
+      // w = D_u^-1 K_up x: x and D_u^-1 in, w out
+      ProfScope ps(PF_DG_PRES, b_tu + 2.0 * 8.0 * nc * NU, s);
+      k_dg_tu<d><<<gs, 256, 0, s>>>(geo, nc, nslot, nb, cur, du, pc->dgtu.as<double>());
     }
     {
-      // S_q rows: K_pu and K_pp of the coupled blocks; D_u^-1 and tu of the
-      // neighbours; x, diag, b, dd (read after the first step), dd, x' written
+      // S_q rows: w, x, diag, b, dd (read after the first step), dd and x'
+      // written, the coefficients
       ProfScope ps(PF_DG_PRES,
-                   2.0 * 8.0 * (cp * (d + 1) * SB + 2.0 * nc * NU + (k > 0 ? 6.0 : 5.0) * nslot) + nbr_b, s);
-      k_dg_sp<d><<<gp, 256, 0, s>>>(nc, nslot, A, nb, du, pc->dgtu.as<double>(), cur, oth, ds, rh,
+                   2.0 * 8.0 * ((double)nc * NU + (k > 0 ? 6.0 : 5.0) * nslot) + 2.0 * dg_coef_bytes(P) + nbr_b, s);
+      k_dg_sp<d><<<gs, 256, 0, s>>>(geo, nc, nslot, k1, k2, bc, P->beta, nb, pc->dgtu.as<double>(), cur, oth, ds, rh,
                                     pc->dgd.as<double>(), c1, c2, true);
     }
     std::swap(cur, oth);
@@ -1033,7 +1315,7 @@ void dg_apply_impl(dpp_precond pc, const double *r, double *z, hipStream_t s) {
   // z_u ~ K_uu^-1 (r_u - K_up z_p), z_p
   {
     ProfScope ps(PF_DG_PRES, b_tu, s);
-    k_dg_tu<d><<<dim3(blocks_for(nc * NU, 256), 2), 256, 0, s>>>(nc, nslot, A, nb, cur, pc->dgtu.as<double>());
+    k_dg_tu<d><<<gs, 256, 0, s>>>(geo, nc, nslot, nb, cur, nullptr, pc->dgtu.as<double>());
   }
   dg_vsolve<d>(pc, DGVec{r + off_u(d, nslot, 0), vstride}, pc->dgtu.as<double>(),
                DGOut{z + off_u(d, nslot, 0), vstride}, s);
