@@ -34,9 +34,11 @@ def build(verbose=False):
     with cf.ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
         results = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     objs = [r[0] for r in results]
-    for _, w in results:
-        for line in w:
-            print(line, file=sys.stderr)
+    # warnings are errors, except the host pass's note that it does not know
+    # the GPU-only target feature above
+    warn = [line for _, w in results for line in w]
+    if warn:
+        raise RuntimeError("hipcc warnings (treated as errors):\n" + "\n".join(warn))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

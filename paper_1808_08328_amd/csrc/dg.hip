@@ -289,7 +289,13 @@ struct DGGeo {
   double h[3];
   double hd;  // twice the circumradius (the box-cell diagonal)
   double mu;
+  double mc;  // M[a][b] = mc (1 + delta_ab), the same for every simplex of the box
 };
+
+// Per-type shape table (one row per simplex type of a box, built on the
+// host with the arithmetic of dg_shape): G[v][c], then nrm[k][c], then wf[k].
+constexpr int DG_TAB_NRM = 1;  // nrm starts at DG_TAB_NRM (d + 1) d
+__host__ __device__ constexpr int dg_tabsz(int d) { return 2 * (d + 1) * d + (d + 1); }
 
 template <int d>
 struct DGShape {
@@ -709,7 +715,12 @@ __global__ __launch_bounds__(256) void k_dg_sp(DGGeo geo, long nc, long nslot, c
 
 // Inverses of the diagonal velocity blocks of K_uu (one per simplex and
 // network, NU x NU, symmetric positive definite): Gauss-Jordan without
-// pivoting, one thread per (network, simplex).
+// pivoting, one thread per (network, simplex).  Stored packed: the upper
+// triangle of the symmetric part, row by row (dg_packed), NU (NU + 1) / 2
+// values per block.
+__host__ __device__ constexpr int dg_npk(int d) { return (d + 1) * d * ((d + 1) * d + 1) / 2; }
+// packed position of entry (i, j), i <= j, of an n x n symmetric matrix
+__host__ __device__ constexpr int dg_packed(int n, int i, int j) { return i * n - i * (i - 1) / 2 + (j - i); }
 template <int d>
 __global__ void k_dg_binv(long nc, const double *__restrict__ A, double *__restrict__ Bi) {
   constexpr int SB = dg_sb(d), NB = d + 2, NU = (d + 1) * d;
@@ -738,9 +749,9 @@ __global__ void k_dg_binv(long nc, const double *__restrict__ A, double *__restr
       }
     }
   }
-  double *Be = Bi + ((size_t)q * nc + e) * NU * NU;
+  double *Be = Bi + ((size_t)q * nc + e) * dg_npk(d);
   for (int r = 0; r < NU; ++r)
-    for (int c = 0; c < NU; ++c) Be[r * NU + c] = X[r][c];
+    for (int c = r; c < NU; ++c) Be[dg_packed(NU, r, c)] = 0.5 * (X[r][c] + X[c][r]);
 }
 
 // Strided view of per-network velocity vectors: network q's value of
@@ -756,95 +767,138 @@ struct DGOut {
 
 // Velocity-block Chebyshev step with the simplex-block Jacobi (Saad, Alg.
 // 12.1): res = b - K_uu x (b less tu when given; x = 0 when xin is null),
-// r' = Binv res, dd = c1 dd + c2 r', xout = x + dd.  power: xout = Binv (K_uu x)
-// (the power steps of the interval).  Workgroups of whole simplices (192
-// threads: 16 simplices in 3D, 32 in 2D): every thread stages one value of
-// its simplex and of each facet neighbour in LDS, one thread per simplex
-// forms the K_uu x rows, and one thread per row applies its row of Binv.
+// r' = Binv res, xout = x + c1 (x - xprev) + c2 r' (the three-term form of
+// dd = c1 dd + c2 r', xout = x + dd; xprev null: 0; xout may be xprev, each
+// thread reading its own entry first).  power: xout = Binv (K_uu x) (the
+// power steps of the interval).  Workgroups of whole simplices (192
+// threads: 16 simplices in 3D, 32 in 2D), in three phases: every thread
+// stages one value of its simplex and of each facet neighbour in LDS (and
+// fetches its row of Binv and its b, x_(k-1) entries); one thread per
+// (simplex, vertex) forms the d K_uu x rows of that vertex from LDS and the
+// simplex type's shape table; one thread per row applies its row of Binv.
 constexpr int DGV_BS = 192;
 template <int d>
-__global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, long nc, const int *__restrict__ nbr,
-                                                     const double *__restrict__ k1, const double *__restrict__ k2,
-                                                     const double *__restrict__ Bi, DGVec b,
-                                                     const double *__restrict__ tu, DGVec xin, DGOut xout,
-                                                     double *__restrict__ dd, Sc2 c1, Sc2 c2, bool power) {
+__global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, const double *__restrict__ tab, long nc,
+                                                     const int *__restrict__ nbr, const double *__restrict__ k1,
+                                                     const double *__restrict__ k2, const double *__restrict__ Bi,
+                                                     DGVec b, const double *__restrict__ tu, DGVec xin, DGOut xout,
+                                                     DGVec xprev, Sc2 c1, Sc2 c2, bool power) {
   constexpr int NU = (d + 1) * d, NV = d + 1;
   constexpr int EPB = DGV_BS / NU;
-  static_assert(EPB * NU == DGV_BS, "whole simplices per workgroup");
-  __shared__ double xs[EPB][NV + 1][NU];
+  // per-simplex LDS stride: odd in doubles, so that the simplices of a wave
+  // spread over the banks
+  constexpr int XS = (NV + 1) * NU + 1, TS = dg_tabsz(d) * dg_nper(d);
+  static_assert(EPB * NU == DGV_BS && NU > NV && TS <= DGV_BS, "whole simplices per workgroup");
+  __shared__ double xs[EPB * XS];   // own values, then the facet neighbours' (NU each)
+  __shared__ double sa[EPB][NV + 1];  // mu/k of the facet neighbours (0 across the boundary), own last
   __shared__ double sh[DGV_BS];
+  __shared__ double st[TS];           // the shape table
   const int q = blockIdx.y;
   const int loc = threadIdx.x / NU, r = threadIdx.x % NU;
   const long e = (long)blockIdx.x * EPB + loc;
   const bool live = e < nc;
   const double *xq = xin.base ? xin.base + (size_t)q * xin.stride : nullptr;
+  // operands of the last phase, fetched first: row r of the packed
+  // symmetric block ((r, c) for c >= r, (c, r) below), b less tu, x_(k-1)
+  double brow[NU], bv = 0.0, xp = 0.0;
+  if (live) {
+    const double *Be = Bi + ((size_t)q * nc + e) * dg_npk(d);
+    const int rb = dg_packed(NU, r, 0);
+#pragma unroll
+    for (int c = 0; c < NU; ++c) brow[c] = Be[r <= c ? rb + c : dg_packed(NU, c, 0) + r];
+    if (!power) {
+      bv = b.base[(size_t)q * b.stride + e * NU + r] - (tu ? tu[(size_t)q * nc * NU + e * NU + r] : 0.0);
+      if (xprev.base) xp = xprev.base[(size_t)q * xprev.stride + e * NU + r];
+    }
+  }
   if (xq) {  // uniform over the launch
+    const double *kq = q ? k2 : k1;
+    if (threadIdx.x < TS) st[threadIdx.x] = tab[threadIdx.x];
     if (live) {
-      xs[loc][0][r] = xq[e * NU + r];
+      double *xl = xs + loc * XS;
+      xl[r] = xq[e * NU + r];
 #pragma unroll
       for (int k = 0; k <= d; ++k) {
         const int nb = nbr[e * NV + k];
-        xs[loc][1 + k][r] = nb >= 0 ? xq[(long)nb * NU + r] : 0.0;
+        xl[(1 + k) * NU + r] = nb >= 0 ? xq[(long)nb * NU + r] : 0.0;
+      }
+      if (r < NV) {
+        const int nb = nbr[e * NV + r];
+        sa[loc][r] = nb >= 0 ? geo.mu / kq[nb] : 0.0;
+      } else if (r == NV) {
+        sa[loc][NV] = geo.mu / kq[e];
       }
     }
     __syncthreads();
-    const long es = (long)blockIdx.x * EPB + threadIdx.x;
-    if (threadIdx.x < EPB && es < nc) {
-      DGShape<d> S;
-      dg_shape<d>(geo, es, S);
-      const double *kq = q ? k2 : k1;
-      const double alpha = geo.mu / kq[es];
-      double xu[NU], yu[NU];
+    if (threadIdx.x < EPB * NV) {
+      const int l2 = threadIdx.x / NV, a = threadIdx.x % NV;
+      const long e2 = (long)blockIdx.x * EPB + l2;
+      if (e2 < nc) {
+        const double *T = st + (e2 % dg_nper(d)) * dg_tabsz(d);
+        const double alpha = sa[l2][NV];
+        const double *x0 = xs + l2 * XS;
+        double su[d], y[d];
 #pragma unroll
-      for (int j = 0; j < NU; ++j) {
-        xu[j] = xs[threadIdx.x][0][j];
-        yu[j] = 0.0;
+        for (int c = 0; c < d; ++c) {
+          double t = 0.0;
+#pragma unroll
+          for (int v = 0; v <= d; ++v) t += x0[v * d + c];
+          su[c] = t;
+        }
+        // volume: (1/2) (mu/k) M, M[a][b] = mc (1 + delta_ab), per component
+#pragma unroll
+        for (int c = 0; c < d; ++c) y[c] = 0.5 * alpha * geo.mc * (x0[a * d + c] + su[c]);
+#pragma unroll
+        for (int k = 0; k <= d; ++k) {
+          const double an = sa[l2][k];
+          if (an == 0.0 || k == a) continue;
+          const double *xk = x0 + (1 + k) * NU;
+          double n[d];
+#pragma unroll
+          for (int c = 0; c < d; ++c) n[c] = T[DG_TAB_NRM * NV * d + k * d + c];
+          // normal jumps at the facet vertices: all of them, then own vertex a
+          double sj = 0.0;
+#pragma unroll
+          for (int v = 0; v <= d; ++v) {
+            if (v == k) continue;
+            const int m = k == 0 ? v - 1 : (k == d ? v + 1 : v);
+#pragma unroll
+            for (int c = 0; c < d; ++c) sj += n[c] * (x0[v * d + c] - xk[m * d + c]);
+          }
+          const int ma = k == 0 ? a - 1 : (k == d ? a + 1 : a);
+          double ja = 0.0;
+#pragma unroll
+          for (int c = 0; c < d; ++c) ja += n[c] * (x0[a * d + c] - xk[ma * d + c]);
+          const double cu = ETA_U * geo.hd * 0.5 * (alpha + an);
+          const double mjn = T[2 * NV * d + k] * (ja + sj);
+#pragma unroll
+          for (int c = 0; c < d; ++c) y[c] += cu * n[c] * mjn;
+        }
+#pragma unroll
+        for (int c = 0; c < d; ++c) sh[l2 * NU + a * d + c] = y[c];
       }
-      dg_volume<d, true, false, false, false>(S, alpha, 0.0, 0.0, xu, nullptr, yu, nullptr);
-      int nb[NV];
-      dg_ldi<NV>(nbr + es * NV, nb);
-#pragma unroll
-      for (int k = 0; k <= d; ++k) {
-        if (nb[k] < 0) continue;
-        double nu[NU];
-#pragma unroll
-        for (int j = 0; j < NU; ++j) nu[j] = xs[threadIdx.x][1 + k][j];
-        dg_facet<d, true, false, false, false>(S, k, ETA_U * geo.hd * 0.5 * (alpha + geo.mu / kq[nb[k]]), 0.0, xu,
-                                               nullptr, nu, nullptr, yu, nullptr);
-      }
-#pragma unroll
-      for (int j = 0; j < NU; ++j) sh[threadIdx.x * NU + j] = yu[j];
     }
     __syncthreads();
   }
   double res = 0.0, xr = 0.0;
   if (live) {
     const double acc = xq ? sh[threadIdx.x] : 0.0;
-    if (xq) xr = xs[loc][0][r];
-    if (power) {
-      res = acc;
-    } else {
-      const double bv = b.base[(size_t)q * b.stride + e * NU + r] - (tu ? tu[(size_t)q * nc * NU + e * NU + r] : 0.0);
-      res = bv - acc;
-    }
+    if (xq) xr = xs[loc * XS + r];
+    res = power ? acc : bv - acc;
   }
   __syncthreads();
   sh[threadIdx.x] = res;
   __syncthreads();
   if (!live) return;
-  const double *Be = Bi + (((size_t)q * nc + e) * NU + r) * NU;
   double rp = 0.0;
 #pragma unroll
-  for (int c = 0; c < NU; ++c) rp += Be[c] * sh[loc * NU + c];
+  for (int c = 0; c < NU; ++c) rp += brow[c] * sh[loc * NU + c];
   double *out = xout.base + (size_t)q * xout.stride + e * NU + r;
   if (power) {
     *out = rp;
     return;
   }
-  const size_t i = (size_t)q * nc * NU + e * NU + r;
-  const double dn = (c1.v[q] != 0.0 ? c1.v[q] * dd[i] : 0.0) + c2.v[q] * rp;
-  dd[i] = dn;
-  *out = xr + dn;
+  *out = xr + (c1.v[q] != 0.0 ? c1.v[q] * (xr - xp) : 0.0) + c2.v[q] * rp;
 }
 
 // z_p = zp (the pressure part of the fieldsplit's output)
@@ -973,7 +1027,51 @@ DGGeo dg_geo(dpp_problem P) {
   }
   geo.hd = std::sqrt(hd);
   geo.mu = P->mu;
+  double v = 1.0;
+  for (int a = 0; a < P->g.dim; ++a) v *= P->g.h[a];
+  const int d = P->g.dim;
+  geo.mc = v / (d == 3 ? 6.0 : 2.0) / ((d + 1) * (d + 2));
   return geo;
+}
+
+// the per-type shape table (dg_tabsz values per type), with dg_shape's arithmetic
+std::vector<double> dg_shape_table(const Grid &g) {
+  const int d = g.dim, NP = dg_nper(d), NV = d + 1;
+  std::vector<double> tab((size_t)NP * dg_tabsz(d), 0.0);
+  double v = 1.0;
+  for (int a = 0; a < d; ++a) v *= g.h[a];
+  const double vol = v / (d == 3 ? 6.0 : 2.0), mf0 = 1.0 / (d * (d + 1));
+  for (int t = 0; t < NP; ++t) {
+    int p[3] = {0, 0, 0};
+    if (d == 2) {
+      p[0] = t;
+      p[1] = 1 - t;
+    } else {
+      const int f = t >> 1, lo = f == 0 ? 1 : 0, hi = f == 2 ? 1 : 2;
+      p[0] = f;
+      p[1] = (t & 1) ? hi : lo;
+      p[2] = (t & 1) ? lo : hi;
+    }
+    double G[4][3] = {};
+    for (int c = 0; c < d; ++c) {
+      const double ih = 1.0 / g.h[c];
+      G[0][c] = p[0] == c ? -ih : 0.0;
+      for (int k = 1; k < d; ++k) G[k][c] = p[k - 1] == c ? ih : (p[k] == c ? -ih : 0.0);
+      G[d][c] = p[d - 1] == c ? ih : 0.0;
+    }
+    double *T = tab.data() + (size_t)t * dg_tabsz(d);
+    for (int k = 0; k <= d; ++k) {
+      double gn = 0.0;
+      for (int c = 0; c < d; ++c) gn += G[k][c] * G[k][c];
+      gn = std::sqrt(gn);
+      T[2 * NV * d + k] = d * vol * gn * mf0;
+      for (int c = 0; c < d; ++c) {
+        T[k * d + c] = G[k][c];
+        T[DG_TAB_NRM * NV * d + k * d + c] = -G[k][c] / gn;
+      }
+    }
+  }
+  return tab;
 }
 const double *dg_betac(dpp_problem P) { return P->beta_per_cell ? P->betac.as<double>() : nullptr; }
 // coefficient bytes a product reads per network: k (and beta per simplex)
@@ -991,6 +1089,12 @@ void dg_assemble(dpp_problem P, const dpp_params *prm, hipStream_t s) {
   P->dgA.alloc(sizeof(double) * 2 * (size_t)nc * (d + 2) * SB * SB);
   P->dgB.alloc(sizeof(double) * (size_t)nc * (d + 1) * (d + 1));
   P->dgnb.alloc(sizeof(int) * (size_t)nc * (d + 1));
+  {
+    const std::vector<double> tab = dg_shape_table(g);
+    P->dgtab.alloc(sizeof(double) * tab.size());
+    DPP_HIP(hipMemcpyAsync(P->dgtab.ptr, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s));
+    DPP_HIP(hipStreamSynchronize(s));  // the host table is freed on return
+  }
   P->f.alloc(sizeof(double) * P->ndof());
   // coefficient copies: the preconditioner assembles the nodal problem of the
   // same box and coefficients
@@ -1112,7 +1216,7 @@ void dg_vsolve(dpp_precond pc, DGVec b, const double *tu, DGOut out, hipStream_t
     rho[q] = 1.0 / sig[q];
   }
   double *buf[2] = {pc->dgva.as<double>(), pc->dgvb.as<double>()};
-  DGVec xin{nullptr, 0};
+  DGVec xin{nullptr, 0}, xprev{nullptr, 0};
   for (int k = 0; k < DG_VEL_DEGREE; ++k) {
     Sc2 c1{{0, 0}}, c2{{0, 0}};
     for (int q = 0; q < 2; ++q) {
@@ -1125,17 +1229,19 @@ void dg_vsolve(dpp_precond pc, DGVec b, const double *tu, DGOut out, hipStream_t
         rho[q] = rn;
       }
     }
+    // x_(k+1) overwrites x_(k-1) (buf alternates), the last one goes to out
     const DGOut o = k + 1 == DG_VEL_DEGREE ? out : DGOut{buf[k & 1], nc * NU};
-    // bytes: the block inverses; b (less tu), dd and x' written; after the
-    // first step (x = 0) also x and dd read, the coefficients and the
-    // neighbour table
-    const double vecs = 2.0 + (tu ? 1.0 : 0.0) + (k > 0 ? 2.0 : 0.0) + 1.0;
+    // bytes: the packed block inverses; b (less tu) read, x' written; x read
+    // after the first step (x_0 = 0), x_(k-1) after the second, with the
+    // coefficients and the neighbour table
+    const double vecs = 2.0 + (tu ? 1.0 : 0.0) + (k > 0 ? 1.0 : 0.0) + (k > 1 ? 1.0 : 0.0);
     ProfScope ps(PF_DG_VEL,
-                 2.0 * 8.0 * ((double)nc * NU * NU + vecs * nc * NU) +
+                 2.0 * 8.0 * ((double)nc * dg_npk(d) + vecs * nc * NU) +
                      (k > 0 ? 2.0 * 8.0 * nc + 4.0 * nc * (d + 1) : 0.0), s);
-    k_dg_vcheb<d><<<gv, DGV_BS, 0, s>>>(geo, nc, P->dgnb.as<int>(), P->k1.as<double>(), P->k2.as<double>(),
-                                        pc->dgbinv.as<double>(), b, tu, xin, o, pc->dgvd.as<double>(), c1, c2,
+    k_dg_vcheb<d><<<gv, DGV_BS, 0, s>>>(geo, P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(),
+                                        P->k2.as<double>(), pc->dgbinv.as<double>(), b, tu, xin, o, xprev, c1, c2,
                                         false);
+    xprev = xin;
     xin = DGVec{o.base, o.stride};
   }
   check_launch("DG velocity solve");
@@ -1180,8 +1286,8 @@ void dg_setup_impl(dpp_precond pc, hipStream_t s) {
   pc->dgds.alloc(sizeof(double) * 2 * nslot);
   for (DBuf *b : {&pc->dgrh, &pc->dgza, &pc->dgzb, &pc->dgd}) b->alloc(sizeof(double) * 2 * nslot);
   pc->dgtu.alloc(sizeof(double) * 2 * nc * NU);
-  for (DBuf *b : {&pc->dgva, &pc->dgvb, &pc->dgvd, &pc->dgyu}) b->alloc(sizeof(double) * 2 * nc * NU);
-  pc->dgbinv.alloc(sizeof(double) * 2 * nc * NU * NU);
+  for (DBuf *b : {&pc->dgva, &pc->dgvb, &pc->dgyu}) b->alloc(sizeof(double) * 2 * nc * NU);
+  pc->dgbinv.alloc(sizeof(double) * 2 * nc * dg_npk(d));
   pc->dgcb.alloc(sizeof(double) * 2 * g.N);
   pc->dgcx.alloc(sizeof(double) * 2 * g.N);
   pc->dgpart.alloc(sizeof(double) * 2 * DG_RB + 2 * sizeof(double));
@@ -1217,9 +1323,10 @@ void dg_setup_impl(dpp_precond pc, hipStream_t s) {
     dg_sumsq(pc, vx, nu, ssd, s);
     k_dg_scale<<<gu, 256, 0, s>>>(vx, nu, ssd);
     for (int it = 0; it < o.power_iters; ++it) {
-      k_dg_vcheb<d><<<gb, DGV_BS, 0, s>>>(dg_geo(P), nc, P->dgnb.as<int>(), P->k1.as<double>(), P->k2.as<double>(),
-                                          pc->dgbinv.as<double>(), DGVec{nullptr, 0}, nullptr, DGVec{vx, nu},
-                                          DGOut{vy, nu}, nullptr, Sc2{{0, 0}}, Sc2{{0, 0}}, true);
+      k_dg_vcheb<d><<<gb, DGV_BS, 0, s>>>(dg_geo(P), P->dgtab.as<double>(), nc, P->dgnb.as<int>(),
+                                          P->k1.as<double>(), P->k2.as<double>(), pc->dgbinv.as<double>(),
+                                          DGVec{nullptr, 0}, nullptr, DGVec{vx, nu}, DGOut{vy, nu}, DGVec{nullptr, 0},
+                                          Sc2{{0, 0}}, Sc2{{0, 0}}, true);
       dg_sumsq(pc, vy, nu, ssd, s);
       k_dg_scale<<<gu, 256, 0, s>>>(vy, nu, ssd);
       std::swap(vx, vy);

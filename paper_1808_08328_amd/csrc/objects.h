@@ -75,6 +75,7 @@ struct dpp_problem_s {
   dpp::DBuf dgB;        // [n_cells][dim+1][dim+1] inter-network transfer -(beta/mu) M
   dpp::DBuf dgnb;       // [n_cells][dim+1] facet neighbours (-1: boundary)
   long dgcoupled = 0;   // (simplex, simplex) blocks per network: self plus interior facets
+  dpp::DBuf dgtab;      // per simplex type of a box: barycentric gradients, facet normals, facet weights
   long npos() const { return dg ? nslot : g.N; }  // positions per field component
   long ndof() const { return (long)(2 * g.dim + 2) * npos(); }
 };
@@ -134,7 +135,7 @@ struct dpp_precond_s {
   std::unique_ptr<dpp_problem_s> dgcg;
   dpp_precond_s *dgpc = nullptr;
   dpp::DBuf dgzero, dgdu, dgds, dgrh, dgza, dgzb, dgd, dgtu, dgcb, dgcx, dgpart;
-  dpp::DBuf dgbinv, dgva, dgvb, dgvd, dgyu;  // velocity block: simplex-block inverses, Chebyshev work
+  dpp::DBuf dgbinv, dgva, dgvb, dgyu;  // velocity block: packed simplex-block inverses, Chebyshev work
   double dghi[2] = {0.0, 0.0}, dglo[2] = {0.0, 0.0};    // pressure-block Chebyshev interval
   double dgvhi[2] = {0.0, 0.0}, dgvlo[2] = {0.0, 0.0};  // velocity-block Chebyshev interval
   void drop_graphs() {
