@@ -355,15 +355,20 @@ class FieldSplitDG:
         return chebyshev_op(lambda v: self.Kuu[i] @ v, lambda v: self.Binv[i] @ v, b, np.zeros_like(b),
                             VEL_DEGREE, self.vlo[i], self.vhi[i])
 
-    def apply(self, r):
+    def pressure(self, i, rhat):
+        """B_i(rhat): the nodal V-cycle on the summed residual, copied back to
+        the slots, then Chebyshev post-smoothing on S_i."""
         from . import mg
+        zp = self.R.T @ mg.vcycle(self.H[i], self.R @ rhat)
+        return mg.chebyshev(self.Sp[i], self.dS[i], rhat, zp, self.deg, self.lo[i], self.hi[i])
+
+    def apply(self, r):
         F = self.F
         z = np.empty_like(r)
         for i, (u, p) in enumerate((("u1", "p1"), ("u2", "p2"))):
             ru, rp = r[F[u]], r[F[p]]
             rhat = rp - self.Kpu[i] @ self.velocity(i, ru)
-            zp = self.R.T @ mg.vcycle(self.H[i], self.R @ rhat)
-            zp = mg.chebyshev(self.Sp[i], self.dS[i], rhat, zp, self.deg, self.lo[i], self.hi[i])
+            zp = self.pressure(i, rhat)
             z[F[p]] = zp
             z[F[u]] = self.velocity(i, ru - self.Kup[i] @ zp)
         return z

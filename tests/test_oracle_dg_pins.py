@@ -176,3 +176,126 @@ def test_mms_convergence_3d():
         r = np.log2(errs[0][f] / errs[1][f])
         print(f, [e[f] for e in errs], r)
         assert r >= (1.8 if f.startswith("p") else 1.3), (f, r)
+
+
+# ------------------------------------------------------------ fieldsplit --
+
+def small_dg(dim, n, seed=5):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    prob = I.mms_problem(dim, n, k1=1.0, k2=0.1, beta=1.0, mu=1.0, elem="dg")
+    prob.k1 = 10 ** rng.uniform(-1, 1, prob.n_cells)
+    prob.k2 = 10 ** rng.uniform(-2, 0, prob.n_cells)
+    return prob, odg.assemble(prob)
+
+
+def velocity_blocks(S, i):
+    """K_uu of network i and the inverses of its simplex blocks, densely."""
+    F = odg.fields(S.dim, S.S)
+    u = ("u1", "u2")[i]
+    Kuu = S.K[F[u], F[u]].toarray()
+    NU = (S.dim + 1) * S.dim
+    Binv = np.zeros_like(Kuu)
+    for e in range(Kuu.shape[0] // NU):
+        s = slice(e * NU, (e + 1) * NU)
+        Binv[s, s] = np.linalg.inv(Kuu[s, s])
+    return Kuu, Binv
+
+
+@pytest.mark.parametrize("dim,n", [(2, 3), (3, (1, 2, 1))])
+def test_velocity_power_bound_matches_dense_eigenvalue(dim, n):
+    """power_bound after k steps is ||(M A)^k x0|| / ||(M A)^(k-1) x0|| with
+    M the simplex-block inverses, evaluated here through the eigendecomposition
+    of M A (real spectrum: similar to an SPD matrix); it tends to the largest
+    eigenvalue.  A dropped M, a missing normalisation or an off-by-one step
+    count fails it."""
+    from oracle import mg
+    _, S = small_dg(dim, n)
+    for i in (0, 1):
+        A, M = velocity_blocks(S, i)
+        # repeated eigenvalues: numpy may return complex eigenvectors, so the
+        # evaluation stays complex
+        lam, Vec = np.linalg.eig(M @ A)
+        assert np.abs(lam.imag).max() < 1e-10 * np.abs(lam.real).max()
+        c0 = np.linalg.solve(Vec, mg.hash_start(A.shape[0]))
+        for k in (1, 2, 15):
+            est = odg.power_bound(lambda v: A @ v, lambda v: M @ v, A.shape[0], k)
+            ref = np.linalg.norm(Vec @ (lam ** k * c0)) / np.linalg.norm(Vec @ (lam ** (k - 1) * c0))
+            assert abs(est - ref) < 1e-10 * ref, (k, est, ref)
+        lmax = lam.real.max()
+        assert abs(odg.power_bound(lambda v: A @ v, lambda v: M @ v, A.shape[0], 3000) - lmax) < 1e-3 * lmax
+        # block Jacobi, not the diagonal: the spectra differ
+        lam_d = np.linalg.eigvals(np.diag(1.0 / np.diag(A)) @ A).real.max()
+        assert abs(lam_d - lmax) > 0.05 * lmax
+
+
+@pytest.mark.parametrize("degree", [2, 3, 4, 8])
+def test_velocity_chebyshev_error_is_the_scaled_chebyshev_polynomial(degree):
+    """k steps of chebyshev_op on [lo, hi] with the block inverses M multiply the
+    error by T_k((theta - t)/delta) / T_k(theta/delta) at the eigenvalues t of
+    M A (numpy's Chebyshev basis, not the recurrence the smoother runs)."""
+    _, S = small_dg(2, 3)
+    A, M = velocity_blocks(S, 0)
+    lam, Vec = np.linalg.eig(M @ A)
+    lmax = lam.real.max()
+    b = I.random_vector(A.shape[0], 11)
+    xs = np.linalg.solve(A, b)
+    x0 = I.random_vector(A.shape[0], 12)
+    for lo, hi in ((0.01 * lmax, 1.1 * lmax), (0.2 * lmax, 0.8 * lmax)):
+        theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+        Tk = np.polynomial.chebyshev.Chebyshev.basis(degree)
+        pk = Tk((theta - lam) / delta) / Tk(theta / delta)
+        e_pred = (Vec @ (pk * np.linalg.solve(Vec, x0 - xs))).real
+        x = odg.chebyshev_op(lambda v: A @ v, lambda v: M @ v, b, x0, degree, lo, hi)
+        assert np.linalg.norm((x - xs) - e_pred) < 1e-9 * np.linalg.norm(x0 - xs), (lo, hi)
+
+
+@pytest.mark.parametrize("dim,n", [(2, (3, 2)), (3, (1, 2, 1))])
+def test_fieldsplit_with_exact_pieces_is_the_inverse(dim, n):
+    """With beta = 0 the networks decouple; with the velocity solve replaced by
+    K_uu^-1 and the pressure solve by the exact Schur complement's inverse,
+    the fieldsplit's full factorisation (rhat = r_p - K_pu y_u, z_u =
+    K_uu^-1 (r_u - K_up z_p)) is K^-1: signs and block order of the apply."""
+    prob, _ = small_dg(dim, n)
+    prob.beta = 0.0
+    S = odg.assemble(prob)
+    P = odg.FieldSplitDG(S, prob)
+    F = odg.fields(dim, S.S)
+    K = S.K.toarray()
+    inv = []
+    for u, p in (("u1", "p1"), ("u2", "p2")):
+        A, B = K[F[u], F[u]], K[F[u], F[p]]
+        C, D = K[F[p], F[u]], K[F[p], F[p]]
+        inv.append((np.linalg.inv(A), np.linalg.inv(D - C @ np.linalg.solve(A, B))))
+    P.velocity = lambda i, b: inv[i][0] @ b
+    P.pressure = lambda i, b: inv[i][1] @ b
+    r = I.random_vector(K.shape[0], 3)
+    z = P.apply(r)
+    assert np.linalg.norm(K @ z - r) < 1e-10 * np.linalg.norm(r)
+
+
+@pytest.mark.parametrize("dim,n", [(2, (4, 3)), (3, (3, 2, 2))])
+def test_slot_transfers_and_selfp_of_the_fieldsplit(dim, n):
+    """R sums the slots of each node: R 1 counts the simplices around the node
+    (6 triangles / 24 tetrahedra at an interior node of the Kuhn split), R^T
+    copies node values to the slots (a continuous field); S_q is
+    K_pp - K_pu diag(K_uu)^-1 K_up evaluated densely, SPD."""
+    prob, S = small_dg(dim, n)
+    P = odg.FieldSplitDG(S, prob)
+    msh = S.mesh
+    counts = P.R @ np.ones(S.S)
+    m = [k + 1 for k in (n if np.ndim(n) else (n,) * dim)]
+    ijk = np.stack(np.unravel_index(np.arange(msh.N), m[::-1])[::-1], axis=1)
+    interior = np.all((ijk > 0) & (ijk < np.array(m) - 1), axis=1)
+    assert interior.any()
+    assert np.all(counts[interior] == (6 if dim == 2 else 24))
+    assert counts.sum() == S.S
+    v = I.random_vector(msh.N, 4)
+    assert np.array_equal(P.R.T @ v, v[msh.cells.ravel()])
+    F = odg.fields(dim, S.S)
+    K = S.K.toarray()
+    for i, (u, p) in enumerate((("u1", "p1"), ("u2", "p2"))):
+        A, B, C, D = K[F[u], F[u]], K[F[u], F[p]], K[F[p], F[u]], K[F[p], F[p]]
+        Sq = D - C @ np.diag(1.0 / np.diag(A)) @ B
+        assert np.abs(P.Sp[i].toarray() - Sq).max() <= 1e-12 * np.abs(Sq).max()
+        assert np.abs(Sq - Sq.T).max() <= 1e-12 * np.abs(Sq).max()
+        assert np.linalg.eigvalsh(0.5 * (Sq + Sq.T)).min() > 0
