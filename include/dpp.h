@@ -248,7 +248,8 @@ dpp_status dpp_solve(dpp_problem prob, dpp_precond pc, const dpp_solve_opts *opt
 /* Adjoint solve K^T lambda = g.  Uses K^T = D K D with D = diag(I_u, -I_p)
  * (D K is symmetric because K_pu = -K_up^T and K_pp, K_uu are symmetric), so
  * lambda = D * solve(K, D g) with the same preconditioner.  lambda: [n_dof]
- * (zero initial guess). */
+ * (zero initial guess).  CG-VMS and DG-VMS problems (the DG-VMS blocks of
+ * eq. S4_dg_stiffness_matrix have the same structure). */
 dpp_status dpp_solve_adjoint(dpp_problem prob, dpp_precond pc, const dpp_solve_opts *opts,
                              const double *g, double *lambda, dpp_solve_stats *stats,
                              void *stream);

@@ -379,7 +379,6 @@ dpp_status dpp_solve_adjoint(dpp_problem P, dpp_precond pc, const dpp_solve_opts
   dpp_status st = guard([&] {
     DPP_CHECK(P && pc && g && lambda && g != lambda, DPP_ERR_ARG, "bad argument");
     DPP_CHECK(pc->prob == P, DPP_ERR_ARG, "preconditioner belongs to another problem");
-    DPP_CHECK(!P->dg, DPP_ERR_UNSUPPORTED, "the adjoint solve is implemented for CG-VMS problems");
     const long n = P->ndof();
     // allocated on the first adjoint solve of this preconditioner, then reused
     if (!pc->adjrhs.ptr) pc->adjrhs.alloc(sizeof(double) * n);

@@ -112,7 +112,7 @@ __global__ void k_sum_fixed(const double *__restrict__ v, long n, double *__rest
 
 void flip_pressure_sign(dpp_problem P, const double *in, double *out, hipStream_t s) {
   const long n = P->ndof();
-  k_flip<<<std::min(2048, blocks_for(n, 256)), 256, 0, s>>>(0, P->g.N, P->g.dim, in, out);
+  k_flip<<<std::min(2048, blocks_for(n, 256)), 256, 0, s>>>(0, P->npos(), P->g.dim, in, out);
   check_launch("flip");
 }
 

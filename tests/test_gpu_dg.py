@@ -126,8 +126,34 @@ def test_dg_solves_in_fp64_only():
         with pytest.raises(dpp.DppError) as e:
             P.solve(pc, precision=precision)
         assert e.value.status == 7
-    with pytest.raises(dpp.DppError):
-        P.solve_adjoint(pc, torch.zeros(P.n_dof, dtype=torch.float64, device="cuda"))
+
+
+
+@pytest.mark.parametrize("case", ["2d_ragged", "3d_ragged"])
+def test_dg_adjoint_matches_oracle(case):
+    """K^T lambda = g through D K D on the DG blocks, against the oracle's
+    sparse LU of K^T, for g = 2 (p1 - p_obs) (a least-squares misfit)."""
+    import paper_1808_08328_amd as dpp
+    from oracle import solver as osolver
+    dim, n = SOLVE_CASES[case]
+    print("dg adjoint case", case, flush=True)
+    prob = random_problem(dim, n, 23, True)
+    S = odg.assemble(prob)
+    P = dpp.assemble_problem(prob)
+    pc = P.setup_precond(coarse_max=40)
+    x, st = P.solve(pc, rtol=1e-12)
+    assert st.converged == 1
+    F = odg.fields(dim, S.S)
+    xh = H(x)
+    g = np.zeros(P.n_dof)
+    g[F["p1"]] = 2 * (xh[F["p1"]] - I.random_vector(S.S, 29))
+    lam, st = P.solve_adjoint(pc, torch.as_tensor(g, device="cuda"), rtol=1e-12)
+    assert st.converged == 1
+    lo = osolver.adjoint_solve(S, g)
+    assert np.linalg.norm(H(lam) - lo) <= 1e-10 * np.linalg.norm(lo)
+    with pytest.raises(dpp.DppError) as e:
+        P.param_grad(x, lam)
+    assert e.value.status == 7
 
 
 @pytest.mark.timeout(400)
