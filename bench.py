@@ -65,7 +65,8 @@ SINGLE_KERNEL_FAMILIES = ("spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "sch
 
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("mg.hip", "ops.hip", "krylov.hip", "common.h", "stencil.h", "mvec.h"):
+    for f in ("mg.hip", "ops.hip", "krylov.hip", "common.h", "stencil.h", "mvec.h", "batch.hip", "batch.h",
+              "dg.hip"):
         with open(os.path.join(ROOT, "paper_1808_08328_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
