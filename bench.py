@@ -82,7 +82,9 @@ def kernel_name(family, dim, pc, flux=False, dg=False):
         k = "k_cheb" if family == "cheb_S_l0" else "k_lspmv"
         return "%s<%d, double, double, %d, %s, true>" % (k, dim, lanes, "true" if sym else "false")
     bc = "true" if flux else "false"
-    return {"spmv_K": "k_spmv_K<%d, double, " + bc + ">", "schur_rhs": "k_schur_rhs<%d, double, double, " + bc + ">",
+    # the K product: node pairs without velocity faces, one node per thread with them
+    return {"spmv_K": "k_spmv_K1<%d, double>" if flux else "k_spmv_K<%d, double>",
+            "schur_rhs": "k_schur_rhs<%d, double, double, " + bc + ">",
             "schur_vel": "k_schur_vel<%d, double, double, " + bc + ">"}[family] % dim
 
 

@@ -49,8 +49,8 @@ def test_kernel_names_of_single_kernel_families():
     pc = _Shape()
     assert bench.kernel_name("cheb_S_l0", 3, pc) == "k_cheb<3, double, double, 0, true, true>"
     assert bench.kernel_name("resid_S_l0", 3, pc) == "k_lspmv<3, double, double, 0, true, true>"
-    assert bench.kernel_name("spmv_K", 3, pc) == "k_spmv_K<3, double, false>"
-    assert bench.kernel_name("spmv_K", 2, pc, flux=True) == "k_spmv_K<2, double, true>"
+    assert bench.kernel_name("spmv_K", 3, pc) == "k_spmv_K<3, double>"
+    assert bench.kernel_name("spmv_K", 2, pc, flux=True) == "k_spmv_K1<2, double>"
     assert bench.kernel_name("schur_rhs", 3, pc) == "k_schur_rhs<3, double, double, false>"
     assert bench.kernel_name("schur_vel", 3, pc, flux=True) == "k_schur_vel<3, double, double, true>"
     assert bench.kernel_name("spmv_K", 3, pc, dg=True) == "k_dg_spmv<3>"
