@@ -64,7 +64,17 @@ typedef struct dpp_batch_s *dpp_batch;
  * hexahedra; cell h = i + n_x(j + n_y k) is box h, and per-cell arrays have
  * one entry per box).  With Q1 the solver, mixed precision and velocity
  * faces are available; the parameter gradient, the L2-error integrals and
- * batched solves are P1 only (DPP_ERR_UNSUPPORTED). */
+ * batched solves are P1 only (DPP_ERR_UNSUPPORTED).  2 = DG-VMS, discontinuous
+ * P1 on the Kuhn simplices (section "Stabilized mixed discontinuous Galerkin
+ * formulation (DG-VMS)", eq. VMS_DG_Weak_Form, eqs. S4_dg_stiffness_matrix and
+ * S4_dg_rhs): every simplex e owns d + 1 vertex slots e (d+1) + v, the vector
+ * is [u1 | p1 | u2 | p2] over slots and n_dof = (2d+2)(d+1) x simplices
+ * (dpp_problem_sizes reports the slots as n_nodes).  DG-VMS problems take
+ * pressure faces only (face_bc NULL or zero) and are solved with precision 0
+ * or 2; the adjoint solve, the CSR export and the full product K x are
+ * available, while precision 1, the block products, dpp_vcycle, the parameter
+ * gradient, the L2-error integrals and batched solves return
+ * DPP_ERR_UNSUPPORTED. */
 typedef struct {
   int dim;
   int n[3];
@@ -77,9 +87,9 @@ typedef struct {
  * beta: scalar mass-transfer coefficient (>= 0), used when beta_cells == NULL,
  * else beta_cells [n_cells] (>= 0; DPP_ERR_NUMERIC for a negative or
  * non-finite entry, as for k1, k2 <= 0).  body: gamma*b per cell [n_cells*dim] or NULL (b = 0).
- * p0_1, p0_2: nodal pressures [n_nodes]; only boundary nodes are read, and the
- * boundary integral -(w.n; p0) uses their P1 interpolant exactly (on the
- * pressure faces).
+ * p0_1, p0_2: nodal pressures on the box's grid nodes ((n_x+1)(n_y+1)(n_z+1),
+ * also for DG-VMS); only boundary nodes are read, and the boundary integral
+ * -(w.n; p0) uses their P1 interpolant exactly (on the pressure faces).
  * Velocity (flux) boundaries (eq. DG_GE_vBC): face_bc (host, int8 [2][2*dim])
  * or NULL (every box face a pressure boundary); face_bc[i][2a + s] = 1 makes
  * face s (0: x_a = 0, 1: x_a = L_a) a velocity boundary of network i, 0 a

@@ -266,7 +266,8 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
     }
     // a rejected call leaves the handle as it was
     check_opts(o);
-    DPP_CHECK(!P->dg || o.precision == 0, DPP_ERR_UNSUPPORTED, "DG-VMS problems are solved in FP64 (precision 0)");
+    DPP_CHECK(!P->dg || o.precision != 1, DPP_ERR_UNSUPPORTED,
+              "DG-VMS problems are solved in FP64 or with the FP32 preconditioner (precision 0 or 2)");
     pc->opts.cheb_degree = o.cheb_degree;
     pc->opts.cheb_pre_fine = o.cheb_pre_fine;
     pc->opts.cheb_post_fine = o.cheb_post_fine;

@@ -441,10 +441,10 @@ __device__ inline void dg_facet(const DGShape<d> &S, int k, double cu, double cp
   }
 }
 
-template <int n>
-__device__ inline void dg_ld(const double *__restrict__ p, double *v) {
+template <int n, typename T>
+__device__ inline void dg_ld(const T *__restrict__ p, double *v) {
 #pragma unroll
-  for (int j = 0; j < n; ++j) v[j] = p[j];
+  for (int j = 0; j < n; ++j) v[j] = (double)p[j];
 }
 template <int n>
 __device__ inline void dg_ldi(const int *__restrict__ p, int *v) {
@@ -586,19 +586,23 @@ __global__ void k_dg_diag_s(long nc, const double *__restrict__ A, const int *__
   ds[(size_t)q * nc * (d + 1) + t] = 1.0 / v;
 }
 
+// The fieldsplit kernels below store their vectors (and the block inverses
+// and diagonals) in T: double, or float for the FP32 preconditioner; they
+// compute in double.
+
 // rhat = r_p - K_pu y_u (y_u [2][n_cells NU], the velocity solve's output):
 // one thread per (network, simplex)
-template <int d>
+template <int d, typename T>
 __global__ __launch_bounds__(256) void k_dg_rhat(DGGeo geo, long nc, long nslot, const int *__restrict__ nbr,
-                                                 const double *__restrict__ yu, const double *__restrict__ r,
-                                                 double *__restrict__ rh) {
+                                                 const T *__restrict__ yu, const T *__restrict__ r,
+                                                 T *__restrict__ rh) {
   constexpr int NU = (d + 1) * d, NV = d + 1;
   const int q = blockIdx.y;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nc) return;
   DGShape<d> S;
   dg_shape<d>(geo, e, S);
-  const double *yq = yu + (size_t)q * nc * NU;
+  const T *yq = yu + (size_t)q * nc * NU;
   double xu[NU], yp[NV];
   dg_ld<NU>(yq + e * NU, xu);
 #pragma unroll
@@ -613,25 +617,25 @@ __global__ __launch_bounds__(256) void k_dg_rhat(DGGeo geo, long nc, long nslot,
     dg_ld<NU>(yq + (long)nb[k] * NU, nu);
     dg_facet<d, false, false, true, false>(S, k, 0.0, 0.0, xu, nullptr, nu, nullptr, nullptr, yp);
   }
-  const double *rp = r + off_p(d, nslot, q) + e * NV;
-  double *o = rh + (size_t)q * nslot + e * NV;
+  const T *rp = r + off_p(d, nslot, q) + e * NV;
+  T *o = rh + (size_t)q * nslot + e * NV;
 #pragma unroll
-  for (int j = 0; j < NV; ++j) o[j] = rp[j] - yp[j];
+  for (int j = 0; j < NV; ++j) o[j] = (T)((double)rp[j] - yp[j]);
 }
 
 // tu = K_up zp, or w = D_u^-1 K_up zp when du is given: one thread per
 // (network, simplex)
-template <int d>
+template <int d, typename T>
 __global__ __launch_bounds__(256) void k_dg_tu(DGGeo geo, long nc, long nslot, const int *__restrict__ nbr,
-                                               const double *__restrict__ zp, const double *__restrict__ du,
-                                               double *__restrict__ tu) {
+                                               const T *__restrict__ zp, const T *__restrict__ du,
+                                               T *__restrict__ tu) {
   constexpr int NU = (d + 1) * d, NV = d + 1;
   const int q = blockIdx.y;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nc) return;
   DGShape<d> S;
   dg_shape<d>(geo, e, S);
-  const double *z = zp + (size_t)q * nslot;
+  const T *z = zp + (size_t)q * nslot;
   double xp[NV], yu[NU];
   dg_ld<NV>(z + e * NV, xp);
 #pragma unroll
@@ -649,23 +653,22 @@ __global__ __launch_bounds__(256) void k_dg_tu(DGGeo geo, long nc, long nslot, c
   const size_t o = (size_t)q * nc * NU + e * NU;
   if (du) {
 #pragma unroll
-    for (int j = 0; j < NU; ++j) tu[o + j] = du[o + j] * yu[j];
+    for (int j = 0; j < NU; ++j) tu[o + j] = (T)((double)du[o + j] * yu[j]);
   } else {
 #pragma unroll
-    for (int j = 0; j < NU; ++j) tu[o + j] = yu[j];
+    for (int j = 0; j < NU; ++j) tu[o + j] = (T)yu[j];
   }
 }
 
 // y = S_q x = K_pp x - K_pu w with w = D_u^-1 K_up x (from k_dg_tu); with
 // cheb, one Chebyshev step instead: r = D_S^-1 (b - S_q x), dd = c1 dd + c2 r,
 // xout = x + dd.  One thread per (network, simplex).
-template <int d>
+template <int d, typename T>
 __global__ __launch_bounds__(256) void k_dg_sp(DGGeo geo, long nc, long nslot, const double *__restrict__ k1,
                                                const double *__restrict__ k2, const double *__restrict__ betac,
-                                               double beta, const int *__restrict__ nbr,
-                                               const double *__restrict__ w, const double *__restrict__ x,
-                                               double *__restrict__ y, const double *__restrict__ ds,
-                                               const double *__restrict__ b, double *__restrict__ dd, Sc2 c1, Sc2 c2,
+                                               double beta, const int *__restrict__ nbr, const T *__restrict__ w,
+                                               const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ ds,
+                                               const T *__restrict__ b, T *__restrict__ dd, Sc2 c1, Sc2 c2,
                                                bool cheb) {
   constexpr int NU = (d + 1) * d, NV = d + 1;
   const int q = blockIdx.y;
@@ -676,7 +679,7 @@ __global__ __launch_bounds__(256) void k_dg_sp(DGGeo geo, long nc, long nslot, c
   const double *kq = q ? k2 : k1;
   const double ke = kq[e], alpha = geo.mu / ke, kappa = ke / geo.mu;
   const double bm = (betac ? betac[e] : beta) / geo.mu;
-  const double *xq = x + (size_t)q * nslot, *wq = w + (size_t)q * nc * NU;
+  const T *xq = x + (size_t)q * nslot, *wq = w + (size_t)q * nc * NU;
   double xp[NV], wu[NU], ypp[NV], ypu[NV];
   dg_ld<NV>(xq + e * NV, xp);
   dg_ld<NU>(wq + e * NU, wu);
@@ -703,13 +706,13 @@ __global__ __launch_bounds__(256) void k_dg_sp(DGGeo geo, long nc, long nslot, c
     const size_t i = i0 + j;
     const double acc = ypp[j] - ypu[j];
     if (!cheb) {
-      y[i] = ds ? ds[i] * acc : acc;
+      y[i] = (T)(ds ? (double)ds[i] * acc : acc);
       continue;
     }
-    const double rr = ds[i] * (b[i] - acc);
-    const double dn = (c1.v[q] != 0.0 ? c1.v[q] * dd[i] : 0.0) + c2.v[q] * rr;
-    dd[i] = dn;
-    y[i] = xp[j] + dn;
+    const double rr = (double)ds[i] * ((double)b[i] - acc);
+    const double dn = (c1.v[q] != 0.0 ? c1.v[q] * (double)dd[i] : 0.0) + c2.v[q] * rr;
+    dd[i] = (T)dn;
+    y[i] = (T)(xp[j] + dn);
   }
 }
 
@@ -756,12 +759,14 @@ __global__ void k_dg_binv(long nc, const double *__restrict__ A, double *__restr
 
 // Strided view of per-network velocity vectors: network q's value of
 // simplex e, row r sits at base[q * stride + e NU + r].
+template <typename T>
 struct DGVec {
-  const double *base;
+  const T *base;
   long stride;
 };
+template <typename T>
 struct DGOut {
-  double *base;
+  T *base;
   long stride;
 };
 
@@ -777,12 +782,12 @@ struct DGOut {
 // (simplex, vertex) forms the d K_uu x rows of that vertex from LDS and the
 // simplex type's shape table; one thread per row applies its row of Binv.
 constexpr int DGV_BS = 192;
-template <int d>
+template <int d, typename T>
 __global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, const double *__restrict__ tab, long nc,
                                                      const int *__restrict__ nbr, const double *__restrict__ k1,
-                                                     const double *__restrict__ k2, const double *__restrict__ Bi,
-                                                     DGVec b, const double *__restrict__ tu, DGVec xin, DGOut xout,
-                                                     DGVec xprev, Sc2 c1, Sc2 c2, bool power) {
+                                                     const double *__restrict__ k2, const T *__restrict__ Bi,
+                                                     DGVec<T> b, const T *__restrict__ tu, DGVec<T> xin,
+                                                     DGOut<T> xout, DGVec<T> xprev, Sc2 c1, Sc2 c2, bool power) {
   constexpr int NU = (d + 1) * d, NV = d + 1;
   constexpr int EPB = DGV_BS / NU;
   // per-simplex LDS stride: odd in doubles, so that the simplices of a wave
@@ -797,18 +802,19 @@ __global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, const double *__
   const int loc = threadIdx.x / NU, r = threadIdx.x % NU;
   const long e = (long)blockIdx.x * EPB + loc;
   const bool live = e < nc;
-  const double *xq = xin.base ? xin.base + (size_t)q * xin.stride : nullptr;
+  const T *xq = xin.base ? xin.base + (size_t)q * xin.stride : nullptr;
   // operands of the last phase, fetched first: row r of the packed
   // symmetric block ((r, c) for c >= r, (c, r) below), b less tu, x_(k-1)
   double brow[NU], bv = 0.0, xp = 0.0;
   if (live) {
-    const double *Be = Bi + ((size_t)q * nc + e) * dg_npk(d);
+    const T *Be = Bi + ((size_t)q * nc + e) * dg_npk(d);
     const int rb = dg_packed(NU, r, 0);
 #pragma unroll
-    for (int c = 0; c < NU; ++c) brow[c] = Be[r <= c ? rb + c : dg_packed(NU, c, 0) + r];
+    for (int c = 0; c < NU; ++c) brow[c] = (double)Be[r <= c ? rb + c : dg_packed(NU, c, 0) + r];
     if (!power) {
-      bv = b.base[(size_t)q * b.stride + e * NU + r] - (tu ? tu[(size_t)q * nc * NU + e * NU + r] : 0.0);
-      if (xprev.base) xp = xprev.base[(size_t)q * xprev.stride + e * NU + r];
+      bv = (double)b.base[(size_t)q * b.stride + e * NU + r] -
+           (tu ? (double)tu[(size_t)q * nc * NU + e * NU + r] : 0.0);
+      if (xprev.base) xp = (double)xprev.base[(size_t)q * xprev.stride + e * NU + r];
     }
   }
   if (xq) {  // uniform over the launch
@@ -816,11 +822,11 @@ __global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, const double *__
     if (threadIdx.x < TS) st[threadIdx.x] = tab[threadIdx.x];
     if (live) {
       double *xl = xs + loc * XS;
-      xl[r] = xq[e * NU + r];
+      xl[r] = (double)xq[e * NU + r];
 #pragma unroll
       for (int k = 0; k <= d; ++k) {
         const int nb = nbr[e * NV + k];
-        xl[(1 + k) * NU + r] = nb >= 0 ? xq[(long)nb * NU + r] : 0.0;
+        xl[(1 + k) * NU + r] = nb >= 0 ? (double)xq[(long)nb * NU + r] : 0.0;
       }
       if (r < NV) {
         const int nb = nbr[e * NV + r];
@@ -834,7 +840,7 @@ __global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, const double *__
       const int l2 = threadIdx.x / NV, a = threadIdx.x % NV;
       const long e2 = (long)blockIdx.x * EPB + l2;
       if (e2 < nc) {
-        const double *T = st + (e2 % dg_nper(d)) * dg_tabsz(d);
+        const double *tb = st + (e2 % dg_nper(d)) * dg_tabsz(d);
         const double alpha = sa[l2][NV];
         const double *x0 = xs + l2 * XS;
         double su[d], y[d];
@@ -855,7 +861,7 @@ __global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, const double *__
           const double *xk = x0 + (1 + k) * NU;
           double n[d];
 #pragma unroll
-          for (int c = 0; c < d; ++c) n[c] = T[DG_TAB_NRM * NV * d + k * d + c];
+          for (int c = 0; c < d; ++c) n[c] = tb[DG_TAB_NRM * NV * d + k * d + c];
           // normal jumps at the facet vertices: all of them, then own vertex a
           double sj = 0.0;
 #pragma unroll
@@ -870,7 +876,7 @@ __global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, const double *__
 #pragma unroll
           for (int c = 0; c < d; ++c) ja += n[c] * (x0[a * d + c] - xk[ma * d + c]);
           const double cu = ETA_U * geo.hd * 0.5 * (alpha + an);
-          const double mjn = T[2 * NV * d + k] * (ja + sj);
+          const double mjn = tb[2 * NV * d + k] * (ja + sj);
 #pragma unroll
           for (int c = 0; c < d; ++c) y[c] += cu * n[c] * mjn;
         }
@@ -893,17 +899,17 @@ __global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, const double *__
   double rp = 0.0;
 #pragma unroll
   for (int c = 0; c < NU; ++c) rp += brow[c] * sh[loc * NU + c];
-  double *out = xout.base + (size_t)q * xout.stride + e * NU + r;
+  T *out = xout.base + (size_t)q * xout.stride + e * NU + r;
   if (power) {
-    *out = rp;
+    *out = (T)rp;
     return;
   }
-  *out = xr + (c1.v[q] != 0.0 ? c1.v[q] * (xr - xp) : 0.0) + c2.v[q] * rp;
+  *out = (T)(xr + (c1.v[q] != 0.0 ? c1.v[q] * (xr - xp) : 0.0) + c2.v[q] * rp);
 }
 
 // z_p = zp (the pressure part of the fieldsplit's output)
-template <int d>
-__global__ void k_dg_copyp(long nslot, const double *__restrict__ zp, double *__restrict__ z) {
+template <int d, typename T>
+__global__ void k_dg_copyp(long nslot, const T *__restrict__ zp, T *__restrict__ z) {
   const int q = blockIdx.y;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nslot) return;
@@ -913,8 +919,8 @@ __global__ void k_dg_copyp(long nslot, const double *__restrict__ zp, double *__
 // node value = sum over the slots on the node: for each box around the node
 // and each simplex of it, the node is local vertex |delta| when the axes of
 // its offset delta from the box corner are the first |delta| axes of pi
-template <int d>
-__global__ void k_dg_restrict(GridDev g, long nslot, const double *__restrict__ xs, double *__restrict__ xn) {
+template <int d, typename T>
+__global__ void k_dg_restrict(GridDev g, long nslot, const T *__restrict__ xs, T *__restrict__ xn) {
   constexpr int NP = dg_nper(d);
   const int q = blockIdx.y;
   const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -941,15 +947,15 @@ __global__ void k_dg_restrict(GridDev g, long nslot, const double *__restrict__ 
       dg_perm(d, s, p);
       int pre = 0;
       for (int j = 0; j < v; ++j) pre |= 1 << p[j];
-      if (pre == m) acc += xs[(size_t)q * nslot + (box * NP + s) * (d + 1) + v];
+      if (pre == m) acc += (double)xs[(size_t)q * nslot + (box * NP + s) * (d + 1) + v];
     }
   }
-  xn[(size_t)q * g.N + a] = acc;
+  xn[(size_t)q * g.N + a] = (T)acc;
 }
 
 // slot value = value of its node
-template <int d>
-__global__ void k_dg_prolong(GridDev g, long nc, long nslot, const double *__restrict__ xn, double *__restrict__ xs) {
+template <int d, typename T>
+__global__ void k_dg_prolong(GridDev g, long nc, long nslot, const T *__restrict__ xn, T *__restrict__ xs) {
   constexpr int NP = dg_nper(d);
   const int q = blockIdx.y;
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1191,19 +1197,43 @@ void dg_s_apply(dpp_precond pc, const double *x, double *y, const double *ds, hi
   const long nc = P->g.nc, nslot = P->nslot;
   const DGGeo geo = dg_geo(P);
   const dim3 gs(blocks_for(nc, 256), 2);
-  k_dg_tu<d><<<gs, 256, 0, s>>>(geo, nc, nslot, P->dgnb.as<int>(), x, pc->dgdu.as<double>(), pc->dgtu.as<double>());
-  k_dg_sp<d><<<gs, 256, 0, s>>>(geo, nc, nslot, P->k1.as<double>(), P->k2.as<double>(), dg_betac(P), P->beta,
-                                P->dgnb.as<int>(), pc->dgtu.as<double>(), x, y, ds, nullptr, nullptr, Sc2{{0, 0}},
-                                Sc2{{0, 0}}, false);
+  k_dg_tu<d, double><<<gs, 256, 0, s>>>(geo, nc, nslot, P->dgnb.as<int>(), x, pc->dgdu.as<double>(),
+                                        pc->dgtu.as<double>());
+  k_dg_sp<d, double><<<gs, 256, 0, s>>>(geo, nc, nslot, P->k1.as<double>(), P->k2.as<double>(), dg_betac(P), P->beta,
+                                        P->dgnb.as<int>(), pc->dgtu.as<double>(), x, y, ds, nullptr, nullptr,
+                                        Sc2{{0, 0}}, Sc2{{0, 0}}, false);
 }
+
+// Work buffers of the fieldsplit in one precision: FP64, or FP32 (the block
+// inverses and diagonals rounded once, dg_make32) for the FP32 preconditioner.
+template <typename T>
+struct DGWork {
+  const T *du, *ds, *binv;
+  T *rh, *za, *zb, *dd, *tu, *cb, *cx, *va, *vb, *yu;
+};
+DGWork<double> dg_work(dpp_precond pc, double) {
+  return {pc->dgdu.as<double>(), pc->dgds.as<double>(), pc->dgbinv.as<double>(), pc->dgrh.as<double>(),
+          pc->dgza.as<double>(), pc->dgzb.as<double>(),  pc->dgd.as<double>(),     pc->dgtu.as<double>(),
+          pc->dgcb.as<double>(), pc->dgcx.as<double>(),  pc->dgva.as<double>(),    pc->dgvb.as<double>(),
+          pc->dgyu.as<double>()};
+}
+DGWork<float> dg_work(dpp_precond pc, float) {
+  return {pc->dgdu32.as<float>(), pc->dgds32.as<float>(), pc->dgbinv32.as<float>(), pc->dgrh32.as<float>(),
+          pc->dgza32.as<float>(), pc->dgzb32.as<float>(),  pc->dgd32.as<float>(),     pc->dgtu32.as<float>(),
+          pc->dgcb32.as<float>(), pc->dgcx32.as<float>(),  pc->dgva32.as<float>(),    pc->dgvb32.as<float>(),
+          pc->dgyu32.as<float>()};
+}
+// the nodal CG-VMS cycle in the fieldsplit's precision
+void dg_vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s) { vcycle(pc, b, x, s); }
+void dg_vcycle(dpp_precond pc, const float *b, float *x, hipStream_t s) { vcycle32(pc, b, x, s); }
 
 constexpr int DG_VEL_DEGREE = 8;      // Chebyshev steps of the velocity-block solve
 constexpr double DG_VEL_LO_FRAC = 0.01;  // its interval [0.01 hi, hi]
 
 // out ~ K_uu^-1 (b - tu) per network: DG_VEL_DEGREE Chebyshev steps from
-// zero with the simplex-block Jacobi (intermediate iterates in dgva / dgvb)
-template <int d>
-void dg_vsolve(dpp_precond pc, DGVec b, const double *tu, DGOut out, hipStream_t s) {
+// zero with the simplex-block Jacobi (intermediate iterates in w.va / w.vb)
+template <int d, typename T>
+void dg_vsolve(dpp_precond pc, const DGWork<T> &w, DGVec<T> b, const T *tu, DGOut<T> out, hipStream_t s) {
   dpp_problem P = pc->prob;
   const long nc = P->g.nc, NU = (d + 1) * d;
   const dim3 gv(blocks_for(nc, DGV_BS / NU), 2);
@@ -1215,8 +1245,8 @@ void dg_vsolve(dpp_precond pc, DGVec b, const double *tu, DGOut out, hipStream_t
     sig[q] = th[q] / de[q];
     rho[q] = 1.0 / sig[q];
   }
-  double *buf[2] = {pc->dgva.as<double>(), pc->dgvb.as<double>()};
-  DGVec xin{nullptr, 0}, xprev{nullptr, 0};
+  T *buf[2] = {w.va, w.vb};
+  DGVec<T> xin{nullptr, 0}, xprev{nullptr, 0};
   for (int k = 0; k < DG_VEL_DEGREE; ++k) {
     Sc2 c1{{0, 0}}, c2{{0, 0}};
     for (int q = 0; q < 2; ++q) {
@@ -1230,19 +1260,18 @@ void dg_vsolve(dpp_precond pc, DGVec b, const double *tu, DGOut out, hipStream_t
       }
     }
     // x_(k+1) overwrites x_(k-1) (buf alternates), the last one goes to out
-    const DGOut o = k + 1 == DG_VEL_DEGREE ? out : DGOut{buf[k & 1], nc * NU};
+    const DGOut<T> o = k + 1 == DG_VEL_DEGREE ? out : DGOut<T>{buf[k & 1], nc * NU};
     // bytes: the packed block inverses; b (less tu) read, x' written; x read
     // after the first step (x_0 = 0), x_(k-1) after the second, with the
     // coefficients and the neighbour table
     const double vecs = 2.0 + (tu ? 1.0 : 0.0) + (k > 0 ? 1.0 : 0.0) + (k > 1 ? 1.0 : 0.0);
     ProfScope ps(PF_DG_VEL,
-                 2.0 * 8.0 * ((double)nc * dg_npk(d) + vecs * nc * NU) +
+                 2.0 * sizeof(T) * ((double)nc * dg_npk(d) + vecs * nc * NU) +
                      (k > 0 ? 2.0 * 8.0 * nc + 4.0 * nc * (d + 1) : 0.0), s);
-    k_dg_vcheb<d><<<gv, DGV_BS, 0, s>>>(geo, P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(),
-                                        P->k2.as<double>(), pc->dgbinv.as<double>(), b, tu, xin, o, xprev, c1, c2,
-                                        false);
+    k_dg_vcheb<d, T><<<gv, DGV_BS, 0, s>>>(geo, P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(),
+                                           P->k2.as<double>(), w.binv, b, tu, xin, o, xprev, c1, c2, false);
     xprev = xin;
-    xin = DGVec{o.base, o.stride};
+    xin = DGVec<T>{o.base, o.stride};
   }
   check_launch("DG velocity solve");
 }
@@ -1323,10 +1352,10 @@ void dg_setup_impl(dpp_precond pc, hipStream_t s) {
     dg_sumsq(pc, vx, nu, ssd, s);
     k_dg_scale<<<gu, 256, 0, s>>>(vx, nu, ssd);
     for (int it = 0; it < o.power_iters; ++it) {
-      k_dg_vcheb<d><<<gb, DGV_BS, 0, s>>>(dg_geo(P), P->dgtab.as<double>(), nc, P->dgnb.as<int>(),
-                                          P->k1.as<double>(), P->k2.as<double>(), pc->dgbinv.as<double>(),
-                                          DGVec{nullptr, 0}, nullptr, DGVec{vx, nu}, DGOut{vy, nu}, DGVec{nullptr, 0},
-                                          Sc2{{0, 0}}, Sc2{{0, 0}}, true);
+      k_dg_vcheb<d, double><<<gb, DGV_BS, 0, s>>>(
+          dg_geo(P), P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(), P->k2.as<double>(),
+          pc->dgbinv.as<double>(), DGVec<double>{nullptr, 0}, nullptr, DGVec<double>{vx, nu}, DGOut<double>{vy, nu},
+          DGVec<double>{nullptr, 0}, Sc2{{0, 0}}, Sc2{{0, 0}}, true);
       dg_sumsq(pc, vy, nu, ssd, s);
       k_dg_scale<<<gu, 256, 0, s>>>(vy, nu, ssd);
       std::swap(vx, vy);
@@ -1351,37 +1380,37 @@ void dg_setup_impl(dpp_precond pc, hipStream_t s) {
   }
 }
 
-template <int d>
-void dg_apply_impl(dpp_precond pc, const double *r, double *z, hipStream_t s) {
+template <int d, typename T>
+void dg_apply_impl(dpp_precond pc, const T *r, T *z, hipStream_t s) {
   dpp_problem P = pc->prob;
   const Grid &g = P->g;
   const long nc = g.nc, nslot = P->nslot;
-  const double *du = pc->dgdu.as<double>(), *ds = pc->dgds.as<double>();
+  const DGWork<T> w = dg_work(pc, T());
   const double *k1 = P->k1.as<double>(), *k2 = P->k2.as<double>(), *bc = dg_betac(P);
   const int *nb = P->dgnb.as<int>();
   const DGGeo geo = dg_geo(P);
   const dim3 gp(blocks_for(nslot, 256), 2), gs(blocks_for(nc, 256), 2);
-  double *rh = pc->dgrh.as<double>();
   const long NU = (d + 1) * d, vstride = (d + 1) * nslot;  // network stride of the ABI vector
-  dg_vsolve<d>(pc, DGVec{r + off_u(d, nslot, 0), vstride}, nullptr, DGOut{pc->dgyu.as<double>(), nc * NU}, s);
+  const double vb = sizeof(T);                               // bytes per stored vector value
+  dg_vsolve<d, T>(pc, w, DGVec<T>{r + off_u(d, nslot, 0), vstride}, nullptr, DGOut<T>{w.yu, nc * NU}, s);
   // algorithmic bytes of the pressure-side launches (2 networks, matrix-free):
   // vectors once, the neighbour table, the coefficients where they enter
   const double nbr_b = 4.0 * nc * (d + 1);
-  const double b_tu = 2.0 * 8.0 * ((double)nslot + (double)nc * NU) + nbr_b;  // zp in, tu out
+  const double b_tu = 2.0 * vb * ((double)nslot + (double)nc * NU) + nbr_b;  // zp in, tu out
   {
-    ProfScope ps(PF_DG_PRES, 2.0 * 8.0 * ((double)nc * NU + 2.0 * nslot) + nbr_b, s);
-    k_dg_rhat<d><<<gs, 256, 0, s>>>(geo, nc, nslot, nb, pc->dgyu.as<double>(), r, rh);
+    ProfScope ps(PF_DG_PRES, 2.0 * vb * ((double)nc * NU + 2.0 * nslot) + nbr_b, s);
+    k_dg_rhat<d, T><<<gs, 256, 0, s>>>(geo, nc, nslot, nb, w.yu, r, w.rh);
   }
   // coarse correction on the nodes, back to the slots
   {
-    ProfScope ps(PF_DG_TRANSFER, 2.0 * 8.0 * ((double)nslot + (double)g.N), s);
-    k_dg_restrict<d><<<dim3(blocks_for(g.N, 256), 2), 256, 0, s>>>(dev(g), nslot, rh, pc->dgcb.as<double>());
+    ProfScope ps(PF_DG_TRANSFER, 2.0 * vb * ((double)nslot + (double)g.N), s);
+    k_dg_restrict<d, T><<<dim3(blocks_for(g.N, 256), 2), 256, 0, s>>>(dev(g), nslot, w.rh, w.cb);
   }
-  vcycle(pc->dgpc, pc->dgcb.as<double>(), pc->dgcx.as<double>(), s);
-  double *cur = pc->dgza.as<double>(), *oth = pc->dgzb.as<double>();
+  dg_vcycle(pc->dgpc, w.cb, w.cx, s);
+  T *cur = w.za, *oth = w.zb;
   {
-    ProfScope ps(PF_DG_TRANSFER, 2.0 * 8.0 * ((double)nslot + (double)g.N), s);
-    k_dg_prolong<d><<<gp, 256, 0, s>>>(dev(g), nc, nslot, pc->dgcx.as<double>(), cur);
+    ProfScope ps(PF_DG_TRANSFER, 2.0 * vb * ((double)nslot + (double)g.N), s);
+    k_dg_prolong<d, T><<<gp, 256, 0, s>>>(dev(g), nc, nslot, w.cx, cur);
   }
   // Chebyshev post-smoothing on S_q (Saad, Alg. 12.1 with the diagonal of S_q)
   const int deg = pc->opts.cheb_post_fine >= 1 ? pc->opts.cheb_post_fine : pc->opts.cheb_degree;
@@ -1406,31 +1435,40 @@ void dg_apply_impl(dpp_precond pc, const double *r, double *z, hipStream_t s) {
     }
     {
       // w = D_u^-1 K_up x: x and D_u^-1 in, w out
-      ProfScope ps(PF_DG_PRES, b_tu + 2.0 * 8.0 * nc * NU, s);
-      k_dg_tu<d><<<gs, 256, 0, s>>>(geo, nc, nslot, nb, cur, du, pc->dgtu.as<double>());
+      ProfScope ps(PF_DG_PRES, b_tu + 2.0 * vb * nc * NU, s);
+      k_dg_tu<d, T><<<gs, 256, 0, s>>>(geo, nc, nslot, nb, cur, w.du, w.tu);
     }
     {
       // S_q rows: w, x, diag, b, dd (read after the first step), dd and x'
       // written, the coefficients
       ProfScope ps(PF_DG_PRES,
-                   2.0 * 8.0 * ((double)nc * NU + (k > 0 ? 6.0 : 5.0) * nslot) + 2.0 * dg_coef_bytes(P) + nbr_b, s);
-      k_dg_sp<d><<<gs, 256, 0, s>>>(geo, nc, nslot, k1, k2, bc, P->beta, nb, pc->dgtu.as<double>(), cur, oth, ds, rh,
-                                    pc->dgd.as<double>(), c1, c2, true);
+                   2.0 * vb * ((double)nc * NU + (k > 0 ? 6.0 : 5.0) * nslot) + 2.0 * dg_coef_bytes(P) + nbr_b, s);
+      k_dg_sp<d, T><<<gs, 256, 0, s>>>(geo, nc, nslot, k1, k2, bc, P->beta, nb, w.tu, cur, oth, w.ds, w.rh, w.dd, c1,
+                                       c2, true);
     }
     std::swap(cur, oth);
   }
   // z_u ~ K_uu^-1 (r_u - K_up z_p), z_p
   {
     ProfScope ps(PF_DG_PRES, b_tu, s);
-    k_dg_tu<d><<<gs, 256, 0, s>>>(geo, nc, nslot, nb, cur, nullptr, pc->dgtu.as<double>());
+    k_dg_tu<d, T><<<gs, 256, 0, s>>>(geo, nc, nslot, nb, cur, nullptr, w.tu);
   }
-  dg_vsolve<d>(pc, DGVec{r + off_u(d, nslot, 0), vstride}, pc->dgtu.as<double>(),
-               DGOut{z + off_u(d, nslot, 0), vstride}, s);
+  dg_vsolve<d, T>(pc, w, DGVec<T>{r + off_u(d, nslot, 0), vstride}, w.tu, DGOut<T>{z + off_u(d, nslot, 0), vstride},
+                  s);
   {
-    ProfScope ps(PF_DG_PRES, 2.0 * 2.0 * 8.0 * nslot, s);
-    k_dg_copyp<d><<<gp, 256, 0, s>>>(nslot, cur, z);
+    ProfScope ps(PF_DG_PRES, 2.0 * 2.0 * vb * nslot, s);
+    k_dg_copyp<d, T><<<gp, 256, 0, s>>>(nslot, cur, z);
   }
   check_launch("DG fieldsplit");
+}
+
+__global__ void k_dg_to32(const double *__restrict__ x, float *__restrict__ y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+__global__ void k_dg_to64(const float *__restrict__ x, double *__restrict__ y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
 }
 
 }  // namespace
@@ -1442,11 +1480,47 @@ void dg_precond_setup(dpp_precond pc, hipStream_t s) {
     dg_setup_impl<2>(pc, s);
 }
 
-void dg_precond_apply(dpp_precond pc, const double *r, double *z, hipStream_t s) {
-  if (pc->prob->g.dim == 3)
-    dg_apply_impl<3>(pc, r, z, s);
+void dg_make32(dpp_precond pc, hipStream_t s) {
+  if (pc->dg32) return;
+  dpp_problem P = pc->prob;
+  const int d = P->g.dim;
+  const long nc = P->g.nc, nslot = P->nslot, NU = (d + 1) * d, N = P->g.N;
+  auto conv = [&](const DBuf &src, DBuf &dst, long n) {
+    dst.alloc(sizeof(float) * n);
+    k_dg_to32<<<std::min(2048, blocks_for(n, 256)), 256, 0, s>>>(src.as<double>(), dst.as<float>(), n);
+  };
+  conv(pc->dgdu, pc->dgdu32, 2 * nc * NU);
+  conv(pc->dgds, pc->dgds32, 2 * nslot);
+  conv(pc->dgbinv, pc->dgbinv32, 2 * nc * dg_npk(d));
+  for (DBuf *b : {&pc->dgrh32, &pc->dgza32, &pc->dgzb32, &pc->dgd32}) b->alloc(sizeof(float) * 2 * nslot);
+  for (DBuf *b : {&pc->dgtu32, &pc->dgva32, &pc->dgvb32, &pc->dgyu32}) b->alloc(sizeof(float) * 2 * nc * NU);
+  for (DBuf *b : {&pc->dgcb32, &pc->dgcx32}) b->alloc(sizeof(float) * 2 * N);
+  for (DBuf *b : {&pc->dgr32, &pc->dgz32}) b->alloc(sizeof(float) * P->ndof());
+  check_launch("DG fp32 copies");
+  precond_make32(pc->dgpc, s);
+  pc->dg32 = true;
+}
+
+void dg_precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStream_t s) {
+  const int d = pc->prob->g.dim;
+  if (!fp32) {
+    if (d == 3)
+      dg_apply_impl<3, double>(pc, r, z, s);
+    else
+      dg_apply_impl<2, double>(pc, r, z, s);
+    return;
+  }
+  // FP32 preconditioner: the residual rounded once, the correction widened once
+  DPP_CHECK(pc->dg32, DPP_ERR_ARG, "internal: DG FP32 preconditioner not set up");
+  const long n = pc->prob->ndof();
+  const int nb = std::min(2048, blocks_for(n, 256));
+  k_dg_to32<<<nb, 256, 0, s>>>(r, pc->dgr32.as<float>(), n);
+  if (d == 3)
+    dg_apply_impl<3, float>(pc, pc->dgr32.as<float>(), pc->dgz32.as<float>(), s);
   else
-    dg_apply_impl<2>(pc, r, z, s);
+    dg_apply_impl<2, float>(pc, pc->dgr32.as<float>(), pc->dgz32.as<float>(), s);
+  k_dg_to64<<<nb, 256, 0, s>>>(pc->dgz32.as<float>(), z, n);
+  check_launch("DG fieldsplit (fp32)");
 }
 
 }  // namespace dpp

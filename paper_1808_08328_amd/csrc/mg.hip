@@ -857,6 +857,10 @@ void precond_setup(dpp_precond pc, hipStream_t s) {
 }
 
 void precond_make32(dpp_precond pc, hipStream_t s) {
+  if (pc->prob->dg) {
+    dg_make32(pc, s);
+    return;
+  }
   if (pc->has32) return;
   make_k32(pc->prob, s);
   for (auto &lp : pc->lv) {
@@ -884,11 +888,15 @@ void vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s) {
   DPP_TAG_SWITCH(pc->prob->g, (vcyc<D_, double>(pc, 0, b, x, s)));
 }
 
+void vcycle32(dpp_precond pc, const float *b, float *x, hipStream_t s) {
+  DPP_CHECK(pc->has32, DPP_ERR_ARG, "internal: FP32 levels not set up");
+  DPP_TAG_SWITCH(pc->prob->g, (vcyc<D_, float>(pc, 0, b, x, s)));
+}
+
 void precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStream_t s) {
   dpp_problem P = pc->prob;
   if (P->dg) {
-    DPP_CHECK(!fp32, DPP_ERR_UNSUPPORTED, "DG-VMS problems are solved in FP64");
-    dg_precond_apply(pc, r, z, s);
+    dg_precond_apply(pc, r, z, fp32, s);
     return;
   }
   Level &L0 = *pc->lv[0];

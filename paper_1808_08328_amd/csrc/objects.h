@@ -136,6 +136,11 @@ struct dpp_precond_s {
   dpp_precond_s *dgpc = nullptr;
   dpp::DBuf dgzero, dgdu, dgds, dgrh, dgza, dgzb, dgd, dgtu, dgcb, dgcx, dgpart;
   dpp::DBuf dgbinv, dgva, dgvb, dgyu;  // velocity block: packed simplex-block inverses, Chebyshev work
+  // FP32 copies (diagonals and block inverses rounded once) and FP32 work
+  // vectors of the FP32 preconditioner (precision 2), made on demand
+  dpp::DBuf dgdu32, dgds32, dgbinv32, dgrh32, dgza32, dgzb32, dgd32, dgtu32, dgcb32, dgcx32, dgva32, dgvb32, dgyu32;
+  dpp::DBuf dgr32, dgz32;  // [n_dof] the residual and the correction
+  bool dg32 = false;
   double dghi[2] = {0.0, 0.0}, dglo[2] = {0.0, 0.0};    // pressure-block Chebyshev interval
   double dgvhi[2] = {0.0, 0.0}, dgvlo[2] = {0.0, 0.0};  // velocity-block Chebyshev interval
   void drop_graphs() {
@@ -198,10 +203,12 @@ void dg_assemble(dpp_problem P, const dpp_params *prm, hipStream_t s);
 void dg_spmv(dpp_problem P, const double *x, const double *bsub, double *y, hipStream_t s);
 void dg_export_csr(dpp_problem P, int64_t *rowptr, int32_t *cols, double *vals, hipStream_t s);
 void dg_precond_setup(dpp_precond pc, hipStream_t s);
-void dg_precond_apply(dpp_precond pc, const double *r, double *z, hipStream_t s);
+void dg_precond_apply(dpp_precond pc, const double *r, double *z, bool fp32, hipStream_t s);
+void dg_make32(dpp_precond pc, hipStream_t s);
 void consistent_rhs(dpp_problem P, double *b, hipStream_t s);
 void normalize_pressures(dpp_problem P, double *x, hipStream_t s);
 void vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s);  // FP64, [2][N] in/out
+void vcycle32(dpp_precond pc, const float *b, float *x, hipStream_t s);  // FP32 levels (precond_make32)
 void level_spmv(dpp_precond pc, int level, int net, const double *x, double *y, hipStream_t s);
 void precond_make32(dpp_precond pc, hipStream_t s);
 // Chebyshev degrees of level l's pre- and post-smoothing (the finest level or
