@@ -770,6 +770,67 @@ struct DGOut {
   long stride;
 };
 
+// Facet neighbours of simplex e by the Freudenthal rule of the Kuhn split (as
+// dg_simplex builds the neighbour table), computed in registers so that the
+// neighbours' values can be fetched without waiting for the table: nb[k] is
+// the simplex across the facet opposite local vertex k, -1 on the boundary.
+template <int d>
+__device__ inline void dg_neighbours(const GridDev &g, long e, int *nb) {
+  constexpr int NP = dg_nper(d);
+  const long box = e / NP;
+  const int s = (int)(e - box * NP);
+  int cell[3] = {0, 0, 0}, p[3] = {0, 0, 0};
+  long rr = box;
+#pragma unroll
+  for (int a = 0; a < d; ++a) {
+    const long t = rr / g.n[a];
+    cell[a] = (int)(rr - t * g.n[a]);
+    rr = t;
+  }
+  if constexpr (d == 2) {
+    p[0] = s;
+    p[1] = 1 - s;
+  } else {
+    const int f = s >> 1, lo = f == 0 ? 1 : 0, hi = f == 2 ? 1 : 2;
+    p[0] = f;
+    p[1] = (s & 1) ? hi : lo;
+    p[2] = (s & 1) ? lo : hi;
+  }
+#pragma unroll
+  for (int k = 0; k <= d; ++k) {
+    // the neighbour's box: one step along p[0] (k = 0) or back along p[d-1] (k = d)
+    const int ax = k == 0 ? p[0] : (k == d ? p[d - 1] : -1);
+    const int step = k == 0 ? 1 : -1;
+    bool inside = true;
+    long nbox = 0, mul = 1;
+#pragma unroll
+    for (int a = 0; a < d; ++a) {
+      const int c = cell[a] + (ax == a ? step : 0);
+      inside = inside && c >= 0 && c < g.n[a];
+      nbox += c * mul;
+      mul *= g.n[a];
+    }
+    // its axis permutation: p rotated left (k = 0), right (k = d), or with
+    // entries k-1 and k swapped
+    int q0, q1, q2 = 0;
+    if (k == 0) {
+      q0 = p[1];
+      q1 = d == 3 ? p[2] : p[0];
+      if (d == 3) q2 = p[0];
+    } else if (k == d) {
+      q0 = p[d - 1];
+      q1 = p[0];
+      if (d == 3) q2 = p[1];
+    } else {
+      q0 = k == 1 ? p[1] : p[0];
+      q1 = k == 1 ? p[0] : p[2];
+      if (d == 3) q2 = k == 1 ? p[2] : p[1];
+    }
+    const int pidx = d == 2 ? q0 : 2 * q0 + (q1 > q2 ? 1 : 0);
+    nb[k] = inside ? (int)(nbox * NP + pidx) : -1;
+  }
+}
+
 // Velocity-block Chebyshev step with the simplex-block Jacobi (Saad, Alg.
 // 12.1): res = b - K_uu x (b less tu when given; x = 0 when xin is null),
 // r' = Binv res, xout = x + c1 (x - xprev) + c2 r' (the three-term form of
@@ -778,12 +839,14 @@ struct DGOut {
 // power steps of the interval).  Workgroups of whole simplices (192
 // threads: 16 simplices in 3D, 32 in 2D), in three phases: every thread
 // stages one value of its simplex and of each facet neighbour in LDS (and
-// fetches its row of Binv and its b, x_(k-1) entries); one thread per
-// (simplex, vertex) forms the d K_uu x rows of that vertex from LDS and the
-// simplex type's shape table; one thread per row applies its row of Binv.
+// fetches its b, x_(k-1) entries); one thread per (simplex, vertex) forms the
+// d K_uu x rows of that vertex from LDS and the simplex type's shape table;
+// one thread per row applies its row of Binv.  The step is bound by the
+// latency of these dependent phases more than by its bytes, so the launch
+// bound asks for 7 waves per SIMD (72 VGPRs in 3D, no spills; 8 spill).
 constexpr int DGV_BS = 192;
 template <int d, typename T>
-__global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, const double *__restrict__ tab, long nc,
+__global__ __launch_bounds__(DGV_BS, 7) void k_dg_vcheb(DGGeo geo, GridDev g, const double *__restrict__ tab, long nc,
                                                      const int *__restrict__ nbr, const double *__restrict__ k1,
                                                      const double *__restrict__ k2, const T *__restrict__ Bi,
                                                      DGVec<T> b, const T *__restrict__ tu, DGVec<T> xin,
@@ -803,14 +866,9 @@ __global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, const double *__
   const long e = (long)blockIdx.x * EPB + loc;
   const bool live = e < nc;
   const T *xq = xin.base ? xin.base + (size_t)q * xin.stride : nullptr;
-  // operands of the last phase, fetched first: row r of the packed
-  // symmetric block ((r, c) for c >= r, (c, r) below), b less tu, x_(k-1)
-  double brow[NU], bv = 0.0, xp = 0.0;
+  // operands of the last phase, fetched first: b less tu, x_(k-1)
+  double bv = 0.0, xp = 0.0;
   if (live) {
-    const T *Be = Bi + ((size_t)q * nc + e) * dg_npk(d);
-    const int rb = dg_packed(NU, r, 0);
-#pragma unroll
-    for (int c = 0; c < NU; ++c) brow[c] = (double)Be[r <= c ? rb + c : dg_packed(NU, c, 0) + r];
     if (!power) {
       bv = (double)b.base[(size_t)q * b.stride + e * NU + r] -
            (tu ? (double)tu[(size_t)q * nc * NU + e * NU + r] : 0.0);
@@ -822,15 +880,16 @@ __global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, const double *__
     if (threadIdx.x < TS) st[threadIdx.x] = tab[threadIdx.x];
     if (live) {
       double *xl = xs + loc * XS;
+      int nb[NV];
+      dg_neighbours<d>(g, e, nb);
       xl[r] = (double)xq[e * NU + r];
 #pragma unroll
-      for (int k = 0; k <= d; ++k) {
-        const int nb = nbr[e * NV + k];
-        xl[(1 + k) * NU + r] = nb >= 0 ? (double)xq[(long)nb * NU + r] : 0.0;
-      }
+      for (int k = 0; k <= d; ++k) xl[(1 + k) * NU + r] = nb[k] >= 0 ? (double)xq[(long)nb[k] * NU + r] : 0.0;
       if (r < NV) {
-        const int nb = nbr[e * NV + r];
-        sa[loc][r] = nb >= 0 ? geo.mu / kq[nb] : 0.0;
+        int nr = nb[0];
+#pragma unroll
+        for (int k = 1; k <= d; ++k) nr = r == k ? nb[k] : nr;
+        sa[loc][r] = nr >= 0 ? geo.mu / kq[nr] : 0.0;
       } else if (r == NV) {
         sa[loc][NV] = geo.mu / kq[e];
       }
@@ -896,9 +955,12 @@ __global__ __launch_bounds__(DGV_BS) void k_dg_vcheb(DGGeo geo, const double *__
   sh[threadIdx.x] = res;
   __syncthreads();
   if (!live) return;
+  // row r of the packed symmetric block: (r, c) for c >= r, (c, r) below
+  const T *Be = Bi + ((size_t)q * nc + e) * dg_npk(d);
+  const int rb = dg_packed(NU, r, 0);
   double rp = 0.0;
 #pragma unroll
-  for (int c = 0; c < NU; ++c) rp += brow[c] * sh[loc * NU + c];
+  for (int c = 0; c < NU; ++c) rp += (double)Be[r <= c ? rb + c : dg_packed(NU, c, 0) + r] * sh[loc * NU + c];
   T *out = xout.base + (size_t)q * xout.stride + e * NU + r;
   if (power) {
     *out = (T)rp;
@@ -1268,7 +1330,7 @@ void dg_vsolve(dpp_precond pc, const DGWork<T> &w, DGVec<T> b, const T *tu, DGOu
     ProfScope ps(PF_DG_VEL,
                  2.0 * sizeof(T) * ((double)nc * dg_npk(d) + vecs * nc * NU) +
                      (k > 0 ? 2.0 * 8.0 * nc + 4.0 * nc * (d + 1) : 0.0), s);
-    k_dg_vcheb<d, T><<<gv, DGV_BS, 0, s>>>(geo, P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(),
+    k_dg_vcheb<d, T><<<gv, DGV_BS, 0, s>>>(geo, dev(P->g), P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(),
                                            P->k2.as<double>(), w.binv, b, tu, xin, o, xprev, c1, c2, false);
     xprev = xin;
     xin = DGVec<T>{o.base, o.stride};
@@ -1353,7 +1415,7 @@ void dg_setup_impl(dpp_precond pc, hipStream_t s) {
     k_dg_scale<<<gu, 256, 0, s>>>(vx, nu, ssd);
     for (int it = 0; it < o.power_iters; ++it) {
       k_dg_vcheb<d, double><<<gb, DGV_BS, 0, s>>>(
-          dg_geo(P), P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(), P->k2.as<double>(),
+          dg_geo(P), dev(P->g), P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(), P->k2.as<double>(),
           pc->dgbinv.as<double>(), DGVec<double>{nullptr, 0}, nullptr, DGVec<double>{vx, nu}, DGOut<double>{vy, nu},
           DGVec<double>{nullptr, 0}, Sc2{{0, 0}}, Sc2{{0, 0}}, true);
       dg_sumsq(pc, vy, nu, ssd, s);
