@@ -290,6 +290,7 @@ struct DGGeo {
   double hd;  // twice the circumradius (the box-cell diagonal)
   double mu;
   double mc;  // M[a][b] = mc (1 + delta_ab), the same for every simplex of the box
+  int n[3];   // boxes per axis
 };
 
 // Per-type shape table (one row per simplex type of a box, built on the
@@ -441,6 +442,67 @@ __device__ inline void dg_facet(const DGShape<d> &S, int k, double cu, double cp
   }
 }
 
+// Facet neighbours of simplex e by the Freudenthal rule of the Kuhn split (as
+// dg_simplex builds the neighbour table), computed in registers so that the
+// neighbours' values can be fetched without waiting for the table: nb[k] is
+// the simplex across the facet opposite local vertex k, -1 on the boundary.
+template <int d>
+__device__ inline void dg_neighbours(const DGGeo &g, long e, int *nb) {
+  constexpr int NP = dg_nper(d);
+  const long box = e / NP;
+  const int s = (int)(e - box * NP);
+  int cell[3] = {0, 0, 0}, p[3] = {0, 0, 0};
+  long rr = box;
+#pragma unroll
+  for (int a = 0; a < d; ++a) {
+    const long t = rr / g.n[a];
+    cell[a] = (int)(rr - t * g.n[a]);
+    rr = t;
+  }
+  if constexpr (d == 2) {
+    p[0] = s;
+    p[1] = 1 - s;
+  } else {
+    const int f = s >> 1, lo = f == 0 ? 1 : 0, hi = f == 2 ? 1 : 2;
+    p[0] = f;
+    p[1] = (s & 1) ? hi : lo;
+    p[2] = (s & 1) ? lo : hi;
+  }
+#pragma unroll
+  for (int k = 0; k <= d; ++k) {
+    // the neighbour's box: one step along p[0] (k = 0) or back along p[d-1] (k = d)
+    const int ax = k == 0 ? p[0] : (k == d ? p[d - 1] : -1);
+    const int step = k == 0 ? 1 : -1;
+    bool inside = true;
+    long nbox = 0, mul = 1;
+#pragma unroll
+    for (int a = 0; a < d; ++a) {
+      const int c = cell[a] + (ax == a ? step : 0);
+      inside = inside && c >= 0 && c < g.n[a];
+      nbox += c * mul;
+      mul *= g.n[a];
+    }
+    // its axis permutation: p rotated left (k = 0), right (k = d), or with
+    // entries k-1 and k swapped
+    int q0, q1, q2 = 0;
+    if (k == 0) {
+      q0 = p[1];
+      q1 = d == 3 ? p[2] : p[0];
+      if (d == 3) q2 = p[0];
+    } else if (k == d) {
+      q0 = p[d - 1];
+      q1 = p[0];
+      if (d == 3) q2 = p[1];
+    } else {
+      q0 = k == 1 ? p[1] : p[0];
+      q1 = k == 1 ? p[0] : p[2];
+      if (d == 3) q2 = k == 1 ? p[2] : p[1];
+    }
+    const int pidx = d == 2 ? q0 : 2 * q0 + (q1 > q2 ? 1 : 0);
+    nb[k] = inside ? (int)(nbox * NP + pidx) : -1;
+  }
+}
+
 template <int n, typename T>
 __device__ inline void dg_ld(const T *__restrict__ p, double *v) {
 #pragma unroll
@@ -486,7 +548,7 @@ __global__ __launch_bounds__(256) void k_dg_spmv(DGGeo geo, long nc, long nslot,
 #pragma unroll
   for (int a = 0; a <= d; ++a) yp[a] -= bm * S.mc * (xo[a] + so);
   int nb[NV];
-  dg_ldi<NV>(nbr + e * NV, nb);
+  dg_neighbours<d>(geo, e, nb);
 #pragma unroll
   for (int k = 0; k <= d; ++k) {
     if (nb[k] < 0) continue;
@@ -609,7 +671,7 @@ __global__ __launch_bounds__(256) void k_dg_rhat(DGGeo geo, long nc, long nslot,
   for (int j = 0; j < NV; ++j) yp[j] = 0.0;
   dg_volume<d, false, false, true, false>(S, 0.0, 0.0, 0.0, xu, nullptr, nullptr, yp);
   int nb[NV];
-  dg_ldi<NV>(nbr + e * NV, nb);
+  dg_neighbours<d>(geo, e, nb);
 #pragma unroll
   for (int k = 0; k <= d; ++k) {
     if (nb[k] < 0) continue;
@@ -642,7 +704,7 @@ __global__ __launch_bounds__(256) void k_dg_tu(DGGeo geo, long nc, long nslot, c
   for (int j = 0; j < NU; ++j) yu[j] = 0.0;
   dg_volume<d, false, true, false, false>(S, 0.0, 0.0, 0.0, nullptr, xp, yu, nullptr);
   int nb[NV];
-  dg_ldi<NV>(nbr + e * NV, nb);
+  dg_neighbours<d>(geo, e, nb);
 #pragma unroll
   for (int k = 0; k <= d; ++k) {
     if (nb[k] < 0) continue;
@@ -688,7 +750,7 @@ __global__ __launch_bounds__(256) void k_dg_sp(DGGeo geo, long nc, long nslot, c
   dg_volume<d, false, false, false, true>(S, alpha, kappa, bm, nullptr, xp, nullptr, ypp);
   dg_volume<d, false, false, true, false>(S, alpha, kappa, bm, wu, nullptr, nullptr, ypu);
   int nb[NV];
-  dg_ldi<NV>(nbr + e * NV, nb);
+  dg_neighbours<d>(geo, e, nb);
 #pragma unroll
   for (int k = 0; k <= d; ++k) {
     if (nb[k] < 0) continue;
@@ -770,67 +832,6 @@ struct DGOut {
   long stride;
 };
 
-// Facet neighbours of simplex e by the Freudenthal rule of the Kuhn split (as
-// dg_simplex builds the neighbour table), computed in registers so that the
-// neighbours' values can be fetched without waiting for the table: nb[k] is
-// the simplex across the facet opposite local vertex k, -1 on the boundary.
-template <int d>
-__device__ inline void dg_neighbours(const GridDev &g, long e, int *nb) {
-  constexpr int NP = dg_nper(d);
-  const long box = e / NP;
-  const int s = (int)(e - box * NP);
-  int cell[3] = {0, 0, 0}, p[3] = {0, 0, 0};
-  long rr = box;
-#pragma unroll
-  for (int a = 0; a < d; ++a) {
-    const long t = rr / g.n[a];
-    cell[a] = (int)(rr - t * g.n[a]);
-    rr = t;
-  }
-  if constexpr (d == 2) {
-    p[0] = s;
-    p[1] = 1 - s;
-  } else {
-    const int f = s >> 1, lo = f == 0 ? 1 : 0, hi = f == 2 ? 1 : 2;
-    p[0] = f;
-    p[1] = (s & 1) ? hi : lo;
-    p[2] = (s & 1) ? lo : hi;
-  }
-#pragma unroll
-  for (int k = 0; k <= d; ++k) {
-    // the neighbour's box: one step along p[0] (k = 0) or back along p[d-1] (k = d)
-    const int ax = k == 0 ? p[0] : (k == d ? p[d - 1] : -1);
-    const int step = k == 0 ? 1 : -1;
-    bool inside = true;
-    long nbox = 0, mul = 1;
-#pragma unroll
-    for (int a = 0; a < d; ++a) {
-      const int c = cell[a] + (ax == a ? step : 0);
-      inside = inside && c >= 0 && c < g.n[a];
-      nbox += c * mul;
-      mul *= g.n[a];
-    }
-    // its axis permutation: p rotated left (k = 0), right (k = d), or with
-    // entries k-1 and k swapped
-    int q0, q1, q2 = 0;
-    if (k == 0) {
-      q0 = p[1];
-      q1 = d == 3 ? p[2] : p[0];
-      if (d == 3) q2 = p[0];
-    } else if (k == d) {
-      q0 = p[d - 1];
-      q1 = p[0];
-      if (d == 3) q2 = p[1];
-    } else {
-      q0 = k == 1 ? p[1] : p[0];
-      q1 = k == 1 ? p[0] : p[2];
-      if (d == 3) q2 = k == 1 ? p[2] : p[1];
-    }
-    const int pidx = d == 2 ? q0 : 2 * q0 + (q1 > q2 ? 1 : 0);
-    nb[k] = inside ? (int)(nbox * NP + pidx) : -1;
-  }
-}
-
 // Velocity-block Chebyshev step with the simplex-block Jacobi (Saad, Alg.
 // 12.1): res = b - K_uu x (b less tu when given; x = 0 when xin is null),
 // r' = Binv res, xout = x + c1 (x - xprev) + c2 r' (the three-term form of
@@ -846,7 +847,7 @@ __device__ inline void dg_neighbours(const GridDev &g, long e, int *nb) {
 // bound asks for 7 waves per SIMD (72 VGPRs in 3D, no spills; 8 spill).
 constexpr int DGV_BS = 192;
 template <int d, typename T>
-__global__ __launch_bounds__(DGV_BS, 7) void k_dg_vcheb(DGGeo geo, GridDev g, const double *__restrict__ tab, long nc,
+__global__ __launch_bounds__(DGV_BS, 7) void k_dg_vcheb(DGGeo geo, const double *__restrict__ tab, long nc,
                                                      const int *__restrict__ nbr, const double *__restrict__ k1,
                                                      const double *__restrict__ k2, const T *__restrict__ Bi,
                                                      DGVec<T> b, const T *__restrict__ tu, DGVec<T> xin,
@@ -881,7 +882,7 @@ __global__ __launch_bounds__(DGV_BS, 7) void k_dg_vcheb(DGGeo geo, GridDev g, co
     if (live) {
       double *xl = xs + loc * XS;
       int nb[NV];
-      dg_neighbours<d>(g, e, nb);
+      dg_neighbours<d>(geo, e, nb);
       xl[r] = (double)xq[e * NU + r];
 #pragma unroll
       for (int k = 0; k <= d; ++k) xl[(1 + k) * NU + r] = nb[k] >= 0 ? (double)xq[(long)nb[k] * NU + r] : 0.0;
@@ -1095,6 +1096,7 @@ DGGeo dg_geo(dpp_problem P) {
   }
   geo.hd = std::sqrt(hd);
   geo.mu = P->mu;
+  for (int a = 0; a < 3; ++a) geo.n[a] = P->g.n[a];
   double v = 1.0;
   for (int a = 0; a < P->g.dim; ++a) v *= P->g.h[a];
   const int d = P->g.dim;
@@ -1330,7 +1332,7 @@ void dg_vsolve(dpp_precond pc, const DGWork<T> &w, DGVec<T> b, const T *tu, DGOu
     ProfScope ps(PF_DG_VEL,
                  2.0 * sizeof(T) * ((double)nc * dg_npk(d) + vecs * nc * NU) +
                      (k > 0 ? 2.0 * 8.0 * nc + 4.0 * nc * (d + 1) : 0.0), s);
-    k_dg_vcheb<d, T><<<gv, DGV_BS, 0, s>>>(geo, dev(P->g), P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(),
+    k_dg_vcheb<d, T><<<gv, DGV_BS, 0, s>>>(geo, P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(),
                                            P->k2.as<double>(), w.binv, b, tu, xin, o, xprev, c1, c2, false);
     xprev = xin;
     xin = DGVec<T>{o.base, o.stride};
@@ -1415,7 +1417,7 @@ void dg_setup_impl(dpp_precond pc, hipStream_t s) {
     k_dg_scale<<<gu, 256, 0, s>>>(vx, nu, ssd);
     for (int it = 0; it < o.power_iters; ++it) {
       k_dg_vcheb<d, double><<<gb, DGV_BS, 0, s>>>(
-          dg_geo(P), dev(P->g), P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(), P->k2.as<double>(),
+          dg_geo(P), P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(), P->k2.as<double>(),
           pc->dgbinv.as<double>(), DGVec<double>{nullptr, 0}, nullptr, DGVec<double>{vx, nu}, DGOut<double>{vy, nu},
           DGVec<double>{nullptr, 0}, Sc2{{0, 0}}, Sc2{{0, 0}}, true);
       dg_sumsq(pc, vy, nu, ssd, s);
