@@ -76,7 +76,7 @@ def kernel_name(family, dim, pc, flux=False, dg=False):
     """rocprofv3 name of a single-kernel family's FP64 kernel (flux: the
     instances for problems with velocity faces; dg: DG-VMS problems)."""
     if dg:
-        return {"spmv_K": "k_dg_spmv<%d>", "dg_vel": "k_dg_vcheb<%d>"}[family] % dim
+        return {"spmv_K": "k_dg_spmv<%d>", "dg_vel": "k_dg_vcheb<%d, double>"}[family] % dim
     if family in ("cheb_S_l0", "resid_S_l0"):
         lanes, sym = pc.shape(0)
         k = "k_cheb" if family == "cheb_S_l0" else "k_lspmv"

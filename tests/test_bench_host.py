@@ -54,7 +54,7 @@ def test_kernel_names_of_single_kernel_families():
     assert bench.kernel_name("schur_rhs", 3, pc) == "k_schur_rhs<3, double, double, false>"
     assert bench.kernel_name("schur_vel", 3, pc, flux=True) == "k_schur_vel<3, double, double, true>"
     assert bench.kernel_name("spmv_K", 3, pc, dg=True) == "k_dg_spmv<3>"
-    assert bench.kernel_name("dg_vel", 2, pc, dg=True) == "k_dg_vcheb<2>"
+    assert bench.kernel_name("dg_vel", 2, pc, dg=True) == "k_dg_vcheb<2, double>"
     assert set(bench.SINGLE_KERNEL_FAMILIES) == {"spmv_K", "cheb_S_l0", "resid_S_l0", "schur_rhs", "schur_vel",
                                                  "dg_vel"}
 
