@@ -35,6 +35,8 @@ CASES = {
     "3d_ragged": (3, (3, 2, 4), True),
     "3d_cube": (3, 3, False),
     "3d_thin": (3, (1, 2, 1), False),
+    "2d_single_box": (2, (1, 1), True),
+    "3d_single_box": (3, (1, 1, 1), True),
 }
 
 
@@ -93,7 +95,8 @@ def test_dg_fieldsplit_matches_oracle(case):
     assert np.abs(z - zo).max() <= 1e-11 * np.abs(zo).max()
 
 
-SOLVE_CASES = {"2d_ragged": (2, (12, 7)), "2d_mms": (2, 16), "3d_ragged": (3, (4, 3, 5)), "3d_mms": (3, 4)}
+SOLVE_CASES = {"2d_ragged": (2, (12, 7)), "2d_mms": (2, 16), "3d_ragged": (3, (4, 3, 5)), "3d_mms": (3, 4),
+               "3d_ragged_single_box": (3, (1, 1, 1))}
 
 
 @pytest.mark.parametrize("case", sorted(SOLVE_CASES))
