@@ -159,6 +159,23 @@ def test_dg_fp32_preconditioner_solve_matches_oracle(case):
     assert np.array_equal(H(x64b), H(x64))
 
 
+@pytest.mark.parametrize("precision", [0, 2])
+def test_dg_graph_replay_matches_eager_solve(precision):
+    """Arnoldi steps replayed from captured hipGraphs (the DG fieldsplit and the
+    nodal cycle inside them) give the eager solve bit for bit, with eager work
+    between the replays."""
+    import paper_1808_08328_amd as dpp
+    P = dpp.assemble_problem(random_problem(3, (3, 4, 2), 31, True))
+    pc = P.setup_precond(coarse_max=40)
+    xe, se = P.solve(pc, rtol=1e-10, precision=precision)
+    for rep in range(2):
+        xg, sg = P.solve(pc, rtol=1e-10, precision=precision, use_graph=1)
+        assert torch.equal(xg, xe) and sg.iters == se.iters, rep
+        y = P.spmv(xg)
+        torch.cuda.synchronize()
+        del y
+
+
 @pytest.mark.parametrize("case", ["2d_ragged", "3d_ragged"])
 def test_dg_adjoint_matches_oracle(case):
     """K^T lambda = g through D K D on the DG blocks, against the oracle's
