@@ -508,19 +508,14 @@ __device__ inline void dg_ld(const T *__restrict__ p, double *v) {
 #pragma unroll
   for (int j = 0; j < n; ++j) v[j] = (double)p[j];
 }
-template <int n>
-__device__ inline void dg_ldi(const int *__restrict__ p, int *v) {
-#pragma unroll
-  for (int j = 0; j < n; ++j) v[j] = p[j];
-}
 
 // y = K x (bsub null) or y = bsub - K x: one thread per (network, simplex)
 // computes the (d + 1)^2 rows of its simplex.
 template <int d>
 __global__ __launch_bounds__(256) void k_dg_spmv(DGGeo geo, long nc, long nslot, const double *__restrict__ k1,
                                                  const double *__restrict__ k2, const double *__restrict__ betac,
-                                                 double beta, const int *__restrict__ nbr,
-                                                 const double *__restrict__ x, const double *__restrict__ bsub,
+                                                 double beta, const double *__restrict__ x,
+                                                 const double *__restrict__ bsub,
                                                  double *__restrict__ y) {
   constexpr int NU = (d + 1) * d, NV = d + 1;
   const int q = blockIdx.y;
@@ -655,7 +650,7 @@ __global__ void k_dg_diag_s(long nc, const double *__restrict__ A, const int *__
 // rhat = r_p - K_pu y_u (y_u [2][n_cells NU], the velocity solve's output):
 // one thread per (network, simplex)
 template <int d, typename T>
-__global__ __launch_bounds__(256) void k_dg_rhat(DGGeo geo, long nc, long nslot, const int *__restrict__ nbr,
+__global__ __launch_bounds__(256) void k_dg_rhat(DGGeo geo, long nc, long nslot,
                                                  const T *__restrict__ yu, const T *__restrict__ r,
                                                  T *__restrict__ rh) {
   constexpr int NU = (d + 1) * d, NV = d + 1;
@@ -688,7 +683,7 @@ __global__ __launch_bounds__(256) void k_dg_rhat(DGGeo geo, long nc, long nslot,
 // tu = K_up zp, or w = D_u^-1 K_up zp when du is given: one thread per
 // (network, simplex)
 template <int d, typename T>
-__global__ __launch_bounds__(256) void k_dg_tu(DGGeo geo, long nc, long nslot, const int *__restrict__ nbr,
+__global__ __launch_bounds__(256) void k_dg_tu(DGGeo geo, long nc, long nslot,
                                                const T *__restrict__ zp, const T *__restrict__ du,
                                                T *__restrict__ tu) {
   constexpr int NU = (d + 1) * d, NV = d + 1;
@@ -728,7 +723,7 @@ __global__ __launch_bounds__(256) void k_dg_tu(DGGeo geo, long nc, long nslot, c
 template <int d, typename T>
 __global__ __launch_bounds__(256) void k_dg_sp(DGGeo geo, long nc, long nslot, const double *__restrict__ k1,
                                                const double *__restrict__ k2, const double *__restrict__ betac,
-                                               double beta, const int *__restrict__ nbr, const T *__restrict__ w,
+                                               double beta, const T *__restrict__ w,
                                                const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ ds,
                                                const T *__restrict__ b, T *__restrict__ dd, Sc2 c1, Sc2 c2,
                                                bool cheb) {
@@ -848,7 +843,7 @@ struct DGOut {
 constexpr int DGV_BS = 192;
 template <int d, typename T>
 __global__ __launch_bounds__(DGV_BS, 7) void k_dg_vcheb(DGGeo geo, const double *__restrict__ tab, long nc,
-                                                     const int *__restrict__ nbr, const double *__restrict__ k1,
+                                                     const double *__restrict__ k1,
                                                      const double *__restrict__ k2, const T *__restrict__ Bi,
                                                      DGVec<T> b, const T *__restrict__ tu, DGVec<T> xin,
                                                      DGOut<T> xout, DGVec<T> xprev, Sc2 c1, Sc2 c2, bool power) {
@@ -1204,16 +1199,16 @@ void dg_spmv(dpp_problem P, const double *x, const double *bsub, double *y, hipS
   const int d = g.dim;
   const long nc = g.nc;
   const dim3 grid(blocks_for(nc, 256), 2);
-  // algorithmic bytes (matrix-free): x and y (and b) once, the coefficients
-  // of both networks, the neighbour table
-  ProfScope ps(PF_SPMV_K, 8.0 * P->ndof() * (bsub ? 3.0 : 2.0) + 2.0 * dg_coef_bytes(P) + 4.0 * nc * (d + 1), s);
+  // algorithmic bytes (matrix-free, neighbours from the Freudenthal rule): x
+  // and y (and b) once, the coefficients of both networks
+  ProfScope ps(PF_SPMV_K, 8.0 * P->ndof() * (bsub ? 3.0 : 2.0) + 2.0 * dg_coef_bytes(P), s);
   const DGGeo geo = dg_geo(P);
   if (d == 3)
     k_dg_spmv<3><<<grid, 256, 0, s>>>(geo, nc, P->nslot, P->k1.as<double>(), P->k2.as<double>(), dg_betac(P),
-                                      P->beta, P->dgnb.as<int>(), x, bsub, y);
+                                      P->beta, x, bsub, y);
   else
     k_dg_spmv<2><<<grid, 256, 0, s>>>(geo, nc, P->nslot, P->k1.as<double>(), P->k2.as<double>(), dg_betac(P),
-                                      P->beta, P->dgnb.as<int>(), x, bsub, y);
+                                      P->beta, x, bsub, y);
   check_launch("DG spmv");
 }
 
@@ -1261,10 +1256,10 @@ void dg_s_apply(dpp_precond pc, const double *x, double *y, const double *ds, hi
   const long nc = P->g.nc, nslot = P->nslot;
   const DGGeo geo = dg_geo(P);
   const dim3 gs(blocks_for(nc, 256), 2);
-  k_dg_tu<d, double><<<gs, 256, 0, s>>>(geo, nc, nslot, P->dgnb.as<int>(), x, pc->dgdu.as<double>(),
+  k_dg_tu<d, double><<<gs, 256, 0, s>>>(geo, nc, nslot, x, pc->dgdu.as<double>(),
                                         pc->dgtu.as<double>());
   k_dg_sp<d, double><<<gs, 256, 0, s>>>(geo, nc, nslot, P->k1.as<double>(), P->k2.as<double>(), dg_betac(P), P->beta,
-                                        P->dgnb.as<int>(), pc->dgtu.as<double>(), x, y, ds, nullptr, nullptr,
+                                        pc->dgtu.as<double>(), x, y, ds, nullptr, nullptr,
                                         Sc2{{0, 0}}, Sc2{{0, 0}}, false);
 }
 
@@ -1327,12 +1322,12 @@ void dg_vsolve(dpp_precond pc, const DGWork<T> &w, DGVec<T> b, const T *tu, DGOu
     const DGOut<T> o = k + 1 == DG_VEL_DEGREE ? out : DGOut<T>{buf[k & 1], nc * NU};
     // bytes: the packed block inverses; b (less tu) read, x' written; x read
     // after the first step (x_0 = 0), x_(k-1) after the second, with the
-    // coefficients and the neighbour table
+    // coefficients
     const double vecs = 2.0 + (tu ? 1.0 : 0.0) + (k > 0 ? 1.0 : 0.0) + (k > 1 ? 1.0 : 0.0);
     ProfScope ps(PF_DG_VEL,
                  2.0 * sizeof(T) * ((double)nc * dg_npk(d) + vecs * nc * NU) +
-                     (k > 0 ? 2.0 * 8.0 * nc + 4.0 * nc * (d + 1) : 0.0), s);
-    k_dg_vcheb<d, T><<<gv, DGV_BS, 0, s>>>(geo, P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(),
+                     (k > 0 ? 2.0 * 8.0 * nc : 0.0), s);
+    k_dg_vcheb<d, T><<<gv, DGV_BS, 0, s>>>(geo, P->dgtab.as<double>(), nc, P->k1.as<double>(),
                                            P->k2.as<double>(), w.binv, b, tu, xin, o, xprev, c1, c2, false);
     xprev = xin;
     xin = DGVec<T>{o.base, o.stride};
@@ -1417,7 +1412,7 @@ void dg_setup_impl(dpp_precond pc, hipStream_t s) {
     k_dg_scale<<<gu, 256, 0, s>>>(vx, nu, ssd);
     for (int it = 0; it < o.power_iters; ++it) {
       k_dg_vcheb<d, double><<<gb, DGV_BS, 0, s>>>(
-          dg_geo(P), P->dgtab.as<double>(), nc, P->dgnb.as<int>(), P->k1.as<double>(), P->k2.as<double>(),
+          dg_geo(P), P->dgtab.as<double>(), nc, P->k1.as<double>(), P->k2.as<double>(),
           pc->dgbinv.as<double>(), DGVec<double>{nullptr, 0}, nullptr, DGVec<double>{vx, nu}, DGOut<double>{vy, nu},
           DGVec<double>{nullptr, 0}, Sc2{{0, 0}}, Sc2{{0, 0}}, true);
       dg_sumsq(pc, vy, nu, ssd, s);
@@ -1451,19 +1446,17 @@ void dg_apply_impl(dpp_precond pc, const T *r, T *z, hipStream_t s) {
   const long nc = g.nc, nslot = P->nslot;
   const DGWork<T> w = dg_work(pc, T());
   const double *k1 = P->k1.as<double>(), *k2 = P->k2.as<double>(), *bc = dg_betac(P);
-  const int *nb = P->dgnb.as<int>();
   const DGGeo geo = dg_geo(P);
   const dim3 gp(blocks_for(nslot, 256), 2), gs(blocks_for(nc, 256), 2);
   const long NU = (d + 1) * d, vstride = (d + 1) * nslot;  // network stride of the ABI vector
   const double vb = sizeof(T);                               // bytes per stored vector value
   dg_vsolve<d, T>(pc, w, DGVec<T>{r + off_u(d, nslot, 0), vstride}, nullptr, DGOut<T>{w.yu, nc * NU}, s);
   // algorithmic bytes of the pressure-side launches (2 networks, matrix-free):
-  // vectors once, the neighbour table, the coefficients where they enter
-  const double nbr_b = 4.0 * nc * (d + 1);
-  const double b_tu = 2.0 * vb * ((double)nslot + (double)nc * NU) + nbr_b;  // zp in, tu out
+  // vectors once, the coefficients where they enter
+  const double b_tu = 2.0 * vb * ((double)nslot + (double)nc * NU);  // zp in, tu out
   {
-    ProfScope ps(PF_DG_PRES, 2.0 * vb * ((double)nc * NU + 2.0 * nslot) + nbr_b, s);
-    k_dg_rhat<d, T><<<gs, 256, 0, s>>>(geo, nc, nslot, nb, w.yu, r, w.rh);
+    ProfScope ps(PF_DG_PRES, 2.0 * vb * ((double)nc * NU + 2.0 * nslot), s);
+    k_dg_rhat<d, T><<<gs, 256, 0, s>>>(geo, nc, nslot, w.yu, r, w.rh);
   }
   // coarse correction on the nodes, back to the slots
   {
@@ -1500,14 +1493,14 @@ void dg_apply_impl(dpp_precond pc, const T *r, T *z, hipStream_t s) {
     {
       // w = D_u^-1 K_up x: x and D_u^-1 in, w out
       ProfScope ps(PF_DG_PRES, b_tu + 2.0 * vb * nc * NU, s);
-      k_dg_tu<d, T><<<gs, 256, 0, s>>>(geo, nc, nslot, nb, cur, w.du, w.tu);
+      k_dg_tu<d, T><<<gs, 256, 0, s>>>(geo, nc, nslot, cur, w.du, w.tu);
     }
     {
       // S_q rows: w, x, diag, b, dd (read after the first step), dd and x'
       // written, the coefficients
       ProfScope ps(PF_DG_PRES,
-                   2.0 * vb * ((double)nc * NU + (k > 0 ? 6.0 : 5.0) * nslot) + 2.0 * dg_coef_bytes(P) + nbr_b, s);
-      k_dg_sp<d, T><<<gs, 256, 0, s>>>(geo, nc, nslot, k1, k2, bc, P->beta, nb, w.tu, cur, oth, w.ds, w.rh, w.dd, c1,
+                   2.0 * vb * ((double)nc * NU + (k > 0 ? 6.0 : 5.0) * nslot) + 2.0 * dg_coef_bytes(P), s);
+      k_dg_sp<d, T><<<gs, 256, 0, s>>>(geo, nc, nslot, k1, k2, bc, P->beta, w.tu, cur, oth, w.ds, w.rh, w.dd, c1,
                                        c2, true);
     }
     std::swap(cur, oth);
@@ -1515,7 +1508,7 @@ void dg_apply_impl(dpp_precond pc, const T *r, T *z, hipStream_t s) {
   // z_u ~ K_uu^-1 (r_u - K_up z_p), z_p
   {
     ProfScope ps(PF_DG_PRES, b_tu, s);
-    k_dg_tu<d, T><<<gs, 256, 0, s>>>(geo, nc, nslot, nb, cur, nullptr, w.tu);
+    k_dg_tu<d, T><<<gs, 256, 0, s>>>(geo, nc, nslot, cur, nullptr, w.tu);
   }
   dg_vsolve<d, T>(pc, w, DGVec<T>{r + off_u(d, nslot, 0), vstride}, w.tu, DGOut<T>{z + off_u(d, nslot, 0), vstride},
                   s);
