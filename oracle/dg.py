@@ -253,6 +253,7 @@ def l2_errors(S_sys, x, exact):
 
 
 VEL_DEGREE = 8       # Chebyshev steps of the velocity-block solve
+NODAL_COARSE_2D = 1800   # default coarsest size of the nodal cycle in 2D
 VEL_LO_FRAC = 0.01   # its interval [0.01 hi, hi]
 
 
@@ -306,7 +307,8 @@ class FieldSplitDG:
       with ILU sub-blocks plays this part there.
     * S_i = K_pp - K_pu diag(K_uu)^-1 K_up (selfp), and B_i a two-level cycle
       whose coarse level is the nodal CG-VMS problem of the same box and
-      coefficients (its selfp block and multigrid hierarchy, oracle.mg):
+      coefficients (its selfp block and multigrid hierarchy, oracle.mg, whose
+      coarsest level by default takes up to NODAL_COARSE_2D nodes in 2D):
       restrict by summing the slot values on each node (R), one V-cycle,
       copy the node values back to the slots (R^T), then Chebyshev
       post-smoothing on S_i with its diagonal (the nodal levels' smoother:
@@ -347,7 +349,8 @@ class FieldSplitDG:
         self.lo = [lo_frac * h for h in self.hi]
         self.deg = o.post(0)
         cg = odpp.assemble(replace(prob, elem="p1"))
-        self.H = solver.FieldSplit(cg, o).H
+        oc = replace(o, coarse_max=NODAL_COARSE_2D) if (o.coarse_max == 0 and d == 2) else o
+        self.H = solver.FieldSplit(cg, oc).H
         msh = system.mesh
         self.R = sp.csr_matrix((np.ones(S), (msh.cells.ravel(), np.arange(S))), shape=(msh.N, S))
 

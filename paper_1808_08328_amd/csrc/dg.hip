@@ -1287,6 +1287,7 @@ void dg_vcycle(dpp_precond pc, const double *b, double *x, hipStream_t s) { vcyc
 void dg_vcycle(dpp_precond pc, const float *b, float *x, hipStream_t s) { vcycle32(pc, b, x, s); }
 
 constexpr int DG_VEL_DEGREE = 8;      // Chebyshev steps of the velocity-block solve
+constexpr int DG_NODAL_COARSE_2D = 1800;  // default coarsest size of the 2D nodal cycle
 constexpr double DG_VEL_LO_FRAC = 0.01;  // its interval [0.01 hi, hi]
 
 // out ~ K_uu^-1 (b - tu) per network: DG_VEL_DEGREE Chebyshev steps from
@@ -1368,6 +1369,9 @@ void dg_setup_impl(dpp_precond pc, hipStream_t s) {
   pc->dgpc = new dpp_precond_s();
   pc->dgpc->prob = pc->dgcg.get();
   pc->dgpc->opts = pc->opts;
+  // in 2D the nodal cycle's small levels are launch-bound: by default its
+  // coarsest level takes up to DG_NODAL_COARSE_2D nodes (solved exactly)
+  if (pc->opts.coarse_max == 0 && d == 2) pc->dgpc->opts.coarse_max = DG_NODAL_COARSE_2D;
   precond_setup(pc->dgpc, s);
   // DG level: diagonals, work vectors, Chebyshev bounds from power steps
   pc->dgdu.alloc(sizeof(double) * 2 * nc * NU);

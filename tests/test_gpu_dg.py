@@ -72,14 +72,16 @@ def test_dg_refuses_what_it_does_not_implement():
     assert e.value.status == 7
 
 
-PC_CASES = {"2d_ragged": (2, (9, 6), 30), "3d_ragged": (3, (4, 3, 5), 20), "3d_cube": (3, 4, 40)}
+PC_CASES = {"2d_ragged": (2, (9, 6), 30), "3d_ragged": (3, (4, 3, 5), 20), "3d_cube": (3, 4, 40),
+            "2d_default_coarse": (2, (50, 45), 0)}
 
 
 @pytest.mark.parametrize("case", sorted(PC_CASES))
 def test_dg_fieldsplit_matches_oracle(case):
-    """The DG fieldsplit apply (velocity Jacobi, two-level pressure blocks
-    over the nodal CG-VMS hierarchy, Chebyshev on S_p^DG) against the
-    oracle's definition, at the cycles' 1e-11."""
+    """The DG fieldsplit apply (block-Jacobi Chebyshev velocity solve,
+    two-level pressure blocks over the nodal CG-VMS hierarchy, Chebyshev on
+    S_q) against the oracle's definition, at the cycles' 1e-11; coarse_max 0
+    takes the default coarsest level of each side (the 2D nodal cycle's own)."""
     import paper_1808_08328_amd as dpp
     from oracle import mg as omg
     dim, n, cmax = PC_CASES[case]
