@@ -71,9 +71,9 @@ typedef struct dpp_batch_s *dpp_batch;
  * is [u1 | p1 | u2 | p2] over slots and n_dof = (2d+2)(d+1) x simplices
  * (dpp_problem_sizes reports the slots as n_nodes).  DG-VMS problems take
  * pressure faces only (face_bc NULL or zero) and are solved with precision 0
- * or 2; the adjoint solve, the CSR export and the full product K x are
- * available, while precision 1, the block products, dpp_vcycle, the parameter
- * gradient, the L2-error integrals and batched solves return
+ * or 2; the adjoint solve, the CSR export, the full product K x and the
+ * L2-error integrals are available, while precision 1, the block products,
+ * dpp_vcycle, the parameter gradient and batched solves return
  * DPP_ERR_UNSUPPORTED. */
 typedef struct {
   int dim;
@@ -277,8 +277,10 @@ dpp_status dpp_param_grad(dpp_problem prob, const double *x, const double *lambd
  * solution of the two- and three-dimensional studies (section "Representative
  * numerical results") with parameters mms = {k1, k2, beta, mu} (host, all
  * > 0), integrated over the problem's simplices with the q-point
- * conical-product Gauss rule (q^d points per simplex, 1 <= q <= 16).  err
- * (host, [4]) receives the errors of u1, p1, u2, p2.  The 3D micro-pressure
+ * conical-product Gauss rule (q^d points per simplex, 1 <= q <= 16); for
+ * DG-VMS problems each simplex takes the values of its own vertex slots.  err
+ * (host, [4]) receives the errors of u1, p1, u2, p2.  Q1 problems return
+ * DPP_ERR_UNSUPPORTED.  The 3D micro-pressure
  * uses mu/(beta k2) (the pair that solves the mass balances).  Synchronises
  * the stream; allocates its scratch per call. */
 dpp_status dpp_mms_l2_errors(dpp_problem prob, const double *x, const double mms[4], int q,

@@ -224,15 +224,15 @@ def interpolate(msh, func_p, func_u, dim):
     return func_p(X), func_u(X)
 
 
-def l2_errors(S_sys, x, exact):
-    """Relative L2 errors per field of the DG solution x against callables
-    exact[f](X) -> values at points X, by a degree-4 rule per simplex
-    (oracle.post's simplex rule)."""
+def l2_errors(S_sys, x, exact, q=4, relative=True):
+    """L2 errors per field of the DG solution x against callables
+    exact[f](X) -> values at points X, by oracle.post's q-point-per-axis
+    simplex rule; relative to the exact field's norm unless relative=False."""
     from . import post as opost
     msh = S_sys.mesh
     d = msh.dim
     P, vol, G = geometry(msh)
-    pts, wts = opost.simplex_rule(d, 4)            # barycentric points [q, d+1], weights summing to 1/d!
+    pts, wts = opost.simplex_rule(d, q)            # barycentric points [q^d, d+1], weights summing to 1/d!
     wts = wts * np.prod(np.arange(1, d + 1))
     F = fields(d, S_sys.S)
     out = {}
@@ -248,7 +248,7 @@ def l2_errors(S_sys, x, exact):
         w = vol[:, None] * wts[None, :]
         err = np.sqrt(np.sum(w[:, :, None] * (num - ex) ** 2))
         ref = np.sqrt(np.sum(w[:, :, None] * ex ** 2))
-        out[f] = err / ref if ref > 0 else err
+        out[f] = err / ref if (relative and ref > 0) else err
     return out
 
 

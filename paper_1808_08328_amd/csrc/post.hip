@@ -72,10 +72,12 @@ template <int D>
 __global__ __launch_bounds__(PBS) void k_l2_error(GridDev g, const double *__restrict__ x,
                                                   MMS m, const double *__restrict__ lam,
                                                   const double *__restrict__ w, int nq,
-                                                  double hx, double hy, double hz,
+                                                  double hx, double hy, double hz, long nslot,
                                                   double *__restrict__ part) {
   constexpr int NPER = D == 3 ? 6 : 2;
-  const long N = g.N;
+  // CG-VMS: the fields live on the nodes; DG-VMS (nslot > 0): on the vertex
+  // slots, slot e (D+1) + k being vertex k of simplex e
+  const long N = nslot > 0 ? nslot : g.N;
   const long ncell = (long)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1) * NPER;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // u1, p1, u2, p2
   // grid-stride over the simplices (one pass when the grid covers them all)
@@ -102,11 +104,12 @@ __global__ __launch_bounds__(PBS) void k_l2_error(GridDev g, const double *__res
     const long op1 = off_p(D, N, 0), op2 = off_p(D, N, 1);
     double vp1[D + 1], vp2[D + 1], vu1[D + 1][D], vu2[D + 1][D];
     for (int k = 0; k <= D; ++k) {
-      vp1[k] = x[op1 + vid[k]];
-      vp2[k] = x[op2 + vid[k]];
+      const long at = nslot > 0 ? e * (D + 1) + k : vid[k];
+      vp1[k] = x[op1 + at];
+      vp2[k] = x[op2 + at];
       for (int c = 0; c < D; ++c) {
-        vu1[k][c] = x[ou1 + D * vid[k] + c];
-        vu2[k][c] = x[ou2 + D * vid[k] + c];
+        vu1[k][c] = x[ou1 + D * at + c];
+        vu2[k][c] = x[ou2 + D * at + c];
       }
     }
     for (int iq = 0; iq < nq; ++iq) {
@@ -366,10 +369,11 @@ static void l2_errors_on(dpp_problem P, const double *x, const double mms[4], in
   const Grid &g = P->g;
   double *dout = dp + 4 * (size_t)nb;
   MMS m{mms[0], mms[1], mms[2], mms[3], std::sqrt(mms[2] * (mms[0] + mms[1]) / (mms[0] * mms[1]))};
+  const long nslot = P->dg ? P->nslot : 0;
   if (g.dim == 3)
-    k_l2_error<3><<<nb, PBS, 0, s>>>(dev(g), x, m, dl, dw, nq, g.h[0], g.h[1], g.h[2], dp);
+    k_l2_error<3><<<nb, PBS, 0, s>>>(dev(g), x, m, dl, dw, nq, g.h[0], g.h[1], g.h[2], nslot, dp);
   else
-    k_l2_error<2><<<nb, PBS, 0, s>>>(dev(g), x, m, dl, dw, nq, g.h[0], g.h[1], 1.0, dp);
+    k_l2_error<2><<<nb, PBS, 0, s>>>(dev(g), x, m, dl, dw, nq, g.h[0], g.h[1], 1.0, nslot, dp);
   check_launch("l2 error");
   k_l2_finish<<<4, PBS, 0, s>>>(dp, nb, dout);
   check_launch("l2 error finish");
@@ -389,7 +393,7 @@ static void check_mms_args(int q, const double mms[4]) {
 void mms_l2_errors(dpp_problem P, const double *x, const double mms[4], int q, double err[4],
                    hipStream_t s) {
   check_mms_args(q, mms);
-  DPP_CHECK(P->g.elem == ELEM_P1 && !P->dg, DPP_ERR_UNSUPPORTED, "L2 errors are integrated for CG-VMS P1 simplices only");
+  DPP_CHECK(P->g.elem == ELEM_P1, DPP_ERR_UNSUPPORTED, "L2 errors are integrated on the Kuhn simplices only (P1, DG-VMS)");
   const Grid &g = P->g;
   std::vector<double> lam, wt;
   simplex_rule(g.dim, q, lam, wt);
@@ -464,7 +468,7 @@ double *scratch_of_current_device() {
 void mms_l2_errors_noalloc(dpp_problem P, const double *x, const double mms[4], int q,
                            double err[4], hipStream_t s) {
   check_mms_args(q, mms);
-  DPP_CHECK(P->g.elem == ELEM_P1 && !P->dg, DPP_ERR_UNSUPPORTED, "L2 errors are integrated for CG-VMS P1 simplices only");
+  DPP_CHECK(P->g.elem == ELEM_P1, DPP_ERR_UNSUPPORTED, "L2 errors are integrated on the Kuhn simplices only (P1, DG-VMS)");
   const Grid &g = P->g;
   int nq = 1;
   for (int a = 0; a < g.dim; ++a) nq *= q;

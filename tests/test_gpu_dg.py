@@ -252,3 +252,31 @@ def test_dg_full_size_solve_oracle_residual(workload):
         o = dict(zip(S.K.indices[lo:hi].tolist(), S.K.data[lo:hi].tolist()))
         assert set(o) <= set(g), rr
         assert max(abs(g[c] - o.get(c, 0.0)) for c in g) <= 1e-13 * scale, rr
+
+
+@pytest.mark.parametrize("dim,n", [(2, (9, 6)), (3, (3, 4, 2))])
+def test_dg_l2_errors_match_oracle(dim, n):
+    """dpp_mms_l2_errors on a DG solution (fields on the vertex slots) and on
+    the DG interpolant of the exact fields, against the oracle's integral of
+    the same rule, at 1e-12."""
+    import paper_1808_08328_amd as dpp
+    prob = I.mms_problem(dim, n, k1=1.0, k2=0.2, beta=1.0, mu=0.9, elem="dg")
+    mms = prob.meta["mms"]
+    S = odg.assemble(prob)
+    P = dpp.assemble_problem(prob)
+    x, st = P.solve(P.setup_precond(coarse_max=40), rtol=1e-10)
+    assert st.converged == 1
+    field = {"p1": 0, "p2": 1, "u1": 2, "u2": 3}
+    exact = {f: (lambda X, i=i: np.asarray(I.mms_fields(dim, X, *mms)[i]).reshape(X.shape[0], -1))
+             for f, i in field.items()}
+    Fs = odg.fields(dim, S.S)
+    X = odg.slot_coords(S.mesh)
+    xi = np.zeros(P.n_dof)
+    for f, i in field.items():
+        xi[Fs[f]] = np.asarray(I.mms_fields(dim, X, *mms)[i]).ravel()
+    for xv in (H(x), xi):
+        for q in (2, 4):
+            eg = P.mms_l2_errors(torch.as_tensor(xv, device="cuda"), mms, q=q)
+            eo = odg.l2_errors(S, xv, exact, q=q, relative=False)
+            for f in ("u1", "p1", "u2", "p2"):
+                assert abs(eg[f] - eo[f]) <= 1e-12 * eo[f], (q, f, eg[f], eo[f])
