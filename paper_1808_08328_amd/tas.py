@@ -1,5 +1,6 @@
-"""Time-accuracy-size (TAS) spectrum of the CG-VMS DPP solver on one GPU
-(section "Performance spectrum modeling").
+"""Time-accuracy-size (TAS) spectrum of the DPP solver on one GPU (section
+"Performance spectrum modeling"), for CG-VMS P1 or DG-VMS on the Kuhn
+simplices.
 
 For a ladder of box sizes the manufactured-solution problem of the 2D or 3D
 study (section "Representative numerical results") is assembled, its
@@ -18,7 +19,7 @@ alpha/d, which holds for log10(DoF) (its printed definition carries a minus).
 
 Usage, from the repository root (the input generator is the repository's
 ``dpp_inputs`` module):
-    python -m paper_1808_08328_amd.tas --dim 3 --n 8 16 32 64 96 [--json out.jsonl]
+    python -m paper_1808_08328_amd.tas --dim 3 --n 8 16 32 64 96 [--elem dg] [--json out.jsonl]
 """
 import argparse
 import json
@@ -39,8 +40,8 @@ def _inputs():
 FIELDS = ("u1", "p1", "u2", "p2")
 
 
-def run_size(dpp, I, torch, dim, n, mms, rtol, q, reps):
-    prob = I.mms_problem(dim, n, k1=mms[0], k2=mms[1], beta=mms[2], mu=mms[3])
+def run_size(dpp, I, torch, dim, n, mms, rtol, q, reps, elem="p1"):
+    prob = I.mms_problem(dim, n, k1=mms[0], k2=mms[1], beta=mms[2], mu=mms[3], elem=elem)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P = dpp.assemble_problem(prob)
@@ -62,7 +63,7 @@ def run_size(dpp, I, torch, dim, n, mms, rtol, q, reps):
     ndof = P.n_dof
     ta, ts, tv = t1 - t0, t2 - t1, (t4 - t3) / reps
     tot = ta + ts + tv
-    row = {"dim": dim, "n": n, "dof": ndof, "DoS": math.log10(ndof), "iters": st.iters,
+    row = {"dim": dim, "n": n, "elem": elem, "dof": ndof, "DoS": math.log10(ndof), "iters": st.iters,
            "converged": bool(st.converged), "assemble_s": ta, "setup_s": ts, "solve_s": tv,
            "total_s": tot, "l2_error_s": t5 - t4,
            "dofs_per_s": {"assemble": ndof / ta, "setup": ndof / ts, "solve": ndof / tv,
@@ -114,16 +115,23 @@ def main(argv=None):
     ap.add_argument("--q", type=int, default=4, help="quadrature points per collapsed direction")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--json", default=None, help="also write one JSON line per size here")
+    ap.add_argument("--elem", default="p1", choices=("p1", "dg"),
+                    help="CG-VMS P1 or DG-VMS (discontinuous P1) on the Kuhn simplices")
     a = ap.parse_args(argv)
-    ns = a.n or ([16, 32, 64, 128, 256, 512] if a.dim == 2 else [8, 16, 32, 64, 96])
+    if a.n:
+        ns = a.n
+    elif a.elem == "dg":  # the DG rows of the h-size tables
+        ns = [10, 20, 40, 80, 160] if a.dim == 2 else [5, 8, 10, 16, 20]
+    else:
+        ns = [16, 32, 64, 128, 256, 512] if a.dim == 2 else [8, 16, 32, 64, 96]
     import torch
     import paper_1808_08328_amd as dpp
     I = _inputs()
     # load the library and its kernels once before timing
-    run_size(dpp, I, torch, a.dim, 4, tuple(a.mms), a.rtol, a.q, 1)
+    run_size(dpp, I, torch, a.dim, 4, tuple(a.mms), a.rtol, a.q, 1, a.elem)
     rows = []
     for n in ns:
-        r = run_size(dpp, I, torch, a.dim, n, tuple(a.mms), a.rtol, a.q, a.reps)
+        r = run_size(dpp, I, torch, a.dim, n, tuple(a.mms), a.rtol, a.q, a.reps, a.elem)
         rows.append(r)
         print(json.dumps(r), flush=True)
         if a.json:

@@ -91,3 +91,22 @@ def test_gpu_mesh_convergence(dim, ns):
     for f in ("u1", "u2"):
         r = post.rates(hs, [e[f] for e in errs])
         assert (r.min() if dim == 2 else r[-1]) > 1.8, (f, r)
+
+
+@pytest.mark.parametrize("dim,ns", [(2, (10, 20, 40, 80)), (3, (4, 8, 16))])
+def test_tas_harness_dg_mesh_convergence(dim, ns):
+    """The TAS harness on DG-VMS (tas.run_size with elem "dg"): the GPU's L2
+    errors of DG solutions decay at the rates the oracle's DG pins show
+    (pressures about h^2, velocities at least h^1; the 3D velocities are
+    pre-asymptotic on these boxes), and the row carries its DoS/DoA/DoE."""
+    import paper_1808_08328_amd as dpp
+    from paper_1808_08328_amd import tas
+    mms = (1.0, 0.1, 1.0, 1.0)
+    rows = [tas.run_size(dpp, I, torch, dim, n, mms, 1e-11, 4, 1, elem="dg") for n in ns]
+    assert all(r["converged"] and r["elem"] == "dg" for r in rows)
+    hs = [1.0 / n for n in ns]
+    for f in ("p1", "p2", "u1", "u2"):
+        r = post.rates(hs, [row["error"][f] for row in rows])
+        assert r[-1] >= (1.8 if f.startswith("p") else 1.0), (f, r)
+    s = tas.slopes(rows)
+    assert s["p1"]["DoA_vs_DoS"] > 0
