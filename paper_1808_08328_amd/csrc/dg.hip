@@ -281,9 +281,10 @@ __global__ __launch_bounds__(128) void k_dg_assemble(GridDev g, double hx, doubl
 // follow from its axis permutation and the box sizes, and every term of
 // eq. S4_dg_stiffness_matrix is a short sum over the simplex's vertices
 // (volume terms) or over the vertices of one facet (jump and average terms).
-// A product then moves the vectors, the coefficients and the neighbour
-// table instead of (d + 2) SB^2 block values per simplex.  The entries are
-// those of the assembly above, summed in another order.
+// A product then moves the vectors and the coefficients instead of (d + 2)
+// SB^2 block values per simplex (facet neighbours follow from the Freudenthal
+// rule, dg_neighbours).  The entries are those of the assembly above, summed
+// in another order.
 
 struct DGGeo {
   double h[3];
@@ -600,9 +601,10 @@ __global__ void k_dg_export(long nc, long nslot, const double *__restrict__ A, c
 // ------------------------------------------------------------ fieldsplit --
 // The Schur fieldsplit of the solver section (Method 2, selfp) on the DG
 // blocks, per network q (both networks in one launch, blockIdx.y = q):
-//   rhat = r_p - K_pu D_u^-1 r_u,  z_p ~ S_q^-1 rhat,  z_u = D_u^-1 (r_u - K_up z_p)
-// with D_u = diag(K_uu) and S_q = K_pp - K_pu D_u^-1 K_up applied without
-// forming it.  z_p comes from a two-level cycle: the nodal CG-VMS hierarchy
+//   rhat = r_p - K_pu V(r_u),  z_p ~ S_q^-1 rhat,  z_u = V(r_u - K_up z_p)
+// with V the velocity solve (Chebyshev steps with the simplex-block Jacobi,
+// k_dg_vcheb) and S_q = K_pp - K_pu D_u^-1 K_up, D_u = diag(K_uu), applied
+// without forming it.  z_p comes from a two-level cycle: the nodal CG-VMS hierarchy
 // of the same box and coefficients corrects the restricted residual (node
 // values = sums over the node's slots; back by copying node values to the
 // slots), then Chebyshev steps on S_q with its diagonal smooth on the slots.
