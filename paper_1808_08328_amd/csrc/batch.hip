@@ -225,8 +225,17 @@ __global__ __launch_bounds__(256) void kb_coarse(const CDesc *__restrict__ cd, i
   if (row >= c.n) return;
   const double *Mr = c.Cinv + (size_t)q * c.n * c.n + (size_t)row * c.n;
   const TX *bq = (const TX *)c.b + (size_t)q * c.n;
-  double s = 0.0;
-  for (int k = lane; k < c.n; k += 64) s += Mr[k] * (double)bq[k];
+  // four independent partial sums, so four loads per lane are in flight
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int k = lane;
+  for (; k + 192 < c.n; k += 256) {
+    s0 += Mr[k] * (double)bq[k];
+    s1 += Mr[k + 64] * (double)bq[k + 64];
+    s2 += Mr[k + 128] * (double)bq[k + 128];
+    s3 += Mr[k + 192] * (double)bq[k + 192];
+  }
+  for (; k < c.n; k += 64) s0 += Mr[k] * (double)bq[k];
+  double s = (s0 + s1) + (s2 + s3);
   s = bwave_sum(s);
   if (lane == 0) ((TX *)c.x)[(size_t)q * c.n + row] = (TX)s;
 }

@@ -485,8 +485,17 @@ __global__ __launch_bounds__(256) void k_coarse(const double *__restrict__ Cinv,
   if (row >= n) return;
   const double *Mr = Cinv + (size_t)q * n * n + (size_t)row * n;
   const TX *bq = b + (size_t)q * n;
-  double s = 0.0;
-  for (int c = lane; c < n; c += 64) s += Mr[c] * (double)bq[c];
+  // four independent partial sums, so four loads per lane are in flight
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int c = lane;
+  for (; c + 192 < n; c += 256) {
+    s0 += Mr[c] * (double)bq[c];
+    s1 += Mr[c + 64] * (double)bq[c + 64];
+    s2 += Mr[c + 128] * (double)bq[c + 128];
+    s3 += Mr[c + 192] * (double)bq[c + 192];
+  }
+  for (; c < n; c += 64) s0 += Mr[c] * (double)bq[c];
+  double s = (s0 + s1) + (s2 + s3);
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (lane == 0) x[(size_t)q * n + row] = (TX)s;
 }
