@@ -30,8 +30,10 @@ functions, Galerkin coarse operators equal re-discretised ones on nested
 meshes, the power steps equal M^k x_0 through the eigendecomposition of
 M = D^-1 A, k Chebyshev steps multiply the error by the scaled Chebyshev
 polynomial p_k(M), the V-cycle is symmetric, a one-level cycle is the exact
-inverse); the values of the cycle as a whole are otherwise "parity unpinned"
-by the paper, which prints none for its multigrid.
+inverse) and, as a whole, by the error-propagation recursion of a multigrid
+cycle, I - B_l A_l = S_post (I - P B_(l+1) P^T A_l) S_pre, evaluated with
+dense matrices.  The paper fixes no particular cycle and prints no numbers
+for its multigrid, so the cycle's definition is this build's reading.
 """
 from __future__ import annotations
 

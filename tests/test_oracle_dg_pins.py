@@ -299,3 +299,29 @@ def test_slot_transfers_and_selfp_of_the_fieldsplit(dim, n):
         assert np.abs(P.Sp[i].toarray() - Sq).max() <= 1e-12 * np.abs(Sq).max()
         assert np.abs(Sq - Sq.T).max() <= 1e-12 * np.abs(Sq).max()
         assert np.linalg.eigvalsh(0.5 * (Sq + Sq.T)).min() > 0
+
+
+@pytest.mark.parametrize("dim,n,cmax", [(2, (8, 7), 20), (3, (4, 3, 4), 30)])
+def test_pressure_cycle_is_the_two_level_error_propagation(dim, n, cmax):
+    """B_i(rhat), the pressure solve: post-smoothing on S_i from the start
+    R^T V R rhat (V the nodal cycle) has the error p(D^-1 S_i) (R^T V R - S_i^-1)
+    rhat, so B_i = (I - p) S_i^-1 + p R^T V R, with p the Chebyshev error
+    polynomial (eigendecomposition) and V the multigrid error-propagation
+    recursion of the nodal hierarchy, both as dense matrices.  A transposed R,
+    a smoother on the wrong operator or interval, or a missing coarse
+    correction fails it."""
+    from oracle import mg
+    from dense_cycles import cheb_error_matrix, cycle_matrix
+    prob, S = small_dg(dim, n)
+    P = odg.FieldSplitDG(S, prob, mg.MGOptions(coarse_max=cmax))
+    R = P.R.toarray()
+    for i in (0, 1):
+        assert len(P.H[i].levels) >= 2
+        Sd = P.Sp[i].toarray()
+        pk = cheb_error_matrix(Sd, P.dS[i], P.deg, P.lo[i], P.hi[i])
+        V = cycle_matrix(P.H[i])
+        B = (np.eye(Sd.shape[0]) - pk) @ np.linalg.inv(Sd) + pk @ R.T @ V @ R
+        for seed in (41, 42):
+            rhat = I.random_vector(Sd.shape[0], seed)
+            z = P.pressure(i, rhat)
+            assert np.linalg.norm(z - B @ rhat) < 1e-10 * np.linalg.norm(B @ rhat), (i, seed)

@@ -11,6 +11,7 @@ import scipy.sparse as sp
 
 import dpp_inputs as I
 from oracle import dpp, mg, post, solver
+from dense_cycles import cheb_error_matrix, cycle_matrix
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -507,6 +508,54 @@ def test_post_only_two_grid_cycle_is_smoother_after_coarse_correction():
     ec = I.random_vector(H.levels[1].A.shape[0], 8)
     e = H.levels[0].P @ ec
     assert np.linalg.norm(mg.vcycle(H, A @ e) - e) < 1e-11 * np.linalg.norm(e)
+
+
+@pytest.mark.parametrize("case", ["default", "symmetric", "pre_fine", "pre_coarse", "q1"])
+def test_vcycle_is_the_multigrid_error_propagation(case):
+    """The cycle's values as a whole: vcycle(b) = B b with B from the
+    error-propagation recursion of a multigrid cycle, built here from dense
+    matrices (Chebyshev error polynomials through an eigendecomposition,
+    explicit P, exact coarsest inverse) on three-level hierarchies.  Restricting
+    b instead of the residual, P in place of P^T, adding the correction where
+    it is assigned, a level class with the wrong degrees or a missing level
+    fails it."""
+    opts = {
+        "default": mg.MGOptions(coarse_max=50),
+        "symmetric": mg.MGOptions(coarse_max=50, pre_fine=2, post_fine=2, pre_coarse=2, post_coarse=2),
+        "pre_fine": mg.MGOptions(coarse_max=50, pre_fine=1, post_fine=2, pre_coarse=0, post_coarse=3),
+        "pre_coarse": mg.MGOptions(coarse_max=50, pre_fine=0, post_fine=3, pre_coarse=2, post_coarse=1),
+        "q1": mg.MGOptions(coarse_max=50),
+    }[case]
+    if case == "q1":
+        S = dpp.assemble(I.grf_problem(3, (6, 5, 6), elem="q1"))
+        A, n, elem = dpp.selfp(S)[0], (6, 5, 6), "q1"
+    elif case == "pre_coarse":
+        S = dpp.assemble(I.grf_problem(2, (12, 11)))
+        A, n, elem = dpp.selfp(S)[1], (12, 11), "p1"
+        opts.coarse_max = 20
+    else:
+        S = dpp.assemble(I.grf_problem(3, (8, 7, 8)))
+        A, n, elem = dpp.selfp(S)[1], (8, 7, 8), "p1"
+    H = mg.setup(A, len(n), n, opts, elem=elem)
+    assert len(H.levels) == 3, [lv.A.shape for lv in H.levels]
+    B = cycle_matrix(H)
+    for seed in (31, 32):
+        b = I.random_vector(A.shape[0], seed)
+        x = mg.vcycle(H, b)
+        assert np.linalg.norm(x - B @ b) < 1e-10 * np.linalg.norm(B @ b), (case, seed)
+    # the recursion is sensitive to the cycle's structure: a cycle that adds
+    # its pre-smoothed iterate to the correction of b (not of the residual)
+    # differs from it wherever there is pre-smoothing
+    if opts.pre(0) > 0:
+        lev = H.levels[0]
+        Ad = lev.A.toarray()
+        Spre = cheb_error_matrix(Ad, lev.dinv, opts.pre(0), lev.lo, lev.hi)
+        Bpre = (np.eye(Ad.shape[0]) - Spre) @ np.linalg.inv(Ad)
+        Bc = cycle_matrix(H, 1)
+        Spost = cheb_error_matrix(Ad, lev.dinv, opts.post(0), lev.lo, lev.hi)
+        x0 = Bpre @ b + lev.P.toarray() @ (Bc @ (lev.P.T @ b))
+        wrong = Spost @ (x0 - np.linalg.solve(Ad, b)) + np.linalg.solve(Ad, b)
+        assert np.linalg.norm(wrong - B @ b) > 1e-3 * np.linalg.norm(B @ b)
 
 
 def test_fieldsplit_with_exact_blocks_is_exact_inverse():
