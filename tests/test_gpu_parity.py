@@ -1,6 +1,6 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle.
 
-Bars (derived in the design doc): assembly and every operator product to 1e-13
+Bars, from the arithmetic of each step: assembly and every operator product to 1e-13
 relative (FP64, only the summation order differs); the multigrid cycle and the
 fieldsplit apply to 1e-11; FP64 solves at rtol 1e-12 to 1e-10 relative per
 field; the mixed-precision solve to 1e-7 per field; full-size solves by the
