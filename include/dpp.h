@@ -62,8 +62,8 @@ typedef struct dpp_batch_s *dpp_batch;
  * element discretizations", CG-VMS rows): 0 = P1 on the Kuhn simplices (the
  * numbering above), 1 = Q1 on the box cells themselves (quadrilaterals /
  * hexahedra; cell h = i + n_x(j + n_y k) is box h, and per-cell arrays have
- * one entry per box).  With Q1 the solver, mixed precision and velocity
- * faces are available; the parameter gradient, the L2-error integrals and
+ * one entry per box).  With Q1 the solver, mixed precision, velocity faces
+ * and the L2-error integrals are available; the parameter gradient and
  * batched solves are P1 only (DPP_ERR_UNSUPPORTED).  2 = DG-VMS, discontinuous
  * P1 on the Kuhn simplices (section "Stabilized mixed discontinuous Galerkin
  * formulation (DG-VMS)", eq. VMS_DG_Weak_Form, eqs. S4_dg_stiffness_matrix and
@@ -276,11 +276,12 @@ dpp_status dpp_param_grad(dpp_problem prob, const double *x, const double *lambd
  * convergence) of a solution x [n_dof] (device) against the manufactured
  * solution of the two- and three-dimensional studies (section "Representative
  * numerical results") with parameters mms = {k1, k2, beta, mu} (host, all
- * > 0), integrated over the problem's simplices with the q-point
- * conical-product Gauss rule (q^d points per simplex, 1 <= q <= 16); for
- * DG-VMS problems each simplex takes the values of its own vertex slots.  err
- * (host, [4]) receives the errors of u1, p1, u2, p2.  Q1 problems return
- * DPP_ERR_UNSUPPORTED.  The 3D micro-pressure
+ * > 0), integrated over the problem's cells: on the simplices with the
+ * q-point conical-product Gauss rule (q^d points per simplex, 1 <= q <= 16),
+ * for DG-VMS problems each simplex taking the values of its own vertex slots;
+ * on Q1 box cells with the tensor Gauss-Legendre rule of q points per axis
+ * and the multilinear interpolation of the cell's corner values.  err
+ * (host, [4]) receives the errors of u1, p1, u2, p2.  The 3D micro-pressure
  * uses mu/(beta k2) (the pair that solves the mass balances).  Synchronises
  * the stream; allocates its scratch per call. */
 dpp_status dpp_mms_l2_errors(dpp_problem prob, const double *x, const double mms[4], int q,
@@ -288,12 +289,13 @@ dpp_status dpp_mms_l2_errors(dpp_problem prob, const double *x, const double mms
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): dpp_mms_l2_errors without
- * any device or host allocation.  The quadrature rule and the partial sums
- * live in one fixed device array of DPP_NOALLOC_SCRATCH_BYTES per GPU, which
+ * any device or host allocation.  The quadrature rule (simplices; the box
+ * cells' tensor rule is passed by value) and the partial sums live in one
+ * fixed device array of DPP_NOALLOC_SCRATCH_BYTES per GPU, which
  * the library holds on every GPU it runs on until the process ends (its
  * address is looked up once per device, on the first call there).  Same
  * arguments and result as dpp_mms_l2_errors; at most 2048 workgroups take
- * the simplices in a grid-stride loop, so the sums are grouped differently
+ * the cells in a grid-stride loop, so the sums are grouped differently
  * and agree with dpp_mms_l2_errors up to rounding.  q > 16 is DPP_ERR_ARG;
  * a device index of 64 or more is DPP_ERR_UNSUPPORTED.  Every call on a GPU
  * uses that GPU's one array and leaves its contents there: calls that

@@ -3,11 +3,13 @@
 // the manufactured solutions of the two- and three-dimensional studies
 // (section "Representative numerical results"), per field u1, p1, u2, p2.
 //
-// The error integral is taken over the Kuhn simplices of the box (the cells of
-// the assembly) with a conical-product Gauss rule (Stroud 1971): Gauss-Legendre
+// The error integral is taken over the cells of the assembly: on the Kuhn
+// simplices with a conical-product Gauss rule (Stroud 1971), Gauss-Legendre
 // nodes on [0, 1] in each collapsed coordinate of the simplex, q^d points per
-// simplex.  One thread per simplex loops over the points; per-workgroup partial
-// sums are added in a fixed order (bit-reproducible).
+// simplex; on Q1 box cells with the tensor Gauss-Legendre rule of q points per
+// axis and the multilinear interpolation of the cell's corner values.  One
+// thread per cell loops over the points; per-workgroup partial sums are added
+// in a fixed order (bit-reproducible).
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -23,6 +25,11 @@ constexpr int QMAX = 16;   // largest rule order (16^3 points per simplex)
 
 struct MMS {
   double k1, k2, beta, mu, eta;
+};
+
+// Gauss-Legendre nodes and weights on [0, 1], passed by value
+struct GL01 {
+  double t[QMAX], w[QMAX];
 };
 
 // Manufactured solution at X: pressures p1, p2 and velocities u_i = -(k_i/mu)
@@ -143,6 +150,87 @@ __global__ __launch_bounds__(PBS) void k_l2_error(GridDev g, const double *__res
     for (int f = 0; f < 4; ++f) acc[f] += se[f] * detj;
   }
   // fixed-order workgroup sum
+  __shared__ double red[4][PBS];
+  for (int f = 0; f < 4; ++f) red[f][threadIdx.x] = acc[f];
+  __syncthreads();
+  for (int st = PBS / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int f = 0; f < 4; ++f) red[f][threadIdx.x] += red[f][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
+}
+
+// Squared errors of Q1 box cell e over the tensor rule gl (q points per axis,
+// x fastest): the fields at a point are the multilinear interpolation of the
+// 2^D corner values, corner v taking the upper node on axis a when bit a of v
+// is set.
+template <int D>
+__global__ __launch_bounds__(PBS) void k_l2_error_box(GridDev g, const double *__restrict__ x,
+                                                      MMS m, GL01 gl, int q, double hx, double hy,
+                                                      double hz, double *__restrict__ part) {
+  constexpr int NV = 1 << D;
+  const long N = g.N;
+  const long ncell = (long)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
+  const int nq = D == 3 ? q * q * q : q * q;
+  const double h[3] = {hx, hy, hz};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // u1, p1, u2, p2
+  for (long e = (long)blockIdx.x * PBS + threadIdx.x; e < ncell; e += (long)gridDim.x * PBS) {
+    long r = e;
+    int c[3] = {(int)(r % g.n[0]), 0, 0};
+    r /= g.n[0];
+    c[1] = (int)(r % g.n[1]);
+    c[2] = D == 3 ? (int)(r / g.n[1]) : 0;
+    const long ou1 = off_u(D, N, 0), ou2 = off_u(D, N, 1);
+    const long op1 = off_p(D, N, 0), op2 = off_p(D, N, 1);
+    double vp1[NV], vp2[NV], vu1[NV][D], vu2[NV][D];
+    for (int v = 0; v < NV; ++v) {
+      const long at = (c[0] + (v & 1)) +
+                      (long)g.m[0] * ((c[1] + ((v >> 1) & 1)) + (long)g.m[1] * (c[2] + ((v >> 2) & 1)));
+      vp1[v] = x[op1 + at];
+      vp2[v] = x[op2 + at];
+      for (int a = 0; a < D; ++a) {
+        vu1[v][a] = x[ou1 + D * at + a];
+        vu2[v][a] = x[ou2 + D * at + a];
+      }
+    }
+    double se[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int iq = 0; iq < nq; ++iq) {
+      const int ia[3] = {iq % q, (iq / q) % q, D == 3 ? iq / (q * q) : 0};
+      double xi[D], X[D], wq = 1.0;
+      for (int a = 0; a < D; ++a) {
+        xi[a] = gl.t[ia[a]];
+        wq *= gl.w[ia[a]];
+        X[a] = c[a] * h[a] + xi[a] * h[a];
+      }
+      double hp1 = 0.0, hp2 = 0.0, hu1[D], hu2[D];
+      for (int a = 0; a < D; ++a) hu1[a] = hu2[a] = 0.0;
+      for (int v = 0; v < NV; ++v) {
+        double sh = 1.0;
+        for (int a = 0; a < D; ++a) sh *= ((v >> a) & 1) ? xi[a] : 1.0 - xi[a];
+        hp1 += sh * vp1[v];
+        hp2 += sh * vp2[v];
+        for (int a = 0; a < D; ++a) {
+          hu1[a] += sh * vu1[v][a];
+          hu2[a] += sh * vu2[v][a];
+        }
+      }
+      double p1, p2, u1[3], u2[3];
+      mms_exact<D>(m, X, p1, p2, u1, u2);
+      double e1 = 0.0, e2 = 0.0;
+      for (int a = 0; a < D; ++a) {
+        e1 += (hu1[a] - u1[a]) * (hu1[a] - u1[a]);
+        e2 += (hu2[a] - u2[a]) * (hu2[a] - u2[a]);
+      }
+      se[0] += wq * e1;
+      se[1] += wq * (hp1 - p1) * (hp1 - p1);
+      se[2] += wq * e2;
+      se[3] += wq * (hp2 - p2) * (hp2 - p2);
+    }
+    // the rule's weights sum to 1 on the unit box: scale by the cell volume
+    const double vol = D == 3 ? hx * hy * hz : hx * hy;
+    for (int f = 0; f < 4; ++f) acc[f] += se[f] * vol;
+  }
   __shared__ double red[4][PBS];
   for (int f = 0; f < 4; ++f) red[f][threadIdx.x] = acc[f];
   __syncthreads();
@@ -361,13 +449,24 @@ void simplex_rule(int dim, int q, std::vector<double> &lam, std::vector<double> 
   simplex_rule_into(dim, q, lam.data(), wt.data());
 }
 
+// Fixed-order sum of the nb partials per field (dp: 4 nb partials, then the 4
+// results), returned to the host as square roots in the order u1, p1, u2, p2.
+static void l2_finish(double *dp, int nb, double err[4], hipStream_t s) {
+  double *dout = dp + 4 * (size_t)nb;
+  k_l2_finish<<<4, PBS, 0, s>>>(dp, nb, dout);
+  check_launch("l2 error finish");
+  double h4[4];
+  DPP_HIP(hipMemcpyAsync(h4, dout, sizeof(h4), hipMemcpyDeviceToHost, s));
+  DPP_HIP(hipStreamSynchronize(s));
+  for (int f = 0; f < 4; ++f) err[f] = std::sqrt(std::max(h4[f], 0.0));
+}
+
 // The error integral with the rule at dl/dw (device), nb workgroups writing
 // their partial sums to dp (device, 4 nb + 4 doubles); err on the host.
 static void l2_errors_on(dpp_problem P, const double *x, const double mms[4], int nq,
                          const double *dl, const double *dw, int nb, double *dp, double err[4],
                          hipStream_t s) {
   const Grid &g = P->g;
-  double *dout = dp + 4 * (size_t)nb;
   MMS m{mms[0], mms[1], mms[2], mms[3], std::sqrt(mms[2] * (mms[0] + mms[1]) / (mms[0] * mms[1]))};
   const long nslot = P->dg ? P->nslot : 0;
   if (g.dim == 3)
@@ -375,13 +474,23 @@ static void l2_errors_on(dpp_problem P, const double *x, const double mms[4], in
   else
     k_l2_error<2><<<nb, PBS, 0, s>>>(dev(g), x, m, dl, dw, nq, g.h[0], g.h[1], 1.0, nslot, dp);
   check_launch("l2 error");
-  k_l2_finish<<<4, PBS, 0, s>>>(dp, nb, dout);
-  check_launch("l2 error finish");
-  double h4[4];
-  DPP_HIP(hipMemcpyAsync(h4, dout, sizeof(h4), hipMemcpyDeviceToHost, s));
-  DPP_HIP(hipStreamSynchronize(s));
-  // field order of the result: u1, p1, u2, p2
-  for (int f = 0; f < 4; ++f) err[f] = std::sqrt(std::max(h4[f], 0.0));
+  l2_finish(dp, nb, err, s);
+}
+
+// The error integral over Q1 box cells with the tensor rule of q points per
+// axis, nb workgroups writing their partial sums to dp (4 nb + 4 doubles).
+static void l2_errors_box_on(dpp_problem P, const double *x, const double mms[4], int q, int nb,
+                             double *dp, double err[4], hipStream_t s) {
+  const Grid &g = P->g;
+  MMS m{mms[0], mms[1], mms[2], mms[3], std::sqrt(mms[2] * (mms[0] + mms[1]) / (mms[0] * mms[1]))};
+  GL01 gl{};
+  gauss_legendre01(q, gl.t, gl.w);
+  if (g.dim == 3)
+    k_l2_error_box<3><<<nb, PBS, 0, s>>>(dev(g), x, m, gl, q, g.h[0], g.h[1], g.h[2], dp);
+  else
+    k_l2_error_box<2><<<nb, PBS, 0, s>>>(dev(g), x, m, gl, q, g.h[0], g.h[1], 1.0, dp);
+  check_launch("l2 error (box cells)");
+  l2_finish(dp, nb, err, s);
 }
 
 static void check_mms_args(int q, const double mms[4]) {
@@ -393,8 +502,14 @@ static void check_mms_args(int q, const double mms[4]) {
 void mms_l2_errors(dpp_problem P, const double *x, const double mms[4], int q, double err[4],
                    hipStream_t s) {
   check_mms_args(q, mms);
-  DPP_CHECK(P->g.elem == ELEM_P1, DPP_ERR_UNSUPPORTED, "L2 errors are integrated on the Kuhn simplices only (P1, DG-VMS)");
   const Grid &g = P->g;
+  if (g.elem == ELEM_Q1) {
+    const long ncell = (long)g.nc;
+    const int nb = (int)((ncell + PBS - 1) / PBS);  // one box cell per thread
+    DBuf part(sizeof(double) * 4 * (size_t)nb + sizeof(double) * 4);
+    l2_errors_box_on(P, x, mms, q, nb, part.as<double>(), err, s);
+    return;
+  }
   std::vector<double> lam, wt;
   simplex_rule(g.dim, q, lam, wt);
   const int nq = (int)wt.size();
@@ -420,11 +535,6 @@ __device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)]
 
 std::mutex na_mu;
 double *na_ptr[MAX_DEVICES] = {};
-
-// Gauss-Legendre nodes and weights on [0, 1], passed by value
-struct GL01 {
-  double t[QMAX], w[QMAX];
-};
 
 // The conical-product rule of simplex_rule_into, expanded on the device from
 // the one-dimensional nodes (same products in the same order).
@@ -468,8 +578,15 @@ double *scratch_of_current_device() {
 void mms_l2_errors_noalloc(dpp_problem P, const double *x, const double mms[4], int q,
                            double err[4], hipStream_t s) {
   check_mms_args(q, mms);
-  DPP_CHECK(P->g.elem == ELEM_P1, DPP_ERR_UNSUPPORTED, "L2 errors are integrated on the Kuhn simplices only (P1, DG-VMS)");
   const Grid &g = P->g;
+  if (g.elem == ELEM_Q1) {
+    // the rule goes by value; only the partial sums use the fixed array
+    const long ncell = (long)g.nc;
+    const int nb = (int)std::min<long>(NA_BLOCKS, (ncell + PBS - 1) / PBS);
+    DPP_CHECK(4 * (size_t)nb + 4 <= NA_DOUBLES, DPP_ERR_ARG, "partial sums larger than the fixed scratch");
+    l2_errors_box_on(P, x, mms, q, nb, scratch_of_current_device(), err, s);
+    return;
+  }
   int nq = 1;
   for (int a = 0; a < g.dim; ++a) nq *= q;
   const size_t nl = (size_t)nq * (g.dim + 1);

@@ -1,5 +1,6 @@
 """Time-accuracy-size (TAS) spectrum of the DPP solver on one GPU (section
-"Performance spectrum modeling"), for CG-VMS P1 or DG-VMS on the Kuhn
+"Performance spectrum modeling"), for CG-VMS P1 on the Kuhn simplices
+(TET / TRI), CG-VMS Q1 on the box cells (HEX / QUAD) or DG-VMS on the
 simplices.
 
 For a ladder of box sizes the manufactured-solution problem of the 2D or 3D
@@ -19,7 +20,7 @@ alpha/d, which holds for log10(DoF) (its printed definition carries a minus).
 
 Usage, from the repository root (the input generator is the repository's
 ``dpp_inputs`` module):
-    python -m paper_1808_08328_amd.tas --dim 3 --n 8 16 32 64 96 [--elem dg] [--json out.jsonl]
+    python -m paper_1808_08328_amd.tas --dim 3 --n 8 16 32 64 96 [--elem q1|dg] [--json out.jsonl]
 """
 import argparse
 import json
@@ -112,11 +113,13 @@ def main(argv=None):
     ap.add_argument("--mms", type=float, nargs=4, default=(1.0, 0.1, 1.0, 1.0),
                     metavar=("K1", "K2", "BETA", "MU"))
     ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--q", type=int, default=4, help="quadrature points per collapsed direction")
+    ap.add_argument("--q", type=int, default=4,
+                    help="quadrature points per collapsed direction (simplices) or per axis (box cells)")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--json", default=None, help="also write one JSON line per size here")
-    ap.add_argument("--elem", default="p1", choices=("p1", "dg"),
-                    help="CG-VMS P1 or DG-VMS (discontinuous P1) on the Kuhn simplices")
+    ap.add_argument("--elem", default="p1", choices=("p1", "q1", "dg"),
+                    help="CG-VMS P1 on the Kuhn simplices, CG-VMS Q1 on the box cells, or DG-VMS "
+                         "(discontinuous P1) on the Kuhn simplices")
     a = ap.parse_args(argv)
     if a.n:
         ns = a.n

@@ -261,8 +261,5 @@ def test_q1_p1_only_calls_are_refused():
         P.param_grad(x, x)
     assert e.value.status == 7
     with pytest.raises(dpp.DppError) as e:
-        P.mms_l2_errors(x, (1.0, 0.1, 1.0, 1.0))
-    assert e.value.status == 7
-    with pytest.raises(dpp.DppError) as e:
         dpp.assemble_batch([prob, prob])
     assert e.value.status == 7

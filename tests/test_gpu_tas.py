@@ -110,3 +110,63 @@ def test_tas_harness_dg_mesh_convergence(dim, ns):
         assert r[-1] >= (1.8 if f.startswith("p") else 1.0), (f, r)
     s = tas.slopes(rows)
     assert s["p1"]["DoA_vs_DoS"] > 0
+
+
+Q1_CASES = [
+    (2, (9, 6), dict(k2=0.3, beta=0.5, mu=1.3, L=(1.0, 0.7))),
+    (3, (4, 3, 3), dict(k2=0.05, beta=1.0, mu=0.8, L=(1.0, 0.6, 0.8))),
+    (3, (1, 2, 1), dict(k2=0.1, beta=1.0)),
+]
+
+
+@pytest.mark.parametrize("dim,n,kw", Q1_CASES)
+def test_q1_l2_errors_match_oracle(dim, n, kw):
+    """The error integral on Q1 box cells (tensor Gauss rule, multilinear
+    interpolation of the corner values) against the oracle's, on GPU
+    solutions and on the nodal interpolant of the exact fields, through the
+    allocating and the allocation-free entry points."""
+    import ctypes as C
+    prob = I.mms_problem(dim, n, elem="q1", **kw)
+    mms = prob.meta["mms"]
+    print("q1 case", dim, n, kw, flush=True)
+    dpp = lib()
+    P = dpp.assemble_problem(prob)
+    x, st = P.solve(P.setup_precond(coarse_max=40), rtol=1e-10)
+    assert st.converged
+    S = odpp.assemble(prob)
+    exact = lambda X: I.mms_fields(dim, X, *mms)
+    L = dpp.lib()
+    f = L.dpp_mms_l2_errors_noalloc
+    f.restype = C.c_int
+    f.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_int,
+                  C.POINTER(C.c_double), C.c_void_p]
+    for v in (x, torch.as_tensor(nodal_exact(prob), device="cuda")):
+        for q in (2, 4):
+            eg = P.mms_l2_errors(v, mms, q=q)
+            eo = post.l2_errors(S, H(v), exact, q=q)
+            m = (C.c_double * 4)(*[float(t) for t in mms])
+            e = (C.c_double * 4)()
+            assert f(P.handle, C.c_void_p(v.data_ptr()), m, q, e,
+                     C.c_void_p(torch.cuda.current_stream().cuda_stream)) == 0
+            en = dict(zip(("u1", "p1", "u2", "p2"), list(e)))
+            for fld in ("u1", "p1", "u2", "p2"):
+                assert abs(eg[fld] - eo[fld]) <= 1e-12 * eo[fld], (q, fld, eg[fld], eo[fld])
+                assert abs(en[fld] - eo[fld]) <= 1e-12 * eo[fld], (q, fld, en[fld], eo[fld])
+
+
+@pytest.mark.parametrize("dim,ns", [(2, (8, 16, 32, 64)), (3, (4, 8, 16))])
+def test_tas_harness_q1_mesh_convergence(dim, ns):
+    """The TAS harness on Q1 box cells (the HEX / QUAD columns): the GPU's L2
+    errors of Q1 solutions decay at the rates of the oracle's Q1 pins (h^2),
+    and the rows carry DoS/DoA/DoE."""
+    import paper_1808_08328_amd as dpp
+    from paper_1808_08328_amd import tas
+    mms = (1.0, 0.1, 1.0, 1.0)
+    rows = [tas.run_size(dpp, I, torch, dim, n, mms, 1e-11, 4, 1, elem="q1") for n in ns]
+    assert all(r["converged"] and r["elem"] == "q1" for r in rows)
+    hs = [1.0 / n for n in ns]
+    for f, lo in (("p1", 1.9), ("p2", 1.9), ("u1", 1.8), ("u2", 1.8)):
+        r = post.rates(hs, [row["error"][f] for row in rows])
+        assert r[-1] > lo, (f, r)
+    s = tas.slopes(rows)
+    assert s["p1"]["DoA_vs_DoS"] > 0

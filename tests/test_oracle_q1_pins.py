@@ -164,6 +164,66 @@ def test_q1_mms_convergence(dim, ns):
         assert post.rates(hs, [e[f] for e in errs])[-1] > lo, (f, errs)
 
 
+@pytest.mark.parametrize("dim,n,L", [(2, (5, 3), (1.0, 0.7)), (3, (3, 2, 4), (1.0, 0.6, 0.8))])
+def test_q1_l2_errors_pinned(dim, n, L):
+    """The error integral on box cells (post.l2_errors with Q1): zero on the
+    nodal interpolant of multilinear exact fields; for linear exact fields
+    (which Q1 reproduces) and random nodal data, the squared error is the sum
+    over cells of e^T M e with the textbook Q1 mass matrix, the tensor product
+    of the one-dimensional (h/6)[[2, 1], [1, 2]] (built here from the corner
+    coordinates, so a wrong basis, weight, point map or cell volume fails
+    it); a constant pressure offset c gives |c| |Omega|^(1/2)."""
+    prob = I.mms_problem(dim, n, L=L, elem="q1")
+    S = dpp.assemble(prob)
+    msh = S.mesh
+    N = msh.N
+    F = dpp.fields(dim, N)
+    h = np.array([L[a] / n[a] for a in range(dim)])
+
+    def multilinear(X):
+        t = np.prod(X + 0.3, axis=1)
+        return (t + X[:, 0], 2.0 * t - 0.5, np.outer(t, [1.0, -2.0, 0.5][:dim]) + 0.3,
+                np.outer(t - X[:, -1], [-0.7, 0.2, 1.1][:dim]))
+
+    def nodal(fn):
+        p1, p2, u1, u2 = fn(msh.X)
+        x = np.zeros(S.K.shape[0])
+        x[F["p1"]], x[F["p2"]] = p1, p2
+        x[F["u1"]], x[F["u2"]] = u1.reshape(-1), u2.reshape(-1)
+        return x
+
+    e = post.l2_errors(S, nodal(multilinear), multilinear, q=3)
+    assert max(e.values()) < 1e-13, e
+    xc = nodal(multilinear)
+    xc[F["p2"]] += 0.37
+    e = post.l2_errors(S, xc, multilinear, q=3)
+    assert abs(e["p2"] - 0.37 * np.sqrt(np.prod(L))) < 1e-13 and e["p1"] < 1e-13
+
+    a = np.array([0.4, -1.3, 0.8][:dim])
+
+    def linear(X):
+        s_ = X @ a
+        return (s_ + 1.0, 2.0 * s_ - 0.5, np.outer(s_, [1.0, -2.0, 0.5][:dim]) + 0.3,
+                np.outer(s_, [-0.7, 0.2, 1.1][:dim]))
+
+    xr = I.random_vector(S.K.shape[0], 23)
+    d = xr - nodal(linear)
+    ref = dict(u1=0.0, p1=0.0, u2=0.0, p2=0.0)
+    for cell in msh.cells:
+        V = msh.X[cell]
+        same = np.abs(V[:, None, :] - V[None, :, :]) < 1e-12 * h   # [v, w, axis]
+        M = np.prod(np.where(same, h / 3.0, h / 6.0), axis=-1)
+        for f in ("p1", "p2"):
+            ev = d[F[f]][cell]
+            ref[f] += ev @ M @ ev
+        for f in ("u1", "u2"):
+            ev = d[F[f]].reshape(N, dim)[cell]
+            ref[f] += np.einsum("vc,vw,wc->", ev, M, ev)
+    got = post.l2_errors(S, xr, linear, q=2)
+    for f in ("u1", "p1", "u2", "p2"):
+        assert abs(got[f] - np.sqrt(ref[f])) < 1e-12 * np.sqrt(ref[f]), (f, got[f], np.sqrt(ref[f]))
+
+
 def test_q1_mass_balance():
     prob = I.grf_problem(3, 6, elem="q1")
     S = dpp.assemble(prob)
