@@ -62,9 +62,9 @@ typedef struct dpp_batch_s *dpp_batch;
  * element discretizations", CG-VMS rows): 0 = P1 on the Kuhn simplices (the
  * numbering above), 1 = Q1 on the box cells themselves (quadrilaterals /
  * hexahedra; cell h = i + n_x(j + n_y k) is box h, and per-cell arrays have
- * one entry per box).  With Q1 the solver, mixed precision, velocity faces
- * and the L2-error integrals are available; the parameter gradient and
- * batched solves are P1 only (DPP_ERR_UNSUPPORTED).  2 = DG-VMS, discontinuous
+ * one entry per box).  With Q1 the solver, mixed precision, velocity faces,
+ * the adjoint solve with the parameter gradient (per box) and the L2-error
+ * integrals are available; batched solves are P1 only (DPP_ERR_UNSUPPORTED).  2 = DG-VMS, discontinuous
  * P1 on the Kuhn simplices (section "Stabilized mixed discontinuous Galerkin
  * formulation (DG-VMS)", eq. VMS_DG_Weak_Form, eqs. S4_dg_stiffness_matrix and
  * S4_dg_rhs): every simplex e owns d + 1 vertex slots e (d+1) + v, the vector
@@ -266,9 +266,10 @@ dpp_status dpp_solve_adjoint(dpp_problem prob, dpp_precond pc, const dpp_solve_o
 
 /* Gradient of J(x(theta)) given x (K x = f) and lambda (K^T lambda = dJ/dx),
  * boundary data held fixed:  dJ/dtheta = -lambda^T (dK/dtheta) x, for
- * theta = ln k1_e, ln k2_e (outputs [n_cells]) and the scalar beta (g_beta [1],
- * or [n_cells] per-cell derivatives when the problem was assembled with
- * beta_cells).  Any output may be NULL. */
+ * theta = ln k1_e, ln k2_e (outputs [n_cells]: per simplex, or per box with
+ * Q1 elements) and the scalar beta (g_beta [1], or [n_cells] per-cell
+ * derivatives when the problem was assembled with beta_cells).  Any output
+ * may be NULL.  DG-VMS problems return DPP_ERR_UNSUPPORTED. */
 dpp_status dpp_param_grad(dpp_problem prob, const double *x, const double *lambda,
                           double *g_logk1, double *g_logk2, double *g_beta, void *stream);
 

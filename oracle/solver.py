@@ -148,6 +148,40 @@ def adjoint_solve(system, g):
     return spla.spsolve(system.K.T.tocsc(), g)
 
 
+def _param_gradient_q1(msh, prob, mu, F, x, lam):
+    """param_gradient on Q1 box cells: the same three terms with the box
+    cell's exact mass and stiffness matrices, tensor products of the
+    one-dimensional linear-element matrices (h/6)[[2, 1], [1, 2]] and
+    (1/h)[[1, -1], [-1, 1]] (local corner v on the upper side of axis a when
+    bit a of v is set)."""
+    d, N = msh.dim, msh.N
+    cells = msh.cells
+    h = np.array([msh.L[a] / msh.n[a] for a in range(d)])
+    nv = 2 ** d
+    bits = np.array([[(v >> a) & 1 for a in range(d)] for v in range(nv)])
+    same = bits[:, None, :] == bits[None, :, :]              # [v, w, axis]
+    m1 = np.where(same, h / 3.0, h / 6.0)
+    s1 = np.where(same, 1.0 / h, -1.0 / h)
+    Mloc = np.prod(m1, axis=-1)
+    Sloc = np.zeros((nv, nv))
+    for a in range(d):
+        Sloc += s1[:, :, a] * np.prod(np.delete(m1, a, axis=-1), axis=-1)
+    out = []
+    for u, p, kk in (("u1", "p1", prob.k1), ("u2", "p2", prob.k2)):
+        xu = x[F[u]].reshape(N, d)[cells]
+        lu = lam[F[u]].reshape(N, d)[cells]
+        xp = x[F[p]][cells]
+        lp = lam[F[p]][cells]
+        k = np.asarray(kk, dtype=np.float64)
+        uu = -(mu / (2.0 * k)) * np.einsum("ab,eac,ebc->e", Mloc, lu, xu)
+        pp = (k / (2.0 * mu)) * np.einsum("ab,ea,eb->e", Sloc, lp, xp)
+        out.append(-(uu + pp))
+    dp_x = (x[F["p1"]] - x[F["p2"]])[cells]
+    dp_l = (lam[F["p1"]] - lam[F["p2"]])[cells]
+    gb = -np.sum(np.einsum("ab,ea,eb->e", Mloc, dp_l, dp_x) / mu)
+    return out[0], out[1], gb
+
+
 def param_gradient(system, prob, x, lam):
     """dJ/d(ln k1_e), dJ/d(ln k2_e), dJ/d beta for J(x(theta)), K x = f, given the
     adjoint lam (K^T lam = dJ/dx) and fixed boundary data (df/dtheta = 0):
@@ -165,6 +199,8 @@ def param_gradient(system, prob, x, lam):
         # dJ/dtheta = lam^T (df~ - dK~ x) = -(P_f lam)^T (dK/dtheta) x
         fixed, _ = dpp.velocity_dofs(msh, prob)
         lam = np.where(fixed, 0.0, lam)
+    if msh.elem == "q1":
+        return _param_gradient_q1(msh, prob, mu, F, x, lam)
     X = msh.X[cells]                                    # [nc, d+1, d]
     J = np.transpose(X[:, 1:, :] - X[:, :1, :], (0, 2, 1))  # columns X_a - X_0
     det = np.linalg.det(J)

@@ -95,6 +95,75 @@ __global__ __launch_bounds__(256) void k_grad(GridDev g, double h0, double h1, d
   gbc[e] = -gb / mu;
 }
 
+// Q1 box cells: one thread per box gathers x and lambda at its 2^D corners
+// (corner v on the upper side of axis a when bit a of v is set).  The cell's
+// mass and stiffness matrices are tensor products of the one-dimensional
+// linear-element matrices (h/6)[[2, 1], [1, 2]] and (1/h)[[1, -1], [-1, 1]].
+template <int D>
+__global__ __launch_bounds__(256) void k_grad_q1(GridDev g, double h0, double h1, double h2,
+                                                 double mu, const double *__restrict__ k1,
+                                                 const double *__restrict__ k2,
+                                                 const double *__restrict__ x,
+                                                 const double *__restrict__ lam,
+                                                 double *__restrict__ g1, double *__restrict__ g2,
+                                                 double *__restrict__ gbc) {
+  constexpr int NV = 1 << D;
+  const long N = g.N;
+  const long ncell = (long)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ncell) return;
+  const double h[3] = {h0, h1, h2};
+  long r = e;
+  int c[3] = {(int)(r % g.n[0]), 0, 0};
+  r /= g.n[0];
+  c[1] = (int)(r % g.n[1]);
+  c[2] = D == 3 ? (int)(r / g.n[1]) : 0;
+  long v[NV];
+  for (int k = 0; k < NV; ++k)
+    v[k] = (c[0] + (k & 1)) + (long)g.m[0] * ((c[1] + ((k >> 1) & 1)) + (long)g.m[1] * (c[2] + ((k >> 2) & 1)));
+  // M(a, b) and S(a, b) of the cell from the corner bits
+  auto mass = [&](int a, int b) {
+    double m = 1.0;
+    for (int ax = 0; ax < D; ++ax) m *= (((a ^ b) >> ax) & 1) ? h[ax] / 6.0 : h[ax] / 3.0;
+    return m;
+  };
+  auto stiff = [&](int a, int b) {
+    double sv = 0.0;
+    for (int ax = 0; ax < D; ++ax) {
+      double t = (((a ^ b) >> ax) & 1) ? -1.0 / h[ax] : 1.0 / h[ax];
+      for (int bx = 0; bx < D; ++bx)
+        if (bx != ax) t *= (((a ^ b) >> bx) & 1) ? h[bx] / 6.0 : h[bx] / 3.0;
+      sv += t;
+    }
+    return sv;
+  };
+  double gnet[2];
+  for (int q = 0; q < 2; ++q) {
+    const double kk = q ? k2[e] : k1[e];
+    const long ou = off_u(D, N, q), op = off_p(D, N, q);
+    double uu = 0.0, pp = 0.0;
+    for (int a = 0; a < NV; ++a)
+      for (int b = 0; b < NV; ++b) {
+        double lx = 0.0;
+        for (int cc = 0; cc < D; ++cc) lx += lam[ou + D * v[a] + cc] * x[ou + D * v[b] + cc];
+        uu += mass(a, b) * lx;
+        pp += stiff(a, b) * lam[op + v[a]] * x[op + v[b]];
+      }
+    gnet[q] = -(-(mu / (2.0 * kk)) * uu + (kk / (2.0 * mu)) * pp);
+  }
+  double dpl[NV], dpx[NV];
+  for (int a = 0; a < NV; ++a) {
+    dpl[a] = lam[off_p(D, N, 0) + v[a]] - lam[off_p(D, N, 1) + v[a]];
+    dpx[a] = x[off_p(D, N, 0) + v[a]] - x[off_p(D, N, 1) + v[a]];
+  }
+  double gb = 0.0;
+  for (int a = 0; a < NV; ++a)
+    for (int b = 0; b < NV; ++b) gb += mass(a, b) * dpl[a] * dpx[b];
+  if (g1) g1[e] = gnet[0];
+  if (g2) g2[e] = gnet[1];
+  gbc[e] = -gb / mu;
+}
+
 __global__ void k_sum_fixed(const double *__restrict__ v, long n, double *__restrict__ out) {
   __shared__ double sh[256];
   double s = 0.0;
@@ -133,8 +202,8 @@ __global__ void k_mask_fixed(GridDev g, const double *__restrict__ lam, double *
 
 void param_grad(dpp_problem P, const double *x, const double *lam, double *g1, double *g2,
                 double *gb, hipStream_t s) {
-  DPP_CHECK(P->g.elem == ELEM_P1 && !P->dg, DPP_ERR_UNSUPPORTED,
-            "the parameter gradient is implemented for CG-VMS P1 simplices");
+  DPP_CHECK(!P->dg, DPP_ERR_UNSUPPORTED,
+            "the parameter gradient is implemented for CG-VMS (P1 simplices, Q1 box cells)");
   const Grid &g = P->g;
   // With velocity faces K~ = P_f K P_f + P_c and f~ = P_f (f - K P_c g) + P_c g,
   // so dJ/dtheta = lam^T (df~ - dK~ x) = -(P_f lam)^T (dK/dtheta) x (x = g on
@@ -155,7 +224,14 @@ void param_grad(dpp_problem P, const double *x, const double *lam, double *g1, d
     gbc = tmp.as<double>();
   }
   const int nb = blocks_for(g.nc, 256);
-  if (g.dim == 3)
+  if (g.elem == ELEM_Q1) {
+    if (g.dim == 3)
+      k_grad_q1<3><<<nb, 256, 0, s>>>(dev(g), g.h[0], g.h[1], g.h[2], P->mu, P->k1.as<double>(),
+                                      P->k2.as<double>(), x, lam, g1, g2, gbc);
+    else
+      k_grad_q1<2><<<nb, 256, 0, s>>>(dev(g), g.h[0], g.h[1], g.h[2], P->mu, P->k1.as<double>(),
+                                      P->k2.as<double>(), x, lam, g1, g2, gbc);
+  } else if (g.dim == 3)
     k_grad<3><<<nb, 256, 0, s>>>(dev(g), g.h[0], g.h[1], g.h[2], P->mu, P->k1.as<double>(),
                                  P->k2.as<double>(), x, lam, g1, g2, gbc);
   else

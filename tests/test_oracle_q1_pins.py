@@ -224,6 +224,50 @@ def test_q1_l2_errors_pinned(dim, n, L):
         assert abs(got[f] - np.sqrt(ref[f])) < 1e-12 * np.sqrt(ref[f]), (f, got[f], np.sqrt(ref[f]))
 
 
+@pytest.mark.parametrize("faces", [False, True])
+def test_q1_parameter_gradient_matches_finite_differences(faces):
+    """dJ/d ln k1_e, dJ/d ln k2_e and dJ/d beta on box cells, J = ||p1 - obs||^2,
+    against central differences of the oracle's own Q1 forward solves (with and
+    without velocity faces)."""
+    ff = [[1, 0, 0, 1, 0, 0], [0, 0, 1, 0, 0, 1]] if faces else None
+    rng = np.random.default_rng(5)
+
+    def problem():
+        return I.mms_problem(3, (3, 2, 3), k1=1.0, k2=0.1, beta=0.7, mu=1.2, elem="q1", flux_faces=ff)
+
+    prob = problem()
+    prob.k1 = 10 ** rng.uniform(-1, 1, prob.n_cells)
+    prob.k2 = 10 ** rng.uniform(-2, 0, prob.n_cells)
+    S = dpp.assemble(prob)
+    F = dpp.fields(3, S.N)
+    obs = I.random_vector(S.N, 19)
+
+    def J_of(k1, k2, beta):
+        pr = problem()
+        pr.k1, pr.k2, pr.beta = k1, k2, beta
+        Sx = dpp.assemble(pr)
+        xx = dpp.solve_direct(Sx.K, Sx.f)
+        return np.sum((xx[F["p1"]] - obs) ** 2)
+
+    x = dpp.solve_direct(S.K, S.f)
+    g = np.zeros_like(x)
+    g[F["p1"]] = 2.0 * (x[F["p1"]] - obs)
+    lam = solver.adjoint_solve(S, g)
+    g1, g2, gb = solver.param_gradient(S, prob, x, lam)
+    assert g1.shape == (prob.n_cells,)
+    eps = 1e-5
+    for d in I.random_directions(2, prob.n_cells, seed0=4100):
+        for which, grad in ((0, g1), (1, g2)):
+            kp = [prob.k1.copy(), prob.k2.copy()]
+            km = [prob.k1.copy(), prob.k2.copy()]
+            kp[which] = kp[which] * np.exp(eps * d)
+            km[which] = km[which] * np.exp(-eps * d)
+            fd = (J_of(kp[0], kp[1], prob.beta) - J_of(km[0], km[1], prob.beta)) / (2 * eps)
+            assert grad @ d == pytest.approx(fd, rel=1e-5, abs=1e-9)
+    fd = (J_of(prob.k1, prob.k2, prob.beta + eps) - J_of(prob.k1, prob.k2, prob.beta - eps)) / (2 * eps)
+    assert gb == pytest.approx(fd, rel=1e-5)
+
+
 def test_q1_mass_balance():
     prob = I.grf_problem(3, 6, elem="q1")
     S = dpp.assemble(prob)
