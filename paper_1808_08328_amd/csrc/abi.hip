@@ -273,6 +273,15 @@ static dpp_status solve_common(dpp_problem P, dpp_precond pc, const dpp_solve_op
     pc->opts.cheb_post_fine = o.cheb_post_fine;
     pc->opts.cheb_pre_coarse = o.cheb_pre_coarse;
     pc->opts.cheb_post_coarse = o.cheb_post_coarse;
+    if (pc->dgpc) {
+      // DG-VMS: the nodal cycle of the pressure solve takes the same degrees
+      dpp_precond_s &nc = *pc->dgpc;
+      nc.opts.cheb_degree = o.cheb_degree;
+      nc.opts.cheb_pre_fine = o.cheb_pre_fine;
+      nc.opts.cheb_post_fine = o.cheb_post_fine;
+      nc.opts.cheb_pre_coarse = o.cheb_pre_coarse;
+      nc.opts.cheb_post_coarse = o.cheb_post_coarse;
+    }
     hipStream_t s = S(stream);
     if (o.use_graph && !dpp::prof_on()) {
       // Graphs are captured and replayed on a stream the library owns (the

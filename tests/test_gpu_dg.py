@@ -280,3 +280,23 @@ def test_dg_l2_errors_match_oracle(dim, n):
             eo = odg.l2_errors(S, xv, exact, q=q, relative=False)
             for f in ("u1", "p1", "u2", "p2"):
                 assert abs(eg[f] - eo[f]) <= 1e-12 * eo[f], (q, f, eg[f], eo[f])
+
+
+def test_dg_solve_time_cycle_degrees_reach_the_nodal_cycle():
+    """Cycle degrees given to the solve act as if given to the setup: on
+    DG-VMS problems they reach the nodal cycle of the pressure solve as well
+    as the smoothing on the slots (same iterations, same solution)."""
+    import paper_1808_08328_amd as dpp
+    prob = random_problem(3, (3, 3, 4), 11)
+    P = dpp.assemble_problem(prob)
+    o = dict(cheb_post_fine=3, cheb_post_coarse=2)
+    xa, sa = P.solve(P.setup_precond(coarse_max=30, **o), rtol=1e-10)
+    pc = P.setup_precond(coarse_max=30)
+    x0, s0 = P.solve(pc, rtol=1e-10)
+    xb, sb = P.solve(pc, rtol=1e-10, **o)
+    assert sa.converged and sb.converged and s0.converged
+    assert sa.iters == sb.iters
+    a, b = H(xa), H(xb)
+    assert np.abs(a - b).max() <= 1e-10 * np.abs(a).max()
+    # and the degrees matter: the default cycle takes a different path
+    assert s0.iters != sa.iters or np.abs(H(x0) - a).max() > 1e-13 * np.abs(a).max()
