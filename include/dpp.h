@@ -141,7 +141,9 @@ typedef struct {
  *   cheb_post_coarse [3]: Chebyshev degrees of the V-cycle's pre- and
  *     post-smoothing on the finest level and on the coarser smoothing levels;
  *     -1 = cheb_degree.  A pre degree of 0 skips pre-smoothing (the level
- *     restricts its right-hand side directly); post degrees are >= 1.
+ *     restricts its right-hand side directly); post degrees are >= 1.  On
+ *     DG-VMS problems they set the nodal cycle of the pressure solve; the
+ *     smoothing on the slots after it takes 3 steps.
  *   inner_maxiter [0]: mixed mode: iteration limit of one inner solve
  *     (0 = what is left of maxiter).
  *   schedule [-1]: kernel schedule of the multigrid levels, fixed at setup:

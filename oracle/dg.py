@@ -255,6 +255,7 @@ def l2_errors(S_sys, x, exact, q=4, relative=True):
 VEL_DEGREE = 8       # Chebyshev steps of the velocity-block solve
 NODAL_COARSE_2D = 1800   # default coarsest size of the nodal cycle in 2D
 VEL_LO_FRAC = 0.01   # its interval [0.01 hi, hi]
+PRES_DEGREE = 3      # Chebyshev steps on S_i after the nodal correction
 
 
 def power_bound(apply_A, apply_M, size, iters):
@@ -310,9 +311,9 @@ class FieldSplitDG:
       coefficients (its selfp block and multigrid hierarchy, oracle.mg, whose
       coarsest level by default takes up to NODAL_COARSE_2D nodes in 2D):
       restrict by summing the slot values on each node (R), one V-cycle,
-      copy the node values back to the slots (R^T), then Chebyshev
-      post-smoothing on S_i with its diagonal (the nodal levels' smoother:
-      power-step bound, interval [lo_frac hi, hi], the finest level's degree)."""
+      copy the node values back to the slots (R^T), then PRES_DEGREE
+      Chebyshev post-smoothing steps on S_i with its diagonal (the nodal
+      levels' power-step bound and interval [lo_frac hi, hi])."""
 
     def __init__(self, system, prob, mg_opts=None):
         from dataclasses import replace
@@ -347,7 +348,7 @@ class FieldSplitDG:
         lo_frac = o.lo_frac if o.lo_frac > 0 else (0.1 if d == 3 else 0.3)
         self.hi = [o.hi_factor * mg.power_lambda(self.Sp[i], self.dS[i], o.power_iters) for i in range(2)]
         self.lo = [lo_frac * h for h in self.hi]
-        self.deg = o.post(0)
+        self.deg = PRES_DEGREE
         cg = odpp.assemble(replace(prob, elem="p1"))
         oc = replace(o, coarse_max=NODAL_COARSE_2D) if (o.coarse_max == 0 and d == 2) else o
         self.H = solver.FieldSplit(cg, oc).H

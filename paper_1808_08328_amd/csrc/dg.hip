@@ -1291,6 +1291,7 @@ void dg_vcycle(dpp_precond pc, const float *b, float *x, hipStream_t s) { vcycle
 constexpr int DG_VEL_DEGREE = 8;      // Chebyshev steps of the velocity-block solve
 constexpr int DG_NODAL_COARSE_2D = 1800;  // default coarsest size of the 2D nodal cycle
 constexpr double DG_VEL_LO_FRAC = 0.01;  // its interval [0.01 hi, hi]
+constexpr int DG_PRES_DEGREE = 3;     // Chebyshev steps on S_q after the nodal correction
 
 // out ~ K_uu^-1 (b - tu) per network: DG_VEL_DEGREE Chebyshev steps from
 // zero with the simplex-block Jacobi (intermediate iterates in w.va / w.vb)
@@ -1476,7 +1477,7 @@ void dg_apply_impl(dpp_precond pc, const T *r, T *z, hipStream_t s) {
     k_dg_prolong<d, T><<<gp, 256, 0, s>>>(dev(g), nc, nslot, w.cx, cur);
   }
   // Chebyshev post-smoothing on S_q (Saad, Alg. 12.1 with the diagonal of S_q)
-  const int deg = pc->opts.cheb_post_fine >= 1 ? pc->opts.cheb_post_fine : pc->opts.cheb_degree;
+  const int deg = DG_PRES_DEGREE;
   double sig[2], rho[2], th[2], de[2];
   for (int q = 0; q < 2; ++q) {
     th[q] = 0.5 * (pc->dghi[q] + pc->dglo[q]);
